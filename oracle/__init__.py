@@ -1,0 +1,171 @@
+"""ctypes wrapper of the plain FP64 CPU revised-simplex oracle (simplex_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the CPU
+baseline leg of bench.py, never by the product package.  It shares no code with
+the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "simplex_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OPTIMAL, UNBOUNDED, ITER_LIMIT = 1, 2, 3
+STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT"}
+FLAG_DEGENERATE, FLAG_TIE, FLAG_ASPIRATION, FLAG_LCLEAR = 1, 2, 4, 8
+
+# -ffp-contract=off: only the explicit fma() calls fuse.  x86-64-v3 has hardware FMA,
+# so fma() is one correctly rounded instruction instead of a libm emulation.
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-march=x86-64-v3", "-fPIC", "-shared"]
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_libs = {}
+
+
+def lib(path: str | None = None):
+    """Load the oracle library (or, for mutation tests, another build of the same source)."""
+    key = path or _LIB
+    if key not in _libs:
+        if path is None and not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(key)
+        P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        L.oracle_create.restype = P
+        L.oracle_create.argtypes = [I32, I32, dp, dp, dp, I32, I32, I32, D, D, D]
+        L.oracle_destroy.argtypes = [P]
+        L.oracle_run.restype = I32
+        L.oracle_run.argtypes = [P, I64]
+        L.oracle_iterations.restype = I64
+        L.oracle_iterations.argtypes = [P]
+        L.oracle_status.restype = I32
+        L.oracle_status.argtypes = [P]
+        L.oracle_ray.restype = I32
+        L.oracle_ray.argtypes = [P]
+        L.oracle_objective.restype = D
+        L.oracle_objective.argtypes = [P]
+        L.oracle_solution.argtypes = [P, dp, dp, ip]
+        L.oracle_state.argtypes = [P, dp, dp, dp, dp]
+        L.oracle_pivots.restype = I64
+        L.oracle_pivots.argtypes = [P, ip, ip, ip, ip, I64]
+        L.oracle_counts.argtypes = [P, C.POINTER(C.c_int64)]
+        _libs[key] = L
+    return _libs[key]
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+@dataclass
+class Result:
+    status: int
+    iterations: int
+    objective: float
+    x: np.ndarray
+    y: np.ndarray
+    basis: np.ndarray
+    enter: np.ndarray
+    row: np.ndarray
+    leave: np.ndarray
+    flags: np.ndarray
+    counts: dict = field(default_factory=dict)
+    ray: int = -1
+
+    @property
+    def status_name(self):
+        return STATUS_NAMES.get(self.status, str(self.status))
+
+
+class Oracle:
+    """One LP held by the oracle; run() may be called repeatedly (resume)."""
+
+    def __init__(self, A, b, c, sense="max", tenure=5, leaving_list=True, eps_d=1e-9, eps_p=1e-9,
+                 eps_z=1e-12, lib_path=None):
+        self._L = lib(lib_path)
+        A = np.asarray(A, dtype=np.float64)
+        m, n = A.shape
+        self.m, self.n = m, n
+        self._A = np.asfortranarray(A)
+        self._b = np.ascontiguousarray(b, dtype=np.float64)
+        self._c = np.ascontiguousarray(c, dtype=np.float64)
+        assert self._b.shape == (m,) and self._c.shape == (n,)
+        s = {"min": 0, "max": 1}[sense]
+        self._h = self._L.oracle_create(m, n, _dp(self._A), _dp(self._b), _dp(self._c), s, int(tenure),
+                                      int(bool(leaving_list)), eps_d, eps_p, eps_z)
+        if not self._h:
+            raise ValueError("oracle_create rejected the LP (m<=0, negative or non-finite b, or no memory)")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._L.oracle_destroy(h)
+            self._h = None
+
+    def run(self, max_iter=None):
+        if max_iter is None:
+            max_iter = 10 * (self.m + self.n)
+        st = self._L.oracle_run(self._h, int(max_iter))
+        if st < 0:
+            raise MemoryError("oracle ran out of memory")
+        return st
+
+    @property
+    def iterations(self):
+        return self._L.oracle_iterations(self._h)
+
+    def state(self):
+        m = self.m
+        Binv = np.empty((m, m))
+        xB = np.empty(m)
+        W = np.empty(m)
+        z = C.c_double()
+        self._L.oracle_state(self._h, _dp(Binv), _dp(xB), _dp(W), C.byref(z))
+        return Binv, xB, W, z.value
+
+    def result(self) -> Result:
+        L = self._L
+        m, n = self.m, self.n
+        x = np.empty(n)
+        y = np.empty(m)
+        basis = np.empty(m, dtype=np.int32)
+        L.oracle_solution(self._h, _dp(x), _dp(y), _ip(basis))
+        cnt = L.oracle_pivots(self._h, None, None, None, None, 0)
+        e = np.empty(cnt, dtype=np.int32)
+        r = np.empty(cnt, dtype=np.int32)
+        lv = np.empty(cnt, dtype=np.int32)
+        f = np.empty(cnt, dtype=np.int32)
+        L.oracle_pivots(self._h, _ip(e), _ip(r), _ip(lv), _ip(f), cnt)
+        counts = (C.c_int64 * 4)()
+        L.oracle_counts(self._h, counts)
+        return Result(status=L.oracle_status(self._h), iterations=L.oracle_iterations(self._h),
+                      objective=L.oracle_objective(self._h), x=x, y=y, basis=basis, enter=e, row=r,
+                      leave=lv, flags=f,
+                      counts=dict(degenerate=counts[0], tie=counts[1], aspiration=counts[2], lclear=counts[3]),
+                      ray=L.oracle_ray(self._h))
+
+
+def solve(A, b, c, sense="max", max_iter=None, **kw) -> Result:
+    o = Oracle(A, b, c, sense=sense, **kw)
+    o.run(max_iter)
+    return o.result()

@@ -1,0 +1,357 @@
+/*
+ * Plain FP64 revised simplex: the oracle of the GPU path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  It shares no code with the HIP
+ * library and includes none of its headers.
+ *
+ * What it computes (paper, Section 2.1 "Revised Simplex algorithm", Steps 1-8 and
+ * Figure 1; Section 3.1 "Tableau updating"; Sections 2.2/3.4 "Tabu rule"):
+ *
+ *   min  chat^T X   s.t.  (A', I_m) X = b,  b >= 0,  X >= 0,
+ *   chat_j = s*c_j for structural j (s = +1 min, -1 max), chat_{n+i} = 0 for slacks.
+ *
+ * It keeps the revised tableau of Figure 1 as separate arrays:
+ *   W      (1 x m)  = chat_B^T B^-1         top-left block
+ *   z      scalar   = chat_B^T B^-1 b       top-middle  (Step 2, read as C_B b-bar)
+ *   Binv   (m x m)  = B^-1, row-major       body
+ *   xB     (m)      = B^-1 b = b-bar        body, middle column
+ * and pivots it on y_rk as Step 8 prescribes, every iteration, never refactorising.
+ *
+ * Readings of points the paper leaves open (each one is also listed in the design doc):
+ *   - m = rows (constraints), n = structural columns.          (Section 2.1)
+ *   - ratio-test index runs over the m rows.                    (Step 6)
+ *   - optimality: no nonbasic d_j = chat_j - W a_j < -eps_d;
+ *     the paper's z_j - c_j equals -d_j.                        (Steps 3-4)
+ *   - Y_k <= 0 read as "no alpha_i > eps_p".                    (Steps 5-6)
+ *   - entering ties: lowest variable index (slacks after structurals).
+ *   - ratio_i = max(xB_i, 0) / alpha_i (IEEE division); tied rows are those whose
+ *     ratio equals the minimum bit for bit.  Every tied row gives the same objective
+ *     change, so the paper's "most noticeable improvement" cannot separate them;
+ *     the tie is broken by the lowest row whose basic variable is not in the
+ *     tabu list L[q] of the entering variable q, and that leaving variable is then
+ *     appended to L[q].  If L[q] excludes every tied row, L[q] is cleared and the
+ *     lowest tied row is taken.                                  (Sections 2.2, 3.4)
+ *   - entering mask: a variable that leaves at iteration t may not enter at
+ *     iterations t+1 .. t+tenure; if every improving variable is masked, the
+ *     choice is made among all improving variables (aspiration).
+ *   - update rounding: row r := B^-1[r,:] / alpha_r (correctly rounded division);
+ *     rows i != r: fma(-alpha_i, rho_j, B^-1[i,j]); W_j := fma(d_q, rho_j, W_j);
+ *     xB_i := fma(-alpha_i, theta, xB_i), xB_r := theta; z := fma(d_q, theta, z);
+ *     afterwards every |xB_i| < eps_z is set to 0.            (Section 3.1)
+ *   - the iteration limit is checked after pricing: a basis that prices out optimal
+ *     is reported OPTIMAL even at the limit.
+ *
+ * Dot products are plain ascending-index fma chains.  Build with
+ * -ffp-contract=off so that no other operation is fused.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_RUNNING 0
+#define OR_OPTIMAL 1
+#define OR_UNBOUNDED 2
+#define OR_ITER_LIMIT 3
+
+#define FLAG_DEGENERATE 1  /* theta == 0 */
+#define FLAG_TIE 2         /* more than one row attains the minimum ratio */
+#define FLAG_ASPIRATION 4  /* every improving variable was masked */
+#define FLAG_LCLEAR 8      /* L[q] excluded every tied row and was cleared */
+
+typedef struct {
+  int32_t m, n, sense, tenure, use_llist;
+  double eps_d, eps_p, eps_z;
+  double *A;    /* m x n column-major: A[i + j*m] */
+  double *b, *c, *chat;
+  double *Binv; /* m x m row-major: Binv[i*m + j] */
+  double *xB, *W, *d, *alpha, *rho, *ratio;
+  double z;
+  int32_t *basis; /* basis[i] = variable basic in row i */
+  int32_t *pos;   /* pos[v] = row of basic variable v, -1 if nonbasic */
+  int64_t *tabu_until;
+  int32_t **L;    /* L[q]: leaving variables chosen on ties while q entered */
+  int32_t *L_len, *L_cap;
+  int64_t t;
+  int32_t status, ray;
+  int64_t n_degenerate, n_tie, n_aspiration, n_lclear;
+  int32_t *log_enter, *log_row, *log_leave, *log_flags;
+  int64_t log_len, log_cap;
+} oracle_lp;
+
+void oracle_destroy(oracle_lp *p);
+
+/* Returns NULL if arguments are invalid or memory runs out. */
+oracle_lp *oracle_create(int32_t m, int32_t n, const double *A_colmajor, const double *b, const double *c,
+                         int32_t sense, int32_t tenure, int32_t use_llist, double eps_d, double eps_p,
+                         double eps_z) {
+  if (m <= 0 || n < 0 || !A_colmajor || !b || !c) return NULL;
+  for (int32_t i = 0; i < m; ++i)
+    if (!(b[i] >= 0.0) || !isfinite(b[i])) return NULL;
+  oracle_lp *p = (oracle_lp *)calloc(1, sizeof(oracle_lp));
+  if (!p) return NULL;
+  int32_t N = n + m;
+  p->m = m; p->n = n; p->sense = sense; p->tenure = tenure; p->use_llist = use_llist;
+  p->eps_d = eps_d; p->eps_p = eps_p; p->eps_z = eps_z;
+  p->A = (double *)malloc(sizeof(double) * (size_t)m * (n > 0 ? n : 1));
+  p->b = (double *)malloc(sizeof(double) * m);
+  p->c = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+  p->chat = (double *)malloc(sizeof(double) * N);
+  p->Binv = (double *)calloc((size_t)m * m, sizeof(double));
+  p->xB = (double *)malloc(sizeof(double) * m);
+  p->W = (double *)calloc(m, sizeof(double));
+  p->d = (double *)malloc(sizeof(double) * N);
+  p->alpha = (double *)malloc(sizeof(double) * m);
+  p->rho = (double *)malloc(sizeof(double) * m);
+  p->ratio = (double *)malloc(sizeof(double) * m);
+  p->basis = (int32_t *)malloc(sizeof(int32_t) * m);
+  p->pos = (int32_t *)malloc(sizeof(int32_t) * N);
+  p->tabu_until = (int64_t *)malloc(sizeof(int64_t) * N);
+  p->L = (int32_t **)calloc(N, sizeof(int32_t *));
+  p->L_len = (int32_t *)calloc(N, sizeof(int32_t));
+  p->L_cap = (int32_t *)calloc(N, sizeof(int32_t));
+  if (!p->A || !p->b || !p->c || !p->chat || !p->Binv || !p->xB || !p->W || !p->d || !p->alpha || !p->rho ||
+      !p->ratio || !p->basis || !p->pos || !p->tabu_until || !p->L || !p->L_len || !p->L_cap) {
+    oracle_destroy(p);
+    return NULL;
+  }
+  memcpy(p->A, A_colmajor, sizeof(double) * (size_t)m * n);
+  memcpy(p->b, b, sizeof(double) * m);
+  memcpy(p->c, c, sizeof(double) * n);
+  double s = sense ? -1.0 : 1.0; /* sense 1 = max: minimise -c^T x */
+  for (int32_t j = 0; j < n; ++j) p->chat[j] = s * c[j];
+  for (int32_t i = 0; i < m; ++i) p->chat[n + i] = 0.0;
+  /* Step 1: the slack columns form B = I, feasible because b >= 0. */
+  for (int32_t i = 0; i < m; ++i) {
+    p->basis[i] = n + i;
+    p->Binv[(size_t)i * m + i] = 1.0;
+    p->xB[i] = b[i];
+  }
+  for (int32_t v = 0; v < N; ++v) { p->pos[v] = -1; p->tabu_until[v] = -1; }
+  for (int32_t i = 0; i < m; ++i) p->pos[n + i] = i;
+  p->z = 0.0;
+  p->t = 0;
+  p->status = OR_RUNNING;
+  p->ray = -1;
+  return p;
+}
+
+void oracle_destroy(oracle_lp *p) {
+  if (!p) return;
+  if (p->L)
+    for (int32_t v = 0; v < p->n + p->m; ++v) free(p->L[v]);
+  free(p->L); free(p->L_len); free(p->L_cap);
+  free(p->A); free(p->b); free(p->c); free(p->chat); free(p->Binv); free(p->xB); free(p->W);
+  free(p->d); free(p->alpha); free(p->rho); free(p->ratio); free(p->basis); free(p->pos);
+  free(p->tabu_until); free(p->log_enter); free(p->log_row); free(p->log_leave); free(p->log_flags);
+  free(p);
+}
+
+static int log_push(oracle_lp *p, int32_t q, int32_t r, int32_t l, int32_t flags) {
+  if (p->log_len == p->log_cap) {
+    int64_t cap = p->log_cap ? 2 * p->log_cap : 1024;
+    int32_t *a = (int32_t *)realloc(p->log_enter, sizeof(int32_t) * cap);
+    if (!a) return -1;
+    p->log_enter = a;
+    a = (int32_t *)realloc(p->log_row, sizeof(int32_t) * cap);
+    if (!a) return -1;
+    p->log_row = a;
+    a = (int32_t *)realloc(p->log_leave, sizeof(int32_t) * cap);
+    if (!a) return -1;
+    p->log_leave = a;
+    a = (int32_t *)realloc(p->log_flags, sizeof(int32_t) * cap);
+    if (!a) return -1;
+    p->log_flags = a;
+    p->log_cap = cap;
+  }
+  p->log_enter[p->log_len] = q;
+  p->log_row[p->log_len] = r;
+  p->log_leave[p->log_len] = l;
+  p->log_flags[p->log_len] = flags;
+  p->log_len++;
+  return 0;
+}
+
+static int in_list(const oracle_lp *p, int32_t q, int32_t v) {
+  for (int32_t k = 0; k < p->L_len[q]; ++k)
+    if (p->L[q][k] == v) return 1;
+  return 0;
+}
+
+static int list_add(oracle_lp *p, int32_t q, int32_t v) {
+  if (p->L_len[q] == p->L_cap[q]) {
+    int32_t cap = p->L_cap[q] ? 2 * p->L_cap[q] : 4;
+    int32_t *a = (int32_t *)realloc(p->L[q], sizeof(int32_t) * cap);
+    if (!a) return -1;
+    p->L[q] = a;
+    p->L_cap[q] = cap;
+  }
+  p->L[q][p->L_len[q]++] = v;
+  return 0;
+}
+
+/* One iteration (Steps 3-8).  Returns the status after it. */
+static int32_t iterate(oracle_lp *p, int64_t max_iter) {
+  const int32_t m = p->m, n = p->n, N = n + m;
+
+  /* Step 3: reduced costs d_j = chat_j - W a_j of every nonbasic variable. */
+  for (int32_t j = 0; j < N; ++j) {
+    if (p->pos[j] >= 0) continue;
+    if (j < n) {
+      const double *a = p->A + (size_t)j * m;
+      double s = 0.0;
+      for (int32_t i = 0; i < m; ++i) s = fma(p->W[i], a[i], s);
+      p->d[j] = p->chat[j] - s;
+    } else {
+      p->d[j] = p->chat[j] - p->W[j - n]; /* a_{n+i} = e_i */
+    }
+  }
+
+  /* Step 4: Dantzig choice, most negative d_j, with the entering mask. */
+  int32_t q_all = -1, q_free = -1;
+  for (int32_t j = 0; j < N; ++j) {
+    if (p->pos[j] >= 0 || !(p->d[j] < -p->eps_d)) continue;
+    if (q_all < 0 || p->d[j] < p->d[q_all]) q_all = j; /* strict: lowest index wins ties */
+    if (p->tabu_until[j] < p->t && (q_free < 0 || p->d[j] < p->d[q_free])) q_free = j;
+  }
+  if (q_all < 0) return OR_OPTIMAL;
+  if (p->t >= max_iter) return OR_ITER_LIMIT;
+  int32_t flags = 0;
+  int32_t q = q_free;
+  if (q < 0) { q = q_all; flags |= FLAG_ASPIRATION; p->n_aspiration++; }
+  const double dq = p->d[q];
+
+  /* Step 5: FTRAN, Y_k = B^-1 a_q. */
+  for (int32_t i = 0; i < m; ++i) {
+    const double *row = p->Binv + (size_t)i * m;
+    if (q < n) {
+      const double *a = p->A + (size_t)q * m;
+      double s = 0.0;
+      for (int32_t k = 0; k < m; ++k) s = fma(row[k], a[k], s);
+      p->alpha[i] = s;
+    } else {
+      p->alpha[i] = row[q - n];
+    }
+  }
+
+  /* Step 6: ratio test over rows with alpha_i > eps_p. */
+  double theta = INFINITY;
+  int32_t nR = 0;
+  for (int32_t i = 0; i < m; ++i) {
+    if (!(p->alpha[i] > p->eps_p)) continue;
+    nR++;
+    p->ratio[i] = fmax(p->xB[i], 0.0) / p->alpha[i];
+    if (p->ratio[i] < theta) theta = p->ratio[i];
+  }
+  if (nR == 0) { p->ray = q; return OR_UNBOUNDED; } /* Step 5: Y_k <= 0 */
+  int32_t nT = 0, r_low = -1, r_free = -1;
+  for (int32_t i = 0; i < m; ++i) {
+    if (!(p->alpha[i] > p->eps_p) || p->ratio[i] != theta) continue;
+    nT++;
+    if (r_low < 0) r_low = i;
+    if (r_free < 0 && !(p->use_llist && in_list(p, q, p->basis[i]))) r_free = i;
+  }
+  int32_t r = r_low;
+  if (nT >= 2) {
+    flags |= FLAG_TIE;
+    p->n_tie++;
+    if (p->use_llist) {
+      if (r_free < 0) { p->L_len[q] = 0; flags |= FLAG_LCLEAR; p->n_lclear++; }
+      else r = r_free;
+      if (list_add(p, q, p->basis[r])) return -1;
+    }
+  }
+  if (theta == 0.0) { flags |= FLAG_DEGENERATE; p->n_degenerate++; }
+
+  /* Step 7 and the tabu mask: the leaving variable may not re-enter for `tenure` iterations. */
+  const int32_t leave = p->basis[r];
+  if (p->tenure > 0) p->tabu_until[leave] = p->t + p->tenure;
+
+  /* Step 8 / Section 3.1: pivot the revised tableau on alpha_r. */
+  const double ar = p->alpha[r];
+  double *rowr = p->Binv + (size_t)r * m;
+  for (int32_t j = 0; j < m; ++j) p->rho[j] = rowr[j] / ar;
+  for (int32_t i = 0; i < m; ++i) {
+    double *row = p->Binv + (size_t)i * m;
+    if (i == r) {
+      for (int32_t j = 0; j < m; ++j) row[j] = p->rho[j];
+    } else {
+      const double na = -p->alpha[i];
+      for (int32_t j = 0; j < m; ++j) row[j] = fma(na, p->rho[j], row[j]);
+    }
+  }
+  for (int32_t j = 0; j < m; ++j) p->W[j] = fma(dq, p->rho[j], p->W[j]);
+  for (int32_t i = 0; i < m; ++i) p->xB[i] = (i == r) ? theta : fma(-p->alpha[i], theta, p->xB[i]);
+  for (int32_t i = 0; i < m; ++i)
+    if (fabs(p->xB[i]) < p->eps_z) p->xB[i] = 0.0;
+  p->z = fma(dq, theta, p->z);
+  p->basis[r] = q;
+  p->pos[q] = r;
+  p->pos[leave] = -1;
+  if (log_push(p, q, r, leave, flags)) return -1;
+  p->t++;
+  return OR_RUNNING;
+}
+
+/* Iterate until a terminal status or until the pivot count reaches max_iter.
+ * A handle stopped at the limit resumes from its state on the next call. */
+int32_t oracle_run(oracle_lp *p, int64_t max_iter) {
+  if (!p) return -1;
+  if (p->status == OR_ITER_LIMIT) p->status = OR_RUNNING;
+  while (p->status == OR_RUNNING) {
+    int32_t s = iterate(p, max_iter);
+    if (s < 0) return -1;
+    p->status = s;
+  }
+  return p->status;
+}
+
+int64_t oracle_iterations(const oracle_lp *p) { return p->t; }
+int32_t oracle_status(const oracle_lp *p) { return p->status; }
+int32_t oracle_ray(const oracle_lp *p) { return p->ray; }
+
+/* Objective in the user's sense: sum over structural basics of c_j x_j, ascending j. */
+double oracle_objective(const oracle_lp *p) {
+  double s = 0.0;
+  for (int32_t j = 0; j < p->n; ++j)
+    if (p->pos[j] >= 0) s += p->c[j] * p->xB[p->pos[j]];
+  return s;
+}
+
+/* x (n structural values), y (m duals in the user's sense: y = s*W), basis (m). Any may be NULL. */
+void oracle_solution(const oracle_lp *p, double *x, double *y, int32_t *basis) {
+  const double s = p->sense ? -1.0 : 1.0;
+  if (x)
+    for (int32_t j = 0; j < p->n; ++j) x[j] = p->pos[j] >= 0 ? p->xB[p->pos[j]] : 0.0;
+  if (y)
+    for (int32_t i = 0; i < p->m; ++i) y[i] = s * p->W[i];
+  if (basis) memcpy(basis, p->basis, sizeof(int32_t) * p->m);
+}
+
+/* Tableau state: Binv (m*m row-major), xB (m), W (m), z (min form). Any may be NULL. */
+void oracle_state(const oracle_lp *p, double *Binv, double *xB, double *W, double *z) {
+  if (Binv) memcpy(Binv, p->Binv, sizeof(double) * (size_t)p->m * p->m);
+  if (xB) memcpy(xB, p->xB, sizeof(double) * p->m);
+  if (W) memcpy(W, p->W, sizeof(double) * p->m);
+  if (z) *z = p->z;
+}
+
+/* Copies up to cap log entries; returns the total number logged. */
+int64_t oracle_pivots(const oracle_lp *p, int32_t *enter, int32_t *row, int32_t *leave, int32_t *flags,
+                      int64_t cap) {
+  int64_t k = p->log_len < cap ? p->log_len : cap;
+  if (enter) memcpy(enter, p->log_enter, sizeof(int32_t) * k);
+  if (row) memcpy(row, p->log_row, sizeof(int32_t) * k);
+  if (leave) memcpy(leave, p->log_leave, sizeof(int32_t) * k);
+  if (flags) memcpy(flags, p->log_flags, sizeof(int32_t) * k);
+  return p->log_len;
+}
+
+/* counts[0..3] = degenerate pivots, tie pivots, aspiration events, L[q] clears. */
+void oracle_counts(const oracle_lp *p, int64_t *counts) {
+  counts[0] = p->n_degenerate;
+  counts[1] = p->n_tie;
+  counts[2] = p->n_aspiration;
+  counts[3] = p->n_lclear;
+}

@@ -1,0 +1,100 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case plants one mistake in a temporary copy of the oracle's C source (a dropped
+term, a wrong sign, a transposed operand, a wrong comparison, a missing tabu-list
+update), builds it with the oracle's own flags, and checks that the pins used in
+test_oracle_pins reject it.  Everything runs on the CPU."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+from test_oracle_pins import _embedded
+from lputil import assert_kkt, brute_force, replay_check
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "simplex_oracle.c")
+
+MUTANTS = {
+    "dropped_cost_term": ("p->d[j] = p->chat[j] - s;", "p->d[j] = -s;"),
+    "W_update_sign": ("p->W[j] = fma(dq, p->rho[j], p->W[j]);", "p->W[j] = fma(-dq, p->rho[j], p->W[j]);"),
+    "ftran_transposed": ("s = fma(row[k], a[k], s);", "s = fma(p->Binv[(size_t)k * m + i], a[k], s);"),
+    "xB_update_sign": ("fma(-p->alpha[i], theta, p->xB[i])", "fma(p->alpha[i], theta, p->xB[i])"),
+    "entering_argmax": ("(q_free < 0 || p->d[j] < p->d[q_free])", "(q_free < 0 || p->d[j] > p->d[q_free])"),
+    "aspiration_argmax": ("if (q_all < 0 || p->d[j] < p->d[q_all]) q_all = j;",
+                          "if (q_all < 0 || p->d[j] > p->d[q_all]) q_all = j;"),
+    "no_entering_mask": ("if (p->tenure > 0) p->tabu_until[leave] = p->t + p->tenure;", "(void)leave;"),
+    "ratio_argmax": ("if (p->ratio[i] < theta) theta = p->ratio[i];",
+                     "if (theta == INFINITY || p->ratio[i] > theta) theta = p->ratio[i];"),
+    "pivot_row_not_divided": ("p->rho[j] = rowr[j] / ar;", "p->rho[j] = rowr[j];"),
+    "no_leaving_list_append": ("if (list_add(p, q, p->basis[r])) return -1;", "(void)0;"),
+    "slack_price_wrong_index": ("p->d[j] = p->chat[j] - p->W[j - n];", "p->d[j] = p->chat[j] - p->W[0];"),
+}
+
+
+def _build(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / f"lib{name}.so"
+    subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", str(so), str(path), "-lm"])
+    return str(so)
+
+
+def _pins_pass(lib_path):
+    """A compact run of the pins; returns False as soon as one rejects the build."""
+    import json
+    from scipy.optimize import linprog
+    try:
+        rng = np.random.default_rng(11)
+        for k in range(12):
+            m, n = 3, 4
+            vals = np.array([-1.0, 0.0, 1.0, 2.0, 0.5])
+            A = rng.choice(vals, size=(m, n)) + 0.1 * rng.random((m, n))
+            A[0] = 0.5 + rng.random(n)
+            b = rng.integers(0, 4, size=m).astype(float)
+            b[0] = 3.0
+            c = rng.random(n) * 3 - 0.5
+            r = oracle.solve(A, b, c, lib_path=lib_path, max_iter=500)
+            best, _ = brute_force(A, b, c)
+            if r.status != oracle.OPTIMAL or abs(r.objective - best) > 1e-9 * (1 + abs(best)):
+                return False
+            assert_kkt(A, b, c, r.x, r.y)
+        for seed in range(2):
+            A, b, c = lpgen.dense_lp(seed, 30, 60)
+            r = oracle.solve(A, b, c, lib_path=lib_path, max_iter=2000)
+            ref = linprog(-c, A_ub=A, b_ub=b, method="highs")
+            if r.status != oracle.OPTIMAL or abs(r.objective + ref.fun) > 1e-9 * abs(ref.fun):
+                return False
+            assert_kkt(A, b, c, r.x, r.y)
+            replay_check(A, b, c, r.enter, r.row)
+        for name in ("beale", "chvatal"):
+            Ae, be, ce = _embedded(name)
+            r = oracle.solve(Ae, be, ce, lib_path=lib_path, max_iter=2000)
+            if r.status != oracle.OPTIMAL:
+                return False
+            replay_check(Ae, be, ce, r.enter, r.row)
+        with open(os.path.join(os.path.dirname(__file__), "golden", "cycling_lps.json")) as f:
+            d = json.load(f)["beale"]
+        A, b, c = np.array(d["A"], float), np.array(d["b"], float), np.array(d["c"], float)
+        r = oracle.solve(A, b, c, lib_path=lib_path, max_iter=200)
+        if r.status != oracle.OPTIMAL or abs(r.objective - d["optimum"]) > 1e-12:
+            return False
+    except AssertionError:
+        return False
+    return True
+
+
+def test_unmutated_source_passes(tmp_path):
+    so = tmp_path / "liborig.so"
+    subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", str(so), SRC, "-lm"])
+    assert _pins_pass(str(so))
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    assert not _pins_pass(_build(tmp_path, name, old, new)), f"pins did not catch mutant {name}"
