@@ -1,0 +1,159 @@
+/*
+ * lpgpu: dense revised simplex with an explicit basis inverse on one MI355X (gfx950).
+ *
+ * The LP is the standard form of Raeisi Gahrouei & Ghatee, "Effective Implementation
+ * of GPU-based Revised Simplex algorithm applying new memory management and cycle
+ * avoidance strategies" (arXiv 1803.04378), Section 2.1:
+ *
+ *     optimise  c^T x   s.t.  A' x + s = b,  x >= 0,  s >= 0,  b >= 0,
+ *
+ * with A' an m x n dense matrix and s the m slack variables, so that A = (A', I_m).
+ * Variables are numbered 0..n-1 (structural) and n..n+m-1 (slack of row i is n+i).
+ * The solver starts from the slack basis (feasible because b >= 0) and runs the
+ * iteration of Section 2.1, Steps 3-8, with the Dantzig entering rule, the tabu
+ * rule of Sections 2.2/3.4, and the tableau update of Section 3.1 applied to an
+ * explicitly stored B^-1 that lives in device memory for the whole solve (the
+ * "Case 1" memory layout of Section 3).
+ *
+ * All functions are thread-compatible, not thread-safe: one handle must not be used
+ * from two threads at once.  No function aborts or throws; failures are reported as
+ * negative return codes, and lp_error_string() describes the most recent failure of
+ * the calling thread.
+ */
+#ifndef LPGPU_H
+#define LPGPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes (negative = error) ---- */
+#define LP_OK 0
+#define LP_ERR_ARG (-1)     /* NULL pointer, m <= 0, n < 0, non-finite data, size above the build limit */
+#define LP_ERR_NEG_RHS (-2) /* some b_i < 0: the slack basis is infeasible (no Phase 1 in this library) */
+#define LP_ERR_NOMEM (-3)   /* device or pinned host memory could not be allocated */
+#define LP_ERR_DEVICE (-4)  /* a HIP runtime call failed (no GPU, bad stream, launch failure) */
+#define LP_ERR_STATE (-5)   /* the handle is not in a state that allows the call */
+
+/* ---- solve status ---- */
+#define LP_RUNNING 0
+#define LP_OPTIMAL 1    /* no nonbasic reduced cost below -eps_d (Step 4) */
+#define LP_UNBOUNDED 2  /* the entering column has no entry alpha_i > eps_p (Step 5) */
+#define LP_ITER_LIMIT 3 /* max_iter pivots done and the basis is not optimal; lp_solve resumes */
+
+/* ---- pivot-log flags ---- */
+#define LP_PIVOT_DEGENERATE 1 /* step length theta == 0 */
+#define LP_PIVOT_TIE 2        /* several rows are within the tie tolerance of the minimum ratio (Step 6) */
+#define LP_PIVOT_ASPIRATION 4 /* every improving variable was tabu; chosen among all of them */
+#define LP_PIVOT_LCLEAR 8     /* the tabu list of the entering variable excluded every tied row */
+
+#define LP_MIN 0
+#define LP_MAX 1
+
+/* Largest m this build accepts: B^-1 pivot row and entering column are staged in LDS. */
+#define LP_MAX_ROWS 10176
+
+typedef struct lp_options {
+  int32_t sense;          /* LP_MIN or LP_MAX (default LP_MAX) */
+  int32_t tabu_tenure;    /* a leaving variable may not re-enter for this many pivots (default 5; 0 = off) */
+  int32_t leaving_list;   /* 1 = tie rows are broken by the entering variable's tabu list (default 1) */
+  int32_t iters_per_sync; /* iterations issued per status read-back (default 16) */
+  int64_t max_iter;       /* pivot limit for lp_solve (default 0 = 10*(m+n)) */
+  double eps_d;           /* optimality tolerance on reduced costs (default 1e-9) */
+  double eps_p;           /* pivot tolerance: rows with alpha_i > eps_p are ratio candidates (1e-9) */
+  double eps_z;           /* after each pivot |x_B,i| < eps_z is set to 0 (default 1e-12) */
+  double eps_t;           /* rows with ratio <= theta_min + eps_t*max(1,theta_min) are tied (default 1e-11) */
+  int32_t record_pivots;  /* 1 = keep the pivot log readable by lp_get_pivots (default 1) */
+  int32_t profile;        /* 1 = time every pricing and update kernel with HIP events (default 0) */
+  void *stream;           /* hipStream_t to run on; NULL = a stream owned by the handle */
+} lp_options;
+
+typedef struct lp_stats {
+  int64_t iterations;       /* pivots done */
+  int64_t degenerate;       /* pivots with theta == 0 */
+  int64_t ties;             /* pivots with a tie in the ratio test */
+  int64_t aspirations;      /* pivots whose entering variable was tabu */
+  int64_t list_clears;      /* tabu lists cleared because they excluded every tied row */
+  int64_t syncs;            /* status read-backs (one per batch of iters_per_sync iterations) */
+  double solve_ms;          /* host wall time spent inside lp_solve calls */
+  int64_t price_launches;   /* pricing kernels timed (profile = 1 only) */
+  double price_ms;          /* their summed duration */
+  int64_t update_launches;  /* update kernels timed (profile = 1 only) */
+  double update_ms;         /* their summed duration */
+  double price_bytes;       /* algorithmic bytes of those pricing launches: 8*m per priced column */
+  double update_bytes;      /* algorithmic bytes of those update launches: 16*m*m (8*m*m if no pivot pending) */
+} lp_stats;
+
+typedef struct lp_problem lp_problem;
+
+/* Fills *opt with the defaults listed above.  Returns LP_OK or LP_ERR_ARG (opt NULL). */
+int lp_default_options(lp_options *opt);
+
+/*
+ * Creates a problem from host arrays (Section 2.1 statement).
+ *   A_colmajor: m*n doubles, entry (i,j) at A_colmajor[i + j*m]; b: m doubles (all >= 0);
+ *   c: n doubles; opt: NULL for defaults.  The arrays are copied to device memory owned
+ *   by the handle; the caller keeps ownership of its arrays.
+ * Errors: LP_ERR_ARG, LP_ERR_NEG_RHS (checked before any device call), LP_ERR_NOMEM,
+ * LP_ERR_DEVICE.  On error *out is set to NULL and nothing is leaked.
+ */
+int lp_create(lp_problem **out, int32_t m, int32_t n, const double *A_colmajor, const double *b,
+              const double *c, const lp_options *opt);
+
+/*
+ * Same as lp_create, but A_colmajor, b and c are device pointers of the current device
+ * (for example the data of torch tensors).  The library copies them into its own
+ * padded device layout before returning and never frees them; the caller may release
+ * them once the call has returned.  Non-finite values and b_i < 0 are detected on the
+ * device and reported as LP_ERR_ARG / LP_ERR_NEG_RHS.
+ */
+int lp_create_device(lp_problem **out, int32_t m, int32_t n, const double *A_colmajor, const double *b,
+                     const double *c, const lp_options *opt);
+
+/* Runs Steps 3-8 until OPTIMAL, UNBOUNDED, or opt.max_iter pivots in total.  *status_out
+ * receives the LP_* status.  After LP_ITER_LIMIT a further call continues from the
+ * device state.  Returns LP_OK or an error code. */
+int lp_solve(lp_problem *p, int32_t *status_out);
+
+/* As lp_solve, with the total pivot limit given by iter_cap instead of opt.max_iter. */
+int lp_solve_until(lp_problem *p, int64_t iter_cap, int32_t *status_out);
+
+/* Returns the problem to the slack basis and clears the pivot log and statistics
+ * (the LP data are kept). */
+int lp_reset(lp_problem *p);
+
+/*
+ * Copies the current solution to host buffers (any may be NULL):
+ *   objective: sum of c_j x_j over structural basics (user's sense);
+ *   x: n structural values; y: m row duals in the user's sense (y = c_B^T B^-1);
+ *   basis: m variable ids (basis[i] is basic in row i); iterations: pivots done.
+ */
+int lp_get_solution(const lp_problem *p, double *objective, double *x, double *y, int32_t *basis,
+                    int64_t *iterations);
+
+/* Copies up to `capacity` pivot-log entries (oldest first) into the host arrays (any may
+ * be NULL) and stores the number of entries in *count. */
+int lp_get_pivots(const lp_problem *p, int32_t *entering, int32_t *leaving_row, int32_t *leaving_var,
+                  int32_t *flags, int64_t capacity, int64_t *count);
+
+/* Copies the revised tableau of Figure 1: Binv (m*m, row-major), x_B (m), W = chat_B^T B^-1
+ * (m, minimisation form), z = chat_B^T x_B.  Any pointer may be NULL. */
+int lp_get_tableau(const lp_problem *p, double *Binv, double *xB, double *W, double *z);
+
+int lp_get_stats(const lp_problem *p, lp_stats *s);
+
+/* Frees every device and host resource of the handle.  NULL-safe. */
+void lp_destroy(lp_problem *p);
+
+/* Text for a return code; for an error returned by the calling thread's most recent
+ * call, the text also names the failing step.  The pointer stays valid until the next
+ * lpgpu call on this thread. */
+const char *lp_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPGPU_H */

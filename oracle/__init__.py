@@ -48,7 +48,7 @@ def lib(path: str | None = None):
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int32)
         L.oracle_create.restype = P
-        L.oracle_create.argtypes = [I32, I32, dp, dp, dp, I32, I32, I32, D, D, D]
+        L.oracle_create.argtypes = [I32, I32, dp, dp, dp, I32, I32, I32, D, D, D, D]
         L.oracle_destroy.argtypes = [P]
         L.oracle_run.restype = I32
         L.oracle_run.argtypes = [P, I64]
@@ -101,7 +101,7 @@ class Oracle:
     """One LP held by the oracle; run() may be called repeatedly (resume)."""
 
     def __init__(self, A, b, c, sense="max", tenure=5, leaving_list=True, eps_d=1e-9, eps_p=1e-9,
-                 eps_z=1e-12, lib_path=None):
+                 eps_z=1e-12, eps_t=1e-11, lib_path=None):
         self._L = lib(lib_path)
         A = np.asarray(A, dtype=np.float64)
         m, n = A.shape
@@ -112,7 +112,7 @@ class Oracle:
         assert self._b.shape == (m,) and self._c.shape == (n,)
         s = {"min": 0, "max": 1}[sense]
         self._h = self._L.oracle_create(m, n, _dp(self._A), _dp(self._b), _dp(self._c), s, int(tenure),
-                                      int(bool(leaving_list)), eps_d, eps_p, eps_z)
+                                      int(bool(leaving_list)), eps_d, eps_p, eps_z, eps_t)
         if not self._h:
             raise ValueError("oracle_create rejected the LP (m<=0, negative or non-finite b, or no memory)")
 

@@ -25,13 +25,16 @@
  *     the paper's z_j - c_j equals -d_j.                        (Steps 3-4)
  *   - Y_k <= 0 read as "no alpha_i > eps_p".                    (Steps 5-6)
  *   - entering ties: lowest variable index (slacks after structurals).
- *   - ratio_i = max(xB_i, 0) / alpha_i (IEEE division); tied rows are those whose
- *     ratio equals the minimum bit for bit.  Every tied row gives the same objective
- *     change, so the paper's "most noticeable improvement" cannot separate them;
- *     the tie is broken by the lowest row whose basic variable is not in the
- *     tabu list L[q] of the entering variable q, and that leaving variable is then
- *     appended to L[q].  If L[q] excludes every tied row, L[q] is cleared and the
- *     lowest tied row is taken.                                  (Sections 2.2, 3.4)
+ *   - ratio_i = max(xB_i, 0) / alpha_i (IEEE division), theta_min = min ratio_i.
+ *     "No unique leaving element" (Sections 2.2, 3.4) is a statement about exact
+ *     ratios; in FP64 rounding splits such ties by a few ulps, so the tied rows are
+ *     those with ratio_i <= theta_min + eps_t * max(1, theta_min).  Every tied row
+ *     gives the same objective change, so the paper's "most noticeable improvement"
+ *     cannot separate them; the tie is broken by the lowest row whose basic variable
+ *     is not in the tabu list L[q] of the entering variable q, and that leaving
+ *     variable is then appended to L[q].  If L[q] excludes every tied row, L[q] is
+ *     cleared and the lowest tied row is taken.  The pivot itself is Step 8's:
+ *     theta = ratio_r of the chosen row r.
  *   - entering mask: a variable that leaves at iteration t may not enter at
  *     iterations t+1 .. t+tenure; if every improving variable is masked, the
  *     choice is made among all improving variables (aspiration).
@@ -56,13 +59,13 @@
 #define OR_ITER_LIMIT 3
 
 #define FLAG_DEGENERATE 1  /* theta == 0 */
-#define FLAG_TIE 2         /* more than one row attains the minimum ratio */
+#define FLAG_TIE 2         /* more than one row is within the tie tolerance of the minimum ratio */
 #define FLAG_ASPIRATION 4  /* every improving variable was masked */
 #define FLAG_LCLEAR 8      /* L[q] excluded every tied row and was cleared */
 
 typedef struct {
   int32_t m, n, sense, tenure, use_llist;
-  double eps_d, eps_p, eps_z;
+  double eps_d, eps_p, eps_z, eps_t;
   double *A;    /* m x n column-major: A[i + j*m] */
   double *b, *c, *chat;
   double *Binv; /* m x m row-major: Binv[i*m + j] */
@@ -85,7 +88,7 @@ void oracle_destroy(oracle_lp *p);
 /* Returns NULL if arguments are invalid or memory runs out. */
 oracle_lp *oracle_create(int32_t m, int32_t n, const double *A_colmajor, const double *b, const double *c,
                          int32_t sense, int32_t tenure, int32_t use_llist, double eps_d, double eps_p,
-                         double eps_z) {
+                         double eps_z, double eps_t) {
   if (m <= 0 || n < 0 || !A_colmajor || !b || !c) return NULL;
   for (int32_t i = 0; i < m; ++i)
     if (!(b[i] >= 0.0) || !isfinite(b[i])) return NULL;
@@ -93,7 +96,7 @@ oracle_lp *oracle_create(int32_t m, int32_t n, const double *A_colmajor, const d
   if (!p) return NULL;
   int32_t N = n + m;
   p->m = m; p->n = n; p->sense = sense; p->tenure = tenure; p->use_llist = use_llist;
-  p->eps_d = eps_d; p->eps_p = eps_p; p->eps_z = eps_z;
+  p->eps_d = eps_d; p->eps_p = eps_p; p->eps_z = eps_z; p->eps_t = eps_t;
   p->A = (double *)malloc(sizeof(double) * (size_t)m * (n > 0 ? n : 1));
   p->b = (double *)malloc(sizeof(double) * m);
   p->c = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
@@ -236,18 +239,19 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
   }
 
   /* Step 6: ratio test over rows with alpha_i > eps_p. */
-  double theta = INFINITY;
+  double theta_min = INFINITY;
   int32_t nR = 0;
   for (int32_t i = 0; i < m; ++i) {
     if (!(p->alpha[i] > p->eps_p)) continue;
     nR++;
     p->ratio[i] = fmax(p->xB[i], 0.0) / p->alpha[i];
-    if (p->ratio[i] < theta) theta = p->ratio[i];
+    if (p->ratio[i] < theta_min) theta_min = p->ratio[i];
   }
   if (nR == 0) { p->ray = q; return OR_UNBOUNDED; } /* Step 5: Y_k <= 0 */
+  const double tie_bound = theta_min + p->eps_t * fmax(1.0, theta_min);
   int32_t nT = 0, r_low = -1, r_free = -1;
   for (int32_t i = 0; i < m; ++i) {
-    if (!(p->alpha[i] > p->eps_p) || p->ratio[i] != theta) continue;
+    if (!(p->alpha[i] > p->eps_p) || !(p->ratio[i] <= tie_bound)) continue;
     nT++;
     if (r_low < 0) r_low = i;
     if (r_free < 0 && !(p->use_llist && in_list(p, q, p->basis[i]))) r_free = i;
@@ -262,6 +266,7 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
       if (list_add(p, q, p->basis[r])) return -1;
     }
   }
+  const double theta = p->ratio[r];
   if (theta == 0.0) { flags |= FLAG_DEGENERATE; p->n_degenerate++; }
 
   /* Step 7 and the tabu mask: the leaving variable may not re-enter for `tenure` iterations. */

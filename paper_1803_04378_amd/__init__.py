@@ -1,0 +1,10 @@
+"""MI355X-native dense revised simplex (explicit B^-1) behind the lpgpu C ABI.
+
+The product path is liblpgpu.so (HIP kernels for gfx950 + C runtime); this package
+only loads it and marshals arguments.  See include/lpgpu.h for the ABI.
+"""
+from .binding import (LP, LP_ITER_LIMIT, LP_MAX, LP_MIN, LP_OPTIMAL, LP_RUNNING, LP_UNBOUNDED, LPError,
+                      STATUS_NAMES, default_options, lib)
+
+__all__ = ["LP", "LPError", "default_options", "lib", "LP_OPTIMAL", "LP_UNBOUNDED", "LP_ITER_LIMIT",
+           "LP_RUNNING", "LP_MAX", "LP_MIN", "STATUS_NAMES"]

@@ -1,0 +1,214 @@
+"""ctypes binding of liblpgpu.so: the C ABI of include/lpgpu.h, argument marshalling only.
+
+Every step of the simplex iteration runs in the library's HIP kernels.  The library is
+loaded from this package directory; if it is missing, importing raises instead of
+falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblpgpu.so")
+
+LP_OK, LP_ERR_ARG, LP_ERR_NEG_RHS, LP_ERR_NOMEM, LP_ERR_DEVICE, LP_ERR_STATE = 0, -1, -2, -3, -4, -5
+LP_RUNNING, LP_OPTIMAL, LP_UNBOUNDED, LP_ITER_LIMIT = 0, 1, 2, 3
+LP_PIVOT_DEGENERATE, LP_PIVOT_TIE, LP_PIVOT_ASPIRATION, LP_PIVOT_LCLEAR = 1, 2, 4, 8
+LP_MIN, LP_MAX = 0, 1
+LP_MAX_ROWS = 10176
+STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT"}
+
+
+class lp_options(C.Structure):
+    _fields_ = [
+        ("sense", C.c_int32),
+        ("tabu_tenure", C.c_int32),
+        ("leaving_list", C.c_int32),
+        ("iters_per_sync", C.c_int32),
+        ("max_iter", C.c_int64),
+        ("eps_d", C.c_double),
+        ("eps_p", C.c_double),
+        ("eps_z", C.c_double),
+        ("eps_t", C.c_double),
+        ("record_pivots", C.c_int32),
+        ("profile", C.c_int32),
+        ("stream", C.c_void_p),
+    ]
+
+
+class lp_stats(C.Structure):
+    _fields_ = [
+        ("iterations", C.c_int64),
+        ("degenerate", C.c_int64),
+        ("ties", C.c_int64),
+        ("aspirations", C.c_int64),
+        ("list_clears", C.c_int64),
+        ("syncs", C.c_int64),
+        ("solve_ms", C.c_double),
+        ("price_launches", C.c_int64),
+        ("price_ms", C.c_double),
+        ("update_launches", C.c_int64),
+        ("update_ms", C.c_double),
+        ("price_bytes", C.c_double),
+        ("update_bytes", C.c_double),
+    ]
+
+
+class LPError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {lib().lp_error_string(code).decode()} (code {code})")
+
+
+_lib = None
+
+# Every function include/lpgpu.h declares, with (restype, argtypes).
+_P = C.c_void_p
+_DP = C.POINTER(C.c_double)
+_IP = C.POINTER(C.c_int32)
+_LP = C.POINTER(C.c_int64)
+SIGNATURES = {
+    "lp_default_options": (C.c_int, [C.POINTER(lp_options)]),
+    "lp_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, _DP, _DP, _DP, C.POINTER(lp_options)]),
+    "lp_create_device": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, _P, _P, _P, C.POINTER(lp_options)]),
+    "lp_solve": (C.c_int, [_P, _IP]),
+    "lp_solve_until": (C.c_int, [_P, C.c_int64, _IP]),
+    "lp_reset": (C.c_int, [_P]),
+    "lp_get_solution": (C.c_int, [_P, _DP, _DP, _DP, _IP, _LP]),
+    "lp_get_pivots": (C.c_int, [_P, _IP, _IP, _IP, _IP, C.c_int64, _LP]),
+    "lp_get_tableau": (C.c_int, [_P, _DP, _DP, _DP, _DP]),
+    "lp_get_stats": (C.c_int, [_P, C.POINTER(lp_stats)]),
+    "lp_destroy": (None, [_P]),
+    "lp_error_string": (C.c_char_p, [C.c_int]),
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is not built; run __graft_entry__.build() or "
+                              "python paper_1803_04378_amd/build.py")
+        L = C.CDLL(_LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code, where):
+    if code != LP_OK:
+        raise LPError(code, where)
+
+
+def default_options(**kw) -> lp_options:
+    o = lp_options()
+    _check(lib().lp_default_options(C.byref(o)), "lp_default_options")
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_DP)
+
+
+class LP:
+    """One LP held on the GPU (an lp_problem handle)."""
+
+    def __init__(self, A=None, b=None, c=None, *, device_tensors=None, sense="max", **opts):
+        o = default_options(sense=LP_MAX if sense == "max" else LP_MIN, **opts)
+        h = _P()
+        if device_tensors is not None:
+            dA, db, dc, m, n = device_tensors
+            rc = lib().lp_create_device(C.byref(h), m, n, dA, db, dc, C.byref(o))
+        else:
+            A = np.asfortranarray(np.asarray(A, dtype=np.float64))
+            b = np.ascontiguousarray(b, dtype=np.float64)
+            c = np.ascontiguousarray(c, dtype=np.float64)
+            m, n = A.shape
+            if b.shape != (m,) or c.shape != (n,):
+                raise ValueError("shapes of A, b, c do not match")
+            self._keep = (A, b, c)
+            rc = lib().lp_create(C.byref(h), m, n, _dptr(A), _dptr(b), _dptr(c), C.byref(o))
+        _check(rc, "lp_create")
+        self._h = h
+        self.m, self.n = m, n
+        self.options = o
+
+    @classmethod
+    def from_torch(cls, A, b, c, **kw):
+        """A, b, c: float64 CUDA tensors; A of shape (m, n) in column-major memory order
+        (A.t().contiguous().t(), i.e. stride (1, m))."""
+        m, n = A.shape
+        if A.dtype != b.dtype or A.dtype != c.dtype or str(A.dtype) != "torch.float64":
+            raise TypeError("tensors must be float64")
+        if not (A.is_cuda and b.is_cuda and c.is_cuda):
+            raise TypeError("tensors must be on the GPU")
+        if n > 1 and A.stride() != (1, m):
+            raise ValueError("A must be column-major: stride (1, m)")
+        return cls(device_tensors=(A.data_ptr(), b.data_ptr(), c.data_ptr(), m, n), **kw)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().lp_destroy(h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def solve(self, max_iter=None) -> int:
+        st = C.c_int32()
+        if max_iter is None:
+            _check(lib().lp_solve(self._h, C.byref(st)), "lp_solve")
+        else:
+            _check(lib().lp_solve_until(self._h, int(max_iter), C.byref(st)), "lp_solve_until")
+        return st.value
+
+    def reset(self):
+        _check(lib().lp_reset(self._h), "lp_reset")
+
+    def solution(self):
+        obj = C.c_double()
+        x = np.empty(self.n)
+        y = np.empty(self.m)
+        basis = np.empty(self.m, dtype=np.int32)
+        it = C.c_int64()
+        _check(lib().lp_get_solution(self._h, C.byref(obj), _dptr(x), _dptr(y), basis.ctypes.data_as(_IP),
+                                     C.byref(it)), "lp_get_solution")
+        return dict(objective=obj.value, x=x, y=y, basis=basis, iterations=it.value)
+
+    def pivots(self):
+        cnt = C.c_int64()
+        _check(lib().lp_get_pivots(self._h, None, None, None, None, 0, C.byref(cnt)), "lp_get_pivots")
+        k = cnt.value
+        arrs = [np.empty(k, dtype=np.int32) for _ in range(4)]
+        _check(lib().lp_get_pivots(self._h, *[a.ctypes.data_as(_IP) for a in arrs], k, C.byref(cnt)),
+               "lp_get_pivots")
+        return dict(enter=arrs[0], row=arrs[1], leave=arrs[2], flags=arrs[3])
+
+    def tableau(self):
+        m = self.m
+        Binv = np.empty((m, m))
+        xB = np.empty(m)
+        W = np.empty(m)
+        z = C.c_double()
+        _check(lib().lp_get_tableau(self._h, _dptr(Binv), _dptr(xB), _dptr(W), C.byref(z)), "lp_get_tableau")
+        return Binv, xB, W, z.value
+
+    def stats(self) -> dict:
+        s = lp_stats()
+        _check(lib().lp_get_stats(self._h, C.byref(s)), "lp_get_stats")
+        return {f: getattr(s, f) for f, _ in lp_stats._fields_}

@@ -1,0 +1,555 @@
+// Host runtime and C ABI of lpgpu (declared in include/lpgpu.h).
+//
+// The handle owns the device state of one LP.  An iteration is the kernel pair
+// k_price -> k_update; lp_solve captures iters_per_sync such pairs once into a HIP
+// graph and replays it, reading back only the small control block after each replay
+// (the status scalar plus counters).  The kernels themselves stop doing work once the
+// status leaves RUNNING, so a replay that overshoots the end of the solve is harmless.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lp_device.h"
+#include "lpgpu.h"
+
+using namespace lpgpu;
+
+namespace {
+
+thread_local std::string g_msg;
+thread_local int g_code = 0;
+
+int fail(int code, const std::string& msg) {
+  g_code = code;
+  g_msg = msg;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return fail(LP_ERR_NOMEM, std::string(what) + ": " + hipGetErrorString(e));
+  return fail(LP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                   \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return fail_hip(e_, what); \
+  } while (0)
+
+int64_t round_up(int64_t x, int64_t k) { return (x + k - 1) / k * k; }
+
+}  // namespace
+
+struct lp_problem {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  lp_options opt{};
+  int32_t m = 0, n = 0, ld = 0;
+  DevLP d{};
+  std::vector<void*> allocs;
+  double* b0 = nullptr;  // device copies of b and c, kept for lp_reset
+  double* c0 = nullptr;
+  std::vector<double> hc;  // host copy of c for the reported objective
+  Ctrl* h_ctrl = nullptr;  // pinned mirror of the control block
+  Ctrl* h_stage = nullptr; // pinned staging for host -> device control writes
+  int num_cu = 0;
+  int price_grid = 1, update_grid = 1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_k = 0;
+  std::vector<hipEvent_t> events;
+  lp_stats stats{};
+};
+
+namespace {
+
+template <class T>
+hipError_t dalloc(lp_problem* p, T** out, size_t count) {
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return e;
+  }
+  p->allocs.push_back(ptr);
+  *out = static_cast<T*>(ptr);
+  return hipSuccess;
+}
+
+void dfree(lp_problem* p, void* ptr) {
+  if (!ptr) return;
+  auto it = std::find(p->allocs.begin(), p->allocs.end(), ptr);
+  if (it != p->allocs.end()) p->allocs.erase(it);
+  (void)hipFree(ptr);
+}
+
+void drop_graph(lp_problem* p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+  p->graph_k = 0;
+  for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+  p->events.clear();
+}
+
+void release(lp_problem* p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  drop_graph(p);
+  for (void* ptr : p->allocs) (void)hipFree(ptr);
+  p->allocs.clear();
+  if (p->h_ctrl) (void)hipHostFree(p->h_ctrl);
+  if (p->h_stage) (void)hipHostFree(p->h_stage);
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+int check_options(const lp_options* o) {
+  if (o->sense != LP_MIN && o->sense != LP_MAX) return fail(LP_ERR_ARG, "options.sense must be LP_MIN or LP_MAX");
+  if (o->tabu_tenure < 0) return fail(LP_ERR_ARG, "options.tabu_tenure must be >= 0");
+  if (o->iters_per_sync < 1 || o->iters_per_sync > 4096)
+    return fail(LP_ERR_ARG, "options.iters_per_sync must be in [1, 4096]");
+  if (o->max_iter < 0) return fail(LP_ERR_ARG, "options.max_iter must be >= 0");
+  if (!(o->eps_d >= 0.0) || !(o->eps_p >= 0.0) || !(o->eps_z >= 0.0) || !(o->eps_t >= 0.0) ||
+      !std::isfinite(o->eps_d) || !std::isfinite(o->eps_p) || !std::isfinite(o->eps_z) || !std::isfinite(o->eps_t))
+    return fail(LP_ERR_ARG, "options.eps_* must be finite and >= 0");
+  return LP_OK;
+}
+
+// Pivot log and tabu-list storage sized for `cap` pivots; keeps existing entries.
+int ensure_capacity(lp_problem* p, int64_t cap) {
+  cap = std::max<int64_t>(cap, 1);
+  if (cap <= p->d.log_cap && cap <= p->d.Lcap) return LP_OK;
+  if (cap > INT32_MAX) return fail(LP_ERR_ARG, "pivot limit above 2^31-1");
+  const int64_t keep_log = std::min<int64_t>(p->h_ctrl ? p->h_ctrl->t : 0, p->d.log_cap);
+  const int64_t keep_L = p->h_ctrl ? std::min<int64_t>(p->h_ctrl->nL, p->d.Lcap) : 0;
+  int32_t* arrs[7] = {nullptr};
+  for (int k = 0; k < 7; ++k) HIP_TRY(dalloc(p, &arrs[k], (size_t)cap), "allocating the pivot log");
+  int32_t* old[7] = {p->d.log_enter, p->d.log_row, p->d.log_leave, p->d.log_flags, p->d.Lq, p->d.Ll, p->d.Lgen};
+  for (int k = 0; k < 7; ++k) {
+    const int64_t keep = k < 4 ? keep_log : keep_L;
+    if (old[k] && keep > 0)
+      HIP_TRY(hipMemcpyAsync(arrs[k], old[k], keep * sizeof(int32_t), hipMemcpyDeviceToDevice, p->stream),
+              "copying the pivot log");
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream), "copying the pivot log");
+  for (int k = 0; k < 7; ++k) dfree(p, old[k]);
+  p->d.log_enter = arrs[0];
+  p->d.log_row = arrs[1];
+  p->d.log_leave = arrs[2];
+  p->d.log_flags = arrs[3];
+  p->d.Lq = arrs[4];
+  p->d.Ll = arrs[5];
+  p->d.Lgen = arrs[6];
+  p->d.log_cap = cap;
+  p->d.Lcap = (int32_t)cap;
+  drop_graph(p);  // kernels captured the old pointers
+  return LP_OK;
+}
+
+int read_ctrl(lp_problem* p) {
+  HIP_TRY(hipMemcpyAsync(p->h_ctrl, p->d.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, p->stream), "reading status");
+  HIP_TRY(hipStreamSynchronize(p->stream), "reading status");
+  return LP_OK;
+}
+
+int build_graph(lp_problem* p) {
+  drop_graph(p);
+  const int K = p->opt.iters_per_sync;
+  const bool prof = p->opt.profile != 0;
+  if (prof) {
+    p->events.resize(2 * K + 1, nullptr);
+    for (auto& e : p->events) HIP_TRY(hipEventCreate(&e), "creating profiling events");
+  }
+  HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal), "capturing the iteration graph");
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < K && err == hipSuccess; ++k) {
+    if (prof) err = hipEventRecordWithFlags(p->events[2 * k], p->stream, hipEventRecordExternal);
+    if (err == hipSuccess) err = launch_price(p->d, p->price_grid, p->stream);
+    if (prof && err == hipSuccess) err = hipEventRecordWithFlags(p->events[2 * k + 1], p->stream, hipEventRecordExternal);
+    if (err == hipSuccess) err = launch_update(p->d, p->update_grid, p->stream);
+  }
+  if (prof && err == hipSuccess) err = hipEventRecordWithFlags(p->events[2 * K], p->stream, hipEventRecordExternal);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(p->stream, &g);
+  if (err != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail_hip(err != hipSuccess ? err : e2, "capturing the iteration graph");
+  }
+  p->graph = g;
+  HIP_TRY(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0), "instantiating the iteration graph");
+  p->graph_k = K;
+  return LP_OK;
+}
+
+int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const double* b, const double* c,
+                  const lp_options* opt, bool device_inputs) {
+  if (!out) return fail(LP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (m <= 0 || n < 0) return fail(LP_ERR_ARG, "need m > 0 and n >= 0");
+  if (m > LP_MAX_ROWS) return fail(LP_ERR_ARG, "m exceeds LP_MAX_ROWS of this build");
+  if ((int64_t)n + m > INT32_MAX / 2) return fail(LP_ERR_ARG, "n + m too large");
+  if (!b || (n > 0 && (!A || !c))) return fail(LP_ERR_ARG, "NULL data pointer");
+  lp_options o;
+  lp_default_options(&o);
+  if (opt) o = *opt;
+  if (int rc = check_options(&o)) return rc;
+  if (o.max_iter == 0) o.max_iter = 10 * ((int64_t)m + n);
+
+  std::vector<double> hb(m), hc(n);
+  if (!device_inputs) {
+    const size_t cnt = (size_t)m * n;
+    for (size_t k = 0; k < cnt; ++k)
+      if (!std::isfinite(A[k])) return fail(LP_ERR_ARG, "A contains a non-finite value");
+    for (int32_t i = 0; i < m; ++i) {
+      if (!std::isfinite(b[i])) return fail(LP_ERR_ARG, "b contains a non-finite value");
+      if (b[i] < 0.0) return fail(LP_ERR_NEG_RHS, "b_i < 0: the slack basis is infeasible");
+    }
+    for (int32_t j = 0; j < n; ++j)
+      if (!std::isfinite(c[j])) return fail(LP_ERR_ARG, "c contains a non-finite value");
+    std::memcpy(hb.data(), b, sizeof(double) * m);
+    if (n) std::memcpy(hc.data(), c, sizeof(double) * n);
+  }
+
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "selecting the device");
+  lp_problem* p = new (std::nothrow) lp_problem();
+  if (!p) return fail(LP_ERR_NOMEM, "host allocation failed");
+  int rc = LP_OK;
+  auto bail = [&](int code) {
+    release(p);
+    return code;
+  };
+  p->device = dev;
+  p->opt = o;
+  p->m = m;
+  p->n = n;
+  p->ld = (int32_t)round_up(m, 8);
+  const int ld = p->ld;
+  const int N = n + m;
+  if (o.stream) {
+    p->stream = static_cast<hipStream_t>(o.stream);
+  } else {
+    // A blocking stream: ordered after work the caller left on the legacy default stream.
+    hipError_t e = hipStreamCreate(&p->stream);
+    if (e != hipSuccess) return bail(fail_hip(e, "creating a stream"));
+    p->own_stream = true;
+  }
+  {
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return bail(fail_hip(e, "querying the device"));
+    p->num_cu = prop.multiProcessorCount;
+  }
+  int price_per_cu = 0, update_per_cu = 0;
+  {
+    hipError_t e = kernel_occupancy(&price_per_cu, &update_per_cu, ld);
+    if (e != hipSuccess) return bail(fail_hip(e, "querying kernel occupancy"));
+    if (price_per_cu < 1 || update_per_cu < 1) return bail(fail(LP_ERR_ARG, "m too large for the kernels' LDS"));
+  }
+  const int pw = kPriceBlock / 64, uw = kUpdateBlock / 64;
+  p->price_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)price_per_cu * p->num_cu, (n + pw - 1) / pw));
+  p->update_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)update_per_cu * p->num_cu, (m + uw - 1) / uw));
+
+  // Device memory: A' (ld x n) + B^-1 (m x ld) dominate.
+  {
+    size_t freeb = 0, totalb = 0;
+    hipError_t e = hipMemGetInfo(&freeb, &totalb);
+    if (e != hipSuccess) return bail(fail_hip(e, "querying device memory"));
+    const double need = 8.0 * ld * (double)n + 8.0 * m * (double)ld + 64.0 * N + 64.0 * ld + 64.0 * o.max_iter;
+    if (need > (double)freeb) return bail(fail(LP_ERR_NOMEM, "LP does not fit in free device memory"));
+  }
+  double* dA = nullptr;
+  double* chat = nullptr;
+#define ALLOC(ptr, cnt)                                                    \
+  do {                                                                     \
+    hipError_t e_ = dalloc(p, &(ptr), (cnt));                              \
+    if (e_ != hipSuccess) return bail(fail_hip(e_, "allocating " #ptr)); \
+  } while (0)
+  ALLOC(dA, (size_t)ld * std::max(n, 1));
+  ALLOC(chat, (size_t)N);
+  ALLOC(p->d.Binv, (size_t)m * ld);
+  ALLOC(p->d.xB, (size_t)m);
+  ALLOC(p->d.W, (size_t)ld);
+  ALLOC(p->d.rho, (size_t)ld);
+  ALLOC(p->d.alpha0, (size_t)m);
+  ALLOC(p->d.alpha1, (size_t)m);
+  ALLOC(p->d.basis, (size_t)m);
+  ALLOC(p->d.pos, (size_t)N);
+  ALLOC(p->d.tabu_until, (size_t)N);
+  ALLOC(p->d.gen, (size_t)N);
+  ALLOC(p->d.excl, (size_t)N);
+  ALLOC(p->d.part_d, 2 * (size_t)p->price_grid);
+  ALLOC(p->d.part_j, 2 * (size_t)p->price_grid);
+  ALLOC(p->d.ctrl, 1);
+  ALLOC(p->b0, (size_t)m);
+  ALLOC(p->c0, (size_t)std::max(n, 1));
+#undef ALLOC
+  p->d.m = m;
+  p->d.n = n;
+  p->d.ld = ld;
+  p->d.A = dA;
+  p->d.chat = chat;
+  p->d.tenure = o.tabu_tenure;
+  p->d.use_llist = o.leaving_list ? 1 : 0;
+  p->d.eps_d = o.eps_d;
+  p->d.eps_p = o.eps_p;
+  p->d.eps_z = o.eps_z;
+  p->d.eps_t = o.eps_t;
+  {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p->h_ctrl), sizeof(Ctrl), hipHostMallocDefault);
+    if (e != hipSuccess) return bail(fail_hip(e, "allocating pinned memory"));
+    std::memset(p->h_ctrl, 0, sizeof(Ctrl));
+    e = hipHostMalloc(reinterpret_cast<void**>(&p->h_stage), sizeof(Ctrl), hipHostMallocDefault);
+    if (e != hipSuccess) return bail(fail_hip(e, "allocating pinned memory"));
+    std::memset(p->h_stage, 0, sizeof(Ctrl));
+  }
+  if ((rc = ensure_capacity(p, o.max_iter)) != LP_OK) return bail(rc);
+
+  hipStream_t s = p->stream;
+  hipError_t e = hipMemsetAsync(dA, 0, sizeof(double) * (size_t)ld * std::max(n, 1), s);
+  if (e != hipSuccess) return bail(fail_hip(e, "clearing A"));
+  const hipMemcpyKind kind = device_inputs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (device_inputs) {
+    // Validate on the device, then bring b and c to the host for the sign check and
+    // the reported objective.
+    int32_t* flag = nullptr;
+    e = dalloc(p, &flag, 1);
+    if (e != hipSuccess) return bail(fail_hip(e, "allocating a flag"));
+    if ((e = hipMemsetAsync(flag, 0, sizeof(int32_t), s)) != hipSuccess) return bail(fail_hip(e, "validating"));
+    if ((e = launch_check_finite(A, (int64_t)m * n, flag, s)) != hipSuccess) return bail(fail_hip(e, "validating A"));
+    int32_t hflag = 0;
+    if ((e = hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(hb.data(), b, sizeof(double) * m, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (n > 0 && (e = hipMemcpyAsync(hc.data(), c, sizeof(double) * n, hipMemcpyDeviceToHost, s)) != hipSuccess) ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return bail(fail_hip(e, "reading the LP data"));
+    dfree(p, flag);
+    if (hflag) return bail(fail(LP_ERR_ARG, "A contains a non-finite value"));
+    for (int32_t i = 0; i < m; ++i) {
+      if (!std::isfinite(hb[i])) return bail(fail(LP_ERR_ARG, "b contains a non-finite value"));
+      if (hb[i] < 0.0) return bail(fail(LP_ERR_NEG_RHS, "b_i < 0: the slack basis is infeasible"));
+    }
+    for (int32_t j = 0; j < n; ++j)
+      if (!std::isfinite(hc[j])) return bail(fail(LP_ERR_ARG, "c contains a non-finite value"));
+  }
+  if (n > 0) {
+    e = hipMemcpy2DAsync(dA, sizeof(double) * ld, A, sizeof(double) * m, sizeof(double) * m, n, kind, s);
+    if (e != hipSuccess) return bail(fail_hip(e, "copying A"));
+    e = hipMemcpyAsync(p->c0, c, sizeof(double) * n, kind, s);
+    if (e != hipSuccess) return bail(fail_hip(e, "copying c"));
+  }
+  e = hipMemcpyAsync(p->b0, b, sizeof(double) * m, kind, s);
+  if (e != hipSuccess) return bail(fail_hip(e, "copying b"));
+  e = launch_init(p->d, p->b0, p->c0, o.sense == LP_MAX ? -1.0 : 1.0, s);
+  if (e != hipSuccess) return bail(fail_hip(e, "initialising the slack basis"));
+  if ((rc = read_ctrl(p)) != LP_OK) return bail(rc);
+  p->hc = std::move(hc);
+  *out = p;
+  return LP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lp_default_options(lp_options* opt) {
+  if (!opt) return fail(LP_ERR_ARG, "opt is NULL");
+  std::memset(opt, 0, sizeof(*opt));
+  opt->sense = LP_MAX;
+  opt->tabu_tenure = 5;
+  opt->leaving_list = 1;
+  opt->iters_per_sync = 16;
+  opt->max_iter = 0;
+  opt->eps_d = 1e-9;
+  opt->eps_p = 1e-9;
+  opt->eps_z = 1e-12;
+  opt->eps_t = 1e-11;
+  opt->record_pivots = 1;
+  opt->profile = 0;
+  opt->stream = nullptr;
+  return LP_OK;
+}
+
+int lp_create(lp_problem** out, int32_t m, int32_t n, const double* A_colmajor, const double* b, const double* c,
+              const lp_options* opt) {
+  return create_common(out, m, n, A_colmajor, b, c, opt, false);
+}
+
+int lp_create_device(lp_problem** out, int32_t m, int32_t n, const double* A_colmajor, const double* b,
+                     const double* c, const lp_options* opt) {
+  return create_common(out, m, n, A_colmajor, b, c, opt, true);
+}
+
+int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
+  if (!p) return fail(LP_ERR_ARG, "p is NULL");
+  if (iter_cap < 0) return fail(LP_ERR_ARG, "iter_cap must be >= 0");
+  int rc;
+  if (p->h_ctrl->status == LP_OPTIMAL || p->h_ctrl->status == LP_UNBOUNDED) {
+    if (status_out) *status_out = p->h_ctrl->status;
+    return LP_OK;
+  }
+  if ((rc = ensure_capacity(p, iter_cap)) != LP_OK) return rc;
+  if (!p->gexec || p->graph_k != p->opt.iters_per_sync) {
+    if ((rc = build_graph(p)) != LP_OK) return rc;
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  // Arm the control block: new pivot limit, and RUNNING again after an ITER_LIMIT stop.
+  p->h_stage->max_iter = iter_cap;
+  p->h_stage->status = LP_RUNNING;
+  HIP_TRY(hipMemcpyAsync(&p->d.ctrl->max_iter, &p->h_stage->max_iter, sizeof(int64_t), hipMemcpyHostToDevice,
+                         p->stream),
+          "arming the solve");
+  HIP_TRY(hipMemcpyAsync(&p->d.ctrl->status, &p->h_stage->status, sizeof(int32_t), hipMemcpyHostToDevice, p->stream),
+          "arming the solve");
+  const bool prof = p->opt.profile != 0;
+  const int K = p->graph_k;
+  for (;;) {
+    const int64_t t_before = p->h_ctrl->t;
+    const int64_t cols_before = p->h_ctrl->price_cols;
+    HIP_TRY(hipGraphLaunch(p->gexec, p->stream), "launching the iteration graph");
+    if ((rc = read_ctrl(p)) != LP_OK) return rc;
+    p->stats.syncs += 1;
+    if (prof && p->h_ctrl->status == LP_RUNNING && t_before > 0 && p->h_ctrl->t == t_before + K) {
+      // Steady state: every kernel of the replay did a full pass.
+      for (int k = 0; k < K; ++k) {
+        float ms_p = 0.f, ms_u = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms_p, p->events[2 * k], p->events[2 * k + 1]), "reading profile events");
+        HIP_TRY(hipEventElapsedTime(&ms_u, p->events[2 * k + 1], p->events[2 * k + 2]), "reading profile events");
+        p->stats.price_ms += ms_p;
+        p->stats.update_ms += ms_u;
+      }
+      p->stats.price_launches += K;
+      p->stats.update_launches += K;
+      p->stats.price_bytes += 8.0 * p->m * (double)(p->h_ctrl->price_cols - cols_before);
+      p->stats.update_bytes += 16.0 * (double)p->m * p->m * K;
+    }
+    if (p->h_ctrl->status != LP_RUNNING) break;
+    // Every replay of a RUNNING solve must pivot K times; anything else is a fault of the
+    // kernels' control logic, reported instead of looping.
+    if (p->h_ctrl->t != t_before + K)
+      return fail(LP_ERR_DEVICE, "iteration graph made no progress while RUNNING");
+  }
+  p->stats.solve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (status_out) *status_out = p->h_ctrl->status;
+  return LP_OK;
+}
+
+int lp_solve(lp_problem* p, int32_t* status_out) {
+  if (!p) return fail(LP_ERR_ARG, "p is NULL");
+  return lp_solve_until(p, p->opt.max_iter, status_out);
+}
+
+int lp_reset(lp_problem* p) {
+  if (!p) return fail(LP_ERR_ARG, "p is NULL");
+  HIP_TRY(launch_init(p->d, p->b0, p->c0, p->opt.sense == LP_MAX ? -1.0 : 1.0, p->stream), "resetting");
+  int rc = read_ctrl(p);
+  if (rc != LP_OK) return rc;
+  p->stats = lp_stats{};
+  return LP_OK;
+}
+
+int lp_get_solution(const lp_problem* pc, double* objective, double* x, double* y, int32_t* basis,
+                    int64_t* iterations) {
+  if (!pc) return fail(LP_ERR_ARG, "p is NULL");
+  lp_problem* p = const_cast<lp_problem*>(pc);
+  const int m = p->m, n = p->n;
+  std::vector<double> xB(m), W(m);
+  std::vector<int32_t> bas(m);
+  HIP_TRY(hipMemcpyAsync(xB.data(), p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
+  HIP_TRY(hipMemcpyAsync(W.data(), p->d.W, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading W");
+  HIP_TRY(hipMemcpyAsync(bas.data(), p->d.basis, sizeof(int32_t) * m, hipMemcpyDeviceToHost, p->stream),
+          "reading the basis");
+  HIP_TRY(hipStreamSynchronize(p->stream), "reading the solution");
+  std::vector<int32_t> row_of(n, -1);
+  for (int i = 0; i < m; ++i)
+    if (bas[i] < n) row_of[bas[i]] = i;
+  if (x)
+    for (int j = 0; j < n; ++j) x[j] = row_of[j] >= 0 ? xB[row_of[j]] : 0.0;
+  if (objective) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j)
+      if (row_of[j] >= 0) s += p->hc[j] * xB[row_of[j]];
+    *objective = s;
+  }
+  const double sgn = p->opt.sense == LP_MAX ? -1.0 : 1.0;
+  if (y)
+    for (int i = 0; i < m; ++i) y[i] = sgn * W[i];
+  if (basis) std::memcpy(basis, bas.data(), sizeof(int32_t) * m);
+  if (iterations) *iterations = p->h_ctrl->t;
+  return LP_OK;
+}
+
+int lp_get_pivots(const lp_problem* pc, int32_t* entering, int32_t* leaving_row, int32_t* leaving_var,
+                  int32_t* flags, int64_t capacity, int64_t* count) {
+  if (!pc) return fail(LP_ERR_ARG, "p is NULL");
+  if (capacity < 0) return fail(LP_ERR_ARG, "capacity must be >= 0");
+  lp_problem* p = const_cast<lp_problem*>(pc);
+  const int64_t have = std::min<int64_t>(p->h_ctrl->t, p->d.log_cap);
+  const int64_t k = std::min<int64_t>(have, capacity);
+  int32_t* dst[4] = {entering, leaving_row, leaving_var, flags};
+  int32_t* src[4] = {p->d.log_enter, p->d.log_row, p->d.log_leave, p->d.log_flags};
+  for (int a = 0; a < 4; ++a)
+    if (dst[a] && k > 0)
+      HIP_TRY(hipMemcpyAsync(dst[a], src[a], sizeof(int32_t) * k, hipMemcpyDeviceToHost, p->stream),
+              "reading the pivot log");
+  HIP_TRY(hipStreamSynchronize(p->stream), "reading the pivot log");
+  if (count) *count = have;
+  return LP_OK;
+}
+
+int lp_get_tableau(const lp_problem* pc, double* Binv, double* xB, double* W, double* z) {
+  if (!pc) return fail(LP_ERR_ARG, "p is NULL");
+  lp_problem* p = const_cast<lp_problem*>(pc);
+  const int m = p->m;
+  if (p->h_ctrl->r >= 0) return fail(LP_ERR_STATE, "a pivot is pending; call lp_solve to completion first");
+  if (Binv)
+    HIP_TRY(hipMemcpy2DAsync(Binv, sizeof(double) * m, p->d.Binv, sizeof(double) * p->ld, sizeof(double) * m, m,
+                             hipMemcpyDeviceToHost, p->stream),
+            "reading B^-1");
+  if (xB) HIP_TRY(hipMemcpyAsync(xB, p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
+  if (W) HIP_TRY(hipMemcpyAsync(W, p->d.W, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading W");
+  HIP_TRY(hipStreamSynchronize(p->stream), "reading the tableau");
+  if (z) *z = p->h_ctrl->z;
+  return LP_OK;
+}
+
+int lp_get_stats(const lp_problem* p, lp_stats* s) {
+  if (!p || !s) return fail(LP_ERR_ARG, "NULL argument");
+  *s = p->stats;
+  s->iterations = p->h_ctrl->t;
+  s->degenerate = p->h_ctrl->n_degenerate;
+  s->ties = p->h_ctrl->n_tie;
+  s->aspirations = p->h_ctrl->n_aspiration;
+  s->list_clears = p->h_ctrl->n_lclear;
+  return LP_OK;
+}
+
+void lp_destroy(lp_problem* p) { release(p); }
+
+const char* lp_error_string(int code) {
+  static thread_local std::string text;
+  const char* base = "unknown code";
+  switch (code) {
+    case LP_OK: base = "ok"; break;
+    case LP_ERR_ARG: base = "invalid argument"; break;
+    case LP_ERR_NEG_RHS: base = "negative right-hand side"; break;
+    case LP_ERR_NOMEM: base = "out of memory"; break;
+    case LP_ERR_DEVICE: base = "device error"; break;
+    case LP_ERR_STATE: base = "invalid state"; break;
+  }
+  text = base;
+  if (code != LP_OK && code == g_code && !g_msg.empty()) text += ": " + g_msg;
+  return text.c_str();
+}
+
+}  // extern "C"

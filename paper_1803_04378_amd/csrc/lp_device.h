@@ -1,0 +1,98 @@
+// Device-side state of one LP and the kernels of one simplex iteration (gfx950).
+//
+// Layout in HBM (all FP64 unless stated; ld = m rounded up to a multiple of 8, the
+// padding is zero and stays zero):
+//   A      ld x n   column-major: column j of A' is contiguous (pricing streams it)
+//   Binv   m x ld   row-major:    row i of B^-1 is contiguous (update + FTRAN stream it)
+//   W, rho ld       W = chat_B^T B^-1 (top row of the Figure 1 tableau), rho = pivot row / alpha_r
+//   xB, alpha[2]    m
+//   chat            n + m   (minimisation costs; slacks 0)
+//   basis (m), pos (n+m), tabu_until (n+m), the leaving-side tabu list, the pivot log: int32
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lpgpu {
+
+constexpr int kStatusRunning = 0;
+constexpr int kStatusOptimal = 1;
+constexpr int kStatusUnbounded = 2;
+constexpr int kStatusIterLimit = 3;
+
+constexpr int kFlagDegenerate = 1;
+constexpr int kFlagTie = 2;
+constexpr int kFlagAspiration = 4;
+constexpr int kFlagLClear = 8;
+
+constexpr int kPriceBlock = 512;
+constexpr int kUpdateBlock = 1024;
+
+// Control block: written only by the last workgroup of a kernel (or by the host between
+// solves), read by every workgroup of the next kernel.
+struct Ctrl {
+  int32_t status;
+  int32_t q;      // entering variable chosen by the latest pricing, -1 if none
+  int32_t r;      // row of the pivot whose B^-1 update is still pending, -1 if none
+  int32_t cur;    // alpha[cur] holds the pending pivot's entering column alpha
+  int64_t t;      // pivots done
+  int64_t max_iter;
+  double dq;      // reduced cost d_q of q
+  double z;       // objective chat_B^T x_B (minimisation form)
+  int32_t ray;    // entering column that proved unboundedness
+  int32_t nL;     // entries in the leaving-side tabu list
+  int32_t flags;  // pivot-log flags gathered for the pivot in progress
+  int32_t pad0;
+  uint32_t price_ticket;
+  uint32_t update_ticket;
+  int64_t n_degenerate, n_tie, n_aspiration, n_lclear;
+  int32_t nsb;   // structural variables in the basis
+  int32_t pad1;
+  int64_t price_launches;       // pricing passes that ran
+  int64_t price_cols;           // structural columns those passes streamed
+  int64_t update_launches;      // update passes that ran
+  int64_t update_rows_written;  // B^-1 rows those passes rewrote
+};
+
+struct DevLP {
+  int32_t m, n, ld, pad0;
+  const double* A;
+  const double* chat;
+  double* Binv;
+  double* xB;
+  double* W;
+  double* rho;
+  double* alpha0;
+  double* alpha1;
+  int32_t* basis;
+  int32_t* pos;
+  int32_t* tabu_until;
+  int32_t* gen;   // generation of each variable's tabu list (bumped to clear it)
+  int32_t* excl;  // scratch stamp per variable for list membership tests
+  int32_t* Lq;    // list entries: (entering q, leaving variable, generation of q's list)
+  int32_t* Ll;
+  int32_t* Lgen;
+  int32_t* log_enter;
+  int32_t* log_row;
+  int32_t* log_leave;
+  int32_t* log_flags;
+  double* part_d;  // pricing partials: 2 per workgroup (all improving, non-tabu improving)
+  int32_t* part_j;
+  Ctrl* ctrl;
+  int64_t log_cap;
+  int32_t Lcap;
+  int32_t tenure;
+  int32_t use_llist;
+  int32_t pad1;
+  double eps_d, eps_p, eps_z, eps_t;
+};
+
+// Launchers (lp_kernels.hip).  grid sizes are chosen by the caller.
+hipError_t launch_init(const DevLP& lp, const double* b, const double* c, double sense, hipStream_t s);
+hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s);
+hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s);
+hipError_t launch_check_finite(const double* x, int64_t count, int32_t* flag, hipStream_t s);
+size_t price_lds_bytes(int ld);
+size_t update_lds_bytes(int ld);
+hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld);
+
+}  // namespace lpgpu

@@ -1,0 +1,595 @@
+// Kernels of one dense revised simplex iteration for CDNA4 (gfx950, wave64).
+//
+// One iteration is two launches:
+//   k_price   Steps 3-4: reduced costs d_j = chat_j - W a_j of every nonbasic column
+//             (one wavefront per column of A', W staged in LDS), Dantzig choice with
+//             the tabu mask; the last workgroup to finish reduces the per-workgroup
+//             (d, j) minima and writes q, or the OPTIMAL / ITER_LIMIT status.
+//   k_update  Section 3.1 update of B^-1 for the pivot chosen in the previous
+//             iteration, fused with Step 5 (FTRAN, alpha = B^-1 a_q) for the column
+//             priced just before: one wavefront per row of B^-1 reads the row once,
+//             writes the updated row, and dots the new row with a_q on the fly.
+//             The last workgroup then runs Step 6 (ratio test, ties, tabu list) and
+//             the O(m) part of Step 8 (pivot row rho, W, x_B, z, basis, log).
+//
+// The B^-1 update of pivot t therefore runs in the same pass as the FTRAN of pivot
+// t+1.  This is legal because pricing for t+1 needs only W_{t+1} = W_t + d_q rho_t,
+// which the tail of the previous launch already holds; it removes one full read of
+// B^-1 per iteration.  Every element still gets the same arithmetic as in Step 8.
+//
+// Reductions are deterministic: each dot product is a fixed per-lane fma chain
+// followed by a fixed xor-butterfly, and every argmin is a lexicographic (value,
+// index) minimum, which does not depend on the order partials arrive in.  No
+// floating-point atomics are used.
+#include "lp_device.h"
+
+#include <limits.h>
+
+#include <algorithm>
+
+namespace lpgpu {
+
+namespace {
+
+constexpr int kUnroll = 8;
+
+__device__ __forceinline__ bool lex_less(double d1, int j1, double d2, int j2) {
+  return d1 < d2 || (d1 == d2 && j1 < j2);
+}
+
+__device__ __forceinline__ void wave_lexmin(double& d, int& j) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double d2 = __shfl_xor(d, off);
+    const int j2 = __shfl_xor(j, off);
+    if (lex_less(d2, j2, d, j)) {
+      d = d2;
+      j = j2;
+    }
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double a) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+  return a;
+}
+
+// Block-wide reductions.  Every thread of the block must call them.
+template <int BLOCK>
+__device__ void block_lexmin(double& d, int& j, double* sd, int* sj) {
+  constexpr int W = BLOCK / 64;
+  wave_lexmin(d, j);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sd[wave] = d;
+    sj[wave] = j;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    d = lane < W ? sd[lane] : __builtin_inf();
+    j = lane < W ? sj[lane] : INT_MAX;
+    wave_lexmin(d, j);
+    if (lane == 0) {
+      sd[0] = d;
+      sj[0] = j;
+    }
+  }
+  __syncthreads();
+  d = sd[0];
+  j = sj[0];
+}
+
+template <int BLOCK>
+__device__ double block_min(double v, double* sd, int* sj) {
+  int dummy = 0;
+  block_lexmin<BLOCK>(v, dummy, sd, sj);
+  return v;
+}
+
+template <int BLOCK>
+__device__ int block_min_int(int v, int* si) {
+  constexpr int W = BLOCK / 64;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) si[wave] = v;
+  __syncthreads();
+  if (wave == 0) {
+    v = lane < W ? si[lane] : INT_MAX;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+    if (lane == 0) si[0] = v;
+  }
+  __syncthreads();
+  return si[0];
+}
+
+template <int BLOCK>
+__device__ int block_sum_int(int v, int* si) {
+  constexpr int W = BLOCK / 64;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) si[wave] = v;
+  __syncthreads();
+  if (wave == 0) {
+    v = lane < W ? si[lane] : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) si[0] = v;
+  }
+  __syncthreads();
+  return si[0];
+}
+
+// Release this workgroup's global writes, take a ticket, and report whether this is
+// the last workgroup of the grid to arrive.  The last one acquires everyone's writes.
+__device__ bool arrive_last(uint32_t* ticket, int* s_flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    *s_flag = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = *s_flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// Dot product of a contiguous HBM vector with an LDS vector, both n2 double2 long.
+// Lane l accumulates elements l, l+64, ... in order; the butterfly then gives every
+// lane the same bits.
+__device__ __forceinline__ double wave_dot(const double2* __restrict__ x, const double2* y, int n2, int lane) {
+  double acc = 0.0;
+  int k = lane;
+  for (; k + 64 * (kUnroll - 1) < n2; k += 64 * kUnroll) {
+    double2 v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) v[u] = x[k + 64 * u];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const double2 w = y[k + 64 * u];
+      acc = fma(v[u].x, w.x, acc);
+      acc = fma(v[u].y, w.y, acc);
+    }
+  }
+  for (; k < n2; k += 64) {
+    const double2 v = x[k];
+    const double2 w = y[k];
+    acc = fma(v.x, w.x, acc);
+    acc = fma(v.y, w.y, acc);
+  }
+  return wave_sum(acc);
+}
+
+// row <- row + na * rho (in place), returning dot(new row, a) when DOT.
+template <bool DOT>
+__device__ __forceinline__ double wave_update_dot(double2* __restrict__ row, const double2* rho, const double2* a,
+                                                  double na, int n2, int lane) {
+  double acc = 0.0;
+  int k = lane;
+  for (; k + 64 * (kUnroll - 1) < n2; k += 64 * kUnroll) {
+    double2 v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) v[u] = row[k + 64 * u];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const double2 rr = rho[k + 64 * u];
+      v[u].x = fma(na, rr.x, v[u].x);
+      v[u].y = fma(na, rr.y, v[u].y);
+      row[k + 64 * u] = v[u];
+      if (DOT) {
+        const double2 w = a[k + 64 * u];
+        acc = fma(v[u].x, w.x, acc);
+        acc = fma(v[u].y, w.y, acc);
+      }
+    }
+  }
+  for (; k < n2; k += 64) {
+    double2 v = row[k];
+    const double2 rr = rho[k];
+    v.x = fma(na, rr.x, v.x);
+    v.y = fma(na, rr.y, v.y);
+    row[k] = v;
+    if (DOT) {
+      const double2 w = a[k];
+      acc = fma(v.x, w.x, acc);
+      acc = fma(v.y, w.y, acc);
+    }
+  }
+  return DOT ? wave_sum(acc) : 0.0;
+}
+
+// row r of the new B^-1 is rho itself: write it and (when DOT) dot it with a.
+template <bool DOT>
+__device__ __forceinline__ double wave_store_dot(double2* __restrict__ row, const double2* rho, const double2* a,
+                                                 int n2, int lane) {
+  double acc = 0.0;
+  for (int k = lane; k < n2; k += 64) {
+    const double2 v = rho[k];
+    row[k] = v;
+    if (DOT) {
+      const double2 w = a[k];
+      acc = fma(v.x, w.x, acc);
+      acc = fma(v.y, w.y, acc);
+    }
+  }
+  return DOT ? wave_sum(acc) : 0.0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// Slack basis (Step 1): B = I, x_B = b, W = 0, z = 0; chat = sense * c.
+__global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __restrict__ c, double sense) {
+  const int m = lp.m, n = lp.n, ld = lp.ld, N = n + m;
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t total = (size_t)m * ld;
+  for (size_t k = tid; k < total; k += stride) {
+    const size_t i = k / ld, j = k - i * ld;
+    lp.Binv[k] = (i == j) ? 1.0 : 0.0;
+  }
+  for (size_t k = tid; k < (size_t)ld; k += stride) {
+    lp.W[k] = 0.0;
+    lp.rho[k] = 0.0;
+  }
+  for (size_t i = tid; i < (size_t)m; i += stride) {
+    lp.xB[i] = b[i];
+    lp.basis[i] = n + (int)i;
+    lp.alpha0[i] = 0.0;
+    lp.alpha1[i] = 0.0;
+  }
+  double* chat = const_cast<double*>(lp.chat);
+  for (size_t v = tid; v < (size_t)N; v += stride) {
+    chat[v] = v < (size_t)n ? sense * c[v] : 0.0;
+    lp.pos[v] = v < (size_t)n ? -1 : (int)(v - n);
+    lp.tabu_until[v] = -1;
+    lp.gen[v] = 0;
+    lp.excl[v] = -1;
+  }
+  if (tid == 0) {
+    Ctrl* ctl = lp.ctrl;
+    *ctl = Ctrl{};
+    ctl->status = kStatusRunning;
+    ctl->q = -1;
+    ctl->r = -1;
+    ctl->ray = -1;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Steps 3-4.
+__global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
+  if (lp.ctrl->status != kStatusRunning) return;
+  const int64_t t = lp.ctrl->t;
+  extern __shared__ double2 s_w2[];
+  __shared__ double red_d[kPriceBlock / 64 + 8];
+  __shared__ int red_j[kPriceBlock / 64 + 8];
+  __shared__ int s_last;
+  const int m = lp.m, n = lp.n, ld2 = lp.ld / 2;
+  const double2* W2 = reinterpret_cast<const double2*>(lp.W);
+  for (int k = threadIdx.x; k < ld2; k += kPriceBlock) s_w2[k] = W2[k];
+  __syncthreads();
+  const double* s_w = reinterpret_cast<const double*>(s_w2);
+
+  constexpr int waves = kPriceBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * waves + (threadIdx.x >> 6);
+  const int nw = gridDim.x * waves;
+  const double neg_eps = -lp.eps_d;
+  double da = __builtin_inf(), df = __builtin_inf();
+  int ja = INT_MAX, jf = INT_MAX;
+  for (int j = gw; j < n; j += nw) {
+    if (lp.pos[j] >= 0) continue;
+    const double s = wave_dot(reinterpret_cast<const double2*>(lp.A + (size_t)j * lp.ld), s_w2, ld2, lane);
+    const double d = lp.chat[j] - s;
+    if (d < neg_eps) {
+      if (lex_less(d, j, da, ja)) {
+        da = d;
+        ja = j;
+      }
+      if (lp.tabu_until[j] < t && lex_less(d, j, df, jf)) {
+        df = d;
+        jf = j;
+      }
+    }
+  }
+  for (int i = blockIdx.x * kPriceBlock + threadIdx.x; i < m; i += gridDim.x * kPriceBlock) {
+    const int v = n + i;
+    if (lp.pos[v] >= 0) continue;
+    const double d = lp.chat[v] - s_w[i];  // a_{n+i} = e_i
+    if (d < neg_eps) {
+      if (lex_less(d, v, da, ja)) {
+        da = d;
+        ja = v;
+      }
+      if (lp.tabu_until[v] < t && lex_less(d, v, df, jf)) {
+        df = d;
+        jf = v;
+      }
+    }
+  }
+  block_lexmin<kPriceBlock>(da, ja, red_d, red_j);
+  block_lexmin<kPriceBlock>(df, jf, red_d, red_j);
+  if (threadIdx.x == 0) {
+    lp.part_d[2 * blockIdx.x] = da;
+    lp.part_j[2 * blockIdx.x] = ja;
+    lp.part_d[2 * blockIdx.x + 1] = df;
+    lp.part_j[2 * blockIdx.x + 1] = jf;
+  }
+  if (!arrive_last(&lp.ctrl->price_ticket, &s_last)) return;
+
+  da = df = __builtin_inf();
+  ja = jf = INT_MAX;
+  for (int k = threadIdx.x; k < (int)gridDim.x; k += kPriceBlock) {
+    const double d0 = lp.part_d[2 * k], d1 = lp.part_d[2 * k + 1];
+    const int j0 = lp.part_j[2 * k], j1 = lp.part_j[2 * k + 1];
+    if (lex_less(d0, j0, da, ja)) {
+      da = d0;
+      ja = j0;
+    }
+    if (lex_less(d1, j1, df, jf)) {
+      df = d1;
+      jf = j1;
+    }
+  }
+  block_lexmin<kPriceBlock>(da, ja, red_d, red_j);
+  block_lexmin<kPriceBlock>(df, jf, red_d, red_j);
+  if (threadIdx.x == 0) {
+    Ctrl* ctl = lp.ctrl;
+    ctl->price_ticket = 0;
+    ctl->price_cols += n - ctl->nsb;
+    ctl->price_launches += 1;
+    if (ja == INT_MAX) {
+      ctl->status = kStatusOptimal;
+      ctl->q = -1;
+    } else if (t >= ctl->max_iter) {
+      ctl->status = kStatusIterLimit;
+      ctl->q = -1;
+    } else if (jf != INT_MAX) {
+      ctl->q = jf;
+      ctl->dq = df;
+      ctl->flags = 0;
+    } else {
+      ctl->q = ja;
+      ctl->dq = da;
+      ctl->flags = kFlagAspiration;
+      ctl->n_aspiration += 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Step 6 and the O(m) part of Step 8, run by the last workgroup of k_update once the
+// whole new B^-1 and alpha = B^-1 a_q are in memory.
+__device__ void pivot_tail(const DevLP& lp, int q, const double* __restrict__ al, int cur, double* red_d,
+                           int* red_j) {
+  constexpr int B = kUpdateBlock;
+  Ctrl* ctl = lp.ctrl;
+  const int m = lp.m, tid = threadIdx.x;
+  const double eps_p = lp.eps_p;
+  const int64_t t = ctl->t;
+
+  double th = __builtin_inf();
+  for (int i = tid; i < m; i += B) {
+    const double a = al[i];
+    if (a > eps_p) {
+      const double rt = fmax(lp.xB[i], 0.0) / a;
+      if (rt < th) th = rt;
+    }
+  }
+  th = block_min<B>(th, red_d, red_j);
+  if (th == __builtin_inf()) {  // Step 5: Y_k <= 0
+    if (tid == 0) {
+      ctl->status = kStatusUnbounded;
+      ctl->ray = q;
+      ctl->q = -1;
+      ctl->r = -1;
+    }
+    return;
+  }
+  // Rows within the tie tolerance of the minimum ratio are tied (exact ties split by rounding).
+  const double tie_bound = th + lp.eps_t * fmax(1.0, th);
+  int cnt = 0, low = INT_MAX;
+  for (int i = tid; i < m; i += B) {
+    const double a = al[i];
+    if (a > eps_p && fmax(lp.xB[i], 0.0) / a <= tie_bound) {
+      ++cnt;
+      low = min(low, i);
+    }
+  }
+  cnt = block_sum_int<B>(cnt, red_j);
+  low = block_min_int<B>(low, red_j);
+  int r = low;
+  int flags = ctl->flags;
+  if (cnt >= 2) {
+    flags |= kFlagTie;
+    if (lp.use_llist) {
+      const int stamp = (int)t + 1;
+      const int g = lp.gen[q];
+      const int nL = ctl->nL;
+      for (int k = tid; k < nL; k += B)
+        if (lp.Lq[k] == q && lp.Lgen[k] == g) lp.excl[lp.Ll[k]] = stamp;
+      __syncthreads();
+      int fl = INT_MAX;
+      for (int i = tid; i < m; i += B) {
+        const double a = al[i];
+        if (a > eps_p && fmax(lp.xB[i], 0.0) / a <= tie_bound && lp.excl[lp.basis[i]] != stamp) fl = min(fl, i);
+      }
+      fl = block_min_int<B>(fl, red_j);
+      int gnew = g;
+      if (fl == INT_MAX) {
+        flags |= kFlagLClear;
+        gnew = g + 1;
+      } else {
+        r = fl;
+      }
+      if (tid == 0) {
+        if (gnew != g) lp.gen[q] = gnew;
+        if (nL < lp.Lcap) {
+          lp.Lq[nL] = q;
+          lp.Ll[nL] = lp.basis[r];
+          lp.Lgen[nL] = gnew;
+          ctl->nL = nL + 1;
+        }
+      }
+    }
+  }
+  // Step 8 pivots on row r: the step is r's own ratio.
+  const double ar = al[r];
+  th = fmax(lp.xB[r], 0.0) / ar;
+  if (th == 0.0) flags |= kFlagDegenerate;
+  __syncthreads();  // every thread has read xB[r] before x_B is rewritten
+
+  // Step 8 on the top row and the right-hand column of the tableau.
+  const double dq = ctl->dq;
+  const double* rowr = lp.Binv + (size_t)r * lp.ld;
+  for (int j = tid; j < m; j += B) {
+    const double rj = rowr[j] / ar;
+    lp.rho[j] = rj;
+    lp.W[j] = fma(dq, rj, lp.W[j]);
+  }
+  const double eps_z = lp.eps_z;
+  for (int i = tid; i < m; i += B) {
+    double x = (i == r) ? th : fma(-al[i], th, lp.xB[i]);
+    if (fabs(x) < eps_z) x = 0.0;
+    lp.xB[i] = x;
+  }
+  if (tid == 0) {
+    const int leave = lp.basis[r];
+    if (lp.tenure > 0) lp.tabu_until[leave] = (int)(t + lp.tenure);
+    ctl->z = fma(dq, th, ctl->z);
+    lp.basis[r] = q;
+    lp.pos[q] = r;
+    lp.pos[leave] = -1;
+    ctl->nsb += (q < lp.n ? 1 : 0) - (leave < lp.n ? 1 : 0);
+    if (t < lp.log_cap) {
+      lp.log_enter[t] = q;
+      lp.log_row[t] = r;
+      lp.log_leave[t] = leave;
+      lp.log_flags[t] = flags;
+    }
+    if (flags & kFlagTie) ctl->n_tie += 1;
+    if (flags & kFlagLClear) ctl->n_lclear += 1;
+    if (flags & kFlagDegenerate) ctl->n_degenerate += 1;
+    ctl->t = t + 1;
+    ctl->r = r;
+    ctl->cur = cur ^ 1;
+    ctl->q = -1;
+    ctl->flags = 0;
+  }
+}
+
+// Section 3.1 update of the pending pivot fused with Step 5 for the newly priced q.
+__global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
+  const int r = lp.ctrl->r, q = lp.ctrl->q;
+  if (r < 0 && q < 0) return;
+  const int cur = lp.ctrl->cur;
+  const double* __restrict__ al_p = cur ? lp.alpha1 : lp.alpha0;  // pending pivot's alpha
+  double* __restrict__ al_n = cur ? lp.alpha0 : lp.alpha1;        // FTRAN result for q
+  extern __shared__ double2 smem2[];
+  __shared__ double red_d[kUpdateBlock / 64 + 8];
+  __shared__ int red_j[kUpdateBlock / 64 + 8];
+  __shared__ int s_last;
+  const int m = lp.m, n = lp.n, ld2 = lp.ld / 2;
+  double2* s_rho = smem2;
+  double2* s_a = smem2 + ld2;
+  if (r >= 0) {
+    const double2* rho2 = reinterpret_cast<const double2*>(lp.rho);
+    for (int k = threadIdx.x; k < ld2; k += kUpdateBlock) s_rho[k] = rho2[k];
+  }
+  if (q >= 0) {
+    if (q < n) {
+      const double2* a2 = reinterpret_cast<const double2*>(lp.A + (size_t)q * lp.ld);
+      for (int k = threadIdx.x; k < ld2; k += kUpdateBlock) s_a[k] = a2[k];
+    } else {
+      const int e = q - n;
+      for (int k = threadIdx.x; k < ld2; k += kUpdateBlock)
+        s_a[k] = make_double2(2 * k == e ? 1.0 : 0.0, 2 * k + 1 == e ? 1.0 : 0.0);
+    }
+  }
+  __syncthreads();
+
+  constexpr int waves = kUpdateBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * waves + (threadIdx.x >> 6);
+  const int nw = gridDim.x * waves;
+  for (int i = gw; i < m; i += nw) {
+    double2* row = reinterpret_cast<double2*>(lp.Binv + (size_t)i * lp.ld);
+    double acc;
+    if (r < 0) {
+      acc = wave_dot(row, s_a, ld2, lane);
+    } else if (i == r) {
+      acc = q >= 0 ? wave_store_dot<true>(row, s_rho, s_a, ld2, lane) : wave_store_dot<false>(row, s_rho, s_a, ld2, lane);
+    } else {
+      const double na = -al_p[i];
+      acc = q >= 0 ? wave_update_dot<true>(row, s_rho, s_a, na, ld2, lane)
+                   : wave_update_dot<false>(row, s_rho, s_a, na, ld2, lane);
+    }
+    if (q >= 0 && lane == 0) al_n[i] = acc;
+  }
+  if (!arrive_last(&lp.ctrl->update_ticket, &s_last)) return;
+  if (threadIdx.x == 0) {
+    lp.ctrl->update_ticket = 0;
+    lp.ctrl->update_launches += 1;
+    lp.ctrl->update_rows_written += (r >= 0) ? m : 0;
+    lp.ctrl->r = -1;
+  }
+  if (q >= 0) pivot_tail(lp, q, al_n, cur, red_d, red_j);
+}
+
+__global__ void k_check_finite(const double* __restrict__ x, int64_t count, int32_t* flag) {
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (size_t k = tid; k < (size_t)count; k += stride) bad |= !isfinite(x[k]);
+  if (bad) *flag = 1;
+}
+
+// ---------------------------------------------------------------------------------------
+size_t price_lds_bytes(int ld) { return sizeof(double) * (size_t)ld; }
+size_t update_lds_bytes(int ld) { return 2 * sizeof(double) * (size_t)ld; }
+
+hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_price),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)price_lds_bytes(ld));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)update_lds_bytes(ld));
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(price_per_cu, k_price, kPriceBlock, price_lds_bytes(ld));
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update, kUpdateBlock, update_lds_bytes(ld));
+}
+
+hipError_t launch_init(const DevLP& lp, const double* b, const double* c, double sense, hipStream_t s) {
+  const size_t work = (size_t)lp.m * lp.ld;
+  const int grid = (int)std::min<size_t>(4096, (work + 255) / 256 + 1);
+  hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, s, lp, b, c, sense);
+  return hipGetLastError();
+}
+
+hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_price, dim3(grid), dim3(kPriceBlock), price_lds_bytes(lp.ld), s, lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(grid), dim3(kUpdateBlock), update_lds_bytes(lp.ld), s, lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double* x, int64_t count, int32_t* flag, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>(2048, (count + 255) / 256);
+  hipLaunchKernelGGL(k_check_finite, dim3(grid), dim3(256), 0, s, x, count, flag);
+  return hipGetLastError();
+}
+
+}  // namespace lpgpu

@@ -1,0 +1,89 @@
+"""The C-ABI library loads and exports every symbol its header declares; host-side argument
+checks run without a GPU (no compute calls here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1803_04378_amd as lpg
+from paper_1803_04378_amd import binding
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lpgpu.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lp_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    names = _declared()
+    assert {"lp_create", "lp_solve", "lp_get_solution", "lp_destroy"} <= set(names)
+    L = lpg.lib()
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in binding.SIGNATURES, f"binding lacks {name}"
+    assert set(binding.SIGNATURES) == set(names)
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    consts = dict(re.findall(r"#define (LP_[A-Z_]+) \(?(-?\d+)\)?", text))
+    for k, v in consts.items():
+        if hasattr(binding, k):
+            assert getattr(binding, k) == int(v), k
+
+
+def test_struct_layouts():
+    assert C.sizeof(binding.lp_options) == 72
+    assert C.sizeof(binding.lp_stats) == 104
+
+
+def test_default_options():
+    o = lpg.default_options()
+    assert o.sense == binding.LP_MAX and o.tabu_tenure == 5 and o.leaving_list == 1
+    assert o.eps_d == 1e-9 and o.eps_p == 1e-9 and o.eps_z == 1e-12 and o.eps_t == 1e-11 and o.max_iter == 0
+    assert lpg.lib().lp_default_options(None) == binding.LP_ERR_ARG
+
+
+def _create(m, n, A, b, c, opt=None):
+    h = C.c_void_p()
+    rc = lpg.lib().lp_create(C.byref(h), m, n, A, b, c, opt)
+    return rc, h
+
+
+def test_argument_errors_need_no_gpu():
+    L = lpg.lib()
+    A = np.ones((3, 2), order="F")
+    b = np.ones(3)
+    c = np.ones(2)
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    assert _create(0, 2, dp(A), dp(b), dp(c))[0] == binding.LP_ERR_ARG
+    assert _create(3, -1, dp(A), dp(b), dp(c))[0] == binding.LP_ERR_ARG
+    assert _create(3, 2, None, dp(b), dp(c))[0] == binding.LP_ERR_ARG
+    assert _create(binding.LP_MAX_ROWS + 1, 2, dp(A), dp(b), dp(c))[0] == binding.LP_ERR_ARG
+    bn = b.copy()
+    bn[1] = -1.0
+    rc, h = _create(3, 2, dp(A), dp(bn), dp(c))
+    assert rc == binding.LP_ERR_NEG_RHS and not h.value
+    assert "negative" in L.lp_error_string(rc).decode()
+    An = A.copy(order="F")
+    An[2, 1] = np.inf
+    assert _create(3, 2, dp(An), dp(b), dp(c))[0] == binding.LP_ERR_ARG
+    o = lpg.default_options(iters_per_sync=0)
+    assert _create(3, 2, dp(A), dp(b), dp(c), C.byref(o))[0] == binding.LP_ERR_ARG
+    o = lpg.default_options(sense=7)
+    assert _create(3, 2, dp(A), dp(b), dp(c), C.byref(o))[0] == binding.LP_ERR_ARG
+    assert L.lp_solve(None, None) == binding.LP_ERR_ARG
+    L.lp_destroy(None)  # NULL-safe
+    with pytest.raises(lpg.LPError):
+        lpg.LP(A, bn, c)
+
+
+def test_error_strings():
+    L = lpg.lib()
+    for code in (0, -1, -2, -3, -4, -5, 99):
+        assert isinstance(L.lp_error_string(code), bytes)

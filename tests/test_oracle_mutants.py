@@ -26,8 +26,8 @@ MUTANTS = {
     "aspiration_argmax": ("if (q_all < 0 || p->d[j] < p->d[q_all]) q_all = j;",
                           "if (q_all < 0 || p->d[j] > p->d[q_all]) q_all = j;"),
     "no_entering_mask": ("if (p->tenure > 0) p->tabu_until[leave] = p->t + p->tenure;", "(void)leave;"),
-    "ratio_argmax": ("if (p->ratio[i] < theta) theta = p->ratio[i];",
-                     "if (theta == INFINITY || p->ratio[i] > theta) theta = p->ratio[i];"),
+    "ratio_argmax": ("if (p->ratio[i] < theta_min) theta_min = p->ratio[i];",
+                     "if (theta_min == INFINITY || p->ratio[i] > theta_min) theta_min = p->ratio[i];"),
     "pivot_row_not_divided": ("p->rho[j] = rowr[j] / ar;", "p->rho[j] = rowr[j];"),
     "no_leaving_list_append": ("if (list_add(p, q, p->basis[r])) return -1;", "(void)0;"),
     "slack_price_wrong_index": ("p->d[j] = p->chat[j] - p->W[j - n];", "p->d[j] = p->chat[j] - p->W[0];"),

@@ -276,3 +276,18 @@ def test_rejects_bad_input():
     bad[1] = np.nan
     with pytest.raises(ValueError):
         oracle.Oracle(A, bad, c)
+
+
+def test_rounding_split_tie_is_a_tie():
+    """Two rows whose exact ratios are equal but whose FP64 ratios differ by an ulp form a
+    tie (Sections 2.2/3.4: no unique leaving element); the lowest row leaves."""
+    b = np.array([0.1 * 3, 0.1])  # 0.30000000000000004 / 3 != 0.1 in FP64
+    assert b[0] / 3.0 != b[1]
+    A = np.array([[3.0], [1.0]])
+    r = oracle.solve(A, b, np.array([1.0]))
+    assert r.row[0] == 0 and r.flags[0] & oracle.FLAG_TIE
+    assert abs(r.objective - b[0] / 3.0) == 0.0  # Step 8 pivots on row 0: x = b_0 / 3
+    # a gap well above the tolerance is not a tie: the smaller ratio leaves
+    b2 = np.array([0.3 * (1 + 1e-9), 0.1])
+    r2 = oracle.solve(A, b2, np.array([1.0]))
+    assert r2.row[0] == 1 and not (r2.flags[0] & oracle.FLAG_TIE)
