@@ -1,0 +1,226 @@
+"""Benchmark of the dense revised simplex iteration on one MI355X.
+
+A step is one simplex iteration (pricing, FTRAN, ratio test, B^-1 update) of the dense
+LP  max c^T x  s.t.  A'x <= b, x >= 0  with m = 4000 rows and n = 8000 columns
+(A'_ij ~ U(0,1), b_i ~ U(1,10), c_j ~ U(1,10), seed 0), all data resident in HBM.
+W warm-up pivots run first, then exactly K pivots are timed, with HIP event nodes
+around every kernel of the iteration graph.  The printed line also carries the roofline
+of the dominant kernel, the time to optimality of the whole solve, and the CPU oracle's
+rate on a bounded sample of the same solve.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+_ROOT = os.path.dirname(os.path.abspath(__file__))
+if _ROOT not in sys.path:
+    sys.path.insert(0, _ROOT)
+
+METRIC = "simplex iter/s + solve time (m=4000,n=8000); batched LPs/s; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+KERNEL_NAMES = {"price": "k_price", "update": "k_update", "finish": "k_finish"}
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_steps(lp, k):
+    """Exactly k pivots from the current state; an LP that finishes early restarts from the
+    slack basis (inside the timed region)."""
+    remaining = k
+    while remaining > 0:
+        cur = lp.stats()["iterations"]
+        st = lp.solve(cur + remaining)
+        done = lp.stats()["iterations"] - cur
+        remaining -= done
+        if remaining > 0 and st != 3:  # finished before the target: start over
+            lp.reset()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch (read + write, copy-calibrated) recorded under profiles/ for the
+    current kernel source, or None if no summary matches it."""
+    import glob
+    import hashlib
+    src = os.path.join(_ROOT, "paper_1803_04378_amd", "csrc", "lp_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(_ROOT, "profiles", "*.md"))):
+        text = open(path).read()
+        for block in text.split("```json")[1:]:
+            try:
+                rec = json.loads(block.split("```")[0])
+            except ValueError:
+                continue
+            if rec.get("kernel_sha16") == sha and kernel in rec.get("traffic_bytes", {}):
+                return rec["traffic_bytes"][kernel]
+    return None
+
+
+def kernel_table(s0, s1):
+    out = {}
+    for name in KERNEL_NAMES:
+        launches = s1[f"{name}_launches"] - s0[f"{name}_launches"]
+        ms = s1[f"{name}_ms"] - s0[f"{name}_ms"]
+        if launches <= 0 or ms <= 0:
+            continue
+        avg_s = ms / launches * 1e-3
+        row = dict(launches=launches, avg_us=round(avg_s * 1e6, 3))
+        if name != "finish":
+            byts = (s1[f"{name}_bytes"] - s0[f"{name}_bytes"]) / launches
+            row.update(bytes_per_launch=byts, gbs=round(byts / avg_s / 1e9, 1))
+        out[name] = row
+    return out
+
+
+def timed_leg(lpg, torch, dev, opts, warmup, steps, profile):
+    with lpg.LP.from_torch(*dev, profile=profile, **opts) as lp:
+        run_steps(lp, warmup)
+        torch.cuda.synchronize()
+        s0 = lp.stats()
+        t0 = time.perf_counter()
+        run_steps(lp, steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s1 = lp.stats()
+    return t1 - t0, kernel_table(s0, s1)
+
+
+def solve_leg(lpg, torch, dev, opts):
+    with lpg.LP.from_torch(*dev, **opts) as lp:
+        lp.solve(1)  # graph built, caches warm
+        lp.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = lp.solve()
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        sol = lp.solution()
+    return dict(status=lpg.STATUS_NAMES[st], seconds=round(ts, 5), iterations=sol["iterations"],
+                objective=sol["objective"], iter_per_s=round(sol["iterations"] / ts, 1))
+
+
+def cpu_baseline(A, b, c, pivots):
+    import oracle
+    o = oracle.Oracle(A, b, c)
+    t0 = time.perf_counter()
+    o.run(pivots)
+    dt = time.perf_counter() - t0
+    done = o.iterations
+    return dict(value=round(done / dt, 3), unit="iter/s", cores=1, kind="oracle",
+                sample=f"first {done} pivots of the m={A.shape[0]},n={A.shape[1]} solve, single thread, "
+                       f"{dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--m", type=int, default=4000)
+    ap.add_argument("--n", type=int, default=8000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--iters-per-sync", type=int, default=16)
+    ap.add_argument("--cpu-pivots", type=int, default=100, help="oracle sample size (0 = skip)")
+    ap.add_argument("--quick", action="store_true",
+                    help="timed leg only (no cross-check, time-to-optimality or CPU legs); for profiler runs")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="finally copy a buffer of this many MiB three times: a kernel of known traffic "
+                         "for scaling hardware byte counters")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of this "
+              "path is a design note, not a built component.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import lpgen
+    import paper_1803_04378_amd as lpg
+
+    m, n = args.m, args.n
+    _log(f"bench: generating dense LP m={m} n={n} seed={args.seed}")
+    A, b, c = lpgen.dense_lp(args.seed, m, n)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        dA = torch.from_numpy(A.T).to("cuda").t()  # (m, n), column-major
+        db = torch.from_numpy(b).cuda()
+        dc = torch.from_numpy(c).cuda()
+    torch.cuda.synchronize()
+    dev = (dA, db, dc)
+    opts = dict(iters_per_sync=args.iters_per_sync, stream=stream.cuda_stream)
+
+    _log(f"bench: timed leg warmup={args.warmup} steps={args.steps}")
+    elapsed, kern = timed_leg(lpg, torch, dev, opts, args.warmup, args.steps, profile=1)
+    value = args.steps / elapsed
+    streaming = {k: v for k, v in kern.items() if "gbs" in v}
+    dominant = max(streaming, key=lambda k: streaming[k]["avg_us"]) if streaming else None
+    roofline = None
+    if dominant:
+        kd = kern[dominant]
+        roofline = {"bound": "hbm", "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(KERNEL_NAMES[dominant]),
+                    "kernel": KERNEL_NAMES[dominant], "bytes_per_launch": kd["bytes_per_launch"],
+                    "avg_us": kd["avg_us"]}
+    iter_bytes = sum(v["bytes_per_launch"] for v in streaming.values()) if len(streaming) == 2 else None
+
+    extra = {}
+    if not args.quick:
+        _log("bench: direct-launch cross-check leg")
+        _, kd = timed_leg(lpg, torch, dev, opts, args.warmup, args.steps, profile=2)
+        extra["kernels_direct_launch"] = {k: v["avg_us"] for k, v in kd.items()}
+        _log("bench: unprofiled leg")
+        el0, _ = timed_leg(lpg, torch, dev, opts, args.warmup, args.steps, profile=0)
+        extra["unprofiled_iter_per_s"] = round(args.steps / el0, 2)
+        _log("bench: time to optimality")
+        extra["solve"] = solve_leg(lpg, torch, dev, opts)
+
+    cpu = None
+    if args.cpu_pivots > 0 and not args.quick:
+        _log(f"bench: CPU oracle on {args.cpu_pivots} pivots")
+        cpu = cpu_baseline(A, b, c, args.cpu_pivots)
+
+    if args.calibrate_copy > 0:
+        _log(f"bench: copy calibration, {args.calibrate_copy} MiB x 3")
+        x = torch.empty(args.calibrate_copy << 17, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"dense LP max c^T x, A'x<=b, m={m}, n={n}, A'~U(0,1), b~U(1,10), c~U(1,10), "
+                               f"seed {args.seed}; plain FP64 path, Dantzig + tabu (tenure 5)",
+                   "m": m, "n": n, "iters_per_sync": args.iters_per_sync},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kern,
+        "iteration": {"model_bytes": iter_bytes,
+                      "gbs": round(iter_bytes * value / 1e9, 1) if iter_bytes else None,
+                      "frac_hbm": round(iter_bytes * value / 1e9 / HBM_PEAK_GBS, 4) if iter_bytes else None},
+        **extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -63,10 +63,12 @@ typedef struct lp_options {
   int64_t max_iter;       /* pivot limit for lp_solve (default 0 = 10*(m+n)) */
   double eps_d;           /* optimality tolerance on reduced costs (default 1e-9) */
   double eps_p;           /* pivot tolerance: rows with alpha_i > eps_p are ratio candidates (1e-9) */
-  double eps_z;           /* after each pivot |x_B,i| < eps_z is set to 0 (default 1e-12) */
+  double eps_z;           /* after each pivot |x_B,i| < eps_z is set to 0 (default 1e-9) */
   double eps_t;           /* rows with ratio <= theta_min + eps_t*max(1,theta_min) are tied (default 1e-11) */
   int32_t record_pivots;  /* 1 = keep the pivot log readable by lp_get_pivots (default 1) */
-  int32_t profile;        /* 1 = time every pricing and update kernel with HIP events (default 0) */
+  int32_t profile;        /* 1 = time every kernel of the iteration with HIP event nodes in the
+                             iteration graph; 2 = launch the kernels directly on the stream with
+                             HIP events between them (no graph); 0 = off (default) */
   void *stream;           /* hipStream_t to run on; NULL = a stream owned by the handle */
 } lp_options;
 
@@ -78,12 +80,14 @@ typedef struct lp_stats {
   int64_t list_clears;      /* tabu lists cleared because they excluded every tied row */
   int64_t syncs;            /* status read-backs (one per batch of iters_per_sync iterations) */
   double solve_ms;          /* host wall time spent inside lp_solve calls */
-  int64_t price_launches;   /* pricing kernels timed (profile = 1 only) */
+  int64_t price_launches;   /* pricing kernels timed (profile = 1 or 2) */
   double price_ms;          /* their summed duration */
-  int64_t update_launches;  /* update kernels timed (profile = 1 only) */
+  int64_t update_launches;  /* update kernels timed (profile = 1 or 2) */
   double update_ms;         /* their summed duration */
   double price_bytes;       /* algorithmic bytes of those pricing launches: 8*m per priced column */
   double update_bytes;      /* algorithmic bytes of those update launches: 16*m*m (8*m*m if no pivot pending) */
+  int64_t finish_launches;  /* ratio-test finishing kernels timed (profile = 1 or 2) */
+  double finish_ms;         /* their summed duration */
 } lp_stats;
 
 typedef struct lp_problem lp_problem;

@@ -53,6 +53,8 @@ class lp_stats(C.Structure):
         ("update_ms", C.c_double),
         ("price_bytes", C.c_double),
         ("update_bytes", C.c_double),
+        ("finish_launches", C.c_int64),
+        ("finish_ms", C.c_double),
     ]
 
 

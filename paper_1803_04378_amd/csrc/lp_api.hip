@@ -119,6 +119,7 @@ int check_options(const lp_options* o) {
   if (o->iters_per_sync < 1 || o->iters_per_sync > 4096)
     return fail(LP_ERR_ARG, "options.iters_per_sync must be in [1, 4096]");
   if (o->max_iter < 0) return fail(LP_ERR_ARG, "options.max_iter must be >= 0");
+  if (o->profile < 0 || o->profile > 2) return fail(LP_ERR_ARG, "options.profile must be 0, 1 or 2");
   if (!(o->eps_d >= 0.0) || !(o->eps_p >= 0.0) || !(o->eps_z >= 0.0) || !(o->eps_t >= 0.0) ||
       !std::isfinite(o->eps_d) || !std::isfinite(o->eps_p) || !std::isfinite(o->eps_z) || !std::isfinite(o->eps_t))
     return fail(LP_ERR_ARG, "options.eps_* must be finite and >= 0");
@@ -162,32 +163,70 @@ int read_ctrl(lp_problem* p) {
   return LP_OK;
 }
 
+// The iteration graph: iters_per_sync x (k_price -> k_update -> k_finish), a linear
+// chain.  With profile = 1 an event-record node sits before every kernel and at the end.
 int build_graph(lp_problem* p) {
   drop_graph(p);
   const int K = p->opt.iters_per_sync;
-  const bool prof = p->opt.profile != 0;
+  const bool prof = p->opt.profile == 1;
   if (prof) {
-    p->events.resize(2 * K + 1, nullptr);
+    p->events.resize(3 * K + 1, nullptr);
     for (auto& e : p->events) HIP_TRY(hipEventCreate(&e), "creating profiling events");
   }
-  HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal), "capturing the iteration graph");
-  hipError_t err = hipSuccess;
-  for (int k = 0; k < K && err == hipSuccess; ++k) {
-    if (prof) err = hipEventRecordWithFlags(p->events[2 * k], p->stream, hipEventRecordExternal);
-    if (err == hipSuccess) err = launch_price(p->d, p->price_grid, p->stream);
-    if (prof && err == hipSuccess) err = hipEventRecordWithFlags(p->events[2 * k + 1], p->stream, hipEventRecordExternal);
-    if (err == hipSuccess) err = launch_update(p->d, p->update_grid, p->stream);
+  HIP_TRY(hipGraphCreate(&p->graph, 0), "creating the iteration graph");
+  hipGraphNode_t prev = nullptr;
+  auto add_event = [&](hipEvent_t ev) -> hipError_t {
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddEventRecordNode(&node, p->graph, prev ? &prev : nullptr, prev ? 1 : 0, ev);
+    if (e == hipSuccess) prev = node;
+    return e;
+  };
+  void* args[] = {&p->d};
+  auto add_kernel = [&](const void* fn, int grid, int block, size_t lds) -> hipError_t {
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(fn);
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(block);
+    kp.sharedMemBytes = (unsigned)lds;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddKernelNode(&node, p->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (e == hipSuccess) prev = node;
+    return e;
+  };
+  for (int k = 0; k < K; ++k) {
+    if (prof) HIP_TRY(add_event(p->events[3 * k]), "adding a profiling event");
+    HIP_TRY(add_kernel(price_kernel(), p->price_grid, kPriceBlock, price_lds_bytes(p->ld)), "adding k_price");
+    if (prof) HIP_TRY(add_event(p->events[3 * k + 1]), "adding a profiling event");
+    HIP_TRY(add_kernel(update_kernel(), p->update_grid, kUpdateBlock, update_lds_bytes(p->ld)), "adding k_update");
+    if (prof) HIP_TRY(add_event(p->events[3 * k + 2]), "adding a profiling event");
+    HIP_TRY(add_kernel(finish_kernel(), 1, kUpdateBlock, 0), "adding k_finish");
   }
-  if (prof && err == hipSuccess) err = hipEventRecordWithFlags(p->events[2 * K], p->stream, hipEventRecordExternal);
-  hipGraph_t g = nullptr;
-  hipError_t e2 = hipStreamEndCapture(p->stream, &g);
-  if (err != hipSuccess || e2 != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
-    return fail_hip(err != hipSuccess ? err : e2, "capturing the iteration graph");
-  }
-  p->graph = g;
-  HIP_TRY(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0), "instantiating the iteration graph");
+  if (prof) HIP_TRY(add_event(p->events[3 * K]), "adding a profiling event");
+  HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0), "instantiating the iteration graph");
   p->graph_k = K;
+  return LP_OK;
+}
+
+// profile = 2: the same K iterations launched directly on the stream with an event
+// before every kernel (no graph), for cross-checking the graph's events.
+int launch_direct(lp_problem* p) {
+  const int K = p->opt.iters_per_sync;
+  if ((int)p->events.size() != 3 * K + 1) {
+    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+    p->events.assign(3 * K + 1, nullptr);
+    for (auto& e : p->events) HIP_TRY(hipEventCreate(&e), "creating profiling events");
+  }
+  for (int k = 0; k < K; ++k) {
+    HIP_TRY(hipEventRecord(p->events[3 * k], p->stream), "recording an event");
+    HIP_TRY(launch_price(p->d, p->price_grid, p->stream), "launching k_price");
+    HIP_TRY(hipEventRecord(p->events[3 * k + 1], p->stream), "recording an event");
+    HIP_TRY(launch_update(p->d, p->update_grid, p->stream), "launching k_update");
+    HIP_TRY(hipEventRecord(p->events[3 * k + 2], p->stream), "recording an event");
+    HIP_TRY(launch_finish(p->d, p->stream), "launching k_finish");
+  }
+  HIP_TRY(hipEventRecord(p->events[3 * K], p->stream), "recording an event");
   return LP_OK;
 }
 
@@ -279,7 +318,9 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   ALLOC(chat, (size_t)N);
   ALLOC(p->d.Binv, (size_t)m * ld);
   ALLOC(p->d.xB, (size_t)m);
-  ALLOC(p->d.W, (size_t)ld);
+  ALLOC(p->d.W0, (size_t)ld);
+  ALLOC(p->d.W1, (size_t)ld);
+  ALLOC(p->d.ratio, (size_t)m);
   ALLOC(p->d.rho, (size_t)ld);
   ALLOC(p->d.alpha0, (size_t)m);
   ALLOC(p->d.alpha1, (size_t)m);
@@ -290,12 +331,17 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   ALLOC(p->d.excl, (size_t)N);
   ALLOC(p->d.part_d, 2 * (size_t)p->price_grid);
   ALLOC(p->d.part_j, 2 * (size_t)p->price_grid);
+  ALLOC(p->d.part_th, (size_t)p->update_grid);
+  ALLOC(p->d.part_cnt, (size_t)p->update_grid);
+  ALLOC(p->d.part_low, (size_t)p->update_grid);
   ALLOC(p->d.ctrl, 1);
   ALLOC(p->b0, (size_t)m);
   ALLOC(p->c0, (size_t)std::max(n, 1));
 #undef ALLOC
   p->d.m = m;
   p->d.n = n;
+  p->d.price_grid = p->price_grid;
+  p->d.update_grid = p->update_grid;
   p->d.ld = ld;
   p->d.A = dA;
   p->d.chat = chat;
@@ -372,7 +418,7 @@ int lp_default_options(lp_options* opt) {
   opt->max_iter = 0;
   opt->eps_d = 1e-9;
   opt->eps_p = 1e-9;
-  opt->eps_z = 1e-12;
+  opt->eps_z = 1e-9;
   opt->eps_t = 1e-11;
   opt->record_pivots = 1;
   opt->profile = 0;
@@ -399,7 +445,8 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
     return LP_OK;
   }
   if ((rc = ensure_capacity(p, iter_cap)) != LP_OK) return rc;
-  if (!p->gexec || p->graph_k != p->opt.iters_per_sync) {
+  const bool direct = p->opt.profile == 2;
+  if (!direct && (!p->gexec || p->graph_k != p->opt.iters_per_sync)) {
     if ((rc = build_graph(p)) != LP_OK) return rc;
   }
   const auto t0 = std::chrono::steady_clock::now();
@@ -412,24 +459,31 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
   HIP_TRY(hipMemcpyAsync(&p->d.ctrl->status, &p->h_stage->status, sizeof(int32_t), hipMemcpyHostToDevice, p->stream),
           "arming the solve");
   const bool prof = p->opt.profile != 0;
-  const int K = p->graph_k;
+  const int K = p->opt.iters_per_sync;
   for (;;) {
     const int64_t t_before = p->h_ctrl->t;
     const int64_t cols_before = p->h_ctrl->price_cols;
-    HIP_TRY(hipGraphLaunch(p->gexec, p->stream), "launching the iteration graph");
+    if (direct) {
+      if ((rc = launch_direct(p)) != LP_OK) return rc;
+    } else {
+      HIP_TRY(hipGraphLaunch(p->gexec, p->stream), "launching the iteration graph");
+    }
     if ((rc = read_ctrl(p)) != LP_OK) return rc;
     p->stats.syncs += 1;
     if (prof && p->h_ctrl->status == LP_RUNNING && t_before > 0 && p->h_ctrl->t == t_before + K) {
       // Steady state: every kernel of the replay did a full pass.
       for (int k = 0; k < K; ++k) {
-        float ms_p = 0.f, ms_u = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms_p, p->events[2 * k], p->events[2 * k + 1]), "reading profile events");
-        HIP_TRY(hipEventElapsedTime(&ms_u, p->events[2 * k + 1], p->events[2 * k + 2]), "reading profile events");
+        float ms_p = 0.f, ms_u = 0.f, ms_f = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms_p, p->events[3 * k], p->events[3 * k + 1]), "reading profile events");
+        HIP_TRY(hipEventElapsedTime(&ms_u, p->events[3 * k + 1], p->events[3 * k + 2]), "reading profile events");
+        HIP_TRY(hipEventElapsedTime(&ms_f, p->events[3 * k + 2], p->events[3 * k + 3]), "reading profile events");
         p->stats.price_ms += ms_p;
         p->stats.update_ms += ms_u;
+        p->stats.finish_ms += ms_f;
       }
       p->stats.price_launches += K;
       p->stats.update_launches += K;
+      p->stats.finish_launches += K;
       p->stats.price_bytes += 8.0 * p->m * (double)(p->h_ctrl->price_cols - cols_before);
       p->stats.update_bytes += 16.0 * (double)p->m * p->m * K;
     }
@@ -466,7 +520,8 @@ int lp_get_solution(const lp_problem* pc, double* objective, double* x, double* 
   std::vector<double> xB(m), W(m);
   std::vector<int32_t> bas(m);
   HIP_TRY(hipMemcpyAsync(xB.data(), p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
-  HIP_TRY(hipMemcpyAsync(W.data(), p->d.W, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading W");
+  const double* dW = p->h_ctrl->wcur ? p->d.W1 : p->d.W0;
+  HIP_TRY(hipMemcpyAsync(W.data(), dW, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading W");
   HIP_TRY(hipMemcpyAsync(bas.data(), p->d.basis, sizeof(int32_t) * m, hipMemcpyDeviceToHost, p->stream),
           "reading the basis");
   HIP_TRY(hipStreamSynchronize(p->stream), "reading the solution");
@@ -517,7 +572,10 @@ int lp_get_tableau(const lp_problem* pc, double* Binv, double* xB, double* W, do
                              hipMemcpyDeviceToHost, p->stream),
             "reading B^-1");
   if (xB) HIP_TRY(hipMemcpyAsync(xB, p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
-  if (W) HIP_TRY(hipMemcpyAsync(W, p->d.W, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading W");
+  if (W)
+    HIP_TRY(hipMemcpyAsync(W, p->h_ctrl->wcur ? p->d.W1 : p->d.W0, sizeof(double) * m, hipMemcpyDeviceToHost,
+                           p->stream),
+            "reading W");
   HIP_TRY(hipStreamSynchronize(p->stream), "reading the tableau");
   if (z) *z = p->h_ctrl->z;
   return LP_OK;

@@ -4,8 +4,9 @@
 // padding is zero and stays zero):
 //   A      ld x n   column-major: column j of A' is contiguous (pricing streams it)
 //   Binv   m x ld   row-major:    row i of B^-1 is contiguous (update + FTRAN stream it)
-//   W, rho ld       W = chat_B^T B^-1 (top row of the Figure 1 tableau), rho = pivot row / alpha_r
-//   xB, alpha[2]    m
+//   W0, W1, rho ld  W = chat_B^T B^-1 (top row of the Figure 1 tableau, two copies: one is
+//                   read while the next is written), rho = pivot row / alpha_r
+//   xB, alpha[2], ratio  m
 //   chat            n + m   (minimisation costs; slacks 0)
 //   basis (m), pos (n+m), tabu_until (n+m), the leaving-side tabu list, the pivot log: int32
 #pragma once
@@ -27,8 +28,9 @@ constexpr int kFlagLClear = 8;
 constexpr int kPriceBlock = 512;
 constexpr int kUpdateBlock = 1024;
 
-// Control block: written only by the last workgroup of a kernel (or by the host between
-// solves), read by every workgroup of the next kernel.
+// Control block: written by one thread of a kernel (or by the host between solves), read
+// by every workgroup of the next kernel; a field is never read and written by different
+// workgroups of the same launch.
 struct Ctrl {
   int32_t status;
   int32_t q;      // entering variable chosen by the latest pricing, -1 if none
@@ -42,8 +44,8 @@ struct Ctrl {
   int32_t nL;     // entries in the leaving-side tabu list
   int32_t flags;  // pivot-log flags gathered for the pivot in progress
   int32_t pad0;
-  uint32_t price_ticket;
-  uint32_t update_ticket;
+  int32_t verdict;  // pricing verdict left by k_update for k_finish (-1: k_update did not run)
+  int32_t pad4;
   int64_t n_degenerate, n_tie, n_aspiration, n_lclear;
   int32_t nsb;   // structural variables in the basis
   int32_t pad1;
@@ -51,6 +53,10 @@ struct Ctrl {
   int64_t price_cols;           // structural columns those passes streamed
   int64_t update_launches;      // update passes that ran
   int64_t update_rows_written;  // B^-1 rows those passes rewrote
+  double theta;   // step length of the pending pivot
+  double pdq;     // reduced cost of the pending pivot's entering variable
+  int32_t wcur;   // W0 or W1 holds the current top row W
+  int32_t pad2;
 };
 
 struct DevLP {
@@ -59,8 +65,10 @@ struct DevLP {
   const double* chat;
   double* Binv;
   double* xB;
-  double* W;
+  double* W0;     // W ping-pong: k_price reads one and writes the other
+  double* W1;
   double* rho;
+  double* ratio;  // per-row ratio of the latest FTRAN (infinity where alpha_i <= eps_p)
   double* alpha0;
   double* alpha1;
   int32_t* basis;
@@ -77,8 +85,13 @@ struct DevLP {
   int32_t* log_flags;
   double* part_d;  // pricing partials: 2 per workgroup (all improving, non-tabu improving)
   int32_t* part_j;
+  double* part_th;  // update partials per workgroup: min ratio, rows within its tie bound, lowest such row
+  int32_t* part_cnt;
+  int32_t* part_low;
   Ctrl* ctrl;
   int64_t log_cap;
+  int32_t price_grid;   // workgroups of k_price (partials to reduce)
+  int32_t update_grid;  // workgroups of k_update
   int32_t Lcap;
   int32_t tenure;
   int32_t use_llist;
@@ -90,7 +103,12 @@ struct DevLP {
 hipError_t launch_init(const DevLP& lp, const double* b, const double* c, double sense, hipStream_t s);
 hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s);
 hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s);
+hipError_t launch_finish(const DevLP& lp, hipStream_t s);
 hipError_t launch_check_finite(const double* x, int64_t count, int32_t* flag, hipStream_t s);
+// Kernel entry points for explicit graph construction.
+const void* price_kernel();
+const void* update_kernel();
+const void* finish_kernel();
 size_t price_lds_bytes(int ld);
 size_t update_lds_bytes(int ld);
 hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld);

@@ -1,20 +1,24 @@
 // Kernels of one dense revised simplex iteration for CDNA4 (gfx950, wave64).
 //
-// One iteration is two launches:
-//   k_price   Steps 3-4: reduced costs d_j = chat_j - W a_j of every nonbasic column
-//             (one wavefront per column of A', W staged in LDS), Dantzig choice with
-//             the tabu mask; the last workgroup to finish reduces the per-workgroup
-//             (d, j) minima and writes q, or the OPTIMAL / ITER_LIMIT status.
-//   k_update  Section 3.1 update of B^-1 for the pivot chosen in the previous
-//             iteration, fused with Step 5 (FTRAN, alpha = B^-1 a_q) for the column
-//             priced just before: one wavefront per row of B^-1 reads the row once,
-//             writes the updated row, and dots the new row with a_q on the fly.
-//             The last workgroup then runs Step 6 (ratio test, ties, tabu list) and
-//             the O(m) part of Step 8 (pivot row rho, W, x_B, z, basis, log).
+// One iteration is three launches, ordered only by kernel boundaries (no grid-wide
+// fences, which cost an L2 write-back per workgroup on this part):
+//   k_price   Step 8 on the top row for the previous pivot (W += d_q rho, formed while
+//             staging W in LDS), then Steps 3-4: reduced costs d_j = chat_j - W a_j of
+//             every nonbasic column, one wavefront per column of A'; each workgroup
+//             leaves its lexicographic (d, j) minima over all improving and over
+//             non-tabu improving columns.
+//   k_update  every workgroup reduces those partials to the same q (Step 4), then runs
+//             the Section 3.1 update of B^-1 and x_B for the previous pivot fused with
+//             Step 5 (FTRAN, alpha = B^-1 a_q) for q: one wavefront per row of B^-1
+//             reads the row once, writes the updated row, dots it with a_q on the fly,
+//             and forms that row's ratio (Step 6); each workgroup leaves its minimum
+//             ratio and its rows within the tie bound.
+//   k_finish  one workgroup: Step 6 ties and tabu list, then the scalar part of Step 8
+//             (basis, entering mask, objective, pivot log).
 //
 // The B^-1 update of pivot t therefore runs in the same pass as the FTRAN of pivot
 // t+1.  This is legal because pricing for t+1 needs only W_{t+1} = W_t + d_q rho_t,
-// which the tail of the previous launch already holds; it removes one full read of
+// which needs only row r of the not yet updated B^-1; it removes one full read of
 // B^-1 per iteration.  Every element still gets the same arithmetic as in Step 8.
 //
 // Reductions are deterministic: each dot product is a fixed per-lane fma chain
@@ -126,21 +130,6 @@ __device__ int block_sum_int(int v, int* si) {
   return si[0];
 }
 
-// Release this workgroup's global writes, take a ticket, and report whether this is
-// the last workgroup of the grid to arrive.  The last one acquires everyone's writes.
-__device__ bool arrive_last(uint32_t* ticket, int* s_flag) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    *s_flag = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  const bool last = *s_flag != 0;
-  if (last) __threadfence();
-  return last;
-}
-
 // Dot product of a contiguous HBM vector with an LDS vector, both n2 double2 long.
 // Lane l accumulates elements l, l+64, ... in order; the butterfly then gives every
 // lane the same bits.
@@ -236,7 +225,8 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
     lp.Binv[k] = (i == j) ? 1.0 : 0.0;
   }
   for (size_t k = tid; k < (size_t)ld; k += stride) {
-    lp.W[k] = 0.0;
+    lp.W0[k] = 0.0;
+    lp.W1[k] = 0.0;
     lp.rho[k] = 0.0;
   }
   for (size_t i = tid; i < (size_t)m; i += stride) {
@@ -244,6 +234,7 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
     lp.basis[i] = n + (int)i;
     lp.alpha0[i] = 0.0;
     lp.alpha1[i] = 0.0;
+    lp.ratio[i] = __builtin_inf();
   }
   double* chat = const_cast<double*>(lp.chat);
   for (size_t v = tid; v < (size_t)N; v += stride) {
@@ -260,21 +251,46 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
     ctl->q = -1;
     ctl->r = -1;
     ctl->ray = -1;
+    ctl->verdict = -1;
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// Steps 3-4.
+// Steps 3-4, preceded by Step 8 on the top row of the tableau for the pending pivot:
+// every workgroup forms W_new = W + d_q rho, rho = B^-1[r,:] / alpha_r, while staging it
+// into LDS (B^-1 still holds the pre-pivot rows, the row update runs in k_update);
+// workgroup 0 also stores rho and W_new for the rest of the iteration.
 __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
   if (lp.ctrl->status != kStatusRunning) return;
   const int64_t t = lp.ctrl->t;
+  const int r = lp.ctrl->r;
+  const int wc = lp.ctrl->wcur;
   extern __shared__ double2 s_w2[];
   __shared__ double red_d[kPriceBlock / 64 + 8];
   __shared__ int red_j[kPriceBlock / 64 + 8];
-  __shared__ int s_last;
   const int m = lp.m, n = lp.n, ld2 = lp.ld / 2;
-  const double2* W2 = reinterpret_cast<const double2*>(lp.W);
-  for (int k = threadIdx.x; k < ld2; k += kPriceBlock) s_w2[k] = W2[k];
+  const double2* Wold = reinterpret_cast<const double2*>(wc ? lp.W1 : lp.W0);
+  if (r >= 0) {
+    const double ar = (lp.ctrl->cur ? lp.alpha1 : lp.alpha0)[r];
+    const double dq = lp.ctrl->pdq;
+    const double2* rowr = reinterpret_cast<const double2*>(lp.Binv + (size_t)r * lp.ld);
+    double2* Wnew = reinterpret_cast<double2*>(wc ? lp.W0 : lp.W1);
+    double2* rho2 = reinterpret_cast<double2*>(lp.rho);
+    const bool writer = blockIdx.x == 0;
+    for (int k = threadIdx.x; k < ld2; k += kPriceBlock) {
+      const double2 b = rowr[k];
+      const double2 w = Wold[k];
+      const double2 rr = make_double2(b.x / ar, b.y / ar);
+      const double2 wn = make_double2(fma(dq, rr.x, w.x), fma(dq, rr.y, w.y));
+      s_w2[k] = wn;
+      if (writer) {
+        rho2[k] = rr;
+        Wnew[k] = wn;
+      }
+    }
+  } else {
+    for (int k = threadIdx.x; k < ld2; k += kPriceBlock) s_w2[k] = Wold[k];
+  }
   __syncthreads();
   const double* s_w = reinterpret_cast<const double*>(s_w2);
 
@@ -323,11 +339,25 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
     lp.part_d[2 * blockIdx.x + 1] = df;
     lp.part_j[2 * blockIdx.x + 1] = jf;
   }
-  if (!arrive_last(&lp.ctrl->price_ticket, &s_last)) return;
+}
 
-  da = df = __builtin_inf();
-  ja = jf = INT_MAX;
-  for (int k = threadIdx.x; k < (int)gridDim.x; k += kPriceBlock) {
+// ---------------------------------------------------------------------------------------
+// Section 3.1 update of the pending pivot (rows of B^-1 and x_B) fused with Step 5 for
+// the newly priced q and with the per-row part of Step 6.  Every workgroup first reduces
+// the pricing partials itself (a lexicographic minimum, so all of them agree on q).
+__global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
+  if (lp.ctrl->status != kStatusRunning) return;
+  const int r = lp.ctrl->r;
+  const int64_t t = lp.ctrl->t;
+  extern __shared__ double2 smem2[];
+  __shared__ double red_d[kUpdateBlock / 64 + 8];
+  __shared__ int red_j[kUpdateBlock / 64 + 8];
+  const int m = lp.m, n = lp.n, ld2 = lp.ld / 2;
+
+  // Step 4 decision from the pricing partials.
+  double da = __builtin_inf(), df = __builtin_inf();
+  int ja = INT_MAX, jf = INT_MAX;
+  for (int k = threadIdx.x; k < lp.price_grid; k += kUpdateBlock) {
     const double d0 = lp.part_d[2 * k], d1 = lp.part_d[2 * k + 1];
     const int j0 = lp.part_j[2 * k], j1 = lp.part_j[2 * k + 1];
     if (lex_less(d0, j0, da, ja)) {
@@ -339,165 +369,46 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
       jf = j1;
     }
   }
-  block_lexmin<kPriceBlock>(da, ja, red_d, red_j);
-  block_lexmin<kPriceBlock>(df, jf, red_d, red_j);
-  if (threadIdx.x == 0) {
+  block_lexmin<kUpdateBlock>(da, ja, red_d, red_j);
+  block_lexmin<kUpdateBlock>(df, jf, red_d, red_j);
+  int status = kStatusRunning, q = -1, flags = 0;
+  double dq = 0.0;
+  if (ja == INT_MAX) {
+    status = kStatusOptimal;
+  } else if (t >= lp.ctrl->max_iter) {
+    status = kStatusIterLimit;
+  } else if (jf != INT_MAX) {
+    q = jf;
+    dq = df;
+  } else {
+    q = ja;
+    dq = da;
+    flags = kFlagAspiration;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // Only fields no k_update workgroup reads: the status itself changes in k_finish.
     Ctrl* ctl = lp.ctrl;
-    ctl->price_ticket = 0;
     ctl->price_cols += n - ctl->nsb;
     ctl->price_launches += 1;
-    if (ja == INT_MAX) {
-      ctl->status = kStatusOptimal;
-      ctl->q = -1;
-    } else if (t >= ctl->max_iter) {
-      ctl->status = kStatusIterLimit;
-      ctl->q = -1;
-    } else if (jf != INT_MAX) {
-      ctl->q = jf;
-      ctl->dq = df;
-      ctl->flags = 0;
-    } else {
-      ctl->q = ja;
-      ctl->dq = da;
-      ctl->flags = kFlagAspiration;
-      ctl->n_aspiration += 1;
+    if (r >= 0) ctl->wcur ^= 1;  // k_price wrote W_new: it is the current top row now
+    ctl->verdict = status;
+    ctl->q = q;
+    ctl->dq = dq;
+    ctl->flags = flags;
+    if (flags & kFlagAspiration) ctl->n_aspiration += 1;
+    if (r >= 0) {
+      ctl->update_launches += 1;
+      ctl->update_rows_written += m;
+    } else if (q >= 0) {
+      ctl->update_launches += 1;
     }
   }
-}
-
-// ---------------------------------------------------------------------------------------
-// Step 6 and the O(m) part of Step 8, run by the last workgroup of k_update once the
-// whole new B^-1 and alpha = B^-1 a_q are in memory.
-__device__ void pivot_tail(const DevLP& lp, int q, const double* __restrict__ al, int cur, double* red_d,
-                           int* red_j) {
-  constexpr int B = kUpdateBlock;
-  Ctrl* ctl = lp.ctrl;
-  const int m = lp.m, tid = threadIdx.x;
-  const double eps_p = lp.eps_p;
-  const int64_t t = ctl->t;
-
-  double th = __builtin_inf();
-  for (int i = tid; i < m; i += B) {
-    const double a = al[i];
-    if (a > eps_p) {
-      const double rt = fmax(lp.xB[i], 0.0) / a;
-      if (rt < th) th = rt;
-    }
-  }
-  th = block_min<B>(th, red_d, red_j);
-  if (th == __builtin_inf()) {  // Step 5: Y_k <= 0
-    if (tid == 0) {
-      ctl->status = kStatusUnbounded;
-      ctl->ray = q;
-      ctl->q = -1;
-      ctl->r = -1;
-    }
-    return;
-  }
-  // Rows within the tie tolerance of the minimum ratio are tied (exact ties split by rounding).
-  const double tie_bound = th + lp.eps_t * fmax(1.0, th);
-  int cnt = 0, low = INT_MAX;
-  for (int i = tid; i < m; i += B) {
-    const double a = al[i];
-    if (a > eps_p && fmax(lp.xB[i], 0.0) / a <= tie_bound) {
-      ++cnt;
-      low = min(low, i);
-    }
-  }
-  cnt = block_sum_int<B>(cnt, red_j);
-  low = block_min_int<B>(low, red_j);
-  int r = low;
-  int flags = ctl->flags;
-  if (cnt >= 2) {
-    flags |= kFlagTie;
-    if (lp.use_llist) {
-      const int stamp = (int)t + 1;
-      const int g = lp.gen[q];
-      const int nL = ctl->nL;
-      for (int k = tid; k < nL; k += B)
-        if (lp.Lq[k] == q && lp.Lgen[k] == g) lp.excl[lp.Ll[k]] = stamp;
-      __syncthreads();
-      int fl = INT_MAX;
-      for (int i = tid; i < m; i += B) {
-        const double a = al[i];
-        if (a > eps_p && fmax(lp.xB[i], 0.0) / a <= tie_bound && lp.excl[lp.basis[i]] != stamp) fl = min(fl, i);
-      }
-      fl = block_min_int<B>(fl, red_j);
-      int gnew = g;
-      if (fl == INT_MAX) {
-        flags |= kFlagLClear;
-        gnew = g + 1;
-      } else {
-        r = fl;
-      }
-      if (tid == 0) {
-        if (gnew != g) lp.gen[q] = gnew;
-        if (nL < lp.Lcap) {
-          lp.Lq[nL] = q;
-          lp.Ll[nL] = lp.basis[r];
-          lp.Lgen[nL] = gnew;
-          ctl->nL = nL + 1;
-        }
-      }
-    }
-  }
-  // Step 8 pivots on row r: the step is r's own ratio.
-  const double ar = al[r];
-  th = fmax(lp.xB[r], 0.0) / ar;
-  if (th == 0.0) flags |= kFlagDegenerate;
-  __syncthreads();  // every thread has read xB[r] before x_B is rewritten
-
-  // Step 8 on the top row and the right-hand column of the tableau.
-  const double dq = ctl->dq;
-  const double* rowr = lp.Binv + (size_t)r * lp.ld;
-  for (int j = tid; j < m; j += B) {
-    const double rj = rowr[j] / ar;
-    lp.rho[j] = rj;
-    lp.W[j] = fma(dq, rj, lp.W[j]);
-  }
-  const double eps_z = lp.eps_z;
-  for (int i = tid; i < m; i += B) {
-    double x = (i == r) ? th : fma(-al[i], th, lp.xB[i]);
-    if (fabs(x) < eps_z) x = 0.0;
-    lp.xB[i] = x;
-  }
-  if (tid == 0) {
-    const int leave = lp.basis[r];
-    if (lp.tenure > 0) lp.tabu_until[leave] = (int)(t + lp.tenure);
-    ctl->z = fma(dq, th, ctl->z);
-    lp.basis[r] = q;
-    lp.pos[q] = r;
-    lp.pos[leave] = -1;
-    ctl->nsb += (q < lp.n ? 1 : 0) - (leave < lp.n ? 1 : 0);
-    if (t < lp.log_cap) {
-      lp.log_enter[t] = q;
-      lp.log_row[t] = r;
-      lp.log_leave[t] = leave;
-      lp.log_flags[t] = flags;
-    }
-    if (flags & kFlagTie) ctl->n_tie += 1;
-    if (flags & kFlagLClear) ctl->n_lclear += 1;
-    if (flags & kFlagDegenerate) ctl->n_degenerate += 1;
-    ctl->t = t + 1;
-    ctl->r = r;
-    ctl->cur = cur ^ 1;
-    ctl->q = -1;
-    ctl->flags = 0;
-  }
-}
-
-// Section 3.1 update of the pending pivot fused with Step 5 for the newly priced q.
-__global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
-  const int r = lp.ctrl->r, q = lp.ctrl->q;
   if (r < 0 && q < 0) return;
+
   const int cur = lp.ctrl->cur;
+  const double theta = lp.ctrl->theta;
   const double* __restrict__ al_p = cur ? lp.alpha1 : lp.alpha0;  // pending pivot's alpha
   double* __restrict__ al_n = cur ? lp.alpha0 : lp.alpha1;        // FTRAN result for q
-  extern __shared__ double2 smem2[];
-  __shared__ double red_d[kUpdateBlock / 64 + 8];
-  __shared__ int red_j[kUpdateBlock / 64 + 8];
-  __shared__ int s_last;
-  const int m = lp.m, n = lp.n, ld2 = lp.ld / 2;
   double2* s_rho = smem2;
   double2* s_a = smem2 + ld2;
   if (r >= 0) {
@@ -520,28 +431,186 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * waves + (threadIdx.x >> 6);
   const int nw = gridDim.x * waves;
+  const double eps_p = lp.eps_p, eps_z = lp.eps_z;
+  double wmin = __builtin_inf();  // this wave's minimum ratio
   for (int i = gw; i < m; i += nw) {
     double2* row = reinterpret_cast<double2*>(lp.Binv + (size_t)i * lp.ld);
     double acc;
+    double x = lp.xB[i];
     if (r < 0) {
       acc = wave_dot(row, s_a, ld2, lane);
-    } else if (i == r) {
-      acc = q >= 0 ? wave_store_dot<true>(row, s_rho, s_a, ld2, lane) : wave_store_dot<false>(row, s_rho, s_a, ld2, lane);
     } else {
-      const double na = -al_p[i];
-      acc = q >= 0 ? wave_update_dot<true>(row, s_rho, s_a, na, ld2, lane)
-                   : wave_update_dot<false>(row, s_rho, s_a, na, ld2, lane);
+      if (i == r) {
+        acc = q >= 0 ? wave_store_dot<true>(row, s_rho, s_a, ld2, lane)
+                     : wave_store_dot<false>(row, s_rho, s_a, ld2, lane);
+        x = theta;
+      } else {
+        const double na = -al_p[i];
+        acc = q >= 0 ? wave_update_dot<true>(row, s_rho, s_a, na, ld2, lane)
+                     : wave_update_dot<false>(row, s_rho, s_a, na, ld2, lane);
+        x = fma(na, theta, x);
+      }
+      if (fabs(x) < eps_z) x = 0.0;
+      if (lane == 0) lp.xB[i] = x;
     }
-    if (q >= 0 && lane == 0) al_n[i] = acc;
+    if (q >= 0) {
+      const double rt = acc > eps_p ? fmax(x, 0.0) / acc : __builtin_inf();
+      wmin = fmin(wmin, rt);
+      if (lane == 0) {
+        al_n[i] = acc;
+        lp.ratio[i] = rt;
+      }
+    }
   }
-  if (!arrive_last(&lp.ctrl->update_ticket, &s_last)) return;
+  if (q < 0) return;
+  // Workgroup partial of Step 6: min ratio, and rows within the tie bound of it.
+  const double th = block_min<kUpdateBlock>(wmin, red_d, red_j);
+  const double bound = th + lp.eps_t * fmax(1.0, th);
+  int cnt = 0, low = INT_MAX;
+  if (th != __builtin_inf()) {
+    for (int i = gw; i < m; i += nw) {
+      if (lane == 0 && lp.ratio[i] <= bound) {
+        ++cnt;
+        low = min(low, i);
+      }
+    }
+  }
+  cnt = block_sum_int<kUpdateBlock>(cnt, red_j);
+  low = block_min_int<kUpdateBlock>(low, red_j);
   if (threadIdx.x == 0) {
-    lp.ctrl->update_ticket = 0;
-    lp.ctrl->update_launches += 1;
-    lp.ctrl->update_rows_written += (r >= 0) ? m : 0;
-    lp.ctrl->r = -1;
+    lp.part_th[blockIdx.x] = th;
+    lp.part_cnt[blockIdx.x] = cnt;
+    lp.part_low[blockIdx.x] = low;
   }
-  if (q >= 0) pivot_tail(lp, q, al_n, cur, red_d, red_j);
+}
+
+// ---------------------------------------------------------------------------------------
+// Step 6 finish and the scalar part of Step 8 (one workgroup).  Every row's ratio is in
+// lp.ratio (infinity where alpha_i <= eps_p) and every k_update workgroup left (min
+// ratio, rows within the tie bound of it, lowest such row).
+__global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
+  constexpr int B = kUpdateBlock;
+  __shared__ double red_d[B / 64 + 8];
+  __shared__ int red_j[B / 64 + 8];
+  Ctrl* ctl = lp.ctrl;
+  const int verdict = ctl->verdict;
+  if (verdict < 0) return;  // k_update did not run
+  const int q = ctl->q;
+  if (verdict != kStatusRunning) {  // OPTIMAL or ITER_LIMIT; k_update applied the pending pivot
+    if (threadIdx.x == 0) {
+      ctl->status = verdict;
+      ctl->verdict = -1;
+      ctl->r = -1;
+      ctl->q = -1;
+    }
+    return;
+  }
+  const int m = lp.m, tid = threadIdx.x, nparts = lp.update_grid;
+  const int64_t t = ctl->t;
+  const int cur = ctl->cur;
+
+  double th = __builtin_inf();
+  for (int k = tid; k < nparts; k += B) th = fmin(th, lp.part_th[k]);
+  th = block_min<B>(th, red_d, red_j);
+  if (th == __builtin_inf()) {  // Step 5: Y_k <= 0
+    if (tid == 0) {
+      ctl->status = kStatusUnbounded;
+      ctl->verdict = -1;
+      ctl->ray = q;
+      ctl->q = -1;
+      ctl->r = -1;
+    }
+    return;
+  }
+  // Rows within the tie tolerance of the minimum ratio are tied (exact ties split by rounding).
+  const double tie_bound = th + lp.eps_t * fmax(1.0, th);
+  // Fast path: a single workgroup holds rows within the bound, and only one of them.
+  int ncand = 0, cand = INT_MAX;
+  for (int k = tid; k < nparts; k += B)
+    if (lp.part_th[k] <= tie_bound) {
+      ++ncand;
+      cand = min(cand, k);
+    }
+  ncand = block_sum_int<B>(ncand, red_j);
+  cand = block_min_int<B>(cand, red_j);
+  int cnt, low;
+  if (ncand == 1 && lp.part_cnt[cand] == 1) {
+    cnt = 1;
+    low = lp.part_low[cand];
+  } else {
+    cnt = 0;
+    low = INT_MAX;
+    for (int i = tid; i < m; i += B)
+      if (lp.ratio[i] <= tie_bound) {
+        ++cnt;
+        low = min(low, i);
+      }
+    cnt = block_sum_int<B>(cnt, red_j);
+    low = block_min_int<B>(low, red_j);
+  }
+  int r = low;
+  int flags = ctl->flags;
+  if (cnt >= 2) {
+    flags |= kFlagTie;
+    if (lp.use_llist) {
+      const int stamp = (int)t + 1;
+      const int g = lp.gen[q];
+      const int nL = ctl->nL;
+      for (int k = tid; k < nL; k += B)
+        if (lp.Lq[k] == q && lp.Lgen[k] == g) lp.excl[lp.Ll[k]] = stamp;
+      __syncthreads();
+      int fl = INT_MAX;
+      for (int i = tid; i < m; i += B)
+        if (lp.ratio[i] <= tie_bound && lp.excl[lp.basis[i]] != stamp) fl = min(fl, i);
+      fl = block_min_int<B>(fl, red_j);
+      int gnew = g;
+      if (fl == INT_MAX) {
+        flags |= kFlagLClear;
+        gnew = g + 1;
+      } else {
+        r = fl;
+      }
+      if (tid == 0) {
+        if (gnew != g) lp.gen[q] = gnew;
+        if (nL < lp.Lcap) {
+          lp.Lq[nL] = q;
+          lp.Ll[nL] = lp.basis[r];
+          lp.Lgen[nL] = gnew;
+          ctl->nL = nL + 1;
+        }
+      }
+    }
+  }
+  if (tid == 0) {
+    // Step 8 pivots on row r: the step is r's own ratio.
+    const double thr = lp.ratio[r];
+    if (thr == 0.0) flags |= kFlagDegenerate;
+    const double dq = ctl->dq;
+    const int leave = lp.basis[r];
+    if (lp.tenure > 0) lp.tabu_until[leave] = (int)(t + lp.tenure);
+    ctl->z = fma(dq, thr, ctl->z);
+    lp.basis[r] = q;
+    lp.pos[q] = r;
+    lp.pos[leave] = -1;
+    ctl->nsb += (q < lp.n ? 1 : 0) - (leave < lp.n ? 1 : 0);
+    if (t < lp.log_cap) {
+      lp.log_enter[t] = q;
+      lp.log_row[t] = r;
+      lp.log_leave[t] = leave;
+      lp.log_flags[t] = flags;
+    }
+    if (flags & kFlagTie) ctl->n_tie += 1;
+    if (flags & kFlagLClear) ctl->n_lclear += 1;
+    if (flags & kFlagDegenerate) ctl->n_degenerate += 1;
+    ctl->t = t + 1;
+    ctl->r = r;        // pending: rows of B^-1 and x_B are pivoted by the next k_update,
+    ctl->theta = thr;  // the top row by the next k_price
+    ctl->pdq = dq;
+    ctl->cur = cur ^ 1;
+    ctl->q = -1;
+    ctl->flags = 0;
+    ctl->verdict = -1;
+  }
 }
 
 __global__ void k_check_finite(const double* __restrict__ x, int64_t count, int32_t* flag) {
@@ -553,6 +622,10 @@ __global__ void k_check_finite(const double* __restrict__ x, int64_t count, int3
 }
 
 // ---------------------------------------------------------------------------------------
+const void* price_kernel() { return reinterpret_cast<const void*>(&k_price); }
+const void* update_kernel() { return reinterpret_cast<const void*>(&k_update); }
+const void* finish_kernel() { return reinterpret_cast<const void*>(&k_finish); }
+
 size_t price_lds_bytes(int ld) { return sizeof(double) * (size_t)ld; }
 size_t update_lds_bytes(int ld) { return 2 * sizeof(double) * (size_t)ld; }
 
@@ -582,6 +655,11 @@ hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s) {
 
 hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_update, dim3(grid), dim3(kUpdateBlock), update_lds_bytes(lp.ld), s, lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const DevLP& lp, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kUpdateBlock), 0, s, lp);
   return hipGetLastError();
 }
 

@@ -39,13 +39,13 @@ def test_header_constants_match_binding():
 
 def test_struct_layouts():
     assert C.sizeof(binding.lp_options) == 72
-    assert C.sizeof(binding.lp_stats) == 104
+    assert C.sizeof(binding.lp_stats) == 120
 
 
 def test_default_options():
     o = lpg.default_options()
     assert o.sense == binding.LP_MAX and o.tabu_tenure == 5 and o.leaving_list == 1
-    assert o.eps_d == 1e-9 and o.eps_p == 1e-9 and o.eps_z == 1e-12 and o.eps_t == 1e-11 and o.max_iter == 0
+    assert o.eps_d == 1e-9 and o.eps_p == 1e-9 and o.eps_z == 1e-9 and o.eps_t == 1e-11 and o.max_iter == 0
     assert lpg.lib().lp_default_options(None) == binding.LP_ERR_ARG
 
 

@@ -236,3 +236,12 @@ def test_dense_4000x8000_bench_configuration(lpg):
     assert st == oracle.OPTIMAL
     assert_kkt(A, b, c, sol["x"], sol["y"])
     assert abs(sol["objective"] - float(c @ sol["x"])) <= 1e-12 * abs(sol["objective"])
+
+
+@pytest.mark.parametrize("profile", [1, 2])
+def test_profiling_modes_time_kernels_without_changing_results(lpg, profile):
+    A, b, c = lpgen.dense_lp(13, 500, 1000)
+    ref, (st, sol, piv, stats) = assert_parity(lpg, A, b, c, profile=profile, iters_per_sync=4)
+    assert stats["price_launches"] > 0 and stats["update_launches"] == stats["price_launches"]
+    assert stats["price_ms"] > 0 and stats["update_ms"] > 0
+    assert stats["update_bytes"] == 16.0 * 500 * 500 * stats["update_launches"]
