@@ -104,6 +104,38 @@ def solve_leg(lpg, torch, dev, opts):
                 objective=sol["objective"], iter_per_s=round(sol["iterations"] / ts, 1))
 
 
+def batch_leg(lpg, count, serial_sample):
+    """Batched form: `count` LPs, m ~ U{16..256}, n = 2m, dense law with per-instance seeds,
+    solved in one persistent launch, against serial lp_solve calls on a sample of them."""
+    import lpgen
+    lps = lpgen.batch_lps(0, count)
+    with lpg.Batch(lps) as bt:
+        bt.solve()  # the first solve also runs the autotuner
+        t0 = time.perf_counter()
+        bt.solve()
+        wall = time.perf_counter() - t0
+        st = bt.stats()
+        res = bt.results()
+    iters = int(res["iterations"].sum())
+    idx = list(range(0, count, max(1, count // serial_sample)))[:serial_sample]
+    handles = [lpg.LP(*lps[i]) for i in idx]
+    for h in handles[:4]:
+        h.solve()
+        h.reset()
+    t0 = time.perf_counter()
+    for h in handles:
+        h.solve()
+    serial = (time.perf_counter() - t0) / len(handles)
+    for h in handles:
+        h.close()
+    lps_per_s = count / (st["solve_ms"] * 1e-3)
+    return dict(lps=count, lps_per_s=round(lps_per_s, 1), solve_ms=round(st["solve_ms"], 3),
+                wall_ms=round(wall * 1e3, 3), pivots=iters, all_optimal=bool((res["status"] == 1).all()),
+                narrow_lps=st["narrow_lps"], wide_lps=st["wide_lps"], tune_ms=round(st["tune_ms"], 1),
+                serial_ms_per_lp=round(serial * 1e3, 4), serial_sample=len(handles),
+                serial_lps_per_s=round(1.0 / serial, 1), speedup_vs_serial=round(lps_per_s * serial, 1))
+
+
 def cpu_baseline(A, b, c, pivots):
     import oracle
     o = oracle.Oracle(A, b, c)
@@ -126,6 +158,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--iters-per-sync", type=int, default=16)
     ap.add_argument("--cpu-pivots", type=int, default=100, help="oracle sample size (0 = skip)")
+    ap.add_argument("--batch", type=int, default=4096, help="LPs in the batched leg (0 = skip)")
+    ap.add_argument("--serial-sample", type=int, default=256,
+                    help="LPs of the batch also solved one by one with lp_solve")
     ap.add_argument("--quick", action="store_true",
                     help="timed leg only (no cross-check, time-to-optimality or CPU legs); for profiler runs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -181,6 +216,10 @@ def main():
         extra["unprofiled_iter_per_s"] = round(args.steps / el0, 2)
         _log("bench: time to optimality")
         extra["solve"] = solve_leg(lpg, torch, dev, opts)
+
+    if not args.quick and args.batch > 0:
+        _log(f"bench: batched leg, {args.batch} LPs")
+        extra["batch"] = batch_leg(lpg, args.batch, args.serial_sample)
 
     cpu = None
     if args.cpu_pivots > 0 and not args.quick:

@@ -45,7 +45,7 @@ extern "C" {
 
 /* ---- pivot-log flags ---- */
 #define LP_PIVOT_DEGENERATE 1 /* step length theta == 0 */
-#define LP_PIVOT_TIE 2        /* several rows are within the tie tolerance of the minimum ratio (Step 6) */
+#define LP_PIVOT_TIE 2        /* several rows reach zero (within eps_t) at the minimum step (Step 6) */
 #define LP_PIVOT_ASPIRATION 4 /* every improving variable was tabu; chosen among all of them */
 #define LP_PIVOT_LCLEAR 8     /* the tabu list of the entering variable excluded every tied row */
 
@@ -53,7 +53,7 @@ extern "C" {
 #define LP_MAX 1
 
 /* Largest m this build accepts: B^-1 pivot row and entering column are staged in LDS. */
-#define LP_MAX_ROWS 10176
+#define LP_MAX_ROWS 10112
 
 typedef struct lp_options {
   int32_t sense;          /* LP_MIN or LP_MAX (default LP_MAX) */
@@ -64,11 +64,14 @@ typedef struct lp_options {
   double eps_d;           /* optimality tolerance on reduced costs (default 1e-9) */
   double eps_p;           /* pivot tolerance: rows with alpha_i > eps_p are ratio candidates (1e-9) */
   double eps_z;           /* after each pivot |x_B,i| < eps_z is set to 0 (default 1e-9) */
-  double eps_t;           /* rows with ratio <= theta_min + eps_t*max(1,theta_min) are tied (default 1e-11) */
+  double eps_t;           /* a row is tied in the ratio test when its value at the minimum step is
+                             <= eps_t, i.e. it reaches zero with the leaving row (default 1e-9) */
   int32_t record_pivots;  /* 1 = keep the pivot log readable by lp_get_pivots (default 1) */
   int32_t profile;        /* 1 = time every kernel of the iteration with HIP event nodes in the
                              iteration graph; 2 = launch the kernels directly on the stream with
                              HIP events between them (no graph); 0 = off (default) */
+  int32_t batch_small_m;  /* batched solver: LPs with m <= this get one wavefront each, larger ones a
+                             whole workgroup; -1 = chosen per m-bucket by timing (default) */
   void *stream;           /* hipStream_t to run on; NULL = a stream owned by the handle */
 } lp_options;
 
@@ -88,6 +91,7 @@ typedef struct lp_stats {
   double update_bytes;      /* algorithmic bytes of those update launches: 16*m*m (8*m*m if no pivot pending) */
   int64_t finish_launches;  /* ratio-test finishing kernels timed (profile = 1 or 2) */
   double finish_ms;         /* their summed duration */
+  int64_t ray;              /* after LP_UNBOUNDED: the entering variable with no positive alpha_i; else -1 */
 } lp_stats;
 
 typedef struct lp_problem lp_problem;
@@ -150,6 +154,56 @@ int lp_get_stats(const lp_problem *p, lp_stats *s);
 
 /* Frees every device and host resource of the handle.  NULL-safe. */
 void lp_destroy(lp_problem *p);
+
+/* ---- batched form: many independent LPs in one persistent kernel launch ---- */
+
+typedef struct lp_batch lp_batch;
+
+typedef struct lp_batch_stats {
+  int64_t count;              /* LPs in the batch */
+  int64_t narrow_lps;         /* LPs solved by one wavefront each in the last solve */
+  int64_t wide_lps;           /* LPs solved by a whole workgroup */
+  int64_t work_items;         /* queue entries of the last launch */
+  int64_t workgroups;         /* persistent workgroups launched */
+  int64_t lds_bytes;          /* LDS per workgroup */
+  int64_t narrow_bucket_mask; /* bit k: m in (16k, 16k+16] was tuned to one wavefront per LP */
+  double solve_ms;            /* device time of the last lp_batch_solve launch */
+  double tune_ms;             /* host time spent by the autotuner */
+} lp_batch_stats;
+
+/*
+ * Creates a batch of `count` LPs, each given as in lp_create (host arrays: A[i] is m[i]*n[i]
+ * doubles column-major, b[i] m[i] doubles >= 0, c[i] n[i] doubles); all LPs share *opt
+ * (NULL = defaults).  Data are copied to device memory owned by the handle.  Every LP of
+ * the batch follows exactly the iteration of lp_solve and gives bit-identical results.
+ * Errors: LP_ERR_ARG (sizes, NULL, non-finite data, an LP too large for the solver's LDS
+ * budget), LP_ERR_NEG_RHS, LP_ERR_NOMEM, LP_ERR_DEVICE.
+ */
+int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32_t *n, const double *const *A,
+                    const double *const *b, const double *const *c, const lp_options *opt);
+
+/* Solves every LP of the batch from its slack basis in one persistent launch (the first
+ * call with batch_small_m = -1 first times both execution modes per m-bucket). */
+int lp_batch_solve(lp_batch *bt);
+
+/* Per-LP status, objective (user's sense) and pivot count; arrays of `count` entries, any
+ * may be NULL.  LP_ERR_STATE before the first lp_batch_solve. */
+int lp_batch_results(const lp_batch *bt, int32_t *status, double *objective, int64_t *iterations);
+
+/* LP i: structural x (n[i]), basis (m[i]), and up to `capacity` pivot-log entries; any
+ * pointer may be NULL; *count receives the number of logged pivots. */
+int lp_batch_get(const lp_batch *bt, int32_t i, double *x, int32_t *basis, int32_t *entering, int32_t *leaving_row,
+                 int32_t *flags, int64_t capacity, int64_t *count);
+
+int lp_batch_get_stats(const lp_batch *bt, lp_batch_stats *s);
+
+/* NULL-safe. */
+void lp_batch_destroy(lp_batch *bt);
+
+/* lp_batch_create + lp_batch_solve + lp_batch_results + lp_batch_destroy. */
+int lp_solve_batch(int32_t count, const int32_t *m, const int32_t *n, const double *const *A, const double *const *b,
+                   const double *const *c, const lp_options *opt, int32_t *status, double *objective,
+                   int64_t *iterations);
 
 /* Text for a return code; for an error returned by the calling thread's most recent
  * call, the text also names the failing step.  The pointer stays valid until the next

@@ -101,7 +101,7 @@ class Oracle:
     """One LP held by the oracle; run() may be called repeatedly (resume)."""
 
     def __init__(self, A, b, c, sense="max", tenure=5, leaving_list=True, eps_d=1e-9, eps_p=1e-9,
-                 eps_z=1e-9, eps_t=1e-11, lib_path=None):
+                 eps_z=1e-9, eps_t=1e-9, lib_path=None):
         self._L = lib(lib_path)
         A = np.asarray(A, dtype=np.float64)
         m, n = A.shape

@@ -25,16 +25,17 @@
  *     the paper's z_j - c_j equals -d_j.                        (Steps 3-4)
  *   - Y_k <= 0 read as "no alpha_i > eps_p".                    (Steps 5-6)
  *   - entering ties: lowest variable index (slacks after structurals).
- *   - ratio_i = max(xB_i, 0) / alpha_i (IEEE division), theta_min = min ratio_i.
- *     "No unique leaving element" (Sections 2.2, 3.4) is a statement about exact
- *     ratios; in FP64 rounding splits such ties by a few ulps, so the tied rows are
- *     those with ratio_i <= theta_min + eps_t * max(1, theta_min).  Every tied row
- *     gives the same objective change, so the paper's "most noticeable improvement"
- *     cannot separate them; the tie is broken by the lowest row whose basic variable
- *     is not in the tabu list L[q] of the entering variable q, and that leaving
- *     variable is then appended to L[q].  If L[q] excludes every tied row, L[q] is
- *     cleared and the lowest tied row is taken.  The pivot itself is Step 8's:
- *     theta = ratio_r of the chosen row r.
+ *   - ratio_i = max(xB_i, 0) / alpha_i (IEEE division), theta = min ratio_i.
+ *     "No unique leaving element" (Sections 2.2, 3.4) means several rows reach zero
+ *     at the step theta.  In FP64 rounding splits such ties, so a row is tied when
+ *     the value it takes at that step, fma(-alpha_i, theta, max(xB_i, 0)), is at most
+ *     eps_t; this tolerance is in the units of x and is not magnified by a large
+ *     alpha_i.  Every tied row gives the same objective change, so the paper's "most
+ *     noticeable improvement" cannot separate them; the tie is broken by the lowest
+ *     row whose basic variable is not in the tabu list L[q] of the entering variable
+ *     q, and that leaving variable is then appended to L[q].  If L[q] excludes every
+ *     tied row, L[q] is cleared and the lowest tied row is taken.  The step is theta
+ *     for whichever tied row leaves.
  *   - entering mask: a variable that leaves at iteration t may not enter at
  *     iterations t+1 .. t+tenure; if every improving variable is masked, the
  *     choice is made among all improving variables (aspiration).
@@ -59,7 +60,7 @@
 #define OR_ITER_LIMIT 3
 
 #define FLAG_DEGENERATE 1  /* theta == 0 */
-#define FLAG_TIE 2         /* more than one row is within the tie tolerance of the minimum ratio */
+#define FLAG_TIE 2         /* more than one row reaches zero (within eps_t) at the step */
 #define FLAG_ASPIRATION 4  /* every improving variable was masked */
 #define FLAG_LCLEAR 8      /* L[q] excluded every tied row and was cleared */
 
@@ -248,10 +249,10 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
     if (p->ratio[i] < theta_min) theta_min = p->ratio[i];
   }
   if (nR == 0) { p->ray = q; return OR_UNBOUNDED; } /* Step 5: Y_k <= 0 */
-  const double tie_bound = theta_min + p->eps_t * fmax(1.0, theta_min);
   int32_t nT = 0, r_low = -1, r_free = -1;
   for (int32_t i = 0; i < m; ++i) {
-    if (!(p->alpha[i] > p->eps_p) || !(p->ratio[i] <= tie_bound)) continue;
+    if (!(p->alpha[i] > p->eps_p)) continue;
+    if (!(fma(-p->alpha[i], theta_min, fmax(p->xB[i], 0.0)) <= p->eps_t)) continue; /* not tied */
     nT++;
     if (r_low < 0) r_low = i;
     if (r_free < 0 && !(p->use_llist && in_list(p, q, p->basis[i]))) r_free = i;
@@ -266,7 +267,7 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
       if (list_add(p, q, p->basis[r])) return -1;
     }
   }
-  const double theta = p->ratio[r];
+  const double theta = theta_min;
   if (theta == 0.0) { flags |= FLAG_DEGENERATE; p->n_degenerate++; }
 
   /* Step 7 and the tabu mask: the leaving variable may not re-enter for `tenure` iterations. */

@@ -17,7 +17,7 @@ LP_OK, LP_ERR_ARG, LP_ERR_NEG_RHS, LP_ERR_NOMEM, LP_ERR_DEVICE, LP_ERR_STATE = 0
 LP_RUNNING, LP_OPTIMAL, LP_UNBOUNDED, LP_ITER_LIMIT = 0, 1, 2, 3
 LP_PIVOT_DEGENERATE, LP_PIVOT_TIE, LP_PIVOT_ASPIRATION, LP_PIVOT_LCLEAR = 1, 2, 4, 8
 LP_MIN, LP_MAX = 0, 1
-LP_MAX_ROWS = 10176
+LP_MAX_ROWS = 10112
 STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT"}
 
 
@@ -34,6 +34,7 @@ class lp_options(C.Structure):
         ("eps_t", C.c_double),
         ("record_pivots", C.c_int32),
         ("profile", C.c_int32),
+        ("batch_small_m", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -55,6 +56,21 @@ class lp_stats(C.Structure):
         ("update_bytes", C.c_double),
         ("finish_launches", C.c_int64),
         ("finish_ms", C.c_double),
+        ("ray", C.c_int64),
+    ]
+
+
+class lp_batch_stats(C.Structure):
+    _fields_ = [
+        ("count", C.c_int64),
+        ("narrow_lps", C.c_int64),
+        ("wide_lps", C.c_int64),
+        ("work_items", C.c_int64),
+        ("workgroups", C.c_int64),
+        ("lds_bytes", C.c_int64),
+        ("narrow_bucket_mask", C.c_int64),
+        ("solve_ms", C.c_double),
+        ("tune_ms", C.c_double),
     ]
 
 
@@ -84,6 +100,15 @@ SIGNATURES = {
     "lp_get_stats": (C.c_int, [_P, C.POINTER(lp_stats)]),
     "lp_destroy": (None, [_P]),
     "lp_error_string": (C.c_char_p, [C.c_int]),
+    "lp_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, _IP, _IP, C.POINTER(_DP), C.POINTER(_DP),
+                                  C.POINTER(_DP), C.POINTER(lp_options)]),
+    "lp_batch_solve": (C.c_int, [_P]),
+    "lp_batch_results": (C.c_int, [_P, _IP, _DP, _LP]),
+    "lp_batch_get": (C.c_int, [_P, C.c_int32, _DP, _IP, _IP, _IP, _IP, C.c_int64, _LP]),
+    "lp_batch_get_stats": (C.c_int, [_P, C.POINTER(lp_batch_stats)]),
+    "lp_batch_destroy": (None, [_P]),
+    "lp_solve_batch": (C.c_int, [C.c_int32, _IP, _IP, C.POINTER(_DP), C.POINTER(_DP), C.POINTER(_DP),
+                                 C.POINTER(lp_options), _IP, _DP, _LP]),
 }
 
 
@@ -214,3 +239,75 @@ class LP:
         s = lp_stats()
         _check(lib().lp_get_stats(self._h, C.byref(s)), "lp_get_stats")
         return {f: getattr(s, f) for f, _ in lp_stats._fields_}
+
+
+class Batch:
+    """A batch of independent LPs (an lp_batch handle), solved in one persistent launch."""
+
+    def __init__(self, lps, sense="max", **opts):
+        """lps: sequence of (A, b, c) host arrays, A of shape (m_i, n_i)."""
+        o = default_options(sense=LP_MAX if sense == "max" else LP_MIN, **opts)
+        cnt = len(lps)
+        As, bs, cs = [], [], []
+        ms = np.empty(cnt, dtype=np.int32)
+        ns = np.empty(cnt, dtype=np.int32)
+        for i, (A, b, c) in enumerate(lps):
+            A = np.asfortranarray(np.asarray(A, dtype=np.float64))
+            As.append(A)
+            bs.append(np.ascontiguousarray(b, dtype=np.float64))
+            cs.append(np.ascontiguousarray(c, dtype=np.float64))
+            ms[i], ns[i] = A.shape
+            if bs[-1].shape != (ms[i],) or cs[-1].shape != (ns[i],):
+                raise ValueError(f"LP {i}: shapes of A, b, c do not match")
+        self._keep = (As, bs, cs, ms, ns)
+        pa = (_DP * cnt)(*[_dptr(a) for a in As])
+        pb = (_DP * cnt)(*[_dptr(a) for a in bs])
+        pc = (_DP * cnt)(*[_dptr(a) for a in cs])
+        h = _P()
+        _check(lib().lp_batch_create(C.byref(h), cnt, ms.ctypes.data_as(_IP), ns.ctypes.data_as(_IP), pa, pb, pc,
+                                     C.byref(o)), "lp_batch_create")
+        self._h = h
+        self.count, self.m, self.n = cnt, ms, ns
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().lp_batch_destroy(h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def solve(self):
+        _check(lib().lp_batch_solve(self._h), "lp_batch_solve")
+
+    def results(self):
+        st = np.empty(self.count, dtype=np.int32)
+        obj = np.empty(self.count)
+        it = np.empty(self.count, dtype=np.int64)
+        _check(lib().lp_batch_results(self._h, st.ctypes.data_as(_IP), _dptr(obj), it.ctypes.data_as(_LP)),
+               "lp_batch_results")
+        return dict(status=st, objective=obj, iterations=it)
+
+    def get(self, i):
+        m, n = int(self.m[i]), int(self.n[i])
+        x = np.empty(n)
+        basis = np.empty(m, dtype=np.int32)
+        cnt = C.c_int64()
+        _check(lib().lp_batch_get(self._h, i, _dptr(x), basis.ctypes.data_as(_IP), None, None, None, 0,
+                                  C.byref(cnt)), "lp_batch_get")
+        k = cnt.value
+        arrs = [np.empty(k, dtype=np.int32) for _ in range(3)]
+        _check(lib().lp_batch_get(self._h, i, None, None, *[a.ctypes.data_as(_IP) for a in arrs], k, C.byref(cnt)),
+               "lp_batch_get")
+        return dict(x=x, basis=basis, enter=arrs[0], row=arrs[1], flags=arrs[2])
+
+    def stats(self) -> dict:
+        s = lp_batch_stats()
+        _check(lib().lp_batch_get_stats(self._h, C.byref(s)), "lp_batch_get_stats")
+        return {f: getattr(s, f) for f, _ in lp_batch_stats._fields_}

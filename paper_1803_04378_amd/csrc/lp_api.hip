@@ -32,6 +32,14 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+namespace lpgpu {
+int record_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace lpgpu
+
+namespace {
+
 int fail_hip(hipError_t e, const char* what) {
   if (e == hipErrorOutOfMemory) return fail(LP_ERR_NOMEM, std::string(what) + ": " + hipGetErrorString(e));
   return fail(LP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -298,6 +306,8 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   const int pw = kPriceBlock / 64, uw = kUpdateBlock / 64;
   p->price_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)price_per_cu * p->num_cu, (n + pw - 1) / pw));
   p->update_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)update_per_cu * p->num_cu, (m + uw - 1) / uw));
+  if ((m + (int64_t)p->update_grid * uw - 1) / ((int64_t)p->update_grid * uw) > kMaxRowsPerWave)
+    return bail(fail(LP_ERR_ARG, "m too large for this device: more than kMaxRowsPerWave rows per wavefront"));
 
   // Device memory: A' (ld x n) + B^-1 (m x ld) dominate.
   {
@@ -320,7 +330,6 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   ALLOC(p->d.xB, (size_t)m);
   ALLOC(p->d.W0, (size_t)ld);
   ALLOC(p->d.W1, (size_t)ld);
-  ALLOC(p->d.ratio, (size_t)m);
   ALLOC(p->d.rho, (size_t)ld);
   ALLOC(p->d.alpha0, (size_t)m);
   ALLOC(p->d.alpha1, (size_t)m);
@@ -332,8 +341,9 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   ALLOC(p->d.part_d, 2 * (size_t)p->price_grid);
   ALLOC(p->d.part_j, 2 * (size_t)p->price_grid);
   ALLOC(p->d.part_th, (size_t)p->update_grid);
-  ALLOC(p->d.part_cnt, (size_t)p->update_grid);
   ALLOC(p->d.part_low, (size_t)p->update_grid);
+  ALLOC(p->d.part_t1, (size_t)p->update_grid);
+  ALLOC(p->d.part_t2, (size_t)p->update_grid);
   ALLOC(p->d.ctrl, 1);
   ALLOC(p->b0, (size_t)m);
   ALLOC(p->c0, (size_t)std::max(n, 1));
@@ -419,9 +429,10 @@ int lp_default_options(lp_options* opt) {
   opt->eps_d = 1e-9;
   opt->eps_p = 1e-9;
   opt->eps_z = 1e-9;
-  opt->eps_t = 1e-11;
+  opt->eps_t = 1e-9;
   opt->record_pivots = 1;
   opt->profile = 0;
+  opt->batch_small_m = -1;
   opt->stream = nullptr;
   return LP_OK;
 }
@@ -589,6 +600,7 @@ int lp_get_stats(const lp_problem* p, lp_stats* s) {
   s->ties = p->h_ctrl->n_tie;
   s->aspirations = p->h_ctrl->n_aspiration;
   s->list_clears = p->h_ctrl->n_lclear;
+  s->ray = p->h_ctrl->status == LP_UNBOUNDED ? p->h_ctrl->ray : -1;
   return LP_OK;
 }
 

@@ -1,0 +1,421 @@
+// Batched form: many independent small LPs solved by one persistent kernel launch.
+//
+// Each LP runs the same iteration as the single-LP path (Section 2.1 Steps 3-8 on the
+// Figure 1 tableau, Section 3.1 update, tabu rule of Sections 2.2/3.4), with the same
+// element-wise arithmetic and the same per-lane dot-product order, so every result is
+// bit-identical to lp_solve on that LP alone.  What changes is the execution shape:
+//
+//   * 256-thread workgroups pop work items from an atomic queue until it is empty (every
+//     wave reaches the exit); items are ordered largest first by the host.
+//   * An item is either one LP solved by all 4 wavefronts of the workgroup ("wide",
+//     block barriers between steps) or up to 4 small LPs, one per wavefront ("narrow",
+//     no block barriers at all: each wavefront runs its own LP with wave-level
+//     reductions).  The host picks the mode per m-bucket (autotuned by timing).
+//   * The LP's vectors (W, rho, a_q, alpha x2, x_B, ratios) and its basis bookkeeping
+//     live in LDS for the whole solve; A' and B^-1 stay in HBM / cache.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lp_batch.h"
+#include "lp_device.h"
+#include "lp_wave.h"
+
+namespace lpgpu {
+using namespace detail;
+
+namespace {
+
+// Group synchronisation: G == 1 is one wavefront (lockstep; the fence orders its LDS and
+// global accesses), G > 1 is the whole workgroup.
+template <int G>
+__device__ __forceinline__ void gsync() {
+  if constexpr (G == 1) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
+// Group reductions: every thread of the group returns the same value.
+template <int G>
+__device__ __forceinline__ void g_lexmin2(double& d1, int& j1, double& d2, int& j2, double* xd, int* xj) {
+  wave_lexmin(d1, j1);
+  wave_lexmin(d2, j2);
+  if constexpr (G > 1) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+      xd[wave] = d1;
+      xj[wave] = j1;
+      xd[G + wave] = d2;
+      xj[G + wave] = j2;
+    }
+    __syncthreads();
+    d1 = xd[0];
+    j1 = xj[0];
+    d2 = xd[G];
+    j2 = xj[G];
+    for (int w = 1; w < G; ++w) {
+      if (lex_less(xd[w], xj[w], d1, j1)) {
+        d1 = xd[w];
+        j1 = xj[w];
+      }
+      if (lex_less(xd[G + w], xj[G + w], d2, j2)) {
+        d2 = xd[G + w];
+        j2 = xj[G + w];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int G>
+__device__ __forceinline__ double g_min(double v, double* xd) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  if constexpr (G > 1) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) xd[wave] = v;
+    __syncthreads();
+    v = xd[0];
+    for (int w = 1; w < G; ++w) v = fmin(v, xd[w]);
+    __syncthreads();
+  }
+  return v;
+}
+
+template <int G>
+__device__ __forceinline__ void g_cnt_min(int& cnt, int& low, int* xj) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    cnt += __shfl_xor(cnt, off);
+    low = min(low, __shfl_xor(low, off));
+  }
+  if constexpr (G > 1) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+      xj[wave] = cnt;
+      xj[G + wave] = low;
+    }
+    __syncthreads();
+    cnt = 0;
+    low = INT_MAX;
+    for (int w = 0; w < G; ++w) {
+      cnt += xj[w];
+      low = min(low, xj[G + w]);
+    }
+    __syncthreads();
+  }
+}
+
+size_t lds_doubles(int m, int ld) { return 3 * (size_t)ld + 4 * (size_t)m; }
+size_t lds_ints(int m, int n) { return (size_t)m + 2 * ((size_t)n + m); }
+
+}  // namespace
+
+size_t batch_lds_bytes(int m, int n) {
+  const int ld = (m + 7) / 8 * 8;
+  const size_t bytes = 8 * lds_doubles(m, ld) + 4 * lds_ints(m, n);
+  return (bytes + 15) / 16 * 16;
+}
+
+// One LP, solved by a group of G wavefronts; tid is the thread's index within the group.
+template <int G>
+__device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int tid, double* xd, int* xj) {
+  constexpr int T = 64 * G;
+  const BatchLP L = bd.lps[id];
+  const int m = L.m, n = L.n, ld = L.ld, ld2 = ld / 2, N = n + m;
+  const int lane = tid & 63, wave = tid >> 6;
+  double* W = reinterpret_cast<double*>(base);
+  double* rho = W + ld;
+  double* av = rho + ld;
+  double* al0 = av + ld;
+  double* al1 = al0 + m;
+  double* xB = al1 + m;
+  double* ratio = xB + m;
+  int* basis = reinterpret_cast<int*>(ratio + m);
+  int* pos = basis + m;
+  int* tabu = pos + N;
+  double2* W2 = reinterpret_cast<double2*>(W);
+  double2* rho2 = reinterpret_cast<double2*>(rho);
+  double2* a2 = reinterpret_cast<double2*>(av);
+
+  const double* A = bd.A + L.offA;
+  const double2* A2 = reinterpret_cast<const double2*>(A);
+  const double* bb = bd.b + L.offb;
+  const double* cc = bd.c + L.offc;
+  double* B = bd.Binv + L.offB;
+  double2* B2 = reinterpret_cast<double2*>(B);
+  int* gen = bd.iscr + L.offI;
+  int* excl = gen + N;
+  int32_t* lg_e = bd.log_enter + L.offLog;
+  int32_t* lg_r = bd.log_row + L.offLog;
+  int32_t* lg_l = bd.log_leave + L.offLog;
+  int32_t* lg_f = bd.log_flags + L.offLog;
+  int32_t* Lq = bd.Lq + L.offLog;
+  int32_t* Ll = bd.Ll + L.offLog;
+  int32_t* Lg = bd.Lgen + L.offLog;
+  const double sense = bd.sense;
+
+  // Step 1: slack basis.
+  for (int k = tid; k < ld; k += T) {
+    W[k] = 0.0;
+    rho[k] = 0.0;
+  }
+  for (int i = tid; i < m; i += T) {
+    xB[i] = bb[i];
+    basis[i] = n + i;
+    al0[i] = 0.0;
+    al1[i] = 0.0;
+  }
+  for (int v = tid; v < N; v += T) {
+    pos[v] = v < n ? -1 : v - n;
+    tabu[v] = -1;
+    gen[v] = 0;
+    excl[v] = -1;
+  }
+  for (int i = wave; i < m; i += G)
+    for (int k = lane; k < ld2; k += 64)
+      B2[(size_t)i * ld2 + k] = make_double2(2 * k == i ? 1.0 : 0.0, 2 * k + 1 == i ? 1.0 : 0.0);
+  gsync<G>();
+
+  int64_t t = 0;
+  int status = kStatusRunning, ray = -1, r = -1, cur = 0, nL = 0;
+  double theta = 0.0, z = 0.0;
+  const double neg_eps = -bd.eps_d;
+  double2 v[kBatch];
+  for (;;) {
+    // Steps 3-4: reduced costs with W in LDS.
+    double da = __builtin_inf(), df = __builtin_inf();
+    int ja = INT_MAX, jf = INT_MAX;
+    for (int j = wave; j < n; j += G) {
+      if (pos[j] >= 0) continue;
+      const double s = wave_dot<kStreamA>(A2 + (size_t)j * ld2, W2, ld2, lane, v, false);
+      const double d = sense * cc[j] - s;
+      if (d < neg_eps) {
+        if (lex_less(d, j, da, ja)) {
+          da = d;
+          ja = j;
+        }
+        if (tabu[j] < t && lex_less(d, j, df, jf)) {
+          df = d;
+          jf = j;
+        }
+      }
+    }
+    for (int i = tid; i < m; i += T) {
+      const int vv = n + i;
+      if (pos[vv] >= 0) continue;
+      const double d = 0.0 - W[i];
+      if (d < neg_eps) {
+        if (lex_less(d, vv, da, ja)) {
+          da = d;
+          ja = vv;
+        }
+        if (tabu[vv] < t && lex_less(d, vv, df, jf)) {
+          df = d;
+          jf = vv;
+        }
+      }
+    }
+    g_lexmin2<G>(da, ja, df, jf, xd, xj);
+    int q = -1, flags = 0;
+    double dq = 0.0;
+    if (ja == INT_MAX) {
+      status = kStatusOptimal;
+    } else if (t >= L.cap) {
+      status = kStatusIterLimit;
+    } else if (jf != INT_MAX) {
+      q = jf;
+      dq = df;
+    } else {
+      q = ja;
+      dq = da;
+      flags = kFlagAspiration;
+    }
+    if (q >= 0) {
+      if (q < n) {
+        for (int k = tid; k < ld2; k += T) a2[k] = A2[(size_t)q * ld2 + k];
+      } else {
+        const int e = q - n;
+        for (int k = tid; k < ld2; k += T) a2[k] = make_double2(2 * k == e ? 1.0 : 0.0, 2 * k + 1 == e ? 1.0 : 0.0);
+      }
+    }
+    gsync<G>();
+
+    // Section 3.1 update of the pending pivot fused with Step 5 and the per-row ratios.
+    double* al_p = cur ? al1 : al0;
+    double* al_n = cur ? al0 : al1;
+    if (r >= 0 || q >= 0) {
+      for (int i = wave; i < m; i += G) {
+        double2* row = B2 + (size_t)i * ld2;
+        double acc = 0.0;
+        double x = xB[i];
+        if (r < 0) {
+          acc = wave_dot<false>(row, a2, ld2, lane, v, false);
+        } else {
+          if (i == r) {
+            acc = q >= 0 ? wave_store_dot<true>(row, rho2, a2, ld2, lane)
+                         : wave_store_dot<false>(row, rho2, a2, ld2, lane);
+            x = theta;
+          } else {
+            const double na = -al_p[i];
+            acc = q >= 0 ? wave_update_dot<true>(row, rho2, a2, na, ld2, lane, v, false)
+                         : wave_update_dot<false>(row, rho2, a2, na, ld2, lane, v, false);
+            x = fma(na, theta, x);
+          }
+          if (fabs(x) < bd.eps_z) x = 0.0;
+        }
+        if (lane == 0) {
+          xB[i] = x;
+          if (q >= 0) {
+            al_n[i] = acc;
+            ratio[i] = acc > bd.eps_p ? fmax(x, 0.0) / acc : __builtin_inf();
+          }
+        }
+      }
+    }
+    gsync<G>();
+    r = -1;
+    if (q < 0) break;  // OPTIMAL or ITER_LIMIT; the pending pivot is applied
+
+    // Step 6: minimum ratio, tolerance ties, tabu list of the entering variable.
+    double th = __builtin_inf();
+    for (int i = tid; i < m; i += T) th = fmin(th, ratio[i]);
+    th = g_min<G>(th, xd);
+    if (th == __builtin_inf()) {  // Step 5: Y_k <= 0
+      status = kStatusUnbounded;
+      ray = q;
+      break;
+    }
+    // A row is tied when it reaches zero (within eps_t) at the step th.
+    int cnt = 0, low = INT_MAX;
+    for (int i = tid; i < m; i += T)
+      if (al_n[i] > bd.eps_p && fma(-al_n[i], th, fmax(xB[i], 0.0)) <= bd.eps_t) {
+        ++cnt;
+        low = min(low, i);
+      }
+    g_cnt_min<G>(cnt, low, xj);
+    int rn = low;
+    if (cnt >= 2) {
+      flags |= kFlagTie;
+      if (bd.use_llist) {
+        const int stamp = (int)t + 1;
+        const int g = gen[q];
+        for (int k = tid; k < nL; k += T)
+          if (Lq[k] == q && Lg[k] == g) excl[Ll[k]] = stamp;
+        gsync<G>();
+        int fc = 0, fl = INT_MAX;
+        for (int i = tid; i < m; i += T)
+          if (al_n[i] > bd.eps_p && fma(-al_n[i], th, fmax(xB[i], 0.0)) <= bd.eps_t && excl[basis[i]] != stamp)
+            fl = min(fl, i);
+        g_cnt_min<G>(fc, fl, xj);
+        int gnew = g;
+        if (fl == INT_MAX) {
+          flags |= kFlagLClear;
+          gnew = g + 1;
+        } else {
+          rn = fl;
+        }
+        if (tid == 0) {
+          if (gnew != g) gen[q] = gnew;
+          if (nL < L.cap) {
+            Lq[nL] = q;
+            Ll[nL] = basis[rn];
+            Lg[nL] = gnew;
+          }
+        }
+        if (nL < L.cap) ++nL;
+      }
+    }
+    // Step 8 pivots on row rn with the step th.
+    const double thr = th;
+    if (thr == 0.0) flags |= kFlagDegenerate;
+    const int leave = basis[rn];
+    const double ar = al_n[rn];
+    gsync<G>();  // every thread has read basis[rn] before it changes
+    if (tid == 0) {
+      if (bd.tenure > 0) tabu[leave] = (int)(t + bd.tenure);
+      basis[rn] = q;
+      pos[q] = rn;
+      pos[leave] = -1;
+      if (t < L.cap) {
+        lg_e[t] = q;
+        lg_r[t] = rn;
+        lg_l[t] = leave;
+        lg_f[t] = flags;
+      }
+    }
+    z = fma(dq, thr, z);
+    ++t;
+    r = rn;
+    theta = thr;
+    cur ^= 1;
+    // Top row of the tableau: rho = B^-1[r,:] / alpha_r from the not yet updated B^-1.
+    for (int k = tid; k < ld2; k += T) {
+      const double2 b = B2[(size_t)r * ld2 + k];
+      const double2 rr = make_double2(b.x / ar, b.y / ar);
+      rho2[k] = rr;
+      const double2 w = W2[k];
+      W2[k] = make_double2(fma(dq, rr.x, w.x), fma(dq, rr.y, w.y));
+    }
+    gsync<G>();
+  }
+
+  double* xo = bd.xB_out + L.offOut;
+  int* bo = bd.basis_out + L.offOut;
+  for (int i = tid; i < m; i += T) {
+    xo[i] = xB[i];
+    bo[i] = basis[i];
+  }
+  if (tid == 0) {
+    bd.status_out[id] = status;
+    bd.iters_out[id] = t;
+    bd.z_out[id] = z;
+    bd.ray_out[id] = ray;
+  }
+}
+
+__global__ __launch_bounds__(kBatchBlock) void k_batch(BatchDev bd) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ double xd[2 * kBatchWaves];
+  __shared__ int xj[2 * kBatchWaves];
+  __shared__ int s_item;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = __hip_atomic_fetch_add(bd.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= bd.n_items) return;
+    const int4 it = bd.items[item];
+    if (bd.lps[it.x].waves > 1) {
+      solve_lp<kBatchWaves>(bd, it.x, lds, threadIdx.x, xd, xj);
+    } else {
+      const int id = wave == 0 ? it.x : wave == 1 ? it.y : wave == 2 ? it.z : it.w;
+      if (id >= 0) solve_lp<1>(bd, id, lds + (size_t)wave * bd.slot_bytes, lane, nullptr, nullptr);
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_batch(const BatchDev& bd, int grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBatchBlock), lds, s, bd);
+  return hipGetLastError();
+}
+
+hipError_t batch_occupancy(int* per_cu, size_t lds) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch, kBatchBlock, lds);
+}
+
+}  // namespace lpgpu

@@ -1,0 +1,472 @@
+// Host side of the batched solver: packing, work-item order, autotuner, C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "lp_batch.h"
+#include "lp_device.h"
+#include "lpgpu.h"
+
+using namespace lpgpu;
+
+namespace lpgpu {
+// Shared with lp_api.hip: error recording for lp_error_string.
+int record_error(int code, const std::string& msg);
+}  // namespace lpgpu
+
+namespace {
+
+int fail(int code, const std::string& msg) { return lpgpu::record_error(code, msg); }
+
+int fail_hip(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? LP_ERR_NOMEM : LP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                            \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return fail_hip(e_, what);   \
+  } while (0)
+
+// m-buckets of the autotuner: (16k, 16k+16]; narrow mode is only possible while one LP
+// fits a wavefront's LDS slot.
+constexpr int kBucketWidth = 16;
+
+}  // namespace
+
+struct lp_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  lp_options opt{};
+  int32_t count = 0;
+  std::vector<BatchLP> lps;        // host copy (waves set per solve)
+  std::vector<std::vector<double>> c;  // host copies of c for the objective
+  std::vector<void*> allocs;
+  BatchDev d{};
+  BatchLP* d_lps = nullptr;
+  int4* d_items = nullptr;
+  int32_t max_items = 0;
+  size_t region = 0;  // LDS bytes per workgroup
+  int grid = 0, per_cu = 0, num_cu = 0;
+  int small_m = -1;   // LPs with m <= small_m are solved one per wavefront (after tuning)
+  std::vector<int> bucket_narrow;  // per bucket: 1 narrow, 0 wide, -1 untuned
+  bool solved = false;
+  double solve_ms = 0.0, tune_ms = 0.0;
+  int64_t narrow_lps = 0, wide_lps = 0, items_last = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+template <class T>
+hipError_t dalloc(lp_batch* p, T** out, size_t count) {
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return e;
+  }
+  p->allocs.push_back(ptr);
+  *out = static_cast<T*>(ptr);
+  return hipSuccess;
+}
+
+void release(lp_batch* p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  for (void* ptr : p->allocs) (void)hipFree(ptr);
+  if (p->ev0) (void)hipEventDestroy(p->ev0);
+  if (p->ev1) (void)hipEventDestroy(p->ev1);
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+// Relative cost of one LP for ordering work items: bytes per iteration (~8 m (n + 2m))
+// times an iteration count growing with m, divided by the wavefronts on it.
+double lp_cost(const BatchLP& L, int waves) {
+  return (double)L.m * ((double)L.n + 2.0 * L.m) * (double)L.m / waves;
+}
+
+// Work items for the LPs in `ids` (indices into p->lps) under the current modes, largest
+// first.  Narrow LPs are packed four per item in descending size.
+std::vector<int4> make_items(const lp_batch* p, const std::vector<int>& ids) {
+  std::vector<int> wide, narrow;
+  for (int i : ids) (p->lps[i].waves == 1 ? narrow : wide).push_back(i);
+  auto bigger = [&](int a, int b) {
+    const double ca = lp_cost(p->lps[a], 1), cb = lp_cost(p->lps[b], 1);
+    return ca != cb ? ca > cb : a < b;
+  };
+  std::sort(wide.begin(), wide.end(), bigger);
+  std::sort(narrow.begin(), narrow.end(), bigger);
+  struct Item {
+    int4 ids;
+    double cost;
+  };
+  std::vector<Item> items;
+  for (int i : wide) items.push_back({make_int4(i, -1, -1, -1), lp_cost(p->lps[i], kBatchWaves)});
+  for (size_t k = 0; k < narrow.size(); k += 4) {
+    int4 it = make_int4(narrow[k], -1, -1, -1);
+    if (k + 1 < narrow.size()) it.y = narrow[k + 1];
+    if (k + 2 < narrow.size()) it.z = narrow[k + 2];
+    if (k + 3 < narrow.size()) it.w = narrow[k + 3];
+    items.push_back({it, lp_cost(p->lps[narrow[k]], 1)});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+  std::vector<int4> out;
+  out.reserve(items.size());
+  for (auto& it : items) out.push_back(it.ids);
+  return out;
+}
+
+int run_items(lp_batch* p, const std::vector<int4>& items, float* ms) {
+  if (items.empty()) {
+    if (ms) *ms = 0.f;
+    return LP_OK;
+  }
+  HIP_TRY(hipMemcpyAsync(p->d_lps, p->lps.data(), sizeof(BatchLP) * p->lps.size(), hipMemcpyHostToDevice, p->stream),
+          "uploading the batch table");
+  HIP_TRY(hipMemcpyAsync(p->d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, p->stream),
+          "uploading work items");
+  HIP_TRY(hipMemsetAsync(p->d.queue, 0, sizeof(int32_t), p->stream), "clearing the work queue");
+  BatchDev d = p->d;
+  d.n_items = (int32_t)items.size();
+  HIP_TRY(hipEventRecord(p->ev0, p->stream), "recording an event");
+  const int grid = std::min<int>(p->grid, (int)items.size());
+  HIP_TRY(launch_batch(d, grid, p->region, p->stream), "launching the batched solver");
+  HIP_TRY(hipEventRecord(p->ev1, p->stream), "recording an event");
+  HIP_TRY(hipEventSynchronize(p->ev1), "running the batched solver");
+  float t = 0.f;
+  HIP_TRY(hipEventElapsedTime(&t, p->ev0, p->ev1), "timing the batched solver");
+  if (ms) *ms = t;
+  return LP_OK;
+}
+
+int bucket_of(int m) { return (m - 1) / kBucketWidth; }
+
+// Chooses narrow or wide per m-bucket by timing both on the bucket's LPs.
+int autotune(lp_batch* p) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const size_t slot = p->region / kBatchWaves;
+  std::vector<std::vector<int>> buckets;
+  for (int i = 0; i < p->count; ++i) {
+    const BatchLP& L = p->lps[i];
+    if (batch_lds_bytes(L.m, L.n) > slot) continue;
+    const int bk = bucket_of(L.m);
+    if ((int)buckets.size() <= bk) buckets.resize(bk + 1);
+    buckets[bk].push_back(i);
+  }
+  p->bucket_narrow.assign(buckets.size(), 0);
+  for (size_t bk = 0; bk < buckets.size(); ++bk) {
+    if (buckets[bk].empty()) continue;
+    float best[2] = {0.f, 0.f};
+    for (int narrow = 0; narrow < 2; ++narrow) {
+      for (int i : buckets[bk]) p->lps[i].waves = narrow ? 1 : kBatchWaves;
+      const std::vector<int4> items = make_items(p, buckets[bk]);
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {  // the second run is timed
+        int rc = run_items(p, items, &ms);
+        if (rc != LP_OK) return rc;
+      }
+      best[narrow] = ms;
+    }
+    p->bucket_narrow[bk] = best[1] < best[0] ? 1 : 0;
+  }
+  p->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return LP_OK;
+}
+
+void assign_modes(lp_batch* p) {
+  const size_t slot = p->region / kBatchWaves;
+  p->narrow_lps = p->wide_lps = 0;
+  for (auto& L : p->lps) {
+    bool narrow = false;
+    if (batch_lds_bytes(L.m, L.n) <= slot) {
+      if (p->small_m >= 0) {
+        narrow = L.m <= p->small_m;
+      } else {
+        const int bk = bucket_of(L.m);
+        narrow = bk < (int)p->bucket_narrow.size() && p->bucket_narrow[bk] == 1;
+      }
+    }
+    L.waves = narrow ? 1 : kBatchWaves;
+    (narrow ? p->narrow_lps : p->wide_lps) += 1;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32_t* n, const double* const* A,
+                    const double* const* b, const double* const* c, const lp_options* opt) {
+  if (!out) return fail(LP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (count <= 0 || !m || !n || !A || !b || !c) return fail(LP_ERR_ARG, "empty batch or NULL array");
+  lp_options o;
+  lp_default_options(&o);
+  if (opt) o = *opt;
+  if (o.sense != LP_MIN && o.sense != LP_MAX) return fail(LP_ERR_ARG, "options.sense must be LP_MIN or LP_MAX");
+  if (o.tabu_tenure < 0 || o.max_iter < 0) return fail(LP_ERR_ARG, "invalid options");
+  size_t max_bytes = 0, max_small = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (m[i] <= 0 || n[i] < 0 || !b[i] || (n[i] > 0 && (!A[i] || !c[i])))
+      return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": invalid size or NULL data");
+    const size_t cnt = (size_t)m[i] * n[i];
+    for (size_t k = 0; k < cnt; ++k)
+      if (!std::isfinite(A[i][k])) return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": non-finite A");
+    for (int32_t k = 0; k < m[i]; ++k) {
+      if (!std::isfinite(b[i][k])) return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": non-finite b");
+      if (b[i][k] < 0.0) return fail(LP_ERR_NEG_RHS, "LP " + std::to_string(i) + ": b_i < 0");
+    }
+    for (int32_t k = 0; k < n[i]; ++k)
+      if (!std::isfinite(c[i][k])) return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": non-finite c");
+    const size_t bytes = batch_lds_bytes(m[i], n[i]);
+    max_bytes = std::max(max_bytes, bytes);
+    if (m[i] <= 4 * kBucketWidth) max_small = std::max(max_small, bytes);
+  }
+  const size_t region = std::max(max_bytes, kBatchWaves * max_small);
+  if (region > 160 * 1024 - 1024) return fail(LP_ERR_ARG, "an LP of the batch is too large for the batched solver");
+
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "selecting the device");
+  lp_batch* p = new (std::nothrow) lp_batch();
+  if (!p) return fail(LP_ERR_NOMEM, "host allocation failed");
+  auto bail = [&](int code) {
+    release(p);
+    return code;
+  };
+  p->device = dev;
+  p->opt = o;
+  p->count = count;
+  p->region = region;
+  p->small_m = o.batch_small_m;
+  if (o.stream) {
+    p->stream = static_cast<hipStream_t>(o.stream);
+  } else {
+    hipError_t e = hipStreamCreate(&p->stream);
+    if (e != hipSuccess) return bail(fail_hip(e, "creating a stream"));
+    p->own_stream = true;
+  }
+  {
+    hipError_t e = hipEventCreate(&p->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev1);
+    if (e != hipSuccess) return bail(fail_hip(e, "creating events"));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return bail(fail_hip(e, "querying the device"));
+    p->num_cu = prop.multiProcessorCount;
+    e = batch_occupancy(&p->per_cu, region);
+    if (e != hipSuccess) return bail(fail_hip(e, "querying occupancy"));
+    if (p->per_cu < 1) return bail(fail(LP_ERR_ARG, "batched solver does not fit the device"));
+    p->grid = p->per_cu * p->num_cu;
+  }
+  // Pool layout.
+  p->lps.resize(count);
+  p->c.resize(count);
+  int64_t oA = 0, ob = 0, oc = 0, oB = 0, oI = 0, oL = 0, oO = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    BatchLP& L = p->lps[i];
+    L.m = m[i];
+    L.n = n[i];
+    L.ld = (m[i] + 7) / 8 * 8;
+    L.waves = kBatchWaves;
+    L.cap = o.max_iter > 0 ? o.max_iter : 10 * ((int64_t)m[i] + n[i]);
+    L.offA = oA;
+    L.offb = ob;
+    L.offc = oc;
+    L.offB = oB;
+    L.offI = oI;
+    L.offLog = oL;
+    L.offOut = oO;
+    oA += (int64_t)L.ld * std::max(L.n, 1);
+    ob += L.m;
+    oc += std::max(L.n, 1);
+    oB += (int64_t)L.m * L.ld;
+    oI += 2 * ((int64_t)L.n + L.m);
+    oL += L.cap;
+    oO += L.m;
+    p->c[i].assign(c[i], c[i] + n[i]);
+  }
+  double* dA = nullptr;
+  double* db = nullptr;
+  double* dc = nullptr;
+#define ALLOC(ptr, cnt)                                                    \
+  do {                                                                     \
+    hipError_t e_ = dalloc(p, &(ptr), (size_t)(cnt));                      \
+    if (e_ != hipSuccess) return bail(fail_hip(e_, "allocating " #ptr)); \
+  } while (0)
+  ALLOC(dA, oA);
+  ALLOC(db, ob);
+  ALLOC(dc, oc);
+  ALLOC(p->d.Binv, oB);
+  ALLOC(p->d.iscr, oI);
+  ALLOC(p->d.log_enter, oL);
+  ALLOC(p->d.log_row, oL);
+  ALLOC(p->d.log_leave, oL);
+  ALLOC(p->d.log_flags, oL);
+  ALLOC(p->d.Lq, oL);
+  ALLOC(p->d.Ll, oL);
+  ALLOC(p->d.Lgen, oL);
+  ALLOC(p->d.xB_out, oO);
+  ALLOC(p->d.basis_out, oO);
+  ALLOC(p->d.status_out, count);
+  ALLOC(p->d.iters_out, count);
+  ALLOC(p->d.z_out, count);
+  ALLOC(p->d.ray_out, count);
+  ALLOC(p->d.queue, 1);
+  ALLOC(p->d_lps, count);
+  ALLOC(p->d_items, count);
+#undef ALLOC
+  p->d.A = dA;
+  p->d.b = db;
+  p->d.c = dc;
+  p->d.lps = p->d_lps;
+  p->d.items = p->d_items;
+  p->d.slot_bytes = (int32_t)(region / kBatchWaves);
+  p->d.sense = o.sense == LP_MAX ? -1.0 : 1.0;
+  p->d.tenure = o.tabu_tenure;
+  p->d.use_llist = o.leaving_list ? 1 : 0;
+  p->d.eps_d = o.eps_d;
+  p->d.eps_p = o.eps_p;
+  p->d.eps_z = o.eps_z;
+  p->d.eps_t = o.eps_t;
+  // Upload: pack on the host (A' padded to ld rows), then one copy per pool.
+  {
+    std::vector<double> hA((size_t)oA, 0.0), hb((size_t)ob), hc((size_t)oc, 0.0);
+    for (int32_t i = 0; i < count; ++i) {
+      const BatchLP& L = p->lps[i];
+      for (int32_t j = 0; j < L.n; ++j)
+        std::memcpy(&hA[L.offA + (size_t)j * L.ld], A[i] + (size_t)j * L.m, sizeof(double) * L.m);
+      std::memcpy(&hb[L.offb], b[i], sizeof(double) * L.m);
+      if (L.n) std::memcpy(&hc[L.offc], c[i], sizeof(double) * L.n);
+    }
+    hipError_t e = hipMemcpy(dA, hA.data(), sizeof(double) * hA.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(db, hb.data(), sizeof(double) * hb.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dc, hc.data(), sizeof(double) * hc.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(fail_hip(e, "uploading the batch"));
+  }
+  *out = p;
+  return LP_OK;
+}
+
+int lp_batch_solve(lp_batch* p) {
+  if (!p) return fail(LP_ERR_ARG, "p is NULL");
+  int rc;
+  if (p->small_m < 0 && p->bucket_narrow.empty()) {
+    if ((rc = autotune(p)) != LP_OK) return rc;
+  }
+  assign_modes(p);
+  std::vector<int> all(p->count);
+  std::iota(all.begin(), all.end(), 0);
+  const std::vector<int4> items = make_items(p, all);
+  float ms = 0.f;
+  if ((rc = run_items(p, items, &ms)) != LP_OK) return rc;
+  p->solve_ms = ms;
+  p->items_last = (int64_t)items.size();
+  p->solved = true;
+  return LP_OK;
+}
+
+int lp_batch_results(const lp_batch* pc, int32_t* status, double* objective, int64_t* iterations) {
+  if (!pc) return fail(LP_ERR_ARG, "p is NULL");
+  if (!pc->solved) return fail(LP_ERR_STATE, "lp_batch_solve has not run");
+  lp_batch* p = const_cast<lp_batch*>(pc);
+  const int count = p->count;
+  std::vector<int32_t> st(count);
+  std::vector<int64_t> it(count);
+  HIP_TRY(hipMemcpy(st.data(), p->d.status_out, sizeof(int32_t) * count, hipMemcpyDeviceToHost), "reading results");
+  HIP_TRY(hipMemcpy(it.data(), p->d.iters_out, sizeof(int64_t) * count, hipMemcpyDeviceToHost), "reading results");
+  if (status) std::memcpy(status, st.data(), sizeof(int32_t) * count);
+  if (iterations) std::memcpy(iterations, it.data(), sizeof(int64_t) * count);
+  if (objective) {
+    const int64_t total = p->lps.back().offOut + p->lps.back().m;
+    std::vector<double> xB((size_t)total);
+    std::vector<int32_t> bas((size_t)total);
+    HIP_TRY(hipMemcpy(xB.data(), p->d.xB_out, sizeof(double) * total, hipMemcpyDeviceToHost), "reading x_B");
+    HIP_TRY(hipMemcpy(bas.data(), p->d.basis_out, sizeof(int32_t) * total, hipMemcpyDeviceToHost), "reading bases");
+    for (int i = 0; i < count; ++i) {
+      const BatchLP& L = p->lps[i];
+      std::vector<int32_t> row_of(L.n, -1);
+      for (int k = 0; k < L.m; ++k)
+        if (bas[L.offOut + k] < L.n) row_of[bas[L.offOut + k]] = k;
+      double s = 0.0;
+      for (int j = 0; j < L.n; ++j)
+        if (row_of[j] >= 0) s += p->c[i][j] * xB[L.offOut + row_of[j]];
+      objective[i] = s;
+    }
+  }
+  return LP_OK;
+}
+
+int lp_batch_get(const lp_batch* pc, int32_t i, double* x, int32_t* basis, int32_t* entering, int32_t* leaving_row,
+                 int32_t* flags, int64_t capacity, int64_t* count) {
+  if (!pc) return fail(LP_ERR_ARG, "p is NULL");
+  if (i < 0 || i >= pc->count) return fail(LP_ERR_ARG, "LP index out of range");
+  if (!pc->solved) return fail(LP_ERR_STATE, "lp_batch_solve has not run");
+  lp_batch* p = const_cast<lp_batch*>(pc);
+  const BatchLP& L = p->lps[i];
+  std::vector<double> xB(L.m);
+  std::vector<int32_t> bas(L.m);
+  int64_t t = 0;
+  HIP_TRY(hipMemcpy(xB.data(), p->d.xB_out + L.offOut, sizeof(double) * L.m, hipMemcpyDeviceToHost), "reading x_B");
+  HIP_TRY(hipMemcpy(bas.data(), p->d.basis_out + L.offOut, sizeof(int32_t) * L.m, hipMemcpyDeviceToHost),
+          "reading the basis");
+  HIP_TRY(hipMemcpy(&t, p->d.iters_out + i, sizeof(int64_t), hipMemcpyDeviceToHost), "reading the pivot count");
+  if (x) {
+    for (int j = 0; j < L.n; ++j) x[j] = 0.0;
+    for (int k = 0; k < L.m; ++k)
+      if (bas[k] < L.n) x[bas[k]] = xB[k];
+  }
+  if (basis) std::memcpy(basis, bas.data(), sizeof(int32_t) * L.m);
+  const int64_t have = std::min<int64_t>(t, L.cap);
+  const int64_t k = std::max<int64_t>(0, std::min<int64_t>(have, capacity));
+  int32_t* dst[3] = {entering, leaving_row, flags};
+  int32_t* src[3] = {p->d.log_enter + L.offLog, p->d.log_row + L.offLog, p->d.log_flags + L.offLog};
+  for (int a = 0; a < 3; ++a)
+    if (dst[a] && k > 0)
+      HIP_TRY(hipMemcpy(dst[a], src[a], sizeof(int32_t) * k, hipMemcpyDeviceToHost), "reading the pivot log");
+  if (count) *count = have;
+  return LP_OK;
+}
+
+int lp_batch_get_stats(const lp_batch* p, lp_batch_stats* s) {
+  if (!p || !s) return fail(LP_ERR_ARG, "NULL argument");
+  std::memset(s, 0, sizeof(*s));
+  s->count = p->count;
+  s->solve_ms = p->solve_ms;
+  s->tune_ms = p->tune_ms;
+  s->narrow_lps = p->narrow_lps;
+  s->wide_lps = p->wide_lps;
+  s->work_items = p->items_last;
+  s->workgroups = p->grid;
+  s->lds_bytes = (int64_t)p->region;
+  int64_t mask = 0;
+  for (size_t bk = 0; bk < p->bucket_narrow.size() && bk < 63; ++bk)
+    if (p->bucket_narrow[bk] == 1) mask |= (int64_t)1 << bk;
+  s->narrow_bucket_mask = mask;
+  return LP_OK;
+}
+
+void lp_batch_destroy(lp_batch* p) { release(p); }
+
+int lp_solve_batch(int32_t count, const int32_t* m, const int32_t* n, const double* const* A, const double* const* b,
+                   const double* const* c, const lp_options* opt, int32_t* status, double* objective,
+                   int64_t* iterations) {
+  lp_batch* p = nullptr;
+  int rc = lp_batch_create(&p, count, m, n, A, b, c, opt);
+  if (rc != LP_OK) return rc;
+  rc = lp_batch_solve(p);
+  if (rc == LP_OK) rc = lp_batch_results(p, status, objective, iterations);
+  lp_batch_destroy(p);
+  return rc;
+}
+
+}  // extern "C"

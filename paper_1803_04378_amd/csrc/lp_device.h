@@ -6,7 +6,7 @@
 //   Binv   m x ld   row-major:    row i of B^-1 is contiguous (update + FTRAN stream it)
 //   W0, W1, rho ld  W = chat_B^T B^-1 (top row of the Figure 1 tableau, two copies: one is
 //                   read while the next is written), rho = pivot row / alpha_r
-//   xB, alpha[2], ratio  m
+//   xB, alpha[2]    m
 //   chat            n + m   (minimisation costs; slacks 0)
 //   basis (m), pos (n+m), tabu_until (n+m), the leaving-side tabu list, the pivot log: int32
 #pragma once
@@ -25,8 +25,16 @@ constexpr int kFlagTie = 2;
 constexpr int kFlagAspiration = 4;
 constexpr int kFlagLClear = 8;
 
-constexpr int kPriceBlock = 512;
-constexpr int kUpdateBlock = 1024;
+#ifndef LPGPU_PRICE_BLOCK
+#define LPGPU_PRICE_BLOCK 512
+#endif
+#ifndef LPGPU_UPDATE_BLOCK
+#define LPGPU_UPDATE_BLOCK 1024
+#endif
+constexpr int kPriceBlock = LPGPU_PRICE_BLOCK;
+constexpr int kUpdateBlock = LPGPU_UPDATE_BLOCK;
+// Rows of B^-1 one wavefront of k_update may own (the host sizes the grid to respect it).
+constexpr int kMaxRowsPerWave = 8;
 
 // Control block: written by one thread of a kernel (or by the host between solves), read
 // by every workgroup of the next kernel; a field is never read and written by different
@@ -55,6 +63,7 @@ struct Ctrl {
   int64_t update_rows_written;  // B^-1 rows those passes rewrote
   double theta;   // step length of the pending pivot
   double pdq;     // reduced cost of the pending pivot's entering variable
+  double ar;      // pivot element alpha_r of the pending pivot
   int32_t wcur;   // W0 or W1 holds the current top row W
   int32_t pad2;
 };
@@ -68,7 +77,6 @@ struct DevLP {
   double* W0;     // W ping-pong: k_price reads one and writes the other
   double* W1;
   double* rho;
-  double* ratio;  // per-row ratio of the latest FTRAN (infinity where alpha_i <= eps_p)
   double* alpha0;
   double* alpha1;
   int32_t* basis;
@@ -85,9 +93,10 @@ struct DevLP {
   int32_t* log_flags;
   double* part_d;  // pricing partials: 2 per workgroup (all improving, non-tabu improving)
   int32_t* part_j;
-  double* part_th;  // update partials per workgroup: min ratio, rows within its tie bound, lowest such row
-  int32_t* part_cnt;
-  int32_t* part_low;
+  double* part_th;   // update partials per workgroup: min ratio and the lowest row attaining it,
+  int32_t* part_low;  // and the two smallest tie thresholds tau of its rows
+  double* part_t1;
+  double* part_t2;
   Ctrl* ctrl;
   int64_t log_cap;
   int32_t price_grid;   // workgroups of k_price (partials to reduce)

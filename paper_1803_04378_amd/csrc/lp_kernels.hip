@@ -26,6 +26,7 @@
 // index) minimum, which does not depend on the order partials arrive in.  No
 // floating-point atomics are used.
 #include "lp_device.h"
+#include "lp_wave.h"
 
 #include <limits.h>
 
@@ -33,185 +34,7 @@
 
 namespace lpgpu {
 
-namespace {
-
-constexpr int kUnroll = 8;
-
-__device__ __forceinline__ bool lex_less(double d1, int j1, double d2, int j2) {
-  return d1 < d2 || (d1 == d2 && j1 < j2);
-}
-
-__device__ __forceinline__ void wave_lexmin(double& d, int& j) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double d2 = __shfl_xor(d, off);
-    const int j2 = __shfl_xor(j, off);
-    if (lex_less(d2, j2, d, j)) {
-      d = d2;
-      j = j2;
-    }
-  }
-}
-
-__device__ __forceinline__ double wave_sum(double a) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
-  return a;
-}
-
-// Block-wide reductions.  Every thread of the block must call them.
-template <int BLOCK>
-__device__ void block_lexmin(double& d, int& j, double* sd, int* sj) {
-  constexpr int W = BLOCK / 64;
-  wave_lexmin(d, j);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) {
-    sd[wave] = d;
-    sj[wave] = j;
-  }
-  __syncthreads();
-  if (wave == 0) {
-    d = lane < W ? sd[lane] : __builtin_inf();
-    j = lane < W ? sj[lane] : INT_MAX;
-    wave_lexmin(d, j);
-    if (lane == 0) {
-      sd[0] = d;
-      sj[0] = j;
-    }
-  }
-  __syncthreads();
-  d = sd[0];
-  j = sj[0];
-}
-
-template <int BLOCK>
-__device__ double block_min(double v, double* sd, int* sj) {
-  int dummy = 0;
-  block_lexmin<BLOCK>(v, dummy, sd, sj);
-  return v;
-}
-
-template <int BLOCK>
-__device__ int block_min_int(int v, int* si) {
-  constexpr int W = BLOCK / 64;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) si[wave] = v;
-  __syncthreads();
-  if (wave == 0) {
-    v = lane < W ? si[lane] : INT_MAX;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
-    if (lane == 0) si[0] = v;
-  }
-  __syncthreads();
-  return si[0];
-}
-
-template <int BLOCK>
-__device__ int block_sum_int(int v, int* si) {
-  constexpr int W = BLOCK / 64;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) si[wave] = v;
-  __syncthreads();
-  if (wave == 0) {
-    v = lane < W ? si[lane] : 0;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) si[0] = v;
-  }
-  __syncthreads();
-  return si[0];
-}
-
-// Dot product of a contiguous HBM vector with an LDS vector, both n2 double2 long.
-// Lane l accumulates elements l, l+64, ... in order; the butterfly then gives every
-// lane the same bits.
-__device__ __forceinline__ double wave_dot(const double2* __restrict__ x, const double2* y, int n2, int lane) {
-  double acc = 0.0;
-  int k = lane;
-  for (; k + 64 * (kUnroll - 1) < n2; k += 64 * kUnroll) {
-    double2 v[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) v[u] = x[k + 64 * u];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const double2 w = y[k + 64 * u];
-      acc = fma(v[u].x, w.x, acc);
-      acc = fma(v[u].y, w.y, acc);
-    }
-  }
-  for (; k < n2; k += 64) {
-    const double2 v = x[k];
-    const double2 w = y[k];
-    acc = fma(v.x, w.x, acc);
-    acc = fma(v.y, w.y, acc);
-  }
-  return wave_sum(acc);
-}
-
-// row <- row + na * rho (in place), returning dot(new row, a) when DOT.
-template <bool DOT>
-__device__ __forceinline__ double wave_update_dot(double2* __restrict__ row, const double2* rho, const double2* a,
-                                                  double na, int n2, int lane) {
-  double acc = 0.0;
-  int k = lane;
-  for (; k + 64 * (kUnroll - 1) < n2; k += 64 * kUnroll) {
-    double2 v[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) v[u] = row[k + 64 * u];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const double2 rr = rho[k + 64 * u];
-      v[u].x = fma(na, rr.x, v[u].x);
-      v[u].y = fma(na, rr.y, v[u].y);
-      row[k + 64 * u] = v[u];
-      if (DOT) {
-        const double2 w = a[k + 64 * u];
-        acc = fma(v[u].x, w.x, acc);
-        acc = fma(v[u].y, w.y, acc);
-      }
-    }
-  }
-  for (; k < n2; k += 64) {
-    double2 v = row[k];
-    const double2 rr = rho[k];
-    v.x = fma(na, rr.x, v.x);
-    v.y = fma(na, rr.y, v.y);
-    row[k] = v;
-    if (DOT) {
-      const double2 w = a[k];
-      acc = fma(v.x, w.x, acc);
-      acc = fma(v.y, w.y, acc);
-    }
-  }
-  return DOT ? wave_sum(acc) : 0.0;
-}
-
-// row r of the new B^-1 is rho itself: write it and (when DOT) dot it with a.
-template <bool DOT>
-__device__ __forceinline__ double wave_store_dot(double2* __restrict__ row, const double2* rho, const double2* a,
-                                                 int n2, int lane) {
-  double acc = 0.0;
-  for (int k = lane; k < n2; k += 64) {
-    const double2 v = rho[k];
-    row[k] = v;
-    if (DOT) {
-      const double2 w = a[k];
-      acc = fma(v.x, w.x, acc);
-      acc = fma(v.y, w.y, acc);
-    }
-  }
-  return DOT ? wave_sum(acc) : 0.0;
-}
-
-}  // namespace
+using namespace detail;
 
 // ---------------------------------------------------------------------------------------
 // Slack basis (Step 1): B = I, x_B = b, W = 0, z = 0; chat = sense * c.
@@ -234,7 +57,6 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
     lp.basis[i] = n + (int)i;
     lp.alpha0[i] = 0.0;
     lp.alpha1[i] = 0.0;
-    lp.ratio[i] = __builtin_inf();
   }
   double* chat = const_cast<double*>(lp.chat);
   for (size_t v = tid; v < (size_t)N; v += stride) {
@@ -266,12 +88,36 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
   const int r = lp.ctrl->r;
   const int wc = lp.ctrl->wcur;
   extern __shared__ double2 s_w2[];
-  __shared__ double red_d[kPriceBlock / 64 + 8];
-  __shared__ int red_j[kPriceBlock / 64 + 8];
+  __shared__ double red_d[2 * (kPriceBlock / 64)];
+  __shared__ int red_j[2 * (kPriceBlock / 64)];
   const int m = lp.m, n = lp.n, ld2 = lp.ld / 2;
+  constexpr int waves = kPriceBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int gw = blockIdx.x * waves + wave;
+  const int nw = gridDim.x * waves;
+
+  // Issued before the staging below so that their latency overlaps it: the state of
+  // this wave's columns (lane c holds column gw + c*nw) and the first batch of its first
+  // column of A'.
+  const int jl = gw + lane * nw;
+  int c_pos = 0, c_tabu = 0;
+  double c_chat = 0.0;
+  if (jl < n) {
+    c_pos = lp.pos[jl];
+    c_tabu = lp.tabu_until[jl];
+    c_chat = lp.chat[jl];
+  }
+  double2 v[kBatch];
+  const bool pre = gw < n;
+  if (pre) {
+    if (kStreamA) load_batch_nt(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
+    else load_batch(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
+  }
+
   const double2* Wold = reinterpret_cast<const double2*>(wc ? lp.W1 : lp.W0);
   if (r >= 0) {
-    const double ar = (lp.ctrl->cur ? lp.alpha1 : lp.alpha0)[r];
+    const double ar = lp.ctrl->ar;
     const double dq = lp.ctrl->pdq;
     const double2* rowr = reinterpret_cast<const double2*>(lp.Binv + (size_t)r * lp.ld);
     double2* Wnew = reinterpret_cast<double2*>(wc ? lp.W0 : lp.W1);
@@ -294,50 +140,76 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
   __syncthreads();
   const double* s_w = reinterpret_cast<const double*>(s_w2);
 
-  constexpr int waves = kPriceBlock / 64;
-  const int lane = threadIdx.x & 63;
-  const int gw = blockIdx.x * waves + (threadIdx.x >> 6);
-  const int nw = gridDim.x * waves;
   const double neg_eps = -lp.eps_d;
   double da = __builtin_inf(), df = __builtin_inf();
   int ja = INT_MAX, jf = INT_MAX;
-  for (int j = gw; j < n; j += nw) {
-    if (lp.pos[j] >= 0) continue;
-    const double s = wave_dot(reinterpret_cast<const double2*>(lp.A + (size_t)j * lp.ld), s_w2, ld2, lane);
-    const double d = lp.chat[j] - s;
+  int c = 0;
+  for (int j = gw; j < n; j += nw, ++c) {
+    int pos, tabu;
+    double ch;
+    if (c < 64) {
+      pos = __shfl(c_pos, c);
+      tabu = __shfl(c_tabu, c);
+      ch = __shfl(c_chat, c);
+    } else {
+      pos = lp.pos[j];
+      tabu = lp.tabu_until[j];
+      ch = lp.chat[j];
+    }
+    const bool first = c == 0;
+    if (pos >= 0) continue;
+    const double s = wave_dot<kStreamA>(reinterpret_cast<const double2*>(lp.A + (size_t)j * lp.ld), s_w2, ld2,
+                                        lane, v, first && pre);
+    const double d = ch - s;
     if (d < neg_eps) {
       if (lex_less(d, j, da, ja)) {
         da = d;
         ja = j;
       }
-      if (lp.tabu_until[j] < t && lex_less(d, j, df, jf)) {
+      if (tabu < t && lex_less(d, j, df, jf)) {
         df = d;
         jf = j;
       }
     }
   }
   for (int i = blockIdx.x * kPriceBlock + threadIdx.x; i < m; i += gridDim.x * kPriceBlock) {
-    const int v = n + i;
-    if (lp.pos[v] >= 0) continue;
-    const double d = lp.chat[v] - s_w[i];  // a_{n+i} = e_i
+    const int vv = n + i;
+    if (lp.pos[vv] >= 0) continue;
+    const double d = lp.chat[vv] - s_w[i];  // a_{n+i} = e_i
     if (d < neg_eps) {
-      if (lex_less(d, v, da, ja)) {
+      if (lex_less(d, vv, da, ja)) {
         da = d;
-        ja = v;
+        ja = vv;
       }
-      if (lp.tabu_until[v] < t && lex_less(d, v, df, jf)) {
+      if (lp.tabu_until[vv] < t && lex_less(d, vv, df, jf)) {
         df = d;
-        jf = v;
+        jf = vv;
       }
     }
   }
-  block_lexmin<kPriceBlock>(da, ja, red_d, red_j);
-  block_lexmin<kPriceBlock>(df, jf, red_d, red_j);
-  if (threadIdx.x == 0) {
-    lp.part_d[2 * blockIdx.x] = da;
-    lp.part_j[2 * blockIdx.x] = ja;
-    lp.part_d[2 * blockIdx.x + 1] = df;
-    lp.part_j[2 * blockIdx.x + 1] = jf;
+  // Workgroup partials: both minima through one LDS exchange.
+  wave_lexmin(da, ja);
+  wave_lexmin(df, jf);
+  if (lane == 0) {
+    red_d[wave] = da;
+    red_j[wave] = ja;
+    red_d[waves + wave] = df;
+    red_j[waves + wave] = jf;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    da = lane < waves ? red_d[lane] : __builtin_inf();
+    ja = lane < waves ? red_j[lane] : INT_MAX;
+    df = lane < waves ? red_d[waves + lane] : __builtin_inf();
+    jf = lane < waves ? red_j[waves + lane] : INT_MAX;
+    wave_lexmin(da, ja);
+    wave_lexmin(df, jf);
+    if (lane == 0) {
+      lp.part_d[2 * blockIdx.x] = da;
+      lp.part_j[2 * blockIdx.x] = ja;
+      lp.part_d[2 * blockIdx.x + 1] = df;
+      lp.part_j[2 * blockIdx.x + 1] = jf;
+    }
   }
 }
 
@@ -350,9 +222,23 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   const int r = lp.ctrl->r;
   const int64_t t = lp.ctrl->t;
   extern __shared__ double2 smem2[];
-  __shared__ double red_d[kUpdateBlock / 64 + 8];
-  __shared__ int red_j[kUpdateBlock / 64 + 8];
+  __shared__ double red_d[2 * (kUpdateBlock / 64)];
+  __shared__ int red_j[2 * (kUpdateBlock / 64)];
+  constexpr int waves = kUpdateBlock / 64;
+  __shared__ double s_rt[waves * kMaxRowsPerWave];
+  __shared__ double s_tau[waves * kMaxRowsPerWave];
+  __shared__ int s_row[waves * kMaxRowsPerWave];
   const int m = lp.m, n = lp.n, ld2 = lp.ld / 2;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int gw = blockIdx.x * waves + wave;
+  const int nw = gridDim.x * waves;
+
+  // The first batch of this wave's first row is in flight while the entering column is
+  // decided and staged.
+  double2 v[kBatch];
+  const bool pre = gw < m && gw != r;
+  if (pre) load_batch(reinterpret_cast<const double2*>(lp.Binv + (size_t)gw * lp.ld), lane, ld2, v);
 
   // Step 4 decision from the pricing partials.
   double da = __builtin_inf(), df = __builtin_inf();
@@ -369,8 +255,21 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
       jf = j1;
     }
   }
-  block_lexmin<kUpdateBlock>(da, ja, red_d, red_j);
-  block_lexmin<kUpdateBlock>(df, jf, red_d, red_j);
+  wave_lexmin(da, ja);
+  wave_lexmin(df, jf);
+  if (lane == 0) {
+    red_d[wave] = da;
+    red_j[wave] = ja;
+    red_d[waves + wave] = df;
+    red_j[waves + wave] = jf;
+  }
+  __syncthreads();
+  da = lane < waves ? red_d[lane] : __builtin_inf();
+  ja = lane < waves ? red_j[lane] : INT_MAX;
+  df = lane < waves ? red_d[waves + lane] : __builtin_inf();
+  jf = lane < waves ? red_j[waves + lane] : INT_MAX;
+  wave_lexmin(da, ja);  // every wave reduces the same values: no second exchange needed
+  wave_lexmin(df, jf);
   int status = kStatusRunning, q = -1, flags = 0;
   double dq = 0.0;
   if (ja == INT_MAX) {
@@ -427,18 +326,15 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   }
   __syncthreads();
 
-  constexpr int waves = kUpdateBlock / 64;
-  const int lane = threadIdx.x & 63;
-  const int gw = blockIdx.x * waves + (threadIdx.x >> 6);
-  const int nw = gridDim.x * waves;
   const double eps_p = lp.eps_p, eps_z = lp.eps_z;
-  double wmin = __builtin_inf();  // this wave's minimum ratio
-  for (int i = gw; i < m; i += nw) {
+  int c = 0;
+  for (int i = gw; i < m; i += nw, ++c) {
     double2* row = reinterpret_cast<double2*>(lp.Binv + (size_t)i * lp.ld);
+    const bool first = c == 0 && pre;
     double acc;
     double x = lp.xB[i];
     if (r < 0) {
-      acc = wave_dot(row, s_a, ld2, lane);
+      acc = wave_dot<false>(row, s_a, ld2, lane, v, first);
     } else {
       if (i == r) {
         acc = q >= 0 ? wave_store_dot<true>(row, s_rho, s_a, ld2, lane)
@@ -446,48 +342,80 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
         x = theta;
       } else {
         const double na = -al_p[i];
-        acc = q >= 0 ? wave_update_dot<true>(row, s_rho, s_a, na, ld2, lane)
-                     : wave_update_dot<false>(row, s_rho, s_a, na, ld2, lane);
+        acc = q >= 0 ? wave_update_dot<true>(row, s_rho, s_a, na, ld2, lane, v, first)
+                     : wave_update_dot<false>(row, s_rho, s_a, na, ld2, lane, v, first);
         x = fma(na, theta, x);
       }
       if (fabs(x) < eps_z) x = 0.0;
       if (lane == 0) lp.xB[i] = x;
     }
     if (q >= 0) {
-      const double rt = acc > eps_p ? fmax(x, 0.0) / acc : __builtin_inf();
-      wmin = fmin(wmin, rt);
+      // ratio_i, and tau_i: the smallest step at which row i would count as tied
+      // (fma(-alpha_i, step, max(x_i, 0)) <= eps_t), lowered by a margin so that the
+      // filter in k_finish never misses a tied row.
+      double rt = __builtin_inf(), tau = __builtin_inf();
+      if (acc > eps_p) {
+        const double xp = fmax(x, 0.0);
+        rt = xp / acc;
+        tau = (xp - lp.eps_t) / acc;
+        tau -= 1e-12 * (fabs(tau) + 1.0);
+      }
       if (lane == 0) {
         al_n[i] = acc;
-        lp.ratio[i] = rt;
+        s_rt[wave * kMaxRowsPerWave + c] = rt;
+        s_tau[wave * kMaxRowsPerWave + c] = tau;
+        s_row[wave * kMaxRowsPerWave + c] = i;
       }
     }
   }
   if (q < 0) return;
-  // Workgroup partial of Step 6: min ratio, and rows within the tie bound of it.
-  const double th = block_min<kUpdateBlock>(wmin, red_d, red_j);
-  const double bound = th + lp.eps_t * fmax(1.0, th);
-  int cnt = 0, low = INT_MAX;
-  if (th != __builtin_inf()) {
-    for (int i = gw; i < m; i += nw) {
-      if (lane == 0 && lp.ratio[i] <= bound) {
-        ++cnt;
-        low = min(low, i);
+  // Workgroup partial of Step 6: (min ratio, lowest row attaining it) and the two
+  // smallest tau of the workgroup's rows.
+  for (int k = c; k < kMaxRowsPerWave; ++k)
+    if (lane == 0) {
+      s_rt[wave * kMaxRowsPerWave + k] = __builtin_inf();
+      s_tau[wave * kMaxRowsPerWave + k] = __builtin_inf();
+      s_row[wave * kMaxRowsPerWave + k] = INT_MAX;
+    }
+  __syncthreads();
+  if (wave == 0) {
+    constexpr int slots = waves * kMaxRowsPerWave;
+    double th = __builtin_inf(), t1 = __builtin_inf(), t2 = __builtin_inf();
+    int low = INT_MAX;
+    for (int k = lane; k < slots; k += 64) {
+      if (lex_less(s_rt[k], s_row[k], th, low)) {
+        th = s_rt[k];
+        low = s_row[k];
+      }
+      const double tk = s_tau[k];
+      if (tk < t1) {
+        t2 = t1;
+        t1 = tk;
+      } else if (tk < t2) {
+        t2 = tk;
       }
     }
-  }
-  cnt = block_sum_int<kUpdateBlock>(cnt, red_j);
-  low = block_min_int<kUpdateBlock>(low, red_j);
-  if (threadIdx.x == 0) {
-    lp.part_th[blockIdx.x] = th;
-    lp.part_cnt[blockIdx.x] = cnt;
-    lp.part_low[blockIdx.x] = low;
+    wave_lexmin(th, low);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o1 = __shfl_xor(t1, off), o2 = __shfl_xor(t2, off);
+      const double n1 = fmin(t1, o1);
+      t2 = fmin(fmax(t1, o1), fmin(t2, o2));
+      t1 = n1;
+    }
+    if (lane == 0) {
+      lp.part_th[blockIdx.x] = th;
+      lp.part_low[blockIdx.x] = low;
+      lp.part_t1[blockIdx.x] = t1;
+      lp.part_t2[blockIdx.x] = t2;
+    }
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// Step 6 finish and the scalar part of Step 8 (one workgroup).  Every row's ratio is in
-// lp.ratio (infinity where alpha_i <= eps_p) and every k_update workgroup left (min
-// ratio, rows within the tie bound of it, lowest such row).
+// Step 6 finish and the scalar part of Step 8 (one workgroup).  Every k_update workgroup
+// left its minimum ratio (with the lowest row attaining it) and the two smallest tie
+// thresholds of its rows; x_B and alpha of this iteration are in memory.
 __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
   constexpr int B = kUpdateBlock;
   __shared__ double red_d[B / 64 + 8];
@@ -509,6 +437,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
   const int64_t t = ctl->t;
   const int cur = ctl->cur;
 
+  const double* al = cur ? lp.alpha0 : lp.alpha1;  // FTRAN result of this iteration
   double th = __builtin_inf();
   for (int k = tid; k < nparts; k += B) th = fmin(th, lp.part_th[k]);
   th = block_min<B>(th, red_d, red_j);
@@ -522,29 +451,31 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
     }
     return;
   }
-  // Rows within the tie tolerance of the minimum ratio are tied (exact ties split by rounding).
-  const double tie_bound = th + lp.eps_t * fmax(1.0, th);
-  // Fast path: a single workgroup holds rows within the bound, and only one of them.
+  // A row is tied when it reaches zero (within eps_t) at the step th; exact test below.
+  const double eps_p = lp.eps_p, eps_t = lp.eps_t;
+  // Fast path: one workgroup may hold tied rows, and only one of its rows may.
   int ncand = 0, cand = INT_MAX;
   for (int k = tid; k < nparts; k += B)
-    if (lp.part_th[k] <= tie_bound) {
+    if (lp.part_t1[k] <= th) {
       ++ncand;
       cand = min(cand, k);
     }
   ncand = block_sum_int<B>(ncand, red_j);
   cand = block_min_int<B>(cand, red_j);
   int cnt, low;
-  if (ncand == 1 && lp.part_cnt[cand] == 1) {
+  if (ncand == 1 && lp.part_t2[cand] > th) {
     cnt = 1;
     low = lp.part_low[cand];
   } else {
     cnt = 0;
     low = INT_MAX;
-    for (int i = tid; i < m; i += B)
-      if (lp.ratio[i] <= tie_bound) {
+    for (int i = tid; i < m; i += B) {
+      const double a = al[i];
+      if (a > eps_p && fma(-a, th, fmax(lp.xB[i], 0.0)) <= eps_t) {
         ++cnt;
         low = min(low, i);
       }
+    }
     cnt = block_sum_int<B>(cnt, red_j);
     low = block_min_int<B>(low, red_j);
   }
@@ -560,8 +491,11 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
         if (lp.Lq[k] == q && lp.Lgen[k] == g) lp.excl[lp.Ll[k]] = stamp;
       __syncthreads();
       int fl = INT_MAX;
-      for (int i = tid; i < m; i += B)
-        if (lp.ratio[i] <= tie_bound && lp.excl[lp.basis[i]] != stamp) fl = min(fl, i);
+      for (int i = tid; i < m; i += B) {
+        const double a = al[i];
+        if (a > eps_p && fma(-a, th, fmax(lp.xB[i], 0.0)) <= eps_t && lp.excl[lp.basis[i]] != stamp)
+          fl = min(fl, i);
+      }
       fl = block_min_int<B>(fl, red_j);
       int gnew = g;
       if (fl == INT_MAX) {
@@ -582,8 +516,8 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
     }
   }
   if (tid == 0) {
-    // Step 8 pivots on row r: the step is r's own ratio.
-    const double thr = lp.ratio[r];
+    // Step 8 pivots on row r with the step th.
+    const double thr = th;
     if (thr == 0.0) flags |= kFlagDegenerate;
     const double dq = ctl->dq;
     const int leave = lp.basis[r];
@@ -605,6 +539,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
     ctl->t = t + 1;
     ctl->r = r;        // pending: rows of B^-1 and x_B are pivoted by the next k_update,
     ctl->theta = thr;  // the top row by the next k_price
+    ctl->ar = al[r];
     ctl->pdq = dq;
     ctl->cur = cur ^ 1;
     ctl->q = -1;

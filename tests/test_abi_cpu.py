@@ -38,14 +38,15 @@ def test_header_constants_match_binding():
 
 
 def test_struct_layouts():
-    assert C.sizeof(binding.lp_options) == 72
-    assert C.sizeof(binding.lp_stats) == 120
+    assert C.sizeof(binding.lp_options) == 80
+    assert C.sizeof(binding.lp_batch_stats) == 72
+    assert C.sizeof(binding.lp_stats) == 128
 
 
 def test_default_options():
     o = lpg.default_options()
     assert o.sense == binding.LP_MAX and o.tabu_tenure == 5 and o.leaving_list == 1
-    assert o.eps_d == 1e-9 and o.eps_p == 1e-9 and o.eps_z == 1e-9 and o.eps_t == 1e-11 and o.max_iter == 0
+    assert o.eps_d == 1e-9 and o.eps_p == 1e-9 and o.eps_z == 1e-9 and o.eps_t == 1e-9 and o.max_iter == 0 and o.batch_small_m == -1
     assert lpg.lib().lp_default_options(None) == binding.LP_ERR_ARG
 
 
@@ -87,3 +88,29 @@ def test_error_strings():
     L = lpg.lib()
     for code in (0, -1, -2, -3, -4, -5, 99):
         assert isinstance(L.lp_error_string(code), bytes)
+
+
+def test_batch_argument_errors_need_no_gpu():
+    L = lpg.lib()
+    A = np.ones((3, 2), order="F")
+    b = np.ones(3)
+    c = np.ones(2)
+    dp = C.POINTER(C.c_double)
+    ms = (C.c_int32 * 2)(3, 3)
+    ns = (C.c_int32 * 2)(2, 2)
+    pa = (dp * 2)(A.ctypes.data_as(dp), A.ctypes.data_as(dp))
+    pb = (dp * 2)(b.ctypes.data_as(dp), b.ctypes.data_as(dp))
+    pc = (dp * 2)(c.ctypes.data_as(dp), c.ctypes.data_as(dp))
+    h = C.c_void_p()
+    assert L.lp_batch_create(C.byref(h), 0, ms, ns, pa, pb, pc, None) == binding.LP_ERR_ARG
+    bn = -b
+    pbn = (dp * 2)(b.ctypes.data_as(dp), bn.ctypes.data_as(dp))
+    assert L.lp_batch_create(C.byref(h), 2, ms, ns, pa, pbn, pc, None) == binding.LP_ERR_NEG_RHS
+    big = (C.c_int32 * 2)(3, 5000)
+    Abig = np.ones((5000, 2), order="F")
+    bbig = np.ones(5000)
+    pa2 = (dp * 2)(A.ctypes.data_as(dp), Abig.ctypes.data_as(dp))
+    pb2 = (dp * 2)(b.ctypes.data_as(dp), bbig.ctypes.data_as(dp))
+    assert L.lp_batch_create(C.byref(h), 2, big, ns, pa2, pb2, pc, None) == binding.LP_ERR_ARG
+    assert L.lp_batch_solve(None) == binding.LP_ERR_ARG
+    L.lp_batch_destroy(None)

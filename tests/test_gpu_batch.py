@@ -1,0 +1,149 @@
+"""Batched form: one persistent launch solves many LPs; each must equal lp_solve on that LP
+alone (status, pivot count, pivot log, objective bit for bit), which itself follows the
+oracle.  Covered in both execution modes (one wavefront per LP, one workgroup per LP) and
+under the autotuner, on mixed sizes, degenerate and cycling LPs, and the 4096-LP batch."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+from lputil import assert_kkt
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lpg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1803_04378_amd as mod
+    mod.lib()
+    return mod
+
+
+def _serial(lpg, A, b, c, **opts):
+    with lpg.LP(A, b, c, **opts) as p:
+        st = p.solve()
+        sol = p.solution()
+        piv = p.pivots()
+    return st, sol, piv
+
+
+def _check_against_serial(lpg, lps, res, bt, idx, **opts):
+    for i in idx:
+        A, b, c = lps[i]
+        st, sol, piv = _serial(lpg, A, b, c, **opts)
+        g = bt.get(i)
+        assert res["status"][i] == st, (i, res["status"][i], st)
+        assert res["iterations"][i] == sol["iterations"], (i, res["iterations"][i], sol["iterations"])
+        assert res["objective"][i] == sol["objective"], (i, res["objective"][i], sol["objective"])
+        np.testing.assert_array_equal(g["enter"], piv["enter"])
+        np.testing.assert_array_equal(g["row"], piv["row"])
+        np.testing.assert_array_equal(g["flags"], piv["flags"])
+        np.testing.assert_array_equal(g["basis"], sol["basis"])
+        np.testing.assert_array_equal(g["x"], sol["x"])
+
+
+def _mixed_batch(seed, count, m_lo, m_hi):
+    ms, ns = lpgen.batch_sizes(seed, count, m_lo, m_hi)
+    return [lpgen.dense_lp(lpgen.instance_seed(seed, i), int(ms[i]), int(ns[i])) for i in range(count)]
+
+
+@pytest.mark.parametrize("small_m", [0, 64, -1])
+def test_batch_equals_serial(lpg, small_m):
+    _say(f"case: 40 dense LPs m in [16,120], batch_small_m={small_m}")
+    lps = _mixed_batch(3, 40, 16, 120)
+    with lpg.Batch(lps, batch_small_m=small_m) as bt:
+        bt.solve()
+        res = bt.results()
+        stats = bt.stats()
+        _check_against_serial(lpg, lps, res, bt, range(len(lps)))
+    if small_m == 0:
+        assert stats["narrow_lps"] == 0
+    if small_m == 64:
+        assert stats["narrow_lps"] == sum(1 for A, _, _ in lps if A.shape[0] <= 64)
+    assert (res["status"] == oracle.OPTIMAL).all()
+
+
+def test_batch_degenerate_and_special_lps(lpg):
+    """Ties, the tabu list, unbounded and trivially optimal LPs inside one batch."""
+    from test_oracle_pins import _embedded
+    lps = [lpgen.degenerate_lp(s, 60 + 10 * s, 120 + 20 * s, budget_row=True) for s in range(6)]
+    lps += [lpgen.degenerate_lp(s, 40, 80) for s in range(4)]
+    lps += [_embedded("beale"), _embedded("chvatal")]
+    with open(os.path.join(os.path.dirname(__file__), "golden", "cycling_lps.json")) as f:
+        cyc = json.load(f)
+    for name in ("beale", "chvatal"):
+        d = cyc[name]
+        lps.append((np.array(d["A"], float), np.array(d["b"], float), np.array(d["c"], float)))
+    A, b, c = lpgen.dense_lp(2, 20, 30)
+    A[:, 5] = -np.abs(A[:, 5])
+    c[5] = 100.0
+    lps.append((A, b, c))
+    A, b, c = lpgen.dense_lp(3, 20, 30)
+    lps.append((A, b, -c))
+    for small_m in (0, 64):
+        _say(f"case: special LPs, batch_small_m={small_m}")
+        with lpg.Batch(lps, batch_small_m=small_m) as bt:
+            bt.solve()
+            res = bt.results()
+            for i, (A, b, c) in enumerate(lps):
+                ref = oracle.solve(A, b, c)
+                g = bt.get(i)
+                assert res["status"][i] == ref.status, (i, res["status"][i], ref.status)
+                np.testing.assert_array_equal(g["enter"], ref.enter)
+                np.testing.assert_array_equal(g["row"], ref.row)
+                np.testing.assert_array_equal(g["flags"], ref.flags)
+                assert abs(res["objective"][i] - ref.objective) <= 1e-9 * max(1.0, abs(ref.objective))
+            _check_against_serial(lpg, lps, res, bt, range(len(lps)))
+
+
+def test_batch_iteration_limit(lpg):
+    lps = _mixed_batch(5, 12, 30, 80)
+    with lpg.Batch(lps, max_iter=7) as bt:
+        bt.solve()
+        res = bt.results()
+        _check_against_serial(lpg, lps, res, bt, range(len(lps)), max_iter=7)
+    limited = res["status"] == oracle.ITER_LIMIT
+    assert limited.any() and (res["iterations"][limited] == 7).all()
+    assert (res["iterations"][~limited] <= 7).all() and (res["status"][~limited] == oracle.OPTIMAL).all()
+
+
+def test_batch_4096_mixed_sizes(lpg):
+    """The batched configuration: 4096 LPs, m ~ U{16..256}, n = 2m, per-instance seeds."""
+    _say("case: 4096 LPs m in [16,256]")
+    lps = lpgen.batch_lps(0, 4096)
+    with lpg.Batch(lps) as bt:
+        bt.solve()
+        res = bt.results()
+        stats = bt.stats()
+        _say(f"  solve {stats['solve_ms']:.2f} ms, narrow {stats['narrow_lps']} wide {stats['wide_lps']}, "
+             f"tune {stats['tune_ms']:.0f} ms, mask {stats['narrow_bucket_mask']:#x}")
+        assert (res["status"] == oracle.OPTIMAL).all()
+        rng = np.random.default_rng(0)
+        sample = sorted(set(rng.choice(4096, 24, replace=False).tolist()) | {0, 4095})
+        _check_against_serial(lpg, lps, res, bt, sample)
+        for i in sample[:8]:
+            A, b, c = lps[i]
+            ref = oracle.solve(A, b, c)
+            g = bt.get(i)
+            np.testing.assert_array_equal(g["enter"], ref.enter)
+            np.testing.assert_array_equal(g["row"], ref.row)
+        for i in range(4096):
+            A, b, c = lps[i]
+            g = bt.get(i)
+            # duals from the basis: KKT certificate of every LP's optimum
+            m = A.shape[0]
+            M = np.hstack([A, np.eye(m)])
+            y = np.linalg.solve(M[:, g["basis"]].T, np.concatenate([c, np.zeros(m)])[g["basis"]])
+            assert_kkt(A, b, c, g["x"], y)

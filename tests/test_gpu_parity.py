@@ -125,8 +125,8 @@ def test_unbounded_and_trivial(lpg):
     A, b, c = lpgen.dense_lp(2, 20, 30)
     A[:, 5] = -np.abs(A[:, 5])
     c[5] = 100.0
-    ref, (st, _, _, _) = assert_parity(lpg, A, b, c)
-    assert st == oracle.UNBOUNDED
+    ref, (st, _, _, stats) = assert_parity(lpg, A, b, c)
+    assert st == oracle.UNBOUNDED and stats["ray"] == ref.ray == 5
     A, b, c = lpgen.dense_lp(3, 20, 30)
     _, (st, sol, _, _) = assert_parity(lpg, A, b, -c)
     assert st == oracle.OPTIMAL and sol["iterations"] == 0

@@ -279,15 +279,29 @@ def test_rejects_bad_input():
 
 
 def test_rounding_split_tie_is_a_tie():
-    """Two rows whose exact ratios are equal but whose FP64 ratios differ by an ulp form a
-    tie (Sections 2.2/3.4: no unique leaving element); the lowest row leaves."""
+    """Two rows that reach zero at the same step in exact arithmetic, but whose FP64 ratios
+    differ by an ulp, form a tie (Sections 2.2/3.4: no unique leaving element): the lowest
+    row leaves and the step is the minimum ratio."""
     b = np.array([0.1 * 3, 0.1])  # 0.30000000000000004 / 3 != 0.1 in FP64
     assert b[0] / 3.0 != b[1]
     A = np.array([[3.0], [1.0]])
     r = oracle.solve(A, b, np.array([1.0]))
     assert r.row[0] == 0 and r.flags[0] & oracle.FLAG_TIE
-    assert abs(r.objective - b[0] / 3.0) == 0.0  # Step 8 pivots on row 0: x = b_0 / 3
-    # a gap well above the tolerance is not a tie: the smaller ratio leaves
-    b2 = np.array([0.3 * (1 + 1e-9), 0.1])
+    assert r.objective == min(b[0] / 3.0, b[1])  # x = theta_min
+    # a row that stays above zero by more than the tolerance is not tied: the smaller ratio leaves
+    b2 = np.array([0.3 * (1 + 1e-6), 0.1])
     r2 = oracle.solve(A, b2, np.array([1.0]))
     assert r2.row[0] == 1 and not (r2.flags[0] & oracle.FLAG_TIE)
+
+
+def test_tie_tolerance_is_in_x_units():
+    """A huge alpha must not turn a ratio-sized tolerance into a large infeasibility: with
+    theta_min = 0 a row with a tiny positive ratio but a large value is not tied."""
+    A = np.array([[1.0, 1.0], [1e12, 1.0], [0.0, 1.0]])
+    b = np.array([0.0, 1.0, 5.0])  # row 0 degenerate (ratio 0), row 1 ratio 1e-12 but x = 1
+    r = oracle.solve(A, b, np.array([1.0, 0.0]), max_iter=1)
+    assert r.row[0] == 0 and not (r.flags[0] & oracle.FLAG_TIE)
+    o = oracle.Oracle(A, b, np.array([1.0, 0.0]))
+    o.run(1)
+    _, xB, _, _ = o.state()
+    assert xB.min() >= 0.0
