@@ -65,6 +65,8 @@ def lib(path: str | None = None):
         L.oracle_pivots.restype = I64
         L.oracle_pivots.argtypes = [P, ip, ip, ip, ip, I64]
         L.oracle_counts.argtypes = [P, C.POINTER(C.c_int64)]
+        L.oracle_basis_inverse.restype = I32
+        L.oracle_basis_inverse.argtypes = [I32, I32, dp, ip, dp]
         _libs[key] = L
     return _libs[key]
 
@@ -169,3 +171,16 @@ def solve(A, b, c, sense="max", max_iter=None, **kw) -> Result:
     o = Oracle(A, b, c, sense=sense, **kw)
     o.run(max_iter)
     return o.result()
+
+
+def basis_inverse(A, basis, lib_path=None):
+    """B^-1 (m x m) of the basis list `basis` of (A', I), by Gauss-Jordan elimination with
+    partial pivoting; None if B is singular."""
+    A = np.asfortranarray(np.asarray(A, dtype=np.float64))
+    m, n = A.shape
+    basis = np.ascontiguousarray(basis, dtype=np.int32)
+    if basis.shape != (m,):
+        raise ValueError("basis must have m entries")
+    out = np.empty((m, m))
+    rc = lib(lib_path).oracle_basis_inverse(m, n, _dp(A), _ip(basis), _dp(out))
+    return out if rc == 0 else None

@@ -48,6 +48,10 @@
  *
  * Dot products are plain ascending-index fma chains.  Build with
  * -ffp-contract=off so that no other operation is fused.
+ *
+ * oracle_basis_inverse, at the end, gives B^-1 of any basis list by its definition:
+ * the reference for the GPU reinversion (parity unpinned by the paper, which does not
+ * refactorise; pinned by the tests against closed forms and a library inverse).
  */
 #include <math.h>
 #include <stdint.h>
@@ -360,4 +364,51 @@ void oracle_counts(const oracle_lp *p, int64_t *counts) {
   counts[1] = p->n_tie;
   counts[2] = p->n_aspiration;
   counts[3] = p->n_lclear;
+}
+
+/*
+ * The basis inverse by its plain definition: B has column p equal to column basis[p] of
+ * (A', I_m), and Binv (m x m, row-major) receives B^-1, computed by Gauss-Jordan
+ * elimination with partial pivoting on the augmented matrix (B | I).  Returns 0, or -1
+ * when a pivot column is entirely zero (B singular) or memory runs out.  This is the
+ * reference of the GPU reinversion (which instead factorises only the block of B that
+ * is not a slack column).
+ */
+int32_t oracle_basis_inverse(int32_t m, int32_t n, const double *A_colmajor, const int32_t *basis, double *Binv) {
+  const int32_t w = 2 * m;
+  double *T = (double *)calloc((size_t)m * w, sizeof(double));
+  if (!T) return -1;
+  for (int32_t p = 0; p < m; ++p) {
+    const int32_t v = basis[p];
+    for (int32_t i = 0; i < m; ++i)
+      T[(size_t)i * w + p] = v < n ? A_colmajor[(size_t)i + (size_t)v * m] : (i == v - n ? 1.0 : 0.0);
+    T[(size_t)p * w + m + p] = 1.0;
+  }
+  for (int32_t c = 0; c < m; ++c) {
+    int32_t piv = c;
+    for (int32_t i = c + 1; i < m; ++i)
+      if (fabs(T[(size_t)i * w + c]) > fabs(T[(size_t)piv * w + c])) piv = i;
+    if (T[(size_t)piv * w + c] == 0.0) {
+      free(T);
+      return -1;
+    }
+    if (piv != c)
+      for (int32_t j = 0; j < w; ++j) {
+        const double tmp = T[(size_t)c * w + j];
+        T[(size_t)c * w + j] = T[(size_t)piv * w + j];
+        T[(size_t)piv * w + j] = tmp;
+      }
+    const double pv = T[(size_t)c * w + c];
+    for (int32_t j = 0; j < w; ++j) T[(size_t)c * w + j] /= pv;
+    for (int32_t i = 0; i < m; ++i) {
+      if (i == c) continue;
+      const double f = T[(size_t)i * w + c];
+      if (f == 0.0) continue;
+      for (int32_t j = 0; j < w; ++j) T[(size_t)i * w + j] -= f * T[(size_t)c * w + j];
+    }
+  }
+  for (int32_t i = 0; i < m; ++i)
+    for (int32_t j = 0; j < m; ++j) Binv[(size_t)i * m + j] = T[(size_t)i * w + m + j];
+  free(T);
+  return 0;
 }
