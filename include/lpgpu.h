@@ -52,6 +52,10 @@ extern "C" {
 #define LP_MIN 0
 #define LP_MAX 1
 
+/* ---- arithmetic of the pricing step ---- */
+#define LP_FP64 0  /* every step in FP64 */
+#define LP_MIXED 1 /* FP32 screening of the reduced costs, shortlist re-priced in FP64 */
+
 /* Largest m this build accepts: B^-1 pivot row and entering column are staged in LDS. */
 #define LP_MAX_ROWS 10112
 
@@ -73,6 +77,19 @@ typedef struct lp_options {
   int32_t batch_small_m;  /* batched solver: LPs with m <= this get one wavefront each, larger ones a
                              whole workgroup; -1 = chosen per m-bucket by timing (default) */
   void *stream;           /* hipStream_t to run on; NULL = a stream owned by the handle */
+  int32_t precision;      /* LP_FP64 (default) or LP_MIXED: the reduced costs are first computed in
+                             FP32 from an FP32 copy of A'; the shortlist_k smallest over nonbasic
+                             non-tabu columns are re-priced in FP64 and the entering variable is the
+                             best improving one among them.  When none of them improves, every
+                             column is priced in FP64 (the plain Step 4), so optimality and the
+                             aspiration case are always decided in FP64.  FTRAN, the ratio test
+                             and the update stay FP64. */
+  int32_t shortlist_k;    /* LP_MIXED: candidates re-priced in FP64, 1..16 (default 16) */
+  int32_t reinv_period;   /* recompute B^-1, x_B, W and z from the basis (FP64 LU on the GPU) after
+                             every this many pivots; 0 = never; -1 = default: 64 for LP_MIXED,
+                             never for LP_FP64.  Takes effect at status read-backs, so it runs
+                             exactly every reinv_period pivots when iters_per_sync divides it. */
+  int32_t pad0;
 } lp_options;
 
 typedef struct lp_stats {
@@ -92,6 +109,16 @@ typedef struct lp_stats {
   int64_t finish_launches;  /* ratio-test finishing kernels timed (profile = 1 or 2) */
   double finish_ms;         /* their summed duration */
   int64_t ray;              /* after LP_UNBOUNDED: the entering variable with no positive alpha_i; else -1 */
+  int64_t price32_launches; /* LP_MIXED: FP32 screening passes run */
+  int64_t full_prices;      /* LP_MIXED: iterations whose shortlist held no improving column, so that
+                               every column was priced in FP64 */
+  int64_t reinversions;     /* reinversions installed */
+  int64_t reinv_failed;     /* reinversions abandoned because the basis block had a zero pivot
+                               column (the updated B^-1 is then kept) */
+  double reinv_ms;          /* device time of all reinversions */
+  double price32_ms;        /* profile = 1 or 2, LP_MIXED: summed duration of the FP32 screening */
+  double shortlist_ms;      /* profile = 1 or 2, LP_MIXED: summed duration of merge + FP64 re-price */
+  double price32_bytes;     /* their algorithmic bytes: 4*m per nonbasic structural column */
 } lp_stats;
 
 typedef struct lp_problem lp_problem;
@@ -151,6 +178,20 @@ int lp_get_pivots(const lp_problem *p, int32_t *entering, int32_t *leaving_row, 
 int lp_get_tableau(const lp_problem *p, double *Binv, double *xB, double *W, double *z);
 
 int lp_get_stats(const lp_problem *p, lp_stats *s);
+
+/*
+ * Reinversion: recomputes B^-1 from the current basis list and A' in FP64 on the GPU,
+ * then x_B = B^-1 b, W = chat_B^T B^-1 and z, discarding the rounding that the
+ * product-form updates of Section 3.1 have accumulated.  Only the block of B formed by
+ * the structural basic columns and the rows whose slack is nonbasic is factorised (LU
+ * with partial pivoting); the slack columns are unit vectors.  lp_solve calls it every
+ * opt.reinv_period pivots; it may also be called directly at any time (a pivot left
+ * pending by an interrupted solve is absorbed).  If that block is numerically singular
+ * (a zero pivot column) the state is left unchanged and lp_stats.reinv_failed counts it.
+ * Blocks until the basis has been read back; the rest runs on the handle's stream.
+ * Returns LP_OK or LP_ERR_NOMEM / LP_ERR_DEVICE.
+ */
+int lp_reinvert(lp_problem *p);
 
 /* Frees every device and host resource of the handle.  NULL-safe. */
 void lp_destroy(lp_problem *p);

@@ -17,6 +17,7 @@ LP_OK, LP_ERR_ARG, LP_ERR_NEG_RHS, LP_ERR_NOMEM, LP_ERR_DEVICE, LP_ERR_STATE = 0
 LP_RUNNING, LP_OPTIMAL, LP_UNBOUNDED, LP_ITER_LIMIT = 0, 1, 2, 3
 LP_PIVOT_DEGENERATE, LP_PIVOT_TIE, LP_PIVOT_ASPIRATION, LP_PIVOT_LCLEAR = 1, 2, 4, 8
 LP_MIN, LP_MAX = 0, 1
+LP_FP64, LP_MIXED = 0, 1
 LP_MAX_ROWS = 10112
 STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT"}
 
@@ -36,6 +37,10 @@ class lp_options(C.Structure):
         ("profile", C.c_int32),
         ("batch_small_m", C.c_int32),
         ("stream", C.c_void_p),
+        ("precision", C.c_int32),
+        ("shortlist_k", C.c_int32),
+        ("reinv_period", C.c_int32),
+        ("pad0", C.c_int32),
     ]
 
 
@@ -57,6 +62,14 @@ class lp_stats(C.Structure):
         ("finish_launches", C.c_int64),
         ("finish_ms", C.c_double),
         ("ray", C.c_int64),
+        ("price32_launches", C.c_int64),
+        ("full_prices", C.c_int64),
+        ("reinversions", C.c_int64),
+        ("reinv_failed", C.c_int64),
+        ("reinv_ms", C.c_double),
+        ("price32_ms", C.c_double),
+        ("shortlist_ms", C.c_double),
+        ("price32_bytes", C.c_double),
     ]
 
 
@@ -98,6 +111,7 @@ SIGNATURES = {
     "lp_get_pivots": (C.c_int, [_P, _IP, _IP, _IP, _IP, C.c_int64, _LP]),
     "lp_get_tableau": (C.c_int, [_P, _DP, _DP, _DP, _DP]),
     "lp_get_stats": (C.c_int, [_P, C.POINTER(lp_stats)]),
+    "lp_reinvert": (C.c_int, [_P]),
     "lp_destroy": (None, [_P]),
     "lp_error_string": (C.c_char_p, [C.c_int]),
     "lp_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, _IP, _IP, C.POINTER(_DP), C.POINTER(_DP),
@@ -149,8 +163,11 @@ def _dptr(a):
 class LP:
     """One LP held on the GPU (an lp_problem handle)."""
 
-    def __init__(self, A=None, b=None, c=None, *, device_tensors=None, sense="max", **opts):
-        o = default_options(sense=LP_MAX if sense == "max" else LP_MIN, **opts)
+    def __init__(self, A=None, b=None, c=None, *, device_tensors=None, sense="max", precision="fp64", **opts):
+        if precision not in ("fp64", "mixed"):
+            raise ValueError("precision must be 'fp64' or 'mixed'")
+        o = default_options(sense=LP_MAX if sense == "max" else LP_MIN,
+                            precision=LP_MIXED if precision == "mixed" else LP_FP64, **opts)
         h = _P()
         if device_tensors is not None:
             dA, db, dc, m, n = device_tensors
@@ -206,6 +223,9 @@ class LP:
 
     def reset(self):
         _check(lib().lp_reset(self._h), "lp_reset")
+
+    def reinvert(self):
+        _check(lib().lp_reinvert(self._h), "lp_reinvert")
 
     def solution(self):
         obj = C.c_double()

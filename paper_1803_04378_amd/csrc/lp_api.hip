@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "lp_device.h"
+#include "lp_reinv.h"
 #include "lpgpu.h"
 
 using namespace lpgpu;
@@ -75,6 +76,12 @@ struct lp_problem {
   int graph_k = 0;
   std::vector<hipEvent_t> events;
   lp_stats stats{};
+  int price32_grid = 0;    // mixed form
+  int reinv_period = 0;    // resolved opt.reinv_period
+  int64_t last_reinv_t = 0;
+  ReinvState* rv = nullptr;
+  hipEvent_t rv_ev[2] = {nullptr, nullptr};
+  bool rv_timing = false;  // a reinversion's events are waiting to be read
 };
 
 namespace {
@@ -117,6 +124,9 @@ void release(lp_problem* p) {
   p->allocs.clear();
   if (p->h_ctrl) (void)hipHostFree(p->h_ctrl);
   if (p->h_stage) (void)hipHostFree(p->h_stage);
+  reinv_free(p->rv);
+  for (hipEvent_t e : p->rv_ev)
+    if (e) (void)hipEventDestroy(e);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }
@@ -128,6 +138,10 @@ int check_options(const lp_options* o) {
     return fail(LP_ERR_ARG, "options.iters_per_sync must be in [1, 4096]");
   if (o->max_iter < 0) return fail(LP_ERR_ARG, "options.max_iter must be >= 0");
   if (o->profile < 0 || o->profile > 2) return fail(LP_ERR_ARG, "options.profile must be 0, 1 or 2");
+  if (o->precision != LP_FP64 && o->precision != LP_MIXED)
+    return fail(LP_ERR_ARG, "options.precision must be LP_FP64 or LP_MIXED");
+  if (o->shortlist_k < 1 || o->shortlist_k > kShortlist) return fail(LP_ERR_ARG, "options.shortlist_k must be in [1, 16]");
+  if (o->reinv_period < -1) return fail(LP_ERR_ARG, "options.reinv_period must be >= -1");
   if (!(o->eps_d >= 0.0) || !(o->eps_p >= 0.0) || !(o->eps_z >= 0.0) || !(o->eps_t >= 0.0) ||
       !std::isfinite(o->eps_d) || !std::isfinite(o->eps_p) || !std::isfinite(o->eps_z) || !std::isfinite(o->eps_t))
     return fail(LP_ERR_ARG, "options.eps_* must be finite and >= 0");
@@ -171,14 +185,61 @@ int read_ctrl(lp_problem* p) {
   return LP_OK;
 }
 
-// The iteration graph: iters_per_sync x (k_price -> k_update -> k_finish), a linear
-// chain.  With profile = 1 an event-record node sits before every kernel and at the end.
+// Reinversion between two replays, bracketed by events whose elapsed time is collected
+// at the next read-back (no extra host wait).
+int run_reinversion(lp_problem* p) {
+  for (auto& e : p->rv_ev)
+    if (!e) HIP_TRY(hipEventCreate(&e), "creating reinversion events");
+  HIP_TRY(hipEventRecord(p->rv_ev[0], p->stream), "recording an event");
+  int k = 0;
+  int rc = reinvert(p->d, p->b0, &p->rv, p->stream, &k);
+  if (rc != LP_OK) return rc;
+  HIP_TRY(hipEventRecord(p->rv_ev[1], p->stream), "recording an event");
+  p->rv_timing = true;
+  p->last_reinv_t = p->h_ctrl->t;
+  return LP_OK;
+}
+
+int collect_reinv_time(lp_problem* p) {
+  if (!p->rv_timing) return LP_OK;
+  float ms = 0.f;
+  HIP_TRY(hipEventSynchronize(p->rv_ev[1]), "waiting for the reinversion");
+  HIP_TRY(hipEventElapsedTime(&ms, p->rv_ev[0], p->rv_ev[1]), "timing the reinversion");
+  p->stats.reinv_ms += ms;
+  p->rv_timing = false;
+  return LP_OK;
+}
+
+// Kernels of one iteration, in launch order: k_price -> k_update -> k_finish, preceded in
+// the mixed form by the FP32 screening and the shortlist re-price.
+struct IterKernel {
+  const void* fn;
+  int grid, block;
+  size_t lds;
+};
+
+int iteration_kernels(const lp_problem* p, IterKernel* out) {
+  int c = 0;
+  if (p->d.mixed) {
+    out[c++] = {price32_kernel(), p->price32_grid, kPrice32Block, price32_lds_bytes(p->ld)};
+    out[c++] = {shortlist_kernel(), p->d.sl_k, 1024, shortlist_lds_bytes(p->price32_grid)};
+  }
+  out[c++] = {price_kernel(), p->price_grid, kPriceBlock, price_lds_bytes(p->ld)};
+  out[c++] = {update_kernel(), p->update_grid, kUpdateBlock, update_lds_bytes(p->ld)};
+  out[c++] = {finish_kernel(), 1, kUpdateBlock, 0};
+  return c;
+}
+
+// The iteration graph: iters_per_sync iterations as a linear chain of kernel nodes.  With
+// profile = 1 an event-record node sits before every kernel and at the end.
 int build_graph(lp_problem* p) {
   drop_graph(p);
   const int K = p->opt.iters_per_sync;
   const bool prof = p->opt.profile == 1;
+  IterKernel ks[5];
+  const int E = iteration_kernels(p, ks);
   if (prof) {
-    p->events.resize(3 * K + 1, nullptr);
+    p->events.resize(E * K + 1, nullptr);
     for (auto& e : p->events) HIP_TRY(hipEventCreate(&e), "creating profiling events");
   }
   HIP_TRY(hipGraphCreate(&p->graph, 0), "creating the iteration graph");
@@ -190,12 +251,12 @@ int build_graph(lp_problem* p) {
     return e;
   };
   void* args[] = {&p->d};
-  auto add_kernel = [&](const void* fn, int grid, int block, size_t lds) -> hipError_t {
+  auto add_kernel = [&](const IterKernel& ik) -> hipError_t {
     hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(fn);
-    kp.gridDim = dim3(grid);
-    kp.blockDim = dim3(block);
-    kp.sharedMemBytes = (unsigned)lds;
+    kp.func = const_cast<void*>(ik.fn);
+    kp.gridDim = dim3(ik.grid);
+    kp.blockDim = dim3(ik.block);
+    kp.sharedMemBytes = (unsigned)ik.lds;
     kp.kernelParams = args;
     kp.extra = nullptr;
     hipGraphNode_t node;
@@ -203,15 +264,12 @@ int build_graph(lp_problem* p) {
     if (e == hipSuccess) prev = node;
     return e;
   };
-  for (int k = 0; k < K; ++k) {
-    if (prof) HIP_TRY(add_event(p->events[3 * k]), "adding a profiling event");
-    HIP_TRY(add_kernel(price_kernel(), p->price_grid, kPriceBlock, price_lds_bytes(p->ld)), "adding k_price");
-    if (prof) HIP_TRY(add_event(p->events[3 * k + 1]), "adding a profiling event");
-    HIP_TRY(add_kernel(update_kernel(), p->update_grid, kUpdateBlock, update_lds_bytes(p->ld)), "adding k_update");
-    if (prof) HIP_TRY(add_event(p->events[3 * k + 2]), "adding a profiling event");
-    HIP_TRY(add_kernel(finish_kernel(), 1, kUpdateBlock, 0), "adding k_finish");
-  }
-  if (prof) HIP_TRY(add_event(p->events[3 * K]), "adding a profiling event");
+  for (int k = 0; k < K; ++k)
+    for (int i = 0; i < E; ++i) {
+      if (prof) HIP_TRY(add_event(p->events[E * k + i]), "adding a profiling event");
+      HIP_TRY(add_kernel(ks[i]), "adding a kernel node");
+    }
+  if (prof) HIP_TRY(add_event(p->events[E * K]), "adding a profiling event");
   HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0), "instantiating the iteration graph");
   p->graph_k = K;
   return LP_OK;
@@ -221,20 +279,21 @@ int build_graph(lp_problem* p) {
 // before every kernel (no graph), for cross-checking the graph's events.
 int launch_direct(lp_problem* p) {
   const int K = p->opt.iters_per_sync;
-  if ((int)p->events.size() != 3 * K + 1) {
+  IterKernel ks[5];
+  const int E = iteration_kernels(p, ks);
+  if ((int)p->events.size() != E * K + 1) {
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
-    p->events.assign(3 * K + 1, nullptr);
+    p->events.assign(E * K + 1, nullptr);
     for (auto& e : p->events) HIP_TRY(hipEventCreate(&e), "creating profiling events");
   }
-  for (int k = 0; k < K; ++k) {
-    HIP_TRY(hipEventRecord(p->events[3 * k], p->stream), "recording an event");
-    HIP_TRY(launch_price(p->d, p->price_grid, p->stream), "launching k_price");
-    HIP_TRY(hipEventRecord(p->events[3 * k + 1], p->stream), "recording an event");
-    HIP_TRY(launch_update(p->d, p->update_grid, p->stream), "launching k_update");
-    HIP_TRY(hipEventRecord(p->events[3 * k + 2], p->stream), "recording an event");
-    HIP_TRY(launch_finish(p->d, p->stream), "launching k_finish");
-  }
-  HIP_TRY(hipEventRecord(p->events[3 * K], p->stream), "recording an event");
+  for (int k = 0; k < K; ++k)
+    for (int i = 0; i < E; ++i) {
+      HIP_TRY(hipEventRecord(p->events[E * k + i], p->stream), "recording an event");
+      void* args[] = {&p->d};
+      HIP_TRY(hipLaunchKernel(ks[i].fn, dim3(ks[i].grid), dim3(ks[i].block), args, ks[i].lds, p->stream),
+              "launching an iteration kernel");
+    }
+  HIP_TRY(hipEventRecord(p->events[E * K], p->stream), "recording an event");
   return LP_OK;
 }
 
@@ -251,6 +310,7 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   if (opt) o = *opt;
   if (int rc = check_options(&o)) return rc;
   if (o.max_iter == 0) o.max_iter = 10 * ((int64_t)m + n);
+  const bool mixed = o.precision == LP_MIXED;
 
   std::vector<double> hb(m), hc(n);
   if (!device_inputs) {
@@ -308,13 +368,24 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   p->update_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)update_per_cu * p->num_cu, (m + uw - 1) / uw));
   if ((m + (int64_t)p->update_grid * uw - 1) / ((int64_t)p->update_grid * uw) > kMaxRowsPerWave)
     return bail(fail(LP_ERR_ARG, "m too large for this device: more than kMaxRowsPerWave rows per wavefront"));
+  p->reinv_period = o.reinv_period >= 0 ? o.reinv_period : (mixed ? 64 : 0);
+  if (mixed) {
+    int per_cu = 0;
+    hipError_t e = price32_occupancy(&per_cu, ld);
+    if (e != hipSuccess) return bail(fail_hip(e, "querying kernel occupancy"));
+    if (per_cu < 1) return bail(fail(LP_ERR_ARG, "m too large for the FP32 pricing kernel's LDS"));
+    const int w32 = kPrice32Block / 64;
+    p->price32_grid = (int)std::max<int64_t>(
+        1, std::min<int64_t>(std::min<int64_t>((int64_t)per_cu * p->num_cu, max_price32_grid()), (N + w32 - 1) / w32));
+  }
 
   // Device memory: A' (ld x n) + B^-1 (m x ld) dominate.
   {
     size_t freeb = 0, totalb = 0;
     hipError_t e = hipMemGetInfo(&freeb, &totalb);
     if (e != hipSuccess) return bail(fail_hip(e, "querying device memory"));
-    const double need = 8.0 * ld * (double)n + 8.0 * m * (double)ld + 64.0 * N + 64.0 * ld + 64.0 * o.max_iter;
+    const double need = (mixed ? 12.0 : 8.0) * ld * (double)n + 8.0 * m * (double)ld + 64.0 * N + 64.0 * ld +
+                        64.0 * o.max_iter;
     if (need > (double)freeb) return bail(fail(LP_ERR_NOMEM, "LP does not fit in free device memory"));
   }
   double* dA = nullptr;
@@ -328,8 +399,7 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   ALLOC(chat, (size_t)N);
   ALLOC(p->d.Binv, (size_t)m * ld);
   ALLOC(p->d.xB, (size_t)m);
-  ALLOC(p->d.W0, (size_t)ld);
-  ALLOC(p->d.W1, (size_t)ld);
+  ALLOC(p->d.W, (size_t)ld);
   ALLOC(p->d.rho, (size_t)ld);
   ALLOC(p->d.alpha0, (size_t)m);
   ALLOC(p->d.alpha1, (size_t)m);
@@ -347,6 +417,14 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   ALLOC(p->d.ctrl, 1);
   ALLOC(p->b0, (size_t)m);
   ALLOC(p->c0, (size_t)std::max(n, 1));
+  float* dA32 = nullptr;
+  if (mixed) {
+    ALLOC(dA32, (size_t)ld * std::max(n, 1));
+    ALLOC(p->d.part32_d, (size_t)p->price32_grid * kShortlist);
+    ALLOC(p->d.part32_j, (size_t)p->price32_grid * kShortlist);
+    ALLOC(p->d.sl_d, (size_t)kShortlist);
+    ALLOC(p->d.sl_j, (size_t)kShortlist);
+  }
 #undef ALLOC
   p->d.m = m;
   p->d.n = n;
@@ -361,6 +439,10 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   p->d.eps_p = o.eps_p;
   p->d.eps_z = o.eps_z;
   p->d.eps_t = o.eps_t;
+  p->d.mixed = mixed ? 1 : 0;
+  p->d.sl_k = o.shortlist_k;
+  p->d.A32 = dA32;
+  p->d.price32_grid = p->price32_grid;
   {
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p->h_ctrl), sizeof(Ctrl), hipHostMallocDefault);
     if (e != hipSuccess) return bail(fail_hip(e, "allocating pinned memory"));
@@ -406,6 +488,11 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   }
   e = hipMemcpyAsync(p->b0, b, sizeof(double) * m, kind, s);
   if (e != hipSuccess) return bail(fail_hip(e, "copying b"));
+  if (mixed) {
+    // FP32 copy of A' with the same padding (round to nearest).
+    e = launch_convert32(dA, dA32, (size_t)ld * n, s);
+    if (e != hipSuccess) return bail(fail_hip(e, "converting A to FP32"));
+  }
   e = launch_init(p->d, p->b0, p->c0, o.sense == LP_MAX ? -1.0 : 1.0, s);
   if (e != hipSuccess) return bail(fail_hip(e, "initialising the slack basis"));
   if ((rc = read_ctrl(p)) != LP_OK) return bail(rc);
@@ -434,6 +521,9 @@ int lp_default_options(lp_options* opt) {
   opt->profile = 0;
   opt->batch_small_m = -1;
   opt->stream = nullptr;
+  opt->precision = LP_FP64;
+  opt->shortlist_k = kShortlist;
+  opt->reinv_period = -1;
   return LP_OK;
 }
 
@@ -471,9 +561,12 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
           "arming the solve");
   const bool prof = p->opt.profile != 0;
   const int K = p->opt.iters_per_sync;
+  const bool mixed = p->d.mixed != 0;
+  const int E = mixed ? 5 : 3;
   for (;;) {
     const int64_t t_before = p->h_ctrl->t;
     const int64_t cols_before = p->h_ctrl->price_cols;
+    const int64_t nsb_before = p->h_ctrl->nsb;
     if (direct) {
       if ((rc = launch_direct(p)) != LP_OK) return rc;
     } else {
@@ -481,28 +574,44 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
     }
     if ((rc = read_ctrl(p)) != LP_OK) return rc;
     p->stats.syncs += 1;
+    if ((rc = collect_reinv_time(p)) != LP_OK) return rc;
     if (prof && p->h_ctrl->status == LP_RUNNING && t_before > 0 && p->h_ctrl->t == t_before + K) {
-      // Steady state: every kernel of the replay did a full pass.
+      // Steady state: every kernel of the replay did a full pass (in the mixed form the
+      // FP64 pricing node may have skipped itself; its bytes count only passes that ran).
       for (int k = 0; k < K; ++k) {
-        float ms_p = 0.f, ms_u = 0.f, ms_f = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms_p, p->events[3 * k], p->events[3 * k + 1]), "reading profile events");
-        HIP_TRY(hipEventElapsedTime(&ms_u, p->events[3 * k + 1], p->events[3 * k + 2]), "reading profile events");
-        HIP_TRY(hipEventElapsedTime(&ms_f, p->events[3 * k + 2], p->events[3 * k + 3]), "reading profile events");
-        p->stats.price_ms += ms_p;
-        p->stats.update_ms += ms_u;
-        p->stats.finish_ms += ms_f;
+        float ms[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < E; ++i)
+          HIP_TRY(hipEventElapsedTime(&ms[i], p->events[E * k + i], p->events[E * k + i + 1]),
+                  "reading profile events");
+        const int o = mixed ? 2 : 0;
+        if (mixed) {
+          p->stats.price32_ms += ms[0];
+          p->stats.shortlist_ms += ms[1];
+        }
+        p->stats.price_ms += ms[o];
+        p->stats.update_ms += ms[o + 1];
+        p->stats.finish_ms += ms[o + 2];
       }
       p->stats.price_launches += K;
       p->stats.update_launches += K;
       p->stats.finish_launches += K;
       p->stats.price_bytes += 8.0 * p->m * (double)(p->h_ctrl->price_cols - cols_before);
       p->stats.update_bytes += 16.0 * (double)p->m * p->m * K;
+      if (mixed) {
+        // Nonbasic structural columns streamed by the K screening passes (the basis
+        // changes by at most one structural column per pivot; the midpoint is used).
+        const double nonbasic = p->n - 0.5 * (double)(nsb_before + p->h_ctrl->nsb);
+        p->stats.price32_bytes += 4.0 * p->m * nonbasic * K;
+      }
     }
     if (p->h_ctrl->status != LP_RUNNING) break;
     // Every replay of a RUNNING solve must pivot K times; anything else is a fault of the
     // kernels' control logic, reported instead of looping.
     if (p->h_ctrl->t != t_before + K)
       return fail(LP_ERR_DEVICE, "iteration graph made no progress while RUNNING");
+    if (p->reinv_period > 0 && p->h_ctrl->t - p->last_reinv_t >= p->reinv_period) {
+      if ((rc = run_reinversion(p)) != LP_OK) return rc;
+    }
   }
   p->stats.solve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (status_out) *status_out = p->h_ctrl->status;
@@ -519,6 +628,8 @@ int lp_reset(lp_problem* p) {
   HIP_TRY(launch_init(p->d, p->b0, p->c0, p->opt.sense == LP_MAX ? -1.0 : 1.0, p->stream), "resetting");
   int rc = read_ctrl(p);
   if (rc != LP_OK) return rc;
+  p->rv_timing = false;
+  p->last_reinv_t = 0;
   p->stats = lp_stats{};
   return LP_OK;
 }
@@ -531,7 +642,7 @@ int lp_get_solution(const lp_problem* pc, double* objective, double* x, double* 
   std::vector<double> xB(m), W(m);
   std::vector<int32_t> bas(m);
   HIP_TRY(hipMemcpyAsync(xB.data(), p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
-  const double* dW = p->h_ctrl->wcur ? p->d.W1 : p->d.W0;
+  const double* dW = p->d.W;
   HIP_TRY(hipMemcpyAsync(W.data(), dW, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading W");
   HIP_TRY(hipMemcpyAsync(bas.data(), p->d.basis, sizeof(int32_t) * m, hipMemcpyDeviceToHost, p->stream),
           "reading the basis");
@@ -584,7 +695,7 @@ int lp_get_tableau(const lp_problem* pc, double* Binv, double* xB, double* W, do
             "reading B^-1");
   if (xB) HIP_TRY(hipMemcpyAsync(xB, p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
   if (W)
-    HIP_TRY(hipMemcpyAsync(W, p->h_ctrl->wcur ? p->d.W1 : p->d.W0, sizeof(double) * m, hipMemcpyDeviceToHost,
+    HIP_TRY(hipMemcpyAsync(W, p->d.W, sizeof(double) * m, hipMemcpyDeviceToHost,
                            p->stream),
             "reading W");
   HIP_TRY(hipStreamSynchronize(p->stream), "reading the tableau");
@@ -601,7 +712,19 @@ int lp_get_stats(const lp_problem* p, lp_stats* s) {
   s->aspirations = p->h_ctrl->n_aspiration;
   s->list_clears = p->h_ctrl->n_lclear;
   s->ray = p->h_ctrl->status == LP_UNBOUNDED ? p->h_ctrl->ray : -1;
+  s->price32_launches = p->h_ctrl->price32_launches;
+  s->full_prices = p->h_ctrl->full_prices;
+  s->reinversions = p->h_ctrl->n_reinv;
+  s->reinv_failed = p->h_ctrl->n_reinv_failed;
   return LP_OK;
+}
+
+int lp_reinvert(lp_problem* p) {
+  if (!p) return fail(LP_ERR_ARG, "p is NULL");
+  int rc = run_reinversion(p);
+  if (rc != LP_OK) return rc;
+  if ((rc = read_ctrl(p)) != LP_OK) return rc;
+  return collect_reinv_time(p);
 }
 
 void lp_destroy(lp_problem* p) { release(p); }

@@ -215,6 +215,8 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
   if (opt) o = *opt;
   if (o.sense != LP_MIN && o.sense != LP_MAX) return fail(LP_ERR_ARG, "options.sense must be LP_MIN or LP_MAX");
   if (o.tabu_tenure < 0 || o.max_iter < 0) return fail(LP_ERR_ARG, "invalid options");
+  if (o.precision != LP_FP64 || o.reinv_period > 0)
+    return fail(LP_ERR_ARG, "the batched solver runs in FP64 without reinversion (precision LP_FP64, reinv_period <= 0)");
   size_t max_bytes = 0, max_small = 0;
   for (int32_t i = 0; i < count; ++i) {
     if (m[i] <= 0 || n[i] < 0 || !b[i] || (n[i] > 0 && (!A[i] || !c[i])))

@@ -4,13 +4,13 @@
 // padding is zero and stays zero):
 //   A      ld x n   column-major: column j of A' is contiguous (pricing streams it)
 //   Binv   m x ld   row-major:    row i of B^-1 is contiguous (update + FTRAN stream it)
-//   W0, W1, rho ld  W = chat_B^T B^-1 (top row of the Figure 1 tableau, two copies: one is
-//                   read while the next is written), rho = pivot row / alpha_r
+//   W, rho    ld    W = chat_B^T B^-1 (top row of the Figure 1 tableau), rho = pivot row / alpha_r
 //   xB, alpha[2]    m
 //   chat            n + m   (minimisation costs; slacks 0)
 //   basis (m), pos (n+m), tabu_until (n+m), the leaving-side tabu list, the pivot log: int32
 #pragma once
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <stdint.h>
 
 namespace lpgpu {
@@ -35,6 +35,9 @@ constexpr int kPriceBlock = LPGPU_PRICE_BLOCK;
 constexpr int kUpdateBlock = LPGPU_UPDATE_BLOCK;
 // Rows of B^-1 one wavefront of k_update may own (the host sizes the grid to respect it).
 constexpr int kMaxRowsPerWave = 8;
+// Mixed form: FP32 screening keeps this many candidates per workgroup and overall.
+constexpr int kShortlist = 16;
+constexpr int kPrice32Block = 1024;
 
 // Control block: written by one thread of a kernel (or by the host between solves), read
 // by every workgroup of the next kernel; a field is never read and written by different
@@ -62,10 +65,10 @@ struct Ctrl {
   int64_t update_launches;      // update passes that ran
   int64_t update_rows_written;  // B^-1 rows those passes rewrote
   double theta;   // step length of the pending pivot
-  double pdq;     // reduced cost of the pending pivot's entering variable
-  double ar;      // pivot element alpha_r of the pending pivot
-  int32_t wcur;   // W0 or W1 holds the current top row W
-  int32_t pad2;
+  int64_t price32_launches;  // mixed form: FP32 screening passes that ran
+  int64_t full_prices;       // mixed form: iterations whose shortlist held no improving column
+  int64_t n_reinv;           // reinversions installed
+  int64_t n_reinv_failed;    // reinversions abandoned on a zero pivot (state kept as it was)
 };
 
 struct DevLP {
@@ -74,8 +77,7 @@ struct DevLP {
   const double* chat;
   double* Binv;
   double* xB;
-  double* W0;     // W ping-pong: k_price reads one and writes the other
-  double* W1;
+  double* W;
   double* rho;
   double* alpha0;
   double* alpha1;
@@ -106,7 +108,26 @@ struct DevLP {
   int32_t use_llist;
   int32_t pad1;
   double eps_d, eps_p, eps_z, eps_t;
+  // Mixed form only (mixed == 0: the pointers are unused).
+  int32_t mixed;
+  int32_t sl_k;          // shortlist length K <= kShortlist
+  const float* A32;      // FP32 copy of A', same ld x n layout
+  float* part32_d;       // FP32 screening: kShortlist candidates per k_price32 workgroup,
+  int32_t* part32_j;     //   ascending in (d32, j)
+  double* sl_d;          // the shortlist re-priced in FP64 (kShortlist entries; j = INT_MAX
+  int32_t* sl_j;         //   marks an empty slot)
+  int32_t price32_grid;  // workgroups of k_price32
+  int32_t pad2;
 };
+
+// Mixed form: does the re-priced shortlist hold an improving column?  Every thread reads
+// the same entries, so all workgroups of a launch agree.
+__device__ __forceinline__ bool shortlist_improves(const DevLP& lp) {
+  const double neg_eps = -lp.eps_d;
+  for (int w = 0; w < lp.sl_k; ++w)
+    if (lp.sl_j[w] != INT_MAX && lp.sl_d[w] < neg_eps) return true;
+  return false;
+}
 
 // Launchers (lp_kernels.hip).  grid sizes are chosen by the caller.
 hipError_t launch_init(const DevLP& lp, const double* b, const double* c, double sense, hipStream_t s);
@@ -121,5 +142,16 @@ const void* finish_kernel();
 size_t price_lds_bytes(int ld);
 size_t update_lds_bytes(int ld);
 hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld);
+
+// Mixed form (lp_mixed.hip).
+hipError_t launch_convert32(const double* A, float* A32, size_t count, hipStream_t s);
+hipError_t launch_price32(const DevLP& lp, int grid, hipStream_t s);
+hipError_t launch_shortlist(const DevLP& lp, hipStream_t s);
+const void* price32_kernel();
+const void* shortlist_kernel();
+size_t price32_lds_bytes(int ld);
+size_t shortlist_lds_bytes(int grid32);
+hipError_t price32_occupancy(int* per_cu, int ld);
+int max_price32_grid();
 
 }  // namespace lpgpu

@@ -2,24 +2,25 @@
 //
 // One iteration is three launches, ordered only by kernel boundaries (no grid-wide
 // fences, which cost an L2 write-back per workgroup on this part):
-//   k_price   Step 8 on the top row for the previous pivot (W += d_q rho, formed while
-//             staging W in LDS), then Steps 3-4: reduced costs d_j = chat_j - W a_j of
-//             every nonbasic column, one wavefront per column of A'; each workgroup
-//             leaves its lexicographic (d, j) minima over all improving and over
-//             non-tabu improving columns.
+//   k_price   Steps 3-4: reduced costs d_j = chat_j - W a_j of every nonbasic column,
+//             one wavefront per column of A', W staged in LDS; each workgroup leaves
+//             its lexicographic (d, j) minima over all improving and over non-tabu
+//             improving columns.
 //   k_update  every workgroup reduces those partials to the same q (Step 4), then runs
 //             the Section 3.1 update of B^-1 and x_B for the previous pivot fused with
 //             Step 5 (FTRAN, alpha = B^-1 a_q) for q: one wavefront per row of B^-1
 //             reads the row once, writes the updated row, dots it with a_q on the fly,
 //             and forms that row's ratio (Step 6); each workgroup leaves its minimum
 //             ratio and its rows within the tie bound.
-//   k_finish  one workgroup: Step 6 ties and tabu list, then the scalar part of Step 8
-//             (basis, entering mask, objective, pivot log).
+//   k_finish  one workgroup: Step 6 ties and tabu list, the scalar part of Step 8
+//             (basis, entering mask, objective, pivot log) and Step 8 on the top row
+//             (rho = B^-1[r,:] / alpha_r, W += d_q rho).
 //
 // The B^-1 update of pivot t therefore runs in the same pass as the FTRAN of pivot
 // t+1.  This is legal because pricing for t+1 needs only W_{t+1} = W_t + d_q rho_t,
-// which needs only row r of the not yet updated B^-1; it removes one full read of
-// B^-1 per iteration.  Every element still gets the same arithmetic as in Step 8.
+// which k_finish forms from row r of the not yet updated B^-1; it removes one full
+// read of B^-1 per iteration.  Every element still gets the same arithmetic as in
+// Step 8.
 //
 // Reductions are deterministic: each dot product is a fixed per-lane fma chain
 // followed by a fixed xor-butterfly, and every argmin is a lexicographic (value,
@@ -48,8 +49,7 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
     lp.Binv[k] = (i == j) ? 1.0 : 0.0;
   }
   for (size_t k = tid; k < (size_t)ld; k += stride) {
-    lp.W0[k] = 0.0;
-    lp.W1[k] = 0.0;
+    lp.W[k] = 0.0;
     lp.rho[k] = 0.0;
   }
   for (size_t i = tid; i < (size_t)m; i += stride) {
@@ -78,15 +78,13 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
 }
 
 // ---------------------------------------------------------------------------------------
-// Steps 3-4, preceded by Step 8 on the top row of the tableau for the pending pivot:
-// every workgroup forms W_new = W + d_q rho, rho = B^-1[r,:] / alpha_r, while staging it
-// into LDS (B^-1 still holds the pre-pivot rows, the row update runs in k_update);
-// workgroup 0 also stores rho and W_new for the rest of the iteration.
+// Steps 3-4: reduced costs of every nonbasic column, W staged in LDS.
+// In the mixed form this pass runs only when the re-priced shortlist holds no improving
+// column.
 __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
   if (lp.ctrl->status != kStatusRunning) return;
+  if (lp.mixed && shortlist_improves(lp)) return;
   const int64_t t = lp.ctrl->t;
-  const int r = lp.ctrl->r;
-  const int wc = lp.ctrl->wcur;
   extern __shared__ double2 s_w2[];
   __shared__ double red_d[2 * (kPriceBlock / 64)];
   __shared__ int red_j[2 * (kPriceBlock / 64)];
@@ -115,28 +113,8 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
     else load_batch(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
   }
 
-  const double2* Wold = reinterpret_cast<const double2*>(wc ? lp.W1 : lp.W0);
-  if (r >= 0) {
-    const double ar = lp.ctrl->ar;
-    const double dq = lp.ctrl->pdq;
-    const double2* rowr = reinterpret_cast<const double2*>(lp.Binv + (size_t)r * lp.ld);
-    double2* Wnew = reinterpret_cast<double2*>(wc ? lp.W0 : lp.W1);
-    double2* rho2 = reinterpret_cast<double2*>(lp.rho);
-    const bool writer = blockIdx.x == 0;
-    for (int k = threadIdx.x; k < ld2; k += kPriceBlock) {
-      const double2 b = rowr[k];
-      const double2 w = Wold[k];
-      const double2 rr = make_double2(b.x / ar, b.y / ar);
-      const double2 wn = make_double2(fma(dq, rr.x, w.x), fma(dq, rr.y, w.y));
-      s_w2[k] = wn;
-      if (writer) {
-        rho2[k] = rr;
-        Wnew[k] = wn;
-      }
-    }
-  } else {
-    for (int k = threadIdx.x; k < ld2; k += kPriceBlock) s_w2[k] = Wold[k];
-  }
+  const double2* W2 = reinterpret_cast<const double2*>(lp.W);
+  for (int k = threadIdx.x; k < ld2; k += kPriceBlock) s_w2[k] = W2[k];
   __syncthreads();
   const double* s_w = reinterpret_cast<const double*>(s_w2);
 
@@ -240,9 +218,24 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   const bool pre = gw < m && gw != r;
   if (pre) load_batch(reinterpret_cast<const double2*>(lp.Binv + (size_t)gw * lp.ld), lane, ld2, v);
 
-  // Step 4 decision from the pricing partials.
+  // Step 4 decision: from the re-priced shortlist in the mixed form when it holds an
+  // improving column (all of its columns are non-tabu), else from the pricing partials.
   double da = __builtin_inf(), df = __builtin_inf();
   int ja = INT_MAX, jf = INT_MAX;
+  const bool from_shortlist = lp.mixed && shortlist_improves(lp);
+  if (from_shortlist) {
+    const double neg_eps = -lp.eps_d;
+    for (int w = 0; w < lp.sl_k; ++w) {
+      const double d = lp.sl_d[w];
+      const int j = lp.sl_j[w];
+      if (j != INT_MAX && d < neg_eps && lex_less(d, j, df, jf)) {
+        df = d;
+        jf = j;
+      }
+    }
+    da = df;
+    ja = jf;
+  } else {
   for (int k = threadIdx.x; k < lp.price_grid; k += kUpdateBlock) {
     const double d0 = lp.part_d[2 * k], d1 = lp.part_d[2 * k + 1];
     const int j0 = lp.part_j[2 * k], j1 = lp.part_j[2 * k + 1];
@@ -270,6 +263,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   jf = lane < waves ? red_j[waves + lane] : INT_MAX;
   wave_lexmin(da, ja);  // every wave reduces the same values: no second exchange needed
   wave_lexmin(df, jf);
+  }
   int status = kStatusRunning, q = -1, flags = 0;
   double dq = 0.0;
   if (ja == INT_MAX) {
@@ -287,9 +281,12 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     // Only fields no k_update workgroup reads: the status itself changes in k_finish.
     Ctrl* ctl = lp.ctrl;
-    ctl->price_cols += n - ctl->nsb;
-    ctl->price_launches += 1;
-    if (r >= 0) ctl->wcur ^= 1;  // k_price wrote W_new: it is the current top row now
+    if (lp.mixed) ctl->price32_launches += 1;
+    if (!from_shortlist) {
+      ctl->price_cols += n - ctl->nsb;
+      ctl->price_launches += 1;
+      if (lp.mixed) ctl->full_prices += 1;
+    }
     ctl->verdict = status;
     ctl->q = q;
     ctl->dq = dq;
@@ -537,14 +534,26 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
     if (flags & kFlagLClear) ctl->n_lclear += 1;
     if (flags & kFlagDegenerate) ctl->n_degenerate += 1;
     ctl->t = t + 1;
-    ctl->r = r;        // pending: rows of B^-1 and x_B are pivoted by the next k_update,
-    ctl->theta = thr;  // the top row by the next k_price
-    ctl->ar = al[r];
-    ctl->pdq = dq;
+    ctl->r = r;        // pending: rows of B^-1 and x_B are pivoted by the next k_update
+    ctl->theta = thr;
     ctl->cur = cur ^ 1;
     ctl->q = -1;
     ctl->flags = 0;
     ctl->verdict = -1;
+  }
+  // Step 8 on the top row of the tableau: rho = B^-1[r,:] / alpha_r from the not yet
+  // updated B^-1, then W <- W + d_q rho.  k_update applies rho to the other rows.
+  const double ar = al[r];
+  const double dq = ctl->dq;
+  const double2* rowr = reinterpret_cast<const double2*>(lp.Binv + (size_t)r * lp.ld);
+  double2* rho2 = reinterpret_cast<double2*>(lp.rho);
+  double2* W2 = reinterpret_cast<double2*>(lp.W);
+  for (int k = tid; k < lp.ld / 2; k += B) {
+    const double2 bv = rowr[k];
+    const double2 rr = make_double2(bv.x / ar, bv.y / ar);
+    const double2 w = W2[k];
+    rho2[k] = rr;
+    W2[k] = make_double2(fma(dq, rr.x, w.x), fma(dq, rr.y, w.y));
   }
 }
 

@@ -38,15 +38,16 @@ def test_header_constants_match_binding():
 
 
 def test_struct_layouts():
-    assert C.sizeof(binding.lp_options) == 80
+    assert C.sizeof(binding.lp_options) == 96
     assert C.sizeof(binding.lp_batch_stats) == 72
-    assert C.sizeof(binding.lp_stats) == 128
+    assert C.sizeof(binding.lp_stats) == 192
 
 
 def test_default_options():
     o = lpg.default_options()
     assert o.sense == binding.LP_MAX and o.tabu_tenure == 5 and o.leaving_list == 1
     assert o.eps_d == 1e-9 and o.eps_p == 1e-9 and o.eps_z == 1e-9 and o.eps_t == 1e-9 and o.max_iter == 0 and o.batch_small_m == -1
+    assert o.precision == binding.LP_FP64 and o.shortlist_k == 16 and o.reinv_period == -1
     assert lpg.lib().lp_default_options(None) == binding.LP_ERR_ARG
 
 
@@ -78,6 +79,11 @@ def test_argument_errors_need_no_gpu():
     assert _create(3, 2, dp(A), dp(b), dp(c), C.byref(o))[0] == binding.LP_ERR_ARG
     o = lpg.default_options(sense=7)
     assert _create(3, 2, dp(A), dp(b), dp(c), C.byref(o))[0] == binding.LP_ERR_ARG
+    for bad in (dict(precision=2), dict(shortlist_k=0), dict(shortlist_k=17), dict(reinv_period=-2)):
+        o = lpg.default_options(**bad)
+        assert _create(3, 2, dp(A), dp(b), dp(c), C.byref(o))[0] == binding.LP_ERR_ARG, bad
+    with pytest.raises(ValueError):
+        lpg.LP(A, b, c, precision="fp16")
     assert L.lp_solve(None, None) == binding.LP_ERR_ARG
     L.lp_destroy(None)  # NULL-safe
     with pytest.raises(lpg.LPError):
@@ -112,5 +118,8 @@ def test_batch_argument_errors_need_no_gpu():
     pa2 = (dp * 2)(A.ctypes.data_as(dp), Abig.ctypes.data_as(dp))
     pb2 = (dp * 2)(b.ctypes.data_as(dp), bbig.ctypes.data_as(dp))
     assert L.lp_batch_create(C.byref(h), 2, big, ns, pa2, pb2, pc, None) == binding.LP_ERR_ARG
+    o = lpg.default_options(precision=binding.LP_MIXED)
+    assert L.lp_batch_create(C.byref(h), 2, ms, ns, pa, pb, pc, C.byref(o)) == binding.LP_ERR_ARG
     assert L.lp_batch_solve(None) == binding.LP_ERR_ARG
+    assert L.lp_reinvert(None) == binding.LP_ERR_ARG
     L.lp_batch_destroy(None)
