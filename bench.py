@@ -3,10 +3,12 @@
 A step is one simplex iteration (pricing, FTRAN, ratio test, B^-1 update) of the dense
 LP  max c^T x  s.t.  A'x <= b, x >= 0  with m = 4000 rows and n = 8000 columns
 (A'_ij ~ U(0,1), b_i ~ U(1,10), c_j ~ U(1,10), seed 0), all data resident in HBM.
-W warm-up pivots run first, then exactly K pivots are timed, with HIP event nodes
-around every kernel of the iteration graph.  The printed line also carries the roofline
-of the dominant kernel, the time to optimality of the whole solve, and the CPU oracle's
-rate on a bounded sample of the same solve.
+W warm-up pivots run first, then exactly K pivots of the iteration graph are timed
+(`value`).  A second pass of K pivots launches the same kernels directly, each with
+start and stop HIP events bound to its dispatch, for the per-kernel durations behind
+the roofline of the dominant kernel.  The printed line also carries the time to
+optimality, the mixed-precision form against the FP64 path on its own configuration,
+the batched form, and the CPU oracle's rate on a bounded sample of the same solve.
 """
 from __future__ import annotations
 
@@ -22,7 +24,8 @@ if _ROOT not in sys.path:
 
 METRIC = "simplex iter/s + solve time (m=4000,n=8000); batched LPs/s; % HBM peak"
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAMES = {"price": "k_price", "update": "k_update", "finish": "k_finish"}
+KERNEL_NAMES = {"price": "k_price", "update": "k_update", "finish": "k_finish", "price32": "k_price32",
+                "shortlist": "k_shortlist"}
 
 
 def _log(msg):
@@ -62,15 +65,21 @@ def measured_traffic(kernel):
 
 
 def kernel_table(s0, s1):
+    """Per-kernel average duration (HIP events of the profiling mode) and, for the
+    streaming kernels, algorithmic bytes per launch and the rate they imply.  In the mixed
+    form the FP32 screening and shortlist kernels run once per iteration (their launch
+    count is the update kernel's), and the FP64 pricing node is counted per launch whether
+    it ran a full pass or skipped itself."""
     out = {}
     for name in KERNEL_NAMES:
-        launches = s1[f"{name}_launches"] - s0[f"{name}_launches"]
         ms = s1[f"{name}_ms"] - s0[f"{name}_ms"]
+        key = "update" if name in ("price32", "shortlist") else name
+        launches = s1[f"{key}_launches"] - s0[f"{key}_launches"]
         if launches <= 0 or ms <= 0:
             continue
         avg_s = ms / launches * 1e-3
         row = dict(launches=launches, avg_us=round(avg_s * 1e6, 3))
-        if name != "finish":
+        if name in ("price", "update", "price32"):
             byts = (s1[f"{name}_bytes"] - s0[f"{name}_bytes"]) / launches
             row.update(bytes_per_launch=byts, gbs=round(byts / avg_s / 1e9, 1))
         out[name] = row
@@ -102,6 +111,71 @@ def solve_leg(lpg, torch, dev, opts):
         sol = lp.solution()
     return dict(status=lpg.STATUS_NAMES[st], seconds=round(ts, 5), iterations=sol["iterations"],
                 objective=sol["objective"], iter_per_s=round(sol["iterations"] / ts, 1))
+
+
+def mixed_leg(lpg, torch, m, n, seed, steps, stream, profile_only=False):
+    """Mixed-precision form on its own configuration (dense law, m x n): time to optimality
+    against the FP64 path on the same GPU, objective error and KKT residuals against the
+    FP64 path's optimum, and a profiled stretch of iterations for the per-kernel split."""
+    import numpy as np
+
+    import lpgen
+    A, b, c = lpgen.dense_lp(seed, m, n)
+    with torch.cuda.stream(stream):
+        dA = torch.from_numpy(A.T).to("cuda").t()
+        db = torch.from_numpy(b).cuda()
+        dc = torch.from_numpy(c).cuda()
+    torch.cuda.synchronize()
+    dev = (dA, db, dc)
+    opts = dict(iters_per_sync=16, stream=stream.cuda_stream)
+    out = {"workload": f"dense LP m={m}, n={n}, seed {seed}; FP32 shortlist top-16 re-priced in FP64, "
+                       f"FP64 reinversion every 64 pivots"}
+    sols = {}
+    for prec in (() if profile_only else ("fp64", "mixed")):
+        with lpg.LP.from_torch(*dev, precision=prec, **opts) as lp:
+            lp.solve(1)
+            lp.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = lp.solve()
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t0
+            sol = lp.solution()
+            stt = lp.stats()
+            if prec == "mixed":
+                # one reinversion of the optimal basis (the largest basis block of the solve)
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    lp.reinvert()
+                torch.cuda.synchronize()
+                reinv_opt = dict(k=int((sol["basis"] < n).sum()), ms=round((time.perf_counter() - t0) / 3 * 1e3, 3))
+        sols[prec] = sol
+        row = dict(status=lpg.STATUS_NAMES[st], seconds=round(ts, 5), iterations=sol["iterations"],
+                   iter_per_s=round(sol["iterations"] / ts, 1), objective=sol["objective"])
+        if prec == "mixed":
+            row.update(reinversions=stt["reinversions"], reinv_ms=round(stt["reinv_ms"], 3),
+                       full_fp64_prices=stt["full_prices"], reinversion_at_optimum=reinv_opt)
+        out[prec] = row
+    if sols:
+        out["speedup_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 4)
+        ref = sols["fp64"]["objective"]
+        x, y = sols["mixed"]["x"], sols["mixed"]["y"]
+        slack = b - A @ x
+        red = A.T @ y - c
+        out["error_vs_fp64"] = dict(objective_rel=abs(sols["mixed"]["objective"] - ref) / max(1.0, abs(ref)),
+                                    primal=float(max(0.0, -slack.min(), -x.min())),
+                                    dual=float(max(0.0, -red.min(), -y.min())),
+                                    gap=float(abs(c @ x - b @ y)))
+    with lpg.LP.from_torch(*dev, precision="mixed", profile=2, **opts) as lp:
+        run_steps(lp, 40)
+        torch.cuda.synchronize()
+        s0 = lp.stats()
+        run_steps(lp, steps)
+        torch.cuda.synchronize()
+        s1 = lp.stats()
+    out["kernels"] = kernel_table(s0, s1)
+    del dA, db, dc
+    return out
 
 
 def batch_leg(lpg, count, serial_sample):
@@ -159,6 +233,10 @@ def main():
     ap.add_argument("--iters-per-sync", type=int, default=16)
     ap.add_argument("--cpu-pivots", type=int, default=100, help="oracle sample size (0 = skip)")
     ap.add_argument("--batch", type=int, default=4096, help="LPs in the batched leg (0 = skip)")
+    ap.add_argument("--mixed-m", type=int, default=8000, help="rows of the mixed-precision leg (0 = skip)")
+    ap.add_argument("--mixed-n", type=int, default=16000)
+    ap.add_argument("--mixed-profile-only", action="store_true",
+                    help="only the profiled stretch of the mixed-precision form (for profiler runs)")
     ap.add_argument("--serial-sample", type=int, default=256,
                     help="LPs of the batch also solved one by one with lp_solve")
     ap.add_argument("--quick", action="store_true",
@@ -178,6 +256,14 @@ def main():
     import lpgen
     import paper_1803_04378_amd as lpg
 
+    if args.mixed_profile_only:
+        torch.cuda.set_device(0)
+        stream = torch.cuda.Stream()
+        _log(f"bench: mixed-precision profiled stretch m={args.mixed_m} n={args.mixed_n}")
+        out = mixed_leg(lpg, torch, args.mixed_m, args.mixed_n, args.seed, args.steps, stream, profile_only=True)
+        print(json.dumps({"mixed": out}), flush=True)
+        return
+
     m, n = args.m, args.n
     _log(f"bench: generating dense LP m={m} n={n} seed={args.seed}")
     A, b, c = lpgen.dense_lp(args.seed, m, n)
@@ -192,8 +278,12 @@ def main():
     opts = dict(iters_per_sync=args.iters_per_sync, stream=stream.cuda_stream)
 
     _log(f"bench: timed leg warmup={args.warmup} steps={args.steps}")
-    elapsed, kern = timed_leg(lpg, torch, dev, opts, args.warmup, args.steps, profile=1)
+    elapsed, _ = timed_leg(lpg, torch, dev, opts, args.warmup, args.steps, profile=0)
     value = args.steps / elapsed
+    # Per-kernel durations: the same iteration launched directly, each kernel with start
+    # and stop events bound to its own dispatch (no launch gaps inside the timings).
+    _log("bench: per-kernel timing leg (dispatch-bound HIP events)")
+    el2, kern = timed_leg(lpg, torch, dev, opts, args.warmup, args.steps, profile=2)
     streaming = {k: v for k, v in kern.items() if "gbs" in v}
     dominant = max(streaming, key=lambda k: streaming[k]["avg_us"]) if streaming else None
     roofline = None
@@ -206,16 +296,18 @@ def main():
                     "avg_us": kd["avg_us"]}
     iter_bytes = sum(v["bytes_per_launch"] for v in streaming.values()) if len(streaming) == 2 else None
 
-    extra = {}
+    extra = {"direct_launch_iter_per_s": round(args.steps / el2, 2)}
     if not args.quick:
-        _log("bench: direct-launch cross-check leg")
-        _, kd = timed_leg(lpg, torch, dev, opts, args.warmup, args.steps, profile=2)
-        extra["kernels_direct_launch"] = {k: v["avg_us"] for k, v in kd.items()}
-        _log("bench: unprofiled leg")
-        el0, _ = timed_leg(lpg, torch, dev, opts, args.warmup, args.steps, profile=0)
-        extra["unprofiled_iter_per_s"] = round(args.steps / el0, 2)
+        _log("bench: graph leg with event nodes around every kernel")
+        el1, k1 = timed_leg(lpg, torch, dev, opts, args.warmup, args.steps, profile=1)
+        extra["kernels_graph_events_us"] = {k: v["avg_us"] for k, v in k1.items()}
+        extra["graph_events_iter_per_s"] = round(args.steps / el1, 2)
         _log("bench: time to optimality")
         extra["solve"] = solve_leg(lpg, torch, dev, opts)
+
+    if not args.quick and args.mixed_m > 0:
+        _log(f"bench: mixed-precision leg m={args.mixed_m} n={args.mixed_n}")
+        extra["mixed"] = mixed_leg(lpg, torch, args.mixed_m, args.mixed_n, args.seed, 200, stream)
 
     if not args.quick and args.batch > 0:
         _log(f"bench: batched leg, {args.batch} LPs")

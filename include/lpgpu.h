@@ -72,8 +72,10 @@ typedef struct lp_options {
                              <= eps_t, i.e. it reaches zero with the leaving row (default 1e-9) */
   int32_t record_pivots;  /* 1 = keep the pivot log readable by lp_get_pivots (default 1) */
   int32_t profile;        /* 1 = time every kernel of the iteration with HIP event nodes in the
-                             iteration graph; 2 = launch the kernels directly on the stream with
-                             HIP events between them (no graph); 0 = off (default) */
+                             iteration graph (each time includes the launch gap before the
+                             kernel); 2 = launch the kernels directly on the stream, each with
+                             start and stop events bound to its own execution (no graph, no
+                             gap); 0 = off (default) */
   int32_t batch_small_m;  /* batched solver: LPs with m <= this get one wavefront each, larger ones a
                              whole workgroup; -1 = chosen per m-bucket by timing (default) */
   void *stream;           /* hipStream_t to run on; NULL = a stream owned by the handle */

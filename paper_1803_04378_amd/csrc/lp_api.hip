@@ -5,6 +5,7 @@
 // graph and replays it, reading back only the small control block after each replay
 // (the status scalar plus counters).  The kernels themselves stop doing work once the
 // status leaves RUNNING, so a replay that overshoots the end of the solve is harmless.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -222,7 +223,7 @@ int iteration_kernels(const lp_problem* p, IterKernel* out) {
   int c = 0;
   if (p->d.mixed) {
     out[c++] = {price32_kernel(), p->price32_grid, kPrice32Block, price32_lds_bytes(p->ld)};
-    out[c++] = {shortlist_kernel(), p->d.sl_k, 1024, shortlist_lds_bytes(p->price32_grid)};
+    out[c++] = {shortlist_kernel(), p->d.sl_k, shortlist_block(), 0};
   }
   out[c++] = {price_kernel(), p->price_grid, kPriceBlock, price_lds_bytes(p->ld)};
   out[c++] = {update_kernel(), p->update_grid, kUpdateBlock, update_lds_bytes(p->ld)};
@@ -275,25 +276,26 @@ int build_graph(lp_problem* p) {
   return LP_OK;
 }
 
-// profile = 2: the same K iterations launched directly on the stream with an event
-// before every kernel (no graph), for cross-checking the graph's events.
+// profile = 2: the same K iterations launched directly on the stream (no graph), each
+// kernel with a start and a stop event bound to its own dispatch, so that the elapsed
+// time between them is the kernel's execution alone (no launch gap).
 int launch_direct(lp_problem* p) {
   const int K = p->opt.iters_per_sync;
   IterKernel ks[5];
   const int E = iteration_kernels(p, ks);
-  if ((int)p->events.size() != E * K + 1) {
+  if ((int)p->events.size() != 2 * E * K) {
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
-    p->events.assign(E * K + 1, nullptr);
+    p->events.assign(2 * E * K, nullptr);
     for (auto& e : p->events) HIP_TRY(hipEventCreate(&e), "creating profiling events");
   }
   for (int k = 0; k < K; ++k)
     for (int i = 0; i < E; ++i) {
-      HIP_TRY(hipEventRecord(p->events[E * k + i], p->stream), "recording an event");
       void* args[] = {&p->d};
-      HIP_TRY(hipLaunchKernel(ks[i].fn, dim3(ks[i].grid), dim3(ks[i].block), args, ks[i].lds, p->stream),
+      const int ev = 2 * (E * k + i);
+      HIP_TRY(hipExtLaunchKernel(ks[i].fn, dim3(ks[i].grid), dim3(ks[i].block), args, ks[i].lds, p->stream,
+                                 p->events[ev], p->events[ev + 1], 0),
               "launching an iteration kernel");
     }
-  HIP_TRY(hipEventRecord(p->events[E * K], p->stream), "recording an event");
   return LP_OK;
 }
 
@@ -377,6 +379,9 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
     const int w32 = kPrice32Block / 64;
     p->price32_grid = (int)std::max<int64_t>(
         1, std::min<int64_t>(std::min<int64_t>((int64_t)per_cu * p->num_cu, max_price32_grid()), (N + w32 - 1) / w32));
+    // The FP64 pass runs rarely in the mixed form but is launched every iteration (and
+    // returns at once): one workgroup per CU keeps that launch cheap.
+    p->price_grid = std::min(p->price_grid, p->num_cu);
   }
 
   // Device memory: A' (ld x n) + B^-1 (m x ld) dominate.
@@ -399,7 +404,8 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   ALLOC(chat, (size_t)N);
   ALLOC(p->d.Binv, (size_t)m * ld);
   ALLOC(p->d.xB, (size_t)m);
-  ALLOC(p->d.W, (size_t)ld);
+  ALLOC(p->d.W0, (size_t)ld);
+  ALLOC(p->d.W1, (size_t)ld);
   ALLOC(p->d.rho, (size_t)ld);
   ALLOC(p->d.alpha0, (size_t)m);
   ALLOC(p->d.alpha1, (size_t)m);
@@ -420,8 +426,7 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   float* dA32 = nullptr;
   if (mixed) {
     ALLOC(dA32, (size_t)ld * std::max(n, 1));
-    ALLOC(p->d.part32_d, (size_t)p->price32_grid * kShortlist);
-    ALLOC(p->d.part32_j, (size_t)p->price32_grid * kShortlist);
+    ALLOC(p->d.part32, (size_t)p->price32_grid * kShortlist);
     ALLOC(p->d.sl_d, (size_t)kShortlist);
     ALLOC(p->d.sl_j, (size_t)kShortlist);
   }
@@ -496,6 +501,7 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   e = launch_init(p->d, p->b0, p->c0, o.sense == LP_MAX ? -1.0 : 1.0, s);
   if (e != hipSuccess) return bail(fail_hip(e, "initialising the slack basis"));
   if ((rc = read_ctrl(p)) != LP_OK) return bail(rc);
+  if (p->reinv_period > 0 && (rc = reinv_prepare(&p->rv, m, ld)) != LP_OK) return bail(rc);
   p->hc = std::move(hc);
   *out = p;
   return LP_OK;
@@ -580,9 +586,12 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
       // FP64 pricing node may have skipped itself; its bytes count only passes that ran).
       for (int k = 0; k < K; ++k) {
         float ms[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        for (int i = 0; i < E; ++i)
-          HIP_TRY(hipEventElapsedTime(&ms[i], p->events[E * k + i], p->events[E * k + i + 1]),
-                  "reading profile events");
+        for (int i = 0; i < E; ++i) {
+          // profile = 1: between the event nodes around kernel i (its launch gap
+          // included); profile = 2: the kernel's own start and stop.
+          const int a = direct ? 2 * (E * k + i) : E * k + i;
+          HIP_TRY(hipEventElapsedTime(&ms[i], p->events[a], p->events[a + 1]), "reading profile events");
+        }
         const int o = mixed ? 2 : 0;
         if (mixed) {
           p->stats.price32_ms += ms[0];
@@ -642,7 +651,7 @@ int lp_get_solution(const lp_problem* pc, double* objective, double* x, double* 
   std::vector<double> xB(m), W(m);
   std::vector<int32_t> bas(m);
   HIP_TRY(hipMemcpyAsync(xB.data(), p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
-  const double* dW = p->d.W;
+  const double* dW = p->h_ctrl->wcur ? p->d.W1 : p->d.W0;
   HIP_TRY(hipMemcpyAsync(W.data(), dW, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading W");
   HIP_TRY(hipMemcpyAsync(bas.data(), p->d.basis, sizeof(int32_t) * m, hipMemcpyDeviceToHost, p->stream),
           "reading the basis");
@@ -695,7 +704,7 @@ int lp_get_tableau(const lp_problem* pc, double* Binv, double* xB, double* W, do
             "reading B^-1");
   if (xB) HIP_TRY(hipMemcpyAsync(xB, p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
   if (W)
-    HIP_TRY(hipMemcpyAsync(W, p->d.W, sizeof(double) * m, hipMemcpyDeviceToHost,
+    HIP_TRY(hipMemcpyAsync(W, p->h_ctrl->wcur ? p->d.W1 : p->d.W0, sizeof(double) * m, hipMemcpyDeviceToHost,
                            p->stream),
             "reading W");
   HIP_TRY(hipStreamSynchronize(p->stream), "reading the tableau");

@@ -4,7 +4,8 @@
 // padding is zero and stays zero):
 //   A      ld x n   column-major: column j of A' is contiguous (pricing streams it)
 //   Binv   m x ld   row-major:    row i of B^-1 is contiguous (update + FTRAN stream it)
-//   W, rho    ld    W = chat_B^T B^-1 (top row of the Figure 1 tableau), rho = pivot row / alpha_r
+//   W0, W1, rho ld  W = chat_B^T B^-1 (top row of the Figure 1 tableau, two copies: one is
+//                   read while the next is written), rho = pivot row / alpha_r
 //   xB, alpha[2]    m
 //   chat            n + m   (minimisation costs; slacks 0)
 //   basis (m), pos (n+m), tabu_until (n+m), the leaving-side tabu list, the pivot log: int32
@@ -65,6 +66,10 @@ struct Ctrl {
   int64_t update_launches;      // update passes that ran
   int64_t update_rows_written;  // B^-1 rows those passes rewrote
   double theta;   // step length of the pending pivot
+  double pdq;     // reduced cost of the pending pivot's entering variable
+  double ar;      // pivot element alpha_r of the pending pivot
+  int32_t wcur;   // W0 or W1 holds the top row W of the tableau before the pending pivot
+  int32_t pad2;
   int64_t price32_launches;  // mixed form: FP32 screening passes that ran
   int64_t full_prices;       // mixed form: iterations whose shortlist held no improving column
   int64_t n_reinv;           // reinversions installed
@@ -77,7 +82,8 @@ struct DevLP {
   const double* chat;
   double* Binv;
   double* xB;
-  double* W;
+  double* W0;     // W ping-pong: pricing forms W + d_q rho for the pending pivot from
+  double* W1;     //   one copy and one workgroup stores it in the other
   double* rho;
   double* alpha0;
   double* alpha1;
@@ -112,13 +118,21 @@ struct DevLP {
   int32_t mixed;
   int32_t sl_k;          // shortlist length K <= kShortlist
   const float* A32;      // FP32 copy of A', same ld x n layout
-  float* part32_d;       // FP32 screening: kShortlist candidates per k_price32 workgroup,
-  int32_t* part32_j;     //   ascending in (d32, j)
+  uint64_t* part32;      // FP32 screening: kShortlist candidate keys per k_price32 workgroup,
+                         //   ascending (key = order-preserving bits of d32, then j)
   double* sl_d;          // the shortlist re-priced in FP64 (kShortlist entries; j = INT_MAX
   int32_t* sl_j;         //   marks an empty slot)
   int32_t price32_grid;  // workgroups of k_price32
   int32_t pad2;
 };
+
+// The top row W this iteration prices with: W + d_q rho of the pending pivot, which the
+// first pricing kernel of the iteration stores in the other copy, or the current copy
+// when no pivot is pending.
+__device__ __forceinline__ const double* pricing_w(const DevLP& lp) {
+  const bool other = lp.ctrl->r >= 0;
+  return (lp.ctrl->wcur != 0) != other ? lp.W1 : lp.W0;
+}
 
 // Mixed form: does the re-priced shortlist hold an improving column?  Every thread reads
 // the same entries, so all workgroups of a launch agree.
@@ -150,7 +164,7 @@ hipError_t launch_shortlist(const DevLP& lp, hipStream_t s);
 const void* price32_kernel();
 const void* shortlist_kernel();
 size_t price32_lds_bytes(int ld);
-size_t shortlist_lds_bytes(int grid32);
+int shortlist_block();
 hipError_t price32_occupancy(int* per_cu, int ld);
 int max_price32_grid();
 

@@ -2,25 +2,24 @@
 //
 // One iteration is three launches, ordered only by kernel boundaries (no grid-wide
 // fences, which cost an L2 write-back per workgroup on this part):
-//   k_price   Steps 3-4: reduced costs d_j = chat_j - W a_j of every nonbasic column,
-//             one wavefront per column of A', W staged in LDS; each workgroup leaves
-//             its lexicographic (d, j) minima over all improving and over non-tabu
-//             improving columns.
+//   k_price   Step 8 on the top row for the previous pivot (W += d_q rho, formed while
+//             staging W in LDS), then Steps 3-4: reduced costs d_j = chat_j - W a_j of
+//             every nonbasic column, one wavefront per column of A'; each workgroup
+//             leaves its lexicographic (d, j) minima over all improving and over
+//             non-tabu improving columns.
 //   k_update  every workgroup reduces those partials to the same q (Step 4), then runs
 //             the Section 3.1 update of B^-1 and x_B for the previous pivot fused with
 //             Step 5 (FTRAN, alpha = B^-1 a_q) for q: one wavefront per row of B^-1
 //             reads the row once, writes the updated row, dots it with a_q on the fly,
 //             and forms that row's ratio (Step 6); each workgroup leaves its minimum
 //             ratio and its rows within the tie bound.
-//   k_finish  one workgroup: Step 6 ties and tabu list, the scalar part of Step 8
-//             (basis, entering mask, objective, pivot log) and Step 8 on the top row
-//             (rho = B^-1[r,:] / alpha_r, W += d_q rho).
+//   k_finish  one workgroup: Step 6 ties and tabu list, then the scalar part of Step 8
+//             (basis, entering mask, objective, pivot log).
 //
 // The B^-1 update of pivot t therefore runs in the same pass as the FTRAN of pivot
 // t+1.  This is legal because pricing for t+1 needs only W_{t+1} = W_t + d_q rho_t,
-// which k_finish forms from row r of the not yet updated B^-1; it removes one full
-// read of B^-1 per iteration.  Every element still gets the same arithmetic as in
-// Step 8.
+// which needs only row r of the not yet updated B^-1; it removes one full read of
+// B^-1 per iteration.  Every element still gets the same arithmetic as in Step 8.
 //
 // Reductions are deterministic: each dot product is a fixed per-lane fma chain
 // followed by a fixed xor-butterfly, and every argmin is a lexicographic (value,
@@ -49,7 +48,8 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
     lp.Binv[k] = (i == j) ? 1.0 : 0.0;
   }
   for (size_t k = tid; k < (size_t)ld; k += stride) {
-    lp.W[k] = 0.0;
+    lp.W0[k] = 0.0;
+    lp.W1[k] = 0.0;
     lp.rho[k] = 0.0;
   }
   for (size_t i = tid; i < (size_t)m; i += stride) {
@@ -78,13 +78,18 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
 }
 
 // ---------------------------------------------------------------------------------------
-// Steps 3-4: reduced costs of every nonbasic column, W staged in LDS.
-// In the mixed form this pass runs only when the re-priced shortlist holds no improving
-// column.
+// Steps 3-4, preceded by Step 8 on the top row of the tableau for the pending pivot:
+// every workgroup forms W_new = W + d_q rho, rho = B^-1[r,:] / alpha_r, while staging it
+// into LDS (B^-1 still holds the pre-pivot rows, the row update runs in k_update);
+// workgroup 0 also stores rho and W_new for the rest of the iteration.  In the mixed
+// form k_price32 has done that already, and this pass runs only when the re-priced
+// shortlist holds no improving column.
 __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
   if (lp.ctrl->status != kStatusRunning) return;
   if (lp.mixed && shortlist_improves(lp)) return;
   const int64_t t = lp.ctrl->t;
+  const int r = lp.ctrl->r;
+  const int wc = lp.ctrl->wcur;
   extern __shared__ double2 s_w2[];
   __shared__ double red_d[2 * (kPriceBlock / 64)];
   __shared__ int red_j[2 * (kPriceBlock / 64)];
@@ -113,8 +118,29 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
     else load_batch(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
   }
 
-  const double2* W2 = reinterpret_cast<const double2*>(lp.W);
-  for (int k = threadIdx.x; k < ld2; k += kPriceBlock) s_w2[k] = W2[k];
+  if (r >= 0 && !lp.mixed) {
+    const double2* Wold = reinterpret_cast<const double2*>(wc ? lp.W1 : lp.W0);
+    const double ar = lp.ctrl->ar;
+    const double dq = lp.ctrl->pdq;
+    const double2* rowr = reinterpret_cast<const double2*>(lp.Binv + (size_t)r * lp.ld);
+    double2* Wnew = reinterpret_cast<double2*>(wc ? lp.W0 : lp.W1);
+    double2* rho2 = reinterpret_cast<double2*>(lp.rho);
+    const bool writer = blockIdx.x == 0;
+    for (int k = threadIdx.x; k < ld2; k += kPriceBlock) {
+      const double2 b = rowr[k];
+      const double2 w = Wold[k];
+      const double2 rr = make_double2(b.x / ar, b.y / ar);
+      const double2 wn = make_double2(fma(dq, rr.x, w.x), fma(dq, rr.y, w.y));
+      s_w2[k] = wn;
+      if (writer) {
+        rho2[k] = rr;
+        Wnew[k] = wn;
+      }
+    }
+  } else {
+    const double2* W2 = reinterpret_cast<const double2*>(pricing_w(lp));
+    for (int k = threadIdx.x; k < ld2; k += kPriceBlock) s_w2[k] = W2[k];
+  }
   __syncthreads();
   const double* s_w = reinterpret_cast<const double*>(s_w2);
 
@@ -287,6 +313,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
       ctl->price_launches += 1;
       if (lp.mixed) ctl->full_prices += 1;
     }
+    if (r >= 0) ctl->wcur ^= 1;  // pricing stored W_new: it is the current top row now
     ctl->verdict = status;
     ctl->q = q;
     ctl->dq = dq;
@@ -534,26 +561,14 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
     if (flags & kFlagLClear) ctl->n_lclear += 1;
     if (flags & kFlagDegenerate) ctl->n_degenerate += 1;
     ctl->t = t + 1;
-    ctl->r = r;        // pending: rows of B^-1 and x_B are pivoted by the next k_update
-    ctl->theta = thr;
+    ctl->r = r;        // pending: rows of B^-1 and x_B are pivoted by the next k_update,
+    ctl->theta = thr;  // the top row by the next pricing kernel
+    ctl->pdq = dq;
+    ctl->ar = al[r];
     ctl->cur = cur ^ 1;
     ctl->q = -1;
     ctl->flags = 0;
     ctl->verdict = -1;
-  }
-  // Step 8 on the top row of the tableau: rho = B^-1[r,:] / alpha_r from the not yet
-  // updated B^-1, then W <- W + d_q rho.  k_update applies rho to the other rows.
-  const double ar = al[r];
-  const double dq = ctl->dq;
-  const double2* rowr = reinterpret_cast<const double2*>(lp.Binv + (size_t)r * lp.ld);
-  double2* rho2 = reinterpret_cast<double2*>(lp.rho);
-  double2* W2 = reinterpret_cast<double2*>(lp.W);
-  for (int k = tid; k < lp.ld / 2; k += B) {
-    const double2 bv = rowr[k];
-    const double2 rr = make_double2(bv.x / ar, bv.y / ar);
-    const double2 w = W2[k];
-    rho2[k] = rr;
-    W2[k] = make_double2(fma(dq, rr.x, w.x), fma(dq, rr.y, w.y));
   }
 }
 

@@ -4,14 +4,14 @@
 //   k_price32    FP32 GEMV over an FP32 copy of A' (half the bytes of the FP64 pass):
 //                d32_j = chat_j - W32 . a32_j for every nonbasic, non-tabu column, and
 //                per workgroup the kShortlist smallest (d32_j, j), ascending.
-//   k_shortlist  merges those lists into the overall kShortlist smallest and re-prices
-//                the first K of them in FP64, one workgroup per candidate, with the same
-//                per-lane fma chain and butterfly as k_price, so each re-priced d_j is
-//                bit-identical to the value the FP64 pass would give that column.
+//   k_shortlist  selects the overall kShortlist smallest of those lists and re-prices
+//                the first K of them in FP64, one workgroup per candidate.
 // k_update then takes the lexicographic (d, j) minimum among improving shortlisted
 // columns.  When none improves, the FP64 pass k_price (which skips itself otherwise)
 // has priced every column, and the decision falls back to it: optimality and the
-// aspiration case of the tabu rule are therefore always decided in FP64.
+// aspiration case of the tabu rule are therefore always decided in FP64.  The re-priced
+// d_j are FP64 dot products like the FP64 pass's, summed in another order, so they agree
+// with them to rounding.
 #include "lp_device.h"
 #include "lp_wave.h"
 
@@ -27,9 +27,19 @@ namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ bool key_less(float d1, int j1, float d2, int j2) {
-  return d1 < d2 || (d1 == d2 && j1 < j2);
+// Candidate key: the FP32 reduced cost's bits mapped to an unsigned order (negative values
+// bit-inverted, others with the sign bit set) in the high word, the variable index in the
+// low word, so that one unsigned compare is the lexicographic (d32, j) order.  NaN never
+// becomes a candidate.
+__device__ __forceinline__ uint64_t make_key(float d, int j) {
+  uint32_t u = __float_as_uint(d);
+  u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((uint64_t)u << 32) | (uint32_t)j;
 }
+
+__device__ __forceinline__ int key_index(uint64_t key) { return (int)(uint32_t)key; }
+
+constexpr uint64_t kNoKey = ~0ull;
 
 __device__ __forceinline__ float wave_sum32(float a) {
 #pragma unroll
@@ -74,30 +84,51 @@ __global__ void k_convert32(const double* __restrict__ A, float* __restrict__ A3
 
 // ---------------------------------------------------------------------------------------
 // FP32 screening.  Wave gw prices columns gw, gw + nw, ... of all N = n + m variables
-// (slack j = n + i needs no GEMV: d_j = chat_j - W_i, computed in FP64 and rounded).
-// Each wave keeps its kShortlist best in lanes 0..15, sorted; the workgroup merges its
-// waves' lists by rank.  Unused slots hold (+inf, j >= N), with distinct j per slot, so
-// every key in the candidate lists is unique.
+// (slack j = n + i needs no GEMV: d_j = chat_j - W_i).  Each wave keeps its kShortlist
+// smallest keys in lanes 0..15, sorted; the workgroup merges its waves' lists by rank.
+// Unused slots are written as (+inf, N + slot), distinct per slot, so every key in the
+// candidate lists is unique.
 __global__ __launch_bounds__(kPrice32Block) void k_price32(DevLP lp) {
   if (lp.ctrl->status != kStatusRunning) return;
   constexpr int waves = kPrice32Block / 64;
   constexpr int S = kShortlist;
   extern __shared__ float4 s_w4[];
-  __shared__ float s_cd[waves * S];
-  __shared__ int s_cj[waves * S];
+  __shared__ uint64_t s_key[waves * S];
   const int64_t t = lp.ctrl->t;
+  const int r = lp.ctrl->r;
+  const int wc = lp.ctrl->wcur;
   const int n = lp.n, N = lp.n + lp.m, n4 = lp.ld / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int gw = blockIdx.x * waves + wave;
   const int nw = gridDim.x * waves;
 
-  for (int k = threadIdx.x; k < lp.ld; k += kPrice32Block) reinterpret_cast<float*>(s_w4)[k] = (float)lp.W[k];
+  // Step 8 on the top row for the pending pivot, as in k_price: W_new = W + d_q rho is
+  // formed in FP64 and staged rounded to FP32; workgroup 0 stores rho and W_new.
+  float* s_w = reinterpret_cast<float*>(s_w4);
+  if (r >= 0) {
+    const double* Wold = wc ? lp.W1 : lp.W0;
+    double* Wnew = wc ? lp.W0 : lp.W1;
+    const double ar = lp.ctrl->ar;
+    const double dq = lp.ctrl->pdq;
+    const double* rowr = lp.Binv + (size_t)r * lp.ld;
+    const bool writer = blockIdx.x == 0;
+    for (int k = threadIdx.x; k < lp.ld; k += kPrice32Block) {
+      const double rr = rowr[k] / ar;
+      const double wn = fma(dq, rr, Wold[k]);
+      s_w[k] = (float)wn;
+      if (writer) {
+        lp.rho[k] = rr;
+        Wnew[k] = wn;
+      }
+    }
+  } else {
+    const double* W = wc ? lp.W1 : lp.W0;
+    for (int k = threadIdx.x; k < lp.ld; k += kPrice32Block) s_w[k] = (float)W[k];
+  }
   __syncthreads();
 
-  float kd = __builtin_inff();
-  int kj = INT_MAX;
-  float worst_d = __builtin_inff();
-  int worst_j = INT_MAX;
+  uint64_t key = kNoKey;  // lane l < S: the wave's l-th smallest key
+  uint64_t worst = kNoKey;
   for (int j = gw; j < N; j += nw) {
     if (lp.pos[j] >= 0 || lp.tabu_until[j] >= t) continue;
     float d;
@@ -105,33 +136,23 @@ __global__ __launch_bounds__(kPrice32Block) void k_price32(DevLP lp) {
       const float s = wave_dot32(reinterpret_cast<const float4*>(lp.A32 + (size_t)j * lp.ld), s_w4, n4, lane);
       d = (float)lp.chat[j] - s;
     } else {
-      d = (float)(lp.chat[j] - lp.W[j - n]);
+      d = (float)lp.chat[j] - s_w[j - n];
     }
-    if (!key_less(d, j, worst_d, worst_j)) continue;
-    // Insert (d, j) at its rank among lanes 0..S-1; the lanes after it shift up by one.
-    const bool before = lane < S && key_less(kd, kj, d, j);
-    const int at = __popcll(__ballot(before));
-    const float ud = __shfl_up(kd, 1);
-    const int uj = __shfl_up(kj, 1);
-    if (lane == at) {
-      kd = d;
-      kj = j;
-    } else if (lane > at && lane < S) {
-      kd = ud;
-      kj = uj;
-    }
-    worst_d = __shfl(kd, S - 1);
-    worst_j = __shfl(kj, S - 1);
+    if (d != d) continue;
+    const uint64_t kn = make_key(d, j);
+    if (kn >= worst) continue;
+    // Insert at its rank among lanes 0..S-1; the lanes after it shift up by one.
+    const int at = __popcll(__ballot(lane < S && key < kn));
+    const uint64_t up = __shfl_up(key, 1);
+    if (lane == at) key = kn;
+    else if (lane > at && lane < S) key = up;
+    worst = __shfl(key, S - 1);
   }
-  if (lane < S) {
-    s_cd[wave * S + lane] = kd;
-    s_cj[wave * S + lane] = kj;
-  }
+  if (lane < S) s_key[wave * S + lane] = key;
   __syncthreads();
   if (threadIdx.x < waves * S) {
     const int w = threadIdx.x / S, l = threadIdx.x % S;
-    const float d = s_cd[threadIdx.x];
-    const int j = s_cj[threadIdx.x];
+    const uint64_t k0 = s_key[threadIdx.x];
     // Rank in the union: own position plus, per other wave, the entries before it; equal
     // keys (empty slots) are ordered by wave.
     int rank = l;
@@ -140,106 +161,152 @@ __global__ __launch_bounds__(kPrice32Block) void k_price32(DevLP lp) {
       int lo = 0, hi = S;
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        const float d2 = s_cd[w2 * S + mid];
-        const int j2 = s_cj[w2 * S + mid];
-        const bool prec = key_less(d2, j2, d, j) || (d2 == d && j2 == j && w2 < w);
-        if (prec) lo = mid + 1;
+        const uint64_t k2 = s_key[w2 * S + mid];
+        if (k2 < k0 || (k2 == k0 && w2 < w)) lo = mid + 1;
         else hi = mid;
       }
       rank += lo;
     }
     if (rank < S) {
       const int slot = blockIdx.x * S + rank;
-      lp.part32_d[slot] = d;
-      lp.part32_j[slot] = j < N ? j : N + slot;
+      lp.part32[slot] = k0 != kNoKey ? k0 : make_key(__builtin_inff(), N + slot);
     }
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// Merge of the k_price32 lists (every workgroup, redundantly) and the FP64 re-price of
-// candidate blockIdx.x.  The lists are merged pairwise in LDS: an entry's rank in the
-// merged pair is its position plus the number of entries of the other list below it
-// (keys are unique), and only ranks below kShortlist are kept.
-constexpr int kShortlistBlock = 1024;
-constexpr int kMergeTasks = 8;  // merge tasks per thread at the widest level (512 lists)
-constexpr int kMaxLists = kShortlistBlock * kMergeTasks / kShortlist;
+// Overall shortlist and its FP64 re-price (every workgroup selects, workgroup w re-prices
+// candidate w).  The kShortlist smallest keys of all lists lie in the kShortlist lists
+// with the smallest heads: if T is the kShortlist-th smallest head, those heads are
+// kShortlist keys <= T, so every key of the overall shortlist is <= T, and any list
+// whose head exceeds T holds only larger keys.  All lists are loaded into LDS at once;
+// each wavefront sorts 64 heads with a bitonic network in registers, the waves' 16
+// smallest heads are ranked by binary search to pick the lists, and the entries of those
+// lists are ranked the same way (keys are unique, so ranks are distinct).
+constexpr int kShortlistBlock = 512;
+constexpr int kMaxLists = kShortlistBlock;
+
+// Entries of a sorted list of kShortlist (= 16) keys below key: a fixed five-read search.
+__device__ __forceinline__ int count_below(const uint64_t* list, uint64_t key) {
+  int pos = 0;
+  pos += list[pos + 7] < key ? 8 : 0;
+  pos += list[pos + 3] < key ? 4 : 0;
+  pos += list[pos + 1] < key ? 2 : 0;
+  pos += list[pos] < key ? 1 : 0;
+  pos += list[pos] < key ? 1 : 0;  // only when pos == 15 can this add
+  return pos;
+}
+static_assert(kShortlist == 16, "count_below is written for lists of 16");
+
+// Elements of a W-length vector one thread of k_shortlist holds (ld / 2 double2 over the
+// block, ld <= LP_MAX_ROWS rounded up to 8).
+constexpr int kShortlistPer = (10112 / 2 + kShortlistBlock - 1) / kShortlistBlock;
 
 __global__ __launch_bounds__(kShortlistBlock) void k_shortlist(DevLP lp) {
-  if (lp.ctrl->status != kStatusRunning) return;
+  // The control fields, W and the candidate lists are loaded up front so that their
+  // latencies overlap; only the entering column waits for the selection.
+  const Ctrl* ctl = lp.ctrl;
+  const int status = ctl->status, r = ctl->r, wc = ctl->wcur;
+  if (status != kStatusRunning) return;
   constexpr int S = kShortlist;
-  extern __shared__ float s_md[];
-  const int G = lp.price32_grid;
-  int L = 1;
-  while (L < G) L <<= 1;
-  int* s_mj = reinterpret_cast<int*>(s_md + L * S);
-  const int N = lp.n + lp.m;
-  const int tid = threadIdx.x;
-  for (int k = tid; k < L * S; k += kShortlistBlock) {
-    if (k < G * S) {
-      s_md[k] = lp.part32_d[k];
-      s_mj[k] = lp.part32_j[k];
-    } else {
-      s_md[k] = __builtin_inff();
-      s_mj[k] = N + k;
+  constexpr int W = kShortlistBlock / 64;
+  __shared__ uint64_t s_all[kMaxLists * S];
+  __shared__ uint64_t s_wh[W * S];
+  __shared__ int s_wg[W * S];
+  __shared__ int s_sel[S];
+  __shared__ int s_top[S];
+  __shared__ double s_red[W];
+  const int G = lp.price32_grid, N = lp.n + lp.m, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int ld2 = lp.ld / 2;
+  const double* Wc = (wc != 0) != (r >= 0) ? lp.W1 : lp.W0;  // pricing_w, from the loads above
+  double2 wv[kShortlistPer];
+#pragma unroll
+  for (int u = 0; u < kShortlistPer; ++u) {
+    const int k = tid + u * kShortlistBlock;
+    wv[u] = k < ld2 ? reinterpret_cast<const double2*>(Wc)[k] : make_double2(0.0, 0.0);
+  }
+  for (int e = tid; e < G * S; e += kShortlistBlock) s_all[e] = lp.part32[e];
+  if (tid < S) s_sel[tid] = -1;
+  __syncthreads();
+  // Bitonic sort of this wave's 64 heads (ascending), each carrying its list index.
+  const int g0 = wave * 64 + lane;
+  uint64_t key = g0 < G ? s_all[g0 * S] : kNoKey;
+  int g = g0;
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t ok = __shfl_xor(key, j);
+      const int og = __shfl_xor(g, j);
+      const bool up = (lane & k) == 0;
+      const bool low = (lane & j) == 0;
+      const bool take_other = (low == up) ? (ok < key) : (ok > key);
+      if (take_other) {
+        key = ok;
+        g = og;
+      }
     }
+  }
+  if (lane < S) {
+    s_wh[wave * S + lane] = key;
+    s_wg[wave * S + lane] = g;
   }
   __syncthreads();
-  for (int len = L; len > 1; len >>= 1) {
-    const int tasks = (len >> 1) * 2 * S;
-    float od[kMergeTasks];
-    int oj[kMergeTasks], oat[kMergeTasks];
-#pragma unroll
-    for (int u = 0; u < kMergeTasks; ++u) {
-      oat[u] = -1;
-      const int e = tid + u * kShortlistBlock;
-      if (e < tasks) {
-        const int p = e / (2 * S), side = (e / S) & 1, idx = e % S;
-        const int mine = (2 * p + side) * S, other = (2 * p + 1 - side) * S;
-        const float d = s_md[mine + idx];
-        const int j = s_mj[mine + idx];
-        int lo = 0, hi = S;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (key_less(s_md[other + mid], s_mj[other + mid], d, j)) lo = mid + 1;
-          else hi = mid;
-        }
-        const int rank = idx + lo;
-        if (rank < S) {
-          od[u] = d;
-          oj[u] = j;
-          oat[u] = p * S + rank;
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kMergeTasks; ++u)
-      if (oat[u] >= 0) {
-        s_md[oat[u]] = od[u];
-        s_mj[oat[u]] = oj[u];
-      }
-    __syncthreads();
+  if (tid < W * S) {
+    const uint64_t k0 = s_wh[tid];
+    int rank = tid % S;
+    for (int w2 = 0; w2 < W; ++w2)
+      if (w2 != tid / S) rank += count_below(s_wh + w2 * S, k0);
+    if (rank < S && k0 != kNoKey) s_sel[rank] = s_wg[tid];
   }
-  // FP64 re-price of candidate w by wave 0 (identical arithmetic to k_price).
+  __syncthreads();
+  if (tid < S * S) {
+    const int l = tid / S, idx = tid % S;
+    const int gl = s_sel[l];
+    if (gl >= 0) {
+      const uint64_t k0 = s_all[gl * S + idx];
+      int rank = idx;
+      for (int l2 = 0; l2 < S; ++l2)
+        if (l2 != l && s_sel[l2] >= 0) rank += count_below(s_all + s_sel[l2] * S, k0);
+      if (rank < S) s_top[rank] = key_index(k0);
+    }
+  }
+  // The selected lists hold at least S keys (one list has S), so every s_top slot is set.
+  __syncthreads();
+  // FP64 re-price of candidate w with the whole workgroup: thread t sums elements
+  // t, t + 512, ... in an fma chain, then a fixed-order reduction.
   const int w = blockIdx.x;
-  if (tid >= 64) return;
-  const int lane = tid;
-  const int j = s_mj[w];
-  double d = __builtin_inf();
-  int jj = INT_MAX;
-  if (j < N) {
-    jj = j;
-    if (j < lp.n) {
-      double2 v[kBatch];
-      const double s = wave_dot<false>(reinterpret_cast<const double2*>(lp.A + (size_t)j * lp.ld),
-                                       reinterpret_cast<const double2*>(lp.W), lp.ld / 2, lane, v, false);
-      d = lp.chat[j] - s;
-    } else {
-      d = lp.chat[j] - lp.W[j - lp.n];
+  const int j = s_top[w];
+  const double chat_j = j < N ? lp.chat[j] : 0.0;
+  const double w_slack = (j >= lp.n && j < N) ? Wc[j - lp.n] : 0.0;
+  double acc = 0.0;
+  if (j < lp.n) {
+    const double2* a2 = reinterpret_cast<const double2*>(lp.A + (size_t)j * lp.ld);
+    double2 av[kShortlistPer];
+#pragma unroll
+    for (int u = 0; u < kShortlistPer; ++u) {
+      const int k = tid + u * kShortlistBlock;
+      av[u] = k < ld2 ? a2[k] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kShortlistPer; ++u) {
+      acc = fma(av[u].x, wv[u].x, acc);
+      acc = fma(av[u].y, wv[u].y, acc);
     }
   }
-  if (lane == 0) {
+  acc = wave_sum(acc);
+  if (lane == 0) s_red[wave] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double sdot = 0.0;
+    for (int k = 0; k < W; ++k) sdot += s_red[k];
+    double d = __builtin_inf();
+    int jj = INT_MAX;
+    if (j < N) {
+      jj = j;
+      d = j < lp.n ? chat_j - sdot : chat_j - w_slack;
+    }
     lp.sl_d[w] = d;
     lp.sl_j[w] = jj;
   }
@@ -254,11 +321,7 @@ hipError_t launch_convert32(const double* A, float* A32, size_t count, hipStream
 
 size_t price32_lds_bytes(int ld) { return sizeof(float) * (size_t)ld; }
 
-size_t shortlist_lds_bytes(int grid32) {
-  int L = 1;
-  while (L < grid32) L <<= 1;
-  return (sizeof(float) + sizeof(int)) * (size_t)L * kShortlist;
-}
+int shortlist_block() { return kShortlistBlock; }
 
 int max_price32_grid() { return kMaxLists; }
 
@@ -268,8 +331,7 @@ hipError_t launch_price32(const DevLP& lp, int grid, hipStream_t s) {
 }
 
 hipError_t launch_shortlist(const DevLP& lp, hipStream_t s) {
-  hipLaunchKernelGGL(k_shortlist, dim3(lp.sl_k), dim3(kShortlistBlock), shortlist_lds_bytes(lp.price32_grid), s,
-                     lp);
+  hipLaunchKernelGGL(k_shortlist, dim3(lp.sl_k), dim3(kShortlistBlock), 0, s, lp);
   return hipGetLastError();
 }
 

@@ -15,6 +15,9 @@ struct ReinvState;  // grow-only work buffers and the BLAS handle of one LP hand
 // a numerically singular basis block is not an error: the device state is then left as
 // it was and Ctrl::n_reinv_failed counts it.
 int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s, int* k_out);
+// Creates the work state and the BLAS handle (loading the BLAS kernels once per process)
+// and allocates the work memory of small basis blocks for an LP with m rows.
+int reinv_prepare(ReinvState** state, int m, int ld);
 void reinv_free(ReinvState* state);
 
 }  // namespace lpgpu

@@ -6,11 +6,15 @@
 //         [ B21  I ],            [ -B21 B11^-1    I ],
 // with B11 = A'[R, K] (order k = |K| = |R|) and B21 = A'[S, K].  Only B11 is factorised:
 //   1. gather G = [B11^T | B21^T] (k x m, column-major) from A';
-//   2. LU with partial pivoting of M = B11^T, blocked right-looking: each panel is
-//      factorised by one workgroup holding the panel in registers (the pivot search is a
-//      chain of k dependent reductions, so it stays inside one workgroup), a second kernel
-//      applies the panel's row interchanges to the other columns and forms
-//      U12 = L11^-1 A12, and the trailing update A22 -= L21 U12 is a DGEMM;
+//   2. LU with partial pivoting of M = B11^T, blocked right-looking on two levels.  An
+//      outer panel of kOuter columns is factorised by narrow inner panels: each inner
+//      panel by one workgroup holding it in registers (the pivot search is a chain of
+//      dependent reductions, so it stays inside one workgroup), then a second kernel
+//      applies its row interchanges and U12 = L11^-1 A12 within the outer panel, and a
+//      DGEMM updates the rest of the outer panel.  The outer panel's interchanges are
+//      then applied to the columns outside it at once, U12 of the outer panel is a
+//      triangular solve, and the trailing update A22 -= L21 U12 one DGEMM of depth
+//      kOuter, so the trailing matrix is streamed once per kOuter columns;
 //   3. X = M^-1 = U^-1 L^-1 P (two triangular solves on X = P), so that row b of B11^-1
 //      is column b of X, contiguous;
 //   4. C^T = -X B21^T (DGEMM): row s of -B21 B11^-1 is column s of C^T;
@@ -18,10 +22,16 @@
 //      and z = chat_B^T x_B from X and C^T.
 // The DGEMMs and triangular solves are rocBLAS calls on the handle's stream (atomics off,
 // so results are reproducible); everything else is below.
+//
+// Small blocks (k <= kSmallK, the common case: the optimal bases of the dense law hold a
+// few hundred structural columns at most) take a shorter path with no library call: one
+// workgroup inverts B11^T in LDS by Gauss-Jordan elimination with partial pivoting, and
+// the rows -B21 B11^-1 are formed inside the kernel that writes B^-1.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,7 +54,7 @@ struct ReinvState {
   size_t part_cap = 0;
   int32_t* idx = nullptr;  // kcol (k) | kpos (k) | rowlist (m) | rinfo (m) | colmap (ld)
   size_t idx_cap = 0;
-  int32_t* aux = nullptr;  // rowperm (m) | interchange list (kPairs dst, kPairs src, count) | info
+  int32_t* aux = nullptr;  // rowperm (m) | opos (m) | inner list | outer list | info
   size_t aux_cap = 0;
   int32_t* h_idx = nullptr;  // pinned
   size_t h_idx_cap = 0;
@@ -54,7 +64,9 @@ struct ReinvState {
 
 namespace {
 
-constexpr int kPairs = 64;  // row interchanges of one panel touch at most 2 * 32 rows
+constexpr int kPairs = 64;        // row moves of one inner panel (at most 2 * 16 rows), room to spare
+constexpr int kOuter = 128;       // outer panel width
+constexpr int kOuterPairs = 2 * kOuter;
 constexpr int kRowPanelThreads = 256;
 constexpr int kWChunk = 64;  // b-range of one partial sum of W
 
@@ -78,224 +90,281 @@ __global__ void k_gather(const double* __restrict__ A, int ld, const int32_t* __
   }
 }
 
-__global__ void k_reinv_setup(int32_t* rowperm, int k, int32_t* info) {
+__global__ void k_reinv_setup(int32_t* rowperm, int32_t* opos, int k, int32_t* info) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < k) rowperm[i] = i;
+  if (i < k) {
+    rowperm[i] = i;
+    opos[i] = i;
+  }
   if (i == 0) *info = 0;
 }
 
-// Factorises the panel M[j0:k, j0:j0+jb] in place (jb <= JB): thread t of NT holds rows
-// t, t + NT, ... (relative to j0) of the panel in registers.  Each column: the pivot is
-// the row of largest |value| at or below the diagonal (lowest row on ties), rows c and p
-// are exchanged through LDS, and the rows below are eliminated.  Rows keep a tag of the
-// row they started the panel in; at the end the moved rows are listed as (dst, src)
-// pairs for k_lu_rowpanel.  A zero (or NaN) pivot column sets *info.
-template <int NT, int JB>
-struct PanelShared {
-  double u[JB], w[JB];
-  double red_v[NT / 64];
-  int red_i[NT / 64];
-  int uo, wo, np;
-};
-
-// Column C of the panel; the column index is a template argument so that every access to
-// the register-held rows is static.
-template <int NT, int RPT, int JB, int C>
-__device__ __forceinline__ void lu_column(double (&a)[RPT][JB], int (&org)[RPT], PanelShared<NT, JB>& sh, int R,
-                                          int jb, bool& singular) {
-  if constexpr (C < JB) {
-    if (C < jb) {
-      constexpr int W = NT / 64;
-      const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-      double bv = -1.0;
-      int bi = INT_MAX;
-#pragma unroll
-      for (int s = 0; s < RPT; ++s) {
-        const int rho = tid + s * NT;
-        if (rho >= C && rho < R) {
-          const double v = fabs(a[s][C]);
-          if (v > bv) {
-            bv = v;
-            bi = rho;
-          }
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > bv || (ov == bv && oi < bi)) {
-          bv = ov;
-          bi = oi;
-        }
-      }
-      if (lane == 0) {
-        sh.red_v[wave] = bv;
-        sh.red_i[wave] = bi;
-      }
-      __syncthreads();
-      bv = sh.red_v[0];
-      bi = sh.red_i[0];
-#pragma unroll
-      for (int w = 1; w < W; ++w) {
-        const double ov = sh.red_v[w];
-        const int oi = sh.red_i[w];
-        if (ov > bv || (ov == bv && oi < bi)) {
-          bv = ov;
-          bi = oi;
-        }
-      }
-      const bool ok = bv > 0.0;
-      if (!ok) singular = true;
-      const int p = ok ? bi : C;
-      // Row p to LDS.  Selects over every slot (rather than a branch on the owning slot)
-      // keep all register indices static.
-      {
-        double uv[JB];
-        int uo = 0;
-        bool mine = false;
-#pragma unroll
-        for (int cc = 0; cc < JB; ++cc) uv[cc] = 0.0;
-#pragma unroll
-        for (int s = 0; s < RPT; ++s) {
-          const bool hit = tid + s * NT == p;
-#pragma unroll
-          for (int cc = 0; cc < JB; ++cc) uv[cc] = hit ? a[s][cc] : uv[cc];
-          uo = hit ? org[s] : uo;
-          mine = mine || hit;
-        }
-        if (mine) {
-#pragma unroll
-          for (int cc = 0; cc < JB; ++cc) sh.u[cc] = uv[cc];
-          sh.uo = uo;
-        }
-      }
-      if (tid == C) {  // row C < JB is slot 0 of thread C
-#pragma unroll
-        for (int cc = 0; cc < JB; ++cc) sh.w[cc] = a[0][cc];
-        sh.wo = org[0];
-      }
-      __syncthreads();
-      if (p != C) {
-#pragma unroll
-        for (int s = 0; s < RPT; ++s) {
-          const bool hit = tid + s * NT == p;
-#pragma unroll
-          for (int cc = 0; cc < JB; ++cc) a[s][cc] = hit ? sh.w[cc] : a[s][cc];
-          org[s] = hit ? sh.wo : org[s];
-        }
-        if (tid == C) {
-#pragma unroll
-          for (int cc = 0; cc < JB; ++cc) a[0][cc] = sh.u[cc];
-          org[0] = sh.uo;
-        }
-      }
-      // Multipliers by one reciprocal of the pivot (as LAPACK's unblocked LU does).
-      const double rpiv = 1.0 / sh.u[C];
-#pragma unroll
-      for (int s = 0; s < RPT; ++s) {
-        const int rho = tid + s * NT;
-        if (rho > C && rho < R) {
-          const double l = a[s][C] * rpiv;
-          a[s][C] = l;
-#pragma unroll
-          for (int cc = C + 1; cc < JB; ++cc) a[s][cc] = fma(-l, sh.u[cc], a[s][cc]);
-        }
-      }
-      __syncthreads();
-    }
-    lu_column<NT, RPT, JB, C + 1>(a, org, sh, R, jb, singular);
-  }
-}
-
+// Factorises the panel M[j0:k, j0:j0+jb] in place (jb <= JB) with partial pivoting.
+// Thread t of NT holds rows t, t + NT, ... (relative to j0) in registers, and rows stay
+// where they are during the elimination: at column c the pivot is the not yet chosen row
+// of largest |value| (lowest row on ties), its remaining entries are broadcast through
+// LDS, and every other unchosen row is eliminated.  Each row keeps its unprocessed
+// columns in a[] and its finished entries (multipliers, or its U row once chosen) in h[],
+// both shifted by one position per column so that every register index is static and
+// the column loop stays compact.  At the end the rows are written to their final places
+// (the c-th pivot row to row c of the panel; rows displaced from the top to the places the
+// pivot rows left), and the moves are listed as (dst, src) pairs for k_lu_rowpanel.  A
+// zero pivot column sets *info.
 template <int NT, int RPT, int JB>
 __global__ __launch_bounds__(NT) void k_lu_panel(double* __restrict__ M, int ld, int k, int j0, int jb,
                                                  int32_t* __restrict__ pairs, int32_t* __restrict__ info) {
-  __shared__ PanelShared<NT, JB> sh;
-  const int R = k - j0, tid = threadIdx.x;
-  double a[RPT][JB];
-  int org[RPT];
+  constexpr int W = NT / 64;
+  __shared__ double s_u[JB];
+  __shared__ double red_v[W];
+  __shared__ int red_i[W];
+  __shared__ int s_piv[JB];
+  __shared__ int s_dst[2 * JB], s_src[2 * JB];
+  __shared__ int s_np;
+  const int R = k - j0, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double a[RPT][JB], h[RPT][JB];
+  bool done[RPT];
 #pragma unroll
   for (int s = 0; s < RPT; ++s) {
     const int rho = tid + s * NT;
-    org[s] = rho;
+    done[s] = rho >= R;
 #pragma unroll
-    for (int c = 0; c < JB; ++c)
+    for (int c = 0; c < JB; ++c) {
       a[s][c] = (rho < R && c < jb) ? M[(size_t)(j0 + rho) + (size_t)(j0 + c) * ld] : 0.0;
-  }
-  if (tid == 0) sh.np = 0;
-  bool singular = false;
-  lu_column<NT, RPT, JB, 0>(a, org, sh, R, jb, singular);
-  // Opaque copies: the store addresses are formed here, not kept live from the loads.
-  int tid2 = tid, ld2 = ld;
-  asm volatile("" : "+v"(tid2));
-  asm volatile("" : "+s"(ld2));
-#pragma unroll
-  for (int s = 0; s < RPT; ++s) {
-    const int rho = tid2 + s * NT;
-    if (rho < R) {
-#pragma unroll
-      for (int c = 0; c < JB; ++c)
-        if (c < jb) M[(size_t)(j0 + rho) + (size_t)(j0 + c) * ld2] = a[s][c];
-      if (org[s] != rho) {
-        const int q = atomicAdd(&sh.np, 1);
-        pairs[q] = j0 + rho;
-        pairs[kPairs + q] = j0 + org[s];
-      }
+      h[s][c] = 0.0;
     }
   }
-  __syncthreads();
+  bool singular = false;
+  for (int c = 0; c < jb; ++c) {
+    double bv = -1.0;
+    int bi = INT_MAX;
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      double v = fabs(a[s][0]);
+      v = v == v ? v : 0.0;  // a NaN never wins (and signals a singular block below)
+      if (!done[s] && v > bv) {
+        bv = v;
+        bi = tid + s * NT;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      red_v[wave] = bv;
+      red_i[wave] = bi;
+    }
+    __syncthreads();
+    bv = red_v[0];
+    bi = red_i[0];
+#pragma unroll
+    for (int w = 1; w < W; ++w) {
+      const double ov = red_v[w];
+      const int oi = red_i[w];
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (!(bv > 0.0)) singular = true;
+    const int p = bi;  // an unchosen row always exists: R - c >= 1
+    // Selects rather than branches on the owning slot keep the register rows from being
+    // copied at branch joins.
+    {
+      double uv[JB];
+#pragma unroll
+      for (int i = 0; i < JB; ++i) uv[i] = 0.0;
+      bool mine = false;
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) {
+        const bool hit = tid + s * NT == p;
+#pragma unroll
+        for (int i = 0; i < JB; ++i) uv[i] = hit ? a[s][i] : uv[i];
+        done[s] = done[s] || hit;
+        mine = mine || hit;
+      }
+      if (mine) {
+#pragma unroll
+        for (int i = 0; i < JB; ++i) s_u[i] = uv[i];
+      }
+    }
+    if (tid == 0) s_piv[c] = p;
+    __syncthreads();
+    const double rpiv = 1.0 / s_u[0];  // one reciprocal per pivot, as LAPACK's unblocked LU
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const bool elim = !done[s];
+      const double l = elim ? a[s][0] * rpiv : a[s][0];
+#pragma unroll
+      for (int i = 1; i < JB; ++i) {
+        const double upd = fma(-l, s_u[i], a[s][i]);
+        a[s][i] = elim ? upd : a[s][i];
+      }
+#pragma unroll
+      for (int i = 0; i + 1 < JB; ++i) {
+        a[s][i] = a[s][i + 1];
+        h[s][i] = h[s][i + 1];
+      }
+      a[s][JB - 1] = 0.0;
+      h[s][JB - 1] = l;
+    }
+    __syncthreads();
+  }
+  // Align the history so that h[c] holds column c (a narrower last panel shifted jb times).
+  for (int x = jb; x < JB; ++x) {
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+#pragma unroll
+      for (int i = 0; i + 1 < JB; ++i) h[s][i] = h[s][i + 1];
+      h[s][JB - 1] = 0.0;
+    }
+  }
+  // Final places: position c receives pivot row p_c; the rows of the top jb that were not
+  // chosen fill, in ascending order, the places of the chosen rows from below the top.
   if (tid == 0) {
-    pairs[2 * kPairs] = sh.np;
+    int np = 0;
+    bool top_chosen[JB];
+#pragma unroll
+    for (int i = 0; i < JB; ++i) top_chosen[i] = false;
+    for (int c = 0; c < jb; ++c) {
+      const int pc = s_piv[c];
+#pragma unroll
+      for (int i = 0; i < JB; ++i)
+        if (i == pc) top_chosen[i] = true;
+      if (pc != c) {
+        s_dst[np] = c;
+        s_src[np] = pc;
+        ++np;
+      }
+    }
+    int cv = 0;
+#pragma unroll
+    for (int i = 0; i < JB; ++i) {
+      if (i >= jb || top_chosen[i]) continue;
+      while (cv < jb && s_piv[cv] < jb) ++cv;  // next chosen row from below the top
+      if (cv >= jb) break;  // cannot happen: as many such rows as unchosen top rows
+      s_dst[np] = s_piv[cv];
+      s_src[np] = i;
+      ++np;
+      ++cv;
+    }
+    s_np = np;
+  }
+  __syncthreads();
+  const int np = s_np;
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int rho = tid + s * NT;
+    if (rho >= R) continue;
+    int dst = rho;
+    for (int q = 0; q < np; ++q)
+      if (s_src[q] == rho) dst = s_dst[q];
+#pragma unroll
+    for (int c = 0; c < JB; ++c)
+      if (c < jb) M[(size_t)(j0 + dst) + (size_t)(j0 + c) * ld] = h[s][c];
+  }
+  if (tid < np) {
+    pairs[tid] = j0 + s_dst[tid];
+    pairs[kPairs + tid] = j0 + s_src[tid];
+  }
+  if (tid == 0) {
+    pairs[2 * kPairs] = np;
     if (singular) *info = 1;
   }
 }
 
-// The panel's row interchanges applied to every column outside the panel and to the row
-// permutation (the extra last "column"), then U12 = L11^-1 A12 by forward substitution
-// (unit lower L11 staged in LDS) for the columns right of the panel.  One wavefront per
-// column: lane q moves interchange pair q, and lane r holds row j0 + r of the column
-// during the substitution.
+// A row permutation given as (dst, src) pairs (row dst receives the row that was at src;
+// np <= 4 * 64 pairs) applied to the columns c in [c_lo, c_hi) outside [skip_lo, skip_hi)
+// and to the integer vector perm (the extra last "column"), then, for the columns from
+// u_lo on, U12 = L11^-1 A12 by forward substitution with the unit lower L11 =
+// M[j0:j0+jb, j0:j0+jb] (jb <= 32, staged in LDS).  One wavefront per column: lane q moves
+// pairs q, q + 64, ..., and lane r holds row j0 + r during the substitution.
 constexpr int kRowPanelWaves = kRowPanelThreads / 64;
 
-__global__ __launch_bounds__(kRowPanelThreads) void k_lu_rowpanel(double* __restrict__ M, int ld, int k, int j0,
-                                                                  int jb, const int32_t* __restrict__ pairs,
-                                                                  int32_t* __restrict__ rowperm) {
+__global__ __launch_bounds__(kRowPanelThreads) void k_lu_rowpanel(double* __restrict__ M, int ld, int c_lo, int c_hi,
+                                                                  int skip_lo, int skip_hi, int u_lo, int j0, int jb,
+                                                                  const int32_t* __restrict__ pairs, int cap,
+                                                                  int32_t* __restrict__ perm) {
   __shared__ double s_l[32 * 32];
-  const int np = pairs[2 * kPairs];
-  for (int e = threadIdx.x; e < 32 * 32; e += kRowPanelThreads) {
-    const int r = e / 32, c = e % 32;
-    s_l[e] = (c < r && r < jb) ? M[(size_t)(j0 + r) + (size_t)(j0 + c) * ld] : 0.0;
+  const int np = pairs[2 * cap];
+  if (u_lo < c_hi) {
+    for (int e = threadIdx.x; e < 32 * 32; e += kRowPanelThreads) {
+      const int r = e / 32, c = e % 32;
+      s_l[e] = (c < r && r < jb) ? M[(size_t)(j0 + r) + (size_t)(j0 + c) * ld] : 0.0;
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int dst = lane < np ? pairs[lane] : 0;
-  const int src = lane < np ? pairs[kPairs + lane] : 0;
-  const int ncols = k - jb + 1;
+  int dst[4], src[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int q = lane + 64 * u;
+    dst[u] = q < np ? pairs[q] : 0;
+    src[u] = q < np ? pairs[cap + q] : 0;
+  }
+  const int nskip = skip_hi - skip_lo;
+  const int ncols = c_hi - c_lo - nskip + 1;
   const int gw = blockIdx.x * kRowPanelWaves + (threadIdx.x >> 6);
   const int nw = gridDim.x * kRowPanelWaves;
   for (int e = gw; e < ncols; e += nw) {
     if (e == ncols - 1) {
-      const int v = lane < np ? rowperm[src] : 0;
+      int v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (lane + 64 * u < np) v[u] = perm[src[u]];
       __builtin_amdgcn_wave_barrier();
-      if (lane < np) rowperm[dst] = v;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (lane + 64 * u < np) perm[dst[u]] = v[u];
       continue;
     }
-    const int col = e < j0 ? e : e + jb;
+    int col = c_lo + e;
+    if (col >= skip_lo) col += nskip;
     double* colp = M + (size_t)col * ld;
-    const double v = lane < np ? colp[src] : 0.0;
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (lane + 64 * u < np) v[u] = colp[src[u]];
     __builtin_amdgcn_wave_barrier();
-    if (lane < np) colp[dst] = v;
-    if (col >= j0 + jb) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (lane + 64 * u < np) colp[dst[u]] = v[u];
+    if (col >= u_lo) {
       // Reads after this wave's own writes above: same wavefront, program order.
-      double u = lane < jb ? colp[j0 + lane] : 0.0;
+      double x = lane < jb ? colp[j0 + lane] : 0.0;
       for (int c = 0; c + 1 < jb; ++c) {
-        const double uc = __shfl(u, c);
-        if (lane > c && lane < jb) u = fma(-s_l[lane * 32 + c], uc, u);
+        const double xc = __shfl(x, c);
+        if (lane > c && lane < jb) x = fma(-s_l[lane * 32 + c], xc, x);
       }
-      if (lane < jb) colp[j0 + lane] = u;
+      if (lane < jb) colp[j0 + lane] = x;
     }
   }
+}
+
+// Composed interchanges of an outer panel: rows x in [r_lo, r_hi) whose opos[x] != x
+// (opos[x] = row, at the start of the outer panel, of what is now row x) become pairs
+// (x, opos[x]), and opos is reset to the identity for the next outer panel.
+__global__ __launch_bounds__(1024) void k_lu_outer_pairs(int32_t* __restrict__ opos, int r_lo, int r_hi,
+                                                         int32_t* __restrict__ pairs) {
+  __shared__ int s_np;
+  if (threadIdx.x == 0) s_np = 0;
+  __syncthreads();
+  for (int x = r_lo + threadIdx.x; x < r_hi; x += 1024) {
+    const int o = opos[x];
+    if (o != x) {
+      const int q = atomicAdd(&s_np, 1);
+      pairs[q] = x;
+      pairs[kOuterPairs + q] = o;
+      opos[x] = x;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) pairs[2 * kOuterPairs] = s_np;
 }
 
 // X = P: X[c, rowperm[c]] = 1 (column-major k x k).
@@ -375,11 +444,13 @@ __global__ void k_reinv_w_part(double* __restrict__ part, int ld, int k, const i
   part[(size_t)chunk * ld + j] = acc;
 }
 
-__global__ void k_reinv_w_sum(double* __restrict__ W, const double* __restrict__ part, int ld, int nchunk,
-                              const int32_t* __restrict__ info) {
+// The result goes to the copy of W that is current once no pivot is pending.
+__global__ void k_reinv_w_sum(double* __restrict__ W0, double* __restrict__ W1, const Ctrl* __restrict__ ctl,
+                              const double* __restrict__ part, int ld, int nchunk, const int32_t* __restrict__ info) {
   if (*info) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= ld) return;
+  double* W = ctl->wcur ? W1 : W0;
   double acc = 0.0;
   for (int c = 0; c < nchunk; ++c) acc += part[(size_t)c * ld + j];
   W[j] = acc;
@@ -413,13 +484,255 @@ __global__ __launch_bounds__(1024) void k_reinv_finish(Ctrl* ctl, int k, const i
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Small blocks.
+constexpr int kSmallK = 128;
+constexpr int kGJThreads = 1024;
+constexpr int kGJRows = kSmallK / 8;  // rows of the block one thread holds
+
+// X = M^-1 for M = G[:, 0:k] (column-major, k <= kSmallK) by in-place Gauss-Jordan
+// elimination with partial pivoting, one workgroup.  Thread 8j + g holds column j of rows
+// g, g + 8, ... (at most 16) in registers, so the eight holders of a column are adjacent
+// lanes of one wavefront.  Column c: its holders find the row of largest |value| at or
+// below the diagonal (lowest row on ties) with three shuffles and publish the old column c;
+// after a barrier the holders of rows p and c publish those rows; after a second barrier
+// row c becomes row p scaled by the reciprocal pivot with its diagonal entry replaced by
+// that reciprocal, row p becomes the old row c, and column c is eliminated from every
+// other row.  The LDS buffers alternate between columns.  The row exchanges make the
+// result (P M)^-1 = M^-1 P^T, so its column c is column idx[c] of M^-1.
+__global__ __launch_bounds__(kGJThreads) void k_gj_inverse(const double* __restrict__ G, int k,
+                                                           double* __restrict__ X, int32_t* __restrict__ info) {
+  __shared__ double s_row[2][kSmallK], s_rowc[2][kSmallK], s_col[2][kSmallK];
+  __shared__ double s_pv[2];
+  __shared__ int s_p[2];
+  __shared__ int s_idx[kSmallK];
+  __shared__ int s_sing;
+  const int tid = threadIdx.x;
+  const int grp = tid & 7, jcol = tid >> 3;
+  const bool active = jcol < k;
+  double a[kGJRows];
+#pragma unroll
+  for (int u = 0; u < kGJRows; ++u) {
+    const int i = grp + 8 * u;
+    a[u] = (active && i < k) ? G[(size_t)i + (size_t)jcol * k] : 0.0;
+  }
+  if (tid < k) s_idx[tid] = tid;
+  if (tid == 0) s_sing = 0;
+  __syncthreads();
+  for (int c = 0; c < k; ++c) {
+    const int bf = c & 1;
+    if (jcol == c) {
+      double bv = -1.0, sv = 0.0;
+      int bi = INT_MAX;
+#pragma unroll
+      for (int u = 0; u < kGJRows; ++u) {
+        const int i = grp + 8 * u;
+        if (i < k) {
+          s_col[bf][i] = a[u];
+          if (i >= c) {
+            double v = fabs(a[u]);
+            v = v == v ? v : 0.0;
+            if (v > bv) {
+              bv = v;
+              bi = i;
+              sv = a[u];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 1; off < 8; off <<= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const double osv = __shfl_xor(sv, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+          sv = osv;
+        }
+      }
+      if (grp == 0) {
+        s_p[bf] = bi;
+        s_pv[bf] = sv;
+        if (!(bv > 0.0)) s_sing = 1;
+        if (bi != c) {
+          const int t = s_idx[c];
+          s_idx[c] = s_idx[bi];
+          s_idx[bi] = t;
+        }
+      }
+    }
+    __syncthreads();
+    const int p = s_p[bf];
+    // Branch-free from here on (selects only), so that the register rows are never
+    // copied at branch joins.
+    if (active) {
+      double vp = 0.0, vc = 0.0;
+#pragma unroll
+      for (int u = 0; u < kGJRows; ++u) {
+        const int i = grp + 8 * u;
+        vp = i == p ? a[u] : vp;
+        vc = i == c ? a[u] : vc;
+      }
+      if ((p & 7) == grp) s_row[bf][jcol] = vp;
+      if ((c & 7) == grp) s_rowc[bf][jcol] = vc;
+    }
+    __syncthreads();
+    if (active) {
+      const double pivinv = 1.0 / s_pv[bf];
+      const double rowc = (jcol == c ? 1.0 : s_row[bf][jcol]) * pivinv;
+      const double oldc = s_rowc[bf][jcol];
+      const double colc = s_col[bf][c];
+      const bool on_c = jcol == c;
+#pragma unroll
+      for (int u = 0; u < kGJRows; ++u) {
+        const int i = grp + 8 * u;
+        const bool isp = i == p;
+        const double f = isp ? colc : s_col[bf][i < k ? i : 0];
+        const double base = on_c ? 0.0 : (isp ? oldc : a[u]);
+        const double upd = fma(-f, rowc, base);
+        a[u] = i < k ? (i == c ? rowc : upd) : a[u];
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int u = 0; u < kGJRows; ++u) {
+      const int i = grp + 8 * u;
+      if (i < k) X[(size_t)i + (size_t)s_idx[jcol] * k] = a[u];
+    }
+  }
+  if (tid == 0 && s_sing) *info = 1;
+}
+
+// B^-1 in its m x ld row-major layout, 4 rows per workgroup.  A structural basis position
+// b copies column b of X; a slack position s forms -sum_b B21[s, b] B11^-1[b, :] from the
+// column k + s of G and X (4 rows share each read of X).
+constexpr int kScatterRows = 4;
+
+__global__ __launch_bounds__(256) void k_reinv_scatter_small(double* __restrict__ Binv, int m, int ld, int k,
+                                                              const int32_t* __restrict__ rinfo,
+                                                              const int32_t* __restrict__ colmap,
+                                                              const int32_t* __restrict__ srow,
+                                                              const double* __restrict__ X,
+                                                              const double* __restrict__ G,
+                                                              const int32_t* __restrict__ info) {
+  if (*info) return;
+  __shared__ double s_g[kScatterRows][kSmallK];
+  __shared__ double s_v[kScatterRows][kSmallK];
+  const int p0 = blockIdx.x * kScatterRows, tid = threadIdx.x;
+  int ri[kScatterRows];
+#pragma unroll
+  for (int r = 0; r < kScatterRows; ++r) {
+    ri[r] = p0 + r < m ? rinfo[p0 + r] : 0;
+    for (int b = tid; b < k; b += 256)
+      s_g[r][b] = (p0 + r < m && ri[r] < 0) ? G[(size_t)b + (size_t)(k + (-ri[r] - 1)) * k] : 0.0;
+  }
+  __syncthreads();
+  if (tid < k) {
+    const int a = tid;
+    double acc[kScatterRows];
+#pragma unroll
+    for (int r = 0; r < kScatterRows; ++r) acc[r] = 0.0;
+    for (int b = 0; b < k; ++b) {
+      const double x = X[(size_t)a + (size_t)b * k];
+#pragma unroll
+      for (int r = 0; r < kScatterRows; ++r) acc[r] = fma(s_g[r][b], x, acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kScatterRows; ++r)
+      s_v[r][a] = ri[r] >= 0 ? X[(size_t)a + (size_t)ri[r] * k] : -acc[r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kScatterRows; ++r) {
+    const int p = p0 + r;
+    if (p >= m) break;
+    const int sr = ri[r] < 0 ? srow[-ri[r] - 1] : -1;
+    double* row = Binv + (size_t)p * ld;
+    for (int j = tid; j < ld; j += 256) {
+      const int a = colmap[j];
+      row[j] = a >= 0 ? s_v[r][a] : (j == sr ? 1.0 : 0.0);
+    }
+  }
+}
+
+// x_B of the structural basis positions, x_K = B11^-1 b_R (column b of X dotted with b_R),
+// also kept in xs for the slack positions.
+__global__ __launch_bounds__(256) void k_reinv_xstruct(double* __restrict__ xB, double* __restrict__ xs, int k,
+                                                       const int32_t* __restrict__ kpos,
+                                                       const int32_t* __restrict__ rowlist,
+                                                       const double* __restrict__ X, const double* __restrict__ b,
+                                                       double eps_z, const int32_t* __restrict__ info) {
+  if (*info) return;
+  __shared__ double s_b[kSmallK];
+  const int bb = threadIdx.x;
+  if (bb < k) s_b[bb] = b[rowlist[bb]];
+  __syncthreads();
+  if (bb >= k) return;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int a = 0; a < k; ++a) acc = fma(X[(size_t)a + (size_t)bb * k], s_b[a], acc);
+  xs[bb] = acc;
+  xB[kpos[bb]] = fabs(acc) < eps_z ? 0.0 : acc;
+}
+
+// x_B of the slack basis positions: b_S - B21 x_K, one wavefront per position.
+__global__ void k_reinv_xslack(double* __restrict__ xB, int m, int k, const int32_t* __restrict__ rinfo,
+                               const int32_t* __restrict__ srow, const double* __restrict__ G,
+                               const double* __restrict__ xs, const double* __restrict__ b, double eps_z,
+                               const int32_t* __restrict__ info) {
+  if (*info) return;
+  const int lane = threadIdx.x & 63;
+  const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  for (int p = gw; p < m; p += nw) {
+    const int ri = rinfo[p];
+    if (ri >= 0) continue;
+    const int s = -ri - 1;
+    const double* g = G + (size_t)(k + s) * k;
+    double acc = 0.0;
+    for (int bb = lane; bb < k; bb += 64) acc = fma(g[bb], xs[bb], acc);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) {
+      const double x = b[srow[s]] - acc;
+      xB[p] = fabs(x) < eps_z ? 0.0 : x;
+    }
+  }
+}
+
+// W_j = sum_b chat_{kcol[b]} B11^-1[b, a] for j = rowlist[a], 0 elsewhere, into the copy of
+// W that is current once no pivot is pending.
+__global__ void k_reinv_w_small(double* __restrict__ W0, double* __restrict__ W1, const Ctrl* __restrict__ ctl,
+                                int ld, int k, const int32_t* __restrict__ colmap, const int32_t* __restrict__ kcol,
+                                const double* __restrict__ chat, const double* __restrict__ X,
+                                const int32_t* __restrict__ info) {
+  if (*info) return;
+  __shared__ double s_c[kSmallK];
+  for (int bb = threadIdx.x; bb < k; bb += blockDim.x) s_c[bb] = chat[kcol[bb]];
+  __syncthreads();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ld) return;
+  const int a = colmap[j];
+  double acc = 0.0;
+  if (a >= 0) {
+#pragma unroll 8
+    for (int bb = 0; bb < k; ++bb) acc = fma(s_c[bb], X[(size_t)a + (size_t)bb * k], acc);
+  }
+  (ctl->wcur ? W1 : W0)[j] = acc;
+}
+
+// Grow-only device buffer; capacity at least doubles so that a basis block growing over a
+// solve reallocates O(log) times (a free synchronises the device).
 template <class T>
-hipError_t grow(T** ptr, size_t* cap, size_t need) {
+hipError_t grow(T** ptr, size_t* cap, size_t need, size_t limit) {
   if (need <= *cap && *ptr) return hipSuccess;
   if (*ptr) (void)hipFree(*ptr);
   *ptr = nullptr;
+  const size_t n = std::max<size_t>(std::max(need, std::min(2 * *cap, limit)), 1);
   *cap = 0;
-  const size_t n = std::max<size_t>(need, 1);
   hipError_t e = hipMalloc(reinterpret_cast<void**>(ptr), n * sizeof(T));
   if (e == hipSuccess) *cap = n;
   return e;
@@ -458,16 +771,19 @@ int blas_fail(rocblas_status st, const char* what) {
     if (st_ != rocblas_status_success) return blas_fail(st_, what); \
   } while (0)
 
+// Inner panel j0..j0+jb of the outer panel J0..J0+JBo: factorisation, then its row
+// interchanges on the other columns of the outer panel (and on opos) with U12 for the
+// columns right of it.
 template <int NT, int RPT, int JB>
-hipError_t launch_panel_step(double* M, int k, int j0, int jb, int32_t* pairs, int32_t* rowperm, int32_t* info,
-                             hipStream_t s) {
+hipError_t launch_inner_panel(double* M, int k, int J0, int JBo, int j0, int jb, int32_t* pairs, int32_t* opos,
+                              int32_t* info, hipStream_t s) {
   hipLaunchKernelGGL((k_lu_panel<NT, RPT, JB>), dim3(1), dim3(NT), 0, s, M, k, k, j0, jb, pairs, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int ncols = k - jb + 1;
+  const int ncols = JBo - jb + 1;
   const int grid = (ncols + kRowPanelWaves - 1) / kRowPanelWaves;
-  hipLaunchKernelGGL(k_lu_rowpanel, dim3(grid), dim3(kRowPanelThreads), 0, s, M, k, k, j0, jb, (const int32_t*)pairs,
-                     rowperm);
+  hipLaunchKernelGGL(k_lu_rowpanel, dim3(grid), dim3(kRowPanelThreads), 0, s, M, k, J0, J0 + JBo, j0, j0 + jb,
+                     j0 + jb, j0, jb, (const int32_t*)pairs, kPairs, opos);
   return hipGetLastError();
 }
 
@@ -483,16 +799,38 @@ void reinv_free(ReinvState* st) {
   delete st;
 }
 
-int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s, int* k_out) {
+int reinv_prepare(ReinvState** state, int m, int ld) {
   if (!*state) {
     *state = new (std::nothrow) ReinvState();
     if (!*state) return record_error(LP_ERR_NOMEM, "reinversion: host allocation failed");
   }
   ReinvState* st = *state;
   if (!st->blas) {
+    // rocBLAS loads its kernels lazily on first use (tens of milliseconds); load them once
+    // per process here, outside any solve.
+    static std::once_flag loaded;
+    std::call_once(loaded, [] { rocblas_initialize(); });
     R_BLAS(rocblas_create_handle(&st->blas), "creating the BLAS handle");
     R_BLAS(rocblas_set_atomics_mode(st->blas, rocblas_atomics_not_allowed), "configuring the BLAS handle");
   }
+  // Work memory for blocks up to kSmallK allocated up front (no allocation, and so no
+  // device synchronisation, inside a solve unless the block grows past that).
+  const size_t mm = (size_t)m * m, ks = (size_t)std::min(m, kSmallK);
+  R_HIP(grow_pinned(&st->h_basis, &st->h_basis_cap, (size_t)m), "allocating pinned memory");
+  R_HIP(grow_pinned(&st->h_idx, &st->h_idx_cap, 3 * (size_t)m + ld), "allocating pinned memory");
+  R_HIP(grow(&st->idx, &st->idx_cap, 3 * (size_t)m + ld, 3 * (size_t)m + ld), "allocating work memory");
+  const size_t naux = 2 * (size_t)m + 2 * kPairs + 2 * kOuterPairs + 3;
+  R_HIP(grow(&st->aux, &st->aux_cap, naux, naux), "allocating work memory");
+  R_HIP(grow(&st->G, &st->G_cap, ks * m, mm), "allocating work memory");
+  R_HIP(grow(&st->X, &st->X_cap, ks * ks, mm), "allocating work memory");
+  R_HIP(grow(&st->part, &st->part_cap, (size_t)ld, ((size_t)m / kWChunk + 1) * ld), "allocating work memory");
+  return LP_OK;
+}
+
+int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s, int* k_out) {
+  int rc = reinv_prepare(state, d.m, d.ld);
+  if (rc != LP_OK) return rc;
+  ReinvState* st = *state;
   R_BLAS(rocblas_set_stream(st->blas, s), "configuring the BLAS handle");
   const int m = d.m, n = d.n, ld = d.ld;
 
@@ -540,8 +878,10 @@ int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s,
     }
   for (int b = 0; b < k; ++b) h_rinfo[h_kpos[b]] = b;
 
-  R_HIP(grow(&st->idx, &st->idx_cap, nidx), "allocating work memory");
-  R_HIP(grow(&st->aux, &st->aux_cap, (size_t)m + 2 * kPairs + 2), "allocating work memory");
+  const size_t mm = (size_t)m * m;
+  R_HIP(grow(&st->idx, &st->idx_cap, nidx, 3 * (size_t)m + ld), "allocating work memory");
+  const size_t naux = 2 * (size_t)m + 2 * kPairs + 2 * kOuterPairs + 3;
+  R_HIP(grow(&st->aux, &st->aux_cap, naux, naux), "allocating work memory");
   R_HIP(hipMemcpyAsync(st->idx, st->h_idx, sizeof(int32_t) * nidx, hipMemcpyHostToDevice, s), "uploading indices");
   const int32_t* kcol_d = st->idx;
   const int32_t* kpos_d = kcol_d + k;
@@ -549,17 +889,21 @@ int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s,
   const int32_t* rinfo_d = rowlist_d + m;
   const int32_t* colmap_d = rinfo_d + m;
   int32_t* rowperm = st->aux;
-  int32_t* pairs = rowperm + m;
-  int32_t* info = pairs + 2 * kPairs + 1;
+  int32_t* opos = rowperm + m;
+  int32_t* pairs = opos + m;
+  int32_t* opairs = pairs + 2 * kPairs + 1;
+  int32_t* info = opairs + 2 * kOuterPairs + 1;
 
   const size_t kk = (size_t)k * k;
-  R_HIP(grow(&st->G, &st->G_cap, (size_t)k * m), "allocating work memory");
-  R_HIP(grow(&st->X, &st->X_cap, kk), "allocating work memory");
-  R_HIP(grow(&st->C, &st->C_cap, (size_t)k * (m - k)), "allocating work memory");
+  R_HIP(grow(&st->G, &st->G_cap, (size_t)k * m, mm), "allocating work memory");
+  R_HIP(grow(&st->X, &st->X_cap, kk, mm), "allocating work memory");
+  const bool small = k <= kSmallK;
+  if (!small) R_HIP(grow(&st->C, &st->C_cap, (size_t)k * (m - k), mm / 4 + 1), "allocating work memory");
   const int nchunk = std::max(1, (k + kWChunk - 1) / kWChunk);
-  R_HIP(grow(&st->part, &st->part_cap, (size_t)nchunk * ld), "allocating work memory");
+  R_HIP(grow(&st->part, &st->part_cap, std::max((size_t)nchunk * ld, (size_t)k), ((size_t)m / kWChunk + 1) * ld),
+        "allocating work memory");
 
-  hipLaunchKernelGGL(k_reinv_setup, dim3(std::max(1, (k + 255) / 256)), dim3(256), 0, s, rowperm, k, info);
+  hipLaunchKernelGGL(k_reinv_setup, dim3(std::max(1, (k + 255) / 256)), dim3(256), 0, s, rowperm, opos, k, info);
   R_HIP(hipGetLastError(), "launching setup");
 
   if (k > 0) {
@@ -567,36 +911,64 @@ int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s,
     hipLaunchKernelGGL(k_gather, dim3((m + 31) / 32, (k + 31) / 32), dim3(32, 8), 0, s, d.A, ld, kcol_d, rowlist_d,
                        k, m, st->G);
     R_HIP(hipGetLastError(), "launching the gather");
+  }
+  if (k > 0 && small) {
+    // 2'-4'. X = M^-1 in one workgroup; -B21 B11^-1 is formed while writing B^-1.
+    hipLaunchKernelGGL(k_gj_inverse, dim3(1), dim3(kGJThreads), 0, s, (const double*)st->G, k, st->X, info);
+    R_HIP(hipGetLastError(), "launching the small inverse");
+  } else if (k > 0) {
     // 2. LU of M = G[:, 0:k] (leading dimension k).
     double* Mx = st->G;
     const double one = 1.0, minus_one = -1.0, zero = 0.0;
-    for (int j0 = 0; j0 < k;) {
-      const int R = k - j0;
-      int jb;
-      hipError_t e;
-      // Panel shapes that keep the rows in registers without spills; R <= LP_MAX_ROWS.
-      if (R <= 1024) {
-        jb = std::min(32, R);
-        e = launch_panel_step<1024, 1, 32>(Mx, k, j0, jb, pairs, rowperm, info, s);
-      } else if (R <= 2048) {
-        jb = 8;
-        e = launch_panel_step<1024, 2, 8>(Mx, k, j0, jb, pairs, rowperm, info, s);
-      } else if (R <= 4096) {
-        jb = 4;
-        e = launch_panel_step<1024, 4, 4>(Mx, k, j0, jb, pairs, rowperm, info, s);
-      } else {
-        jb = 2;
-        e = launch_panel_step<1024, 10, 2>(Mx, k, j0, jb, pairs, rowperm, info, s);
+    for (int J0 = 0; J0 < k; J0 += kOuter) {
+      const int JBo = std::min(kOuter, k - J0);
+      for (int j0 = J0; j0 < J0 + JBo;) {
+        const int R = k - j0, room = J0 + JBo - j0;
+        int jb;
+        hipError_t e;
+        // Inner panel shapes that keep the rows in registers without spills; R <= LP_MAX_ROWS.
+        if (R <= 1024) {
+          jb = std::min(16, room);
+          e = launch_inner_panel<1024, 1, 16>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
+        } else if (R <= 2048) {
+          jb = std::min(8, room);
+          e = launch_inner_panel<1024, 2, 8>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
+        } else if (R <= 4096) {
+          jb = std::min(4, room);
+          e = launch_inner_panel<1024, 4, 4>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
+        } else {
+          jb = std::min(2, room);
+          e = launch_inner_panel<1024, 10, 2>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
+        }
+        R_HIP(e, "launching a panel factorisation");
+        const int rows = k - j0 - jb, cols = J0 + JBo - j0 - jb;
+        if (rows > 0 && cols > 0)
+          R_BLAS(rocblas_dgemm(st->blas, rocblas_operation_none, rocblas_operation_none, rows, cols, jb, &minus_one,
+                               Mx + (size_t)(j0 + jb) + (size_t)j0 * k, k, Mx + (size_t)j0 + (size_t)(j0 + jb) * k, k,
+                               &one, Mx + (size_t)(j0 + jb) + (size_t)(j0 + jb) * k, k),
+                 "inner update");
+        j0 += jb;
       }
-      R_HIP(e, "launching a panel factorisation");
-      const int rest = k - j0 - jb;
+      // The outer panel's interchanges on the columns outside it and on rowperm.
+      hipLaunchKernelGGL(k_lu_outer_pairs, dim3(1), dim3(1024), 0, s, opos, J0, k, opairs);
+      R_HIP(hipGetLastError(), "launching the interchange list");
+      {
+        const int ncols = k - JBo + 1;
+        hipLaunchKernelGGL(k_lu_rowpanel, dim3((ncols + kRowPanelWaves - 1) / kRowPanelWaves), dim3(kRowPanelThreads),
+                           0, s, Mx, k, 0, k, J0, J0 + JBo, k, 0, 0, (const int32_t*)opairs, kOuterPairs, rowperm);
+        R_HIP(hipGetLastError(), "launching the interchanges");
+      }
+      const int rest = k - J0 - JBo;
       if (rest > 0) {
-        R_BLAS(rocblas_dgemm(st->blas, rocblas_operation_none, rocblas_operation_none, rest, rest, jb, &minus_one,
-                             Mx + (size_t)(j0 + jb) + (size_t)j0 * k, k, Mx + (size_t)j0 + (size_t)(j0 + jb) * k, k,
-                             &one, Mx + (size_t)(j0 + jb) + (size_t)(j0 + jb) * k, k),
+        R_BLAS(rocblas_dtrsm(st->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                             rocblas_diagonal_unit, JBo, rest, &one, Mx + (size_t)J0 + (size_t)J0 * k, k,
+                             Mx + (size_t)J0 + (size_t)(J0 + JBo) * k, k),
+               "outer U12");
+        R_BLAS(rocblas_dgemm(st->blas, rocblas_operation_none, rocblas_operation_none, rest, rest, JBo, &minus_one,
+                             Mx + (size_t)(J0 + JBo) + (size_t)J0 * k, k, Mx + (size_t)J0 + (size_t)(J0 + JBo) * k, k,
+                             &one, Mx + (size_t)(J0 + JBo) + (size_t)(J0 + JBo) * k, k),
                "trailing update");
       }
-      j0 += jb;
     }
     // 3. X = U^-1 L^-1 P
     hipLaunchKernelGGL(k_perm_matrix, dim3((unsigned)std::min<size_t>(8192, (kk + 255) / 256)), dim3(256), 0, s,
@@ -615,7 +987,25 @@ int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s,
              "forming -B21 B11^-1");
   }
   // 5. B^-1, x_B, W, z.
-  {
+  if (small) {
+    hipLaunchKernelGGL(k_reinv_scatter_small, dim3((m + kScatterRows - 1) / kScatterRows), dim3(256), 0, s, d.Binv, m,
+                       ld, k, rinfo_d, colmap_d, rowlist_d + k, (const double*)st->X, (const double*)st->G,
+                       (const int32_t*)info);
+    R_HIP(hipGetLastError(), "launching the scatter");
+    hipLaunchKernelGGL(k_reinv_xstruct, dim3(1), dim3(kSmallK), 0, s, d.xB, st->part, k, kpos_d, rowlist_d,
+                       (const double*)st->X, b, d.eps_z, (const int32_t*)info);
+    R_HIP(hipGetLastError(), "launching x_B");
+    hipLaunchKernelGGL(k_reinv_xslack, dim3((unsigned)std::min(4096, (m + 3) / 4)), dim3(256), 0, s, d.xB, m, k,
+                       rinfo_d, rowlist_d + k, (const double*)st->G, (const double*)st->part, b, d.eps_z,
+                       (const int32_t*)info);
+    R_HIP(hipGetLastError(), "launching x_B");
+    hipLaunchKernelGGL(k_reinv_w_small, dim3((ld + 255) / 256), dim3(256), 0, s, d.W0, d.W1, (const Ctrl*)d.ctrl, ld,
+                       k, colmap_d, kcol_d, d.chat, (const double*)st->X, (const int32_t*)info);
+    R_HIP(hipGetLastError(), "launching W");
+    hipLaunchKernelGGL(k_reinv_finish, dim3(1), dim3(1024), 0, s, d.ctrl, k, kcol_d, kpos_d, d.chat,
+                       (const double*)d.xB, (const int32_t*)info);
+    R_HIP(hipGetLastError(), "launching the finish");
+  } else {
     const size_t total = (size_t)m * ld;
     hipLaunchKernelGGL(k_reinv_scatter, dim3((unsigned)std::min<size_t>(16384, (total + 255) / 256)), dim3(256), 0,
                        s, d.Binv, m, ld, k, rinfo_d, colmap_d, rowlist_d + k, (const double*)st->X,
@@ -627,8 +1017,8 @@ int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s,
     hipLaunchKernelGGL(k_reinv_w_part, dim3((ld + 255) / 256, nchunk), dim3(256), 0, s, st->part, ld, k, colmap_d,
                        kcol_d, d.chat, (const double*)st->X, (const int32_t*)info);
     R_HIP(hipGetLastError(), "launching W");
-    hipLaunchKernelGGL(k_reinv_w_sum, dim3((ld + 255) / 256), dim3(256), 0, s, d.W, (const double*)st->part, ld,
-                       nchunk, (const int32_t*)info);
+    hipLaunchKernelGGL(k_reinv_w_sum, dim3((ld + 255) / 256), dim3(256), 0, s, d.W0, d.W1, (const Ctrl*)d.ctrl,
+                       (const double*)st->part, ld, nchunk, (const int32_t*)info);
     R_HIP(hipGetLastError(), "launching W");
     hipLaunchKernelGGL(k_reinv_finish, dim3(1), dim3(1024), 0, s, d.ctrl, k, kcol_d, kpos_d, d.chat,
                        (const double*)d.xB, (const int32_t*)info);
