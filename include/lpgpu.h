@@ -107,7 +107,9 @@ typedef struct lp_stats {
   int64_t update_launches;  /* update kernels timed (profile = 1 or 2) */
   double update_ms;         /* their summed duration */
   double price_bytes;       /* algorithmic bytes of those pricing launches: 8*m per priced column */
-  double update_bytes;      /* algorithmic bytes of those update launches: 16*m*m (8*m*m if no pivot pending) */
+  double update_bytes;      /* algorithmic bytes of those update launches: 8*m*m read, plus 16 per element
+                               pair written back (pairs whose pivot-row entries are both zero are
+                               unchanged and not written) */
   int64_t finish_launches;  /* ratio-test finishing kernels timed (profile = 1 or 2) */
   double finish_ms;         /* their summed duration */
   int64_t ray;              /* after LP_UNBOUNDED: the entering variable with no positive alpha_i; else -1 */

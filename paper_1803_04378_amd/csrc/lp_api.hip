@@ -573,6 +573,7 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
     const int64_t t_before = p->h_ctrl->t;
     const int64_t cols_before = p->h_ctrl->price_cols;
     const int64_t nsb_before = p->h_ctrl->nsb;
+    const int64_t pairs_before = p->h_ctrl->update_pairs_written;
     if (direct) {
       if ((rc = launch_direct(p)) != LP_OK) return rc;
     } else {
@@ -605,7 +606,9 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
       p->stats.update_launches += K;
       p->stats.finish_launches += K;
       p->stats.price_bytes += 8.0 * p->m * (double)(p->h_ctrl->price_cols - cols_before);
-      p->stats.update_bytes += 16.0 * (double)p->m * p->m * K;
+      // read all of B^-1 (8 m^2), write the element pairs the update changed (16 B each)
+      p->stats.update_bytes +=
+          8.0 * (double)p->m * p->m * K + 16.0 * (double)(p->h_ctrl->update_pairs_written - pairs_before);
       if (mixed) {
         // Nonbasic structural columns streamed by the K screening passes (the basis
         // changes by at most one structural column per pivot; the midpoint is used).

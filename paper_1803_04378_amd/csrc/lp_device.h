@@ -74,6 +74,8 @@ struct Ctrl {
   int64_t full_prices;       // mixed form: iterations whose shortlist held no improving column
   int64_t n_reinv;           // reinversions installed
   int64_t n_reinv_failed;    // reinversions abandoned on a zero pivot (state kept as it was)
+  int64_t rho_nz2;           // element pairs of the pending rho with a nonzero entry
+  int64_t update_pairs_written;  // element pairs of B^-1 the update passes wrote
 };
 
 struct DevLP {

@@ -126,6 +126,7 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
     double2* Wnew = reinterpret_cast<double2*>(wc ? lp.W0 : lp.W1);
     double2* rho2 = reinterpret_cast<double2*>(lp.rho);
     const bool writer = blockIdx.x == 0;
+    int nz2 = 0;
     for (int k = threadIdx.x; k < ld2; k += kPriceBlock) {
       const double2 b = rowr[k];
       const double2 w = Wold[k];
@@ -135,7 +136,12 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
       if (writer) {
         rho2[k] = rr;
         Wnew[k] = wn;
+        nz2 += (rr.x != 0.0 || rr.y != 0.0) ? 1 : 0;
       }
+    }
+    if (writer) {
+      nz2 = block_sum_int<kPriceBlock>(nz2, red_j);
+      if (threadIdx.x == 0) lp.ctrl->rho_nz2 = nz2;
     }
   } else {
     const double2* W2 = reinterpret_cast<const double2*>(pricing_w(lp));
@@ -322,6 +328,8 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
     if (r >= 0) {
       ctl->update_launches += 1;
       ctl->update_rows_written += m;
+      // pairs written: those with a nonzero rho entry in every row but r, all of row r
+      ctl->update_pairs_written += (int64_t)(m - 1) * ctl->rho_nz2 + lp.ld / 2;
     } else if (q >= 0) {
       ctl->update_launches += 1;
     }

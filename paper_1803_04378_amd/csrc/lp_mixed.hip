@@ -106,20 +106,32 @@ __global__ __launch_bounds__(kPrice32Block) void k_price32(DevLP lp) {
   // formed in FP64 and staged rounded to FP32; workgroup 0 stores rho and W_new.
   float* s_w = reinterpret_cast<float*>(s_w4);
   if (r >= 0) {
-    const double* Wold = wc ? lp.W1 : lp.W0;
-    double* Wnew = wc ? lp.W0 : lp.W1;
+    const double2* Wold = reinterpret_cast<const double2*>(wc ? lp.W1 : lp.W0);
+    double2* Wnew = reinterpret_cast<double2*>(wc ? lp.W0 : lp.W1);
     const double ar = lp.ctrl->ar;
     const double dq = lp.ctrl->pdq;
-    const double* rowr = lp.Binv + (size_t)r * lp.ld;
+    const double2* rowr = reinterpret_cast<const double2*>(lp.Binv + (size_t)r * lp.ld);
+    double2* rho2 = reinterpret_cast<double2*>(lp.rho);
     const bool writer = blockIdx.x == 0;
-    for (int k = threadIdx.x; k < lp.ld; k += kPrice32Block) {
-      const double rr = rowr[k] / ar;
-      const double wn = fma(dq, rr, Wold[k]);
-      s_w[k] = (float)wn;
+    int nz2 = 0;
+    for (int k = threadIdx.x; k < lp.ld / 2; k += kPrice32Block) {
+      const double2 b = rowr[k];
+      const double2 w = Wold[k];
+      const double2 rr = make_double2(b.x / ar, b.y / ar);
+      const double2 wn = make_double2(fma(dq, rr.x, w.x), fma(dq, rr.y, w.y));
+      s_w[2 * k] = (float)wn.x;
+      s_w[2 * k + 1] = (float)wn.y;
       if (writer) {
-        lp.rho[k] = rr;
+        rho2[k] = rr;
         Wnew[k] = wn;
+        nz2 += (rr.x != 0.0 || rr.y != 0.0) ? 1 : 0;
       }
+    }
+    if (writer) {
+      // pairs of rho with a nonzero entry (the update writes only those)
+      __shared__ int s_nz[kPrice32Block / 64];
+      nz2 = block_sum_int<kPrice32Block>(nz2, s_nz);
+      if (threadIdx.x == 0) lp.ctrl->rho_nz2 = nz2;
     }
   } else {
     const double* W = wc ? lp.W1 : lp.W0;

@@ -167,7 +167,9 @@ __device__ __forceinline__ double wave_dot(const double2* __restrict__ x, const 
   return wave_sum(acc);
 }
 
-// row <- row + na * rho (in place), returning dot(new row, a) when DOT.
+// row <- row + na * rho (in place), returning dot(new row, a) when DOT.  An element pair
+// whose rho entries are both zero is unchanged by the fma, so it is not written back
+// (the pivot row of B^-1 has a zero wherever the column belongs to a basic slack).
 template <bool DOT>
 __device__ __forceinline__ double wave_update_dot(double2* __restrict__ row, const double2* rho, const double2* a,
                                                   double na, int n2, int lane, double2 (&v)[kBatch], bool pre) {
@@ -182,7 +184,7 @@ __device__ __forceinline__ double wave_update_dot(double2* __restrict__ row, con
         const double2 rr = rho[k];
         v[u].x = fma(na, rr.x, v[u].x);
         v[u].y = fma(na, rr.y, v[u].y);
-        row[k] = v[u];
+        if (rr.x != 0.0 || rr.y != 0.0) row[k] = v[u];
         if (DOT) {
           const double2 w = a[k];
           acc = fma(v[u].x, w.x, acc);
