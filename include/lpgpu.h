@@ -107,9 +107,13 @@ typedef struct lp_stats {
   int64_t update_launches;  /* update kernels timed (profile = 1 or 2) */
   double update_ms;         /* their summed duration */
   double price_bytes;       /* algorithmic bytes of those pricing launches: 8*m per priced column */
-  double update_bytes;      /* algorithmic bytes of those update launches: 8*m*m read, plus 16 per element
-                               pair written back (pairs whose pivot-row entries are both zero are
-                               unchanged and not written) */
+  double update_bytes;      /* algorithmic bytes of those update launches.  Dense mode: 8*m*m read, plus
+                               16 per element pair written back (pairs whose pivot-row entries are
+                               both zero are unchanged and not written).  With ld >= 1024 and while
+                               at most ld/8 columns of B^-1 can differ from unit vectors (those of
+                               slacks that left the basis since the last reinversion), only those
+                               columns are read and updated: 8 per entry read or written, plus one
+                               unit entry per row */
   int64_t finish_launches;  /* ratio-test finishing kernels timed (profile = 1 or 2) */
   double finish_ms;         /* their summed duration */
   int64_t ray;              /* after LP_UNBOUNDED: the entering variable with no positive alpha_i; else -1 */

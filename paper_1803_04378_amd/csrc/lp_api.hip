@@ -410,6 +410,8 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   ALLOC(p->d.alpha0, (size_t)m);
   ALLOC(p->d.alpha1, (size_t)m);
   ALLOC(p->d.basis, (size_t)m);
+  ALLOC(p->d.dlist, (size_t)m);
+  ALLOC(p->d.inD, (size_t)m);
   ALLOC(p->d.pos, (size_t)N);
   ALLOC(p->d.tabu_until, (size_t)N);
   ALLOC(p->d.gen, (size_t)N);
@@ -573,7 +575,7 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
     const int64_t t_before = p->h_ctrl->t;
     const int64_t cols_before = p->h_ctrl->price_cols;
     const int64_t nsb_before = p->h_ctrl->nsb;
-    const int64_t pairs_before = p->h_ctrl->update_pairs_written;
+    const int64_t ubytes_before = p->h_ctrl->update_bytes;
     if (direct) {
       if ((rc = launch_direct(p)) != LP_OK) return rc;
     } else {
@@ -606,9 +608,8 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
       p->stats.update_launches += K;
       p->stats.finish_launches += K;
       p->stats.price_bytes += 8.0 * p->m * (double)(p->h_ctrl->price_cols - cols_before);
-      // read all of B^-1 (8 m^2), write the element pairs the update changed (16 B each)
-      p->stats.update_bytes +=
-          8.0 * (double)p->m * p->m * K + 16.0 * (double)(p->h_ctrl->update_pairs_written - pairs_before);
+      // algorithmic bytes of the update passes, counted on the device
+      p->stats.update_bytes += (double)(p->h_ctrl->update_bytes - ubytes_before);
       if (mixed) {
         // Nonbasic structural columns streamed by the K screening passes (the basis
         // changes by at most one structural column per pivot; the midpoint is used).

@@ -32,6 +32,11 @@ using namespace detail;
 
 namespace {
 
+#ifndef LPGPU_BATCH_SMALL
+#define LPGPU_BATCH_SMALL 4
+#endif
+constexpr int kBatchSmall = LPGPU_BATCH_SMALL;
+
 // Group synchronisation: G == 1 is one wavefront (lockstep; the fence orders its LDS and
 // global accesses), G > 1 is the whole workgroup.
 template <int G>
@@ -116,7 +121,7 @@ __device__ __forceinline__ void g_cnt_min(int& cnt, int& low, int* xj) {
 }
 
 size_t lds_doubles(int m, int ld) { return 3 * (size_t)ld + 4 * (size_t)m; }
-size_t lds_ints(int m, int n) { return (size_t)m + 2 * ((size_t)n + m); }
+size_t lds_ints(int m, int n) { return 3 * (size_t)m + 2 * ((size_t)n + m); }
 
 }  // namespace
 
@@ -143,6 +148,8 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
   int* basis = reinterpret_cast<int*>(ratio + m);
   int* pos = basis + m;
   int* tabu = pos + N;
+  int* dl = tabu + N;  // columns of B^-1 that may differ from unit vectors (as in k_update)
+  int* inD = dl + m;
   double2* W2 = reinterpret_cast<double2*>(W);
   double2* rho2 = reinterpret_cast<double2*>(rho);
   double2* a2 = reinterpret_cast<double2*>(av);
@@ -171,6 +178,7 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
   }
   for (int i = tid; i < m; i += T) {
     xB[i] = bb[i];
+    inD[i] = 0;
     basis[i] = n + i;
     al0[i] = 0.0;
     al1[i] = 0.0;
@@ -187,10 +195,10 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
   gsync<G>();
 
   int64_t t = 0;
-  int status = kStatusRunning, ray = -1, r = -1, cur = 0, nL = 0;
+  int status = kStatusRunning, ray = -1, r = -1, cur = 0, nL = 0, nD = 0;
   double theta = 0.0, z = 0.0;
   const double neg_eps = -bd.eps_d;
-  double2 v[kBatch];
+  double2 v[kBatchSmall];  // rows here are short: a shallow batch keeps registers for occupancy
   for (;;) {
     // Steps 3-4: reduced costs with W in LDS.
     double da = __builtin_inf(), df = __builtin_inf();
@@ -253,7 +261,44 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
     // Section 3.1 update of the pending pivot fused with Step 5 and the per-row ratios.
     double* al_p = cur ? al1 : al0;
     double* al_n = cur ? al0 : al1;
-    if (r >= 0 || q >= 0) {
+    const bool sparse = sparse_columns(nD, ld);  // the same switch and arithmetic as k_update
+    if ((r >= 0 || q >= 0) && sparse) {
+      for (int i = wave; i < m; i += G) {
+        double* rowd = B + (size_t)i * ld;
+        const bool isr = i == r;
+        const double na = (r >= 0 && !isr) ? -al_p[i] : 0.0;
+        double acc = 0.0;
+        for (int a = lane; a < nD; a += 64) {
+          const int j = dl[a];
+          double val;
+          if (r >= 0) {
+            const double rr = rho[j];
+            val = isr ? rr : fma(na, rr, rowd[j]);
+            if (rr != 0.0) rowd[j] = val;
+          } else {
+            val = rowd[j];
+          }
+          if (q >= 0) acc = fma(val, av[j], acc);
+        }
+        double x = xB[i];
+        if (r >= 0) {
+          x = isr ? theta : fma(na, theta, x);
+          if (fabs(x) < bd.eps_z) x = 0.0;
+        }
+        if (q >= 0) {
+          acc = wave_sum(acc);
+          const int bv = basis[i];
+          if (bv >= n && !inD[bv - n]) acc += av[bv - n];
+        }
+        if (lane == 0) {
+          xB[i] = x;
+          if (q >= 0) {
+            al_n[i] = acc;
+            ratio[i] = acc > bd.eps_p ? fmax(x, 0.0) / acc : __builtin_inf();
+          }
+        }
+      }
+    } else if (r >= 0 || q >= 0) {
       for (int i = wave; i < m; i += G) {
         double2* row = B2 + (size_t)i * ld2;
         double acc = 0.0;
@@ -340,8 +385,13 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
     if (thr == 0.0) flags |= kFlagDegenerate;
     const int leave = basis[rn];
     const double ar = al_n[rn];
-    gsync<G>();  // every thread has read basis[rn] before it changes
+    const bool to_D = leave >= n && !inD[leave - n];  // its column stops being a unit vector
+    gsync<G>();  // every thread has read basis[rn] and inD before they change
     if (tid == 0) {
+      if (to_D) {
+        inD[leave - n] = 1;
+        dl[nD] = leave - n;
+      }
       if (bd.tenure > 0) tabu[leave] = (int)(t + bd.tenure);
       basis[rn] = q;
       pos[q] = rn;
@@ -353,6 +403,7 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
         lg_f[t] = flags;
       }
     }
+    if (to_D) ++nD;
     z = fma(dq, thr, z);
     ++t;
     r = rn;

@@ -6,6 +6,7 @@
 //   Binv   m x ld   row-major:    row i of B^-1 is contiguous (update + FTRAN stream it)
 //   W0, W1, rho ld  W = chat_B^T B^-1 (top row of the Figure 1 tableau, two copies: one is
 //                   read while the next is written), rho = pivot row / alpha_r
+//   dlist, inD      m int32 each: the columns of B^-1 that may differ from unit vectors
 //   xB, alpha[2]    m
 //   chat            n + m   (minimisation costs; slacks 0)
 //   basis (m), pos (n+m), tabu_until (n+m), the leaving-side tabu list, the pivot log: int32
@@ -75,7 +76,9 @@ struct Ctrl {
   int64_t n_reinv;           // reinversions installed
   int64_t n_reinv_failed;    // reinversions abandoned on a zero pivot (state kept as it was)
   int64_t rho_nz2;           // element pairs of the pending rho with a nonzero entry
-  int64_t update_pairs_written;  // element pairs of B^-1 the update passes wrote
+  int64_t update_bytes;      // algorithmic bytes the update passes moved
+  int32_t nD;                // columns in the list D (below)
+  int32_t pad5;
 };
 
 struct DevLP {
@@ -90,6 +93,12 @@ struct DevLP {
   double* alpha0;
   double* alpha1;
   int32_t* basis;
+  // Columns of B^-1 that may differ from a unit vector: every column whose slack has left
+  // the basis at some point since the last reinversion (append-only), with a membership
+  // flag per column.  A column outside D is e_p for the row p holding its basic slack,
+  // exactly: the update never changes it (its rho entry is zero) until that slack leaves.
+  int32_t* dlist;
+  int32_t* inD;
   int32_t* pos;
   int32_t* tabu_until;
   int32_t* gen;   // generation of each variable's tabu list (bumped to clear it)
@@ -138,6 +147,15 @@ __device__ __forceinline__ const double* pricing_w(const DevLP& lp) {
 
 // Mixed form: does the re-priced shortlist hold an improving column?  Every thread reads
 // the same entries, so all workgroups of a launch agree.
+// Sparse-column mode of the update and FTRAN (k_update and the batched solver take the
+// same decision, so their arithmetic stays identical): used while at most ld/8 columns of
+// B^-1 can differ from unit vectors, and only for rows long enough (ld >= 1024) that
+// skipping the unit columns saves more than the index indirection costs.
+constexpr int kSparseMinLd = 1024;
+__host__ __device__ __forceinline__ bool sparse_columns(int nD, int ld) {
+  return ld >= kSparseMinLd && nD * 8 <= ld;
+}
+
 __device__ __forceinline__ bool shortlist_improves(const DevLP& lp) {
   const double neg_eps = -lp.eps_d;
   for (int w = 0; w < lp.sl_k; ++w)

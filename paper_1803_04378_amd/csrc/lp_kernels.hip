@@ -54,6 +54,7 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
   }
   for (size_t i = tid; i < (size_t)m; i += stride) {
     lp.xB[i] = b[i];
+    lp.inD[i] = 0;
     lp.basis[i] = n + (int)i;
     lp.alpha0[i] = 0.0;
     lp.alpha1[i] = 0.0;
@@ -231,6 +232,10 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   if (lp.ctrl->status != kStatusRunning) return;
   const int r = lp.ctrl->r;
   const int64_t t = lp.ctrl->t;
+  // Sparse mode: while few columns of B^-1 can differ from unit vectors, the update and
+  // FTRAN touch only those (list D); the unit columns contribute one entry per row.
+  const int nD = lp.ctrl->nD;
+  const bool sparse = sparse_columns(nD, lp.ld);
   extern __shared__ double2 smem2[];
   __shared__ double red_d[2 * (kUpdateBlock / 64)];
   __shared__ int red_j[2 * (kUpdateBlock / 64)];
@@ -247,7 +252,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   // The first batch of this wave's first row is in flight while the entering column is
   // decided and staged.
   double2 v[kBatch];
-  const bool pre = gw < m && gw != r;
+  const bool pre = !sparse && gw < m && gw != r;
   if (pre) load_batch(reinterpret_cast<const double2*>(lp.Binv + (size_t)gw * lp.ld), lane, ld2, v);
 
   // Step 4 decision: from the re-priced shortlist in the mixed form when it holds an
@@ -328,10 +333,14 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
     if (r >= 0) {
       ctl->update_launches += 1;
       ctl->update_rows_written += m;
-      // pairs written: those with a nonzero rho entry in every row but r, all of row r
-      ctl->update_pairs_written += (int64_t)(m - 1) * ctl->rho_nz2 + lp.ld / 2;
     } else if (q >= 0) {
       ctl->update_launches += 1;
+    }
+    if (!sparse && (r >= 0 || q >= 0)) {
+      // read all of B^-1; write the pairs with a nonzero rho entry in every row but r,
+      // and all of row r
+      ctl->update_bytes += 8 * (int64_t)m * m;
+      if (r >= 0) ctl->update_bytes += 16 * ((int64_t)(m - 1) * ctl->rho_nz2 + lp.ld / 2);
     }
   }
   if (r < 0 && q < 0) return;
@@ -340,6 +349,81 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   const double theta = lp.ctrl->theta;
   const double* __restrict__ al_p = cur ? lp.alpha1 : lp.alpha0;  // pending pivot's alpha
   double* __restrict__ al_n = cur ? lp.alpha0 : lp.alpha1;        // FTRAN result for q
+  const double eps_p = lp.eps_p, eps_z = lp.eps_z;
+  int c = 0;
+  if (sparse) {
+    // rho and a_q on the columns of D, in D order.
+    double* s_rd = reinterpret_cast<double*>(smem2);
+    double* s_ad = s_rd + nD;
+    int* s_dl = reinterpret_cast<int*>(s_ad + nD);
+    int nz = 0;
+    for (int a = threadIdx.x; a < nD; a += kUpdateBlock) {
+      const int j = lp.dlist[a];
+      s_dl[a] = j;
+      const double rr = r >= 0 ? lp.rho[j] : 0.0;
+      s_rd[a] = rr;
+      nz += rr != 0.0 ? 1 : 0;
+      if (q >= 0) s_ad[a] = q < n ? lp.A[(size_t)q * lp.ld + j] : (j == q - n ? 1.0 : 0.0);
+    }
+    if (blockIdx.x == 0) {
+      // bytes: D entries read in every row but r, the changed ones written in every
+      // row, and one unit lookup (basis, membership, a_q entry) per row
+      nz = block_sum_int<kUpdateBlock>(nz, red_j);
+      if (threadIdx.x == 0)
+        lp.ctrl->update_bytes += 8 * ((int64_t)(m - 1) * nD + (int64_t)m * nz) + 16 * (int64_t)m;
+    }
+    __syncthreads();
+    for (int i = gw; i < m; i += nw, ++c) {
+      double* row = lp.Binv + (size_t)i * lp.ld;
+      const bool isr = i == r;
+      const double na = (r >= 0 && !isr) ? -al_p[i] : 0.0;
+      double acc = 0.0;
+      for (int a = lane; a < nD; a += 64) {
+        const int j = s_dl[a];
+        double val;
+        if (r >= 0) {
+          const double rr = s_rd[a];
+          if (isr) {
+            val = rr;  // row r := rho (zero wherever rho is zero already)
+          } else {
+            val = fma(na, rr, row[j]);
+          }
+          if (rr != 0.0) row[j] = val;
+        } else {
+          val = row[j];
+        }
+        if (q >= 0) acc = fma(val, s_ad[a], acc);
+      }
+      double x = lp.xB[i];
+      if (r >= 0) {
+        x = isr ? theta : fma(na, theta, x);
+        if (fabs(x) < eps_z) x = 0.0;
+        if (lane == 0) lp.xB[i] = x;
+      }
+      if (q >= 0) {
+        acc = wave_sum(acc);
+        // the unit column of this row's basic slack, when it is not in D
+        const int bv = lp.basis[i];
+        if (bv >= n && !lp.inD[bv - n]) {
+          const int j = bv - n;
+          acc += q < n ? lp.A[(size_t)q * lp.ld + j] : (j == q - n ? 1.0 : 0.0);
+        }
+        double rt = __builtin_inf(), tau = __builtin_inf();
+        if (acc > eps_p) {
+          const double xp = fmax(x, 0.0);
+          rt = xp / acc;
+          tau = (xp - lp.eps_t) / acc;
+          tau -= 1e-12 * (fabs(tau) + 1.0);
+        }
+        if (lane == 0) {
+          al_n[i] = acc;
+          s_rt[wave * kMaxRowsPerWave + c] = rt;
+          s_tau[wave * kMaxRowsPerWave + c] = tau;
+          s_row[wave * kMaxRowsPerWave + c] = i;
+        }
+      }
+    }
+  } else {
   double2* s_rho = smem2;
   double2* s_a = smem2 + ld2;
   if (r >= 0) {
@@ -358,8 +442,6 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   }
   __syncthreads();
 
-  const double eps_p = lp.eps_p, eps_z = lp.eps_z;
-  int c = 0;
   for (int i = gw; i < m; i += nw, ++c) {
     double2* row = reinterpret_cast<double2*>(lp.Binv + (size_t)i * lp.ld);
     const bool first = c == 0 && pre;
@@ -399,6 +481,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
         s_row[wave * kMaxRowsPerWave + c] = i;
       }
     }
+  }
   }
   if (q < 0) return;
   // Workgroup partial of Step 6: (min ratio, lowest row attaining it) and the two
@@ -554,6 +637,11 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
     const double dq = ctl->dq;
     const int leave = lp.basis[r];
     if (lp.tenure > 0) lp.tabu_until[leave] = (int)(t + lp.tenure);
+    if (leave >= lp.n && !lp.inD[leave - lp.n]) {  // its column of B^-1 stops being a unit vector
+      lp.inD[leave - lp.n] = 1;
+      lp.dlist[ctl->nD] = leave - lp.n;
+      ctl->nD += 1;
+    }
     ctl->z = fma(dq, thr, ctl->z);
     lp.basis[r] = q;
     lp.pos[q] = r;

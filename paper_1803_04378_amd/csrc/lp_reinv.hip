@@ -458,13 +458,23 @@ __global__ void k_reinv_w_sum(double* __restrict__ W0, double* __restrict__ W1, 
 
 // z = chat_B^T x_B over the structural basic variables, then the control block: the new
 // B^-1 already reflects the last pivot, so no row update is pending any more.
-__global__ __launch_bounds__(1024) void k_reinv_finish(Ctrl* ctl, int k, const int32_t* __restrict__ kcol,
+// Also resets the list D of columns of B^-1 that may differ from unit vectors to the
+// columns of the rows whose slack is nonbasic (rowlist[0..k)): after the reinversion every
+// other column is exactly a unit vector.
+__global__ __launch_bounds__(1024) void k_reinv_finish(Ctrl* ctl, int m, int k, const int32_t* __restrict__ kcol,
                                                        const int32_t* __restrict__ kpos,
+                                                       const int32_t* __restrict__ rowlist,
+                                                       const int32_t* __restrict__ colmap,
+                                                       int32_t* __restrict__ dlist, int32_t* __restrict__ inD,
                                                        const double* __restrict__ chat,
                                                        const double* __restrict__ xB,
                                                        const int32_t* __restrict__ info) {
   __shared__ double red[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (*info == 0) {
+    for (int j = tid; j < m; j += 1024) inD[j] = colmap[j] >= 0 ? 1 : 0;
+    for (int a = tid; a < k; a += 1024) dlist[a] = rowlist[a];
+  }
   double acc = 0.0;
   for (int b = tid; b < k; b += 1024) acc = fma(chat[kcol[b]], xB[kpos[b]], acc);
 #pragma unroll
@@ -477,6 +487,7 @@ __global__ __launch_bounds__(1024) void k_reinv_finish(Ctrl* ctl, int k, const i
     if (*info == 0) {
       ctl->z = z;
       ctl->r = -1;
+      ctl->nD = k;
       ctl->n_reinv += 1;
     } else {
       ctl->n_reinv_failed += 1;
@@ -1002,8 +1013,8 @@ int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s,
     hipLaunchKernelGGL(k_reinv_w_small, dim3((ld + 255) / 256), dim3(256), 0, s, d.W0, d.W1, (const Ctrl*)d.ctrl, ld,
                        k, colmap_d, kcol_d, d.chat, (const double*)st->X, (const int32_t*)info);
     R_HIP(hipGetLastError(), "launching W");
-    hipLaunchKernelGGL(k_reinv_finish, dim3(1), dim3(1024), 0, s, d.ctrl, k, kcol_d, kpos_d, d.chat,
-                       (const double*)d.xB, (const int32_t*)info);
+    hipLaunchKernelGGL(k_reinv_finish, dim3(1), dim3(1024), 0, s, d.ctrl, m, k, kcol_d, kpos_d, rowlist_d, colmap_d,
+                       d.dlist, d.inD, d.chat, (const double*)d.xB, (const int32_t*)info);
     R_HIP(hipGetLastError(), "launching the finish");
   } else {
     const size_t total = (size_t)m * ld;
@@ -1020,8 +1031,8 @@ int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s,
     hipLaunchKernelGGL(k_reinv_w_sum, dim3((ld + 255) / 256), dim3(256), 0, s, d.W0, d.W1, (const Ctrl*)d.ctrl,
                        (const double*)st->part, ld, nchunk, (const int32_t*)info);
     R_HIP(hipGetLastError(), "launching W");
-    hipLaunchKernelGGL(k_reinv_finish, dim3(1), dim3(1024), 0, s, d.ctrl, k, kcol_d, kpos_d, d.chat,
-                       (const double*)d.xB, (const int32_t*)info);
+    hipLaunchKernelGGL(k_reinv_finish, dim3(1), dim3(1024), 0, s, d.ctrl, m, k, kcol_d, kpos_d, rowlist_d, colmap_d,
+                       d.dlist, d.inD, d.chat, (const double*)d.xB, (const int32_t*)info);
     R_HIP(hipGetLastError(), "launching the finish");
   }
   if (k_out) *k_out = k;

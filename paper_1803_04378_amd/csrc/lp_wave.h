@@ -116,15 +116,17 @@ __device__ int block_sum_int(int v, int* si) {
 }
 
 // Streaming helpers.  Lane l of a wavefront owns elements l, l+64, l+128, ... of a
-// contiguous FP64 vector held as n2 double2; a batch is kBatch such elements per lane
-// (16 KB per wavefront in flight at kBatch = 8).  Every dot product below is the lane's
-// fma chain over its elements in ascending order followed by the xor butterfly, whatever
-// the batching, so results do not depend on launch shape.
+// contiguous FP64 vector held as n2 double2; a batch is NB such elements per lane (the
+// size of the register array passed in: 16 KB per wavefront in flight at NB = kBatch = 8).
+// Every dot product below is the lane's fma chain over its elements in ascending order
+// followed by the xor butterfly, whatever the batching, so results depend neither on NB
+// nor on launch shape.
 typedef double v2d __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void load_batch(const double2* __restrict__ x, int k0, int n2, double2 (&v)[kBatch]) {
+template <int NB>
+__device__ __forceinline__ void load_batch(const double2* __restrict__ x, int k0, int n2, double2 (&v)[NB]) {
 #pragma unroll
-  for (int u = 0; u < kBatch; ++u) {
+  for (int u = 0; u < NB; ++u) {
     const int k = k0 + 64 * u;
     if (k < n2) v[u] = x[k];
   }
@@ -132,9 +134,10 @@ __device__ __forceinline__ void load_batch(const double2* __restrict__ x, int k0
 
 // The same with the non-temporal hint (streamed data that should not displace the
 // matrix the next kernel re-reads).
-__device__ __forceinline__ void load_batch_nt(const double2* __restrict__ x, int k0, int n2, double2 (&v)[kBatch]) {
+template <int NB>
+__device__ __forceinline__ void load_batch_nt(const double2* __restrict__ x, int k0, int n2, double2 (&v)[NB]) {
 #pragma unroll
-  for (int u = 0; u < kBatch; ++u) {
+  for (int u = 0; u < NB; ++u) {
     const int k = k0 + 64 * u;
     if (k < n2) {
       const v2d t = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(x + k));
@@ -144,18 +147,18 @@ __device__ __forceinline__ void load_batch_nt(const double2* __restrict__ x, int
 }
 
 // dot(x, y) with x in HBM and y in LDS; `pre` says v already holds the first batch.
-template <bool NT>
+template <bool NT, int NB>
 __device__ __forceinline__ double wave_dot(const double2* __restrict__ x, const double2* y, int n2, int lane,
-                                           double2 (&v)[kBatch], bool pre) {
+                                           double2 (&v)[NB], bool pre) {
   double acc = 0.0;
-  for (int k0 = lane; k0 < n2; k0 += 64 * kBatch) {
+  for (int k0 = lane; k0 < n2; k0 += 64 * NB) {
     if (!pre) {
       if (NT) load_batch_nt(x, k0, n2, v);
       else load_batch(x, k0, n2, v);
     }
     pre = false;
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
+    for (int u = 0; u < NB; ++u) {
       const int k = k0 + 64 * u;
       if (k < n2) {
         const double2 w = y[k];
@@ -170,15 +173,15 @@ __device__ __forceinline__ double wave_dot(const double2* __restrict__ x, const 
 // row <- row + na * rho (in place), returning dot(new row, a) when DOT.  An element pair
 // whose rho entries are both zero is unchanged by the fma, so it is not written back
 // (the pivot row of B^-1 has a zero wherever the column belongs to a basic slack).
-template <bool DOT>
+template <bool DOT, int NB>
 __device__ __forceinline__ double wave_update_dot(double2* __restrict__ row, const double2* rho, const double2* a,
-                                                  double na, int n2, int lane, double2 (&v)[kBatch], bool pre) {
+                                                  double na, int n2, int lane, double2 (&v)[NB], bool pre) {
   double acc = 0.0;
-  for (int k0 = lane; k0 < n2; k0 += 64 * kBatch) {
+  for (int k0 = lane; k0 < n2; k0 += 64 * NB) {
     if (!pre) load_batch(row, k0, n2, v);
     pre = false;
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
+    for (int u = 0; u < NB; ++u) {
       const int k = k0 + 64 * u;
       if (k < n2) {
         const double2 rr = rho[k];

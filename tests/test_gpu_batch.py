@@ -108,6 +108,29 @@ def test_batch_degenerate_and_special_lps(lpg):
             _check_against_serial(lpg, lps, res, bt, range(len(lps)))
 
 
+def test_batch_sparse_column_mode(lpg):
+    """LPs long enough (ld >= 1024) for the update and FTRAN to switch to the columns of
+    B^-1 that can differ from unit vectors: the batched solver takes the same switch, so it
+    still equals lp_solve bit for bit."""
+    lps = [lpgen.dense_lp(11 + k, m, 2 * m) for k, m in enumerate((1024, 1100, 1257))]
+    lps.append(lpgen.degenerate_lp(4, 1030, 2060, budget_row=True))
+    _say("case: batch of 4 LPs m in {1024, 1100, 1257, 1030 degenerate}")
+    for small_m in (0, -1):
+        with lpg.Batch(lps, batch_small_m=small_m) as bt:
+            bt.solve()
+            res = bt.results()
+            _check_against_serial(lpg, lps, res, bt, range(len(lps)))
+        assert (res["status"][:3] == oracle.OPTIMAL).all()
+    # the serial run did use sparse mode: less than the dense read of B^-1 per launch
+    A, b, c = lps[1]
+    with lpg.LP(A, b, c, profile=1) as p:
+        p.solve()
+        st = p.stats()
+    m = A.shape[0]
+    assert st["update_launches"] > 0
+    assert st["update_bytes"] < 8.0 * m * m * st["update_launches"]
+
+
 def test_batch_iteration_limit(lpg):
     lps = _mixed_batch(5, 12, 30, 80)
     with lpg.Batch(lps, max_iter=7) as bt:

@@ -90,7 +90,8 @@ def _feasible_state(A, b, c, p, basis):
     assert xB.min() >= 0.0
     assert np.abs(xB - xt).max() <= 1e-6 * (1.0 + np.abs(xt).max())
     chat = np.concatenate([-c, np.zeros(m)])
-    assert np.abs(W - np.linalg.solve(B.T, chat[basis])).max() <= 1e-6
+    Wt = np.linalg.solve(B.T, chat[basis])
+    assert np.abs(W - Wt).max() <= 1e-6 * (1.0 + np.abs(Wt).max())
 
 
 def test_degenerate_5000x10000(lpg):
