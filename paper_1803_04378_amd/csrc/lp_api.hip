@@ -422,6 +422,8 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   ALLOC(p->d.part_low, (size_t)p->update_grid);
   ALLOC(p->d.part_t1, (size_t)p->update_grid);
   ALLOC(p->d.part_t2, (size_t)p->update_grid);
+  ALLOC(p->d.part_al, (size_t)p->update_grid);
+  ALLOC(p->d.part_bv, (size_t)p->update_grid);
   ALLOC(p->d.ctrl, 1);
   ALLOC(p->b0, (size_t)m);
   ALLOC(p->c0, (size_t)std::max(n, 1));

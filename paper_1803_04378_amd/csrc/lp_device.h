@@ -116,6 +116,8 @@ struct DevLP {
   int32_t* part_low;  // and the two smallest tie thresholds tau of its rows
   double* part_t1;
   double* part_t2;
+  double* part_al;    // for the lowest row attaining the min ratio: its alpha, and its basic
+  int32_t* part_bv;   //   variable v as 2v + 1 when v is structural or a slack in list D, else 2v
   Ctrl* ctrl;
   int64_t log_cap;
   int32_t price_grid;   // workgroups of k_price (partials to reduce)
@@ -145,8 +147,6 @@ __device__ __forceinline__ const double* pricing_w(const DevLP& lp) {
   return (lp.ctrl->wcur != 0) != other ? lp.W1 : lp.W0;
 }
 
-// Mixed form: does the re-priced shortlist hold an improving column?  Every thread reads
-// the same entries, so all workgroups of a launch agree.
 // Sparse-column mode of the update and FTRAN (k_update and the batched solver take the
 // same decision, so their arithmetic stays identical): used while at most ld/8 columns of
 // B^-1 can differ from unit vectors, and only for rows long enough (ld >= 1024) that
@@ -154,13 +154,6 @@ __device__ __forceinline__ const double* pricing_w(const DevLP& lp) {
 constexpr int kSparseMinLd = 1024;
 __host__ __device__ __forceinline__ bool sparse_columns(int nD, int ld) {
   return ld >= kSparseMinLd && nD * 8 <= ld;
-}
-
-__device__ __forceinline__ bool shortlist_improves(const DevLP& lp) {
-  const double neg_eps = -lp.eps_d;
-  for (int w = 0; w < lp.sl_k; ++w)
-    if (lp.sl_j[w] != INT_MAX && lp.sl_d[w] < neg_eps) return true;
-  return false;
 }
 
 // Launchers (lp_kernels.hip).  grid sizes are chosen by the caller.

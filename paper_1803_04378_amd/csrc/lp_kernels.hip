@@ -78,6 +78,24 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
   }
 }
 
+// Mixed form: the best improving column of the re-priced shortlist as (d, j), or
+// (inf, INT_MAX) when it holds none (its columns are all non-tabu).  Lane w reads entry w
+// and a wavefront minimum combines them, so every wavefront gets the same answer.
+__device__ __forceinline__ void shortlist_best(const DevLP& lp, double& d, int& j) {
+  const int lane = threadIdx.x & 63;
+  d = __builtin_inf();
+  j = INT_MAX;
+  if (lane < lp.sl_k) {
+    const double dw = lp.sl_d[lane];
+    const int jw = lp.sl_j[lane];
+    if (jw != INT_MAX && dw < -lp.eps_d) {
+      d = dw;
+      j = jw;
+    }
+  }
+  wave_lexmin(d, j);
+}
+
 // ---------------------------------------------------------------------------------------
 // Steps 3-4, preceded by Step 8 on the top row of the tableau for the pending pivot:
 // every workgroup forms W_new = W + d_q rho, rho = B^-1[r,:] / alpha_r, while staging it
@@ -86,11 +104,6 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
 // form k_price32 has done that already, and this pass runs only when the re-priced
 // shortlist holds no improving column.
 __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
-  if (lp.ctrl->status != kStatusRunning) return;
-  if (lp.mixed && shortlist_improves(lp)) return;
-  const int64_t t = lp.ctrl->t;
-  const int r = lp.ctrl->r;
-  const int wc = lp.ctrl->wcur;
   extern __shared__ double2 s_w2[];
   __shared__ double red_d[2 * (kPriceBlock / 64)];
   __shared__ int red_j[2 * (kPriceBlock / 64)];
@@ -101,9 +114,16 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
   const int gw = blockIdx.x * waves + wave;
   const int nw = gridDim.x * waves;
 
-  // Issued before the staging below so that their latency overlaps it: the state of
-  // this wave's columns (lane c holds column gw + c*nw) and the first batch of its first
-  // column of A'.
+  // Requested together, before anything waits on memory: the control block, the state of
+  // this wave's columns (lane c holds column gw + c*nw) and, in the FP64 form, the first
+  // batch of its first column of A' (read even when the solve has stopped; then unused).
+  const Ctrl* ctl = lp.ctrl;
+  const int status = ctl->status;
+  const int64_t t = ctl->t;
+  const int r = ctl->r;
+  const int wc = ctl->wcur;
+  const double ar = ctl->ar;
+  const double dq = ctl->pdq;
   const int jl = gw + lane * nw;
   int c_pos = 0, c_tabu = 0;
   double c_chat = 0.0;
@@ -113,16 +133,21 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
     c_chat = lp.chat[jl];
   }
   double2 v[kBatch];
-  const bool pre = gw < n;
+  const bool pre = gw < n && !lp.mixed;
   if (pre) {
     if (kStreamA) load_batch_nt(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
     else load_batch(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
   }
+  if (status != kStatusRunning) return;
+  if (lp.mixed) {
+    double d;
+    int j;
+    shortlist_best(lp, d, j);
+    if (j != INT_MAX) return;
+  }
 
   if (r >= 0 && !lp.mixed) {
     const double2* Wold = reinterpret_cast<const double2*>(wc ? lp.W1 : lp.W0);
-    const double ar = lp.ctrl->ar;
-    const double dq = lp.ctrl->pdq;
     const double2* rowr = reinterpret_cast<const double2*>(lp.Binv + (size_t)r * lp.ld);
     double2* Wnew = reinterpret_cast<double2*>(wc ? lp.W0 : lp.W1);
     double2* rho2 = reinterpret_cast<double2*>(lp.rho);
@@ -145,7 +170,8 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
       if (threadIdx.x == 0) lp.ctrl->rho_nz2 = nz2;
     }
   } else {
-    const double2* W2 = reinterpret_cast<const double2*>(pricing_w(lp));
+    // the top row to price with (as pricing_w)
+    const double2* W2 = reinterpret_cast<const double2*>((wc != 0) != (r >= 0) ? lp.W1 : lp.W0);
     for (int k = threadIdx.x; k < ld2; k += kPriceBlock) s_w2[k] = W2[k];
   }
   __syncthreads();
@@ -228,85 +254,179 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
 // Section 3.1 update of the pending pivot (rows of B^-1 and x_B) fused with Step 5 for
 // the newly priced q and with the per-row part of Step 6.  Every workgroup first reduces
 // the pricing partials itself (a lexicographic minimum, so all of them agree on q).
+//
+// The kernel is short on data and long on dependent memory accesses, so it is laid out
+// as two rounds of requests: first everything that depends only on earlier kernels (the
+// control block, the pricing partials or the shortlist, rho, the head of list D, the
+// state of this wavefront's first row), then what depends on q (the column a_q, the row
+// entries of sparse mode).  rho and a_q are staged whole in LDS, so the sparse mode's
+// per-column lookups and the unit term of a row's basic slack are LDS reads.
+
+// A vector of up to 5 * kUpdateBlock double2 (ld <= 10240) loaded by one workgroup into
+// registers, five per thread, with clamped indices (no branch for a load to wait behind).
+// Held as native vectors: copies of the double2 struct go through a stack temporary.
+struct Hold5 {
+  v2d h0, h1, h2, h3, h4;
+};
+constexpr int kUpdRegs = 5;
+// Load batch of the dense row update: 4 double2 per lane (the 8 of the streaming kernels
+// would not leave room for the staged vectors within 128 VGPRs).
+constexpr int kUpdBatch = 4;
+__device__ __forceinline__ void hold_load(Hold5& h, const double2* __restrict__ src2, int tid, int n2) {
+  constexpr int B = kUpdateBlock;
+  const v2d* src = reinterpret_cast<const v2d*>(src2);
+  h.h0 = src[min(tid, n2 - 1)];
+  h.h1 = src[min(tid + B, n2 - 1)];
+  h.h2 = src[min(tid + 2 * B, n2 - 1)];
+  h.h3 = src[min(tid + 3 * B, n2 - 1)];
+  h.h4 = src[min(tid + 4 * B, n2 - 1)];
+}
+// Stores what hold_load read into dst (LDS), then copies any part beyond 5 * kUpdateBlock.
+__device__ __forceinline__ void hold_store(const Hold5& h, double2* dst2, const double2* __restrict__ src2, int tid,
+                                           int n2) {
+  constexpr int B = kUpdateBlock;
+  v2d* dst = reinterpret_cast<v2d*>(dst2);
+  const v2d* src = reinterpret_cast<const v2d*>(src2);
+  if (tid < n2) dst[tid] = h.h0;
+  if (tid + B < n2) dst[tid + B] = h.h1;
+  if (tid + 2 * B < n2) dst[tid + 2 * B] = h.h2;
+  if (tid + 3 * B < n2) dst[tid + 3 * B] = h.h3;
+  if (tid + 4 * B < n2) dst[tid + 4 * B] = h.h4;
+  for (int k = tid + kUpdRegs * B; k < n2; k += B) dst[k] = src[k];
+}
+// Entries of list D per lane gathered from a row in one round (nD <= 512); the rest, if
+// any, follow in a loop.
+constexpr int kGather = 8;
+
 __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
-  if (lp.ctrl->status != kStatusRunning) return;
-  const int r = lp.ctrl->r;
-  const int64_t t = lp.ctrl->t;
-  // Sparse mode: while few columns of B^-1 can differ from unit vectors, the update and
-  // FTRAN touch only those (list D); the unit columns contribute one entry per row.
-  const int nD = lp.ctrl->nD;
-  const bool sparse = sparse_columns(nD, lp.ld);
+  constexpr int B = kUpdateBlock, waves = B / 64;
   extern __shared__ double2 smem2[];
-  __shared__ double red_d[2 * (kUpdateBlock / 64)];
-  __shared__ int red_j[2 * (kUpdateBlock / 64)];
-  constexpr int waves = kUpdateBlock / 64;
+  __shared__ double red_d[2 * waves];
+  __shared__ int red_j[2 * waves];
   __shared__ double s_rt[waves * kMaxRowsPerWave];
   __shared__ double s_tau[waves * kMaxRowsPerWave];
   __shared__ int s_row[waves * kMaxRowsPerWave];
-  const int m = lp.m, n = lp.n, ld2 = lp.ld / 2;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  __shared__ double s_al[waves * kMaxRowsPerWave];
+  __shared__ int s_bv[waves * kMaxRowsPerWave];
+  const int m = lp.m, n = lp.n, ld = lp.ld, ld2 = ld / 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int gw = blockIdx.x * waves + wave;
   const int nw = gridDim.x * waves;
+  double2* s_rho = smem2;
+  double2* s_a = smem2 + ld2;
+  int* s_dl = reinterpret_cast<int*>(smem2 + 2 * ld2);
+  // Sparse mode reads at most ld/8 entries of D (<= m, the list's capacity); below
+  // kSparseMinLd the update is always dense.
+  const bool can_sparse = ld >= kSparseMinLd;
+  const int dcap = can_sparse ? ld / 8 : 0;
 
-  // The first batch of this wave's first row is in flight while the entering column is
-  // decided and staged.
-  double2 v[kBatch];
-  const bool pre = !sparse && gw < m && gw != r;
-  if (pre) load_batch(reinterpret_cast<const double2*>(lp.Binv + (size_t)gw * lp.ld), lane, ld2, v);
+  // ---- first round: requests that depend only on the previous kernels ----
+  const Ctrl* ctl = lp.ctrl;
+  const int status = ctl->status;
+  const int r = ctl->r;
+  const int nD = ctl->nD;
+  const int cur = ctl->cur;
+  const int64_t t = ctl->t;
+  const int64_t max_iter = ctl->max_iter;
+  const double theta = ctl->theta;
+  // Indices are clamped into range rather than guarded, so that no load waits behind a
+  // branch; the values of clamped lanes are discarded below.
+  const int pk = min(tid, lp.price_grid - 1);
+  double pd0 = lp.part_d[2 * pk], pd1 = lp.part_d[2 * pk + 1];
+  int pj0 = lp.part_j[2 * pk], pj1 = lp.part_j[2 * pk + 1];
+  const double2* rho2 = reinterpret_cast<const double2*>(lp.rho);
+  Hold5 hold;
+  hold_load(hold, rho2, tid, ld2);  // unused if no pivot is pending
+  int dl0 = 0, dl1 = 0;
+  if (can_sparse) {
+    dl0 = lp.dlist[min(tid, dcap - 1)];
+    dl1 = lp.dlist[min(tid + B, dcap - 1)];
+  }
+  const int g0 = min(gw, m - 1);
+  double x0 = lp.xB[g0], al00 = lp.alpha0[g0], al10 = lp.alpha1[g0];
+  int bv0 = lp.basis[g0];
+  double2 v[kUpdBatch];
+  const bool pre_now = !can_sparse && gw < m;  // dense for certain: first batch of the row now
+  if (pre_now) load_batch(reinterpret_cast<const double2*>(lp.Binv + (size_t)gw * ld), lane, ld2, v);
+  double sd = __builtin_inf();
+  int sj = INT_MAX;
+  if (lp.mixed) {
+    const int w = min(lane, lp.sl_k - 1);
+    sd = lp.sl_d[w];
+    sj = lp.sl_j[w];
+  }
+  // Compiler-only barrier (no instruction): every request above is issued before any of
+  // the code below waits on one.
+  asm volatile("" ::: "memory");
+  if (tid >= lp.price_grid) {
+    pd0 = pd1 = __builtin_inf();
+    pj0 = pj1 = INT_MAX;
+  }
+
+  hold_store(hold, s_rho, rho2, tid, ld2);
+  if (tid < dcap) s_dl[tid] = dl0;
+  if (tid + B < dcap) s_dl[tid + B] = dl1;
 
   // Step 4 decision: from the re-priced shortlist in the mixed form when it holds an
-  // improving column (all of its columns are non-tabu), else from the pricing partials.
+  // improving column, else from the pricing partials.
   double da = __builtin_inf(), df = __builtin_inf();
   int ja = INT_MAX, jf = INT_MAX;
-  const bool from_shortlist = lp.mixed && shortlist_improves(lp);
-  if (from_shortlist) {
-    const double neg_eps = -lp.eps_d;
-    for (int w = 0; w < lp.sl_k; ++w) {
-      const double d = lp.sl_d[w];
-      const int j = lp.sl_j[w];
-      if (j != INT_MAX && d < neg_eps && lex_less(d, j, df, jf)) {
-        df = d;
-        jf = j;
-      }
+  bool from_shortlist = false;
+  if (lp.mixed) {
+    // the best improving column of the re-priced shortlist (as shortlist_best)
+    if (!(lane < lp.sl_k && sj != INT_MAX && sd < -lp.eps_d)) {
+      sd = __builtin_inf();
+      sj = INT_MAX;
     }
+    wave_lexmin(sd, sj);
+    df = sd;
+    jf = sj;
+    from_shortlist = jf != INT_MAX;
     da = df;
     ja = jf;
-  } else {
-  for (int k = threadIdx.x; k < lp.price_grid; k += kUpdateBlock) {
-    const double d0 = lp.part_d[2 * k], d1 = lp.part_d[2 * k + 1];
-    const int j0 = lp.part_j[2 * k], j1 = lp.part_j[2 * k + 1];
-    if (lex_less(d0, j0, da, ja)) {
-      da = d0;
-      ja = j0;
+  }
+  if (!from_shortlist) {
+    da = pd0;
+    ja = pj0;
+    df = pd1;
+    jf = pj1;
+    for (int k = tid + B; k < lp.price_grid; k += B) {
+      const double d0 = lp.part_d[2 * k], d1 = lp.part_d[2 * k + 1];
+      const int j0 = lp.part_j[2 * k], j1 = lp.part_j[2 * k + 1];
+      if (lex_less(d0, j0, da, ja)) {
+        da = d0;
+        ja = j0;
+      }
+      if (lex_less(d1, j1, df, jf)) {
+        df = d1;
+        jf = j1;
+      }
     }
-    if (lex_less(d1, j1, df, jf)) {
-      df = d1;
-      jf = j1;
+    wave_lexmin(da, ja);
+    wave_lexmin(df, jf);
+    if (lane == 0) {
+      red_d[wave] = da;
+      red_j[wave] = ja;
+      red_d[waves + wave] = df;
+      red_j[waves + wave] = jf;
     }
+    __syncthreads();
+    da = lane < waves ? red_d[lane] : __builtin_inf();
+    ja = lane < waves ? red_j[lane] : INT_MAX;
+    df = lane < waves ? red_d[waves + lane] : __builtin_inf();
+    jf = lane < waves ? red_j[waves + lane] : INT_MAX;
+    wave_lexmin(da, ja);  // every wave reduces the same values: no second exchange needed
+    wave_lexmin(df, jf);
   }
-  wave_lexmin(da, ja);
-  wave_lexmin(df, jf);
-  if (lane == 0) {
-    red_d[wave] = da;
-    red_j[wave] = ja;
-    red_d[waves + wave] = df;
-    red_j[waves + wave] = jf;
-  }
-  __syncthreads();
-  da = lane < waves ? red_d[lane] : __builtin_inf();
-  ja = lane < waves ? red_j[lane] : INT_MAX;
-  df = lane < waves ? red_d[waves + lane] : __builtin_inf();
-  jf = lane < waves ? red_j[waves + lane] : INT_MAX;
-  wave_lexmin(da, ja);  // every wave reduces the same values: no second exchange needed
-  wave_lexmin(df, jf);
-  }
-  int status = kStatusRunning, q = -1, flags = 0;
+  __syncthreads();  // rho and D are in LDS
+  if (status != kStatusRunning) return;
+  const bool sparse = sparse_columns(nD, ld);
+  int verdict = kStatusRunning, q = -1, flags = 0;
   double dq = 0.0;
   if (ja == INT_MAX) {
-    status = kStatusOptimal;
-  } else if (t >= lp.ctrl->max_iter) {
-    status = kStatusIterLimit;
+    verdict = kStatusOptimal;
+  } else if (t >= max_iter) {
+    verdict = kStatusIterLimit;
   } else if (jf != INT_MAX) {
     q = jf;
     dq = df;
@@ -315,86 +435,124 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
     dq = da;
     flags = kFlagAspiration;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && tid == 0) {
     // Only fields no k_update workgroup reads: the status itself changes in k_finish.
-    Ctrl* ctl = lp.ctrl;
-    if (lp.mixed) ctl->price32_launches += 1;
+    Ctrl* cw = lp.ctrl;
+    if (lp.mixed) cw->price32_launches += 1;
     if (!from_shortlist) {
-      ctl->price_cols += n - ctl->nsb;
-      ctl->price_launches += 1;
-      if (lp.mixed) ctl->full_prices += 1;
+      cw->price_cols += n - cw->nsb;
+      cw->price_launches += 1;
+      if (lp.mixed) cw->full_prices += 1;
     }
-    if (r >= 0) ctl->wcur ^= 1;  // pricing stored W_new: it is the current top row now
-    ctl->verdict = status;
-    ctl->q = q;
-    ctl->dq = dq;
-    ctl->flags = flags;
-    if (flags & kFlagAspiration) ctl->n_aspiration += 1;
+    if (r >= 0) cw->wcur ^= 1;  // pricing stored W_new: it is the current top row now
+    cw->verdict = verdict;
+    cw->q = q;
+    cw->dq = dq;
+    cw->flags = flags;
+    if (flags & kFlagAspiration) cw->n_aspiration += 1;
     if (r >= 0) {
-      ctl->update_launches += 1;
-      ctl->update_rows_written += m;
+      cw->update_launches += 1;
+      cw->update_rows_written += m;
     } else if (q >= 0) {
-      ctl->update_launches += 1;
+      cw->update_launches += 1;
     }
     if (!sparse && (r >= 0 || q >= 0)) {
       // read all of B^-1; write the pairs with a nonzero rho entry in every row but r,
       // and all of row r
-      ctl->update_bytes += 8 * (int64_t)m * m;
-      if (r >= 0) ctl->update_bytes += 16 * ((int64_t)(m - 1) * ctl->rho_nz2 + lp.ld / 2);
+      cw->update_bytes += 8 * (int64_t)m * m;
+      if (r >= 0) cw->update_bytes += 16 * ((int64_t)(m - 1) * cw->rho_nz2 + ld / 2);
     }
   }
   if (r < 0 && q < 0) return;
 
-  const int cur = lp.ctrl->cur;
-  const double theta = lp.ctrl->theta;
+  // ---- second round: a_q, and this wave's first row where it depends on D ----
   const double* __restrict__ al_p = cur ? lp.alpha1 : lp.alpha0;  // pending pivot's alpha
   double* __restrict__ al_n = cur ? lp.alpha0 : lp.alpha1;        // FTRAN result for q
   const double eps_p = lp.eps_p, eps_z = lp.eps_z;
+  const bool q_col = q >= 0 && q < n;
+  const double2* aq2 = reinterpret_cast<const double2*>(lp.A + (size_t)(q_col ? q : 0) * ld);
+  if (q_col) hold_load(hold, aq2, tid, ld2);
+  const double* s_rhod = reinterpret_cast<const double*>(s_rho);
+  const double* s_ad = reinterpret_cast<const double*>(s_a);
+  // whether the first row's basic variable is a slack outside D (its B^-1 column is a
+  // unit vector): the sparse FTRAN adds its unit term, and k_finish needs it for the
+  // leaving variable
+  int in0 = 1;
+  if (gw < m && bv0 >= n) in0 = lp.inD[bv0 - n];
   int c = 0;
   if (sparse) {
-    // rho and a_q on the columns of D, in D order.
-    double* s_rd = reinterpret_cast<double*>(smem2);
-    double* s_ad = s_rd + nD;
-    int* s_dl = reinterpret_cast<int*>(s_ad + nD);
-    int nz = 0;
-    for (int a = threadIdx.x; a < nD; a += kUpdateBlock) {
-      const int j = lp.dlist[a];
-      s_dl[a] = j;
-      const double rr = r >= 0 ? lp.rho[j] : 0.0;
-      s_rd[a] = rr;
-      nz += rr != 0.0 ? 1 : 0;
-      if (q >= 0) s_ad[a] = q < n ? lp.A[(size_t)q * lp.ld + j] : (j == q - n ? 1.0 : 0.0);
+    double g[kGather];
+    if (gw < m) {
+      const double* row = lp.Binv + (size_t)gw * ld;
+#pragma unroll
+      for (int u = 0; u < kGather; ++u) {
+        const int a = lane + 64 * u;
+        if (a < nD) g[u] = row[s_dl[a]];
+      }
+    }
+    if (q_col) {
+      hold_store(hold, s_a, aq2, tid, ld2);
+    } else if (q >= 0) {
+      const int e = q - n;
+      for (int k = tid; k < ld2; k += B) s_a[k] = make_double2(2 * k == e ? 1.0 : 0.0, 2 * k + 1 == e ? 1.0 : 0.0);
     }
     if (blockIdx.x == 0) {
       // bytes: D entries read in every row but r, the changed ones written in every
       // row, and one unit lookup (basis, membership, a_q entry) per row
-      nz = block_sum_int<kUpdateBlock>(nz, red_j);
-      if (threadIdx.x == 0)
-        lp.ctrl->update_bytes += 8 * ((int64_t)(m - 1) * nD + (int64_t)m * nz) + 16 * (int64_t)m;
+      int nz = 0;
+      if (r >= 0)
+        for (int a = tid; a < nD; a += B) nz += s_rhod[s_dl[a]] != 0.0 ? 1 : 0;
+      nz = block_sum_int<B>(nz, red_j);
+      if (tid == 0) lp.ctrl->update_bytes += 8 * ((int64_t)(m - 1) * nD + (int64_t)m * nz) + 16 * (int64_t)m;
     }
-    __syncthreads();
+    __syncthreads();  // a_q is in LDS
     for (int i = gw; i < m; i += nw, ++c) {
-      double* row = lp.Binv + (size_t)i * lp.ld;
-      const bool isr = i == r;
-      const double na = (r >= 0 && !isr) ? -al_p[i] : 0.0;
-      double acc = 0.0;
-      for (int a = lane; a < nD; a += 64) {
-        const int j = s_dl[a];
-        double val;
-        if (r >= 0) {
-          const double rr = s_rd[a];
-          if (isr) {
-            val = rr;  // row r := rho (zero wherever rho is zero already)
-          } else {
-            val = fma(na, rr, row[j]);
-          }
-          if (rr != 0.0) row[j] = val;
-        } else {
-          val = row[j];
+      double* row = lp.Binv + (size_t)i * ld;
+      double x, alp;
+      int bv, in;
+      if (c == 0) {
+        x = x0;
+        alp = cur ? al10 : al00;
+        bv = bv0;
+        in = in0;
+      } else {
+        x = lp.xB[i];
+        alp = al_p[i];
+        bv = lp.basis[i];
+        in = bv >= n ? lp.inD[bv - n] : 1;
+#pragma unroll
+        for (int u = 0; u < kGather; ++u) {
+          const int a = lane + 64 * u;
+          if (a < nD) g[u] = row[s_dl[a]];
         }
-        if (q >= 0) acc = fma(val, s_ad[a], acc);
       }
-      double x = lp.xB[i];
+      const bool isr = i == r;
+      const double na = (r >= 0 && !isr) ? -alp : 0.0;
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < kGather; ++u) {
+        const int a = lane + 64 * u;
+        if (a < nD) {
+          const int j = s_dl[a];
+          double val = g[u];
+          if (r >= 0) {
+            const double rr = s_rhod[j];
+            val = isr ? rr : fma(na, rr, val);  // row r := rho (zero wherever rho is zero)
+            if (rr != 0.0) row[j] = val;
+          }
+          if (q >= 0) acc = fma(val, s_ad[j], acc);
+        }
+      }
+      for (int a = lane + 64 * kGather; a < nD; a += 64) {
+        const int j = s_dl[a];
+        double val = row[j];
+        if (r >= 0) {
+          const double rr = s_rhod[j];
+          val = isr ? rr : fma(na, rr, val);
+          if (rr != 0.0) row[j] = val;
+        }
+        if (q >= 0) acc = fma(val, s_ad[j], acc);
+      }
       if (r >= 0) {
         x = isr ? theta : fma(na, theta, x);
         if (fabs(x) < eps_z) x = 0.0;
@@ -403,11 +561,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
       if (q >= 0) {
         acc = wave_sum(acc);
         // the unit column of this row's basic slack, when it is not in D
-        const int bv = lp.basis[i];
-        if (bv >= n && !lp.inD[bv - n]) {
-          const int j = bv - n;
-          acc += q < n ? lp.A[(size_t)q * lp.ld + j] : (j == q - n ? 1.0 : 0.0);
-        }
+        if (bv >= n && !in) acc += s_ad[bv - n];
         double rt = __builtin_inf(), tau = __builtin_inf();
         if (acc > eps_p) {
           const double xp = fmax(x, 0.0);
@@ -420,68 +574,70 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
           s_rt[wave * kMaxRowsPerWave + c] = rt;
           s_tau[wave * kMaxRowsPerWave + c] = tau;
           s_row[wave * kMaxRowsPerWave + c] = i;
+          s_al[wave * kMaxRowsPerWave + c] = acc;
+          s_bv[wave * kMaxRowsPerWave + c] = 2 * bv + ((bv < n || in) ? 1 : 0);
         }
       }
     }
   } else {
-  double2* s_rho = smem2;
-  double2* s_a = smem2 + ld2;
-  if (r >= 0) {
-    const double2* rho2 = reinterpret_cast<const double2*>(lp.rho);
-    for (int k = threadIdx.x; k < ld2; k += kUpdateBlock) s_rho[k] = rho2[k];
-  }
-  if (q >= 0) {
-    if (q < n) {
-      const double2* a2 = reinterpret_cast<const double2*>(lp.A + (size_t)q * lp.ld);
-      for (int k = threadIdx.x; k < ld2; k += kUpdateBlock) s_a[k] = a2[k];
-    } else {
+    // dense mode with rows long enough for sparse mode: the first batch of the row now
+    const bool pre_late = can_sparse && gw < m;
+    if (pre_late) load_batch(reinterpret_cast<const double2*>(lp.Binv + (size_t)gw * ld), lane, ld2, v);
+    if (q_col) {
+      hold_store(hold, s_a, aq2, tid, ld2);
+    } else if (q >= 0) {
       const int e = q - n;
-      for (int k = threadIdx.x; k < ld2; k += kUpdateBlock)
-        s_a[k] = make_double2(2 * k == e ? 1.0 : 0.0, 2 * k + 1 == e ? 1.0 : 0.0);
+      for (int k = tid; k < ld2; k += B) s_a[k] = make_double2(2 * k == e ? 1.0 : 0.0, 2 * k + 1 == e ? 1.0 : 0.0);
     }
-  }
-  __syncthreads();
-
-  for (int i = gw; i < m; i += nw, ++c) {
-    double2* row = reinterpret_cast<double2*>(lp.Binv + (size_t)i * lp.ld);
-    const bool first = c == 0 && pre;
-    double acc;
-    double x = lp.xB[i];
-    if (r < 0) {
-      acc = wave_dot<false>(row, s_a, ld2, lane, v, first);
-    } else {
-      if (i == r) {
-        acc = q >= 0 ? wave_store_dot<true>(row, s_rho, s_a, ld2, lane)
-                     : wave_store_dot<false>(row, s_rho, s_a, ld2, lane);
-        x = theta;
+    __syncthreads();  // a_q is in LDS
+    const bool pre = pre_now || pre_late;
+    for (int i = gw; i < m; i += nw, ++c) {
+      double2* row = reinterpret_cast<double2*>(lp.Binv + (size_t)i * ld);
+      const bool first = c == 0 && pre;
+      double acc;
+      double x = c == 0 ? x0 : lp.xB[i];
+      int bv = bv0, in = in0;
+      if (c > 0 && q >= 0) {
+        bv = lp.basis[i];
+        in = bv >= n ? lp.inD[bv - n] : 1;
+      }
+      if (r < 0) {
+        acc = wave_dot<false>(row, s_a, ld2, lane, v, first);
       } else {
-        const double na = -al_p[i];
-        acc = q >= 0 ? wave_update_dot<true>(row, s_rho, s_a, na, ld2, lane, v, first)
-                     : wave_update_dot<false>(row, s_rho, s_a, na, ld2, lane, v, first);
-        x = fma(na, theta, x);
+        if (i == r) {
+          acc = q >= 0 ? wave_store_dot<true>(row, s_rho, s_a, ld2, lane)
+                       : wave_store_dot<false>(row, s_rho, s_a, ld2, lane);
+          x = theta;
+        } else {
+          const double na = -(c == 0 ? (cur ? al10 : al00) : al_p[i]);
+          acc = q >= 0 ? wave_update_dot<true>(row, s_rho, s_a, na, ld2, lane, v, first)
+                       : wave_update_dot<false>(row, s_rho, s_a, na, ld2, lane, v, first);
+          x = fma(na, theta, x);
+        }
+        if (fabs(x) < eps_z) x = 0.0;
+        if (lane == 0) lp.xB[i] = x;
       }
-      if (fabs(x) < eps_z) x = 0.0;
-      if (lane == 0) lp.xB[i] = x;
+      if (q >= 0) {
+        // ratio_i, and tau_i: the smallest step at which row i would count as tied
+        // (fma(-alpha_i, step, max(x_i, 0)) <= eps_t), lowered by a margin so that the
+        // filter in k_finish never misses a tied row.
+        double rt = __builtin_inf(), tau = __builtin_inf();
+        if (acc > eps_p) {
+          const double xp = fmax(x, 0.0);
+          rt = xp / acc;
+          tau = (xp - lp.eps_t) / acc;
+          tau -= 1e-12 * (fabs(tau) + 1.0);
+        }
+        if (lane == 0) {
+          al_n[i] = acc;
+          s_rt[wave * kMaxRowsPerWave + c] = rt;
+          s_tau[wave * kMaxRowsPerWave + c] = tau;
+          s_row[wave * kMaxRowsPerWave + c] = i;
+          s_al[wave * kMaxRowsPerWave + c] = acc;
+          s_bv[wave * kMaxRowsPerWave + c] = 2 * bv + ((bv < n || in) ? 1 : 0);
+        }
+      }
     }
-    if (q >= 0) {
-      // ratio_i, and tau_i: the smallest step at which row i would count as tied
-      // (fma(-alpha_i, step, max(x_i, 0)) <= eps_t), lowered by a margin so that the
-      // filter in k_finish never misses a tied row.
-      double rt = __builtin_inf(), tau = __builtin_inf();
-      if (acc > eps_p) {
-        const double xp = fmax(x, 0.0);
-        rt = xp / acc;
-        tau = (xp - lp.eps_t) / acc;
-        tau -= 1e-12 * (fabs(tau) + 1.0);
-      }
-      if (lane == 0) {
-        al_n[i] = acc;
-        s_rt[wave * kMaxRowsPerWave + c] = rt;
-        s_tau[wave * kMaxRowsPerWave + c] = tau;
-        s_row[wave * kMaxRowsPerWave + c] = i;
-      }
-    }
-  }
   }
   if (q < 0) return;
   // Workgroup partial of Step 6: (min ratio, lowest row attaining it) and the two
@@ -496,11 +652,12 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   if (wave == 0) {
     constexpr int slots = waves * kMaxRowsPerWave;
     double th = __builtin_inf(), t1 = __builtin_inf(), t2 = __builtin_inf();
-    int low = INT_MAX;
+    int low = INT_MAX, slot = 0;
     for (int k = lane; k < slots; k += 64) {
       if (lex_less(s_rt[k], s_row[k], th, low)) {
         th = s_rt[k];
         low = s_row[k];
+        slot = k;
       }
       const double tk = s_tau[k];
       if (tk < t1) {
@@ -510,37 +667,52 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
         t2 = tk;
       }
     }
-    wave_lexmin(th, low);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double o1 = __shfl_xor(t1, off), o2 = __shfl_xor(t2, off);
-      const double n1 = fmin(t1, o1);
-      t2 = fmin(fmax(t1, o1), fmin(t2, o2));
-      t1 = n1;
-    }
+    wave_lexmin_payload(th, low, slot);
+    wave_two_smallest(t1, t2);
     if (lane == 0) {
       lp.part_th[blockIdx.x] = th;
       lp.part_low[blockIdx.x] = low;
       lp.part_t1[blockIdx.x] = t1;
       lp.part_t2[blockIdx.x] = t2;
+      lp.part_al[blockIdx.x] = low != INT_MAX ? s_al[slot] : 0.0;
+      lp.part_bv[blockIdx.x] = low != INT_MAX ? s_bv[slot] : 0;
     }
   }
 }
 
 // ---------------------------------------------------------------------------------------
 // Step 6 finish and the scalar part of Step 8 (one workgroup).  Every k_update workgroup
-// left its minimum ratio (with the lowest row attaining it) and the two smallest tie
-// thresholds of its rows; x_B and alpha of this iteration are in memory.
+// left its minimum ratio (with the lowest row attaining it, that row's alpha and basic
+// variable) and the two smallest tie thresholds of its rows; x_B and alpha of this
+// iteration are in memory.
 __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
   constexpr int B = kUpdateBlock;
   __shared__ double red_d[B / 64 + 8];
   __shared__ int red_j[B / 64 + 8];
+  __shared__ double s_pick_al;
+  __shared__ int s_pick[3];
   Ctrl* ctl = lp.ctrl;
+  const int m = lp.m, tid = threadIdx.x, nparts = lp.update_grid;
+  // One round of requests: the control block and the first partial of every thread.
   const int verdict = ctl->verdict;
-  if (verdict < 0) return;  // k_update did not run
   const int q = ctl->q;
+  const int cur = ctl->cur;
+  const int64_t t = ctl->t;
+  const int flags0 = ctl->flags;
+  const double dq = ctl->dq;
+  const double z0 = ctl->z;
+  const int nD0 = ctl->nD;
+  const int nsb0 = ctl->nsb;
+  const int pk = min(tid, nparts - 1);  // clamped, not guarded: no load waits behind a branch
+  double pth = lp.part_th[pk], pt1 = lp.part_t1[pk], pt2 = lp.part_t2[pk], pal = lp.part_al[pk];
+  int plow = lp.part_low[pk], pbv = lp.part_bv[pk];
+  asm volatile("" ::: "memory");  // compiler-only: all of the above is requested first
+  if (tid >= nparts) {
+    pth = pt1 = pt2 = __builtin_inf();
+  }
+  if (verdict < 0) return;  // k_update did not run
   if (verdict != kStatusRunning) {  // OPTIMAL or ITER_LIMIT; k_update applied the pending pivot
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       ctl->status = verdict;
       ctl->verdict = -1;
       ctl->r = -1;
@@ -548,13 +720,10 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
     }
     return;
   }
-  const int m = lp.m, tid = threadIdx.x, nparts = lp.update_grid;
-  const int64_t t = ctl->t;
-  const int cur = ctl->cur;
 
   const double* al = cur ? lp.alpha0 : lp.alpha1;  // FTRAN result of this iteration
-  double th = __builtin_inf();
-  for (int k = tid; k < nparts; k += B) th = fmin(th, lp.part_th[k]);
+  double th = pth;
+  for (int k = tid + B; k < nparts; k += B) th = fmin(th, lp.part_th[k]);
   th = block_min<B>(th, red_d, red_j);
   if (th == __builtin_inf()) {  // Step 5: Y_k <= 0
     if (tid == 0) {
@@ -568,19 +737,42 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
   }
   // A row is tied when it reaches zero (within eps_t) at the step th; exact test below.
   const double eps_p = lp.eps_p, eps_t = lp.eps_t;
-  // Fast path: one workgroup may hold tied rows, and only one of its rows may.
+  // Fast path: one workgroup may hold tied rows, and only one of its rows may.  Its
+  // partial then names the pivot row, with that row's alpha and basic variable.
   int ncand = 0, cand = INT_MAX;
-  for (int k = tid; k < nparts; k += B)
+  if (tid < nparts && pt1 <= th) {
+    ncand = 1;
+    cand = tid;
+  }
+  for (int k = tid + B; k < nparts; k += B)
     if (lp.part_t1[k] <= th) {
       ++ncand;
       cand = min(cand, k);
     }
   ncand = block_sum_int<B>(ncand, red_j);
   cand = block_min_int<B>(cand, red_j);
+  bool fast = false;
+  if (ncand == 1) {
+    if (cand < B) {
+      if (tid == cand) {
+        s_pick[0] = pt2 > th ? 1 : 0;
+        s_pick[1] = plow;
+        s_pick[2] = pbv;
+        s_pick_al = pal;
+      }
+    } else if (tid == 0) {
+      s_pick[0] = lp.part_t2[cand] > th ? 1 : 0;
+      s_pick[1] = lp.part_low[cand];
+      s_pick[2] = lp.part_bv[cand];
+      s_pick_al = lp.part_al[cand];
+    }
+    __syncthreads();
+    fast = s_pick[0] != 0;
+  }
   int cnt, low;
-  if (ncand == 1 && lp.part_t2[cand] > th) {
+  if (fast) {
     cnt = 1;
-    low = lp.part_low[cand];
+    low = s_pick[1];
   } else {
     cnt = 0;
     low = INT_MAX;
@@ -595,7 +787,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
     low = block_min_int<B>(low, red_j);
   }
   int r = low;
-  int flags = ctl->flags;
+  int flags = flags0;
   if (cnt >= 2) {
     flags |= kFlagTie;
     if (lp.use_llist) {
@@ -634,19 +826,28 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
     // Step 8 pivots on row r with the step th.
     const double thr = th;
     if (thr == 0.0) flags |= kFlagDegenerate;
-    const double dq = ctl->dq;
-    const int leave = lp.basis[r];
-    if (lp.tenure > 0) lp.tabu_until[leave] = (int)(t + lp.tenure);
-    if (leave >= lp.n && !lp.inD[leave - lp.n]) {  // its column of B^-1 stops being a unit vector
-      lp.inD[leave - lp.n] = 1;
-      lp.dlist[ctl->nD] = leave - lp.n;
-      ctl->nD += 1;
+    int leave, kept;  // kept: the leaving variable is structural or its slack is in D already
+    double ar;
+    if (fast) {
+      leave = s_pick[2] >> 1;
+      kept = s_pick[2] & 1;
+      ar = s_pick_al;
+    } else {
+      leave = lp.basis[r];
+      kept = leave < lp.n || lp.inD[leave - lp.n];
+      ar = al[r];
     }
-    ctl->z = fma(dq, thr, ctl->z);
+    if (lp.tenure > 0) lp.tabu_until[leave] = (int)(t + lp.tenure);
+    if (!kept) {  // its column of B^-1 stops being a unit vector
+      lp.inD[leave - lp.n] = 1;
+      lp.dlist[nD0] = leave - lp.n;
+      ctl->nD = nD0 + 1;
+    }
+    ctl->z = fma(dq, thr, z0);
     lp.basis[r] = q;
     lp.pos[q] = r;
     lp.pos[leave] = -1;
-    ctl->nsb += (q < lp.n ? 1 : 0) - (leave < lp.n ? 1 : 0);
+    ctl->nsb = nsb0 + (q < lp.n ? 1 : 0) - (leave < lp.n ? 1 : 0);
     if (t < lp.log_cap) {
       lp.log_enter[t] = q;
       lp.log_row[t] = r;
@@ -660,7 +861,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
     ctl->r = r;        // pending: rows of B^-1 and x_B are pivoted by the next k_update,
     ctl->theta = thr;  // the top row by the next pricing kernel
     ctl->pdq = dq;
-    ctl->ar = al[r];
+    ctl->ar = ar;
     ctl->cur = cur ^ 1;
     ctl->q = -1;
     ctl->flags = 0;
@@ -682,7 +883,10 @@ const void* update_kernel() { return reinterpret_cast<const void*>(&k_update); }
 const void* finish_kernel() { return reinterpret_cast<const void*>(&k_finish); }
 
 size_t price_lds_bytes(int ld) { return sizeof(double) * (size_t)ld; }
-size_t update_lds_bytes(int ld) { return 2 * sizeof(double) * (size_t)ld; }
+// rho and a_q (ld doubles each) and, where sparse mode is possible, list D (ld/8 ints)
+size_t update_lds_bytes(int ld) {
+  return 2 * sizeof(double) * (size_t)ld + (ld >= kSparseMinLd ? sizeof(int) * (size_t)(ld / 8) : 0);
+}
 
 hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_price),
