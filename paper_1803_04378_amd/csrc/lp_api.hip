@@ -193,7 +193,7 @@ int run_reinversion(lp_problem* p) {
     if (!e) HIP_TRY(hipEventCreate(&e), "creating reinversion events");
   HIP_TRY(hipEventRecord(p->rv_ev[0], p->stream), "recording an event");
   int k = 0;
-  int rc = reinvert(p->d, p->b0, &p->rv, p->stream, &k);
+  int rc = reinvert(p->d, p->b0, &p->rv, p->stream, p->h_ctrl->nsb, p->h_ctrl->nD, &k);
   if (rc != LP_OK) return rc;
   HIP_TRY(hipEventRecord(p->rv_ev[1], p->stream), "recording an event");
   p->rv_timing = true;
@@ -736,7 +736,9 @@ int lp_get_stats(const lp_problem* p, lp_stats* s) {
 
 int lp_reinvert(lp_problem* p) {
   if (!p) return fail(LP_ERR_ARG, "p is NULL");
-  int rc = run_reinversion(p);
+  int rc = read_ctrl(p);  // the structural count and the list D of the current basis
+  if (rc != LP_OK) return rc;
+  rc = run_reinversion(p);
   if (rc != LP_OK) return rc;
   if ((rc = read_ctrl(p)) != LP_OK) return rc;
   return collect_reinv_time(p);

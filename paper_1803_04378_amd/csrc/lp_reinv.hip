@@ -36,6 +36,7 @@
 #include <vector>
 
 #include "lp_reinv.h"
+#include "lp_wave.h"
 #include "lpgpu.h"
 
 namespace lpgpu {
@@ -52,14 +53,11 @@ struct ReinvState {
   size_t C_cap = 0;
   double* part = nullptr;
   size_t part_cap = 0;
-  int32_t* idx = nullptr;  // kcol (k) | kpos (k) | rowlist (m) | rinfo (m) | colmap (ld)
+  int32_t* idx = nullptr;  // kcol (k) | kpos (k) | rowlist (m) | rinfo (m) | colmap (ld) | slack_pos (m)
   size_t idx_cap = 0;
   int32_t* aux = nullptr;  // rowperm (m) | opos (m) | inner list | outer list | info
   size_t aux_cap = 0;
-  int32_t* h_idx = nullptr;  // pinned
-  size_t h_idx_cap = 0;
-  int32_t* h_basis = nullptr;  // pinned
-  size_t h_basis_cap = 0;
+  bool warmed = false;  // the large-block path has run once on this handle
 };
 
 namespace {
@@ -73,7 +71,9 @@ constexpr int kWChunk = 64;  // b-range of one partial sum of W
 // G[b + a*k] = A'[rowlist[a], kcol[b]] for b < k, a < m, through a 32 x 32 LDS tile so that
 // both the reads (down a column of A') and the writes (down a column of G) coalesce.
 __global__ void k_gather(const double* __restrict__ A, int ld, const int32_t* __restrict__ kcol,
-                         const int32_t* __restrict__ rowlist, int k, int m, double* __restrict__ G) {
+                         const int32_t* __restrict__ rowlist, int k, int m, double* __restrict__ G,
+                         const int32_t* __restrict__ info) {
+  if (*info) return;  // the index sets are not valid
   __shared__ double tile[32][33];
   const int a0 = blockIdx.x * 32, b0 = blockIdx.y * 32;
   const int tx = threadIdx.x, ty = threadIdx.y;
@@ -99,6 +99,91 @@ __global__ void k_reinv_setup(int32_t* rowperm, int32_t* opos, int k, int32_t* i
   if (i == 0) *info = 0;
 }
 
+// Exclusive prefix count of a flag over a workgroup of kIndexBlock threads (ballots per
+// wavefront, then the wavefront totals); `total` is the workgroup's count.
+constexpr int kIndexBlock = 1024;
+__device__ __forceinline__ int block_prefix_count(bool f, int* s_wsum, int& total) {
+  constexpr int W = kIndexBlock / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long bal = __ballot(f);
+  const int in_wave = __popcll(bal & ((1ull << lane) - 1ull));
+  __syncthreads();  // s_wsum of the previous call has been read
+  if (lane == 0) s_wsum[wave] = __popcll(bal);
+  __syncthreads();
+  int before = 0;
+  total = 0;
+  for (int w = 0; w < W; ++w) {
+    const int c = s_wsum[w];
+    before += w < wave ? c : 0;
+    total += c;
+  }
+  return before + in_wave;
+}
+
+// The index sets of the block form from the basis list, on the device (one workgroup; m
+// in chunks of kIndexBlock): K = basis positions holding a structural column, in position
+// order, with kcol/kpos and rinfo[p] = its index b; R = rows whose slack is nonbasic,
+// ascending, in rowlist[0..k) with colmap[i] = their index (-1 for every other column up
+// to ld); S = the other rows, ascending, in rowlist[k..m), and rinfo[p] = -(s + 1) at the
+// position p of the slack of the s-th of them.  A basis entry out of range, or a count of
+// structural columns or of rows in R other than k, sets *info = 2 (nothing after this
+// kernel then uses the index sets).
+__global__ __launch_bounds__(kIndexBlock) void k_reinv_index(const int32_t* __restrict__ basis, int m, int n, int ld,
+                                                            int k, int32_t* __restrict__ kcol,
+                                                            int32_t* __restrict__ kpos, int32_t* __restrict__ rowlist,
+                                                            int32_t* __restrict__ rinfo,
+                                                            int32_t* __restrict__ colmap,
+                                                            int32_t* __restrict__ slack_pos,
+                                                            int32_t* __restrict__ info) {
+  constexpr int B = kIndexBlock;
+  __shared__ int s_wsum[B / 64];
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_bad = 0;
+  for (int i = tid; i < m; i += B) slack_pos[i] = -1;
+  for (int j = tid; j < ld; j += B) colmap[j] = -1;
+  __syncthreads();
+  int nk = 0;
+  for (int p0 = 0; p0 < m; p0 += B) {
+    const int p = p0 + tid;
+    const int v = p < m ? basis[p] : -1;
+    const bool ok = p < m && v >= 0 && v < n + m;
+    if (p < m && !ok) s_bad = 1;
+    const bool isK = ok && v < n;
+    if (ok && v >= n) slack_pos[v - n] = p;
+    int tot;
+    const int b = nk + block_prefix_count(isK, s_wsum, tot);
+    if (isK && b < k) {
+      kcol[b] = v;
+      kpos[b] = p;
+      rinfo[p] = b;
+    }
+    nk += tot;
+  }
+  __syncthreads();  // slack_pos is complete
+  int nr = 0, ns = 0;
+  for (int i0 = 0; i0 < m; i0 += B) {
+    const int i = i0 + tid;
+    const int sp = i < m ? slack_pos[i] : 0;
+    const bool isR = i < m && sp < 0;
+    int totR;
+    const int rl = block_prefix_count(isR, s_wsum, totR);
+    const int r = nr + rl;
+    const int sidx = ns + (tid - rl);  // the chunk's valid rows are contiguous from tid 0
+    if (isR && r < k) {
+      colmap[i] = r;
+      rowlist[r] = i;
+    }
+    if (i < m && !isR && k + sidx < m) {
+      rowlist[k + sidx] = i;
+      rinfo[sp] = -(sidx + 1);
+    }
+    nr += totR;
+    ns += min(B, m - i0) - totR;
+  }
+  if (tid == 0 && (s_bad || nk != k || nr != k)) *info = 2;
+}
+
 // Factorises the panel M[j0:k, j0:j0+jb] in place (jb <= JB) with partial pivoting.
 // Thread t of NT holds rows t, t + NT, ... (relative to j0) in registers, and rows stay
 // where they are during the elimination: at column c the pivot is the not yet chosen row
@@ -115,8 +200,8 @@ __global__ __launch_bounds__(NT) void k_lu_panel(double* __restrict__ M, int ld,
                                                  int32_t* __restrict__ pairs, int32_t* __restrict__ info) {
   constexpr int W = NT / 64;
   __shared__ double s_u[JB];
-  __shared__ double red_v[W];
-  __shared__ int red_i[W];
+  __shared__ double red_v[2][W];  // alternate between columns: no barrier at a column's end
+  __shared__ int red_i[2][W];
   __shared__ int s_piv[JB];
   __shared__ int s_dst[2 * JB], s_src[2 * JB];
   __shared__ int s_np;
@@ -135,42 +220,36 @@ __global__ __launch_bounds__(NT) void k_lu_panel(double* __restrict__ M, int ld,
   }
   bool singular = false;
   for (int c = 0; c < jb; ++c) {
-    double bv = -1.0;
+    const int bf = c & 1;
+    // Pivot: largest |value| among unchosen rows, lowest row on ties, i.e. the
+    // lexicographic minimum of (-|value|, row); 1.0 stands for "no candidate".
+    double nv = 1.0;
     int bi = INT_MAX;
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
       double v = fabs(a[s][0]);
       v = v == v ? v : 0.0;  // a NaN never wins (and signals a singular block below)
-      if (!done[s] && v > bv) {
-        bv = v;
-        bi = tid + s * NT;
-      }
+      const bool take = !done[s] && -v < nv;
+      nv = take ? -v : nv;
+      bi = take ? tid + s * NT : bi;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
+    detail::wave_lexmin(nv, bi);
     if (lane == 0) {
-      red_v[wave] = bv;
-      red_i[wave] = bi;
+      red_v[bf][wave] = nv;
+      red_i[bf][wave] = bi;
     }
     __syncthreads();
-    bv = red_v[0];
-    bi = red_i[0];
+    nv = red_v[bf][0];
+    bi = red_i[bf][0];
 #pragma unroll
     for (int w = 1; w < W; ++w) {
-      const double ov = red_v[w];
-      const int oi = red_i[w];
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
+      const double ov = red_v[bf][w];
+      const int oi = red_i[bf][w];
+      const bool take = detail::lex_less(ov, oi, nv, bi);
+      nv = take ? ov : nv;
+      bi = take ? oi : bi;
     }
+    const double bv = -nv;
     if (!(bv > 0.0)) singular = true;
     const int p = bi;  // an unchosen row always exists: R - c >= 1
     // Selects rather than branches on the owning slot keep the register rows from being
@@ -213,7 +292,8 @@ __global__ __launch_bounds__(NT) void k_lu_panel(double* __restrict__ M, int ld,
       a[s][JB - 1] = 0.0;
       h[s][JB - 1] = l;
     }
-    __syncthreads();
+    // No barrier here: the next column's pivot row is published only after its first
+    // barrier, which every thread reaches after reading this column's row.
   }
   // Align the history so that h[c] holds column c (a narrower last panel shifted jb times).
   for (int x = jb; x < JB; ++x) {
@@ -346,6 +426,42 @@ __global__ __launch_bounds__(kRowPanelThreads) void k_lu_rowpanel(double* __rest
   }
 }
 
+// U12 = L11^-1 A12 in place, for the unit lower triangular L11 = M[J0:J0+nb, J0:J0+nb]
+// (nb <= kOuter) and A12 = M[J0:J0+nb, c0:c0+ncol], column-major with leading dimension
+// ld.  Every workgroup stages L11 in LDS; each wavefront solves whole columns by forward
+// substitution, lane l holding rows l and l + 64, the solved entry broadcast by readlane.
+constexpr int kTrsmThreads = 256;
+__device__ __forceinline__ double read_lane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__global__ __launch_bounds__(kTrsmThreads) void k_trsm_outer(double* __restrict__ M, int ld, int J0, int nb, int c0,
+                                                           int ncol) {
+  __shared__ double sL[kOuter * kOuter];  // column-major nb x nb
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int waves = kTrsmThreads / 64;
+  for (int e = tid; e < nb * nb; e += kTrsmThreads) sL[e] = M[(size_t)(J0 + e % nb) + (size_t)(J0 + e / nb) * ld];
+  __syncthreads();
+  for (int col = blockIdx.x * waves + wave; col < ncol; col += gridDim.x * waves) {
+    double* bcol = M + (size_t)J0 + (size_t)(c0 + col) * ld;
+    const int i0 = lane, i1 = lane + 64;
+    double b0 = i0 < nb ? bcol[i0] : 0.0;
+    double b1 = i1 < nb ? bcol[i1] : 0.0;
+    for (int j = 0; j < nb; ++j) {
+      const double xj = j < 64 ? read_lane_d(b0, j) : read_lane_d(b1, j - 64);
+      const double l0 = i0 > j && i0 < nb ? sL[i0 + j * nb] : 0.0;
+      const double l1 = i1 > j && i1 < nb ? sL[i1 + j * nb] : 0.0;
+      b0 = fma(-l0, xj, b0);
+      b1 = fma(-l1, xj, b1);
+    }
+    if (i0 < nb) bcol[i0] = b0;
+    if (i1 < nb) bcol[i1] = b1;
+  }
+}
+
+
 // Composed interchanges of an outer panel: rows x in [r_lo, r_hi) whose opos[x] != x
 // (opos[x] = row, at the start of the outer panel, of what is now row x) become pairs
 // (x, opos[x]), and opos is reset to the identity for the next outer panel.
@@ -380,15 +496,20 @@ __global__ void k_perm_matrix(double* __restrict__ X, int k, const int32_t* __re
 // B^-1 in its m x ld row-major layout.  Row p is the basis position: rinfo[p] = b >= 0 for
 // the structural column kcol[b] (row b of B11^-1 = column b of X), or -(s+1) for the slack
 // of row srow[s] (row s of -B21 B11^-1 = column s of C^T, plus the unit entry).
+// Writes B^-1 row by row: every column (ncols < 0), or only the ncols columns listed in
+// cols (the list D: every other column is already exactly the unit vector it must be).
 __global__ void k_reinv_scatter(double* __restrict__ Binv, int m, int ld, int k, const int32_t* __restrict__ rinfo,
                                 const int32_t* __restrict__ colmap, const int32_t* __restrict__ srow,
                                 const double* __restrict__ X, const double* __restrict__ Ct,
-                                const int32_t* __restrict__ info) {
+                                const int32_t* __restrict__ cols, int ncols, const int32_t* __restrict__ info) {
   if (*info) return;
-  const size_t total = (size_t)m * ld;
+  const bool all = ncols < 0;
+  const int w = all ? ld : ncols;
+  const size_t total = (size_t)m * w;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += stride) {
-    const int p = (int)(e / ld), j = (int)(e % ld);
+    const int p = (int)(e / w), t = (int)(e % w);
+    const int j = all ? t : cols[t];
     const int a = colmap[j];
     const int ri = rinfo[p];
     double v;
@@ -398,7 +519,7 @@ __global__ void k_reinv_scatter(double* __restrict__ Binv, int m, int ld, int k,
       const int s = -ri - 1;
       v = a >= 0 ? Ct[(size_t)a + (size_t)s * k] : (j == srow[s] ? 1.0 : 0.0);
     }
-    Binv[e] = v;
+    Binv[(size_t)p * ld + j] = v;
   }
 }
 
@@ -498,8 +619,6 @@ __global__ __launch_bounds__(1024) void k_reinv_finish(Ctrl* ctl, int m, int k, 
 // ---------------------------------------------------------------------------------------
 // Small blocks.
 constexpr int kSmallK = 128;
-constexpr int kGJThreads = 1024;
-constexpr int kGJRows = kSmallK / 8;  // rows of the block one thread holds
 
 // X = M^-1 for M = G[:, 0:k] (column-major, k <= kSmallK) by in-place Gauss-Jordan
 // elimination with partial pivoting, one workgroup.  Thread 8j + g holds column j of rows
@@ -511,12 +630,16 @@ constexpr int kGJRows = kSmallK / 8;  // rows of the block one thread holds
 // that reciprocal, row p becomes the old row c, and column c is eliminated from every
 // other row.  The LDS buffers alternate between columns.  The row exchanges make the
 // result (P M)^-1 = M^-1 P^T, so its column c is column idx[c] of M^-1.
-__global__ __launch_bounds__(kGJThreads) void k_gj_inverse(const double* __restrict__ G, int k,
-                                                           double* __restrict__ X, int32_t* __restrict__ info) {
-  __shared__ double s_row[2][kSmallK], s_rowc[2][kSmallK], s_col[2][kSmallK];
+// KMAX (<= kSmallK) bounds k; the workgroup has 8 * KMAX threads, so that smaller blocks
+// synchronise fewer wavefronts per column.
+template <int KMAX>
+__global__ __launch_bounds__(8 * KMAX) void k_gj_inverse(const double* __restrict__ G, int k,
+                                                         double* __restrict__ X, int32_t* __restrict__ info) {
+  constexpr int kGJRows = KMAX / 8;  // rows of the block one thread holds
+  __shared__ double s_row[2][KMAX], s_rowc[2][KMAX], s_col[2][KMAX];
   __shared__ double s_pv[2];
   __shared__ int s_p[2];
-  __shared__ int s_idx[kSmallK];
+  __shared__ int s_idx[KMAX];
   __shared__ int s_sing;
   const int tid = threadIdx.x;
   const int grp = tid & 7, jcol = tid >> 3;
@@ -619,7 +742,8 @@ __global__ __launch_bounds__(kGJThreads) void k_gj_inverse(const double* __restr
 
 // B^-1 in its m x ld row-major layout, 4 rows per workgroup.  A structural basis position
 // b copies column b of X; a slack position s forms -sum_b B21[s, b] B11^-1[b, :] from the
-// column k + s of G and X (4 rows share each read of X).
+// column k + s of G and X (4 rows share each read of X).  Every column is written
+// (ncols < 0) or only the ncols columns listed in cols, as k_reinv_scatter.
 constexpr int kScatterRows = 4;
 
 __global__ __launch_bounds__(256) void k_reinv_scatter_small(double* __restrict__ Binv, int m, int ld, int k,
@@ -628,6 +752,7 @@ __global__ __launch_bounds__(256) void k_reinv_scatter_small(double* __restrict_
                                                               const int32_t* __restrict__ srow,
                                                               const double* __restrict__ X,
                                                               const double* __restrict__ G,
+                                                              const int32_t* __restrict__ cols, int ncols,
                                                               const int32_t* __restrict__ info) {
   if (*info) return;
   __shared__ double s_g[kScatterRows][kSmallK];
@@ -662,7 +787,10 @@ __global__ __launch_bounds__(256) void k_reinv_scatter_small(double* __restrict_
     if (p >= m) break;
     const int sr = ri[r] < 0 ? srow[-ri[r] - 1] : -1;
     double* row = Binv + (size_t)p * ld;
-    for (int j = tid; j < ld; j += 256) {
+    const bool all = ncols < 0;
+    const int w = all ? ld : ncols;
+    for (int t = tid; t < w; t += 256) {
+      const int j = all ? t : cols[t];
       const int a = colmap[j];
       row[j] = a >= 0 ? s_v[r][a] : (j == sr ? 1.0 : 0.0);
     }
@@ -749,18 +877,6 @@ hipError_t grow(T** ptr, size_t* cap, size_t need, size_t limit) {
   return e;
 }
 
-template <class T>
-hipError_t grow_pinned(T** ptr, size_t* cap, size_t need) {
-  if (need <= *cap && *ptr) return hipSuccess;
-  if (*ptr) (void)hipHostFree(*ptr);
-  *ptr = nullptr;
-  *cap = 0;
-  const size_t n = std::max<size_t>(need, 1);
-  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(ptr), n * sizeof(T), hipHostMallocDefault);
-  if (e == hipSuccess) *cap = n;
-  return e;
-}
-
 int hip_fail(hipError_t e, const char* what) {
   return record_error(e == hipErrorOutOfMemory ? LP_ERR_NOMEM : LP_ERR_DEVICE,
                       std::string("reinversion: ") + what + ": " + hipGetErrorString(e));
@@ -805,10 +921,107 @@ void reinv_free(ReinvState* st) {
   if (st->blas) (void)rocblas_destroy_handle(st->blas);
   for (void* p : {(void*)st->G, (void*)st->X, (void*)st->C, (void*)st->part, (void*)st->idx, (void*)st->aux})
     if (p) (void)hipFree(p);
-  if (st->h_idx) (void)hipHostFree(st->h_idx);
-  if (st->h_basis) (void)hipHostFree(st->h_basis);
   delete st;
 }
+
+namespace {
+
+// Steps 2-4 of the large-block path on st->G (k x m, k >= 1): LU of M = G[:, 0:k] in place,
+// X = M^-1 = (B11^-1)^T, and C^T = -X B21^T when m > k.  A zero pivot column sets *info.
+int invert_large(ReinvState* st, int k, int m, int32_t* rowperm, int32_t* opos, int32_t* pairs, int32_t* opairs,
+                 int32_t* info, hipStream_t s) {
+  const size_t kk = (size_t)k * k;
+  // 2. LU of M = G[:, 0:k] (leading dimension k).
+  double* Mx = st->G;
+  const double one = 1.0, minus_one = -1.0, zero = 0.0;
+  for (int J0 = 0; J0 < k; J0 += kOuter) {
+    const int JBo = std::min(kOuter, k - J0);
+    for (int j0 = J0; j0 < J0 + JBo;) {
+      const int R = k - j0, room = J0 + JBo - j0;
+      int jb;
+      hipError_t e;
+      // Inner panel shapes that keep the rows in registers without spills; R <= LP_MAX_ROWS.
+      // The per-column cost is synchronisation across the workgroup's wavefronts, so the
+      // workgroup is no larger than the panel needs.
+      if (R <= 256) {
+        jb = std::min(16, room);
+        e = launch_inner_panel<256, 1, 16>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
+      } else if (R <= 512) {
+        jb = std::min(16, room);
+        e = launch_inner_panel<512, 1, 16>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
+      } else if (R <= 1024) {
+        jb = std::min(16, room);
+        e = launch_inner_panel<1024, 1, 16>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
+      } else if (R <= 2048) {
+        jb = std::min(8, room);
+        e = launch_inner_panel<1024, 2, 8>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
+      } else if (R <= 4096) {
+        jb = std::min(4, room);
+        e = launch_inner_panel<1024, 4, 4>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
+      } else {
+        jb = std::min(2, room);
+        e = launch_inner_panel<1024, 10, 2>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
+      }
+      R_HIP(e, "launching a panel factorisation");
+      const int rows = k - j0 - jb, cols = J0 + JBo - j0 - jb;
+      if (rows > 0 && cols > 0)
+        R_BLAS(rocblas_dgemm(st->blas, rocblas_operation_none, rocblas_operation_none, rows, cols, jb, &minus_one,
+                             Mx + (size_t)(j0 + jb) + (size_t)j0 * k, k, Mx + (size_t)j0 + (size_t)(j0 + jb) * k, k,
+                             &one, Mx + (size_t)(j0 + jb) + (size_t)(j0 + jb) * k, k),
+               "inner update");
+      j0 += jb;
+    }
+    // The outer panel's interchanges on the columns outside it and on rowperm.
+    hipLaunchKernelGGL(k_lu_outer_pairs, dim3(1), dim3(1024), 0, s, opos, J0, k, opairs);
+    R_HIP(hipGetLastError(), "launching the interchange list");
+    {
+      const int ncols = k - JBo + 1;
+      hipLaunchKernelGGL(k_lu_rowpanel, dim3((ncols + kRowPanelWaves - 1) / kRowPanelWaves), dim3(kRowPanelThreads),
+                         0, s, Mx, k, 0, k, J0, J0 + JBo, k, 0, 0, (const int32_t*)opairs, kOuterPairs, rowperm);
+      R_HIP(hipGetLastError(), "launching the interchanges");
+    }
+    const int rest = k - J0 - JBo;
+    if (rest > 0) {
+      // (not rocBLAS: its choice of method varies with the width rest, and each method's
+      // first use in a process stalls for tens of milliseconds)
+      const int waves = kTrsmThreads / 64;
+      hipLaunchKernelGGL(k_trsm_outer, dim3((rest + waves - 1) / waves), dim3(kTrsmThreads), 0, s, Mx, k, J0, JBo,
+                         J0 + JBo, rest);
+      R_HIP(hipGetLastError(), "launching the outer U12 solve");
+      R_BLAS(rocblas_dgemm(st->blas, rocblas_operation_none, rocblas_operation_none, rest, rest, JBo, &minus_one,
+                           Mx + (size_t)(J0 + JBo) + (size_t)J0 * k, k, Mx + (size_t)J0 + (size_t)(J0 + JBo) * k, k,
+                           &one, Mx + (size_t)(J0 + JBo) + (size_t)(J0 + JBo) * k, k),
+             "trailing update");
+    }
+  }
+  // 3. X = U^-1 L^-1 P
+  hipLaunchKernelGGL(k_perm_matrix, dim3((unsigned)std::min<size_t>(8192, (kk + 255) / 256)), dim3(256), 0, s,
+                     st->X, k, (const int32_t*)rowperm);
+  R_HIP(hipGetLastError(), "launching the permutation");
+  R_BLAS(rocblas_dtrsm(st->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                       rocblas_diagonal_unit, k, k, &one, Mx, k, st->X, k),
+         "solving with L");
+  R_BLAS(rocblas_dtrsm(st->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                       rocblas_diagonal_non_unit, k, k, &one, Mx, k, st->X, k),
+         "solving with U");
+  // 4. C^T = -X B21^T
+  if (m > k)
+    R_BLAS(rocblas_dgemm(st->blas, rocblas_operation_none, rocblas_operation_none, k, m - k, k, &minus_one, st->X,
+                         k, st->G + kk, k, &zero, st->C, k),
+           "forming -B21 B11^-1");
+  return LP_OK;
+}
+
+// A well-conditioned stand-in block (identity B11, B21 = 0) for the warm-up.
+__global__ void k_warm_block(double* G, int k, int m) {
+  const size_t total = (size_t)k * m;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x)
+    G[e] = (e % k) == (e / k) ? 1.0 : 0.0;
+}
+
+constexpr int kWarmK = 160;  // larger than kSmallK, so that every large-path step runs
+
+}  // namespace
 
 int reinv_prepare(ReinvState** state, int m, int ld) {
   if (!*state) {
@@ -827,85 +1040,65 @@ int reinv_prepare(ReinvState** state, int m, int ld) {
   // Work memory for blocks up to kSmallK allocated up front (no allocation, and so no
   // device synchronisation, inside a solve unless the block grows past that).
   const size_t mm = (size_t)m * m, ks = (size_t)std::min(m, kSmallK);
-  R_HIP(grow_pinned(&st->h_basis, &st->h_basis_cap, (size_t)m), "allocating pinned memory");
-  R_HIP(grow_pinned(&st->h_idx, &st->h_idx_cap, 3 * (size_t)m + ld), "allocating pinned memory");
-  R_HIP(grow(&st->idx, &st->idx_cap, 3 * (size_t)m + ld, 3 * (size_t)m + ld), "allocating work memory");
+  R_HIP(grow(&st->idx, &st->idx_cap, 5 * (size_t)m + ld, 5 * (size_t)m + ld), "allocating work memory");
   const size_t naux = 2 * (size_t)m + 2 * kPairs + 2 * kOuterPairs + 3;
   R_HIP(grow(&st->aux, &st->aux_cap, naux, naux), "allocating work memory");
   R_HIP(grow(&st->G, &st->G_cap, ks * m, mm), "allocating work memory");
   R_HIP(grow(&st->X, &st->X_cap, ks * ks, mm), "allocating work memory");
-  R_HIP(grow(&st->part, &st->part_cap, (size_t)ld, ((size_t)m / kWChunk + 1) * ld), "allocating work memory");
+  R_HIP(grow(&st->part, &st->part_cap, 2 * (size_t)ld, ((size_t)m / kWChunk + 1) * ld), "allocating work memory");
+  if (!st->warmed && m > kSmallK) {
+    // The first launch of a rocBLAS kernel loads its code object and the first triangular
+    // solve of a handle sizes its workspace: 40-130 ms stalls observed in the middle of a
+    // solve.  Run the large-block path once here on a stand-in block of order kWarmK, on
+    // the null stream, outside any solve.
+    const int kw = std::min(m, kWarmK);
+    R_HIP(grow(&st->G, &st->G_cap, (size_t)kw * m, mm), "allocating work memory");
+    R_HIP(grow(&st->X, &st->X_cap, (size_t)kw * kw, mm), "allocating work memory");
+    if (m > kw) R_HIP(grow(&st->C, &st->C_cap, (size_t)kw * (m - kw), mm / 4 + 1), "allocating work memory");
+    R_BLAS(rocblas_set_stream(st->blas, nullptr), "configuring the BLAS handle");
+    int32_t* rowperm = st->aux;
+    int32_t* opos = rowperm + m;
+    int32_t* pairs = opos + m;
+    int32_t* opairs = pairs + 2 * kPairs + 1;
+    int32_t* info = opairs + 2 * kOuterPairs + 1;
+    hipLaunchKernelGGL(k_warm_block, dim3(1024), dim3(256), 0, nullptr, st->G, kw, m);
+    R_HIP(hipGetLastError(), "launching the warm-up block");
+    hipLaunchKernelGGL(k_reinv_setup, dim3((kw + 255) / 256), dim3(256), 0, nullptr, rowperm, opos, kw, info);
+    R_HIP(hipGetLastError(), "launching setup");
+    const int rc = invert_large(st, kw, m, rowperm, opos, pairs, opairs, info, nullptr);
+    if (rc != LP_OK) return rc;
+    R_HIP(hipStreamSynchronize(nullptr), "warming up the factorisation");
+    st->warmed = true;
+  }
   return LP_OK;
 }
 
-int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s, int* k_out) {
+int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s, int k, int nd_old, int* k_out) {
   int rc = reinv_prepare(state, d.m, d.ld);
   if (rc != LP_OK) return rc;
   ReinvState* st = *state;
-  R_BLAS(rocblas_set_stream(st->blas, s), "configuring the BLAS handle");
   const int m = d.m, n = d.n, ld = d.ld;
+  if (k < 0 || k > m) return record_error(LP_ERR_DEVICE, "reinversion: structural count out of range");
+  R_BLAS(rocblas_set_stream(st->blas, s), "configuring the BLAS handle");
 
-  // 1. The basis, and the index sets of the block form.
-  R_HIP(grow_pinned(&st->h_basis, &st->h_basis_cap, (size_t)m), "allocating pinned memory");
-  R_HIP(hipMemcpyAsync(st->h_basis, d.basis, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s), "reading the basis");
-  R_HIP(hipStreamSynchronize(s), "reading the basis");
-  std::vector<int32_t> slack_pos(m, -1);
-  std::vector<int32_t> kcol, kpos;
-  kcol.reserve(m);
-  kpos.reserve(m);
-  for (int p = 0; p < m; ++p) {
-    const int v = st->h_basis[p];
-    if (v < 0 || v >= n + m) return record_error(LP_ERR_DEVICE, "reinversion: corrupt basis");
-    if (v < n) {
-      kcol.push_back(v);
-      kpos.push_back(p);
-    } else {
-      slack_pos[v - n] = p;
-    }
-  }
-  const int k = (int)kcol.size();
-  const size_t nidx = 2 * (size_t)k + 2 * (size_t)m + ld;
-  R_HIP(grow_pinned(&st->h_idx, &st->h_idx_cap, nidx), "allocating pinned memory");
-  int32_t* h_kcol = st->h_idx;
-  int32_t* h_kpos = h_kcol + k;
-  int32_t* h_rowlist = h_kpos + k;
-  int32_t* h_rinfo = h_rowlist + m;
-  int32_t* h_colmap = h_rinfo + m;
-  std::copy(kcol.begin(), kcol.end(), h_kcol);
-  std::copy(kpos.begin(), kpos.end(), h_kpos);
-  for (int j = 0; j < ld; ++j) h_colmap[j] = -1;
-  int nr = 0;
-  for (int i = 0; i < m; ++i)
-    if (slack_pos[i] < 0) {
-      h_colmap[i] = nr;
-      h_rowlist[nr++] = i;
-    }
-  if (nr != k) return record_error(LP_ERR_DEVICE, "reinversion: basis list is not a basis");
-  int ns = 0;
-  for (int i = 0; i < m; ++i)
-    if (slack_pos[i] >= 0) {
-      h_rinfo[slack_pos[i]] = -(ns + 1);
-      h_rowlist[k + ns++] = i;
-    }
-  for (int b = 0; b < k; ++b) h_rinfo[h_kpos[b]] = b;
-
-  const size_t mm = (size_t)m * m;
-  R_HIP(grow(&st->idx, &st->idx_cap, nidx, 3 * (size_t)m + ld), "allocating work memory");
+  // 1. The index sets of the block form, built on the device from the basis list.
+  const size_t nidx = 2 * (size_t)k + 3 * (size_t)m + ld;
+  R_HIP(grow(&st->idx, &st->idx_cap, nidx, 5 * (size_t)m + ld), "allocating work memory");
   const size_t naux = 2 * (size_t)m + 2 * kPairs + 2 * kOuterPairs + 3;
   R_HIP(grow(&st->aux, &st->aux_cap, naux, naux), "allocating work memory");
-  R_HIP(hipMemcpyAsync(st->idx, st->h_idx, sizeof(int32_t) * nidx, hipMemcpyHostToDevice, s), "uploading indices");
-  const int32_t* kcol_d = st->idx;
-  const int32_t* kpos_d = kcol_d + k;
-  const int32_t* rowlist_d = kpos_d + k;
-  const int32_t* rinfo_d = rowlist_d + m;
-  const int32_t* colmap_d = rinfo_d + m;
+  int32_t* kcol_d = st->idx;
+  int32_t* kpos_d = kcol_d + k;
+  int32_t* rowlist_d = kpos_d + k;
+  int32_t* rinfo_d = rowlist_d + m;
+  int32_t* colmap_d = rinfo_d + m;
+  int32_t* slackpos_d = colmap_d + ld;
   int32_t* rowperm = st->aux;
   int32_t* opos = rowperm + m;
   int32_t* pairs = opos + m;
   int32_t* opairs = pairs + 2 * kPairs + 1;
   int32_t* info = opairs + 2 * kOuterPairs + 1;
 
-  const size_t kk = (size_t)k * k;
+  const size_t kk = (size_t)k * k, mm = (size_t)m * m;
   R_HIP(grow(&st->G, &st->G_cap, (size_t)k * m, mm), "allocating work memory");
   R_HIP(grow(&st->X, &st->X_cap, kk, mm), "allocating work memory");
   const bool small = k <= kSmallK;
@@ -913,95 +1106,40 @@ int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s,
   const int nchunk = std::max(1, (k + kWChunk - 1) / kWChunk);
   R_HIP(grow(&st->part, &st->part_cap, std::max((size_t)nchunk * ld, (size_t)k), ((size_t)m / kWChunk + 1) * ld),
         "allocating work memory");
+  // Columns of B^-1 to write: those of the list D, which holds every column that can
+  // differ from a unit vector (the new R included), while it is short; else all.
+  const int ncols = (nd_old >= 0 && (size_t)nd_old * 8 <= (size_t)ld) ? nd_old : -1;
 
   hipLaunchKernelGGL(k_reinv_setup, dim3(std::max(1, (k + 255) / 256)), dim3(256), 0, s, rowperm, opos, k, info);
   R_HIP(hipGetLastError(), "launching setup");
+  hipLaunchKernelGGL(k_reinv_index, dim3(1), dim3(kIndexBlock), 0, s, (const int32_t*)d.basis, m, n, ld, k, kcol_d,
+                     kpos_d, rowlist_d, rinfo_d, colmap_d, slackpos_d, info);
+  R_HIP(hipGetLastError(), "launching the index sets");
 
   if (k > 0) {
     // 1. G = [B11^T | B21^T]
-    hipLaunchKernelGGL(k_gather, dim3((m + 31) / 32, (k + 31) / 32), dim3(32, 8), 0, s, d.A, ld, kcol_d, rowlist_d,
-                       k, m, st->G);
+    hipLaunchKernelGGL(k_gather, dim3((m + 31) / 32, (k + 31) / 32), dim3(32, 8), 0, s, d.A, ld,
+                       (const int32_t*)kcol_d, (const int32_t*)rowlist_d, k, m, st->G, (const int32_t*)info);
     R_HIP(hipGetLastError(), "launching the gather");
   }
   if (k > 0 && small) {
     // 2'-4'. X = M^-1 in one workgroup; -B21 B11^-1 is formed while writing B^-1.
-    hipLaunchKernelGGL(k_gj_inverse, dim3(1), dim3(kGJThreads), 0, s, (const double*)st->G, k, st->X, info);
+    if (k <= 32)
+      hipLaunchKernelGGL(k_gj_inverse<32>, dim3(1), dim3(8 * 32), 0, s, (const double*)st->G, k, st->X, info);
+    else if (k <= 64)
+      hipLaunchKernelGGL(k_gj_inverse<64>, dim3(1), dim3(8 * 64), 0, s, (const double*)st->G, k, st->X, info);
+    else
+      hipLaunchKernelGGL(k_gj_inverse<kSmallK>, dim3(1), dim3(8 * kSmallK), 0, s, (const double*)st->G, k, st->X,
+                         info);
     R_HIP(hipGetLastError(), "launching the small inverse");
   } else if (k > 0) {
-    // 2. LU of M = G[:, 0:k] (leading dimension k).
-    double* Mx = st->G;
-    const double one = 1.0, minus_one = -1.0, zero = 0.0;
-    for (int J0 = 0; J0 < k; J0 += kOuter) {
-      const int JBo = std::min(kOuter, k - J0);
-      for (int j0 = J0; j0 < J0 + JBo;) {
-        const int R = k - j0, room = J0 + JBo - j0;
-        int jb;
-        hipError_t e;
-        // Inner panel shapes that keep the rows in registers without spills; R <= LP_MAX_ROWS.
-        if (R <= 1024) {
-          jb = std::min(16, room);
-          e = launch_inner_panel<1024, 1, 16>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
-        } else if (R <= 2048) {
-          jb = std::min(8, room);
-          e = launch_inner_panel<1024, 2, 8>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
-        } else if (R <= 4096) {
-          jb = std::min(4, room);
-          e = launch_inner_panel<1024, 4, 4>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
-        } else {
-          jb = std::min(2, room);
-          e = launch_inner_panel<1024, 10, 2>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
-        }
-        R_HIP(e, "launching a panel factorisation");
-        const int rows = k - j0 - jb, cols = J0 + JBo - j0 - jb;
-        if (rows > 0 && cols > 0)
-          R_BLAS(rocblas_dgemm(st->blas, rocblas_operation_none, rocblas_operation_none, rows, cols, jb, &minus_one,
-                               Mx + (size_t)(j0 + jb) + (size_t)j0 * k, k, Mx + (size_t)j0 + (size_t)(j0 + jb) * k, k,
-                               &one, Mx + (size_t)(j0 + jb) + (size_t)(j0 + jb) * k, k),
-                 "inner update");
-        j0 += jb;
-      }
-      // The outer panel's interchanges on the columns outside it and on rowperm.
-      hipLaunchKernelGGL(k_lu_outer_pairs, dim3(1), dim3(1024), 0, s, opos, J0, k, opairs);
-      R_HIP(hipGetLastError(), "launching the interchange list");
-      {
-        const int ncols = k - JBo + 1;
-        hipLaunchKernelGGL(k_lu_rowpanel, dim3((ncols + kRowPanelWaves - 1) / kRowPanelWaves), dim3(kRowPanelThreads),
-                           0, s, Mx, k, 0, k, J0, J0 + JBo, k, 0, 0, (const int32_t*)opairs, kOuterPairs, rowperm);
-        R_HIP(hipGetLastError(), "launching the interchanges");
-      }
-      const int rest = k - J0 - JBo;
-      if (rest > 0) {
-        R_BLAS(rocblas_dtrsm(st->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                             rocblas_diagonal_unit, JBo, rest, &one, Mx + (size_t)J0 + (size_t)J0 * k, k,
-                             Mx + (size_t)J0 + (size_t)(J0 + JBo) * k, k),
-               "outer U12");
-        R_BLAS(rocblas_dgemm(st->blas, rocblas_operation_none, rocblas_operation_none, rest, rest, JBo, &minus_one,
-                             Mx + (size_t)(J0 + JBo) + (size_t)J0 * k, k, Mx + (size_t)J0 + (size_t)(J0 + JBo) * k, k,
-                             &one, Mx + (size_t)(J0 + JBo) + (size_t)(J0 + JBo) * k, k),
-               "trailing update");
-      }
-    }
-    // 3. X = U^-1 L^-1 P
-    hipLaunchKernelGGL(k_perm_matrix, dim3((unsigned)std::min<size_t>(8192, (kk + 255) / 256)), dim3(256), 0, s,
-                       st->X, k, (const int32_t*)rowperm);
-    R_HIP(hipGetLastError(), "launching the permutation");
-    R_BLAS(rocblas_dtrsm(st->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                         rocblas_diagonal_unit, k, k, &one, Mx, k, st->X, k),
-           "solving with L");
-    R_BLAS(rocblas_dtrsm(st->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
-                         rocblas_diagonal_non_unit, k, k, &one, Mx, k, st->X, k),
-           "solving with U");
-    // 4. C^T = -X B21^T
-    if (m > k)
-      R_BLAS(rocblas_dgemm(st->blas, rocblas_operation_none, rocblas_operation_none, k, m - k, k, &minus_one, st->X,
-                           k, st->G + kk, k, &zero, st->C, k),
-             "forming -B21 B11^-1");
+    if ((rc = invert_large(st, k, m, rowperm, opos, pairs, opairs, info, s)) != LP_OK) return rc;
   }
   // 5. B^-1, x_B, W, z.
   if (small) {
     hipLaunchKernelGGL(k_reinv_scatter_small, dim3((m + kScatterRows - 1) / kScatterRows), dim3(256), 0, s, d.Binv, m,
                        ld, k, rinfo_d, colmap_d, rowlist_d + k, (const double*)st->X, (const double*)st->G,
-                       (const int32_t*)info);
+                       (const int32_t*)d.dlist, ncols, (const int32_t*)info);
     R_HIP(hipGetLastError(), "launching the scatter");
     hipLaunchKernelGGL(k_reinv_xstruct, dim3(1), dim3(kSmallK), 0, s, d.xB, st->part, k, kpos_d, rowlist_d,
                        (const double*)st->X, b, d.eps_z, (const int32_t*)info);
@@ -1017,10 +1155,10 @@ int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s,
                        d.dlist, d.inD, d.chat, (const double*)d.xB, (const int32_t*)info);
     R_HIP(hipGetLastError(), "launching the finish");
   } else {
-    const size_t total = (size_t)m * ld;
+    const size_t total = (size_t)m * (ncols < 0 ? ld : ncols);
     hipLaunchKernelGGL(k_reinv_scatter, dim3((unsigned)std::min<size_t>(16384, (total + 255) / 256)), dim3(256), 0,
                        s, d.Binv, m, ld, k, rinfo_d, colmap_d, rowlist_d + k, (const double*)st->X,
-                       (const double*)st->C, (const int32_t*)info);
+                       (const double*)st->C, (const int32_t*)d.dlist, ncols, (const int32_t*)info);
     R_HIP(hipGetLastError(), "launching the scatter");
     hipLaunchKernelGGL(k_reinv_xb, dim3((unsigned)std::min(4096, (m + 3) / 4)), dim3(256), 0, s, d.xB, m, k, rinfo_d,
                        rowlist_d, (const double*)st->X, (const double*)st->C, b, d.eps_z, (const int32_t*)info);
