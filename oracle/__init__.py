@@ -17,8 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "simplex_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-OPTIMAL, UNBOUNDED, ITER_LIMIT = 1, 2, 3
-STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT"}
+OPTIMAL, UNBOUNDED, ITER_LIMIT, NUMERICAL = 1, 2, 3, 4
+STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT", 4: "NUMERICAL"}
 FLAG_DEGENERATE, FLAG_TIE, FLAG_ASPIRATION, FLAG_LCLEAR = 1, 2, 4, 8
 
 # -ffp-contract=off: only the explicit fma() calls fuse.  x86-64-v3 has hardware FMA,

@@ -45,6 +45,9 @@
  *     afterwards every |xB_i| < eps_z is set to 0.            (Section 3.1)
  *   - the iteration limit is checked after pricing: a basis that prices out optimal
  *     is reported OPTIMAL even at the limit.
+ *   - non-finite arithmetic (the paper assumes none): if Y_k has a non-finite entry,
+ *     or the minimum ratio over the candidate rows overflows, the solve stops with
+ *     status NUMERICAL before the pivot; "no candidate row" stays UNBOUNDED.
  *
  * Dot products are plain ascending-index fma chains.  Build with
  * -ffp-contract=off so that no other operation is fused.
@@ -62,6 +65,7 @@
 #define OR_OPTIMAL 1
 #define OR_UNBOUNDED 2
 #define OR_ITER_LIMIT 3
+#define OR_NUMERICAL 4
 
 #define FLAG_DEGENERATE 1  /* theta == 0 */
 #define FLAG_TIE 2         /* more than one row reaches zero (within eps_t) at the step */
@@ -243,6 +247,10 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
     }
   }
 
+  /* A non-finite entry of Y_k (overflow of the product-form B^-1) stops the solve. */
+  for (int32_t i = 0; i < m; ++i)
+    if (!isfinite(p->alpha[i])) return OR_NUMERICAL;
+
   /* Step 6: ratio test over rows with alpha_i > eps_p. */
   double theta_min = INFINITY;
   int32_t nR = 0;
@@ -253,6 +261,7 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
     if (p->ratio[i] < theta_min) theta_min = p->ratio[i];
   }
   if (nR == 0) { p->ray = q; return OR_UNBOUNDED; } /* Step 5: Y_k <= 0 */
+  if (!isfinite(theta_min)) return OR_NUMERICAL;     /* the step overflowed */
   int32_t nT = 0, r_low = -1, r_free = -1;
   for (int32_t i = 0; i < m; ++i) {
     if (!(p->alpha[i] > p->eps_p)) continue;

@@ -31,6 +31,8 @@ MUTANTS = {
     "pivot_row_not_divided": ("p->rho[j] = rowr[j] / ar;", "p->rho[j] = rowr[j];"),
     "no_leaving_list_append": ("if (list_add(p, q, p->basis[r])) return -1;", "(void)0;"),
     "slack_price_wrong_index": ("p->d[j] = p->chat[j] - p->W[j - n];", "p->d[j] = p->chat[j] - p->W[0];"),
+    "no_alpha_finite_check": ("if (!isfinite(p->alpha[i])) return OR_NUMERICAL;", "(void)0;"),
+    "no_step_finite_check": ("if (!isfinite(theta_min)) return OR_NUMERICAL;", "(void)0;"),
 }
 
 
@@ -82,6 +84,14 @@ def _pins_pass(lib_path):
         A, b, c = np.array(d["A"], float), np.array(d["b"], float), np.array(d["c"], float)
         r = oracle.solve(A, b, c, lib_path=lib_path, max_iter=200)
         if r.status != oracle.OPTIMAL or abs(r.objective - d["optimum"]) > 1e-12:
+            return False
+        # overflow stops the solve (the two cases of test_numerical_status_on_overflow)
+        r = oracle.solve(np.array([[1e-8]]), np.array([1e301]), np.array([1.0]), lib_path=lib_path)
+        if r.status != oracle.NUMERICAL:
+            return False
+        r = oracle.solve(np.array([[1e-8, 0.0], [1e301, 1.0]]), np.array([0.0, 1.0]), np.array([1.0, 1.0]),
+                         lib_path=lib_path)
+        if r.status != oracle.NUMERICAL or r.iterations != 1:
             return False
     except AssertionError:
         return False

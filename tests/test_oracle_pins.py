@@ -258,6 +258,25 @@ def test_unbounded_column():
     assert r.status == oracle.UNBOUNDED and r.ray == 5 and r.iterations == 0
 
 
+def test_numerical_status_on_overflow():
+    """Non-finite arithmetic stops the solve with NUMERICAL before the pivot.
+
+    (i) The step overflows: one row, a_11 = 1e-8, b = 1e301, so the only ratio is 1e309.
+    (ii) Y_k overflows: x_1 enters on row 0 with alpha = (1e-8, 1e301) at the step 0
+    (b_0 = 0), which sets B^-1[1,0] = -1e301/1e-8 = -inf; x_2 (reduced cost -1) is then
+    improving and its FTRAN gives alpha_1 = -inf * 0 + 1 = NaN."""
+    r = oracle.solve(np.array([[1e-8]]), np.array([1e301]), np.array([1.0]))
+    assert r.status == oracle.NUMERICAL and r.iterations == 0
+    A = np.array([[1e-8, 0.0], [1e301, 1.0]])
+    r = oracle.solve(A, np.array([0.0, 1.0]), np.array([1.0, 1.0]))
+    assert r.status == oracle.NUMERICAL and r.iterations == 1
+    assert list(r.enter) == [0] and list(r.row) == [0]
+    # the same LP with a finite second column entry in row 1 solves normally
+    A2 = np.array([[1e-8, 0.0], [1.0, 1.0]])
+    r = oracle.solve(A2, np.array([0.0, 1.0]), np.array([1.0, 1.0]))
+    assert r.status == oracle.OPTIMAL
+
+
 def test_already_optimal():
     A, b, c = lpgen.dense_lp(2, 20, 30)
     r = oracle.solve(A, b, -c)
