@@ -42,6 +42,8 @@ extern "C" {
 #define LP_OPTIMAL 1    /* no nonbasic reduced cost below -eps_d (Step 4) */
 #define LP_UNBOUNDED 2  /* the entering column has no entry alpha_i > eps_p (Step 5) */
 #define LP_ITER_LIMIT 3 /* max_iter pivots done and the basis is not optimal; lp_solve resumes */
+#define LP_NUMERICAL 4  /* the entering column Y_k had a non-finite entry, or the minimum ratio
+                           overflowed: the solve stopped before that pivot */
 
 /* ---- pivot-log flags ---- */
 #define LP_PIVOT_DEGENERATE 1 /* step length theta == 0 */
@@ -85,7 +87,8 @@ typedef struct lp_options {
                              best improving one among them.  When none of them improves, every
                              column is priced in FP64 (the plain Step 4), so optimality and the
                              aspiration case are always decided in FP64.  FTRAN, the ratio test
-                             and the update stay FP64. */
+                             and the update stay FP64.  Every |A'_ij| must then be at most
+                             FLT_MAX (else LP_ERR_ARG). */
   int32_t shortlist_k;    /* LP_MIXED: candidates re-priced in FP64, 1..16 (default 16) */
   int32_t reinv_period;   /* recompute B^-1, x_B, W and z from the basis (FP64 LU on the GPU) after
                              every this many pivots; 0 = never; -1 = default: 64 for LP_MIXED,

@@ -14,12 +14,12 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblpgpu.so")
 
 LP_OK, LP_ERR_ARG, LP_ERR_NEG_RHS, LP_ERR_NOMEM, LP_ERR_DEVICE, LP_ERR_STATE = 0, -1, -2, -3, -4, -5
-LP_RUNNING, LP_OPTIMAL, LP_UNBOUNDED, LP_ITER_LIMIT = 0, 1, 2, 3
+LP_RUNNING, LP_OPTIMAL, LP_UNBOUNDED, LP_ITER_LIMIT, LP_NUMERICAL = 0, 1, 2, 3, 4
 LP_PIVOT_DEGENERATE, LP_PIVOT_TIE, LP_PIVOT_ASPIRATION, LP_PIVOT_LCLEAR = 1, 2, 4, 8
 LP_MIN, LP_MAX = 0, 1
 LP_FP64, LP_MIXED = 0, 1
 LP_MAX_ROWS = 10112
-STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT"}
+STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT", 4: "NUMERICAL"}
 
 
 class lp_options(C.Structure):

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -317,8 +318,11 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   std::vector<double> hb(m), hc(n);
   if (!device_inputs) {
     const size_t cnt = (size_t)m * n;
-    for (size_t k = 0; k < cnt; ++k)
+    for (size_t k = 0; k < cnt; ++k) {
       if (!std::isfinite(A[k])) return fail(LP_ERR_ARG, "A contains a non-finite value");
+      if (mixed && std::fabs(A[k]) > (double)FLT_MAX)
+        return fail(LP_ERR_ARG, "A has an entry beyond the FP32 range, which the mixed form cannot screen");
+    }
     for (int32_t i = 0; i < m; ++i) {
       if (!std::isfinite(b[i])) return fail(LP_ERR_ARG, "b contains a non-finite value");
       if (b[i] < 0.0) return fail(LP_ERR_NEG_RHS, "b_i < 0: the slack basis is infeasible");
@@ -473,7 +477,10 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
     e = dalloc(p, &flag, 1);
     if (e != hipSuccess) return bail(fail_hip(e, "allocating a flag"));
     if ((e = hipMemsetAsync(flag, 0, sizeof(int32_t), s)) != hipSuccess) return bail(fail_hip(e, "validating"));
-    if ((e = launch_check_finite(A, (int64_t)m * n, flag, s)) != hipSuccess) return bail(fail_hip(e, "validating A"));
+    // (the mixed form keeps an FP32 copy of A', so there every entry must be in the FP32 range)
+    const double bound = mixed ? (double)FLT_MAX : DBL_MAX;
+    if ((e = launch_check_finite(A, (int64_t)m * n, bound, flag, s)) != hipSuccess)
+      return bail(fail_hip(e, "validating A"));
     int32_t hflag = 0;
     if ((e = hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipMemcpyAsync(hb.data(), b, sizeof(double) * m, hipMemcpyDeviceToHost, s)) != hipSuccess ||
@@ -481,7 +488,9 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
         (e = hipStreamSynchronize(s)) != hipSuccess)
       return bail(fail_hip(e, "reading the LP data"));
     dfree(p, flag);
-    if (hflag) return bail(fail(LP_ERR_ARG, "A contains a non-finite value"));
+    if (hflag)
+      return bail(fail(LP_ERR_ARG, mixed ? "A contains a non-finite value or one beyond the FP32 range (mixed form)"
+                                         : "A contains a non-finite value"));
     for (int32_t i = 0; i < m; ++i) {
       if (!std::isfinite(hb[i])) return bail(fail(LP_ERR_ARG, "b contains a non-finite value"));
       if (hb[i] < 0.0) return bail(fail(LP_ERR_NEG_RHS, "b_i < 0: the slack basis is infeasible"));

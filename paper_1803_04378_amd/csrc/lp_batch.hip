@@ -96,21 +96,6 @@ __device__ __forceinline__ void g_lexmin2(double& d1, int& j1, double& d2, int& 
 }
 
 template <int G>
-__device__ __forceinline__ double g_min(double v, double* xd) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
-  if constexpr (G > 1) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) xd[wave] = v;
-    __syncthreads();
-    v = xd[0];
-    for (int w = 1; w < G; ++w) v = fmin(v, xd[w]);
-    __syncthreads();
-  }
-  return v;
-}
-
-template <int G>
 __device__ __forceinline__ void g_cnt_min(int& cnt, int& low, int* xj) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -346,10 +331,24 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
     if (q < 0) break;  // OPTIMAL or ITER_LIMIT; the pending pivot is applied
 
     // Step 6: minimum ratio, tolerance ties, tabu list of the entering variable.
-    double th = __builtin_inf();
-    for (int i = tid; i < m; i += T) th = fmin(th, ratio[i]);
-    th = g_min<G>(th, xd);
-    if (th == __builtin_inf()) {  // Step 5: Y_k <= 0
+    // (minimum ratio, lowest candidate row) and whether some alpha is not finite, in one
+    // reduction; the same decisions as k_finish.
+    double th = __builtin_inf(), fin = 1.0;
+    int lowc = INT_MAX, fj = INT_MAX;
+    for (int i = tid; i < m; i += T) {
+      const double a = al_n[i];
+      if (!isfinite(a)) fin = 0.0;
+      if (a > bd.eps_p && lex_less(ratio[i], i, th, lowc)) {
+        th = ratio[i];
+        lowc = i;
+      }
+    }
+    g_lexmin2<G>(th, lowc, fin, fj, xd, xj);
+    if (fin == 0.0 || (lowc != INT_MAX && !isfinite(th))) {
+      status = kStatusNumerical;
+      break;
+    }
+    if (lowc == INT_MAX) {  // Step 5: Y_k <= 0
       status = kStatusUnbounded;
       ray = q;
       break;

@@ -21,6 +21,7 @@ constexpr int kStatusRunning = 0;
 constexpr int kStatusOptimal = 1;
 constexpr int kStatusUnbounded = 2;
 constexpr int kStatusIterLimit = 3;
+constexpr int kStatusNumerical = 4;
 
 constexpr int kFlagDegenerate = 1;
 constexpr int kFlagTie = 2;
@@ -161,7 +162,8 @@ hipError_t launch_init(const DevLP& lp, const double* b, const double* c, double
 hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s);
 hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s);
 hipError_t launch_finish(const DevLP& lp, hipStream_t s);
-hipError_t launch_check_finite(const double* x, int64_t count, int32_t* flag, hipStream_t s);
+// Sets *flag when some |x_k| exceeds bound (or is NaN).
+hipError_t launch_check_finite(const double* x, int64_t count, double bound, int32_t* flag, hipStream_t s);
 // Kernel entry points for explicit graph construction.
 const void* price_kernel();
 const void* update_kernel();

@@ -308,8 +308,10 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   __shared__ int s_row[waves * kMaxRowsPerWave];
   __shared__ double s_al[waves * kMaxRowsPerWave];
   __shared__ int s_bv[waves * kMaxRowsPerWave];
+  __shared__ int s_nf;  // some row of this workgroup has a non-finite alpha
   const int m = lp.m, n = lp.n, ld = lp.ld, ld2 = ld / 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_nf = 0;  // read after the barriers below
   const int gw = blockIdx.x * waves + wave;
   const int nw = gridDim.x * waves;
   double2* s_rho = smem2;
@@ -573,7 +575,8 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
           al_n[i] = acc;
           s_rt[wave * kMaxRowsPerWave + c] = rt;
           s_tau[wave * kMaxRowsPerWave + c] = tau;
-          s_row[wave * kMaxRowsPerWave + c] = i;
+          s_row[wave * kMaxRowsPerWave + c] = acc > eps_p ? i : INT_MAX;  // INT_MAX: not a candidate
+          if (!isfinite(acc)) s_nf = 1;
           s_al[wave * kMaxRowsPerWave + c] = acc;
           s_bv[wave * kMaxRowsPerWave + c] = 2 * bv + ((bv < n || in) ? 1 : 0);
         }
@@ -632,7 +635,8 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
           al_n[i] = acc;
           s_rt[wave * kMaxRowsPerWave + c] = rt;
           s_tau[wave * kMaxRowsPerWave + c] = tau;
-          s_row[wave * kMaxRowsPerWave + c] = i;
+          s_row[wave * kMaxRowsPerWave + c] = acc > eps_p ? i : INT_MAX;  // INT_MAX: not a candidate
+          if (!isfinite(acc)) s_nf = 1;
           s_al[wave * kMaxRowsPerWave + c] = acc;
           s_bv[wave * kMaxRowsPerWave + c] = 2 * bv + ((bv < n || in) ? 1 : 0);
         }
@@ -670,8 +674,9 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
     wave_lexmin_payload(th, low, slot);
     wave_two_smallest(t1, t2);
     if (lane == 0) {
-      lp.part_th[blockIdx.x] = th;
-      lp.part_low[blockIdx.x] = low;
+      // a non-finite alpha is published as (-inf, -1), which no ratio (>= 0) undercuts
+      lp.part_th[blockIdx.x] = s_nf ? -__builtin_inf() : th;
+      lp.part_low[blockIdx.x] = s_nf ? -1 : low;
       lp.part_t1[blockIdx.x] = t1;
       lp.part_t2[blockIdx.x] = t2;
       lp.part_al[blockIdx.x] = low != INT_MAX ? s_al[slot] : 0.0;
@@ -709,6 +714,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
   asm volatile("" ::: "memory");  // compiler-only: all of the above is requested first
   if (tid >= nparts) {
     pth = pt1 = pt2 = __builtin_inf();
+    plow = INT_MAX;
   }
   if (verdict < 0) return;  // k_update did not run
   if (verdict != kStatusRunning) {  // OPTIMAL or ITER_LIMIT; k_update applied the pending pivot
@@ -722,14 +728,29 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
   }
 
   const double* al = cur ? lp.alpha0 : lp.alpha1;  // FTRAN result of this iteration
+  // (minimum ratio, lowest candidate row): row INT_MAX means no candidate row, and
+  // (-inf, -1) a non-finite alpha somewhere.
   double th = pth;
-  for (int k = tid + B; k < nparts; k += B) th = fmin(th, lp.part_th[k]);
-  th = block_min<B>(th, red_d, red_j);
-  if (th == __builtin_inf()) {  // Step 5: Y_k <= 0
+  int lowc = plow;
+  for (int k = tid + B; k < nparts; k += B) {
+    const double d = lp.part_th[k];
+    const int j = lp.part_low[k];
+    if (lex_less(d, j, th, lowc)) {
+      th = d;
+      lowc = j;
+    }
+  }
+  block_lexmin<B>(th, lowc, red_d, red_j);
+  const bool nonfinite = th == -__builtin_inf() || (lowc != INT_MAX && !isfinite(th));
+  if (nonfinite || lowc == INT_MAX) {
     if (tid == 0) {
-      ctl->status = kStatusUnbounded;
+      if (nonfinite) {
+        ctl->status = kStatusNumerical;
+      } else {  // Step 5: Y_k <= 0
+        ctl->status = kStatusUnbounded;
+        ctl->ray = q;
+      }
       ctl->verdict = -1;
-      ctl->ray = q;
       ctl->q = -1;
       ctl->r = -1;
     }
@@ -869,11 +890,12 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
   }
 }
 
-__global__ void k_check_finite(const double* __restrict__ x, int64_t count, int32_t* flag) {
+// Sets *flag when some |x_k| exceeds bound or is NaN.
+__global__ void k_check_finite(const double* __restrict__ x, int64_t count, double bound, int32_t* flag) {
   const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   bool bad = false;
-  for (size_t k = tid; k < (size_t)count; k += stride) bad |= !isfinite(x[k]);
+  for (size_t k = tid; k < (size_t)count; k += stride) bad |= !(fabs(x[k]) <= bound);
   if (bad) *flag = 1;
 }
 
@@ -922,10 +944,10 @@ hipError_t launch_finish(const DevLP& lp, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_check_finite(const double* x, int64_t count, int32_t* flag, hipStream_t s) {
+hipError_t launch_check_finite(const double* x, int64_t count, double bound, int32_t* flag, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const int grid = (int)std::min<int64_t>(2048, (count + 255) / 256);
-  hipLaunchKernelGGL(k_check_finite, dim3(grid), dim3(256), 0, s, x, count, flag);
+  hipLaunchKernelGGL(k_check_finite, dim3(grid), dim3(256), 0, s, x, count, bound, flag);
   return hipGetLastError();
 }
 

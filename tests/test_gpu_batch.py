@@ -76,7 +76,8 @@ def test_batch_equals_serial(lpg, small_m):
 
 
 def test_batch_degenerate_and_special_lps(lpg):
-    """Ties, the tabu list, unbounded and trivially optimal LPs inside one batch."""
+    """Ties, the tabu list, unbounded, trivially optimal and overflowing (NUMERICAL) LPs
+    inside one batch."""
     from test_oracle_pins import _embedded
     lps = [lpgen.degenerate_lp(s, 60 + 10 * s, 120 + 20 * s, budget_row=True) for s in range(6)]
     lps += [lpgen.degenerate_lp(s, 40, 80) for s in range(4)]
@@ -92,6 +93,8 @@ def test_batch_degenerate_and_special_lps(lpg):
     lps.append((A, b, c))
     A, b, c = lpgen.dense_lp(3, 20, 30)
     lps.append((A, b, -c))
+    from test_gpu_parity import NUMERICAL_LPS
+    lps += NUMERICAL_LPS
     for small_m in (0, 64):
         _say(f"case: special LPs, batch_small_m={small_m}")
         with lpg.Batch(lps, batch_small_m=small_m) as bt:

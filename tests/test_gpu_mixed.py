@@ -237,6 +237,23 @@ def test_mixed_options(lpg, opts):
         assert stats["reinversions"] == sol["iterations"] // 128
 
 
+def test_mixed_rejects_entries_beyond_fp32_range(lpg):
+    """The mixed form screens with an FP32 copy of A': an entry beyond FLT_MAX is an
+    argument error there (host and device inputs), and accepted by the FP64 path."""
+    import torch
+    A, b, c = lpgen.dense_lp(1, 4, 5)
+    A[2, 3] = 1e39
+    with pytest.raises(lpg.LPError) as e:
+        lpg.LP(A, b, c, precision="mixed")
+    assert e.value.code == -1
+    dA = torch.from_numpy(np.asfortranarray(A).T.copy()).cuda().t()
+    with pytest.raises(lpg.LPError) as e:
+        lpg.LP.from_torch(dA, torch.from_numpy(b).cuda(), torch.from_numpy(c).cuda(), precision="mixed")
+    assert e.value.code == -1
+    with lpg.LP(A, b, c) as p:
+        assert p.solve() in (lpg.LP_OPTIMAL, lpg.LP_UNBOUNDED)
+
+
 def test_mixed_unbounded_and_trivial(lpg):
     A, b, c = lpgen.dense_lp(2, 20, 30)
     A[:, 5] = -np.abs(A[:, 5])

@@ -84,6 +84,28 @@ def test_dense_ragged_shapes(lpg, m, n):
     assert_parity(lpg, A, b, c)
 
 
+NUMERICAL_LPS = [
+    # the only ratio is 1e301 / 1e-8 = inf
+    (np.array([[1e-8]]), np.array([1e301]), np.array([1.0])),
+    # a degenerate pivot on alpha_r = 1e-8 drives B^-1[1,0] to -inf; the next FTRAN gives NaN
+    (np.array([[1e-8, 0.0], [1e301, 1.0]]), np.array([0.0, 1.0]), np.array([1.0, 1.0])),
+]
+
+
+@pytest.mark.parametrize("case", range(len(NUMERICAL_LPS)))
+@pytest.mark.parametrize("ips", [1, 16])
+def test_numerical_status_matches_oracle(lpg, case, ips):
+    """Overflow stops the solve with NUMERICAL at the same pivot as the oracle; a second
+    solve call on the stopped handle reports it again without pivoting."""
+    A, b, c = NUMERICAL_LPS[case]
+    ref, (st, sol, piv, _) = assert_parity(lpg, A, b, c, iters_per_sync=ips)
+    assert st == oracle.NUMERICAL == lpg.LP_NUMERICAL
+    with lpg.LP(A, b, c, iters_per_sync=ips) as p:
+        assert p.solve() == lpg.LP_NUMERICAL
+        assert p.solve() == lpg.LP_NUMERICAL
+        assert p.solution()["iterations"] == len(ref.enter)
+
+
 @pytest.mark.parametrize("m,seed", [(60, 0), (100, 1), (150, 2), (200, 3)])
 def test_degenerate_budget_law(lpg, m, seed):
     """Ties, degenerate pivots, the leaving-side tabu list and aspiration all occur here."""
