@@ -7,14 +7,17 @@ W warm-up pivots run first, then exactly K pivots of the iteration graph are tim
 (`value`).  A second pass of K pivots launches the same kernels directly, each with
 start and stop HIP events bound to its dispatch, for the per-kernel durations behind
 the roofline of the dominant kernel.  The printed line also carries the time to
-optimality, the mixed-precision form against the FP64 path on its own configuration,
-the batched form, and the CPU oracle's rate on a bounded sample of the same solve.
+optimality (median of 5 solves after a warm-up), the mixed-precision form against the
+FP64 path and against the FP64 path with the same reinversion period on its own
+configuration, the batched form (solve, and with the host-to-device upload), and the CPU
+oracle's rate on a bounded sample of the same solve.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -99,21 +102,32 @@ def timed_leg(lpg, torch, dev, opts, warmup, steps, profile):
     return t1 - t0, kernel_table(s0, s1)
 
 
-def solve_leg(lpg, torch, dev, opts):
-    with lpg.LP.from_torch(*dev, **opts) as lp:
-        lp.solve(1)  # graph built, caches warm
+def timed_solves(lp, torch, reps):
+    """One warm-up solve, then `reps` solves from the slack basis; returns the times and
+    the status of the last one."""
+    lp.solve()
+    times = []
+    for _ in range(reps):
         lp.reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = lp.solve()
         torch.cuda.synchronize()
-        ts = time.perf_counter() - t0
+        times.append(time.perf_counter() - t0)
+    return times, st
+
+
+def solve_leg(lpg, torch, dev, opts, reps=5):
+    """Time to optimality: median of `reps` solves after a warm-up solve."""
+    with lpg.LP.from_torch(*dev, **opts) as lp:
+        times, st = timed_solves(lp, torch, reps)
         sol = lp.solution()
-    return dict(status=lpg.STATUS_NAMES[st], seconds=round(ts, 5), iterations=sol["iterations"],
-                objective=sol["objective"], iter_per_s=round(sol["iterations"] / ts, 1))
+    ts = statistics.median(times)
+    return dict(status=lpg.STATUS_NAMES[st], seconds=round(ts, 5), runs=[round(t, 5) for t in times],
+                iterations=sol["iterations"], objective=sol["objective"], iter_per_s=round(sol["iterations"] / ts, 1))
 
 
-def mixed_leg(lpg, torch, m, n, seed, steps, stream, profile_only=False):
+def mixed_leg(lpg, torch, m, n, seed, steps, stream, profile_only=False, reps=5):
     """Mixed-precision form on its own configuration (dense law, m x n): time to optimality
     against the FP64 path on the same GPU, objective error and KKT residuals against the
     FP64 path's optimum, and a profiled stretch of iterations for the per-kernel split."""
@@ -129,17 +143,16 @@ def mixed_leg(lpg, torch, m, n, seed, steps, stream, profile_only=False):
     dev = (dA, db, dc)
     opts = dict(iters_per_sync=16, stream=stream.cuda_stream)
     out = {"workload": f"dense LP m={m}, n={n}, seed {seed}; FP32 shortlist top-16 re-priced in FP64, "
-                       f"FP64 reinversion every 64 pivots"}
+                       f"FP64 reinversion every 64 pivots; times are medians of {reps} solves after a warm-up"}
     sols = {}
-    for prec in (() if profile_only else ("fp64", "mixed")):
-        with lpg.LP.from_torch(*dev, precision=prec, **opts) as lp:
-            lp.solve(1)
-            lp.reset()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st = lp.solve()
-            torch.cuda.synchronize()
-            ts = time.perf_counter() - t0
+    # the plain FP64 path, the same with reinversion every 64 pivots (separates the two
+    # effects), and the mixed form
+    variants = {"fp64": dict(precision="fp64"), "fp64_reinv64": dict(precision="fp64", reinv_period=64),
+                "mixed": dict(precision="mixed")}
+    for prec, vopt in (() if profile_only else variants.items()):
+        with lpg.LP.from_torch(*dev, **vopt, **opts) as lp:
+            times, st = timed_solves(lp, torch, reps)
+            ts = statistics.median(times)
             sol = lp.solution()
             stt = lp.stats()
             if prec == "mixed":
@@ -150,14 +163,18 @@ def mixed_leg(lpg, torch, m, n, seed, steps, stream, profile_only=False):
                 torch.cuda.synchronize()
                 reinv_opt = dict(k=int((sol["basis"] < n).sum()), ms=round((time.perf_counter() - t0) / 3 * 1e3, 3))
         sols[prec] = sol
-        row = dict(status=lpg.STATUS_NAMES[st], seconds=round(ts, 5), iterations=sol["iterations"],
-                   iter_per_s=round(sol["iterations"] / ts, 1), objective=sol["objective"])
+        row = dict(status=lpg.STATUS_NAMES[st], seconds=round(ts, 5), runs=[round(t, 5) for t in times],
+                   iterations=sol["iterations"], iter_per_s=round(sol["iterations"] / ts, 1),
+                   objective=sol["objective"])
+        if prec != "fp64":
+            # reinversion counters of the last solve (stats restart at each reset)
+            row.update(reinversions=stt["reinversions"], reinv_ms=round(stt["reinv_ms"], 3))
         if prec == "mixed":
-            row.update(reinversions=stt["reinversions"], reinv_ms=round(stt["reinv_ms"], 3),
-                       full_fp64_prices=stt["full_prices"], reinversion_at_optimum=reinv_opt)
+            row.update(full_fp64_prices=stt["full_prices"], reinversion_at_optimum=reinv_opt)
         out[prec] = row
     if sols:
         out["speedup_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 4)
+        out["speedup_vs_fp64_reinv64"] = round(out["fp64_reinv64"]["seconds"] / out["mixed"]["seconds"], 4)
         ref = sols["fp64"]["objective"]
         x, y = sols["mixed"]["x"], sols["mixed"]["y"]
         slack = b - A @ x
@@ -183,7 +200,10 @@ def batch_leg(lpg, count, serial_sample):
     solved in one persistent launch, against serial lp_solve calls on a sample of them."""
     import lpgen
     lps = lpgen.batch_lps(0, count)
-    with lpg.Batch(lps) as bt:
+    t0 = time.perf_counter()
+    bt0 = lpg.Batch(lps)  # host -> device upload of every LP (and the pooled work memory)
+    create = time.perf_counter() - t0
+    with bt0 as bt:
         bt.solve()  # the first solve also runs the autotuner
         t0 = time.perf_counter()
         bt.solve()
@@ -204,6 +224,8 @@ def batch_leg(lpg, count, serial_sample):
         h.close()
     lps_per_s = count / (st["solve_ms"] * 1e-3)
     return dict(lps=count, lps_per_s=round(lps_per_s, 1), solve_ms=round(st["solve_ms"], 3),
+                create_ms=round(create * 1e3, 3),
+                lps_per_s_with_upload=round(count / (create + st["solve_ms"] * 1e-3), 1),
                 wall_ms=round(wall * 1e3, 3), pivots=iters, all_optimal=bool((res["status"] == 1).all()),
                 narrow_lps=st["narrow_lps"], wide_lps=st["wide_lps"], tune_ms=round(st["tune_ms"], 1),
                 serial_ms_per_lp=round(serial * 1e3, 4), serial_sample=len(handles),

@@ -8,6 +8,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "lp_batch.h"
@@ -340,17 +341,79 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
   p->d.eps_p = o.eps_p;
   p->d.eps_z = o.eps_z;
   p->d.eps_t = o.eps_t;
-  // Upload: pack on the host (A' padded to ld rows), then one copy per pool.
+  // Upload.  The LPs' A' blocks are consecutive in the pool, so runs of consecutive LPs
+  // are packed (columns padded to ld rows with zeros) into one of two pinned staging
+  // buffers while the other one's copy is in flight.
   {
-    std::vector<double> hA((size_t)oA, 0.0), hb((size_t)ob), hc((size_t)oc, 0.0);
+    std::vector<double> hb((size_t)ob), hc((size_t)oc, 0.0);
     for (int32_t i = 0; i < count; ++i) {
       const BatchLP& L = p->lps[i];
-      for (int32_t j = 0; j < L.n; ++j)
-        std::memcpy(&hA[L.offA + (size_t)j * L.ld], A[i] + (size_t)j * L.m, sizeof(double) * L.m);
       std::memcpy(&hb[L.offb], b[i], sizeof(double) * L.m);
       if (L.n) std::memcpy(&hc[L.offc], c[i], sizeof(double) * L.n);
     }
-    hipError_t e = hipMemcpy(dA, hA.data(), sizeof(double) * hA.size(), hipMemcpyHostToDevice);
+    size_t largest = 0;
+    for (const BatchLP& L : p->lps) largest = std::max(largest, (size_t)L.ld * std::max(L.n, 1));
+    const size_t cap = std::min<size_t>((size_t)oA, std::max<size_t>((size_t)8 << 20, largest));  // doubles
+    double* stage[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+      e = hipHostMalloc(reinterpret_cast<void**>(&stage[k]), sizeof(double) * cap, hipHostMallocDefault);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&done[k], hipEventDisableTiming);
+    }
+    int buf = 0;
+    bool pending[2] = {false, false};
+    size_t used = 0, run_start = 0;  // doubles packed in stage[buf]; pool offset of its first
+    auto flush = [&]() -> hipError_t {
+      if (used == 0) return hipSuccess;
+      hipError_t f = hipMemcpyAsync(dA + run_start, stage[buf], sizeof(double) * used, hipMemcpyHostToDevice,
+                                    p->stream);
+      if (f == hipSuccess) f = hipEventRecord(done[buf], p->stream);
+      pending[buf] = true;
+      buf ^= 1;
+      used = 0;
+      if (f == hipSuccess && pending[buf]) f = hipEventSynchronize(done[buf]);  // the other copy is done
+      pending[buf] = false;
+      return f;
+    };
+    // Runs of LPs that fill a staging buffer; each run is packed by up to 8 threads.
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int nthreads = (int)std::max(1u, std::min(8u, hw));
+    auto pack = [&](int32_t i, double* dst) {
+      const BatchLP& L = p->lps[i];
+      for (int32_t j = 0; j < L.n; ++j) {
+        std::memcpy(dst + (size_t)j * L.ld, A[i] + (size_t)j * L.m, sizeof(double) * L.m);
+        std::memset(dst + (size_t)j * L.ld + L.m, 0, sizeof(double) * (L.ld - L.m));
+      }
+      if (L.n == 0) std::memset(dst, 0, sizeof(double) * L.ld);
+    };
+    for (int32_t i0 = 0; i0 < count && e == hipSuccess;) {
+      int32_t i1 = i0;
+      size_t sz = 0;
+      while (i1 < count) {
+        const size_t s1 = (size_t)p->lps[i1].ld * std::max(p->lps[i1].n, 1);
+        if (sz + s1 > cap) break;
+        sz += s1;
+        ++i1;
+      }
+      run_start = (size_t)p->lps[i0].offA;
+      double* base = stage[buf];
+      auto work = [&](int tno) {
+        for (int32_t i = i0 + tno; i < i1; i += nthreads) pack(i, base + ((size_t)p->lps[i].offA - run_start));
+      };
+      std::vector<std::thread> pool;
+      for (int tno = 1; tno < nthreads && i0 + tno < i1; ++tno) pool.emplace_back(work, tno);
+      work(0);
+      for (auto& th : pool) th.join();
+      used = sz;
+      e = flush();
+      i0 = i1;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    for (int k = 0; k < 2; ++k) {
+      if (stage[k]) (void)hipHostFree(stage[k]);
+      if (done[k]) (void)hipEventDestroy(done[k]);
+    }
     if (e == hipSuccess) e = hipMemcpy(db, hb.data(), sizeof(double) * hb.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dc, hc.data(), sizeof(double) * hc.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(fail_hip(e, "uploading the batch"));
