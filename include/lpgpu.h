@@ -94,7 +94,9 @@ typedef struct lp_options {
                              every this many pivots; 0 = never; -1 = default: 64 for LP_MIXED,
                              never for LP_FP64.  Takes effect at status read-backs, so it runs
                              exactly every reinv_period pivots when iters_per_sync divides it. */
-  int32_t pad0;
+  int32_t batch_binv_lds_m; /* batched solver: wide LPs with m <= this keep B^-1 in LDS (run by a
+                             second persistent launch); 0 = never; -1 = the threshold is chosen by
+                             timing the whole batch on its first solve (default) */
 } lp_options;
 
 typedef struct lp_stats {
@@ -207,7 +209,8 @@ int lp_reinvert(lp_problem *p);
 /* Frees every device and host resource of the handle.  NULL-safe. */
 void lp_destroy(lp_problem *p);
 
-/* ---- batched form: many independent LPs in one persistent kernel launch ---- */
+/* ---- batched form: many independent LPs in persistent kernel launches (one, or two when
+ *      some LPs keep B^-1 in LDS) ---- */
 
 typedef struct lp_batch lp_batch;
 
@@ -215,12 +218,14 @@ typedef struct lp_batch_stats {
   int64_t count;              /* LPs in the batch */
   int64_t narrow_lps;         /* LPs solved by one wavefront each in the last solve */
   int64_t wide_lps;           /* LPs solved by a whole workgroup */
-  int64_t work_items;         /* queue entries of the last launch */
-  int64_t workgroups;         /* persistent workgroups launched */
-  int64_t lds_bytes;          /* LDS per workgroup */
+  int64_t work_items;         /* queue entries of the last solve (both launches) */
+  int64_t workgroups;         /* persistent workgroups of the launch that keeps B^-1 in HBM */
+  int64_t lds_bytes;          /* LDS per workgroup of that launch */
   int64_t narrow_bucket_mask; /* bit k: m in (16k, 16k+16] was tuned to one wavefront per LP */
-  double solve_ms;            /* device time of the last lp_batch_solve launch */
+  double solve_ms;            /* device time of the last lp_batch_solve (both launches) */
   double tune_ms;             /* host time spent by the autotuner */
+  int64_t binv_lds_lps;       /* LPs that kept B^-1 in LDS in the last solve */
+  int64_t binv_lds_m;         /* the threshold in effect (option or tuned) */
 } lp_batch_stats;
 
 /*
@@ -234,8 +239,11 @@ typedef struct lp_batch_stats {
 int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32_t *n, const double *const *A,
                     const double *const *b, const double *const *c, const lp_options *opt);
 
-/* Solves every LP of the batch from its slack basis in one persistent launch (the first
- * call with batch_small_m = -1 first times both execution modes per m-bucket). */
+/* Solves every LP of the batch from its slack basis: one persistent launch for the LPs
+ * whose B^-1 stays in HBM, then one for those that keep it in LDS (none by default on
+ * mixed batches; see batch_binv_lds_m).  The first call with batch_small_m = -1 first times
+ * both execution modes per m-bucket, and with batch_binv_lds_m = -1 then times each
+ * threshold in {0, 48, 96, 128} that moves some LP to LDS on the whole batch. */
 int lp_batch_solve(lp_batch *bt);
 
 /* Per-LP status, objective (user's sense) and pivot count; arrays of `count` entries, any

@@ -40,7 +40,7 @@ class lp_options(C.Structure):
         ("precision", C.c_int32),
         ("shortlist_k", C.c_int32),
         ("reinv_period", C.c_int32),
-        ("pad0", C.c_int32),
+        ("batch_binv_lds_m", C.c_int32),
     ]
 
 
@@ -84,6 +84,8 @@ class lp_batch_stats(C.Structure):
         ("narrow_bucket_mask", C.c_int64),
         ("solve_ms", C.c_double),
         ("tune_ms", C.c_double),
+        ("binv_lds_lps", C.c_int64),
+        ("binv_lds_m", C.c_int64),
     ]
 
 

@@ -539,6 +539,7 @@ int lp_default_options(lp_options* opt) {
   opt->record_pivots = 1;
   opt->profile = 0;
   opt->batch_small_m = -1;
+  opt->batch_binv_lds_m = -1;
   opt->stream = nullptr;
   opt->precision = LP_FP64;
   opt->shortlist_k = kShortlist;

@@ -2,8 +2,8 @@
 //
 // All LPs live in pooled arrays; BatchLP holds each one's sizes and element offsets.
 // Per LP:  A' ld x n column-major (ld = m rounded up to 8), b (m), c (n), B^-1 m x ld
-// row-major scratch, gen/excl (2*(n+m) ints), pivot log and tabu list (cap entries
-// each), and the final x_B / basis (m each).
+// row-major scratch (unused when the LP keeps B^-1 in LDS), gen/excl (2*(n+m) ints),
+// pivot log and tabu list (cap entries each), and the final x_B / basis (m each).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -17,6 +17,8 @@ struct BatchLP {
   int32_t m, n, ld, waves;  // waves: 1 (one wavefront per LP) or kBatchWaves (whole workgroup)
   int64_t offA, offb, offc, offB, offI, offLog, offOut;
   int64_t cap;              // pivot limit = capacity of its pivot log and tabu list
+  int32_t binv_lds;         // 1: B^-1 lives in LDS after the LP's vectors (k_batch<true>)
+  int32_t pad;
 };
 
 struct BatchDev {
@@ -49,9 +51,19 @@ struct BatchDev {
   double eps_d, eps_p, eps_z, eps_t;
 };
 
-// LDS bytes one LP needs (rounded to 16).
-size_t batch_lds_bytes(int m, int n);
-hipError_t launch_batch(const BatchDev& bd, int grid, size_t lds, hipStream_t s);
-hipError_t batch_occupancy(int* per_cu, size_t lds);
+// LDS one LP needs: W, rho, a_q (ld each), alpha x2, x_B and the ratios (m each) in FP64,
+// then basis and the list D with its flags (3m), pos and the tabu marks (2(n+m)) in
+// int32, rounded to 16 bytes.  With B^-1 in LDS, its m x ld FP64 follow.
+__host__ __device__ inline size_t batch_lds_bytes(int m, int n) {
+  const size_t ld = (size_t)(m + 7) / 8 * 8;
+  const size_t bytes = 8 * (3 * ld + 4 * (size_t)m) + 4 * (3 * (size_t)m + 2 * ((size_t)n + m));
+  return (bytes + 15) / 16 * 16;
+}
+__host__ __device__ inline size_t batch_lds_bytes_binv(int m, int n) {
+  return batch_lds_bytes(m, n) + 8 * (size_t)m * ((size_t)(m + 7) / 8 * 8);
+}
+// Launches k_batch<binv_lds>: B^-1 in the pooled HBM array, or in LDS.
+hipError_t launch_batch(const BatchDev& bd, int grid, size_t lds, bool binv_lds, hipStream_t s);
+hipError_t batch_occupancy(int* per_cu, size_t lds, bool binv_lds);
 
 }  // namespace lpgpu

@@ -119,19 +119,12 @@ __device__ __forceinline__ void g_cnt_min(int& cnt, int& low, int* xj) {
   }
 }
 
-size_t lds_doubles(int m, int ld) { return 3 * (size_t)ld + 4 * (size_t)m; }
-size_t lds_ints(int m, int n) { return 3 * (size_t)m + 2 * ((size_t)n + m); }
-
 }  // namespace
 
-size_t batch_lds_bytes(int m, int n) {
-  const int ld = (m + 7) / 8 * 8;
-  const size_t bytes = 8 * lds_doubles(m, ld) + 4 * lds_ints(m, n);
-  return (bytes + 15) / 16 * 16;
-}
-
 // One LP, solved by a group of G wavefronts; tid is the thread's index within the group.
-template <int G>
+// BLDS: B^-1 lives in LDS right after the LP's vectors (batch_lds_bytes), so the update
+// and FTRAN run on LDS; otherwise in the pooled HBM array.  The arithmetic is the same.
+template <int G, bool BLDS>
 __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int tid, double* xd, int* xj) {
   constexpr int T = 64 * G;
   const BatchLP L = bd.lps[id];
@@ -157,7 +150,7 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
   const double2* A2 = reinterpret_cast<const double2*>(A);
   const double* bb = bd.b + L.offb;
   const double* cc = bd.c + L.offc;
-  double* B = bd.Binv + L.offB;
+  double* B = BLDS ? reinterpret_cast<double*>(base + batch_lds_bytes(m, n)) : bd.Binv + L.offB;
   double2* B2 = reinterpret_cast<double2*>(B);
   int* gen = bd.iscr + L.offI;
   int* excl = gen + N;
@@ -447,6 +440,7 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
   }
 }
 
+template <bool BLDS>
 __global__ __launch_bounds__(kBatchBlock) void k_batch(BatchDev bd) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ double xd[2 * kBatchWaves];
@@ -461,25 +455,27 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BatchDev bd) {
     if (item >= bd.n_items) return;
     const int4 it = bd.items[item];
     if (bd.lps[it.x].waves > 1) {
-      solve_lp<kBatchWaves>(bd, it.x, lds, threadIdx.x, xd, xj);
+      solve_lp<kBatchWaves, BLDS>(bd, it.x, lds, threadIdx.x, xd, xj);
     } else {
       const int id = wave == 0 ? it.x : wave == 1 ? it.y : wave == 2 ? it.z : it.w;
-      if (id >= 0) solve_lp<1>(bd, id, lds + (size_t)wave * bd.slot_bytes, lane, nullptr, nullptr);
+      if (id >= 0) solve_lp<1, BLDS>(bd, id, lds + (size_t)wave * bd.slot_bytes, lane, nullptr, nullptr);
     }
     __syncthreads();
   }
 }
 
-hipError_t launch_batch(const BatchDev& bd, int grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBatchBlock), lds, s, bd);
+hipError_t launch_batch(const BatchDev& bd, int grid, size_t lds, bool binv_lds, hipStream_t s) {
+  if (binv_lds) hipLaunchKernelGGL(k_batch<true>, dim3(grid), dim3(kBatchBlock), lds, s, bd);
+  else hipLaunchKernelGGL(k_batch<false>, dim3(grid), dim3(kBatchBlock), lds, s, bd);
   return hipGetLastError();
 }
 
-hipError_t batch_occupancy(int* per_cu, size_t lds) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+hipError_t batch_occupancy(int* per_cu, size_t lds, bool binv_lds) {
+  const void* f = binv_lds ? reinterpret_cast<const void*>(&k_batch<true>) : reinterpret_cast<const void*>(&k_batch<false>);
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch, kBatchBlock, lds);
+  return binv_lds ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch<true>, kBatchBlock, lds)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch<false>, kBatchBlock, lds);
 }
 
 }  // namespace lpgpu

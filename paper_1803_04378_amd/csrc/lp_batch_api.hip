@@ -39,6 +39,10 @@ int fail_hip(hipError_t e, const char* what) {
 // m-buckets of the autotuner: (16k, 16k+16]; narrow mode is only possible while one LP
 // fits a wavefront's LDS slot.
 constexpr int kBucketWidth = 16;
+// LDS a workgroup may take (the kernel's static LDS comes on top).
+constexpr size_t kLdsLimit = 160 * 1024 - 1024;
+// Thresholds tried by the autotuner for keeping B^-1 in LDS (LPs with m <= threshold).
+constexpr int kBinvCandidates[] = {0, 48, 96, 128};
 
 }  // namespace
 
@@ -55,13 +59,18 @@ struct lp_batch {
   BatchLP* d_lps = nullptr;
   int4* d_items = nullptr;
   int32_t max_items = 0;
-  size_t region = 0;  // LDS bytes per workgroup
+  size_t region = 0;  // LDS bytes per workgroup (B^-1 in HBM)
   int grid = 0, per_cu = 0, num_cu = 0;
   int small_m = -1;   // LPs with m <= small_m are solved one per wavefront (after tuning)
   std::vector<int> bucket_narrow;  // per bucket: 1 narrow, 0 wide, -1 untuned
+  int binv_opt = -1;    // option batch_binv_lds_m
+  int binv_m = 0;       // wide LPs with m <= binv_m keep B^-1 in LDS (second launch)
+  bool binv_tuned = false;
+  size_t region_l = 0;  // LDS bytes per workgroup of that launch
+  int grid_l = 0;
   bool solved = false;
   double solve_ms = 0.0, tune_ms = 0.0;
-  int64_t narrow_lps = 0, wide_lps = 0, items_last = 0;
+  int64_t narrow_lps = 0, wide_lps = 0, binv_lds_lps = 0, items_last = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -127,7 +136,8 @@ std::vector<int4> make_items(const lp_batch* p, const std::vector<int>& ids) {
   return out;
 }
 
-int run_items(lp_batch* p, const std::vector<int4>& items, float* ms) {
+// One persistent launch over `items`: B^-1 in HBM (binv_lds false) or in LDS.
+int run_items(lp_batch* p, const std::vector<int4>& items, float* ms, bool binv_lds = false) {
   if (items.empty()) {
     if (ms) *ms = 0.f;
     return LP_OK;
@@ -140,8 +150,9 @@ int run_items(lp_batch* p, const std::vector<int4>& items, float* ms) {
   BatchDev d = p->d;
   d.n_items = (int32_t)items.size();
   HIP_TRY(hipEventRecord(p->ev0, p->stream), "recording an event");
-  const int grid = std::min<int>(p->grid, (int)items.size());
-  HIP_TRY(launch_batch(d, grid, p->region, p->stream), "launching the batched solver");
+  const int grid = std::min<int>(binv_lds ? p->grid_l : p->grid, (int)items.size());
+  HIP_TRY(launch_batch(d, grid, binv_lds ? p->region_l : p->region, binv_lds, p->stream),
+          "launching the batched solver");
   HIP_TRY(hipEventRecord(p->ev1, p->stream), "recording an event");
   HIP_TRY(hipEventSynchronize(p->ev1), "running the batched solver");
   float t = 0.f;
@@ -184,9 +195,13 @@ int autotune(lp_batch* p) {
   return LP_OK;
 }
 
-void assign_modes(lp_batch* p) {
+// Narrow or wide per LP (the tuned buckets or small_m), then B^-1 in LDS for wide LPs
+// with m <= binv_m whose vectors and B^-1 fit a workgroup's LDS, and that launch's LDS
+// size and grid.
+int assign_modes(lp_batch* p) {
   const size_t slot = p->region / kBatchWaves;
-  p->narrow_lps = p->wide_lps = 0;
+  p->narrow_lps = p->wide_lps = p->binv_lds_lps = 0;
+  size_t need = 0;
   for (auto& L : p->lps) {
     bool narrow = false;
     if (batch_lds_bytes(L.m, L.n) <= slot) {
@@ -199,7 +214,67 @@ void assign_modes(lp_batch* p) {
     }
     L.waves = narrow ? 1 : kBatchWaves;
     (narrow ? p->narrow_lps : p->wide_lps) += 1;
+    L.binv_lds = (!narrow && L.m <= p->binv_m && batch_lds_bytes_binv(L.m, L.n) <= kLdsLimit) ? 1 : 0;
+    if (L.binv_lds) {
+      p->binv_lds_lps += 1;
+      need = std::max(need, batch_lds_bytes_binv(L.m, L.n));
+    }
   }
+  p->region_l = need;
+  p->grid_l = 0;
+  if (need > 0) {
+    int per_cu = 0;
+    HIP_TRY(batch_occupancy(&per_cu, need, true), "querying occupancy");
+    if (per_cu < 1) return fail(LP_ERR_DEVICE, "batched solver: no occupancy with B^-1 in LDS");
+    p->grid_l = per_cu * p->num_cu;
+  }
+  return LP_OK;
+}
+
+// Every LP of the batch: the LPs with B^-1 in HBM in one launch, the others in a second
+// one; *ms is the sum of their device times and *items their work items.
+int solve_all(lp_batch* p, float* ms, int64_t* items_out) {
+  std::vector<int> hbm, lds;
+  for (int i = 0; i < p->count; ++i) (p->lps[i].binv_lds ? lds : hbm).push_back(i);
+  const std::vector<int4> ih = make_items(p, hbm), il = make_items(p, lds);
+  float m1 = 0.f, m2 = 0.f;
+  int rc;
+  if ((rc = run_items(p, ih, &m1, false)) != LP_OK) return rc;
+  if ((rc = run_items(p, il, &m2, true)) != LP_OK) return rc;
+  if (ms) *ms = m1 + m2;
+  if (items_out) *items_out = (int64_t)(ih.size() + il.size());
+  return LP_OK;
+}
+
+// The B^-1-in-LDS threshold: every candidate that moves some LP to LDS is timed once on
+// the whole batch (modes of the tuned buckets; the bucket tuning has warmed the kernels),
+// the fastest kept.  No timing at all when no candidate applies to any LP.
+int tune_binv(lp_batch* p) {
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<int> cands;
+  for (int cand : kBinvCandidates) {
+    p->binv_m = cand;
+    int rc = assign_modes(p);
+    if (rc != LP_OK) return rc;
+    if (cand == 0 || p->binv_lds_lps > 0) cands.push_back(cand);
+  }
+  float best = 0.f;
+  int best_m = 0;
+  for (size_t k = 0; cands.size() > 1 && k < cands.size(); ++k) {
+    p->binv_m = cands[k];
+    int rc = assign_modes(p);
+    if (rc != LP_OK) return rc;
+    float ms = 0.f;
+    if ((rc = solve_all(p, &ms, nullptr)) != LP_OK) return rc;
+    if (k == 0 || ms < best) {
+      best = ms;
+      best_m = cands[k];
+    }
+  }
+  p->binv_m = best_m;
+  p->binv_tuned = true;
+  p->tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return LP_OK;
 }
 
 }  // namespace
@@ -215,7 +290,7 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
   lp_default_options(&o);
   if (opt) o = *opt;
   if (o.sense != LP_MIN && o.sense != LP_MAX) return fail(LP_ERR_ARG, "options.sense must be LP_MIN or LP_MAX");
-  if (o.tabu_tenure < 0 || o.max_iter < 0) return fail(LP_ERR_ARG, "invalid options");
+  if (o.tabu_tenure < 0 || o.max_iter < 0 || o.batch_binv_lds_m < -1) return fail(LP_ERR_ARG, "invalid options");
   if (o.precision != LP_FP64 || o.reinv_period > 0)
     return fail(LP_ERR_ARG, "the batched solver runs in FP64 without reinversion (precision LP_FP64, reinv_period <= 0)");
   size_t max_bytes = 0, max_small = 0;
@@ -235,7 +310,8 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
     max_bytes = std::max(max_bytes, bytes);
     if (m[i] <= 4 * kBucketWidth) max_small = std::max(max_small, bytes);
   }
-  const size_t region = std::max(max_bytes, kBatchWaves * max_small);
+  // a multiple of 64, so that the narrow items' per-wavefront slots stay 16-byte aligned
+  const size_t region = (std::max(max_bytes, kBatchWaves * max_small) + 63) / 64 * 64;
   if (region > 160 * 1024 - 1024) return fail(LP_ERR_ARG, "an LP of the batch is too large for the batched solver");
 
   int dev = 0;
@@ -251,6 +327,7 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
   p->count = count;
   p->region = region;
   p->small_m = o.batch_small_m;
+  p->binv_opt = o.batch_binv_lds_m;
   if (o.stream) {
     p->stream = static_cast<hipStream_t>(o.stream);
   } else {
@@ -266,7 +343,7 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
     e = hipGetDeviceProperties(&prop, dev);
     if (e != hipSuccess) return bail(fail_hip(e, "querying the device"));
     p->num_cu = prop.multiProcessorCount;
-    e = batch_occupancy(&p->per_cu, region);
+    e = batch_occupancy(&p->per_cu, region, false);
     if (e != hipSuccess) return bail(fail_hip(e, "querying occupancy"));
     if (p->per_cu < 1) return bail(fail(LP_ERR_ARG, "batched solver does not fit the device"));
     p->grid = p->per_cu * p->num_cu;
@@ -428,14 +505,15 @@ int lp_batch_solve(lp_batch* p) {
   if (p->small_m < 0 && p->bucket_narrow.empty()) {
     if ((rc = autotune(p)) != LP_OK) return rc;
   }
-  assign_modes(p);
-  std::vector<int> all(p->count);
-  std::iota(all.begin(), all.end(), 0);
-  const std::vector<int4> items = make_items(p, all);
+  if (p->binv_opt >= 0) {
+    p->binv_m = p->binv_opt;
+  } else if (!p->binv_tuned) {
+    if ((rc = tune_binv(p)) != LP_OK) return rc;
+  }
+  if ((rc = assign_modes(p)) != LP_OK) return rc;
   float ms = 0.f;
-  if ((rc = run_items(p, items, &ms)) != LP_OK) return rc;
+  if ((rc = solve_all(p, &ms, &p->items_last)) != LP_OK) return rc;
   p->solve_ms = ms;
-  p->items_last = (int64_t)items.size();
   p->solved = true;
   return LP_OK;
 }
@@ -513,6 +591,8 @@ int lp_batch_get_stats(const lp_batch* p, lp_batch_stats* s) {
   s->work_items = p->items_last;
   s->workgroups = p->grid;
   s->lds_bytes = (int64_t)p->region;
+  s->binv_lds_lps = p->binv_lds_lps;
+  s->binv_lds_m = p->binv_m;
   int64_t mask = 0;
   for (size_t bk = 0; bk < p->bucket_narrow.size() && bk < 63; ++bk)
     if (p->bucket_narrow[bk] == 1) mask |= (int64_t)1 << bk;

@@ -263,7 +263,8 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
 // per-column lookups and the unit term of a row's basic slack are LDS reads.
 
 // A vector of up to 5 * kUpdateBlock double2 (ld <= 10240) loaded by one workgroup into
-// registers, five per thread, with clamped indices (no branch for a load to wait behind).
+// registers, up to five per thread, with clamped indices inside a chunk (no lane-level
+// branch for a load to wait behind).
 // Held as native vectors: copies of the double2 struct go through a stack temporary.
 struct Hold5 {
   v2d h0, h1, h2, h3, h4;
@@ -272,14 +273,16 @@ constexpr int kUpdRegs = 5;
 // Load batch of the dense row update: 4 double2 per lane (the 8 of the streaming kernels
 // would not leave room for the staged vectors within 128 VGPRs).
 constexpr int kUpdBatch = 4;
+// Chunks wholly beyond n2 are skipped (a condition uniform over the workgroup, so no
+// lane-level branch); h.hu is then undefined and hold_store does not read it.
 __device__ __forceinline__ void hold_load(Hold5& h, const double2* __restrict__ src2, int tid, int n2) {
   constexpr int B = kUpdateBlock;
   const v2d* src = reinterpret_cast<const v2d*>(src2);
   h.h0 = src[min(tid, n2 - 1)];
-  h.h1 = src[min(tid + B, n2 - 1)];
-  h.h2 = src[min(tid + 2 * B, n2 - 1)];
-  h.h3 = src[min(tid + 3 * B, n2 - 1)];
-  h.h4 = src[min(tid + 4 * B, n2 - 1)];
+  if (B < n2) h.h1 = src[min(tid + B, n2 - 1)];
+  if (2 * B < n2) h.h2 = src[min(tid + 2 * B, n2 - 1)];
+  if (3 * B < n2) h.h3 = src[min(tid + 3 * B, n2 - 1)];
+  if (4 * B < n2) h.h4 = src[min(tid + 4 * B, n2 - 1)];
 }
 // Stores what hold_load read into dst (LDS), then copies any part beyond 5 * kUpdateBlock.
 __device__ __forceinline__ void hold_store(const Hold5& h, double2* dst2, const double2* __restrict__ src2, int tid,

@@ -39,7 +39,7 @@ def test_header_constants_match_binding():
 
 def test_struct_layouts():
     assert C.sizeof(binding.lp_options) == 96
-    assert C.sizeof(binding.lp_batch_stats) == 72
+    assert C.sizeof(binding.lp_batch_stats) == 88
     assert C.sizeof(binding.lp_stats) == 192
 
 
@@ -47,6 +47,7 @@ def test_default_options():
     o = lpg.default_options()
     assert o.sense == binding.LP_MAX and o.tabu_tenure == 5 and o.leaving_list == 1
     assert o.eps_d == 1e-9 and o.eps_p == 1e-9 and o.eps_z == 1e-9 and o.eps_t == 1e-9 and o.max_iter == 0 and o.batch_small_m == -1
+    assert o.batch_binv_lds_m == -1
     assert o.precision == binding.LP_FP64 and o.shortlist_k == 16 and o.reinv_period == -1
     assert lpg.lib().lp_default_options(None) == binding.LP_ERR_ARG
 

@@ -75,6 +75,25 @@ def test_batch_equals_serial(lpg, small_m):
     assert (res["status"] == oracle.OPTIMAL).all()
 
 
+@pytest.mark.parametrize("binv", [64, 256])
+def test_batch_binv_in_lds_equals_serial(lpg, binv):
+    """LPs that keep B^-1 in LDS (a second persistent launch) still equal lp_solve bit for
+    bit, on dense, degenerate (ties, tabu list) and overflowing LPs."""
+    from test_gpu_parity import NUMERICAL_LPS
+    lps = _mixed_batch(3, 40, 16, 120)
+    lps += [lpgen.degenerate_lp(s, 60 + 10 * s, 120 + 20 * s, budget_row=True) for s in range(3)]
+    lps += NUMERICAL_LPS
+    _say(f"case: {len(lps)} LPs, B^-1 in LDS for m <= {binv}")
+    with lpg.Batch(lps, batch_small_m=0, batch_binv_lds_m=binv) as bt:
+        bt.solve()
+        res = bt.results()
+        stats = bt.stats()
+        _check_against_serial(lpg, lps, res, bt, range(len(lps)))
+    assert stats["binv_lds_m"] == binv
+    assert stats["binv_lds_lps"] == sum(1 for A, _, _ in lps if A.shape[0] <= binv)
+    assert stats["binv_lds_lps"] > 0
+
+
 def test_batch_degenerate_and_special_lps(lpg):
     """Ties, the tabu list, unbounded, trivially optimal and overflowing (NUMERICAL) LPs
     inside one batch."""
@@ -119,9 +138,11 @@ def test_batch_sparse_column_mode(lpg):
     lps.append(lpgen.degenerate_lp(4, 1030, 2060, budget_row=True))
     _say("case: batch of 4 LPs m in {1024, 1100, 1257, 1030 degenerate}")
     for small_m in (0, -1):
+        _say(f"  batch_small_m={small_m}: batched solve")
         with lpg.Batch(lps, batch_small_m=small_m) as bt:
             bt.solve()
             res = bt.results()
+            _say("  serial solves")
             _check_against_serial(lpg, lps, res, bt, range(len(lps)))
         assert (res["status"][:3] == oracle.OPTIMAL).all()
     # the serial run did use sparse mode: less than the dense read of B^-1 per launch
@@ -154,6 +175,7 @@ def test_batch_4096_mixed_sizes(lpg):
         res = bt.results()
         stats = bt.stats()
         _say(f"  solve {stats['solve_ms']:.2f} ms, narrow {stats['narrow_lps']} wide {stats['wide_lps']}, "
+             f"B^-1 in LDS {stats['binv_lds_lps']} (m <= {stats['binv_lds_m']}), "
              f"tune {stats['tune_ms']:.0f} ms, mask {stats['narrow_bucket_mask']:#x}")
         assert (res["status"] == oracle.OPTIMAL).all()
         rng = np.random.default_rng(0)
