@@ -115,6 +115,35 @@ def degenerate_lp(seed: int, m: int, n: int, col_frac=0.02, zero_b_frac=0.30, bu
     return A, bv, cv
 
 
+ROW_LE, ROW_GE, ROW_EQ = 0, 1, 2
+
+
+def general_lp(seed: int, m: int, n: int, ge_frac=0.2, eq_frac=0.1, neg_frac=0.1):
+    """General-row law (an LP that needs the two-phase start of Section 3.4), feasible by
+    construction and bounded: max c^T x s.t. row i of A'x (<=, >=, =) b_i, x >= 0.
+
+    A'_ij ~ U(0,1) (the dense law's bits), a point x0_j ~ U(0,1) and r = A'x0.  Row i is
+    >= with probability ge_frac (b_i = r_i * U(0.5,1)), = with probability eq_frac
+    (b_i = r_i), else <= (b_i = r_i + U(1,10)); so x0 satisfies every row.  Then with
+    probability neg_frac the row and b_i are multiplied by -1 and <= / >= swap, which
+    gives b_i < 0.  c_j ~ U(1,10).  Returns (A, b, c, row_type) with row_type int32
+    codes ROW_LE, ROW_GE, ROW_EQ.
+    """
+    A, _, cv = dense_lp(seed, m, n)
+    x0 = uniform(seed, S_EXTRA, np.arange(n, dtype=np.uint64), 0.0, 1.0)
+    r = (A * x0[None, :]).sum(axis=1)
+    ui = np.arange(m, dtype=np.uint64)
+    kind = uniform(seed, S_ROWSEL, ui, 0.0, 1.0)
+    rt = np.where(kind < ge_frac, ROW_GE, np.where(kind < ge_frac + eq_frac, ROW_EQ, ROW_LE)).astype(np.int32)
+    bv = np.where(rt == ROW_GE, r * uniform(seed, S_B, ui, 0.5, 1.0),
+                  np.where(rt == ROW_EQ, r, r + uniform(seed, S_B, ui, 1.0, 10.0)))
+    neg = uniform(seed, S_ZEROB, ui, 0.0, 1.0) < neg_frac
+    A[neg, :] *= -1.0
+    bv = np.where(neg, -bv, bv)
+    rt = np.where(neg & (rt == ROW_LE), ROW_GE, np.where(neg & (rt == ROW_GE), ROW_LE, rt)).astype(np.int32)
+    return A, bv, cv, rt
+
+
 def batch_sizes(seed: int, count: int, m_lo=16, m_hi=256):
     """m_i = m_lo + (h(seed, size, i) mod (m_hi-m_lo+1)); n_i = 2 m_i."""
     span = m_hi - m_lo + 1

@@ -17,9 +17,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "simplex_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-OPTIMAL, UNBOUNDED, ITER_LIMIT, NUMERICAL = 1, 2, 3, 4
-STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT", 4: "NUMERICAL"}
-FLAG_DEGENERATE, FLAG_TIE, FLAG_ASPIRATION, FLAG_LCLEAR = 1, 2, 4, 8
+OPTIMAL, UNBOUNDED, ITER_LIMIT, NUMERICAL, INFEASIBLE = 1, 2, 3, 4, 5
+STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT", 4: "NUMERICAL", 5: "INFEASIBLE"}
+FLAG_DEGENERATE, FLAG_TIE, FLAG_ASPIRATION, FLAG_LCLEAR, FLAG_DRIVEOUT = 1, 2, 4, 8, 16
+ROW_LE, ROW_GE, ROW_EQ = 0, 1, 2
 
 # -ffp-contract=off: only the explicit fma() calls fuse.  x86-64-v3 has hardware FMA,
 # so fma() is one correctly rounded instruction instead of a libm emulation.
@@ -49,6 +50,12 @@ def lib(path: str | None = None):
         ip = C.POINTER(C.c_int32)
         L.oracle_create.restype = P
         L.oracle_create.argtypes = [I32, I32, dp, dp, dp, I32, I32, I32, D, D, D, D]
+        L.oracle_create_general.restype = P
+        L.oracle_create_general.argtypes = [I32, I32, dp, dp, dp, ip, I32, I32, I32, D, D, D, D]
+        L.oracle_phase.restype = I32
+        L.oracle_phase.argtypes = [P]
+        L.oracle_columns.restype = I32
+        L.oracle_columns.argtypes = [P]
         L.oracle_destroy.argtypes = [P]
         L.oracle_run.restype = I32
         L.oracle_run.argtypes = [P, I64]
@@ -100,10 +107,14 @@ class Result:
 
 
 class Oracle:
-    """One LP held by the oracle; run() may be called repeatedly (resume)."""
+    """One LP held by the oracle; run() may be called repeatedly (resume).
+
+    With row_type (ROW_LE / ROW_GE / ROW_EQ per row) the LP may have >= and = rows and b of
+    any sign, and is solved by the two-phase method; its handle then has extra surplus
+    columns after the caller's n (self.ncols in all), which pivot logs and bases use."""
 
     def __init__(self, A, b, c, sense="max", tenure=5, leaving_list=True, eps_d=1e-9, eps_p=1e-9,
-                 eps_z=1e-9, eps_t=1e-9, lib_path=None):
+                 eps_z=1e-9, eps_t=1e-9, lib_path=None, row_type=None):
         self._L = lib(lib_path)
         A = np.asarray(A, dtype=np.float64)
         m, n = A.shape
@@ -113,10 +124,23 @@ class Oracle:
         self._c = np.ascontiguousarray(c, dtype=np.float64)
         assert self._b.shape == (m,) and self._c.shape == (n,)
         s = {"min": 0, "max": 1}[sense]
-        self._h = self._L.oracle_create(m, n, _dp(self._A), _dp(self._b), _dp(self._c), s, int(tenure),
-                                      int(bool(leaving_list)), eps_d, eps_p, eps_z, eps_t)
+        if row_type is None:
+            self._h = self._L.oracle_create(m, n, _dp(self._A), _dp(self._b), _dp(self._c), s, int(tenure),
+                                          int(bool(leaving_list)), eps_d, eps_p, eps_z, eps_t)
+        else:
+            self._rt = np.ascontiguousarray(row_type, dtype=np.int32)
+            assert self._rt.shape == (m,)
+            self._h = self._L.oracle_create_general(m, n, _dp(self._A), _dp(self._b), _dp(self._c),
+                                                  _ip(self._rt), s, int(tenure), int(bool(leaving_list)),
+                                                  eps_d, eps_p, eps_z, eps_t)
         if not self._h:
-            raise ValueError("oracle_create rejected the LP (m<=0, negative or non-finite b, or no memory)")
+            raise ValueError("oracle_create rejected the LP (m<=0, negative or non-finite b, bad row type, "
+                             "or no memory)")
+        self.ncols = self._L.oracle_columns(self._h)
+
+    @property
+    def phase(self):
+        return self._L.oracle_phase(self._h)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -148,10 +172,11 @@ class Oracle:
     def result(self) -> Result:
         L = self._L
         m, n = self.m, self.n
-        x = np.empty(n)
+        x = np.empty(self.ncols)
         y = np.empty(m)
         basis = np.empty(m, dtype=np.int32)
         L.oracle_solution(self._h, _dp(x), _dp(y), _ip(basis))
+        x = x[:n].copy()
         cnt = L.oracle_pivots(self._h, None, None, None, None, 0)
         e = np.empty(cnt, dtype=np.int32)
         r = np.empty(cnt, dtype=np.int32)

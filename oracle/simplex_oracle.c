@@ -49,6 +49,31 @@
  *     or the minimum ratio over the candidate rows overflows, the solve stops with
  *     status NUMERICAL before the pivot; "no candidate row" stays UNBOUNDED.
  *
+ * Two-phase start (Section 3.4, "Finding the initial feasible solution"; the textbook
+ * two-phase method it refers to), for LPs given with row types (<=, >=, =) and b of any
+ * sign, oracle_create_general:
+ *   - a row with b_i < 0 is multiplied by -1 (its type flips between <= and >=), so that
+ *     b >= 0;
+ *   - a <= row keeps its slack as the unit column n+i, basic at the start;
+ *   - a >= row gets a surplus column -e_i, appended after the caller's n columns in
+ *     ascending row order, and its unit column n+i is an artificial variable;
+ *   - an = row has no slack; its unit column n+i is an artificial variable.
+ *   Phase 1 minimises the sum of the artificial variables from the basis of the unit
+ *   columns (W and z from their definitions).  An artificial variable that leaves the
+ *   basis never enters again, in either phase.  At the phase-1 optimum:
+ *   - a sum above eps_f = 1e-9 (1 + max_i |b_i|) means the LP is INFEASIBLE;
+ *   - otherwise, for each row r in ascending order whose basic variable is still an
+ *     artificial one, the nonbasic non-artificial column j with the largest |entry| of
+ *     row r of the tableau, B^-1[r,:] a_j (lowest j on equal magnitude; only entries
+ *     above eps_p count), replaces it by a pivot with step 0 (x_B[r] := 0, flag
+ *     FLAG_DRIVEOUT); a row with no such column is redundant and keeps its artificial
+ *     variable, basic at zero;
+ *   - phase 2 then restores the costs of the LP and recomputes W = chat_B^T B^-1 and
+ *     z = chat_B^T x_B from their definitions (ascending sums over the rows whose basic
+ *     variable has a nonzero cost), and the iteration continues.
+ *   The tabu state and the pivot count carry over from phase 1.  Reported duals refer
+ *   to the caller's rows: y_i = s W_i, negated for rows that were multiplied by -1.
+ *
  * Dot products are plain ascending-index fma chains.  Build with
  * -ffp-contract=off so that no other operation is fused.
  *
@@ -66,11 +91,20 @@
 #define OR_UNBOUNDED 2
 #define OR_ITER_LIMIT 3
 #define OR_NUMERICAL 4
+#define OR_INFEASIBLE 5
+
+#define ROW_LE 0
+#define ROW_GE 1
+#define ROW_EQ 2
 
 #define FLAG_DEGENERATE 1  /* theta == 0 */
 #define FLAG_TIE 2         /* more than one row reaches zero (within eps_t) at the step */
 #define FLAG_ASPIRATION 4  /* every improving variable was masked */
 #define FLAG_LCLEAR 8      /* L[q] excluded every tied row and was cleared */
+#define FLAG_DRIVEOUT 16   /* phase switch: an artificial variable at zero level replaced */
+
+/* pos[v] of an artificial variable that has left the basis: it never enters again. */
+#define POS_BARRED (-2)
 
 typedef struct {
   int32_t m, n, sense, tenure, use_llist;
@@ -90,6 +124,13 @@ typedef struct {
   int64_t n_degenerate, n_tie, n_aspiration, n_lclear;
   int32_t *log_enter, *log_row, *log_leave, *log_flags;
   int64_t log_len, log_cap;
+  /* Two-phase start (NULL / 0 for an LP created by oracle_create). */
+  int32_t phase;   /* 0: one phase; 1: phase 1 running; 2: phase 2 */
+  int32_t n_user;  /* the caller's structural columns; n_user..n-1 are surplus columns */
+  int8_t *art;     /* art[i] = 1: the unit column n+i is the artificial variable of row i */
+  double *rsign;   /* -1 for rows multiplied by -1, else +1 */
+  double *chat2;   /* the LP's own costs, restored for phase 2 */
+  double eps_f;
 } oracle_lp;
 
 void oracle_destroy(oracle_lp *p);
@@ -146,6 +187,7 @@ oracle_lp *oracle_create(int32_t m, int32_t n, const double *A_colmajor, const d
   p->t = 0;
   p->status = OR_RUNNING;
   p->ray = -1;
+  p->n_user = n;
   return p;
 }
 
@@ -157,6 +199,7 @@ void oracle_destroy(oracle_lp *p) {
   free(p->A); free(p->b); free(p->c); free(p->chat); free(p->Binv); free(p->xB); free(p->W);
   free(p->d); free(p->alpha); free(p->rho); free(p->ratio); free(p->basis); free(p->pos);
   free(p->tabu_until); free(p->log_enter); free(p->log_row); free(p->log_leave); free(p->log_flags);
+  free(p->art); free(p->rsign); free(p->chat2);
   free(p);
 }
 
@@ -203,13 +246,48 @@ static int list_add(oracle_lp *p, int32_t q, int32_t v) {
   return 0;
 }
 
+/* Step 5: Y_k = B^-1 a_q into alpha (a slack's column is a column of B^-1). */
+static void ftran(oracle_lp *p, int32_t q) {
+  const int32_t m = p->m, n = p->n;
+  for (int32_t i = 0; i < m; ++i) {
+    const double *row = p->Binv + (size_t)i * m;
+    if (q < n) {
+      const double *a = p->A + (size_t)q * m;
+      double s = 0.0;
+      for (int32_t k = 0; k < m; ++k) s = fma(row[k], a[k], s);
+      p->alpha[i] = s;
+    } else {
+      p->alpha[i] = row[q - n];
+    }
+  }
+}
+
+/* Step 8 / Section 3.1 on the body of the tableau: rho = B^-1[r,:] / alpha_r becomes
+ * row r, every other row i gets fma(-alpha_i, rho_j, B^-1[i,j]). */
+static void pivot_inverse(oracle_lp *p, int32_t r) {
+  const int32_t m = p->m;
+  const double ar = p->alpha[r];
+  double *rowr = p->Binv + (size_t)r * m;
+  for (int32_t j = 0; j < m; ++j) p->rho[j] = rowr[j] / ar;
+  for (int32_t i = 0; i < m; ++i) {
+    double *row = p->Binv + (size_t)i * m;
+    if (i == r) {
+      for (int32_t j = 0; j < m; ++j) row[j] = p->rho[j];
+    } else {
+      const double na = -p->alpha[i];
+      for (int32_t j = 0; j < m; ++j) row[j] = fma(na, p->rho[j], row[j]);
+    }
+  }
+}
+
 /* One iteration (Steps 3-8).  Returns the status after it. */
 static int32_t iterate(oracle_lp *p, int64_t max_iter) {
   const int32_t m = p->m, n = p->n, N = n + m;
 
-  /* Step 3: reduced costs d_j = chat_j - W a_j of every nonbasic variable. */
+  /* Step 3: reduced costs d_j = chat_j - W a_j of every nonbasic variable (barred
+   * artificial variables are not candidates). */
   for (int32_t j = 0; j < N; ++j) {
-    if (p->pos[j] >= 0) continue;
+    if (p->pos[j] != -1) continue;
     if (j < n) {
       const double *a = p->A + (size_t)j * m;
       double s = 0.0;
@@ -223,7 +301,7 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
   /* Step 4: Dantzig choice, most negative d_j, with the entering mask. */
   int32_t q_all = -1, q_free = -1;
   for (int32_t j = 0; j < N; ++j) {
-    if (p->pos[j] >= 0 || !(p->d[j] < -p->eps_d)) continue;
+    if (p->pos[j] != -1 || !(p->d[j] < -p->eps_d)) continue;
     if (q_all < 0 || p->d[j] < p->d[q_all]) q_all = j; /* strict: lowest index wins ties */
     if (p->tabu_until[j] < p->t && (q_free < 0 || p->d[j] < p->d[q_free])) q_free = j;
   }
@@ -235,17 +313,7 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
   const double dq = p->d[q];
 
   /* Step 5: FTRAN, Y_k = B^-1 a_q. */
-  for (int32_t i = 0; i < m; ++i) {
-    const double *row = p->Binv + (size_t)i * m;
-    if (q < n) {
-      const double *a = p->A + (size_t)q * m;
-      double s = 0.0;
-      for (int32_t k = 0; k < m; ++k) s = fma(row[k], a[k], s);
-      p->alpha[i] = s;
-    } else {
-      p->alpha[i] = row[q - n];
-    }
-  }
+  ftran(p, q);
 
   /* A non-finite entry of Y_k (overflow of the product-form B^-1) stops the solve. */
   for (int32_t i = 0; i < m; ++i)
@@ -288,18 +356,7 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
   if (p->tenure > 0) p->tabu_until[leave] = p->t + p->tenure;
 
   /* Step 8 / Section 3.1: pivot the revised tableau on alpha_r. */
-  const double ar = p->alpha[r];
-  double *rowr = p->Binv + (size_t)r * m;
-  for (int32_t j = 0; j < m; ++j) p->rho[j] = rowr[j] / ar;
-  for (int32_t i = 0; i < m; ++i) {
-    double *row = p->Binv + (size_t)i * m;
-    if (i == r) {
-      for (int32_t j = 0; j < m; ++j) row[j] = p->rho[j];
-    } else {
-      const double na = -p->alpha[i];
-      for (int32_t j = 0; j < m; ++j) row[j] = fma(na, p->rho[j], row[j]);
-    }
-  }
+  pivot_inverse(p, r);
   for (int32_t j = 0; j < m; ++j) p->W[j] = fma(dq, p->rho[j], p->W[j]);
   for (int32_t i = 0; i < m; ++i) p->xB[i] = (i == r) ? theta : fma(-p->alpha[i], theta, p->xB[i]);
   for (int32_t i = 0; i < m; ++i)
@@ -307,9 +364,75 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
   p->z = fma(dq, theta, p->z);
   p->basis[r] = q;
   p->pos[q] = r;
-  p->pos[leave] = -1;
+  p->pos[leave] = (p->art && leave >= n && p->art[leave - n]) ? POS_BARRED : -1;
   if (log_push(p, q, r, leave, flags)) return -1;
   p->t++;
+  return OR_RUNNING;
+}
+
+/* W = chat_B^T B^-1 and z = chat_B^T x_B by their definitions: ascending fma sums over
+ * the rows whose basic variable has a nonzero cost. */
+static void reprice(oracle_lp *p) {
+  const int32_t m = p->m;
+  for (int32_t j = 0; j < m; ++j) {
+    double s = 0.0;
+    for (int32_t i = 0; i < m; ++i) {
+      const double cb = p->chat[p->basis[i]];
+      if (cb != 0.0) s = fma(cb, p->Binv[(size_t)i * m + j], s);
+    }
+    p->W[j] = s;
+  }
+  double z = 0.0;
+  for (int32_t i = 0; i < m; ++i) {
+    const double cb = p->chat[p->basis[i]];
+    if (cb != 0.0) z = fma(cb, p->xB[i], z);
+  }
+  p->z = z;
+}
+
+/* A pivot on (q, r) with step 0: B^-1 as in Step 8, x_B[r] := 0, the other x_B unchanged;
+ * W and z are left for reprice.  The leaving variable is an artificial one: barred. */
+static int drive_out(oracle_lp *p, int32_t q, int32_t r) {
+  ftran(p, q);
+  pivot_inverse(p, r);
+  const int32_t leave = p->basis[r];
+  p->xB[r] = 0.0;
+  p->basis[r] = q;
+  p->pos[q] = r;
+  p->pos[leave] = POS_BARRED;
+  if (log_push(p, q, r, leave, FLAG_DRIVEOUT)) return -1;
+  p->t++;
+  return 0;
+}
+
+/* The end of phase 1 (its optimum has been reached): INFEASIBLE, or the start of phase 2. */
+static int32_t phase_switch(oracle_lp *p) {
+  const int32_t m = p->m, n = p->n, N = n + m;
+  if (p->z > p->eps_f) return OR_INFEASIBLE;
+  for (int32_t r = 0; r < m; ++r) {
+    const int32_t v = p->basis[r];
+    if (v < n || !p->art[v - n]) continue;
+    const double *row = p->Binv + (size_t)r * m;
+    int32_t best = -1;
+    double bt = 0.0;
+    for (int32_t j = 0; j < N; ++j) {
+      if (p->pos[j] != -1 || (j >= n && p->art[j - n])) continue;
+      double t;
+      if (j < n) {
+        const double *a = p->A + (size_t)j * m;
+        double s = 0.0;
+        for (int32_t k = 0; k < m; ++k) s = fma(a[k], row[k], s);  /* row r of B^-1 times a_j */
+        t = s;
+      } else {
+        t = row[j - n];
+      }
+      if (fabs(t) > p->eps_p && fabs(t) > fabs(bt)) { best = j; bt = t; }
+    }
+    if (best >= 0 && drive_out(p, best, r)) return -1;
+  }
+  memcpy(p->chat, p->chat2, sizeof(double) * N);
+  reprice(p);
+  p->phase = 2;
   return OR_RUNNING;
 }
 
@@ -320,11 +443,73 @@ int32_t oracle_run(oracle_lp *p, int64_t max_iter) {
   if (p->status == OR_ITER_LIMIT) p->status = OR_RUNNING;
   while (p->status == OR_RUNNING) {
     int32_t s = iterate(p, max_iter);
+    if (s == OR_OPTIMAL && p->phase == 1) s = phase_switch(p);
     if (s < 0) return -1;
     p->status = s;
   }
   return p->status;
 }
+
+/*
+ * An LP with row types (ROW_LE, ROW_GE, ROW_EQ; NULL = all ROW_LE) and b of any sign,
+ * solved by the two-phase method described at the top.  The handle's columns are the
+ * caller's n followed by one surplus column per >= row (after the sign change); pivot
+ * logs and basis lists use that numbering.  Returns NULL on invalid input.
+ */
+oracle_lp *oracle_create_general(int32_t m, int32_t n, const double *A_colmajor, const double *b, const double *c,
+                                 const int32_t *row_type, int32_t sense, int32_t tenure, int32_t use_llist,
+                                 double eps_d, double eps_p, double eps_z, double eps_t) {
+  if (m <= 0 || n < 0 || !A_colmajor || !b || !c) return NULL;
+  double *sg = (double *)malloc(sizeof(double) * m);
+  int8_t *ge = (int8_t *)malloc((size_t)m);
+  int8_t *art = (int8_t *)calloc((size_t)m, 1);
+  if (!sg || !ge || !art) { free(sg); free(ge); free(art); return NULL; }
+  int32_t ns = 0, na = 0;
+  double bmax = 0.0;
+  for (int32_t i = 0; i < m; ++i) {
+    const int32_t ty = row_type ? row_type[i] : ROW_LE;
+    if (!isfinite(b[i]) || ty < ROW_LE || ty > ROW_EQ) { free(sg); free(ge); free(art); return NULL; }
+    sg[i] = b[i] < 0.0 ? -1.0 : 1.0;
+    int32_t t2 = ty;
+    if (sg[i] < 0.0 && ty != ROW_EQ) t2 = ty == ROW_LE ? ROW_GE : ROW_LE;
+    ge[i] = t2 == ROW_GE;
+    art[i] = t2 != ROW_LE;
+    ns += ge[i];
+    na += art[i];
+    if (fabs(b[i]) > bmax) bmax = fabs(b[i]);
+  }
+  const int32_t n2 = n + ns;
+  double *A2 = (double *)calloc((size_t)m * (n2 > 0 ? n2 : 1), sizeof(double));
+  double *b2 = (double *)malloc(sizeof(double) * m);
+  double *c2 = (double *)calloc(n2 > 0 ? n2 : 1, sizeof(double));
+  if (!A2 || !b2 || !c2) { free(sg); free(ge); free(art); free(A2); free(b2); free(c2); return NULL; }
+  for (int32_t j = 0; j < n; ++j)
+    for (int32_t i = 0; i < m; ++i) A2[(size_t)j * m + i] = sg[i] * A_colmajor[(size_t)j * m + i];
+  for (int32_t i = 0, k = n; i < m; ++i)
+    if (ge[i]) A2[(size_t)(k++) * m + i] = -1.0;
+  for (int32_t i = 0; i < m; ++i) b2[i] = sg[i] * b[i];
+  for (int32_t j = 0; j < n; ++j) c2[j] = c[j];
+  oracle_lp *p = oracle_create(m, n2, A2, b2, c2, sense, tenure, use_llist, eps_d, eps_p, eps_z, eps_t);
+  free(A2); free(b2); free(c2); free(ge);
+  if (!p) { free(sg); free(art); return NULL; }
+  p->n_user = n;
+  p->rsign = sg;
+  p->art = art;
+  p->eps_f = 1e-9 * (1.0 + bmax);
+  if (na > 0) {
+    const int32_t N = n2 + m;
+    p->chat2 = (double *)malloc(sizeof(double) * N);
+    if (!p->chat2) { oracle_destroy(p); return NULL; }
+    memcpy(p->chat2, p->chat, sizeof(double) * N);
+    for (int32_t v = 0; v < N; ++v) p->chat[v] = (v >= n2 && art[v - n2]) ? 1.0 : 0.0;
+    reprice(p);
+    p->phase = 1;
+  }
+  return p;
+}
+
+int32_t oracle_phase(const oracle_lp *p) { return p->phase; }
+int32_t oracle_columns(const oracle_lp *p) { return p->n; }
 
 int64_t oracle_iterations(const oracle_lp *p) { return p->t; }
 int32_t oracle_status(const oracle_lp *p) { return p->status; }
@@ -338,13 +523,14 @@ double oracle_objective(const oracle_lp *p) {
   return s;
 }
 
-/* x (n structural values), y (m duals in the user's sense: y = s*W), basis (m). Any may be NULL. */
+/* x (n values, the handle's columns), y (m duals in the user's sense: y = s*W, negated for rows
+ * multiplied by -1), basis (m). Any may be NULL. */
 void oracle_solution(const oracle_lp *p, double *x, double *y, int32_t *basis) {
   const double s = p->sense ? -1.0 : 1.0;
   if (x)
     for (int32_t j = 0; j < p->n; ++j) x[j] = p->pos[j] >= 0 ? p->xB[p->pos[j]] : 0.0;
   if (y)
-    for (int32_t i = 0; i < p->m; ++i) y[i] = s * p->W[i];
+    for (int32_t i = 0; i < p->m; ++i) y[i] = s * p->W[i] * (p->rsign ? p->rsign[i] : 1.0);
   if (basis) memcpy(basis, p->basis, sizeof(int32_t) * p->m);
 }
 

@@ -113,3 +113,109 @@ def basis_sets(n, m, enter, row):
         basis[r] = q
         out.append(frozenset(basis))
     return out
+
+
+# ---- LPs with row types (<= 0, >= 1, = 2) and b of any sign ----
+
+def general_standard(A, b, row_type):
+    """M with the caller's columns, then a slack column +e_i for each <= row and a surplus
+    column -e_i for each >= row (ascending i): the constraints read M X = b, X >= 0."""
+    A = np.asarray(A, float)
+    m = A.shape[0]
+    cols = [A]
+    for i in range(m):
+        if row_type[i] != 2:
+            e = np.zeros((m, 1))
+            e[i, 0] = 1.0 if row_type[i] == 0 else -1.0
+            cols.append(e)
+    return np.hstack(cols)
+
+
+def brute_force_general(A, b, c, row_type, sense="max"):
+    """Best objective over all basic feasible solutions of M X = b, X >= 0 (M as above, of
+    full row rank); (None, None) when there is no feasible vertex."""
+    A = np.asarray(A, float)
+    m, n = A.shape
+    M = general_standard(A, b, row_type)
+    assert np.linalg.matrix_rank(M) == m, "brute force needs rows of full rank"
+    N = M.shape[1]
+    cf = np.concatenate([np.asarray(c, float), np.zeros(N - n)])
+    best, bestx = None, None
+    for cols in itertools.combinations(range(N), m):
+        B = M[:, cols]
+        if abs(np.linalg.det(B)) < 1e-10:
+            continue
+        xb = np.linalg.solve(B, b)
+        if np.any(xb < -1e-10):
+            continue
+        x = np.zeros(N)
+        x[list(cols)] = xb
+        obj = cf @ x
+        if best is None or (obj > best if sense == "max" else obj < best):
+            best, bestx = obj, x[:n]
+    return best, bestx
+
+
+def highs_general(A, b, c, row_type, sense="max"):
+    """(status, objective) from scipy's HiGHS: status 'OPTIMAL', 'INFEASIBLE' or 'UNBOUNDED'."""
+    from scipy.optimize import linprog
+    A = np.asarray(A, float)
+    b = np.asarray(b, float)
+    rt = np.asarray(row_type)
+    Aub = np.vstack([A[rt == 0], -A[rt == 1]])
+    bub = np.concatenate([b[rt == 0], -b[rt == 1]])
+    kw = dict(A_ub=Aub, b_ub=bub) if Aub.shape[0] else {}
+    if (rt == 2).any():
+        kw.update(A_eq=A[rt == 2], b_eq=b[rt == 2])
+    sg = -1.0 if sense == "max" else 1.0
+    res = linprog(sg * np.asarray(c, float), method="highs", **kw)
+    name = {0: "OPTIMAL", 2: "INFEASIBLE", 3: "UNBOUNDED"}.get(res.status, f"status{res.status}")
+    return name, (sg * res.fun if res.status == 0 else None)
+
+
+def kkt_general_residuals(A, b, c, x, y, row_type, sense="max"):
+    """Max violations of the optimality conditions of  max/min c^T x  s.t.  row i of A x
+    (<=, >=, =) b_i, x >= 0, with duals y: primal rows, x >= 0, dual signs (for max:
+    y_i >= 0 on <= rows, <= 0 on >= rows, free on = rows), A^T y >= c, complementary
+    slackness and the duality gap."""
+    A = np.asarray(A, float)
+    b = np.asarray(b, float)
+    c = np.asarray(c, float)
+    rt = np.asarray(row_type)
+    sgn = 1.0 if sense == "max" else -1.0
+    cs, ys = sgn * c, sgn * np.asarray(y, float)
+    Ax = A @ x
+    viol = np.where(rt == 0, Ax - b, np.where(rt == 1, b - Ax, np.abs(Ax - b)))
+    ysign = np.where(rt == 0, -ys, np.where(rt == 1, ys, 0.0))
+    red = A.T @ ys - cs
+    return dict(
+        x_neg=float(max(0.0, -x.min())) if x.size else 0.0,
+        primal=float(max(0.0, viol.max())),
+        y_sign=float(max(0.0, ysign.max())),
+        dual=float(max(0.0, -red.min())) if red.size else 0.0,
+        comp_row=float(np.max(np.abs(ys * (b - Ax)))),
+        comp_col=float(np.max(np.abs(x * red))) if red.size else 0.0,
+        gap=float(abs(cs @ x - b @ ys)),
+    )
+
+
+def assert_kkt_general(A, b, c, x, y, row_type, sense="max", tol=1e-8):
+    r = kkt_general_residuals(A, b, c, x, y, row_type, sense)
+    scale = 1.0 + float(np.max(np.abs(b))) + float(np.max(np.abs(c))) * (1.0 + float(np.sum(np.abs(x))))
+    bad = {k: v for k, v in r.items() if v > tol * scale}
+    assert not bad, f"KKT violated: {bad} (scale {scale})"
+
+
+def small_general_lps(seed, count):
+    """Tiny degenerate LPs with integer-ish data and random row types / signs of b: the law
+    on which phase 1 often ends with an artificial variable basic at zero."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        m, n = int(rng.integers(2, 5)), int(rng.integers(2, 5))
+        A = rng.choice([-1.0, 0.0, 1.0, 2.0], size=(m, n))
+        rt = rng.choice([0, 1, 2], size=m, p=[0.3, 0.3, 0.4]).astype(np.int32)
+        b = rng.choice([0.0, 0.0, 1.0, 2.0, -1.0], size=m)
+        c = rng.choice([-1.0, 0.0, 1.0, 2.0], size=n)
+        out.append((A, b, c, rt))
+    return out

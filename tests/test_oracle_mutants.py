@@ -13,7 +13,7 @@ import pytest
 import lpgen
 import oracle
 from test_oracle_pins import _embedded
-from lputil import assert_kkt, brute_force, replay_check
+from lputil import assert_kkt, assert_kkt_general, brute_force, highs_general, replay_check, small_general_lps
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "simplex_oracle.c")
 
@@ -33,6 +33,18 @@ MUTANTS = {
     "slack_price_wrong_index": ("p->d[j] = p->chat[j] - p->W[j - n];", "p->d[j] = p->chat[j] - p->W[0];"),
     "no_alpha_finite_check": ("if (!isfinite(p->alpha[i])) return OR_NUMERICAL;", "(void)0;"),
     "no_step_finite_check": ("if (!isfinite(theta_min)) return OR_NUMERICAL;", "(void)0;"),
+    # two-phase start
+    "artificial_cost_zero": ("(v >= n2 && art[v - n2]) ? 1.0 : 0.0;", "(v >= n2 && art[v - n2]) ? 0.0 : 0.0;"),
+    "no_row_negation": ("sg[i] = b[i] < 0.0 ? -1.0 : 1.0;", "sg[i] = 1.0;"),
+    "surplus_sign": ("if (ge[i]) A2[(size_t)(k++) * m + i] = -1.0;", "if (ge[i]) A2[(size_t)(k++) * m + i] = 1.0;"),
+    "infeasibility_test_sign": ("if (p->z > p->eps_f) return OR_INFEASIBLE;", "if (p->z < -p->eps_f) return OR_INFEASIBLE;"),
+    "no_drive_out": ("if (best >= 0 && drive_out(p, best, r)) return -1;", "(void)best;"),
+    "no_barring": ("p->pos[leave] = (p->art && leave >= n && p->art[leave - n]) ? POS_BARRED : -1;",
+                   "p->pos[leave] = -1;"),
+    "reprice_transposed": ("if (cb != 0.0) s = fma(cb, p->Binv[(size_t)i * m + j], s);",
+                           "if (cb != 0.0) s = fma(cb, p->Binv[(size_t)j * m + i], s);"),
+    "no_phase2_costs": ("memcpy(p->chat, p->chat2, sizeof(double) * N);", "(void)0;"),
+    "dual_ignores_row_sign": ("y[i] = s * p->W[i] * (p->rsign ? p->rsign[i] : 1.0);", "y[i] = s * p->W[i];"),
 }
 
 
@@ -93,7 +105,28 @@ def _pins_pass(lib_path):
                          lib_path=lib_path)
         if r.status != oracle.NUMERICAL or r.iterations != 1:
             return False
-    except AssertionError:
+        # two-phase start: the hand-derived optimum, the status against HiGHS and a KKT
+        # certificate on the tiny degenerate law, the general law against HiGHS
+        r = oracle.solve(np.array([[3.0, 1.0], [4.0, 3.0], [1.0, 2.0]]), np.array([3.0, 6.0, 4.0]),
+                         np.array([4.0, 1.0]), sense="min", row_type=[2, 1, 0], lib_path=lib_path)
+        if r.status != oracle.OPTIMAL or abs(r.objective - 3.4) > 1e-14:
+            return False
+        for A, b, c, rt in small_general_lps(3, 250):
+            r = oracle.solve(A, b, c, row_type=rt, max_iter=500, lib_path=lib_path)
+            ref, obj = highs_general(A, b, c, rt)
+            if r.status_name != ref:
+                return False
+            if ref == "OPTIMAL":
+                if abs(r.objective - obj) > 1e-9 * (1 + abs(obj)):
+                    return False
+                assert_kkt_general(A, b, c, r.x, r.y, rt)
+        A, b, c, rt = lpgen.general_lp(0, 60, 120)
+        r = oracle.solve(A, b, c, row_type=rt, lib_path=lib_path)
+        ref, obj = highs_general(A, b, c, rt)
+        if r.status != oracle.OPTIMAL or abs(r.objective - obj) > 1e-9 * abs(obj):
+            return False
+        assert_kkt_general(A, b, c, r.x, r.y, rt)
+    except (AssertionError, ValueError):
         return False
     return True
 
