@@ -195,6 +195,41 @@ def mixed_leg(lpg, torch, m, n, seed, steps, stream, profile_only=False, reps=5)
     return out
 
 
+def general_leg(lpg, torch, m, n, seed, stream, reps=3):
+    """Two-phase start (rows <=, >=, =, b of any sign), general-row law at m x n: time to
+    optimality (median of `reps` solves after a warm-up, phase switch included), the split
+    between the phases, and the optimality residuals of the GPU's result for the given rows."""
+    import numpy as np
+
+    import lpgen
+    A, b, c, rt = lpgen.general_lp(seed, m, n)
+    t0 = time.perf_counter()
+    lp = lpg.LP(A, b, c, row_type=rt, stream=stream.cuda_stream)
+    create = time.perf_counter() - t0
+    with lp:
+        times, st = timed_solves(lp, torch, reps)
+        sol = lp.solution()
+        stats = lp.stats()
+    ts = statistics.median(times)
+    x, y = sol["x"], sol["y"]
+    Ax = A @ x
+    viol = np.where(rt == 0, Ax - b, np.where(rt == 1, b - Ax, np.abs(Ax - b)))
+    # max sense: A^T y >= c, y >= 0 on <= rows, y <= 0 on >= rows
+    red = A.T @ y - c
+    ysign = np.where(rt == 0, -y, np.where(rt == 1, y, 0.0))
+    return dict(workload=f"general-row LP m={m}, n={n}, seed {seed}: A'~U(0,1), rows >= (5%), = (2%), "
+                         f"<= (rest), 5% negated (b < 0), b on the dense law's scale, c~U(1,10); "
+                         f"{int((rt == 1).sum())} >= rows, "
+                         f"{int((rt == 2).sum())} = rows, {int((b < 0).sum())} with b < 0",
+                status=lpg.STATUS_NAMES[st], seconds=round(ts, 5), runs=[round(t, 5) for t in times],
+                iterations=sol["iterations"], iter_per_s=round(sol["iterations"] / ts, 1),
+                phase1_pivots=stats["phase1_iterations"], drive_outs=stats["drive_outs"],
+                switch_ms=round(stats["phase_switch_ms"], 3), objective=sol["objective"],
+                primal_violation=float(max(0.0, viol.max())),
+                dual_violation=float(max(0.0, -red.min(), ysign.max())),
+                gap=float(abs(c @ x - b @ y)), create_s=round(create, 4))
+
+
 def batch_leg(lpg, count, serial_sample):
     """Batched form: `count` LPs, m ~ U{16..256}, n = 2m, dense law with per-instance seeds,
     solved in one persistent launch, against serial lp_solve calls on a sample of them."""
@@ -257,6 +292,8 @@ def main():
     ap.add_argument("--batch", type=int, default=4096, help="LPs in the batched leg (0 = skip)")
     ap.add_argument("--mixed-m", type=int, default=8000, help="rows of the mixed-precision leg (0 = skip)")
     ap.add_argument("--mixed-n", type=int, default=16000)
+    ap.add_argument("--general-m", type=int, default=4000, help="rows of the two-phase leg (0 = skip)")
+    ap.add_argument("--general-n", type=int, default=8000)
     ap.add_argument("--mixed-profile-only", action="store_true",
                     help="only the profiled stretch of the mixed-precision form (for profiler runs)")
     ap.add_argument("--serial-sample", type=int, default=256,
@@ -330,6 +367,10 @@ def main():
     if not args.quick and args.mixed_m > 0:
         _log(f"bench: mixed-precision leg m={args.mixed_m} n={args.mixed_n}")
         extra["mixed"] = mixed_leg(lpg, torch, args.mixed_m, args.mixed_n, args.seed, 200, stream)
+
+    if not args.quick and args.general_m > 0:
+        _log(f"bench: two-phase leg m={args.general_m} n={args.general_n}")
+        extra["two_phase"] = general_leg(lpg, torch, args.general_m, args.general_n, args.seed, stream)
 
     if not args.quick and args.batch > 0:
         _log(f"bench: batched leg, {args.batch} LPs")

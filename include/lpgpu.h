@@ -15,6 +15,9 @@
  * explicitly stored B^-1 that lives in device memory for the whole solve (the
  * "Case 1" memory layout of Section 3).
  *
+ * lp_create_general adds the two-phase start of Section 3.4 (finding the initial
+ * feasible solution): rows of type <=, >= or =, and b of any sign.
+ *
  * All functions are thread-compatible, not thread-safe: one handle must not be used
  * from two threads at once.  No function aborts or throws; failures are reported as
  * negative return codes, and lp_error_string() describes the most recent failure of
@@ -32,7 +35,8 @@ extern "C" {
 /* ---- return codes (negative = error) ---- */
 #define LP_OK 0
 #define LP_ERR_ARG (-1)     /* NULL pointer, m <= 0, n < 0, non-finite data, size above the build limit */
-#define LP_ERR_NEG_RHS (-2) /* some b_i < 0: the slack basis is infeasible (no Phase 1 in this library) */
+#define LP_ERR_NEG_RHS (-2) /* lp_create / lp_create_device: some b_i < 0, so the slack basis is infeasible
+                               (lp_create_general accepts such LPs: it runs the two-phase start) */
 #define LP_ERR_NOMEM (-3)   /* device or pinned host memory could not be allocated */
 #define LP_ERR_DEVICE (-4)  /* a HIP runtime call failed (no GPU, bad stream, launch failure) */
 #define LP_ERR_STATE (-5)   /* the handle is not in a state that allows the call */
@@ -44,12 +48,21 @@ extern "C" {
 #define LP_ITER_LIMIT 3 /* max_iter pivots done and the basis is not optimal; lp_solve resumes */
 #define LP_NUMERICAL 4  /* the entering column Y_k had a non-finite entry, or the minimum ratio
                            overflowed: the solve stopped before that pivot */
+#define LP_INFEASIBLE 5 /* lp_create_general: phase 1 ended with the sum of the artificial
+                           variables above eps_f = 1e-9 (1 + max_i |b_i|): no x satisfies the rows */
 
 /* ---- pivot-log flags ---- */
 #define LP_PIVOT_DEGENERATE 1 /* step length theta == 0 */
 #define LP_PIVOT_TIE 2        /* several rows reach zero (within eps_t) at the minimum step (Step 6) */
 #define LP_PIVOT_ASPIRATION 4 /* every improving variable was tabu; chosen among all of them */
 #define LP_PIVOT_LCLEAR 8     /* the tabu list of the entering variable excluded every tied row */
+#define LP_PIVOT_DRIVEOUT 16  /* phase switch: a pivot with step 0 that replaced an artificial
+                                 variable left basic at zero by phase 1 */
+
+/* ---- row types of lp_create_general ---- */
+#define LP_ROW_LE 0 /* a_i x <= b_i */
+#define LP_ROW_GE 1 /* a_i x >= b_i */
+#define LP_ROW_EQ 2 /* a_i x  = b_i */
 
 #define LP_MIN 0
 #define LP_MAX 1
@@ -132,6 +145,10 @@ typedef struct lp_stats {
   double price32_ms;        /* profile = 1 or 2, LP_MIXED: summed duration of the FP32 screening */
   double shortlist_ms;      /* profile = 1 or 2, LP_MIXED: summed duration of merge + FP64 re-price */
   double price32_bytes;     /* their algorithmic bytes: 4*m per nonbasic structural column */
+  int64_t phase1_iterations; /* lp_create_general: pivots of phase 1 (the rest are phase 2 and
+                                drive-outs); -1 while phase 1 runs or when it was not needed */
+  int64_t drive_outs;       /* pivots flagged LP_PIVOT_DRIVEOUT */
+  double phase_switch_ms;   /* host wall time of the switch (drive-outs and re-pricing) */
 } lp_stats;
 
 typedef struct lp_problem lp_problem;
@@ -149,6 +166,32 @@ int lp_default_options(lp_options *opt);
  */
 int lp_create(lp_problem **out, int32_t m, int32_t n, const double *A_colmajor, const double *b,
               const double *c, const lp_options *opt);
+
+/*
+ * Creates an LP whose rows have types and whose right-hand sides have any sign:
+ *   optimise c^T x  s.t.  row i of A' x  (<=, >=, =)  b_i,  x >= 0,
+ * row_type[i] one of LP_ROW_LE, LP_ROW_GE, LP_ROW_EQ (row_type NULL = all LP_ROW_LE);
+ * host arrays as in lp_create.  lp_solve runs the two-phase method (Section 3.4):
+ *   - a row with b_i < 0 is multiplied by -1 (its type flips between <= and >=);
+ *   - a <= row keeps its slack as the unit column; a >= row gets a surplus column -e_i,
+ *     appended after the n given columns in ascending row order; a >= or = row gets an
+ *     artificial variable as its unit column;
+ *   - phase 1 minimises the sum of the artificial variables with the iteration of
+ *     lp_solve; an artificial variable that leaves the basis never enters again;
+ *   - its optimum above eps_f (LP_INFEASIBLE) stops the solve; else each artificial
+ *     variable still basic (at zero) is replaced by a step-0 pivot on the largest |entry|
+ *     of its row of the tableau (LP_PIVOT_DRIVEOUT; lowest column on equal magnitude,
+ *     none above eps_p: the row is redundant and keeps it), the costs of the LP are
+ *     restored, W = chat_B^T B^-1 and z = chat_B^T x_B are recomputed, and phase 2 runs.
+ * When every row is <= after the sign change, no phase 1 runs.  Variable numbers in
+ * pivot logs and bases: 0..n-1 the given columns, n..n+ns-1 the surplus columns, then
+ * the unit column of row i.  lp_get_solution reports x (n values) and the objective of
+ * the given LP, and y_i for the given row i (negated where the row was multiplied by -1).
+ * LP_MIXED skips reinversions while phase 1 runs.  Not available in the batched form.
+ * Errors: LP_ERR_ARG (also an unknown row type), LP_ERR_NOMEM, LP_ERR_DEVICE.
+ */
+int lp_create_general(lp_problem **out, int32_t m, int32_t n, const double *A_colmajor, const double *b,
+                      const double *c, const int32_t *row_type, const lp_options *opt);
 
 /*
  * Same as lp_create, but A_colmajor, b and c are device pointers of the current device

@@ -150,7 +150,7 @@ class Oracle:
 
     def run(self, max_iter=None):
         if max_iter is None:
-            max_iter = 10 * (self.m + self.n)
+            max_iter = 10 * (self.m + self.ncols)
         st = self._L.oracle_run(self._h, int(max_iter))
         if st < 0:
             raise MemoryError("oracle ran out of memory")

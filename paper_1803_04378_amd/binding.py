@@ -14,12 +14,13 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblpgpu.so")
 
 LP_OK, LP_ERR_ARG, LP_ERR_NEG_RHS, LP_ERR_NOMEM, LP_ERR_DEVICE, LP_ERR_STATE = 0, -1, -2, -3, -4, -5
-LP_RUNNING, LP_OPTIMAL, LP_UNBOUNDED, LP_ITER_LIMIT, LP_NUMERICAL = 0, 1, 2, 3, 4
-LP_PIVOT_DEGENERATE, LP_PIVOT_TIE, LP_PIVOT_ASPIRATION, LP_PIVOT_LCLEAR = 1, 2, 4, 8
+LP_RUNNING, LP_OPTIMAL, LP_UNBOUNDED, LP_ITER_LIMIT, LP_NUMERICAL, LP_INFEASIBLE = 0, 1, 2, 3, 4, 5
+LP_PIVOT_DEGENERATE, LP_PIVOT_TIE, LP_PIVOT_ASPIRATION, LP_PIVOT_LCLEAR, LP_PIVOT_DRIVEOUT = 1, 2, 4, 8, 16
+LP_ROW_LE, LP_ROW_GE, LP_ROW_EQ = 0, 1, 2
 LP_MIN, LP_MAX = 0, 1
 LP_FP64, LP_MIXED = 0, 1
 LP_MAX_ROWS = 10112
-STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT", 4: "NUMERICAL"}
+STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT", 4: "NUMERICAL", 5: "INFEASIBLE"}
 
 
 class lp_options(C.Structure):
@@ -70,6 +71,9 @@ class lp_stats(C.Structure):
         ("price32_ms", C.c_double),
         ("shortlist_ms", C.c_double),
         ("price32_bytes", C.c_double),
+        ("phase1_iterations", C.c_int64),
+        ("drive_outs", C.c_int64),
+        ("phase_switch_ms", C.c_double),
     ]
 
 
@@ -106,6 +110,8 @@ SIGNATURES = {
     "lp_default_options": (C.c_int, [C.POINTER(lp_options)]),
     "lp_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, _DP, _DP, _DP, C.POINTER(lp_options)]),
     "lp_create_device": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, _P, _P, _P, C.POINTER(lp_options)]),
+    "lp_create_general": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, _DP, _DP, _DP, _IP,
+                                    C.POINTER(lp_options)]),
     "lp_solve": (C.c_int, [_P, _IP]),
     "lp_solve_until": (C.c_int, [_P, C.c_int64, _IP]),
     "lp_reset": (C.c_int, [_P]),
@@ -163,9 +169,12 @@ def _dptr(a):
 
 
 class LP:
-    """One LP held on the GPU (an lp_problem handle)."""
+    """One LP held on the GPU (an lp_problem handle).  With row_type (LP_ROW_LE / LP_ROW_GE /
+    LP_ROW_EQ per row) the rows may be >= or = and b may have any sign (lp_create_general,
+    two-phase start)."""
 
-    def __init__(self, A=None, b=None, c=None, *, device_tensors=None, sense="max", precision="fp64", **opts):
+    def __init__(self, A=None, b=None, c=None, *, device_tensors=None, sense="max", precision="fp64",
+                 row_type=None, **opts):
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         o = default_options(sense=LP_MAX if sense == "max" else LP_MIN,
@@ -182,7 +191,15 @@ class LP:
             if b.shape != (m,) or c.shape != (n,):
                 raise ValueError("shapes of A, b, c do not match")
             self._keep = (A, b, c)
-            rc = lib().lp_create(C.byref(h), m, n, _dptr(A), _dptr(b), _dptr(c), C.byref(o))
+            if row_type is None:
+                rc = lib().lp_create(C.byref(h), m, n, _dptr(A), _dptr(b), _dptr(c), C.byref(o))
+            else:
+                rt = np.ascontiguousarray(row_type, dtype=np.int32)
+                if rt.shape != (m,):
+                    raise ValueError("row_type must have m entries")
+                self._keep += (rt,)
+                rc = lib().lp_create_general(C.byref(h), m, n, _dptr(A), _dptr(b), _dptr(c),
+                                             rt.ctypes.data_as(_IP), C.byref(o))
         _check(rc, "lp_create")
         self._h = h
         self.m, self.n = m, n

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblpgpu.so")
-SOURCES = ["lp_kernels.hip", "lp_mixed.hip", "lp_reinv.hip", "lp_api.hip", "lp_batch.hip", "lp_batch_api.hip"]
+SOURCES = ["lp_kernels.hip", "lp_mixed.hip", "lp_reinv.hip", "lp_phase.hip", "lp_api.hip", "lp_batch.hip",
+           "lp_batch_api.hip"]
 
 HIPCC_FLAGS = [
     "-O3",

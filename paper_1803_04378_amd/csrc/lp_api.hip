@@ -84,6 +84,21 @@ struct lp_problem {
   ReinvState* rv = nullptr;
   hipEvent_t rv_ev[2] = {nullptr, nullptr};
   bool rv_timing = false;  // a reinversion's events are waiting to be read
+  // Two-phase start (lp_create_general); n_user == n and phase == 0 otherwise.
+  int32_t n_user = 0;       // the caller's columns; n_user..n-1 are surplus columns
+  int phase = 0;            // 0: one phase; 1: phase 1 running; 2: phase 2
+  bool two_phase = false;   // phase 1 is needed (some row has an artificial variable)
+  std::vector<double> rsign;     // -1 for rows multiplied by -1
+  std::vector<int8_t> art_h;     // art_h[i]: the unit column of row i is artificial
+  double eps_f = 0.0;
+  double* chat1 = nullptr;  // phase-1 costs (device)
+  double* chat2 = nullptr;  // the LP's own costs (device)
+  double* tab_t = nullptr;  // drive-out scratch: per-workgroup tableau-row candidates
+  int32_t* tab_j = nullptr;
+  int32_t* drive = nullptr;
+  int64_t phase1_t = -1;
+  int64_t drive_outs = 0;
+  double switch_ms = 0.0;
 };
 
 namespace {
@@ -346,6 +361,7 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   p->opt = o;
   p->m = m;
   p->n = n;
+  p->n_user = n;
   p->ld = (int32_t)round_up(m, 8);
   const int ld = p->ld;
   const int N = n + m;
@@ -520,6 +536,60 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   return LP_OK;
 }
 
+// Phase 1 from the basis of unit columns: its costs into chat, W and z from them.
+int start_phase1(lp_problem* p) {
+  HIP_TRY(hipMemcpyAsync(const_cast<double*>(p->d.chat), p->chat1, sizeof(double) * ((size_t)p->n + p->m),
+                         hipMemcpyDeviceToDevice, p->stream),
+          "setting the phase-1 costs");
+  HIP_TRY(launch_reprice(p->d, p->stream), "pricing the phase-1 basis");
+  p->phase = 1;
+  p->phase1_t = -1;
+  p->drive_outs = 0;
+  p->switch_ms = 0.0;
+  return read_ctrl(p);
+}
+
+// Section 3.4 / the two-phase method: phase 1 has priced out optimal (no pivot pending).
+// Either the LP is infeasible, or the artificial variables left basic at zero are driven
+// out and phase 2 starts from this basis with the LP's own costs.
+int phase_switch(lp_problem* p) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int m = p->m, n = p->n;
+  p->phase1_t = p->h_ctrl->t;
+  if (p->h_ctrl->z > p->eps_f) {
+    p->h_stage->status = LP_INFEASIBLE;
+    HIP_TRY(hipMemcpyAsync(&p->d.ctrl->status, &p->h_stage->status, sizeof(int32_t), hipMemcpyHostToDevice,
+                           p->stream),
+            "setting the status");
+    p->phase = 2;
+    int rc = read_ctrl(p);
+    p->switch_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+  }
+  std::vector<int32_t> bas(m);
+  HIP_TRY(hipMemcpyAsync(bas.data(), p->d.basis, sizeof(int32_t) * m, hipMemcpyDeviceToHost, p->stream),
+          "reading the basis");
+  HIP_TRY(hipStreamSynchronize(p->stream), "reading the basis");
+  for (int r = 0; r < m; ++r) {
+    // A drive-out changes only its own row of the basis: this list stays valid.
+    if (bas[r] < n || !p->art_h[bas[r] - n]) continue;
+    HIP_TRY(launch_drive_out(p->d, r, p->tab_t, p->tab_j, p->drive, p->stream), "driving out an artificial variable");
+  }
+  HIP_TRY(hipMemcpyAsync(const_cast<double*>(p->d.chat), p->chat2, sizeof(double) * ((size_t)n + m),
+                         hipMemcpyDeviceToDevice, p->stream),
+          "restoring the costs");
+  HIP_TRY(launch_reprice(p->d, p->stream), "pricing the phase-2 basis");
+  p->h_stage->status = LP_RUNNING;
+  HIP_TRY(hipMemcpyAsync(&p->d.ctrl->status, &p->h_stage->status, sizeof(int32_t), hipMemcpyHostToDevice, p->stream),
+          "setting the status");
+  int rc = read_ctrl(p);
+  if (rc != LP_OK) return rc;
+  p->drive_outs = p->h_ctrl->t - p->phase1_t;
+  p->phase = 2;
+  p->switch_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return LP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -557,15 +627,87 @@ int lp_create_device(lp_problem** out, int32_t m, int32_t n, const double* A_col
   return create_common(out, m, n, A_colmajor, b, c, opt, true);
 }
 
+int lp_create_general(lp_problem** out, int32_t m, int32_t n, const double* A_colmajor, const double* b,
+                      const double* c, const int32_t* row_type, const lp_options* opt) {
+  if (!out) return fail(LP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (m <= 0 || n < 0) return fail(LP_ERR_ARG, "need m > 0 and n >= 0");
+  if (!b || (n > 0 && (!A_colmajor || !c))) return fail(LP_ERR_ARG, "NULL data pointer");
+  // Normal form: b >= 0 by row sign changes; >= rows get a surplus column -e_i.
+  std::vector<double> sg(m);
+  std::vector<int8_t> art(m, 0), ge(m, 0);
+  int32_t ns = 0, na = 0;
+  double bmax = 0.0;
+  for (int32_t i = 0; i < m; ++i) {
+    const int32_t ty = row_type ? row_type[i] : LP_ROW_LE;
+    if (ty < LP_ROW_LE || ty > LP_ROW_EQ) return fail(LP_ERR_ARG, "unknown row type");
+    if (!std::isfinite(b[i])) return fail(LP_ERR_ARG, "b contains a non-finite value");
+    sg[i] = b[i] < 0.0 ? -1.0 : 1.0;
+    int32_t t2 = ty;
+    if (sg[i] < 0.0 && ty != LP_ROW_EQ) t2 = ty == LP_ROW_LE ? LP_ROW_GE : LP_ROW_LE;
+    ge[i] = t2 == LP_ROW_GE;
+    art[i] = t2 != LP_ROW_LE;
+    ns += ge[i];
+    na += art[i];
+    bmax = std::max(bmax, std::fabs(b[i]));
+  }
+  if ((int64_t)n + ns > INT32_MAX / 4) return fail(LP_ERR_ARG, "n too large");
+  const int32_t n2 = n + ns;
+  std::vector<double> A2((size_t)m * std::max(n2, 1), 0.0), b2(m), c2(std::max(n2, 1), 0.0);
+  for (int32_t j = 0; j < n; ++j)
+    for (int32_t i = 0; i < m; ++i) A2[(size_t)j * m + i] = sg[i] * A_colmajor[(size_t)j * m + i];
+  for (int32_t i = 0, k = n; i < m; ++i)
+    if (ge[i]) A2[(size_t)(k++) * m + i] = -1.0;
+  for (int32_t i = 0; i < m; ++i) b2[i] = sg[i] * b[i];
+  for (int32_t j = 0; j < n; ++j) c2[j] = c[j];
+  lp_problem* p = nullptr;
+  int rc = create_common(&p, m, n2, A2.data(), b2.data(), c2.data(), opt, false);
+  if (rc != LP_OK) return rc;
+  auto bail = [&](int code) {
+    release(p);
+    return code;
+  };
+  p->n_user = n;
+  p->rsign = std::move(sg);
+  p->eps_f = 1e-9 * (1.0 + bmax);
+  p->two_phase = na > 0;
+  if (p->two_phase) {
+    const size_t N = (size_t)n2 + m;
+    int8_t* dart = nullptr;
+    const int g = tabrow_grid(p->d);
+    hipError_t e;
+    if ((e = dalloc(p, &dart, (size_t)m)) != hipSuccess || (e = dalloc(p, &p->chat1, N)) != hipSuccess ||
+        (e = dalloc(p, &p->chat2, N)) != hipSuccess || (e = dalloc(p, &p->tab_t, (size_t)g)) != hipSuccess ||
+        (e = dalloc(p, &p->tab_j, (size_t)g)) != hipSuccess || (e = dalloc(p, &p->drive, 4)) != hipSuccess)
+      return bail(fail_hip(e, "allocating the two-phase state"));
+    std::vector<double> c1(N, 0.0);
+    for (int32_t i = 0; i < m; ++i) c1[(size_t)n2 + i] = art[i] ? 1.0 : 0.0;
+    if ((e = hipMemcpyAsync(dart, art.data(), (size_t)m, hipMemcpyHostToDevice, p->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(p->chat1, c1.data(), sizeof(double) * N, hipMemcpyHostToDevice, p->stream)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(p->chat2, p->d.chat, sizeof(double) * N, hipMemcpyDeviceToDevice, p->stream)) !=
+            hipSuccess)
+      return bail(fail_hip(e, "uploading the two-phase state"));
+    p->d.art = dart;
+    p->art_h = std::move(art);
+    if ((rc = ensure_capacity(p, p->opt.max_iter + m)) != LP_OK) return bail(rc);
+    if ((rc = start_phase1(p)) != LP_OK) return bail(rc);
+  }
+  *out = p;
+  return LP_OK;
+}
+
 int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
   if (!p) return fail(LP_ERR_ARG, "p is NULL");
   if (iter_cap < 0) return fail(LP_ERR_ARG, "iter_cap must be >= 0");
   int rc;
-  if (p->h_ctrl->status == LP_OPTIMAL || p->h_ctrl->status == LP_UNBOUNDED) {
+  if ((p->h_ctrl->status == LP_OPTIMAL && p->phase != 1) || p->h_ctrl->status == LP_UNBOUNDED ||
+      p->h_ctrl->status == LP_INFEASIBLE) {
     if (status_out) *status_out = p->h_ctrl->status;
     return LP_OK;
   }
-  if ((rc = ensure_capacity(p, iter_cap)) != LP_OK) return rc;
+  // (drive-out pivots of a phase switch may add up to m log entries past the limit)
+  if ((rc = ensure_capacity(p, iter_cap + (p->phase == 1 ? p->m : 0))) != LP_OK) return rc;
   const bool direct = p->opt.profile == 2;
   if (!direct && (!p->gexec || p->graph_k != p->opt.iters_per_sync)) {
     if ((rc = build_graph(p)) != LP_OK) return rc;
@@ -629,12 +771,17 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
         p->stats.price32_bytes += 4.0 * p->m * nonbasic * K;
       }
     }
+    if (p->h_ctrl->status == LP_OPTIMAL && p->phase == 1) {
+      if ((rc = phase_switch(p)) != LP_OK) return rc;
+      if (p->h_ctrl->status == LP_RUNNING) continue;
+    }
     if (p->h_ctrl->status != LP_RUNNING) break;
     // Every replay of a RUNNING solve must pivot K times; anything else is a fault of the
     // kernels' control logic, reported instead of looping.
     if (p->h_ctrl->t != t_before + K)
       return fail(LP_ERR_DEVICE, "iteration graph made no progress while RUNNING");
-    if (p->reinv_period > 0 && p->h_ctrl->t - p->last_reinv_t >= p->reinv_period) {
+    // (reinversion recomputes W from the structural basic variables only: not in phase 1)
+    if (p->reinv_period > 0 && p->phase != 1 && p->h_ctrl->t - p->last_reinv_t >= p->reinv_period) {
       if ((rc = run_reinversion(p)) != LP_OK) return rc;
     }
   }
@@ -656,6 +803,7 @@ int lp_reset(lp_problem* p) {
   p->rv_timing = false;
   p->last_reinv_t = 0;
   p->stats = lp_stats{};
+  if (p->two_phase) return start_phase1(p);
   return LP_OK;
 }
 
@@ -663,7 +811,7 @@ int lp_get_solution(const lp_problem* pc, double* objective, double* x, double* 
                     int64_t* iterations) {
   if (!pc) return fail(LP_ERR_ARG, "p is NULL");
   lp_problem* p = const_cast<lp_problem*>(pc);
-  const int m = p->m, n = p->n;
+  const int m = p->m, n = p->n_user;
   std::vector<double> xB(m), W(m);
   std::vector<int32_t> bas(m);
   HIP_TRY(hipMemcpyAsync(xB.data(), p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
@@ -685,7 +833,7 @@ int lp_get_solution(const lp_problem* pc, double* objective, double* x, double* 
   }
   const double sgn = p->opt.sense == LP_MAX ? -1.0 : 1.0;
   if (y)
-    for (int i = 0; i < m; ++i) y[i] = sgn * W[i];
+    for (int i = 0; i < m; ++i) y[i] = sgn * W[i] * (p->rsign.empty() ? 1.0 : p->rsign[i]);
   if (basis) std::memcpy(basis, bas.data(), sizeof(int32_t) * m);
   if (iterations) *iterations = p->h_ctrl->t;
   return LP_OK;
@@ -741,6 +889,9 @@ int lp_get_stats(const lp_problem* p, lp_stats* s) {
   s->full_prices = p->h_ctrl->full_prices;
   s->reinversions = p->h_ctrl->n_reinv;
   s->reinv_failed = p->h_ctrl->n_reinv_failed;
+  s->phase1_iterations = p->phase1_t;
+  s->drive_outs = p->drive_outs;
+  s->phase_switch_ms = p->switch_ms;
   return LP_OK;
 }
 

@@ -22,11 +22,17 @@ constexpr int kStatusOptimal = 1;
 constexpr int kStatusUnbounded = 2;
 constexpr int kStatusIterLimit = 3;
 constexpr int kStatusNumerical = 4;
+constexpr int kStatusInfeasible = 5;
 
 constexpr int kFlagDegenerate = 1;
 constexpr int kFlagTie = 2;
 constexpr int kFlagAspiration = 4;
 constexpr int kFlagLClear = 8;
+constexpr int kFlagDriveOut = 16;
+
+// pos[v] of an artificial variable (two-phase start) that has left the basis: any value
+// >= 0 keeps a column out of pricing, and this one names no row.
+constexpr int kPosBarred = INT_MAX;
 
 #ifndef LPGPU_PRICE_BLOCK
 #define LPGPU_PRICE_BLOCK 512
@@ -138,6 +144,10 @@ struct DevLP {
   int32_t* sl_j;         //   marks an empty slot)
   int32_t price32_grid;  // workgroups of k_price32
   int32_t pad2;
+  // Two-phase start only (nullptr otherwise): art[i] = 1 when the unit column n+i is the
+  // artificial variable of row i; such a variable is barred (pos = kPosBarred) once it
+  // leaves the basis.
+  const int8_t* art;
 };
 
 // The top row W this iteration prices with: W + d_q rho of the pending pivot, which the
@@ -171,6 +181,13 @@ const void* finish_kernel();
 size_t price_lds_bytes(int ld);
 size_t update_lds_bytes(int ld);
 hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld);
+
+// Two-phase start (lp_phase.hip): W and z from their definitions for the current costs,
+// and the step-0 pivot that replaces the artificial variable basic in row r (no-op for a
+// redundant row).  part_t / part_j hold tabrow_grid(lp) entries, drive one int32.
+hipError_t launch_reprice(const DevLP& lp, hipStream_t s);
+int tabrow_grid(const DevLP& lp);
+hipError_t launch_drive_out(const DevLP& lp, int r, double* part_t, int32_t* part_j, int32_t* drive, hipStream_t s);
 
 // Mixed form (lp_mixed.hip).
 hipError_t launch_convert32(const double* A, float* A32, size_t count, hipStream_t s);

@@ -870,7 +870,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
     ctl->z = fma(dq, thr, z0);
     lp.basis[r] = q;
     lp.pos[q] = r;
-    lp.pos[leave] = -1;
+    lp.pos[leave] = (lp.art && leave >= lp.n && lp.art[leave - lp.n]) ? kPosBarred : -1;
     ctl->nsb = nsb0 + (q < lp.n ? 1 : 0) - (leave < lp.n ? 1 : 0);
     if (t < lp.log_cap) {
       lp.log_enter[t] = q;

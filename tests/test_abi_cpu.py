@@ -40,7 +40,7 @@ def test_header_constants_match_binding():
 def test_struct_layouts():
     assert C.sizeof(binding.lp_options) == 96
     assert C.sizeof(binding.lp_batch_stats) == 88
-    assert C.sizeof(binding.lp_stats) == 192
+    assert C.sizeof(binding.lp_stats) == 216
 
 
 def test_default_options():
@@ -89,6 +89,39 @@ def test_argument_errors_need_no_gpu():
     L.lp_destroy(None)  # NULL-safe
     with pytest.raises(lpg.LPError):
         lpg.LP(A, bn, c)
+
+
+def test_general_create_argument_errors_need_no_gpu():
+    L = lpg.lib()
+    A = np.ones((3, 2), order="F")
+    b = np.array([1.0, -2.0, 0.5])
+    c = np.ones(2)
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+
+    def create(m, n, A_, b_, c_, rt, o=None):
+        h = C.c_void_p()
+        return L.lp_create_general(C.byref(h), m, n, A_, b_, c_, rt, o), h
+
+    rt = np.array([binding.LP_ROW_LE, binding.LP_ROW_GE, binding.LP_ROW_EQ], dtype=np.int32)
+    assert L.lp_create_general(None, 3, 2, dp(A), dp(b), dp(c), ip(rt), None) == binding.LP_ERR_ARG
+    assert create(0, 2, dp(A), dp(b), dp(c), ip(rt))[0] == binding.LP_ERR_ARG
+    assert create(3, 2, None, dp(b), dp(c), ip(rt))[0] == binding.LP_ERR_ARG
+    bad = rt.copy()
+    bad[1] = 3
+    rc, h = create(3, 2, dp(A), dp(b), dp(c), ip(bad))
+    assert rc == binding.LP_ERR_ARG and not h.value
+    assert "row type" in L.lp_error_string(rc).decode()
+    bi = b.copy()
+    bi[0] = np.nan
+    assert create(3, 2, dp(A), dp(bi), dp(c), ip(rt))[0] == binding.LP_ERR_ARG
+    An = A.copy(order="F")
+    An[1, 0] = np.inf
+    assert create(3, 2, dp(An), dp(b), dp(c), ip(rt))[0] == binding.LP_ERR_ARG
+    o = lpg.default_options(iters_per_sync=0)
+    assert create(3, 2, dp(A), dp(b), dp(c), ip(rt), C.byref(o))[0] == binding.LP_ERR_ARG
+    with pytest.raises(ValueError):
+        lpg.LP(A, b, c, row_type=[0, 1])
 
 
 def test_error_strings():

@@ -52,3 +52,20 @@ def test_batch_sizes_law():
     ms, ns = lpgen.batch_sizes(0, 4096)
     assert ms.min() >= 16 and ms.max() <= 256 and np.all(ns == 2 * ms)
     assert len(np.unique(ms)) > 200
+
+
+def test_general_law_is_feasible_by_construction():
+    """x0 (regenerated from its stream) satisfies every row of the general law, in the
+    given row types and signs; the law has >= rows, = rows and negative b."""
+    m, n = 200, 400
+    A, b, c, rt = lpgen.general_lp(3, m, n, ge_frac=0.2, eq_frac=0.1, neg_frac=0.1)
+    x0 = lpgen.uniform(3, lpgen.S_EXTRA, np.arange(n, dtype=np.uint64), 0.0, 2.0 / n)
+    Ax = A @ x0
+    tol = 1e-12 * (1 + np.abs(b).max())
+    assert np.all(Ax[rt == lpgen.ROW_LE] <= b[rt == lpgen.ROW_LE] + tol)
+    assert np.all(Ax[rt == lpgen.ROW_GE] >= b[rt == lpgen.ROW_GE] - tol)
+    assert np.allclose(Ax[rt == lpgen.ROW_EQ], b[rt == lpgen.ROW_EQ], rtol=0, atol=tol)
+    assert (rt == lpgen.ROW_GE).any() and (rt == lpgen.ROW_EQ).any() and (b < 0).any()
+    assert A.flags.f_contiguous and (c >= 1).all() and (c < 10).all()
+    A2, b2, c2, rt2 = lpgen.general_lp(3, m, n, ge_frac=0.2, eq_frac=0.1, neg_frac=0.1)
+    assert np.array_equal(A, A2) and np.array_equal(b, b2) and np.array_equal(rt, rt2)

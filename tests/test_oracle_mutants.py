@@ -120,7 +120,7 @@ def _pins_pass(lib_path):
                 if abs(r.objective - obj) > 1e-9 * (1 + abs(obj)):
                     return False
                 assert_kkt_general(A, b, c, r.x, r.y, rt)
-        A, b, c, rt = lpgen.general_lp(0, 60, 120)
+        A, b, c, rt = lpgen.general_lp(0, 60, 120, ge_frac=0.2, eq_frac=0.1, neg_frac=0.1)
         r = oracle.solve(A, b, c, row_type=rt, lib_path=lib_path)
         ref, obj = highs_general(A, b, c, rt)
         if r.status != oracle.OPTIMAL or abs(r.objective - obj) > 1e-9 * abs(obj):

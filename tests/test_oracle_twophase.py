@@ -13,6 +13,8 @@ from lputil import (assert_kkt_general, brute_force_general, general_standard, h
                     small_general_lps)
 
 LE, GE, EQ = oracle.ROW_LE, oracle.ROW_GE, oracle.ROW_EQ
+# a heavier share of >= / = / negated rows than the generator's default, for small LPs
+HEAVY = dict(ge_frac=0.2, eq_frac=0.1, neg_frac=0.1)
 
 
 def test_hand_derived_equality_lp():
@@ -67,7 +69,7 @@ def test_small_degenerate_lps_vs_highs_and_vertices():
 
 @pytest.mark.parametrize("m,n,seed", [(60, 120, 0), (60, 120, 1), (60, 120, 2), (150, 300, 0)])
 def test_general_law_vs_highs(m, n, seed):
-    A, b, c, rt = lpgen.general_lp(seed, m, n)
+    A, b, c, rt = lpgen.general_lp(seed, m, n, **HEAVY)
     assert (b < 0).any() and (rt == GE).any() and (rt == EQ).any()
     r = oracle.solve(A, b, c, row_type=rt)
     ref, obj = highs_general(A, b, c, rt)
@@ -80,7 +82,7 @@ def test_redundant_rows_keep_an_artificial_basic():
     """Appending a copy of an = row and the sum of two = rows adds constraints that hold
     whenever the others do: same optimum, and the artificial variable of a redundant row
     cannot be driven out, so one stays basic (at zero)."""
-    A, b, c, rt = lpgen.general_lp(4, 40, 80)
+    A, b, c, rt = lpgen.general_lp(4, 40, 80, **HEAVY)
     eq = np.flatnonzero(rt == EQ)
     assert eq.size >= 2
     A2 = np.vstack([A, A[eq[0]], A[eq[0]] + A[eq[1]]])
@@ -133,7 +135,7 @@ def test_unbounded_in_phase_two():
 
 
 def test_resume_across_the_phase_switch():
-    A, b, c, rt = lpgen.general_lp(7, 50, 100)
+    A, b, c, rt = lpgen.general_lp(7, 50, 100, **HEAVY)
     full = oracle.solve(A, b, c, row_type=rt)
     o = oracle.Oracle(A, b, c, row_type=rt)
     cap, phases = 0, set()
