@@ -219,3 +219,20 @@ def small_general_lps(seed, count):
         c = rng.choice([-1.0, 0.0, 1.0, 2.0], size=n)
         out.append((A, b, c, rt))
     return out
+
+
+def transportation_lp(seed, S, D):
+    """min sum c_sd x_sd over S supplies and D demands: row s sums x_s* = supply_s, row S+d
+    sums x_*d = demand_d, all = rows; total supply equals total demand, so one row is
+    implied by the others (a redundant = row).  Integer data, numpy seeded.
+    Returns (A, b, c, row_type) for the min sense."""
+    rng = np.random.default_rng(seed)
+    supply = rng.integers(5, 30, size=S).astype(float)
+    demand = rng.multinomial(int(supply.sum()) - D, np.full(D, 1.0 / D)).astype(float) + 1.0
+    cost = rng.integers(1, 20, size=(S, D)).astype(float)
+    A = np.zeros((S + D, S * D))
+    for s in range(S):
+        for d in range(D):
+            A[s, s * D + d] = 1.0
+            A[S + d, s * D + d] = 1.0
+    return A, np.concatenate([supply, demand]), cost.ravel(), np.full(S + D, 2, dtype=np.int32)

@@ -176,3 +176,46 @@ def test_general_full_size_4000x8000(lpg):
     assert_kkt_general(A, b, c, sol["x"], sol["y"], rt)
     _say(f"  {sol['iterations']} pivots, phase 1 {stats['phase1_iterations']}, drive-outs {stats['drive_outs']}, "
          f"switch {stats['phase_switch_ms']:.2f} ms")
+
+
+@pytest.mark.parametrize("S,D,seed", [(6, 9, 1), (12, 15, 2), (30, 40, 3)])
+def test_transportation_problem(lpg, S, D, seed):
+    """All rows =, phase 1 from artificial variables only, one redundant row."""
+    from lputil import transportation_lp
+    _say(f"case: transportation problem {S} x {D} seed {seed}")
+    A, b, c, rt = transportation_lp(seed, S, D)
+    st, sol, _, _ = assert_parity(lpg, A, b, c, rt, sense="min")
+    assert st == lpg.LP_OPTIMAL
+    assert np.all(np.abs(sol["x"] - np.round(sol["x"])) < 1e-9)
+
+
+@pytest.mark.parametrize("opts", [dict(tabu_tenure=0), dict(leaving_list=0), dict(iters_per_sync=64),
+                                  dict(sense="min")])
+def test_general_law_rule_variants(lpg, opts):
+    _say(f"case: general law m=150 n=300 seed 6, options {opts}")
+    A, b, c, rt = lpgen.general_lp(6, 150, 300, **HEAVY)
+    if opts.get("sense") == "min":
+        c = -c  # min of -c^T x: the same optimum as max c^T x
+    ref_kw = {k: v for k, v in opts.items() if k in ("sense",)}
+    ref = oracle.solve(A, b, c, row_type=rt, tenure=opts.get("tabu_tenure", 5),
+                       leaving_list=bool(opts.get("leaving_list", 1)), **ref_kw)
+    st, sol, piv, _ = _gpu(lpg, A, b, c, rt, **opts)
+    assert st == ref.status == lpg.LP_OPTIMAL
+    for k in ("enter", "row", "leave", "flags"):
+        assert np.array_equal(getattr(ref, k), piv[k]), k
+    assert abs(sol["objective"] - ref.objective) <= OBJ_RTOL * (1 + abs(ref.objective))
+    assert_kkt_general(A, b, c, sol["x"], sol["y"], rt, sense=opts.get("sense", "max"))
+
+
+def test_one_equality_row_and_zero_rhs(lpg):
+    """sum a_j x_j = 4 alone (closed form 4 max c_j/a_j), and the same LP with an extra
+    = row x_0 - x_1 = 0 whose artificial variable starts at zero."""
+    _say("case: one = row; one = row plus a zero right-hand side")
+    rng = np.random.default_rng(9)
+    a = rng.uniform(0.5, 2.0, 7)
+    c = rng.uniform(1.0, 3.0, 7)
+    st, sol, _, _ = assert_parity(lpg, a[None, :], np.array([4.0]), c, [EQ])
+    assert st == lpg.LP_OPTIMAL and abs(sol["objective"] - 4.0 * np.max(c / a)) <= 1e-12 * sol["objective"]
+    A2 = np.vstack([a, np.eye(7)[0] - np.eye(7)[1]])
+    st, sol, _, _ = assert_parity(lpg, A2, np.array([4.0, 0.0]), c, [EQ, EQ])
+    assert st == lpg.LP_OPTIMAL and abs(sol["x"][0] - sol["x"][1]) < 1e-12

@@ -148,3 +148,31 @@ def test_resume_across_the_phase_switch():
     r = o.result()
     assert phases == {1, 2}
     assert r.status == full.status and np.array_equal(r.enter, full.enter) and np.array_equal(r.flags, full.flags)
+
+
+@pytest.mark.parametrize("S,D,seed", [(3, 4, 0), (6, 9, 1), (12, 15, 2)])
+def test_transportation_problem(S, D, seed):
+    """All rows are =, no slack exists, phase 1 starts from artificial variables only, and
+    one row is redundant (supplies and demands have the same total)."""
+    from lputil import transportation_lp
+    A, b, c, rt = transportation_lp(seed, S, D)
+    o = oracle.Oracle(A, b, c, sense="min", row_type=rt)
+    assert o.run() == oracle.OPTIMAL
+    r = o.result()
+    ref, obj = highs_general(A, b, c, rt, sense="min")
+    assert ref == "OPTIMAL" and abs(r.objective - obj) <= 1e-9 * abs(obj)
+    assert_kkt_general(A, b, c, r.x, r.y, rt, sense="min")
+    assert np.all(np.abs(r.x - np.round(r.x)) < 1e-9)  # integral data: vertices are integral
+    # the redundant row keeps an artificial variable in the basis
+    assert any(v >= o.ncols for v in r.basis)
+
+
+def test_one_equality_row_closed_form():
+    """max sum c_j x_j s.t. sum a_j x_j = beta (a > 0): the optimum is beta * max_j c_j / a_j,
+    like the one-row <= case, since the row must be tight anyway when c > 0."""
+    rng = np.random.default_rng(9)
+    a = rng.uniform(0.5, 2.0, 7)
+    c = rng.uniform(1.0, 3.0, 7)
+    r = oracle.solve(a[None, :], np.array([4.0]), c, row_type=[EQ])
+    assert r.status == oracle.OPTIMAL
+    assert abs(r.objective - 4.0 * np.max(c / a)) <= 1e-12 * r.objective
