@@ -38,7 +38,7 @@ constexpr int kPosBarred = INT_MAX;
 #define LPGPU_PRICE_BLOCK 512
 #endif
 #ifndef LPGPU_UPDATE_BLOCK
-#define LPGPU_UPDATE_BLOCK 1024
+#define LPGPU_UPDATE_BLOCK 512
 #endif
 constexpr int kPriceBlock = LPGPU_PRICE_BLOCK;
 constexpr int kUpdateBlock = LPGPU_UPDATE_BLOCK;

@@ -262,9 +262,9 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
 // entries of sparse mode).  rho and a_q are staged whole in LDS, so the sparse mode's
 // per-column lookups and the unit term of a row's basic slack are LDS reads.
 
-// A vector of up to 5 * kUpdateBlock double2 (ld <= 10240) loaded by one workgroup into
+// A vector of up to 5 * kUpdateBlock double2 (ld <= 5120) loaded by one workgroup into
 // registers, up to five per thread, with clamped indices inside a chunk (no lane-level
-// branch for a load to wait behind).
+// branch for a load to wait behind); hold_store copies any longer tail directly.
 // Held as native vectors: copies of the double2 struct go through a stack temporary.
 struct Hold5 {
   v2d h0, h1, h2, h3, h4;

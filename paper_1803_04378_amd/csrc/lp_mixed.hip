@@ -211,8 +211,8 @@ __device__ __forceinline__ int count_below(const uint64_t* list, uint64_t key) {
 static_assert(kShortlist == 16, "count_below is written for lists of 16");
 
 // Elements of a W-length vector one thread of k_shortlist holds (ld / 2 double2 over the
-// block, ld <= LP_MAX_ROWS rounded up to 8).
-constexpr int kShortlistPer = (10112 / 2 + kShortlistBlock - 1) / kShortlistBlock;
+// block, ld <= LP_MAX_ROWS = 9792).
+constexpr int kShortlistPer = (9792 / 2 + kShortlistBlock - 1) / kShortlistBlock;
 
 __global__ __launch_bounds__(kShortlistBlock) void k_shortlist(DevLP lp) {
   // The control fields, W and the candidate lists are loaded up front so that their

@@ -180,3 +180,23 @@ def test_degenerate_budget_500_full_parity(lpg):
     np.testing.assert_array_equal(piv["flags"], ref.flags)
     assert st == ref.status == oracle.OPTIMAL
     assert abs(sol["objective"] - ref.objective) <= 1e-9 * abs(ref.objective)
+
+
+def test_max_rows(lpg):
+    """m = LP_MAX_ROWS (the largest m whose update-kernel staging fits the LDS of one CU):
+    the solve runs and takes the oracle's pivots; one row more is rejected."""
+    m, n = lpg.binding.LP_MAX_ROWS, 24
+    _say(f"case: dense law m={m} n={n} seed 0 (largest m of this build)")
+    A, b, c = lpgen.dense_lp(0, m, n)
+    ref = oracle.solve(A, b, c)
+    with lpg.LP(A, b, c) as p:
+        st = p.solve()
+        piv = p.pivots()
+        sol = p.solution()
+    assert st == ref.status == lpg.LP_OPTIMAL
+    for k in ("enter", "row", "leave", "flags"):
+        assert np.array_equal(piv[k], getattr(ref, k)), k
+    assert abs(sol["objective"] - ref.objective) <= 1e-9 * abs(ref.objective)
+    A1, b1, c1 = lpgen.dense_lp(0, m + 1, 2)
+    with pytest.raises(lpg.LPError):
+        lpg.LP(A1, b1, c1)
