@@ -243,7 +243,7 @@ int iteration_kernels(const lp_problem* p, IterKernel* out) {
   }
   out[c++] = {price_kernel(), p->price_grid, kPriceBlock, price_lds_bytes(p->ld)};
   out[c++] = {update_kernel(), p->update_grid, kUpdateBlock, update_lds_bytes(p->ld)};
-  out[c++] = {finish_kernel(), 1, kUpdateBlock, 0};
+  out[c++] = {finish_kernel(), 1, kFinishBlock, 0};
   return c;
 }
 

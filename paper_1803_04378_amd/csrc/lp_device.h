@@ -42,6 +42,10 @@ constexpr int kPosBarred = INT_MAX;
 #endif
 constexpr int kPriceBlock = LPGPU_PRICE_BLOCK;
 constexpr int kUpdateBlock = LPGPU_UPDATE_BLOCK;
+#ifndef LPGPU_FINISH_BLOCK
+#define LPGPU_FINISH_BLOCK LPGPU_UPDATE_BLOCK
+#endif
+constexpr int kFinishBlock = LPGPU_FINISH_BLOCK;  // the one workgroup of k_finish
 // Rows of B^-1 one wavefront of k_update may own (the host sizes the grid to respect it).
 constexpr int kMaxRowsPerWave = 8;
 // Mixed form: FP32 screening keeps this many candidates per workgroup and overall.

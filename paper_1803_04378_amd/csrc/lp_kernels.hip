@@ -262,39 +262,39 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
 // entries of sparse mode).  rho and a_q are staged whole in LDS, so the sparse mode's
 // per-column lookups and the unit term of a row's basic slack are LDS reads.
 
-// A vector of up to 5 * kUpdateBlock double2 (ld <= 5120) loaded by one workgroup into
-// registers, up to five per thread, with clamped indices inside a chunk (no lane-level
+// A vector of up to kUpdRegs * kUpdateBlock double2 loaded by one workgroup into
+// registers, up to kUpdRegs per thread, with clamped indices inside a chunk (no lane-level
 // branch for a load to wait behind); hold_store copies any longer tail directly.
 // Held as native vectors: copies of the double2 struct go through a stack temporary.
+#ifndef LPGPU_UPD_REGS
+#define LPGPU_UPD_REGS 5
+#endif
+constexpr int kUpdRegs = LPGPU_UPD_REGS;
 struct Hold5 {
-  v2d h0, h1, h2, h3, h4;
+  v2d h[kUpdRegs];
 };
-constexpr int kUpdRegs = 5;
 // Load batch of the dense row update: 4 double2 per lane (the 8 of the streaming kernels
 // would not leave room for the staged vectors within 128 VGPRs).
 constexpr int kUpdBatch = 4;
 // Chunks wholly beyond n2 are skipped (a condition uniform over the workgroup, so no
-// lane-level branch); h.hu is then undefined and hold_store does not read it.
+// lane-level branch); h.h[u] is then undefined and hold_store does not read it.
 __device__ __forceinline__ void hold_load(Hold5& h, const double2* __restrict__ src2, int tid, int n2) {
   constexpr int B = kUpdateBlock;
   const v2d* src = reinterpret_cast<const v2d*>(src2);
-  h.h0 = src[min(tid, n2 - 1)];
-  if (B < n2) h.h1 = src[min(tid + B, n2 - 1)];
-  if (2 * B < n2) h.h2 = src[min(tid + 2 * B, n2 - 1)];
-  if (3 * B < n2) h.h3 = src[min(tid + 3 * B, n2 - 1)];
-  if (4 * B < n2) h.h4 = src[min(tid + 4 * B, n2 - 1)];
+  h.h[0] = src[min(tid, n2 - 1)];
+#pragma unroll
+  for (int u = 1; u < kUpdRegs; ++u)
+    if (u * B < n2) h.h[u] = src[min(tid + u * B, n2 - 1)];
 }
-// Stores what hold_load read into dst (LDS), then copies any part beyond 5 * kUpdateBlock.
+// Stores what hold_load read into dst (LDS), then copies any part beyond kUpdRegs * kUpdateBlock.
 __device__ __forceinline__ void hold_store(const Hold5& h, double2* dst2, const double2* __restrict__ src2, int tid,
                                            int n2) {
   constexpr int B = kUpdateBlock;
   v2d* dst = reinterpret_cast<v2d*>(dst2);
   const v2d* src = reinterpret_cast<const v2d*>(src2);
-  if (tid < n2) dst[tid] = h.h0;
-  if (tid + B < n2) dst[tid + B] = h.h1;
-  if (tid + 2 * B < n2) dst[tid + 2 * B] = h.h2;
-  if (tid + 3 * B < n2) dst[tid + 3 * B] = h.h3;
-  if (tid + 4 * B < n2) dst[tid + 4 * B] = h.h4;
+#pragma unroll
+  for (int u = 0; u < kUpdRegs; ++u)
+    if (tid + u * B < n2) dst[tid + u * B] = h.h[u];
   for (int k = tid + kUpdRegs * B; k < n2; k += B) dst[k] = src[k];
 }
 // Entries of list D per lane gathered from a row in one round (nD <= 512); the rest, if
@@ -693,8 +693,8 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
 // left its minimum ratio (with the lowest row attaining it, that row's alpha and basic
 // variable) and the two smallest tie thresholds of its rows; x_B and alpha of this
 // iteration are in memory.
-__global__ __launch_bounds__(kUpdateBlock) void k_finish(DevLP lp) {
-  constexpr int B = kUpdateBlock;
+__global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
+  constexpr int B = kFinishBlock;
   __shared__ double red_d[B / 64 + 8];
   __shared__ int red_j[B / 64 + 8];
   __shared__ double s_pick_al;
@@ -943,7 +943,7 @@ hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s) {
 }
 
 hipError_t launch_finish(const DevLP& lp, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kUpdateBlock), 0, s, lp);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, lp);
   return hipGetLastError();
 }
 
