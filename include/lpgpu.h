@@ -71,7 +71,7 @@ extern "C" {
 #define LP_FP64 0  /* every step in FP64 */
 #define LP_MIXED 1 /* FP32 screening of the reduced costs, shortlist re-priced in FP64 */
 
-/* Largest m this build accepts: the update kernel stages the pivot row rho and the entering
+/* Largest m the library accepts: the update kernel stages the pivot row rho and the entering
  * column a_q (8 bytes per row each) and the sparse-column index list (ld/8 int32) in the
  * 160 KB of LDS of one CU, next to 2.2 KB of its own: 16.5 * 9792 + 2256 <= 163840. */
 #define LP_MAX_ROWS 9792

@@ -18,7 +18,7 @@
  *   xB     (m)      = B^-1 b = b-bar        body, middle column
  * and pivots it on y_rk as Step 8 prescribes, every iteration, never refactorising.
  *
- * Readings of points the paper leaves open (each one is also listed in the design doc):
+ * Readings of points the paper leaves open:
  *   - m = rows (constraints), n = structural columns.          (Section 2.1)
  *   - ratio-test index runs over the m rows.                    (Step 6)
  *   - optimality: no nonbasic d_j = chat_j - W a_j < -eps_d;

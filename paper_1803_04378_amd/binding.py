@@ -138,8 +138,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
-            raise ImportError(f"{_LIB_PATH} is not built; run __graft_entry__.build() or "
-                              "python paper_1803_04378_amd/build.py")
+            raise ImportError(f"{_LIB_PATH} is not built; run python paper_1803_04378_amd/build.py")
         L = C.CDLL(_LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)

@@ -320,7 +320,7 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   if (!out) return fail(LP_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (m <= 0 || n < 0) return fail(LP_ERR_ARG, "need m > 0 and n >= 0");
-  if (m > LP_MAX_ROWS) return fail(LP_ERR_ARG, "m exceeds LP_MAX_ROWS of this build");
+  if (m > LP_MAX_ROWS) return fail(LP_ERR_ARG, "m exceeds LP_MAX_ROWS");
   if ((int64_t)n + m > INT32_MAX / 2) return fail(LP_ERR_ARG, "n + m too large");
   if (!b || (n > 0 && (!A || !c))) return fail(LP_ERR_ARG, "NULL data pointer");
   lp_options o;

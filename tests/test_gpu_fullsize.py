@@ -186,7 +186,7 @@ def test_max_rows(lpg):
     """m = LP_MAX_ROWS (the largest m whose update-kernel staging fits the LDS of one CU):
     the solve runs and takes the oracle's pivots; one row more is rejected."""
     m, n = lpg.binding.LP_MAX_ROWS, 24
-    _say(f"case: dense law m={m} n={n} seed 0 (largest m of this build)")
+    _say(f"case: dense law m={m} n={n} seed 0 (LP_MAX_ROWS)")
     A, b, c = lpgen.dense_lp(0, m, n)
     ref = oracle.solve(A, b, c)
     with lpg.LP(A, b, c) as p:
