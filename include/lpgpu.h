@@ -34,7 +34,7 @@ extern "C" {
 
 /* ---- return codes (negative = error) ---- */
 #define LP_OK 0
-#define LP_ERR_ARG (-1)     /* NULL pointer, m <= 0, n < 0, non-finite data, size above the build limit */
+#define LP_ERR_ARG (-1)     /* NULL pointer, m <= 0, n < 0, non-finite data, m above LP_MAX_ROWS */
 #define LP_ERR_NEG_RHS (-2) /* lp_create / lp_create_device: some b_i < 0, so the slack basis is infeasible
                                (lp_create_general accepts such LPs: it runs the two-phase start) */
 #define LP_ERR_NOMEM (-3)   /* device or pinned host memory could not be allocated */

@@ -271,3 +271,11 @@ def test_profiling_modes_time_kernels_without_changing_results(lpg, profile):
     L = stats["update_launches"]
     written = stats["update_bytes"] - 8.0 * 500 * 500 * L
     assert 0 < written <= 8.0 * 500 * 500 * L and written % 16 == 0
+
+
+def test_no_structural_columns(lpg):
+    """n = 0: the slack basis is the only basis; OPTIMAL at once with objective 0."""
+    _say("case: m=3 n=0")
+    A, b, c = np.zeros((3, 0)), np.array([1.0, 2.0, 3.0]), np.zeros(0)
+    ref, (st, sol, _, _) = assert_parity(lpg, A, b, c)
+    assert st == oracle.OPTIMAL and sol["iterations"] == 0 and sol["objective"] == 0.0

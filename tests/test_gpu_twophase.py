@@ -219,3 +219,17 @@ def test_one_equality_row_and_zero_rhs(lpg):
     A2 = np.vstack([a, np.eye(7)[0] - np.eye(7)[1]])
     st, sol, _, _ = assert_parity(lpg, A2, np.array([4.0, 0.0]), c, [EQ, EQ])
     assert st == lpg.LP_OPTIMAL and abs(sol["x"][0] - sol["x"][1]) < 1e-12
+
+
+def test_no_given_columns(lpg):
+    """n = 0 with = and >= rows: feasible only when every such b_i is 0 (then the >= row's
+    surplus column drives its artificial variable out and the = row is redundant);
+    a nonzero b_i on an = row, or b_i < 0 on a <= row, is infeasible."""
+    _say("case: n=0 with = / >= / <= rows")
+    Z = np.zeros((2, 0))
+    st, sol, _, stats = assert_parity(lpg, Z, np.array([0.0, 0.0]), np.zeros(0), [EQ, GE])
+    assert st == lpg.LP_OPTIMAL and stats["drive_outs"] == 1
+    st, _, _, _ = assert_parity(lpg, Z, np.array([1.0, 0.0]), np.zeros(0), [EQ, LE])
+    assert st == lpg.LP_INFEASIBLE
+    st, _, _, _ = assert_parity(lpg, Z, np.array([-1.0, 0.0]), np.zeros(0), [LE, LE])
+    assert st == lpg.LP_INFEASIBLE
