@@ -246,6 +246,9 @@ int lp_get_stats(const lp_problem *p, lp_stats *s);
  * opt.reinv_period pivots; it may also be called directly at any time (a pivot left
  * pending by an interrupted solve is absorbed).  If that block is numerically singular
  * (a zero pivot column) the state is left unchanged and lp_stats.reinv_failed counts it.
+ * During phase 1 of lp_create_general's two-phase start (where lp_solve does not
+ * reinvert on its own), W and z are afterwards recomputed from their definitions with
+ * the phase-1 costs.
  * Blocks until the basis has been read back; the rest runs on the handle's stream.
  * Returns LP_OK or LP_ERR_NOMEM / LP_ERR_DEVICE.
  */

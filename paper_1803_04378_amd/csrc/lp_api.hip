@@ -211,6 +211,9 @@ int run_reinversion(lp_problem* p) {
   int k = 0;
   int rc = reinvert(p->d, p->b0, &p->rv, p->stream, p->h_ctrl->nsb, p->h_ctrl->nD, &k);
   if (rc != LP_OK) return rc;
+  // The reinversion forms W from the structural basic variables' costs; in phase 1 the
+  // artificial variables cost 1, so W and z are recomputed from their definitions.
+  if (p->phase == 1) HIP_TRY(launch_reprice(p->d, p->stream), "pricing the phase-1 basis");
   HIP_TRY(hipEventRecord(p->rv_ev[1], p->stream), "recording an event");
   p->rv_timing = true;
   p->last_reinv_t = p->h_ctrl->t;

@@ -201,7 +201,7 @@ def kkt_general_residuals(A, b, c, x, y, row_type, sense="max"):
 
 def assert_kkt_general(A, b, c, x, y, row_type, sense="max", tol=1e-8):
     r = kkt_general_residuals(A, b, c, x, y, row_type, sense)
-    scale = 1.0 + float(np.max(np.abs(b))) + float(np.max(np.abs(c))) * (1.0 + float(np.sum(np.abs(x))))
+    scale = 1.0 + float(np.max(np.abs(b))) + float(np.max(np.abs(c), initial=0.0)) * (1.0 + float(np.sum(np.abs(x))))
     bad = {k: v for k, v in r.items() if v > tol * scale}
     assert not bad, f"KKT violated: {bad} (scale {scale})"
 

@@ -57,7 +57,7 @@ def assert_parity(lpg, A, b, c, rt, max_iter=None, kkt=True, **opts):
     assert stats["drive_outs"] == int(np.count_nonzero(ref.flags & oracle.FLAG_DRIVEOUT))
     if st == lpg.LP_OPTIMAL:
         assert abs(sol["objective"] - ref.objective) <= OBJ_RTOL * (1 + abs(ref.objective))
-        np.testing.assert_allclose(sol["x"], ref.x, rtol=0, atol=1e-9 * (1 + np.abs(ref.x).max()))
+        np.testing.assert_allclose(sol["x"], ref.x, rtol=0, atol=1e-9 * (1 + np.abs(ref.x).max(initial=0.0)))
         if kkt:
             assert_kkt_general(A, b, c, sol["x"], sol["y"], rt, sense=opts.get("sense", "max"))
     return st, sol, piv, stats
@@ -233,3 +233,23 @@ def test_no_given_columns(lpg):
     assert st == lpg.LP_INFEASIBLE
     st, _, _, _ = assert_parity(lpg, Z, np.array([-1.0, 0.0]), np.zeros(0), [LE, LE])
     assert st == lpg.LP_INFEASIBLE
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_reinversion_during_phase_one(lpg, precision):
+    """lp_reinvert in the middle of phase 1: W and z are recomputed with the phase-1 costs,
+    and the solve still ends at the oracle's optimum with a KKT certificate."""
+    _say(f"case: general law m=300 n=600 seed 1, reinversion after 40 pivots, {precision}")
+    A, b, c, rt = lpgen.general_lp(1, 300, 600, **HEAVY)
+    ref = oracle.solve(A, b, c, row_type=rt)
+    with lpg.LP(A, b, c, row_type=rt, precision=precision, iters_per_sync=8) as p:
+        assert p.solve(40) == lpg.LP_ITER_LIMIT
+        assert p.stats()["phase1_iterations"] == -1  # still in phase 1
+        p.reinvert()
+        st = p.solve()
+        sol = p.solution()
+        stats = p.stats()
+    assert st == ref.status == lpg.LP_OPTIMAL
+    assert stats["reinversions"] >= 1 and stats["phase1_iterations"] > 40
+    assert abs(sol["objective"] - ref.objective) <= OBJ_RTOL * abs(ref.objective)
+    assert_kkt_general(A, b, c, sol["x"], sol["y"], rt)
