@@ -71,8 +71,8 @@ def kernel_table(s0, s1):
     """Per-kernel average duration (HIP events of the profiling mode) and, for the
     streaming kernels, algorithmic bytes per launch and the rate they imply.  In the mixed
     form the FP32 screening and shortlist kernels run once per iteration (their launch
-    count is the update kernel's), and the FP64 pricing node is counted per launch whether
-    it ran a full pass or skipped itself."""
+    count is the update kernel's); its rare FP64 passes run inside the screening kernel's
+    launch and are not timed separately."""
     out = {}
     for name in KERNEL_NAMES:
         ms = s1[f"{name}_ms"] - s0[f"{name}_ms"]

@@ -138,7 +138,9 @@ typedef struct lp_stats {
   double finish_ms;         /* their summed duration */
   int64_t ray;              /* after LP_UNBOUNDED: the entering variable with no positive alpha_i; else -1 */
   int64_t price32_launches; /* LP_MIXED: FP32 screening passes run */
-  int64_t full_prices;      /* LP_MIXED: iterations whose shortlist held no improving column, so that
+  int64_t full_prices;      /* LP_MIXED: FP64 passes: after an iteration whose shortlist held no improving
+                               column (it ends without a pivot), the next one prices every column in
+                               FP64 (and is not counted in price32_launches), so that
                                every column was priced in FP64 */
   int64_t reinversions;     /* reinversions installed */
   int64_t reinv_failed;     /* reinversions abandoned because the basis block had a zero pivot

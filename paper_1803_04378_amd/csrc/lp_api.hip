@@ -230,8 +230,9 @@ int collect_reinv_time(lp_problem* p) {
   return LP_OK;
 }
 
-// Kernels of one iteration, in launch order: k_price -> k_update -> k_finish, preceded in
-// the mixed form by the FP32 screening and the shortlist re-price.
+// Kernels of one iteration, in launch order: k_price -> k_update -> k_finish; in the mixed
+// form k_price32 -> k_shortlist -> k_update -> k_finish (k_price32 runs the FP64 pass in
+// the iteration after a fallback verdict).
 struct IterKernel {
   const void* fn;
   int grid, block;
@@ -243,8 +244,9 @@ int iteration_kernels(const lp_problem* p, IterKernel* out) {
   if (p->d.mixed) {
     out[c++] = {price32_kernel(), p->price32_grid, kPrice32Block, price32_lds_bytes(p->ld)};
     out[c++] = {shortlist_kernel(), p->d.sl_k, shortlist_block(), 0};
+  } else {
+    out[c++] = {price_kernel(), p->price_grid, kPriceBlock, price_lds_bytes(p->ld)};
   }
-  out[c++] = {price_kernel(), p->price_grid, kPriceBlock, price_lds_bytes(p->ld)};
   out[c++] = {update_kernel(), p->update_grid, kUpdateBlock, update_lds_bytes(p->ld)};
   out[c++] = {finish_kernel(), 1, kFinishBlock, 0};
   return c;
@@ -402,9 +404,8 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
     const int w32 = kPrice32Block / 64;
     p->price32_grid = (int)std::max<int64_t>(
         1, std::min<int64_t>(std::min<int64_t>((int64_t)per_cu * p->num_cu, max_price32_grid()), (N + w32 - 1) / w32));
-    // The FP64 pass runs rarely in the mixed form but is launched every iteration (and
-    // returns at once): one workgroup per CU keeps that launch cheap.
-    p->price_grid = std::min(p->price_grid, p->num_cu);
+    // The FP64 pass runs inside k_price32's grid: its partials are k_price32's.
+    p->price_grid = p->price32_grid;
   }
 
   // Device memory: A' (ld x n) + B^-1 (m x ld) dominate.
@@ -727,9 +728,10 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
   const bool prof = p->opt.profile != 0;
   const int K = p->opt.iters_per_sync;
   const bool mixed = p->d.mixed != 0;
-  const int E = mixed ? 5 : 3;
+  const int E = mixed ? 4 : 3;
   for (;;) {
     const int64_t t_before = p->h_ctrl->t;
+    const int64_t fb_before = p->h_ctrl->n_fallback;
     const int64_t cols_before = p->h_ctrl->price_cols;
     const int64_t nsb_before = p->h_ctrl->nsb;
     const int64_t ubytes_before = p->h_ctrl->update_bytes;
@@ -742,26 +744,27 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
     p->stats.syncs += 1;
     if ((rc = collect_reinv_time(p)) != LP_OK) return rc;
     if (prof && p->h_ctrl->status == LP_RUNNING && t_before > 0 && p->h_ctrl->t == t_before + K) {
-      // Steady state: every kernel of the replay did a full pass (in the mixed form the
-      // FP64 pricing node may have skipped itself; its bytes count only passes that ran).
+      // Steady state: every kernel of the replay did a full pass (K pivots, so in the
+      // mixed form no fallback iteration and no FP64 pass).
       for (int k = 0; k < K; ++k) {
-        float ms[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        float ms[4] = {0.f, 0.f, 0.f, 0.f};
         for (int i = 0; i < E; ++i) {
           // profile = 1: between the event nodes around kernel i (its launch gap
           // included); profile = 2: the kernel's own start and stop.
           const int a = direct ? 2 * (E * k + i) : E * k + i;
           HIP_TRY(hipEventElapsedTime(&ms[i], p->events[a], p->events[a + 1]), "reading profile events");
         }
-        const int o = mixed ? 2 : 0;
+        const int o = mixed ? 2 : 1;
         if (mixed) {
           p->stats.price32_ms += ms[0];
           p->stats.shortlist_ms += ms[1];
+        } else {
+          p->stats.price_ms += ms[0];
         }
-        p->stats.price_ms += ms[o];
-        p->stats.update_ms += ms[o + 1];
-        p->stats.finish_ms += ms[o + 2];
+        p->stats.update_ms += ms[o];
+        p->stats.finish_ms += ms[o + 1];
       }
-      p->stats.price_launches += K;
+      if (!mixed) p->stats.price_launches += K;
       p->stats.update_launches += K;
       p->stats.finish_launches += K;
       p->stats.price_bytes += 8.0 * p->m * (double)(p->h_ctrl->price_cols - cols_before);
@@ -779,9 +782,10 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
       if (p->h_ctrl->status == LP_RUNNING) continue;
     }
     if (p->h_ctrl->status != LP_RUNNING) break;
-    // Every replay of a RUNNING solve must pivot K times; anything else is a fault of the
-    // kernels' control logic, reported instead of looping.
-    if (p->h_ctrl->t != t_before + K)
+    // Every iteration of a RUNNING solve's replay must pivot, or (mixed form) end with the
+    // fallback verdict; anything else is a fault of the kernels' control logic, reported
+    // instead of looping.
+    if (p->h_ctrl->t + p->h_ctrl->n_fallback != t_before + fb_before + K)
       return fail(LP_ERR_DEVICE, "iteration graph made no progress while RUNNING");
     // (reinversion recomputes W from the structural basic variables only: not in phase 1)
     if (p->reinv_period > 0 && p->phase != 1 && p->h_ctrl->t - p->last_reinv_t >= p->reinv_period) {

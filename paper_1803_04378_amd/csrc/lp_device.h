@@ -23,6 +23,9 @@ constexpr int kStatusUnbounded = 2;
 constexpr int kStatusIterLimit = 3;
 constexpr int kStatusNumerical = 4;
 constexpr int kStatusInfeasible = 5;
+// k_update's verdict in the mixed form when the re-priced shortlist holds no improving
+// column: no pivot this iteration; the next k_price32 runs the full FP64 pricing pass.
+constexpr int kVerdictFallback = 16;
 
 constexpr int kFlagDegenerate = 1;
 constexpr int kFlagTie = 2;
@@ -69,7 +72,7 @@ struct Ctrl {
   int32_t flags;  // pivot-log flags gathered for the pivot in progress
   int32_t pad0;
   int32_t verdict;  // pricing verdict left by k_update for k_finish (-1: k_update did not run)
-  int32_t pad4;
+  int32_t fb;       // mixed form: the next k_price32 runs the full FP64 pricing pass
   int64_t n_degenerate, n_tie, n_aspiration, n_lclear;
   int32_t nsb;   // structural variables in the basis
   int32_t pad1;
@@ -90,6 +93,7 @@ struct Ctrl {
   int64_t update_bytes;      // algorithmic bytes the update passes moved
   int32_t nD;                // columns in the list D (below)
   int32_t pad5;
+  int64_t n_fallback;        // mixed form: iterations that ended with kVerdictFallback (no pivot)
 };
 
 struct DevLP {

@@ -334,6 +334,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   const int64_t t = ctl->t;
   const int64_t max_iter = ctl->max_iter;
   const double theta = ctl->theta;
+  const int fb = ctl->fb;
   // Indices are clamped into range rather than guarded, so that no load waits behind a
   // branch; the values of clamped lanes are discarded below.
   const int pk = min(tid, lp.price_grid - 1);
@@ -372,12 +373,14 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   if (tid < dcap) s_dl[tid] = dl0;
   if (tid + B < dcap) s_dl[tid + B] = dl1;
 
-  // Step 4 decision: from the re-priced shortlist in the mixed form when it holds an
-  // improving column, else from the pricing partials.
+  // Step 4 decision: in the mixed form from the re-priced shortlist (none improving: the
+  // fallback verdict below), else, and in the mixed form's FP64 pass, from the pricing
+  // partials.
   double da = __builtin_inf(), df = __builtin_inf();
   int ja = INT_MAX, jf = INT_MAX;
   bool from_shortlist = false;
-  if (lp.mixed) {
+  const bool use_parts = !lp.mixed || fb;
+  if (lp.mixed && !fb) {
     // the best improving column of the re-priced shortlist (as shortlist_best)
     if (!(lane < lp.sl_k && sj != INT_MAX && sd < -lp.eps_d)) {
       sd = __builtin_inf();
@@ -390,7 +393,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
     da = df;
     ja = jf;
   }
-  if (!from_shortlist) {
+  if (use_parts) {
     da = pd0;
     ja = pj0;
     df = pd1;
@@ -428,7 +431,9 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   const bool sparse = sparse_columns(nD, ld);
   int verdict = kStatusRunning, q = -1, flags = 0;
   double dq = 0.0;
-  if (ja == INT_MAX) {
+  if (!use_parts && !from_shortlist) {
+    verdict = kVerdictFallback;
+  } else if (ja == INT_MAX) {
     verdict = kStatusOptimal;
   } else if (t >= max_iter) {
     verdict = kStatusIterLimit;
@@ -443,8 +448,8 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   if (blockIdx.x == 0 && tid == 0) {
     // Only fields no k_update workgroup reads: the status itself changes in k_finish.
     Ctrl* cw = lp.ctrl;
-    if (lp.mixed) cw->price32_launches += 1;
-    if (!from_shortlist) {
+    if (lp.mixed && !fb) cw->price32_launches += 1;
+    if (use_parts) {
       cw->price_cols += n - cw->nsb;
       cw->price_launches += 1;
       if (lp.mixed) cw->full_prices += 1;
@@ -720,6 +725,16 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
     plow = INT_MAX;
   }
   if (verdict < 0) return;  // k_update did not run
+  if (tid == 0) ctl->fb = verdict == kVerdictFallback ? 1 : 0;
+  if (verdict == kVerdictFallback) {  // no pivot; k_update applied the pending one
+    if (tid == 0) {
+      ctl->verdict = -1;
+      ctl->r = -1;
+      ctl->q = -1;
+      ctl->n_fallback += 1;
+    }
+    return;
+  }
   if (verdict != kStatusRunning) {  // OPTIMAL or ITER_LIMIT; k_update applied the pending pivot
     if (tid == 0) {
       ctl->status = verdict;

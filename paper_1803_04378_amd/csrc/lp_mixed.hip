@@ -7,11 +7,12 @@
 //   k_shortlist  selects the overall kShortlist smallest of those lists and re-prices
 //                the first K of them in FP64, one workgroup per candidate.
 // k_update then takes the lexicographic (d, j) minimum among improving shortlisted
-// columns.  When none improves, the FP64 pass k_price (which skips itself otherwise)
-// has priced every column, and the decision falls back to it: optimality and the
-// aspiration case of the tabu rule are therefore always decided in FP64.  The re-priced
-// d_j are FP64 dot products like the FP64 pass's, summed in another order, so they agree
-// with them to rounding.
+// columns.  When none improves, the iteration ends without a pivot (the fallback verdict)
+// and the next one prices every column in FP64: k_price32 runs the FP64 pass instead of
+// the screening (k_shortlist skips itself), and k_update decides from its partials.
+// Optimality and the aspiration case of the tabu rule are therefore always decided in
+// FP64.  The re-priced d_j are FP64 dot products like the FP64 pass's, summed in another
+// order, so they agree with them to rounding.
 #include "lp_device.h"
 #include "lp_wave.h"
 
@@ -83,6 +84,81 @@ __global__ void k_convert32(const double* __restrict__ A, float* __restrict__ A3
 }
 
 // ---------------------------------------------------------------------------------------
+// The full FP64 pass of Steps 3-4 (k_price's reduced costs and per-workgroup minima over
+// all improving and non-tabu improving columns), run by k_price32's grid in the
+// iteration after a fallback verdict.  No pivot is pending then, so the current W is
+// the top row; it is read from memory (each d_j is the same wave_dot as k_price's).
+__device__ void fp64_pass(const DevLP& lp) {
+  constexpr int waves = kPrice32Block / 64;
+  __shared__ double red_d[2 * waves];
+  __shared__ int red_j[2 * waves];
+  const int m = lp.m, n = lp.n, ld2 = lp.ld / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gw = blockIdx.x * waves + wave, nw = gridDim.x * waves;
+  const int64_t t = lp.ctrl->t;
+  const double* W = lp.ctrl->wcur ? lp.W1 : lp.W0;
+  const double2* W2 = reinterpret_cast<const double2*>(W);
+  const double neg_eps = -lp.eps_d;
+  double da = __builtin_inf(), df = __builtin_inf();
+  int ja = INT_MAX, jf = INT_MAX;
+  double2 v[kBatch];
+  for (int j = gw; j < n; j += nw) {
+    if (lp.pos[j] >= 0) continue;
+    const double s =
+        wave_dot<kStreamA>(reinterpret_cast<const double2*>(lp.A + (size_t)j * lp.ld), W2, ld2, lane, v, false);
+    const double d = lp.chat[j] - s;
+    if (d < neg_eps) {
+      if (lex_less(d, j, da, ja)) {
+        da = d;
+        ja = j;
+      }
+      if (lp.tabu_until[j] < t && lex_less(d, j, df, jf)) {
+        df = d;
+        jf = j;
+      }
+    }
+  }
+  for (int i = blockIdx.x * kPrice32Block + threadIdx.x; i < m; i += gridDim.x * kPrice32Block) {
+    const int vv = n + i;
+    if (lp.pos[vv] >= 0) continue;
+    const double d = lp.chat[vv] - W[i];  // a_{n+i} = e_i
+    if (d < neg_eps) {
+      if (lex_less(d, vv, da, ja)) {
+        da = d;
+        ja = vv;
+      }
+      if (lp.tabu_until[vv] < t && lex_less(d, vv, df, jf)) {
+        df = d;
+        jf = vv;
+      }
+    }
+  }
+  wave_lexmin(da, ja);
+  wave_lexmin(df, jf);
+  if (lane == 0) {
+    red_d[wave] = da;
+    red_j[wave] = ja;
+    red_d[waves + wave] = df;
+    red_j[waves + wave] = jf;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    da = lane < waves ? red_d[lane] : __builtin_inf();
+    ja = lane < waves ? red_j[lane] : INT_MAX;
+    df = lane < waves ? red_d[waves + lane] : __builtin_inf();
+    jf = lane < waves ? red_j[waves + lane] : INT_MAX;
+    wave_lexmin(da, ja);
+    wave_lexmin(df, jf);
+    if (lane == 0) {
+      lp.part_d[2 * blockIdx.x] = da;
+      lp.part_j[2 * blockIdx.x] = ja;
+      lp.part_d[2 * blockIdx.x + 1] = df;
+      lp.part_j[2 * blockIdx.x + 1] = jf;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // FP32 screening.  Wave gw prices columns gw, gw + nw, ... of all N = n + m variables
 // (slack j = n + i needs no GEMV: d_j = chat_j - W_i).  Each wave keeps its kShortlist
 // smallest keys in lanes 0..15, sorted; the workgroup merges its waves' lists by rank.
@@ -90,6 +166,10 @@ __global__ void k_convert32(const double* __restrict__ A, float* __restrict__ A3
 // candidate lists is unique.
 __global__ __launch_bounds__(kPrice32Block) void k_price32(DevLP lp) {
   if (lp.ctrl->status != kStatusRunning) return;
+  if (lp.ctrl->fb) {
+    fp64_pass(lp);
+    return;
+  }
   constexpr int waves = kPrice32Block / 64;
   constexpr int S = kShortlist;
   extern __shared__ float4 s_w4[];
@@ -218,8 +298,8 @@ __global__ __launch_bounds__(kShortlistBlock) void k_shortlist(DevLP lp) {
   // The control fields, W and the candidate lists are loaded up front so that their
   // latencies overlap; only the entering column waits for the selection.
   const Ctrl* ctl = lp.ctrl;
-  const int status = ctl->status, r = ctl->r, wc = ctl->wcur;
-  if (status != kStatusRunning) return;
+  const int status = ctl->status, r = ctl->r, wc = ctl->wcur, fb = ctl->fb;
+  if (status != kStatusRunning || fb) return;  // (fb: this iteration runs the FP64 pass)
   constexpr int S = kShortlist;
   constexpr int W = kShortlistBlock / 64;
   __shared__ uint64_t s_all[kMaxLists * S];

@@ -201,7 +201,7 @@ def test_mixed_profile_modes_agree(lpg):
         assert stats["price32_ms"] > 0 and stats["shortlist_ms"] > 0 and stats["update_ms"] > 0
         assert stats["price32_bytes"] > 0
         _say(f"  profile={prof}: price32 {stats['price32_ms']:.2f} ms shortlist {stats['shortlist_ms']:.2f} ms "
-             f"price(FP64, conditional) {stats['price_ms']:.2f} ms update {stats['update_ms']:.2f} ms")
+             f"update {stats['update_ms']:.2f} ms")
 
 
 def test_mixed_reset_is_deterministic(lpg):
