@@ -122,7 +122,8 @@ typedef struct lp_stats {
   int64_t list_clears;      /* tabu lists cleared because they excluded every tied row */
   int64_t syncs;            /* status read-backs (one per batch of iters_per_sync iterations) */
   double solve_ms;          /* host wall time spent inside lp_solve calls */
-  int64_t price_launches;   /* pricing kernels timed (profile = 1 or 2) */
+  int64_t price_launches;   /* FP64 pricing kernels timed (profile = 1 or 2; LP_FP64 only, the mixed
+                               form times its screening as price32_ms) */
   double price_ms;          /* their summed duration */
   int64_t update_launches;  /* update kernels timed (profile = 1 or 2) */
   double update_ms;         /* their summed duration */
