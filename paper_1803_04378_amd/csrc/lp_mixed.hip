@@ -345,11 +345,16 @@ __global__ __launch_bounds__(kShortlistBlock) void k_shortlist(DevLP lp) {
     s_wg[wave * S + lane] = g;
   }
   __syncthreads();
+  // The searches of one key in the other lists are independent: unrolled and without
+  // branches, their LDS reads interleave (six dependent rounds instead of six per list).
   if (tid < W * S) {
     const uint64_t k0 = s_wh[tid];
     int rank = tid % S;
-    for (int w2 = 0; w2 < W; ++w2)
-      if (w2 != tid / S) rank += count_below(s_wh + w2 * S, k0);
+#pragma unroll
+    for (int w2 = 0; w2 < W; ++w2) {
+      const int cb = count_below(s_wh + w2 * S, k0);
+      rank += w2 != tid / S ? cb : 0;
+    }
     if (rank < S && k0 != kNoKey) s_sel[rank] = s_wg[tid];
   }
   __syncthreads();
@@ -359,8 +364,12 @@ __global__ __launch_bounds__(kShortlistBlock) void k_shortlist(DevLP lp) {
     if (gl >= 0) {
       const uint64_t k0 = s_all[gl * S + idx];
       int rank = idx;
-      for (int l2 = 0; l2 < S; ++l2)
-        if (l2 != l && s_sel[l2] >= 0) rank += count_below(s_all + s_sel[l2] * S, k0);
+#pragma unroll
+      for (int l2 = 0; l2 < S; ++l2) {
+        const int sl = s_sel[l2];
+        const int cb = count_below(s_all + (sl >= 0 ? sl : 0) * S, k0);
+        rank += (l2 != l && sl >= 0) ? cb : 0;
+      }
       if (rank < S) s_top[rank] = key_index(k0);
     }
   }
