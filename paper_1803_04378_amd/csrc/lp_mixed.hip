@@ -83,6 +83,28 @@ __global__ void k_convert32(const double* __restrict__ A, float* __restrict__ A3
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < count; k += stride) A32[k] = (float)A[k];
 }
 
+// Entries of a sorted list of kShortlist (= 16) keys below key: a fixed five-read search.
+__device__ __forceinline__ int count_below(const uint64_t* list, uint64_t key) {
+  int pos = 0;
+  pos += list[pos + 7] < key ? 8 : 0;
+  pos += list[pos + 3] < key ? 4 : 0;
+  pos += list[pos + 1] < key ? 2 : 0;
+  pos += list[pos] < key ? 1 : 0;
+  pos += list[pos] < key ? 1 : 0;  // only when pos == 15 can this add
+  return pos;
+}
+// The same for entries at most key.
+__device__ __forceinline__ int count_le(const uint64_t* list, uint64_t key) {
+  int pos = 0;
+  pos += list[pos + 7] <= key ? 8 : 0;
+  pos += list[pos + 3] <= key ? 4 : 0;
+  pos += list[pos + 1] <= key ? 2 : 0;
+  pos += list[pos] <= key ? 1 : 0;
+  pos += list[pos] <= key ? 1 : 0;
+  return pos;
+}
+static_assert(kShortlist == 16, "count_below and count_le are written for lists of 16");
+
 // ---------------------------------------------------------------------------------------
 // The full FP64 pass of Steps 3-4 (k_price's reduced costs and per-workgroup minima over
 // all improving and non-tabu improving columns), run by k_price32's grid in the
@@ -246,18 +268,14 @@ __global__ __launch_bounds__(kPrice32Block) void k_price32(DevLP lp) {
     const int w = threadIdx.x / S, l = threadIdx.x % S;
     const uint64_t k0 = s_key[threadIdx.x];
     // Rank in the union: own position plus, per other wave, the entries before it; equal
-    // keys (empty slots) are ordered by wave.
+    // keys (empty slots) are ordered by wave.  The searches are independent: unrolled and
+    // without branches, their LDS reads interleave.
     int rank = l;
+#pragma unroll
     for (int w2 = 0; w2 < waves; ++w2) {
-      if (w2 == w) continue;
-      int lo = 0, hi = S;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        const uint64_t k2 = s_key[w2 * S + mid];
-        if (k2 < k0 || (k2 == k0 && w2 < w)) lo = mid + 1;
-        else hi = mid;
-      }
-      rank += lo;
+      const uint64_t* l2 = s_key + w2 * S;
+      const int cb = w2 < w ? count_le(l2, k0) : count_below(l2, k0);
+      rank += w2 != w ? cb : 0;
     }
     if (rank < S) {
       const int slot = blockIdx.x * S + rank;
@@ -278,17 +296,6 @@ __global__ __launch_bounds__(kPrice32Block) void k_price32(DevLP lp) {
 constexpr int kShortlistBlock = 512;
 constexpr int kMaxLists = kShortlistBlock;
 
-// Entries of a sorted list of kShortlist (= 16) keys below key: a fixed five-read search.
-__device__ __forceinline__ int count_below(const uint64_t* list, uint64_t key) {
-  int pos = 0;
-  pos += list[pos + 7] < key ? 8 : 0;
-  pos += list[pos + 3] < key ? 4 : 0;
-  pos += list[pos + 1] < key ? 2 : 0;
-  pos += list[pos] < key ? 1 : 0;
-  pos += list[pos] < key ? 1 : 0;  // only when pos == 15 can this add
-  return pos;
-}
-static_assert(kShortlist == 16, "count_below is written for lists of 16");
 
 // Elements of a W-length vector one thread of k_shortlist holds (ld / 2 double2 over the
 // block, ld <= LP_MAX_ROWS = 9792).
