@@ -184,7 +184,8 @@ hipError_t launch_finish(const DevLP& lp, hipStream_t s);
 hipError_t launch_check_finite(const double* x, int64_t count, double bound, int32_t* flag, hipStream_t s);
 // Kernel entry points for explicit graph construction.
 const void* price_kernel();
-const void* update_kernel();
+const void* update_kernel(int ld);
+int update_block(int ld);
 const void* finish_kernel();
 size_t price_lds_bytes(int ld);
 size_t update_lds_bytes(int ld);

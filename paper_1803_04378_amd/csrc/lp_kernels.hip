@@ -278,8 +278,8 @@ struct Hold5 {
 constexpr int kUpdBatch = 4;
 // Chunks wholly beyond n2 are skipped (a condition uniform over the workgroup, so no
 // lane-level branch); h.h[u] is then undefined and hold_store does not read it.
+template <int B>
 __device__ __forceinline__ void hold_load(Hold5& h, const double2* __restrict__ src2, int tid, int n2) {
-  constexpr int B = kUpdateBlock;
   const v2d* src = reinterpret_cast<const v2d*>(src2);
   h.h[0] = src[min(tid, n2 - 1)];
 #pragma unroll
@@ -287,9 +287,9 @@ __device__ __forceinline__ void hold_load(Hold5& h, const double2* __restrict__ 
     if (u * B < n2) h.h[u] = src[min(tid + u * B, n2 - 1)];
 }
 // Stores what hold_load read into dst (LDS), then copies any part beyond kUpdRegs * kUpdateBlock.
+template <int B>
 __device__ __forceinline__ void hold_store(const Hold5& h, double2* dst2, const double2* __restrict__ src2, int tid,
                                            int n2) {
-  constexpr int B = kUpdateBlock;
   v2d* dst = reinterpret_cast<v2d*>(dst2);
   const v2d* src = reinterpret_cast<const v2d*>(src2);
 #pragma unroll
@@ -301,8 +301,9 @@ __device__ __forceinline__ void hold_store(const Hold5& h, double2* dst2, const 
 // any, follow in a loop.
 constexpr int kGather = 8;
 
-__global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
-  constexpr int B = kUpdateBlock, waves = B / 64;
+template <int B>
+__global__ __launch_bounds__(B) void k_update(DevLP lp) {
+  constexpr int waves = B / 64;
   extern __shared__ double2 smem2[];
   __shared__ double red_d[2 * waves];
   __shared__ int red_j[2 * waves];
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   int pj0 = lp.part_j[2 * pk], pj1 = lp.part_j[2 * pk + 1];
   const double2* rho2 = reinterpret_cast<const double2*>(lp.rho);
   Hold5 hold;
-  hold_load(hold, rho2, tid, ld2);  // unused if no pivot is pending
+  hold_load<B>(hold, rho2, tid, ld2);  // unused if no pivot is pending
   int dl0 = 0, dl1 = 0;
   if (can_sparse) {
     dl0 = lp.dlist[min(tid, dcap - 1)];
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
     pj0 = pj1 = INT_MAX;
   }
 
-  hold_store(hold, s_rho, rho2, tid, ld2);
+  hold_store<B>(hold, s_rho, rho2, tid, ld2);
   if (tid < dcap) s_dl[tid] = dl0;
   if (tid + B < dcap) s_dl[tid + B] = dl1;
 
@@ -481,7 +482,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
   const double eps_p = lp.eps_p, eps_z = lp.eps_z;
   const bool q_col = q >= 0 && q < n;
   const double2* aq2 = reinterpret_cast<const double2*>(lp.A + (size_t)(q_col ? q : 0) * ld);
-  if (q_col) hold_load(hold, aq2, tid, ld2);
+  if (q_col) hold_load<B>(hold, aq2, tid, ld2);
   const double* s_rhod = reinterpret_cast<const double*>(s_rho);
   const double* s_ad = reinterpret_cast<const double*>(s_a);
   // whether the first row's basic variable is a slack outside D (its B^-1 column is a
@@ -501,7 +502,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
       }
     }
     if (q_col) {
-      hold_store(hold, s_a, aq2, tid, ld2);
+      hold_store<B>(hold, s_a, aq2, tid, ld2);
     } else if (q >= 0) {
       const int e = q - n;
       for (int k = tid; k < ld2; k += B) s_a[k] = make_double2(2 * k == e ? 1.0 : 0.0, 2 * k + 1 == e ? 1.0 : 0.0);
@@ -595,7 +596,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(DevLP lp) {
     const bool pre_late = can_sparse && gw < m;
     if (pre_late) load_batch(reinterpret_cast<const double2*>(lp.Binv + (size_t)gw * ld), lane, ld2, v);
     if (q_col) {
-      hold_store(hold, s_a, aq2, tid, ld2);
+      hold_store<B>(hold, s_a, aq2, tid, ld2);
     } else if (q >= 0) {
       const int e = q - n;
       for (int k = tid; k < ld2; k += B) s_a[k] = make_double2(2 * k == e ? 1.0 : 0.0, 2 * k + 1 == e ? 1.0 : 0.0);
@@ -919,7 +920,35 @@ __global__ void k_check_finite(const double* __restrict__ x, int64_t count, doub
 
 // ---------------------------------------------------------------------------------------
 const void* price_kernel() { return reinterpret_cast<const void*>(&k_price); }
-const void* update_kernel() { return reinterpret_cast<const void*>(&k_update); }
+// k_update's workgroup size for a row stride ld: kUpdateBlock threads, or twice that where
+// the staging in LDS admits only one such workgroup per CU and one of the larger ones
+// fits (it keeps twice the wavefronts in flight).
+int update_block(int ld) {
+  const int lds = (int)update_lds_bytes(ld);
+  int small = 0, large = 0;
+  const void* fs = reinterpret_cast<const void*>(&k_update<kUpdateBlock>);
+  const void* fl = reinterpret_cast<const void*>(&k_update<2 * kUpdateBlock>);
+  if (hipFuncSetAttribute(fs, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&small, k_update<kUpdateBlock>, kUpdateBlock, lds) !=
+          hipSuccess) {
+    (void)hipGetLastError();  // reported by the caller's own occupancy query
+    return kUpdateBlock;
+  }
+  if (small >= 2) return kUpdateBlock;
+  // The larger workgroup has more static LDS: near the largest ld it may not fit at all,
+  // and a refused attribute would otherwise stay as the runtime's last error.
+  if (hipFuncSetAttribute(fl, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&large, k_update<2 * kUpdateBlock>, 2 * kUpdateBlock, lds) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return kUpdateBlock;
+  }
+  return large >= 1 ? 2 * kUpdateBlock : kUpdateBlock;
+}
+const void* update_kernel(int ld) {
+  return update_block(ld) == kUpdateBlock ? reinterpret_cast<const void*>(&k_update<kUpdateBlock>)
+                                          : reinterpret_cast<const void*>(&k_update<2 * kUpdateBlock>);
+}
 const void* finish_kernel() { return reinterpret_cast<const void*>(&k_finish); }
 
 size_t price_lds_bytes(int ld) { return sizeof(double) * (size_t)ld; }
@@ -932,12 +961,15 @@ hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_price),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)price_lds_bytes(ld));
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)update_lds_bytes(ld));
+  e = hipFuncSetAttribute(update_kernel(ld), hipFuncAttributeMaxDynamicSharedMemorySize, (int)update_lds_bytes(ld));
   if (e != hipSuccess) return e;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(price_per_cu, k_price, kPriceBlock, price_lds_bytes(ld));
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update, kUpdateBlock, update_lds_bytes(ld));
+  if (update_block(ld) == kUpdateBlock)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update<kUpdateBlock>, kUpdateBlock,
+                                                        update_lds_bytes(ld));
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update<2 * kUpdateBlock>, 2 * kUpdateBlock,
+                                                      update_lds_bytes(ld));
 }
 
 hipError_t launch_init(const DevLP& lp, const double* b, const double* c, double sense, hipStream_t s) {
@@ -953,7 +985,11 @@ hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s) {
 }
 
 hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(grid), dim3(kUpdateBlock), update_lds_bytes(lp.ld), s, lp);
+  if (update_block(lp.ld) == kUpdateBlock)
+    hipLaunchKernelGGL(k_update<kUpdateBlock>, dim3(grid), dim3(kUpdateBlock), update_lds_bytes(lp.ld), s, lp);
+  else
+    hipLaunchKernelGGL(k_update<2 * kUpdateBlock>, dim3(grid), dim3(2 * kUpdateBlock), update_lds_bytes(lp.ld), s,
+                       lp);
   return hipGetLastError();
 }
 
