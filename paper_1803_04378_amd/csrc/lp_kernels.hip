@@ -78,31 +78,12 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
   }
 }
 
-// Mixed form: the best improving column of the re-priced shortlist as (d, j), or
-// (inf, INT_MAX) when it holds none (its columns are all non-tabu).  Lane w reads entry w
-// and a wavefront minimum combines them, so every wavefront gets the same answer.
-__device__ __forceinline__ void shortlist_best(const DevLP& lp, double& d, int& j) {
-  const int lane = threadIdx.x & 63;
-  d = __builtin_inf();
-  j = INT_MAX;
-  if (lane < lp.sl_k) {
-    const double dw = lp.sl_d[lane];
-    const int jw = lp.sl_j[lane];
-    if (jw != INT_MAX && dw < -lp.eps_d) {
-      d = dw;
-      j = jw;
-    }
-  }
-  wave_lexmin(d, j);
-}
-
 // ---------------------------------------------------------------------------------------
 // Steps 3-4, preceded by Step 8 on the top row of the tableau for the pending pivot:
 // every workgroup forms W_new = W + d_q rho, rho = B^-1[r,:] / alpha_r, while staging it
 // into LDS (B^-1 still holds the pre-pivot rows, the row update runs in k_update);
-// workgroup 0 also stores rho and W_new for the rest of the iteration.  In the mixed
-// form k_price32 has done that already, and this pass runs only when the re-priced
-// shortlist holds no improving column.
+// workgroup 0 also stores rho and W_new for the rest of the iteration.  (The mixed form
+// does not launch this kernel: k_price32 screens, and runs the FP64 pass when needed.)
 __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
   extern __shared__ double2 s_w2[];
   __shared__ double red_d[2 * (kPriceBlock / 64)];
@@ -133,20 +114,14 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
     c_chat = lp.chat[jl];
   }
   double2 v[kBatch];
-  const bool pre = gw < n && !lp.mixed;
+  const bool pre = gw < n;
   if (pre) {
     if (kStreamA) load_batch_nt(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
     else load_batch(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
   }
   if (status != kStatusRunning) return;
-  if (lp.mixed) {
-    double d;
-    int j;
-    shortlist_best(lp, d, j);
-    if (j != INT_MAX) return;
-  }
 
-  if (r >= 0 && !lp.mixed) {
+  if (r >= 0) {
     const double2* Wold = reinterpret_cast<const double2*>(wc ? lp.W1 : lp.W0);
     const double2* rowr = reinterpret_cast<const double2*>(lp.Binv + (size_t)r * lp.ld);
     double2* Wnew = reinterpret_cast<double2*>(wc ? lp.W0 : lp.W1);
@@ -382,7 +357,8 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
   bool from_shortlist = false;
   const bool use_parts = !lp.mixed || fb;
   if (lp.mixed && !fb) {
-    // the best improving column of the re-priced shortlist (as shortlist_best)
+    // the best improving column of the re-priced shortlist: lane w reads entry w, a
+  // wavefront minimum combines them (its columns are all non-tabu)
     if (!(lane < lp.sl_k && sj != INT_MAX && sd < -lp.eps_d)) {
       sd = __builtin_inf();
       sj = INT_MAX;
