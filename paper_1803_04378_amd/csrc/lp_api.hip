@@ -247,7 +247,7 @@ int iteration_kernels(const lp_problem* p, IterKernel* out) {
   } else {
     out[c++] = {price_kernel(), p->price_grid, kPriceBlock, price_lds_bytes(p->ld)};
   }
-  out[c++] = {update_kernel(p->ld), p->update_grid, update_block(p->ld), update_lds_bytes(p->ld)};
+  out[c++] = {update_kernel_for_block(p->d.upd_block), p->update_grid, p->d.upd_block, update_lds_bytes(p->ld)};
   out[c++] = {finish_kernel(), 1, kFinishBlock, 0};
   return c;
 }
@@ -390,7 +390,8 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
     if (e != hipSuccess) return bail(fail_hip(e, "querying kernel occupancy"));
     if (price_per_cu < 1 || update_per_cu < 1) return bail(fail(LP_ERR_ARG, "m too large for the kernels' LDS"));
   }
-  const int pw = kPriceBlock / 64, uw = update_block(ld) / 64;
+  const int upd_block = update_block(ld);
+  const int pw = kPriceBlock / 64, uw = upd_block / 64;
   p->price_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)price_per_cu * p->num_cu, (n + pw - 1) / pw));
   p->update_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)update_per_cu * p->num_cu, (m + uw - 1) / uw));
   if ((m + (int64_t)p->update_grid * uw - 1) / ((int64_t)p->update_grid * uw) > kMaxRowsPerWave)
@@ -461,6 +462,7 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
 #undef ALLOC
   p->d.m = m;
   p->d.n = n;
+  p->d.upd_block = upd_block;
   p->d.price_grid = p->price_grid;
   p->d.update_grid = p->update_grid;
   p->d.ld = ld;

@@ -97,7 +97,8 @@ struct Ctrl {
 };
 
 struct DevLP {
-  int32_t m, n, ld, pad0;
+  int32_t m, n, ld;
+  int32_t upd_block;  // k_update's workgroup size, update_block(ld), fixed at creation
   const double* A;
   const double* chat;
   double* Binv;
@@ -185,6 +186,7 @@ hipError_t launch_check_finite(const double* x, int64_t count, double bound, int
 // Kernel entry points for explicit graph construction.
 const void* price_kernel();
 const void* update_kernel(int ld);
+const void* update_kernel_for_block(int block);
 int update_block(int ld);
 const void* finish_kernel();
 size_t price_lds_bytes(int ld);

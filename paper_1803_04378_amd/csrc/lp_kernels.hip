@@ -921,10 +921,11 @@ int update_block(int ld) {
   }
   return large >= 1 ? 2 * kUpdateBlock : kUpdateBlock;
 }
-const void* update_kernel(int ld) {
-  return update_block(ld) == kUpdateBlock ? reinterpret_cast<const void*>(&k_update<kUpdateBlock>)
-                                          : reinterpret_cast<const void*>(&k_update<2 * kUpdateBlock>);
+const void* update_kernel_for_block(int block) {
+  return block == kUpdateBlock ? reinterpret_cast<const void*>(&k_update<kUpdateBlock>)
+                               : reinterpret_cast<const void*>(&k_update<2 * kUpdateBlock>);
 }
+const void* update_kernel(int ld) { return update_kernel_for_block(update_block(ld)); }
 const void* finish_kernel() { return reinterpret_cast<const void*>(&k_finish); }
 
 size_t price_lds_bytes(int ld) { return sizeof(double) * (size_t)ld; }
@@ -961,7 +962,7 @@ hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s) {
 }
 
 hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s) {
-  if (update_block(lp.ld) == kUpdateBlock)
+  if (lp.upd_block == kUpdateBlock)
     hipLaunchKernelGGL(k_update<kUpdateBlock>, dim3(grid), dim3(kUpdateBlock), update_lds_bytes(lp.ld), s, lp);
   else
     hipLaunchKernelGGL(k_update<2 * kUpdateBlock>, dim3(grid), dim3(2 * kUpdateBlock), update_lds_bytes(lp.ld), s,
