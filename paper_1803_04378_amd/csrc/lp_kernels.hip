@@ -678,7 +678,7 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
 __global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
   constexpr int B = kFinishBlock;
   __shared__ double red_d[B / 64 + 8];
-  __shared__ int red_j[B / 64 + 8];
+  __shared__ int red_j[2 * (B / 64) + 8];
   __shared__ double s_pick_al;
   __shared__ int s_pick[3];
   Ctrl* ctl = lp.ctrl;
@@ -765,8 +765,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
       ++ncand;
       cand = min(cand, k);
     }
-  ncand = block_sum_int<B>(ncand, red_j);
-  cand = block_min_int<B>(cand, red_j);
+  block_sum_min_int<B>(ncand, cand, red_j);
   bool fast = false;
   if (ncand == 1) {
     if (cand < B) {
@@ -799,8 +798,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
         low = min(low, i);
       }
     }
-    cnt = block_sum_int<B>(cnt, red_j);
-    low = block_min_int<B>(low, red_j);
+    block_sum_min_int<B>(cnt, low, red_j);
   }
   int r = low;
   int flags = flags0;

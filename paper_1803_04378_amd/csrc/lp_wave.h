@@ -213,6 +213,29 @@ __device__ int block_sum_int(int v, int* si) {
   return v;
 }
 
+// An integer sum and an integer minimum over the block in one exchange (si holds
+// 2 * BLOCK / 64 entries).
+template <int BLOCK>
+__device__ void block_sum_min_int(int& s, int& mn, int* si) {
+  constexpr int W = BLOCK / 64;
+  s = wave_sum_int(s);
+  mn = wave_min_int(mn);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    si[wave] = s;
+    si[W + wave] = mn;
+  }
+  __syncthreads();
+  s = 0;
+  mn = INT_MAX;
+  for (int w = 0; w < W; ++w) {
+    s += si[w];
+    mn = min(mn, si[W + w]);
+  }
+  __syncthreads();  // si may be reused at once
+}
+
 // Streaming helpers.  Lane l of a wavefront owns elements l, l+64, l+128, ... of a
 // contiguous FP64 vector held as n2 double2; a batch is NB such elements per lane (the
 // size of the register array passed in: 16 KB per wavefront in flight at NB = kBatch = 8).
