@@ -37,7 +37,9 @@ extern "C" {
 #define LP_ERR_ARG (-1)     /* NULL pointer, m <= 0, n < 0, non-finite data, m above LP_MAX_ROWS */
 #define LP_ERR_NEG_RHS (-2) /* lp_create / lp_create_device: some b_i < 0, so the slack basis is infeasible
                                (lp_create_general accepts such LPs: it runs the two-phase start) */
-#define LP_ERR_NOMEM (-3)   /* device or pinned host memory could not be allocated */
+#define LP_ERR_NOMEM (-3)   /* device, pinned or ordinary host memory could not be allocated; no
+                               host exception leaves an entry point: it becomes this code, and a
+                               handle under construction is released */
 #define LP_ERR_DEVICE (-4)  /* a HIP runtime call failed (no GPU, bad stream, launch failure) */
 #define LP_ERR_STATE (-5)   /* the handle is not in a state that allows the call */
 

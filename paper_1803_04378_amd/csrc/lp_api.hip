@@ -1,8 +1,9 @@
 // Host runtime and C ABI of lpgpu (declared in include/lpgpu.h).
 //
-// The handle owns the device state of one LP.  An iteration is the kernel pair
-// k_price -> k_update; lp_solve captures iters_per_sync such pairs once into a HIP
-// graph and replays it, reading back only the small control block after each replay
+// The handle owns the device state of one LP.  An iteration is the kernel chain
+// k_price -> k_update -> k_finish (k_price32 -> k_shortlist -> k_update -> k_finish in the
+// mixed form); lp_solve captures iters_per_sync such chains once into a HIP graph and
+// replays it, reading back only the small control block after each replay
 // (the status scalar plus counters).  The kernels themselves stop doing work once the
 // status leaves RUNNING, so a replay that overshoots the end of the solve is harmless.
 #include <hip/hip_ext.h>
@@ -14,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <string>
 #include <vector>
@@ -39,6 +41,27 @@ int fail(int code, const std::string& msg) {
 
 namespace lpgpu {
 int record_error(int code, const std::string& msg) { return fail(code, msg); }
+
+// Called from a catch-all handler: an exception of host code (an allocation that failed, a
+// thread that could not start) becomes LP_ERR_NOMEM, since nothing may unwind through the
+// C ABI.
+int host_exception() noexcept {
+  try {
+    try {
+      throw;
+    } catch (const std::bad_alloc&) {
+      return fail(LP_ERR_NOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+      return fail(LP_ERR_NOMEM, std::string("host resources exhausted: ") + e.what());
+    } catch (...) {
+      return fail(LP_ERR_NOMEM, "unexpected host exception");
+    }
+  } catch (...) {  // the message itself could not be stored
+    g_code = LP_ERR_NOMEM;
+    g_msg.clear();
+    return LP_ERR_NOMEM;
+  }
+}
 }  // namespace lpgpu
 
 namespace {
@@ -55,6 +78,17 @@ int fail_hip(hipError_t e, const char* what) {
   } while (0)
 
 int64_t round_up(int64_t x, int64_t k) { return (x + k - 1) / k * k; }
+
+// Runs f when the scope ends, by a return or by an exception.
+template <class F>
+struct ScopeExit {
+  F f;
+  ~ScopeExit() { f(); }
+};
+template <class F>
+ScopeExit<F> on_scope_exit(F f) {
+  return {f};
+}
 
 }  // namespace
 
@@ -360,8 +394,12 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   int rc = LP_OK;
   auto bail = [&](int code) {
     release(p);
+    p = nullptr;
     return code;
   };
+  const auto drop = on_scope_exit([&] {  // an exception before the hand-over releases it too
+    if (p) release(p);
+  });
   p->device = dev;
   p->opt = o;
   p->m = m;
@@ -539,6 +577,7 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   if (p->reinv_period > 0 && (rc = reinv_prepare(&p->rv, m, ld)) != LP_OK) return bail(rc);
   p->hc = std::move(hc);
   *out = p;
+  p = nullptr;  // handed over
   return LP_OK;
 }
 
@@ -600,7 +639,7 @@ int phase_switch(lp_problem* p) {
 
 extern "C" {
 
-int lp_default_options(lp_options* opt) {
+int lp_default_options(lp_options* opt) try {
   if (!opt) return fail(LP_ERR_ARG, "opt is NULL");
   std::memset(opt, 0, sizeof(*opt));
   opt->sense = LP_MAX;
@@ -621,23 +660,30 @@ int lp_default_options(lp_options* opt) {
   opt->shortlist_k = kShortlist;
   opt->reinv_period = -1;
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
 int lp_create(lp_problem** out, int32_t m, int32_t n, const double* A_colmajor, const double* b, const double* c,
-              const lp_options* opt) {
+              const lp_options* opt) try {
   return create_common(out, m, n, A_colmajor, b, c, opt, false);
+} catch (...) {
+  return host_exception();
 }
 
 int lp_create_device(lp_problem** out, int32_t m, int32_t n, const double* A_colmajor, const double* b,
-                     const double* c, const lp_options* opt) {
+                     const double* c, const lp_options* opt) try {
   return create_common(out, m, n, A_colmajor, b, c, opt, true);
+} catch (...) {
+  return host_exception();
 }
 
 int lp_create_general(lp_problem** out, int32_t m, int32_t n, const double* A_colmajor, const double* b,
-                      const double* c, const int32_t* row_type, const lp_options* opt) {
+                      const double* c, const int32_t* row_type, const lp_options* opt) try {
   if (!out) return fail(LP_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (m <= 0 || n < 0) return fail(LP_ERR_ARG, "need m > 0 and n >= 0");
+  if (m > LP_MAX_ROWS) return fail(LP_ERR_ARG, "m exceeds LP_MAX_ROWS");
   if (!b || (n > 0 && (!A_colmajor || !c))) return fail(LP_ERR_ARG, "NULL data pointer");
   // Normal form: b >= 0 by row sign changes; >= rows get a surplus column -e_i.
   std::vector<double> sg(m);
@@ -659,7 +705,8 @@ int lp_create_general(lp_problem** out, int32_t m, int32_t n, const double* A_co
   }
   if ((int64_t)n + ns > INT32_MAX / 4) return fail(LP_ERR_ARG, "n too large");
   const int32_t n2 = n + ns;
-  std::vector<double> A2((size_t)m * std::max(n2, 1), 0.0), b2(m), c2(std::max(n2, 1), 0.0);
+  const size_t N = (size_t)n2 + m;
+  std::vector<double> A2((size_t)m * std::max(n2, 1), 0.0), b2(m), c2(std::max(n2, 1), 0.0), c1(N, 0.0);
   for (int32_t j = 0; j < n; ++j)
     for (int32_t i = 0; i < m; ++i) A2[(size_t)j * m + i] = sg[i] * A_colmajor[(size_t)j * m + i];
   for (int32_t i = 0, k = n; i < m; ++i)
@@ -671,14 +718,17 @@ int lp_create_general(lp_problem** out, int32_t m, int32_t n, const double* A_co
   if (rc != LP_OK) return rc;
   auto bail = [&](int code) {
     release(p);
+    p = nullptr;
     return code;
   };
+  const auto drop = on_scope_exit([&] {  // an exception before the hand-over releases it too
+    if (p) release(p);
+  });
   p->n_user = n;
   p->rsign = std::move(sg);
   p->eps_f = 1e-9 * (1.0 + bmax);
   p->two_phase = na > 0;
   if (p->two_phase) {
-    const size_t N = (size_t)n2 + m;
     int8_t* dart = nullptr;
     const int g = tabrow_grid(p->d);
     hipError_t e;
@@ -686,7 +736,6 @@ int lp_create_general(lp_problem** out, int32_t m, int32_t n, const double* A_co
         (e = dalloc(p, &p->chat2, N)) != hipSuccess || (e = dalloc(p, &p->tab_t, (size_t)g)) != hipSuccess ||
         (e = dalloc(p, &p->tab_j, (size_t)g)) != hipSuccess || (e = dalloc(p, &p->drive, 4)) != hipSuccess)
       return bail(fail_hip(e, "allocating the two-phase state"));
-    std::vector<double> c1(N, 0.0);
     for (int32_t i = 0; i < m; ++i) c1[(size_t)n2 + i] = art[i] ? 1.0 : 0.0;
     if ((e = hipMemcpyAsync(dart, art.data(), (size_t)m, hipMemcpyHostToDevice, p->stream)) != hipSuccess ||
         (e = hipMemcpyAsync(p->chat1, c1.data(), sizeof(double) * N, hipMemcpyHostToDevice, p->stream)) !=
@@ -700,10 +749,13 @@ int lp_create_general(lp_problem** out, int32_t m, int32_t n, const double* A_co
     if ((rc = start_phase1(p)) != LP_OK) return bail(rc);
   }
   *out = p;
+  p = nullptr;  // handed over
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
-int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
+int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) try {
   if (!p) return fail(LP_ERR_ARG, "p is NULL");
   if (iter_cap < 0) return fail(LP_ERR_ARG, "iter_cap must be >= 0");
   int rc;
@@ -797,14 +849,18 @@ int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) {
   p->stats.solve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (status_out) *status_out = p->h_ctrl->status;
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
-int lp_solve(lp_problem* p, int32_t* status_out) {
+int lp_solve(lp_problem* p, int32_t* status_out) try {
   if (!p) return fail(LP_ERR_ARG, "p is NULL");
   return lp_solve_until(p, p->opt.max_iter, status_out);
+} catch (...) {
+  return host_exception();
 }
 
-int lp_reset(lp_problem* p) {
+int lp_reset(lp_problem* p) try {
   if (!p) return fail(LP_ERR_ARG, "p is NULL");
   HIP_TRY(launch_init(p->d, p->b0, p->c0, p->opt.sense == LP_MAX ? -1.0 : 1.0, p->stream), "resetting");
   int rc = read_ctrl(p);
@@ -814,10 +870,12 @@ int lp_reset(lp_problem* p) {
   p->stats = lp_stats{};
   if (p->two_phase) return start_phase1(p);
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
 int lp_get_solution(const lp_problem* pc, double* objective, double* x, double* y, int32_t* basis,
-                    int64_t* iterations) {
+                    int64_t* iterations) try {
   if (!pc) return fail(LP_ERR_ARG, "p is NULL");
   lp_problem* p = const_cast<lp_problem*>(pc);
   const int m = p->m, n = p->n_user;
@@ -846,10 +904,12 @@ int lp_get_solution(const lp_problem* pc, double* objective, double* x, double* 
   if (basis) std::memcpy(basis, bas.data(), sizeof(int32_t) * m);
   if (iterations) *iterations = p->h_ctrl->t;
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
 int lp_get_pivots(const lp_problem* pc, int32_t* entering, int32_t* leaving_row, int32_t* leaving_var,
-                  int32_t* flags, int64_t capacity, int64_t* count) {
+                  int32_t* flags, int64_t capacity, int64_t* count) try {
   if (!pc) return fail(LP_ERR_ARG, "p is NULL");
   if (capacity < 0) return fail(LP_ERR_ARG, "capacity must be >= 0");
   lp_problem* p = const_cast<lp_problem*>(pc);
@@ -864,9 +924,11 @@ int lp_get_pivots(const lp_problem* pc, int32_t* entering, int32_t* leaving_row,
   HIP_TRY(hipStreamSynchronize(p->stream), "reading the pivot log");
   if (count) *count = have;
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
-int lp_get_tableau(const lp_problem* pc, double* Binv, double* xB, double* W, double* z) {
+int lp_get_tableau(const lp_problem* pc, double* Binv, double* xB, double* W, double* z) try {
   if (!pc) return fail(LP_ERR_ARG, "p is NULL");
   lp_problem* p = const_cast<lp_problem*>(pc);
   const int m = p->m;
@@ -883,9 +945,11 @@ int lp_get_tableau(const lp_problem* pc, double* Binv, double* xB, double* W, do
   HIP_TRY(hipStreamSynchronize(p->stream), "reading the tableau");
   if (z) *z = p->h_ctrl->z;
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
-int lp_get_stats(const lp_problem* p, lp_stats* s) {
+int lp_get_stats(const lp_problem* p, lp_stats* s) try {
   if (!p || !s) return fail(LP_ERR_ARG, "NULL argument");
   *s = p->stats;
   s->iterations = p->h_ctrl->t;
@@ -902,9 +966,11 @@ int lp_get_stats(const lp_problem* p, lp_stats* s) {
   s->drive_outs = p->drive_outs;
   s->phase_switch_ms = p->switch_ms;
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
-int lp_reinvert(lp_problem* p) {
+int lp_reinvert(lp_problem* p) try {
   if (!p) return fail(LP_ERR_ARG, "p is NULL");
   int rc = read_ctrl(p);  // the structural count and the list D of the current basis
   if (rc != LP_OK) return rc;
@@ -912,6 +978,8 @@ int lp_reinvert(lp_problem* p) {
   if (rc != LP_OK) return rc;
   if ((rc = read_ctrl(p)) != LP_OK) return rc;
   return collect_reinv_time(p);
+} catch (...) {
+  return host_exception();
 }
 
 void lp_destroy(lp_problem* p) { release(p); }
@@ -927,9 +995,13 @@ const char* lp_error_string(int code) {
     case LP_ERR_DEVICE: base = "device error"; break;
     case LP_ERR_STATE: base = "invalid state"; break;
   }
-  text = base;
-  if (code != LP_OK && code == g_code && !g_msg.empty()) text += ": " + g_msg;
-  return text.c_str();
+  try {
+    text = base;
+    if (code != LP_OK && code == g_code && !g_msg.empty()) text += ": " + g_msg;
+    return text.c_str();
+  } catch (...) {  // no memory for the detail: the code's own text
+    return base;
+  }
 }
 
 }  // extern "C"

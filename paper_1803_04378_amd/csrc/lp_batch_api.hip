@@ -18,8 +18,10 @@
 using namespace lpgpu;
 
 namespace lpgpu {
-// Shared with lp_api.hip: error recording for lp_error_string.
+// Shared with lp_api.hip: error recording for lp_error_string, and the conversion of a
+// host exception (inside a catch-all handler) into LP_ERR_NOMEM.
 int record_error(int code, const std::string& msg);
+int host_exception() noexcept;
 }  // namespace lpgpu
 
 namespace {
@@ -28,6 +30,17 @@ int fail(int code, const std::string& msg) { return lpgpu::record_error(code, ms
 
 int fail_hip(hipError_t e, const char* what) {
   return fail(e == hipErrorOutOfMemory ? LP_ERR_NOMEM : LP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Runs f when the scope ends, by a return or by an exception.
+template <class F>
+struct ScopeExit {
+  F f;
+  ~ScopeExit() { f(); }
+};
+template <class F>
+ScopeExit<F> on_scope_exit(F f) {
+  return {f};
 }
 
 #define HIP_TRY(expr, what)                            \
@@ -282,7 +295,7 @@ int tune_binv(lp_batch* p) {
 extern "C" {
 
 int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32_t* n, const double* const* A,
-                    const double* const* b, const double* const* c, const lp_options* opt) {
+                    const double* const* b, const double* const* c, const lp_options* opt) try {
   if (!out) return fail(LP_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (count <= 0 || !m || !n || !A || !b || !c) return fail(LP_ERR_ARG, "empty batch or NULL array");
@@ -320,8 +333,12 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
   if (!p) return fail(LP_ERR_NOMEM, "host allocation failed");
   auto bail = [&](int code) {
     release(p);
+    p = nullptr;
     return code;
   };
+  const auto drop = on_scope_exit([&] {  // an exception before the hand-over releases it too
+    if (p) release(p);
+  });
   p->device = dev;
   p->opt = o;
   p->count = count;
@@ -479,7 +496,13 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
         for (int32_t i = i0 + tno; i < i1; i += nthreads) pack(i, base + ((size_t)p->lps[i].offA - run_start));
       };
       std::vector<std::thread> pool;
-      for (int tno = 1; tno < nthreads && i0 + tno < i1; ++tno) pool.emplace_back(work, tno);
+      int started = 1;
+      try {
+        pool.reserve(nthreads);
+        for (; started < nthreads && i0 + started < i1; ++started) pool.emplace_back(work, started);
+      } catch (...) {  // a thread that could not start: this one packs its share
+      }
+      for (int tno = started; tno < nthreads && i0 + tno < i1; ++tno) work(tno);
       work(0);
       for (auto& th : pool) th.join();
       used = sz;
@@ -496,10 +519,13 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
     if (e != hipSuccess) return bail(fail_hip(e, "uploading the batch"));
   }
   *out = p;
+  p = nullptr;  // handed over
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
-int lp_batch_solve(lp_batch* p) {
+int lp_batch_solve(lp_batch* p) try {
   if (!p) return fail(LP_ERR_ARG, "p is NULL");
   int rc;
   if (p->small_m < 0 && p->bucket_narrow.empty()) {
@@ -516,9 +542,11 @@ int lp_batch_solve(lp_batch* p) {
   p->solve_ms = ms;
   p->solved = true;
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
-int lp_batch_results(const lp_batch* pc, int32_t* status, double* objective, int64_t* iterations) {
+int lp_batch_results(const lp_batch* pc, int32_t* status, double* objective, int64_t* iterations) try {
   if (!pc) return fail(LP_ERR_ARG, "p is NULL");
   if (!pc->solved) return fail(LP_ERR_STATE, "lp_batch_solve has not run");
   lp_batch* p = const_cast<lp_batch*>(pc);
@@ -547,10 +575,12 @@ int lp_batch_results(const lp_batch* pc, int32_t* status, double* objective, int
     }
   }
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
 int lp_batch_get(const lp_batch* pc, int32_t i, double* x, int32_t* basis, int32_t* entering, int32_t* leaving_row,
-                 int32_t* flags, int64_t capacity, int64_t* count) {
+                 int32_t* flags, int64_t capacity, int64_t* count) try {
   if (!pc) return fail(LP_ERR_ARG, "p is NULL");
   if (i < 0 || i >= pc->count) return fail(LP_ERR_ARG, "LP index out of range");
   if (!pc->solved) return fail(LP_ERR_STATE, "lp_batch_solve has not run");
@@ -578,9 +608,11 @@ int lp_batch_get(const lp_batch* pc, int32_t i, double* x, int32_t* basis, int32
       HIP_TRY(hipMemcpy(dst[a], src[a], sizeof(int32_t) * k, hipMemcpyDeviceToHost), "reading the pivot log");
   if (count) *count = have;
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
-int lp_batch_get_stats(const lp_batch* p, lp_batch_stats* s) {
+int lp_batch_get_stats(const lp_batch* p, lp_batch_stats* s) try {
   if (!p || !s) return fail(LP_ERR_ARG, "NULL argument");
   std::memset(s, 0, sizeof(*s));
   s->count = p->count;
@@ -598,13 +630,15 @@ int lp_batch_get_stats(const lp_batch* p, lp_batch_stats* s) {
     if (p->bucket_narrow[bk] == 1) mask |= (int64_t)1 << bk;
   s->narrow_bucket_mask = mask;
   return LP_OK;
+} catch (...) {
+  return host_exception();
 }
 
 void lp_batch_destroy(lp_batch* p) { release(p); }
 
 int lp_solve_batch(int32_t count, const int32_t* m, const int32_t* n, const double* const* A, const double* const* b,
                    const double* const* c, const lp_options* opt, int32_t* status, double* objective,
-                   int64_t* iterations) {
+                   int64_t* iterations) try {
   lp_batch* p = nullptr;
   int rc = lp_batch_create(&p, count, m, n, A, b, c, opt);
   if (rc != LP_OK) return rc;
@@ -612,6 +646,8 @@ int lp_solve_batch(int32_t count, const int32_t* m, const int32_t* n, const doub
   if (rc == LP_OK) rc = lp_batch_results(p, status, objective, iterations);
   lp_batch_destroy(p);
   return rc;
+} catch (...) {
+  return host_exception();
 }
 
 }  // extern "C"

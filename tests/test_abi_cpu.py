@@ -157,3 +157,38 @@ def test_batch_argument_errors_need_no_gpu():
     assert L.lp_batch_solve(None) == binding.LP_ERR_ARG
     assert L.lp_reinvert(None) == binding.LP_ERR_ARG
     L.lp_batch_destroy(None)
+
+
+_HUGE_CREATE = r"""
+import ctypes as C, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from paper_1803_04378_amd import binding
+L = binding.lib()
+m, n = binding.LP_MAX_ROWS, 500_000_000  # the normal form alone needs m * n doubles (39 TB)
+b, A, c = np.ones(m), np.ones(4), np.ones(4)
+dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+h = C.c_void_p()
+rc = L.lp_create_general(C.byref(h), m, n, dp(A), dp(b), dp(c), None, None)
+print(rc, bool(h.value), L.lp_error_string(rc).decode())
+"""
+
+
+def test_host_allocation_failure_is_an_error_code():
+    """A host allocation that fails inside an entry point comes back as LP_ERR_NOMEM, not as
+    an exception unwinding through the C ABI (which aborts the process).  Run in a child
+    process so that a regression cannot take the test runner down."""
+    import subprocess
+    import sys
+    try:
+        mode = open("/proc/sys/vm/overcommit_memory").read().strip()
+    except OSError:
+        mode = "?"
+    if mode not in ("0", "2"):
+        pytest.skip("the kernel may grant a 39 TB allocation (overcommit_memory = %s)" % mode)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", _HUGE_CREATE, root], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    rc, handed, msg = out.stdout.strip().split(" ", 2)
+    assert int(rc) == binding.LP_ERR_NOMEM and handed == "False"
+    assert "host allocation failed" in msg
