@@ -71,6 +71,23 @@ int fail_hip(hipError_t e, const char* what) {
   return fail(LP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Transfers between pageable host memory and the device: the stream is drained, then a
+// blocking copy runs, so the copy follows the stream's earlier work and is complete on
+// return, whatever kind of stream the caller gave.  (Pinned control-block traffic and
+// device-to-device copies stay asynchronous on the stream.)
+hipError_t pageable_copy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess && bytes > 0) e = hipMemcpy(dst, src, bytes, kind);
+  return e;
+}
+
+hipError_t pageable_copy_2d(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t height,
+                            hipMemcpyKind kind, hipStream_t s) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess && width > 0 && height > 0) e = hipMemcpy2D(dst, dpitch, src, spitch, width, height, kind);
+  return e;
+}
+
 #define HIP_TRY(expr, what)                   \
   do {                                        \
     hipError_t e_ = (expr);                   \
@@ -542,10 +559,9 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
     if ((e = launch_check_finite(A, (int64_t)m * n, bound, flag, s)) != hipSuccess)
       return bail(fail_hip(e, "validating A"));
     int32_t hflag = 0;
-    if ((e = hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(hb.data(), b, sizeof(double) * m, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (n > 0 && (e = hipMemcpyAsync(hc.data(), c, sizeof(double) * n, hipMemcpyDeviceToHost, s)) != hipSuccess) ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
+    if ((e = pageable_copy(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = pageable_copy(hb.data(), b, sizeof(double) * m, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = pageable_copy(hc.data(), c, sizeof(double) * n, hipMemcpyDeviceToHost, s)) != hipSuccess)
       return bail(fail_hip(e, "reading the LP data"));
     dfree(p, flag);
     if (hflag)
@@ -559,12 +575,17 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
       if (!std::isfinite(hc[j])) return bail(fail(LP_ERR_ARG, "c contains a non-finite value"));
   }
   if (n > 0) {
-    e = hipMemcpy2DAsync(dA, sizeof(double) * ld, A, sizeof(double) * m, sizeof(double) * m, n, kind, s);
+    // (one contiguous copy when there is no padding, ld = m)
+    e = device_inputs ? hipMemcpy2DAsync(dA, sizeof(double) * ld, A, sizeof(double) * m, sizeof(double) * m, n, kind, s)
+        : ld == m     ? pageable_copy(dA, A, sizeof(double) * (size_t)m * n, kind, s)
+                      : pageable_copy_2d(dA, sizeof(double) * ld, A, sizeof(double) * m, sizeof(double) * m, n, kind, s);
     if (e != hipSuccess) return bail(fail_hip(e, "copying A"));
-    e = hipMemcpyAsync(p->c0, c, sizeof(double) * n, kind, s);
+    e = device_inputs ? hipMemcpyAsync(p->c0, c, sizeof(double) * n, kind, s)
+                      : pageable_copy(p->c0, c, sizeof(double) * n, kind, s);
     if (e != hipSuccess) return bail(fail_hip(e, "copying c"));
   }
-  e = hipMemcpyAsync(p->b0, b, sizeof(double) * m, kind, s);
+  e = device_inputs ? hipMemcpyAsync(p->b0, b, sizeof(double) * m, kind, s)
+                    : pageable_copy(p->b0, b, sizeof(double) * m, kind, s);
   if (e != hipSuccess) return bail(fail_hip(e, "copying b"));
   if (mixed) {
     // FP32 copy of A' with the same padding (round to nearest).
@@ -612,9 +633,8 @@ int phase_switch(lp_problem* p) {
     return rc;
   }
   std::vector<int32_t> bas(m);
-  HIP_TRY(hipMemcpyAsync(bas.data(), p->d.basis, sizeof(int32_t) * m, hipMemcpyDeviceToHost, p->stream),
+  HIP_TRY(pageable_copy(bas.data(), p->d.basis, sizeof(int32_t) * m, hipMemcpyDeviceToHost, p->stream),
           "reading the basis");
-  HIP_TRY(hipStreamSynchronize(p->stream), "reading the basis");
   for (int r = 0; r < m; ++r) {
     // A drive-out changes only its own row of the basis: this list stays valid.
     if (bas[r] < n || !p->art_h[bas[r] - n]) continue;
@@ -737,8 +757,8 @@ int lp_create_general(lp_problem** out, int32_t m, int32_t n, const double* A_co
         (e = dalloc(p, &p->tab_j, (size_t)g)) != hipSuccess || (e = dalloc(p, &p->drive, 4)) != hipSuccess)
       return bail(fail_hip(e, "allocating the two-phase state"));
     for (int32_t i = 0; i < m; ++i) c1[(size_t)n2 + i] = art[i] ? 1.0 : 0.0;
-    if ((e = hipMemcpyAsync(dart, art.data(), (size_t)m, hipMemcpyHostToDevice, p->stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(p->chat1, c1.data(), sizeof(double) * N, hipMemcpyHostToDevice, p->stream)) !=
+    if ((e = pageable_copy(dart, art.data(), (size_t)m, hipMemcpyHostToDevice, p->stream)) != hipSuccess ||
+        (e = pageable_copy(p->chat1, c1.data(), sizeof(double) * N, hipMemcpyHostToDevice, p->stream)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(p->chat2, p->d.chat, sizeof(double) * N, hipMemcpyDeviceToDevice, p->stream)) !=
             hipSuccess)
@@ -881,12 +901,11 @@ int lp_get_solution(const lp_problem* pc, double* objective, double* x, double* 
   const int m = p->m, n = p->n_user;
   std::vector<double> xB(m), W(m);
   std::vector<int32_t> bas(m);
-  HIP_TRY(hipMemcpyAsync(xB.data(), p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
+  HIP_TRY(pageable_copy(xB.data(), p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
   const double* dW = p->h_ctrl->wcur ? p->d.W1 : p->d.W0;
-  HIP_TRY(hipMemcpyAsync(W.data(), dW, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading W");
-  HIP_TRY(hipMemcpyAsync(bas.data(), p->d.basis, sizeof(int32_t) * m, hipMemcpyDeviceToHost, p->stream),
+  HIP_TRY(pageable_copy(W.data(), dW, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading W");
+  HIP_TRY(pageable_copy(bas.data(), p->d.basis, sizeof(int32_t) * m, hipMemcpyDeviceToHost, p->stream),
           "reading the basis");
-  HIP_TRY(hipStreamSynchronize(p->stream), "reading the solution");
   std::vector<int32_t> row_of(n, -1);
   for (int i = 0; i < m; ++i)
     if (bas[i] < n) row_of[bas[i]] = i;
@@ -919,9 +938,8 @@ int lp_get_pivots(const lp_problem* pc, int32_t* entering, int32_t* leaving_row,
   int32_t* src[4] = {p->d.log_enter, p->d.log_row, p->d.log_leave, p->d.log_flags};
   for (int a = 0; a < 4; ++a)
     if (dst[a] && k > 0)
-      HIP_TRY(hipMemcpyAsync(dst[a], src[a], sizeof(int32_t) * k, hipMemcpyDeviceToHost, p->stream),
+      HIP_TRY(pageable_copy(dst[a], src[a], sizeof(int32_t) * k, hipMemcpyDeviceToHost, p->stream),
               "reading the pivot log");
-  HIP_TRY(hipStreamSynchronize(p->stream), "reading the pivot log");
   if (count) *count = have;
   return LP_OK;
 } catch (...) {
@@ -934,13 +952,14 @@ int lp_get_tableau(const lp_problem* pc, double* Binv, double* xB, double* W, do
   const int m = p->m;
   if (p->h_ctrl->r >= 0) return fail(LP_ERR_STATE, "a pivot is pending; call lp_solve to completion first");
   if (Binv)
-    HIP_TRY(hipMemcpy2DAsync(Binv, sizeof(double) * m, p->d.Binv, sizeof(double) * p->ld, sizeof(double) * m, m,
-                             hipMemcpyDeviceToHost, p->stream),
+    HIP_TRY(p->ld == m ? pageable_copy(Binv, p->d.Binv, sizeof(double) * (size_t)m * m, hipMemcpyDeviceToHost, p->stream)
+                       : pageable_copy_2d(Binv, sizeof(double) * m, p->d.Binv, sizeof(double) * p->ld,
+                                          sizeof(double) * m, m, hipMemcpyDeviceToHost, p->stream),
             "reading B^-1");
-  if (xB) HIP_TRY(hipMemcpyAsync(xB, p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
+  if (xB) HIP_TRY(pageable_copy(xB, p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
   if (W)
-    HIP_TRY(hipMemcpyAsync(W, p->h_ctrl->wcur ? p->d.W1 : p->d.W0, sizeof(double) * m, hipMemcpyDeviceToHost,
-                           p->stream),
+    HIP_TRY(pageable_copy(W, p->h_ctrl->wcur ? p->d.W1 : p->d.W0, sizeof(double) * m, hipMemcpyDeviceToHost,
+                          p->stream),
             "reading W");
   HIP_TRY(hipStreamSynchronize(p->stream), "reading the tableau");
   if (z) *z = p->h_ctrl->z;

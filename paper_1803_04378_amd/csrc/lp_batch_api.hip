@@ -43,6 +43,14 @@ ScopeExit<F> on_scope_exit(F f) {
   return {f};
 }
 
+// Transfers from pageable host memory: the stream is drained, then a blocking copy runs, so
+// the copy follows the stream's earlier work and is complete on return.
+hipError_t pageable_copy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess && bytes > 0) e = hipMemcpy(dst, src, bytes, kind);
+  return e;
+}
+
 #define HIP_TRY(expr, what)                            \
   do {                                                 \
     hipError_t e_ = (expr);                            \
@@ -155,9 +163,9 @@ int run_items(lp_batch* p, const std::vector<int4>& items, float* ms, bool binv_
     if (ms) *ms = 0.f;
     return LP_OK;
   }
-  HIP_TRY(hipMemcpyAsync(p->d_lps, p->lps.data(), sizeof(BatchLP) * p->lps.size(), hipMemcpyHostToDevice, p->stream),
+  HIP_TRY(pageable_copy(p->d_lps, p->lps.data(), sizeof(BatchLP) * p->lps.size(), hipMemcpyHostToDevice, p->stream),
           "uploading the batch table");
-  HIP_TRY(hipMemcpyAsync(p->d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, p->stream),
+  HIP_TRY(pageable_copy(p->d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, p->stream),
           "uploading work items");
   HIP_TRY(hipMemsetAsync(p->d.queue, 0, sizeof(int32_t), p->stream), "clearing the work queue");
   BatchDev d = p->d;
