@@ -236,3 +236,137 @@ def transportation_lp(seed, S, D):
             A[s, s * D + d] = 1.0
             A[S + d, s * D + d] = 1.0
     return A, np.concatenate([supply, demand]), cost.ravel(), np.full(S + D, 2, dtype=np.int32)
+
+
+# ---- the tie rules, replayed from the basis alone ----
+
+def _band(values, target, tol):
+    """Indices with |values - target| <= tol, and whether some other value sits close
+    enough (within 100 tol) that the two cannot be told apart at this precision."""
+    dist = np.abs(values - target)
+    inside = dist <= tol
+    near = (dist > tol) & (dist <= 100 * tol)
+    return np.flatnonzero(inside), bool(near.any())
+
+
+def replay_strict(A, b, c, enter, row, flags, sense="max", tenure=5, leaving_list=True, eps_d=1e-9, eps_p=1e-9,
+                  eps_t=1e-9):
+    """Replays a pivot log from the slack basis with numpy and checks every decision,
+    ties included, against the stated rule:
+
+    - entering (Step 4 with the entering mask): among the nonbasic variables with
+      d_j < -eps_d (those the mask allows, else all of them: aspiration), the smallest
+      d_j; equal smallest values go to the lowest variable index;
+    - leaving (Step 6 with the tabu list of Sections 2.2/3.4): rows with alpha_i > eps_p
+      are candidates, theta is their smallest ratio max(x_i, 0)/alpha_i, and a row is
+      tied when max(x_i, 0) - alpha_i theta <= eps_t; with one tied row it leaves; with
+      several, the lowest one whose basic variable is not in the entering variable's
+      list L[q] leaves, or, if L[q] holds all of them, L[q] is emptied and the lowest
+      tied row leaves; either way the leaving variable is then appended to L[q];
+    - the logged TIE and LCLEAR flags match.
+
+    L is simulated here from the log, independently of any solver.  A decision whose
+    inputs lie so close to a threshold that numpy's rounding could change it is not
+    judged (the log's own choice is followed there); the number of decisions judged is
+    returned with the final basis."""
+    A = np.asarray(A, float)
+    m, n = A.shape
+    M = full_matrix(A)
+    chat = np.concatenate([(-1.0 if sense == "max" else 1.0) * np.asarray(c, float), np.zeros(m)])
+    basis = list(range(n, n + m))
+    tabu_until = np.full(n + m, -1)
+    L = {}
+    judged = 0
+    scale_b = 1.0 + float(np.abs(b).max())
+    for t, (q, r, f) in enumerate(zip(enter, row, flags)):
+        q, r, f = int(q), int(r), int(f)
+        B = M[:, basis]
+        pi = np.linalg.solve(B.T, chat[basis])
+        d = chat - M.T @ pi
+        nonbasic = np.ones(n + m, bool)
+        nonbasic[basis] = False
+        dtol = 1e-10 * (1.0 + np.abs(chat).max())
+        improving = nonbasic & (d < -eps_d)
+        allowed = improving & (tabu_until < t)
+        pool = np.flatnonzero(allowed if allowed.any() else improving)
+        assert q in pool, f"pivot {t}: entering {q} not eligible"
+        at_min, close = _band(d[pool], d[pool].min(), dtol)
+        if not close:
+            assert q == pool[at_min].min(), f"pivot {t}: entering {q}, rule gives {pool[at_min].min()}"
+            judged += 1
+        alpha = np.linalg.solve(B, M[:, q])
+        xb = np.maximum(np.linalg.solve(B, b), 0.0)
+        cand = alpha > eps_p
+        assert cand[r], f"pivot {t}: row {r} is not a candidate"
+        ratios = np.where(cand, xb / np.where(cand, alpha, 1.0), np.inf)
+        th = ratios.min()
+        level = np.where(cand, xb - alpha * th, np.inf)
+        xtol = min(1e-12 * scale_b, 0.5 * eps_t)
+        tied = np.flatnonzero(level <= eps_t + xtol)
+        sure = np.flatnonzero(level <= eps_t - xtol)
+        lst = L.setdefault(q, [])
+        if len(tied) == len(sure):
+            free = [i for i in tied if not (leaving_list and basis[i] in lst)]
+            is_tie = len(tied) >= 2
+            clear = is_tie and leaving_list and not free
+            want = int(tied.min()) if (not is_tie or not leaving_list or clear) else int(min(free))
+            assert r == want, f"pivot {t}: leaving row {r}, rule gives {want} (tied rows {list(tied)})"
+            assert bool(f & 2) == is_tie, f"pivot {t}: tie flag {f & 2} but {len(tied)} tied rows"
+            assert bool(f & 8) == clear, f"pivot {t}: list-clear flag {f & 8}, rule says {clear}"
+            judged += 1
+        else:  # follow the log
+            is_tie, clear = bool(f & 2), bool(f & 8)
+        if is_tie and leaving_list:
+            if clear:
+                lst.clear()
+            lst.append(basis[r])
+        if tenure > 0:
+            tabu_until[basis[r]] = t + tenure
+        basis[r] = q
+    return basis, judged
+
+
+def general_normal_form(A, b, row_type):
+    """The form the two-phase start solves: rows with b_i < 0 negated (<= and >= swap),
+    a surplus column -e_i for each >= row after the caller's n columns (ascending i),
+    then the unit column of every row (a slack for <= rows, an artificial variable for
+    >= and = rows).  Returns (M, b2, n2, art) with M of shape m x (n2 + m)."""
+    A = np.asarray(A, float)
+    m, n = A.shape
+    rt = np.asarray(row_type)
+    sg = np.where(np.asarray(b) < 0, -1.0, 1.0)
+    rt2 = np.where((sg < 0) & (rt == 0), 1, np.where((sg < 0) & (rt == 1), 0, rt))
+    ge = np.flatnonzero(rt2 == 1)
+    sur = np.zeros((m, len(ge)))
+    sur[ge, np.arange(len(ge))] = -1.0
+    M = np.hstack([sg[:, None] * A, sur, np.eye(m)])
+    return M, sg * np.asarray(b, float), n + len(ge), rt2 != 0
+
+
+def check_drive_outs(A, b, row_type, enter, row, flags, eps_p=1e-9):
+    """Every pivot flagged DRIVEOUT (16), replayed from the unit basis: the entering column
+    has the largest |entry| of row r of the tableau, B^-1 M[:, j], over the nonbasic
+    columns that are not artificial variables (entries above eps_p only), the lowest such
+    column among equal magnitudes.  Returns the number of drive-outs judged."""
+    M, b2, n2, art = general_normal_form(A, b, row_type)
+    m = M.shape[0]
+    basis = list(range(n2, n2 + m))
+    judged = 0
+    for t, (q, r, f) in enumerate(zip(enter, row, flags)):
+        q, r = int(q), int(r)
+        if f & 16:
+            B = M[:, basis]
+            tr = np.linalg.solve(B.T, np.eye(m)[r]) @ M  # row r of B^-1 M
+            elig = np.ones(n2 + m, bool)
+            elig[basis] = False
+            elig[n2:] &= ~art
+            mag = np.where(elig, np.abs(tr), 0.0)
+            ok = np.flatnonzero(mag > eps_p)
+            assert q in ok, f"pivot {t}: drive-out column {q} has entry {tr[q]}"
+            top = mag[ok].max()
+            at_top, close = _band(mag[ok], top, 1e-12 * (1.0 + top))
+            if not close:
+                assert q == ok[at_top].min(), f"pivot {t}: drive-out column {q}, rule gives {ok[at_top].min()}"
+                judged += 1
+        basis[r] = q
+    return judged

@@ -13,7 +13,8 @@ import pytest
 import lpgen
 import oracle
 from test_oracle_pins import _embedded
-from lputil import assert_kkt, assert_kkt_general, brute_force, highs_general, replay_check, small_general_lps
+from lputil import (assert_kkt, assert_kkt_general, brute_force, check_drive_outs, highs_general, replay_check,
+                    replay_strict, small_general_lps)
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "simplex_oracle.c")
 
@@ -45,14 +46,25 @@ MUTANTS = {
                            "if (cb != 0.0) s = fma(cb, p->Binv[(size_t)j * m + i], s);"),
     "no_phase2_costs": ("memcpy(p->chat, p->chat2, sizeof(double) * N);", "(void)0;"),
     "dual_ignores_row_sign": ("y[i] = s * p->W[i] * (p->rsign ? p->rsign[i] : 1.0);", "y[i] = s * p->W[i];"),
+    # tie rules (Sections 2.2/3.4 and the readings of Step 4 and of the phase switch)
+    "no_lclear": ("if (r_free < 0) { p->L_len[q] = 0; flags |= FLAG_LCLEAR; p->n_lclear++; }",
+                  "if (r_free < 0) { flags |= FLAG_LCLEAR; p->n_lclear++; }"),
+    "entering_tie_highest": [("if (q_all < 0 || p->d[j] < p->d[q_all]) q_all = j;",
+                              "if (q_all < 0 || p->d[j] <= p->d[q_all]) q_all = j;"),
+                             ("(q_free < 0 || p->d[j] < p->d[q_free])", "(q_free < 0 || p->d[j] <= p->d[q_free])")],
+    "driveout_first_not_largest": ("if (fabs(t) > p->eps_p && fabs(t) > fabs(bt)) { best = j; bt = t; }",
+                                   "if (fabs(t) > p->eps_p && best < 0) { best = j; bt = t; }"),
 }
 
 
-def _build(tmp_path, name, old, new):
+def _build(tmp_path, name, subs):
+    """subs: one (old, new) pair, or a list of them applied together."""
     src = open(SRC).read()
-    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    for old, new in ([subs] if isinstance(subs, tuple) else subs):
+        assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+        src = src.replace(old, new)
     path = tmp_path / f"{name}.c"
-    path.write_text(src.replace(old, new))
+    path.write_text(src)
     so = tmp_path / f"lib{name}.so"
     subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", str(so), str(path), "-lm"])
     return str(so)
@@ -85,6 +97,21 @@ def _pins_pass(lib_path):
                 return False
             assert_kkt(A, b, c, r.x, r.y)
             replay_check(A, b, c, r.enter, r.row)
+        # entering ties (equal reduced costs) go to the lowest index
+        r = oracle.solve(np.array([[1.0, 1.0]]), np.array([2.0]), np.array([3.0, 3.0]), lib_path=lib_path)
+        if list(r.enter) != [0]:
+            return False
+        A0, b0, c0 = lpgen.dense_lp(3, 30, 20)
+        Ad, cd = np.hstack([A0, A0]), np.concatenate([c0, c0])
+        r = oracle.solve(Ad, b0, cd, lib_path=lib_path)
+        replay_strict(Ad, b0, cd, r.enter, r.row, r.flags)
+        # the leaving-side tabu list on degenerate LPs where it decides pivots
+        for m, seed in ((150, 9), (150, 8)):
+            A, b, c = lpgen.degenerate_lp(seed, m, 2 * m)
+            r = oracle.solve(A, b, c, lib_path=lib_path)
+            if r.status != oracle.OPTIMAL:
+                return False
+            replay_strict(A, b, c, r.enter, r.row, r.flags)
         for name in ("beale", "chvatal"):
             Ae, be, ce = _embedded(name)
             r = oracle.solve(Ae, be, ce, lib_path=lib_path, max_iter=2000)
@@ -113,6 +140,7 @@ def _pins_pass(lib_path):
             return False
         for A, b, c, rt in small_general_lps(3, 250):
             r = oracle.solve(A, b, c, row_type=rt, max_iter=500, lib_path=lib_path)
+            check_drive_outs(A, b, rt, r.enter, r.row, r.flags)
             ref, obj = highs_general(A, b, c, rt)
             if r.status_name != ref:
                 return False
@@ -139,5 +167,4 @@ def test_unmutated_source_passes(tmp_path):
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_is_caught(tmp_path, name):
-    old, new = MUTANTS[name]
-    assert not _pins_pass(_build(tmp_path, name, old, new)), f"pins did not catch mutant {name}"
+    assert not _pins_pass(_build(tmp_path, name, MUTANTS[name])), f"pins did not catch mutant {name}"

@@ -6,6 +6,9 @@
 - the pivot rule of Steps 3-6: every logged pivot replayed with dense linear algebra;
 - the tableau of Figure 1 after every pivot: B^-1, W, x_B and z recomputed from the basis;
 - anti-cycling (Sections 2.2, 3.4): two textbook LPs that cycle under plain Dantzig;
+- the tie rules: hand-derived pivots for equal reduced costs, and a replay that simulates
+  the leaving-side tabu list on its own and checks every entering and leaving choice,
+  ties and list clears included, on degenerate LPs where those rules decide the pivots;
 - special cases: unbounded column (Step 5), already optimal (Step 4), rejected input.
 """
 import json
@@ -16,7 +19,7 @@ import pytest
 
 import lpgen
 import oracle
-from lputil import assert_kkt, basis_sets, brute_force, full_matrix, replay_check
+from lputil import assert_kkt, basis_sets, brute_force, full_matrix, replay_check, replay_strict
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "cycling_lps.json")
 
@@ -324,3 +327,48 @@ def test_tie_tolerance_is_in_x_units():
     o.run(1)
     _, xB, _, _ = o.state()
     assert xB.min() >= 0.0
+
+
+def test_entering_tie_goes_to_lowest_index():
+    """Equal reduced costs: the lowest variable index enters (reading of Step 4).
+
+    max 3x0 + 3x1 s.t. x0 + x1 <= 2 from the slack basis: W = 0, so d = (-3, -3), bit for
+    bit equal.  x0 enters, its only row (alpha = 1, ratio 2) leaves with slack variable 2,
+    and then W = -3 gives d_1 = -3 - (-3)(1) = 0 and d_2 = 0 - (-3) = 3: optimal at
+    x = (2, 0), objective 6.  Taking the higher index would end at x = (0, 2) instead."""
+    r = oracle.solve(np.array([[1.0, 1.0]]), np.array([2.0]), np.array([3.0, 3.0]))
+    assert r.status == oracle.OPTIMAL
+    assert list(r.enter) == [0] and list(r.row) == [0] and list(r.leave) == [2]
+    assert np.array_equal(r.x, [2.0, 0.0]) and r.objective == 6.0
+    # A dense LP whose 20 columns appear twice (j and j + 20 identical, equal costs): the two
+    # copies always have equal reduced costs, so only the lower copy (or a slack, >= 40) enters.
+    A0, b0, c0 = lpgen.dense_lp(3, 30, 20)
+    A, c = np.hstack([A0, A0]), np.concatenate([c0, c0])
+    r = oracle.solve(A, b0, c)
+    assert r.status == oracle.OPTIMAL and r.iterations > 0
+    assert all(q < 20 or q >= 40 for q in r.enter)
+    replay_strict(A, b0, c, r.enter, r.row, r.flags)
+
+
+# Degenerate LPs on which the leaving-side tabu list decides pivots: each has a tie whose
+# tied rows' leaving variables are all in the entering variable's list (a list clear), and
+# a later tie that the cleared list decides (keeping the stale entries picks another row).
+TIE_LPS = [(150, 9, False), (150, 8, False), (200, 15, True)]
+
+
+@pytest.mark.parametrize("m,seed,budget", TIE_LPS)
+def test_tie_rules_replayed_on_degenerate_lps(m, seed, budget):
+    A, b, c = lpgen.degenerate_lp(seed, m, 2 * m, budget_row=budget)
+    r = oracle.solve(A, b, c)
+    assert r.status == oracle.OPTIMAL
+    assert r.counts["lclear"] >= 1 and r.counts["tie"] >= 20
+    _, judged = replay_strict(A, b, c, r.enter, r.row, r.flags)
+    assert judged >= 2 * r.iterations - 4  # nearly every decision is far from a threshold
+
+
+@pytest.mark.parametrize("case", ["dense0", "dense1", "beale", "chvatal"])
+def test_tie_rules_replayed(case):
+    A, b, c = lpgen.dense_lp(int(case[-1]), 64, 128) if case.startswith("dense") else _embedded(case)
+    r = oracle.solve(A, b, c)
+    assert r.status == oracle.OPTIMAL
+    replay_strict(A, b, c, r.enter, r.row, r.flags)

@@ -9,7 +9,7 @@ import pytest
 
 import lpgen
 import oracle
-from lputil import (assert_kkt_general, brute_force_general, general_standard, highs_general,
+from lputil import (assert_kkt_general, brute_force_general, check_drive_outs, general_standard, highs_general,
                     small_general_lps)
 
 LE, GE, EQ = oracle.ROW_LE, oracle.ROW_GE, oracle.ROW_EQ
@@ -176,3 +176,34 @@ def test_one_equality_row_closed_form():
     r = oracle.solve(a[None, :], np.array([4.0]), c, row_type=[EQ])
     assert r.status == oracle.OPTIMAL
     assert abs(r.objective - 4.0 * np.max(c / a)) <= 1e-12 * r.objective
+
+
+@pytest.mark.parametrize("coef,want", [((-1.0, -3.0), 1), ((-3.0, -3.0), 0)])
+def test_drive_out_takes_the_largest_entry(coef, want):
+    """max x0 + x1 + 2x2 s.t. a0 x0 + a1 x1 = 0 (row 0), x0 + x1 + x2 <= 4 (row 1), with
+    a0, a1 < 0.  Phase 1 starts from the artificial variable of row 0 (variable 3, the
+    columns being x0, x1, x2) at level 0: its reduced costs are d_j = -a_j > 0, so phase 1
+    is optimal at once with the artificial variable basic at zero.  Row 0 of the tableau is
+    (a0, a1, 0, ., 0): the drive-out enters the column of the largest |entry|, x1 for
+    (-1, -3) and, on equal magnitudes (-3, -3), the lowest column x0, with step 0.
+    Phase 2 then lets x2 replace the slack of row 1 (theta = 4): x = (0, 0, 4),
+    objective 8, whichever column was driven in."""
+    A = np.array([[coef[0], coef[1], 0.0], [1.0, 1.0, 1.0]])
+    r = oracle.solve(A, np.array([0.0, 4.0]), np.array([1.0, 1.0, 2.0]), row_type=[EQ, LE])
+    assert r.status == oracle.OPTIMAL
+    assert r.flags[0] & oracle.FLAG_DRIVEOUT
+    assert r.enter[0] == want and r.row[0] == 0 and r.leave[0] == 3
+    assert list(r.enter[1:]) == [2] and list(r.row[1:]) == [1]
+    np.testing.assert_allclose(r.x, [0.0, 0.0, 4.0], rtol=0, atol=0)
+    assert r.objective == 8.0
+
+
+def test_drive_outs_replayed_on_small_lps():
+    """Every drive-out of the tiny degenerate law, replayed from the unit basis with numpy:
+    the entering column has the largest |entry| of its tableau row (lowest column on equal
+    magnitudes), among the nonbasic columns that are not artificial variables."""
+    judged = 0
+    for A, b, c, rt in small_general_lps(3, 400):
+        r = oracle.solve(A, b, c, row_type=rt, max_iter=500)
+        judged += check_drive_outs(A, b, rt, r.enter, r.row, r.flags)
+    assert judged >= 20
