@@ -36,15 +36,15 @@ def _log(msg):
 
 
 def run_steps(lp, k):
-    """Exactly k pivots from the current state; an LP that finishes early restarts from the
-    slack basis (inside the timed region)."""
+    """Exactly k pivots from the current state (lp_iterate: no iteration runs past them); an
+    LP that finishes early restarts from the slack basis (inside the timed region)."""
     remaining = k
     while remaining > 0:
         cur = lp.stats()["iterations"]
-        st = lp.solve(cur + remaining)
+        st = lp.iterate(remaining)
         done = lp.stats()["iterations"] - cur
         remaining -= done
-        if remaining > 0 and st != 3:  # finished before the target: start over
+        if remaining > 0 and st != 0:  # finished before the target: start over
             lp.reset()
 
 
@@ -267,16 +267,33 @@ def batch_leg(lpg, count, serial_sample):
                 serial_lps_per_s=round(1.0 / serial, 1), speedup_vs_serial=round(lps_per_s * serial, 1))
 
 
-def cpu_baseline(A, b, c, pivots):
+def cpu_baseline(A, b, c, pivots, budget_s=20.0):
+    """The oracle on the host's cores: its -fopenmp build (bit-identical results) on every
+    core OpenMP is given, over the whole solve or as many 25-pivot chunks as fit in
+    budget_s, and the sequential build on the first `pivots` pivots."""
     import oracle
-    o = oracle.Oracle(A, b, c)
+    lib = oracle.omp_lib(0)
+    cores = oracle.threads(lib)
+    o = oracle.Oracle(A, b, c, lib_path=lib)
     t0 = time.perf_counter()
-    o.run(pivots)
+    st = oracle.ITER_LIMIT
+    while st == oracle.ITER_LIMIT and time.perf_counter() - t0 < budget_s:
+        st = o.run(o.iterations + 25)
     dt = time.perf_counter() - t0
     done = o.iterations
-    return dict(value=round(done / dt, 3), unit="iter/s", cores=1, kind="oracle",
-                sample=f"first {done} pivots of the m={A.shape[0]},n={A.shape[1]} solve, single thread, "
-                       f"{dt:.1f} s")
+    whole = st != oracle.ITER_LIMIT
+    o1 = oracle.Oracle(A, b, c)
+    t1 = time.perf_counter()
+    o1.run(pivots)
+    dt1 = time.perf_counter() - t1
+    shape = f"m={A.shape[0]},n={A.shape[1]}"
+    return dict(value=round(done / dt, 3), unit="iter/s", cores=cores, kind="oracle",
+                sample=(f"the whole {shape} solve ({done} pivots, {oracle.STATUS_NAMES[st]}) in {dt:.1f} s"
+                        if whole else f"first {done} pivots of the {shape} solve in {dt:.1f} s") +
+                       f" on {cores} threads (OpenMP build, bit-identical to the sequential oracle)",
+                single_core=dict(value=round(o1.iterations / dt1, 3), unit="iter/s", cores=1,
+                                 sample=f"first {o1.iterations} pivots of the {shape} solve, sequential build, "
+                                        f"{dt1:.1f} s"))
 
 
 def main():

@@ -215,8 +215,18 @@ int lp_create_device(lp_problem **out, int32_t m, int32_t n, const double *A_col
  * device state.  Returns LP_OK or an error code. */
 int lp_solve(lp_problem *p, int32_t *status_out);
 
-/* As lp_solve, with the total pivot limit given by iter_cap instead of opt.max_iter. */
+/* As lp_solve, with the total pivot limit given by iter_cap instead of opt.max_iter.  At
+ * the cap one more pricing pass decides between LP_OPTIMAL and LP_ITER_LIMIT (Step 4 runs
+ * before the limit is checked). */
 int lp_solve_until(lp_problem *p, int64_t iter_cap, int32_t *status_out);
+
+/* Runs exactly `count` further iterations of Steps 3-8 (pivots; in the LP_MIXED form an
+ * iteration whose shortlist held no improving column does not count), or fewer if a
+ * terminal status comes first, and stops without pricing the next one: *status_out is then
+ * LP_RUNNING.  A later lp_iterate or lp_solve continues from the device state; the result
+ * is the same as one uninterrupted solve.  Returns LP_OK or an error code (LP_ERR_ARG for
+ * count < 0). */
+int lp_iterate(lp_problem *p, int64_t count, int32_t *status_out);
 
 /* Returns the problem to the slack basis and clears the pivot log and statistics
  * (the LP data are kept). */
@@ -261,6 +271,28 @@ int lp_reinvert(lp_problem *p);
 
 /* Frees every device and host resource of the handle.  NULL-safe. */
 void lp_destroy(lp_problem *p);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lp_create_device + lp_solve +
+ * lp_get_solution + lp_destroy in one call that allocates nothing.  Every buffer of the
+ * solve lives in one fixed 128 MiB array of device memory per GPU, which each GPU the
+ * library runs on holds until the process ends; no graph, stream or event is created.
+ *   A_colmajor (m*n, lda = m), b (m), c (n): device pointers of the current device, read only;
+ *   x (n), y (m duals in the user's sense), objective (1): device pointers, any may be NULL;
+ *   status, iterations: host pointers, any may be NULL.
+ * Runs on opt->stream (NULL = the null stream) and returns when the results are written.
+ * Only the FP64 form without reinversion and without profiling is available (LP_ERR_ARG
+ * otherwise).  An LP whose buffers (about 8*ld*(n+m) bytes plus 28 bytes per pivot of
+ * max_iter, ld = m rounded up to 8) exceed the array is rejected with LP_ERR_ARG before
+ * any device work; non-finite data give LP_ERR_ARG and some b_i < 0 LP_ERR_NEG_RHS.
+ * The pivots, x, y and objective equal those of lp_create_device + lp_solve (same
+ * kernels, same order of operations).  All calls on one GPU share its array, so calls
+ * that overlap on one GPU (from two threads, or on two streams) race and must not be made.
+ */
+int lp_solve_device_noalloc(int32_t m, int32_t n, const double *A_colmajor, const double *b, const double *c,
+                            const lp_options *opt, double *x, double *y, double *objective, int32_t *status,
+                            int64_t *iterations);
 
 /* ---- batched form: many independent LPs in persistent kernel launches (one, or two when
  *      some LPs keep B^-1 in LDS) ---- */

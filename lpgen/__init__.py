@@ -115,6 +115,19 @@ def degenerate_lp(seed: int, m: int, n: int, col_frac=0.02, zero_b_frac=0.30, bu
     return A, bv, cv
 
 
+def diagonal_lp(seed: int, m: int, n: int, off=(0.0, 1e-4)):
+    """Nearly diagonal law: A'_jj ~ U(1,2) for j < min(m, n), every other entry U(off)
+    (the dense law's bits rescaled), b_i ~ U(1,10), c_j ~ U(1,10), max sense.  Each pivot
+    of a Dantzig solve from the slack basis tends to bring in a new structural column in
+    place of the slack of its diagonal row, so the basis fills with structural columns
+    and the number of slacks that have left grows by about one per pivot."""
+    A, bv, cv = dense_lp(seed, m, n, a=off)
+    k = min(m, n)
+    d = np.arange(k)
+    A[d, d] = uniform(seed, S_EXTRA, np.arange(k, dtype=np.uint64), 1.0, 2.0)
+    return A, bv, cv
+
+
 ROW_LE, ROW_GE, ROW_EQ = 0, 1, 2
 
 

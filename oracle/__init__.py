@@ -16,6 +16,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "simplex_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The same source built with -fopenmp: loops over independent columns and rows run on
+# several threads, with bit-identical results (each dot product keeps its order).
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 OPTIMAL, UNBOUNDED, ITER_LIMIT, NUMERICAL, INFEASIBLE = 1, 2, 3, 4, 5
 STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT", 4: "NUMERICAL", 5: "INFEASIBLE"}
@@ -28,11 +31,28 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-march=x86-64-v3", "-fP
 
 
 def build(force: bool = True) -> str:
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Builds the sequential library and the -fopenmp one; returns the sequential one's path."""
+    for path, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", *CFLAGS, *extra, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
     return _LIB
+
+
+def omp_lib(threads: int = 0) -> str:
+    """Path of the -fopenmp build (built if missing), with its thread count set (0: the
+    OpenMP default, normally every core)."""
+    if not os.path.exists(_LIB_OMP):
+        build(force=False)
+    L = lib(_LIB_OMP)
+    L.oracle_set_threads(int(threads))
+    return _LIB_OMP
+
+
+def threads(lib_path: str | None = None) -> int:
+    """Threads the given build runs on (1 for the sequential build)."""
+    return int(lib(lib_path).oracle_set_threads(0))
 
 
 _libs = {}
@@ -72,6 +92,8 @@ def lib(path: str | None = None):
         L.oracle_pivots.restype = I64
         L.oracle_pivots.argtypes = [P, ip, ip, ip, ip, I64]
         L.oracle_counts.argtypes = [P, C.POINTER(C.c_int64)]
+        L.oracle_set_threads.restype = I32
+        L.oracle_set_threads.argtypes = [I32]
         L.oracle_basis_inverse.restype = I32
         L.oracle_basis_inverse.argtypes = [I32, I32, dp, ip, dp]
         _libs[key] = L

@@ -77,12 +77,20 @@
  * Dot products are plain ascending-index fma chains.  Build with
  * -ffp-contract=off so that no other operation is fused.
  *
+ * Built with -fopenmp, the loops over independent columns (pricing) and rows (FTRAN,
+ * the pivot) are shared among threads.  Each dot product and each element is still
+ * computed by one thread in the same order, and every choice is made afterwards by a
+ * sequential scan, so the results are bit-identical to the sequential build.
+ *
  * oracle_basis_inverse, at the end, gives B^-1 of any basis list by its definition:
  * the reference for the GPU reinversion (parity unpinned by the paper, which does not
  * refactorise; pinned by the tests against closed forms and a library inverse).
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -249,6 +257,7 @@ static int list_add(oracle_lp *p, int32_t q, int32_t v) {
 /* Step 5: Y_k = B^-1 a_q into alpha (a slack's column is a column of B^-1). */
 static void ftran(oracle_lp *p, int32_t q) {
   const int32_t m = p->m, n = p->n;
+#pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < m; ++i) {
     const double *row = p->Binv + (size_t)i * m;
     if (q < n) {
@@ -269,6 +278,7 @@ static void pivot_inverse(oracle_lp *p, int32_t r) {
   const double ar = p->alpha[r];
   double *rowr = p->Binv + (size_t)r * m;
   for (int32_t j = 0; j < m; ++j) p->rho[j] = rowr[j] / ar;
+#pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < m; ++i) {
     double *row = p->Binv + (size_t)i * m;
     if (i == r) {
@@ -286,6 +296,7 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
 
   /* Step 3: reduced costs d_j = chat_j - W a_j of every nonbasic variable (barred
    * artificial variables are not candidates). */
+#pragma omp parallel for schedule(static)
   for (int32_t j = 0; j < N; ++j) {
     if (p->pos[j] != -1) continue;
     if (j < n) {
@@ -506,6 +517,18 @@ oracle_lp *oracle_create_general(int32_t m, int32_t n, const double *A_colmajor,
     p->phase = 1;
   }
   return p;
+}
+
+/* Threads of the -fopenmp build (n <= 0: leave the default); returns the number in use,
+ * 1 for the sequential build. */
+int32_t oracle_set_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 int32_t oracle_phase(const oracle_lp *p) { return p->phase; }

@@ -114,6 +114,10 @@ SIGNATURES = {
                                     C.POINTER(lp_options)]),
     "lp_solve": (C.c_int, [_P, _IP]),
     "lp_solve_until": (C.c_int, [_P, C.c_int64, _IP]),
+    "lp_iterate": (C.c_int, [_P, C.c_int64, _IP]),
+    "lp_solve_device_noalloc": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.POINTER(lp_options), C.c_void_p, C.c_void_p, C.c_void_p, _IP,
+                                          C.POINTER(C.c_int64)]),
     "lp_reset": (C.c_int, [_P]),
     "lp_get_solution": (C.c_int, [_P, _DP, _DP, _DP, _IP, _LP]),
     "lp_get_pivots": (C.c_int, [_P, _IP, _IP, _IP, _IP, C.c_int64, _LP]),
@@ -239,6 +243,12 @@ class LP:
             _check(lib().lp_solve_until(self._h, int(max_iter), C.byref(st)), "lp_solve_until")
         return st.value
 
+    def iterate(self, count) -> int:
+        """Exactly `count` more pivots (fewer if the solve ends first); LP_RUNNING if it has not."""
+        st = C.c_int32()
+        _check(lib().lp_iterate(self._h, int(count), C.byref(st)), "lp_iterate")
+        return st.value
+
     def reset(self):
         _check(lib().lp_reset(self._h), "lp_reset")
 
@@ -277,6 +287,29 @@ class LP:
         s = lp_stats()
         _check(lib().lp_get_stats(self._h, C.byref(s)), "lp_get_stats")
         return {f: getattr(s, f) for f, _ in lp_stats._fields_}
+
+
+def solve_device_noalloc(A, b, c, x=None, y=None, objective=None, sense="max", **opts):
+    """lp_solve_device_noalloc on torch CUDA tensors (A float64 of shape (m, n) with stride
+    (1, m), b and c float64); x (n), y (m), objective (1): float64 CUDA tensors or None.
+    Returns (status, iterations)."""
+    m, n = A.shape
+    for t in (A, b, c):
+        if str(t.dtype) != "torch.float64" or not t.is_cuda:
+            raise TypeError("A, b, c must be float64 CUDA tensors")
+    if n > 1 and A.stride() != (1, m):
+        raise ValueError("A must be column-major: stride (1, m)")
+    for t, k in ((x, n), (y, m), (objective, 1)):
+        if t is not None and (str(t.dtype) != "torch.float64" or not t.is_cuda or t.numel() != k
+                              or not t.is_contiguous()):
+            raise ValueError("outputs must be contiguous float64 CUDA tensors of n, m and 1 entries")
+    o = default_options(sense=LP_MAX if sense == "max" else LP_MIN, **opts)
+    st = C.c_int32()
+    it = C.c_int64()
+    ptr = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+    _check(lib().lp_solve_device_noalloc(m, n, A.data_ptr(), b.data_ptr(), c.data_ptr(), C.byref(o), ptr(x), ptr(y),
+                                         ptr(objective), C.byref(st), C.byref(it)), "lp_solve_device_noalloc")
+    return st.value, it.value
 
 
 class Batch:

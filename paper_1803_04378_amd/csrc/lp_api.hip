@@ -6,6 +6,8 @@
 // replays it, reading back only the small control block after each replay
 // (the status scalar plus counters).  The kernels themselves stop doing work once the
 // status leaves RUNNING, so a replay that overshoots the end of the solve is harmless.
+// Near a pivot cap, shorter graphs of 1, 2, 4, ... iterations are replayed instead, so
+// that no replay runs iterations past the cap.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -16,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -25,6 +28,13 @@
 #include "lpgpu.h"
 
 using namespace lpgpu;
+
+// Device memory of lp_solve_device_noalloc: one array per GPU, alive until the process
+// ends.  Host code never passes this name to a kernel or a copy (on the host it is only a
+// stand-in for the symbol): it uses the address hipGetSymbolAddress returns for the
+// current device.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -81,11 +91,17 @@ hipError_t pageable_copy(void* dst, const void* src, size_t bytes, hipMemcpyKind
   return e;
 }
 
-hipError_t pageable_copy_2d(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t height,
-                            hipMemcpyKind kind, hipStream_t s) {
-  hipError_t e = hipStreamSynchronize(s);
-  if (e == hipSuccess && width > 0 && height > 0) e = hipMemcpy2D(dst, dpitch, src, spitch, width, height, kind);
-  return e;
+// Order-independent 64-bit hash of the bit patterns of `count` doubles whose first one sits
+// at element `base` of an array: the wrapping sum of a SplitMix64 finaliser of (bits,
+// index), so a device kernel can form it in any order and compare it with this value.
+uint64_t hash_doubles(const double* x, size_t count, uint64_t base) {
+  uint64_t h = 0;
+  for (size_t k = 0; k < count; ++k) {
+    uint64_t bits;
+    std::memcpy(&bits, &x[k], sizeof(bits));
+    h += hash_word(bits, base + k);
+  }
+  return h;
 }
 
 #define HIP_TRY(expr, what)                   \
@@ -127,6 +143,9 @@ struct lp_problem {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_k = 0;
+  // tail graphs: 2^k iterations each, for the last replays before a pivot cap
+  hipGraph_t tail_graph[12] = {};
+  hipGraphExec_t tail_exec[12] = {};
   std::vector<hipEvent_t> events;
   lp_stats stats{};
   int price32_grid = 0;    // mixed form
@@ -180,6 +199,12 @@ void drop_graph(lp_problem* p) {
   p->gexec = nullptr;
   p->graph = nullptr;
   p->graph_k = 0;
+  for (int k = 0; k < 12; ++k) {
+    if (p->tail_exec[k]) (void)hipGraphExecDestroy(p->tail_exec[k]);
+    if (p->tail_graph[k]) (void)hipGraphDestroy(p->tail_graph[k]);
+    p->tail_exec[k] = nullptr;
+    p->tail_graph[k] = nullptr;
+  }
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   p->events.clear();
 }
@@ -303,23 +328,20 @@ int iteration_kernels(const lp_problem* p, IterKernel* out) {
   return c;
 }
 
-// The iteration graph: iters_per_sync iterations as a linear chain of kernel nodes.  With
-// profile = 1 an event-record node sits before every kernel and at the end.
-int build_graph(lp_problem* p) {
-  drop_graph(p);
-  const int K = p->opt.iters_per_sync;
-  const bool prof = p->opt.profile == 1;
+// An iteration graph: K iterations as a linear chain of kernel nodes.  With events (the
+// main graph under profile = 1) an event-record node sits before every kernel and at the end.
+int build_chain(lp_problem* p, int K, bool prof, hipGraph_t* graph, hipGraphExec_t* gexec) {
   IterKernel ks[5];
   const int E = iteration_kernels(p, ks);
   if (prof) {
     p->events.resize(E * K + 1, nullptr);
     for (auto& e : p->events) HIP_TRY(hipEventCreate(&e), "creating profiling events");
   }
-  HIP_TRY(hipGraphCreate(&p->graph, 0), "creating the iteration graph");
+  HIP_TRY(hipGraphCreate(graph, 0), "creating the iteration graph");
   hipGraphNode_t prev = nullptr;
   auto add_event = [&](hipEvent_t ev) -> hipError_t {
     hipGraphNode_t node;
-    hipError_t e = hipGraphAddEventRecordNode(&node, p->graph, prev ? &prev : nullptr, prev ? 1 : 0, ev);
+    hipError_t e = hipGraphAddEventRecordNode(&node, *graph, prev ? &prev : nullptr, prev ? 1 : 0, ev);
     if (e == hipSuccess) prev = node;
     return e;
   };
@@ -333,7 +355,7 @@ int build_graph(lp_problem* p) {
     kp.kernelParams = args;
     kp.extra = nullptr;
     hipGraphNode_t node;
-    hipError_t e = hipGraphAddKernelNode(&node, p->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    hipError_t e = hipGraphAddKernelNode(&node, *graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
     if (e == hipSuccess) prev = node;
     return e;
   };
@@ -343,21 +365,26 @@ int build_graph(lp_problem* p) {
       HIP_TRY(add_kernel(ks[i]), "adding a kernel node");
     }
   if (prof) HIP_TRY(add_event(p->events[E * K]), "adding a profiling event");
-  HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0), "instantiating the iteration graph");
-  p->graph_k = K;
+  HIP_TRY(hipGraphInstantiate(gexec, *graph, nullptr, nullptr, 0), "instantiating the iteration graph");
   return LP_OK;
+}
+
+int build_graph(lp_problem* p) {
+  drop_graph(p);
+  const int rc = build_chain(p, p->opt.iters_per_sync, p->opt.profile == 1, &p->graph, &p->gexec);
+  if (rc == LP_OK) p->graph_k = p->opt.iters_per_sync;
+  return rc;
 }
 
 // profile = 2: the same K iterations launched directly on the stream (no graph), each
 // kernel with a start and a stop event bound to its own dispatch, so that the elapsed
 // time between them is the kernel's execution alone (no launch gap).
-int launch_direct(lp_problem* p) {
-  const int K = p->opt.iters_per_sync;
+int launch_direct(lp_problem* p, int K) {
   IterKernel ks[5];
   const int E = iteration_kernels(p, ks);
-  if ((int)p->events.size() != 2 * E * K) {
+  if ((int)p->events.size() != 2 * E * p->opt.iters_per_sync) {
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
-    p->events.assign(2 * E * K, nullptr);
+    p->events.assign(2 * E * p->opt.iters_per_sync, nullptr);
     for (auto& e : p->events) HIP_TRY(hipEventCreate(&e), "creating profiling events");
   }
   for (int k = 0; k < K; ++k)
@@ -368,6 +395,23 @@ int launch_direct(lp_problem* p) {
                                  p->events[ev], p->events[ev + 1], 0),
               "launching an iteration kernel");
     }
+  return LP_OK;
+}
+
+// Workgroup counts of the iteration kernels for an m x n LP (FP64 form) on a device with
+// num_cu compute units, from the occupancy the kernels' LDS allows.
+int iteration_grids(int32_t m, int32_t n, int num_cu, int* price_grid, int* update_grid, int* upd_block) {
+  const int ld = (int)round_up(m, 8);
+  int price_per_cu = 0, update_per_cu = 0;
+  hipError_t e = kernel_occupancy(&price_per_cu, &update_per_cu, ld);
+  if (e != hipSuccess) return fail_hip(e, "querying kernel occupancy");
+  if (price_per_cu < 1 || update_per_cu < 1) return fail(LP_ERR_ARG, "m too large for the kernels' LDS");
+  *upd_block = update_block(ld);
+  const int pw = kPriceBlock / 64, uw = *upd_block / 64;
+  *price_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)price_per_cu * num_cu, (n + pw - 1) / pw));
+  *update_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)update_per_cu * num_cu, (m + uw - 1) / uw));
+  if ((m + (int64_t)*update_grid * uw - 1) / ((int64_t)*update_grid * uw) > kMaxRowsPerWave)
+    return fail(LP_ERR_ARG, "m too large for this device: more than kMaxRowsPerWave rows per wavefront");
   return LP_OK;
 }
 
@@ -439,18 +483,8 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
     if (e != hipSuccess) return bail(fail_hip(e, "querying the device"));
     p->num_cu = prop.multiProcessorCount;
   }
-  int price_per_cu = 0, update_per_cu = 0;
-  {
-    hipError_t e = kernel_occupancy(&price_per_cu, &update_per_cu, ld);
-    if (e != hipSuccess) return bail(fail_hip(e, "querying kernel occupancy"));
-    if (price_per_cu < 1 || update_per_cu < 1) return bail(fail(LP_ERR_ARG, "m too large for the kernels' LDS"));
-  }
-  const int upd_block = update_block(ld);
-  const int pw = kPriceBlock / 64, uw = upd_block / 64;
-  p->price_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)price_per_cu * p->num_cu, (n + pw - 1) / pw));
-  p->update_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)update_per_cu * p->num_cu, (m + uw - 1) / uw));
-  if ((m + (int64_t)p->update_grid * uw - 1) / ((int64_t)p->update_grid * uw) > kMaxRowsPerWave)
-    return bail(fail(LP_ERR_ARG, "m too large for this device: more than kMaxRowsPerWave rows per wavefront"));
+  int upd_block = 0;
+  if ((rc = iteration_grids(m, n, p->num_cu, &p->price_grid, &p->update_grid, &upd_block)) != LP_OK) return bail(rc);
   p->reinv_period = o.reinv_period >= 0 ? o.reinv_period : (mixed ? 64 : 0);
   if (mixed) {
     int per_cu = 0;
@@ -544,49 +578,56 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   if ((rc = ensure_capacity(p, o.max_iter)) != LP_OK) return bail(rc);
 
   hipStream_t s = p->stream;
-  hipError_t e = hipMemsetAsync(dA, 0, sizeof(double) * (size_t)ld * std::max(n, 1), s);
-  if (e != hipSuccess) return bail(fail_hip(e, "clearing A"));
-  const hipMemcpyKind kind = device_inputs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  hipError_t e = hipSuccess;
+  // Device scratch of the upload: a flag word and a hash word.
+  int32_t* flag = nullptr;
+  unsigned long long* dhash = nullptr;
+  if ((e = dalloc(p, &flag, 1)) != hipSuccess || (e = dalloc(p, &dhash, 1)) != hipSuccess)
+    return bail(fail_hip(e, "allocating the upload check"));
   if (device_inputs) {
-    // Validate on the device, then bring b and c to the host for the sign check and
-    // the reported objective.
-    int32_t* flag = nullptr;
-    e = dalloc(p, &flag, 1);
-    if (e != hipSuccess) return bail(fail_hip(e, "allocating a flag"));
-    if ((e = hipMemsetAsync(flag, 0, sizeof(int32_t), s)) != hipSuccess) return bail(fail_hip(e, "validating"));
+    // Packed into the padded layout and validated on the device, then b and c come to
+    // the host for the reported objective.
+    if ((e = launch_clear_flag(flag, s)) != hipSuccess ||
+        (e = launch_pack_lp(dA, ld, A, m, n, p->b0, b, p->c0, c, flag, s)) != hipSuccess)
+      return bail(fail_hip(e, "copying the LP"));
     // (the mixed form keeps an FP32 copy of A', so there every entry must be in the FP32 range)
-    const double bound = mixed ? (double)FLT_MAX : DBL_MAX;
-    if ((e = launch_check_finite(A, (int64_t)m * n, bound, flag, s)) != hipSuccess)
+    if (mixed && (e = launch_check_finite(dA, (int64_t)ld * n, (double)FLT_MAX, flag, s)) != hipSuccess)
       return bail(fail_hip(e, "validating A"));
     int32_t hflag = 0;
     if ((e = pageable_copy(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = pageable_copy(hb.data(), b, sizeof(double) * m, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = pageable_copy(hc.data(), c, sizeof(double) * n, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        (e = pageable_copy(hb.data(), p->b0, sizeof(double) * m, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = pageable_copy(hc.data(), p->c0, sizeof(double) * n, hipMemcpyDeviceToHost, s)) != hipSuccess)
       return bail(fail_hip(e, "reading the LP data"));
-    dfree(p, flag);
+    if (hflag & 2) return bail(fail(LP_ERR_NEG_RHS, "b_i < 0: the slack basis is infeasible"));
     if (hflag)
-      return bail(fail(LP_ERR_ARG, mixed ? "A contains a non-finite value or one beyond the FP32 range (mixed form)"
-                                         : "A contains a non-finite value"));
-    for (int32_t i = 0; i < m; ++i) {
-      if (!std::isfinite(hb[i])) return bail(fail(LP_ERR_ARG, "b contains a non-finite value"));
-      if (hb[i] < 0.0) return bail(fail(LP_ERR_NEG_RHS, "b_i < 0: the slack basis is infeasible"));
+      return bail(fail(LP_ERR_ARG, mixed ? "A, b or c contains a non-finite value, or A one beyond the FP32 range "
+                                           "(mixed form)"
+                                         : "A, b or c contains a non-finite value"));
+  } else {
+    // One contiguous copy of A' in the padded layout (packed on the host unless ld = m),
+    // then an order-independent hash of what arrived, formed on the device, against the
+    // same hash of what was sent: a copy that moved nothing, or not all of it, is an error.
+    std::vector<double> packed;
+    const double* src = A;
+    if (ld != m && n > 0) {
+      packed.assign((size_t)ld * n, 0.0);
+      for (int32_t j = 0; j < n; ++j) std::memcpy(&packed[(size_t)j * ld], A + (size_t)j * m, sizeof(double) * m);
+      src = packed.data();
     }
-    for (int32_t j = 0; j < n; ++j)
-      if (!std::isfinite(hc[j])) return bail(fail(LP_ERR_ARG, "c contains a non-finite value"));
+    const size_t na = (size_t)ld * n;
+    const uint64_t want = hash_doubles(src, na, 0) + hash_doubles(hb.data(), m, na) + hash_doubles(hc.data(), n, na + m);
+    if ((n > 0 && ((e = pageable_copy(dA, src, sizeof(double) * na, hipMemcpyHostToDevice, s)) != hipSuccess ||
+                   (e = pageable_copy(p->c0, hc.data(), sizeof(double) * n, hipMemcpyHostToDevice, s)) != hipSuccess)) ||
+        (e = pageable_copy(p->b0, hb.data(), sizeof(double) * m, hipMemcpyHostToDevice, s)) != hipSuccess)
+      return bail(fail_hip(e, "copying the LP"));
+    uint64_t got = 0;
+    if ((e = launch_hash(dA, na, 0, p->b0, m, p->c0, n, dhash, s)) != hipSuccess ||
+        (e = pageable_copy(&got, dhash, sizeof(got), hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return bail(fail_hip(e, "checking the upload"));
+    if (got != want) return bail(fail(LP_ERR_DEVICE, "the LP data on the device differ from the host's after the copy"));
   }
-  if (n > 0) {
-    // (one contiguous copy when there is no padding, ld = m)
-    e = device_inputs ? hipMemcpy2DAsync(dA, sizeof(double) * ld, A, sizeof(double) * m, sizeof(double) * m, n, kind, s)
-        : ld == m     ? pageable_copy(dA, A, sizeof(double) * (size_t)m * n, kind, s)
-                      : pageable_copy_2d(dA, sizeof(double) * ld, A, sizeof(double) * m, sizeof(double) * m, n, kind, s);
-    if (e != hipSuccess) return bail(fail_hip(e, "copying A"));
-    e = device_inputs ? hipMemcpyAsync(p->c0, c, sizeof(double) * n, kind, s)
-                      : pageable_copy(p->c0, c, sizeof(double) * n, kind, s);
-    if (e != hipSuccess) return bail(fail_hip(e, "copying c"));
-  }
-  e = device_inputs ? hipMemcpyAsync(p->b0, b, sizeof(double) * m, kind, s)
-                    : pageable_copy(p->b0, b, sizeof(double) * m, kind, s);
-  if (e != hipSuccess) return bail(fail_hip(e, "copying b"));
+  dfree(p, flag);
+  dfree(p, dhash);
   if (mixed) {
     // FP32 copy of A' with the same padding (round to nearest).
     e = launch_convert32(dA, dA32, (size_t)ld * n, s);
@@ -653,6 +694,196 @@ int phase_switch(lp_problem* p) {
   p->phase = 2;
   p->switch_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return LP_OK;
+}
+
+// Iterates until a terminal status or until the pivot count reaches iter_cap.  decide:
+// at the cap, one more pricing decides between OPTIMAL and ITER_LIMIT (lp_solve_until);
+// otherwise the solve stops there still RUNNING (lp_iterate).  Replays of the main graph
+// run while at least iters_per_sync pivots remain, then power-of-two tail graphs.
+int run_until(lp_problem* p, int64_t iter_cap, bool decide, int32_t* status_out) {
+  int rc;
+  if ((p->h_ctrl->status == LP_OPTIMAL && p->phase != 1) || p->h_ctrl->status == LP_UNBOUNDED ||
+      p->h_ctrl->status == LP_INFEASIBLE) {
+    if (status_out) *status_out = p->h_ctrl->status;
+    return LP_OK;
+  }
+  // (drive-out pivots of a phase switch may add up to m log entries past the limit)
+  if ((rc = ensure_capacity(p, iter_cap + (p->phase == 1 ? p->m : 0))) != LP_OK) return rc;
+  const bool direct = p->opt.profile == 2;
+  if (!direct && (!p->gexec || p->graph_k != p->opt.iters_per_sync)) {
+    if ((rc = build_graph(p)) != LP_OK) return rc;
+  }
+  if (!decide && p->h_ctrl->t >= iter_cap) {
+    if (status_out) *status_out = p->h_ctrl->status == LP_ITER_LIMIT ? LP_RUNNING : p->h_ctrl->status;
+    return LP_OK;
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  // Arm the control block: new pivot limit, and RUNNING again after an ITER_LIMIT stop.
+  p->h_stage->max_iter = iter_cap;
+  p->h_stage->status = LP_RUNNING;
+  HIP_TRY(hipMemcpyAsync(&p->d.ctrl->max_iter, &p->h_stage->max_iter, sizeof(int64_t), hipMemcpyHostToDevice,
+                         p->stream),
+          "arming the solve");
+  HIP_TRY(hipMemcpyAsync(&p->d.ctrl->status, &p->h_stage->status, sizeof(int32_t), hipMemcpyHostToDevice, p->stream),
+          "arming the solve");
+  const bool prof = p->opt.profile != 0;
+  const int K = p->opt.iters_per_sync;
+  const bool mixed = p->d.mixed != 0;
+  const int E = mixed ? 4 : 3;
+  for (;;) {
+    const int64_t left = iter_cap - p->h_ctrl->t;
+    int k = K;
+    if (left < K) {
+      if (left <= 0 && !decide) break;
+      k = 1;
+      while (2 * (int64_t)k <= left) k *= 2;
+    }
+    const int64_t t_before = p->h_ctrl->t;
+    const int64_t fb_before = p->h_ctrl->n_fallback;
+    const int64_t cols_before = p->h_ctrl->price_cols;
+    const int64_t nsb_before = p->h_ctrl->nsb;
+    const int64_t ubytes_before = p->h_ctrl->update_bytes;
+    if (direct) {
+      if ((rc = launch_direct(p, k)) != LP_OK) return rc;
+    } else if (k == K) {
+      HIP_TRY(hipGraphLaunch(p->gexec, p->stream), "launching the iteration graph");
+    } else {
+      int lg = 0;
+      while ((1 << lg) < k) ++lg;
+      if (!p->tail_exec[lg] &&
+          (rc = build_chain(p, k, false, &p->tail_graph[lg], &p->tail_exec[lg])) != LP_OK)
+        return rc;
+      HIP_TRY(hipGraphLaunch(p->tail_exec[lg], p->stream), "launching a tail graph");
+    }
+    if ((rc = read_ctrl(p)) != LP_OK) return rc;
+    p->stats.syncs += 1;
+    if ((rc = collect_reinv_time(p)) != LP_OK) return rc;
+    if (prof && k == K && p->h_ctrl->status == LP_RUNNING && t_before > 0 && p->h_ctrl->t == t_before + K) {
+      // Steady state: every kernel of the replay did a full pass (K pivots, so in the
+      // mixed form no fallback iteration and no FP64 pass).
+      for (int it = 0; it < K; ++it) {
+        float ms[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < E; ++i) {
+          // profile = 1: between the event nodes around kernel i (its launch gap
+          // included); profile = 2: the kernel's own start and stop.
+          const int a = direct ? 2 * (E * it + i) : E * it + i;
+          HIP_TRY(hipEventElapsedTime(&ms[i], p->events[a], p->events[a + 1]), "reading profile events");
+        }
+        const int o = mixed ? 2 : 1;
+        if (mixed) {
+          p->stats.price32_ms += ms[0];
+          p->stats.shortlist_ms += ms[1];
+        } else {
+          p->stats.price_ms += ms[0];
+        }
+        p->stats.update_ms += ms[o];
+        p->stats.finish_ms += ms[o + 1];
+      }
+      if (!mixed) p->stats.price_launches += K;
+      p->stats.update_launches += K;
+      p->stats.finish_launches += K;
+      p->stats.price_bytes += 8.0 * p->m * (double)(p->h_ctrl->price_cols - cols_before);
+      // algorithmic bytes of the update passes, counted on the device
+      p->stats.update_bytes += (double)(p->h_ctrl->update_bytes - ubytes_before);
+      if (mixed) {
+        // Nonbasic structural columns streamed by the K screening passes (the basis
+        // changes by at most one structural column per pivot; the midpoint is used).
+        const double nonbasic = p->n - 0.5 * (double)(nsb_before + p->h_ctrl->nsb);
+        p->stats.price32_bytes += 4.0 * p->m * nonbasic * K;
+      }
+    }
+    if (p->h_ctrl->status == LP_OPTIMAL && p->phase == 1) {
+      if ((rc = phase_switch(p)) != LP_OK) return rc;
+      if (p->h_ctrl->status == LP_RUNNING) continue;
+    }
+    if (p->h_ctrl->status != LP_RUNNING) break;
+    // Every iteration of a RUNNING solve's replay must pivot, or (mixed form) end with the
+    // fallback verdict; anything else is a fault of the kernels' control logic, reported
+    // instead of looping.
+    if (p->h_ctrl->t + p->h_ctrl->n_fallback != t_before + fb_before + k)
+      return fail(LP_ERR_DEVICE, "iteration graph made no progress while RUNNING");
+    // (reinversion recomputes W from the structural basic variables only: not in phase 1)
+    if (p->reinv_period > 0 && p->phase != 1 && p->h_ctrl->t - p->last_reinv_t >= p->reinv_period) {
+      if ((rc = run_reinversion(p)) != LP_OK) return rc;
+    }
+  }
+  p->stats.solve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (status_out) *status_out = p->h_ctrl->status;
+  return LP_OK;
+}
+
+// ---- the entry point that allocates nothing ----
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+// The address of `scratch` on the current device, looked up once per device.
+int scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(LP_ERR_DEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail_hip(e != hipSuccess ? e : hipErrorInvalidSymbol, "locating the scratch array");
+    g_scratch[dev] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return LP_OK;
+}
+
+// Carves consecutive 256-byte aligned pieces out of the scratch array (or, with base null,
+// only counts the bytes they take).
+struct Carver {
+  unsigned char* base;
+  size_t used = 0;
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
+    return p;
+  }
+};
+
+// Lays out every buffer of an m x n solve with pivot capacity cap; returns the bytes used.
+size_t carve_lp(Carver& cv, DevLP& d, int32_t m, int32_t n, int64_t cap, double** b0, double** c0, int32_t** flag) {
+  const size_t ld = (size_t)round_up(m, 8), N = (size_t)n + m;
+  d.A = cv.take<double>(ld * std::max(n, 1));
+  d.chat = cv.take<double>(N);
+  d.Binv = cv.take<double>((size_t)m * ld);
+  d.xB = cv.take<double>(m);
+  d.W0 = cv.take<double>(ld);
+  d.W1 = cv.take<double>(ld);
+  d.rho = cv.take<double>(ld);
+  d.alpha0 = cv.take<double>(m);
+  d.alpha1 = cv.take<double>(m);
+  d.basis = cv.take<int32_t>(m);
+  d.dlist = cv.take<int32_t>(m);
+  d.inD = cv.take<int32_t>(m);
+  d.pos = cv.take<int32_t>(N);
+  d.tabu_until = cv.take<int32_t>(N);
+  d.gen = cv.take<int32_t>(N);
+  d.excl = cv.take<int32_t>(N);
+  d.part_d = cv.take<double>(2 * (size_t)d.price_grid);
+  d.part_j = cv.take<int32_t>(2 * (size_t)d.price_grid);
+  d.part_th = cv.take<double>(d.update_grid);
+  d.part_low = cv.take<int32_t>(d.update_grid);
+  d.part_t1 = cv.take<double>(d.update_grid);
+  d.part_t2 = cv.take<double>(d.update_grid);
+  d.part_al = cv.take<double>(d.update_grid);
+  d.part_bv = cv.take<int32_t>(d.update_grid);
+  d.ctrl = cv.take<Ctrl>(1);
+  d.log_enter = cv.take<int32_t>(cap);
+  d.log_row = cv.take<int32_t>(cap);
+  d.log_leave = cv.take<int32_t>(cap);
+  d.log_flags = cv.take<int32_t>(cap);
+  d.Lq = cv.take<int32_t>(cap);
+  d.Ll = cv.take<int32_t>(cap);
+  d.Lgen = cv.take<int32_t>(cap);
+  *b0 = cv.take<double>(m);
+  *c0 = cv.take<double>(std::max(n, 1));
+  *flag = cv.take<int32_t>(1);
+  return cv.used;
 }
 
 }  // namespace
@@ -778,97 +1009,16 @@ int lp_create_general(lp_problem** out, int32_t m, int32_t n, const double* A_co
 int lp_solve_until(lp_problem* p, int64_t iter_cap, int32_t* status_out) try {
   if (!p) return fail(LP_ERR_ARG, "p is NULL");
   if (iter_cap < 0) return fail(LP_ERR_ARG, "iter_cap must be >= 0");
-  int rc;
-  if ((p->h_ctrl->status == LP_OPTIMAL && p->phase != 1) || p->h_ctrl->status == LP_UNBOUNDED ||
-      p->h_ctrl->status == LP_INFEASIBLE) {
-    if (status_out) *status_out = p->h_ctrl->status;
-    return LP_OK;
-  }
-  // (drive-out pivots of a phase switch may add up to m log entries past the limit)
-  if ((rc = ensure_capacity(p, iter_cap + (p->phase == 1 ? p->m : 0))) != LP_OK) return rc;
-  const bool direct = p->opt.profile == 2;
-  if (!direct && (!p->gexec || p->graph_k != p->opt.iters_per_sync)) {
-    if ((rc = build_graph(p)) != LP_OK) return rc;
-  }
-  const auto t0 = std::chrono::steady_clock::now();
-  // Arm the control block: new pivot limit, and RUNNING again after an ITER_LIMIT stop.
-  p->h_stage->max_iter = iter_cap;
-  p->h_stage->status = LP_RUNNING;
-  HIP_TRY(hipMemcpyAsync(&p->d.ctrl->max_iter, &p->h_stage->max_iter, sizeof(int64_t), hipMemcpyHostToDevice,
-                         p->stream),
-          "arming the solve");
-  HIP_TRY(hipMemcpyAsync(&p->d.ctrl->status, &p->h_stage->status, sizeof(int32_t), hipMemcpyHostToDevice, p->stream),
-          "arming the solve");
-  const bool prof = p->opt.profile != 0;
-  const int K = p->opt.iters_per_sync;
-  const bool mixed = p->d.mixed != 0;
-  const int E = mixed ? 4 : 3;
-  for (;;) {
-    const int64_t t_before = p->h_ctrl->t;
-    const int64_t fb_before = p->h_ctrl->n_fallback;
-    const int64_t cols_before = p->h_ctrl->price_cols;
-    const int64_t nsb_before = p->h_ctrl->nsb;
-    const int64_t ubytes_before = p->h_ctrl->update_bytes;
-    if (direct) {
-      if ((rc = launch_direct(p)) != LP_OK) return rc;
-    } else {
-      HIP_TRY(hipGraphLaunch(p->gexec, p->stream), "launching the iteration graph");
-    }
-    if ((rc = read_ctrl(p)) != LP_OK) return rc;
-    p->stats.syncs += 1;
-    if ((rc = collect_reinv_time(p)) != LP_OK) return rc;
-    if (prof && p->h_ctrl->status == LP_RUNNING && t_before > 0 && p->h_ctrl->t == t_before + K) {
-      // Steady state: every kernel of the replay did a full pass (K pivots, so in the
-      // mixed form no fallback iteration and no FP64 pass).
-      for (int k = 0; k < K; ++k) {
-        float ms[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int i = 0; i < E; ++i) {
-          // profile = 1: between the event nodes around kernel i (its launch gap
-          // included); profile = 2: the kernel's own start and stop.
-          const int a = direct ? 2 * (E * k + i) : E * k + i;
-          HIP_TRY(hipEventElapsedTime(&ms[i], p->events[a], p->events[a + 1]), "reading profile events");
-        }
-        const int o = mixed ? 2 : 1;
-        if (mixed) {
-          p->stats.price32_ms += ms[0];
-          p->stats.shortlist_ms += ms[1];
-        } else {
-          p->stats.price_ms += ms[0];
-        }
-        p->stats.update_ms += ms[o];
-        p->stats.finish_ms += ms[o + 1];
-      }
-      if (!mixed) p->stats.price_launches += K;
-      p->stats.update_launches += K;
-      p->stats.finish_launches += K;
-      p->stats.price_bytes += 8.0 * p->m * (double)(p->h_ctrl->price_cols - cols_before);
-      // algorithmic bytes of the update passes, counted on the device
-      p->stats.update_bytes += (double)(p->h_ctrl->update_bytes - ubytes_before);
-      if (mixed) {
-        // Nonbasic structural columns streamed by the K screening passes (the basis
-        // changes by at most one structural column per pivot; the midpoint is used).
-        const double nonbasic = p->n - 0.5 * (double)(nsb_before + p->h_ctrl->nsb);
-        p->stats.price32_bytes += 4.0 * p->m * nonbasic * K;
-      }
-    }
-    if (p->h_ctrl->status == LP_OPTIMAL && p->phase == 1) {
-      if ((rc = phase_switch(p)) != LP_OK) return rc;
-      if (p->h_ctrl->status == LP_RUNNING) continue;
-    }
-    if (p->h_ctrl->status != LP_RUNNING) break;
-    // Every iteration of a RUNNING solve's replay must pivot, or (mixed form) end with the
-    // fallback verdict; anything else is a fault of the kernels' control logic, reported
-    // instead of looping.
-    if (p->h_ctrl->t + p->h_ctrl->n_fallback != t_before + fb_before + K)
-      return fail(LP_ERR_DEVICE, "iteration graph made no progress while RUNNING");
-    // (reinversion recomputes W from the structural basic variables only: not in phase 1)
-    if (p->reinv_period > 0 && p->phase != 1 && p->h_ctrl->t - p->last_reinv_t >= p->reinv_period) {
-      if ((rc = run_reinversion(p)) != LP_OK) return rc;
-    }
-  }
-  p->stats.solve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  if (status_out) *status_out = p->h_ctrl->status;
-  return LP_OK;
+  return run_until(p, iter_cap, true, status_out);
+} catch (...) {
+  return host_exception();
+}
+
+int lp_iterate(lp_problem* p, int64_t count, int32_t* status_out) try {
+  if (!p) return fail(LP_ERR_ARG, "p is NULL");
+  if (count < 0) return fail(LP_ERR_ARG, "count must be >= 0");
+  if (count > INT32_MAX - p->h_ctrl->t) return fail(LP_ERR_ARG, "count too large");
+  return run_until(p, p->h_ctrl->t + count, false, status_out);
 } catch (...) {
   return host_exception();
 }
@@ -951,11 +1101,19 @@ int lp_get_tableau(const lp_problem* pc, double* Binv, double* xB, double* W, do
   lp_problem* p = const_cast<lp_problem*>(pc);
   const int m = p->m;
   if (p->h_ctrl->r >= 0) return fail(LP_ERR_STATE, "a pivot is pending; call lp_solve to completion first");
-  if (Binv)
-    HIP_TRY(p->ld == m ? pageable_copy(Binv, p->d.Binv, sizeof(double) * (size_t)m * m, hipMemcpyDeviceToHost, p->stream)
-                       : pageable_copy_2d(Binv, sizeof(double) * m, p->d.Binv, sizeof(double) * p->ld,
-                                          sizeof(double) * m, m, hipMemcpyDeviceToHost, p->stream),
+  if (Binv) {
+    // one contiguous copy, unpacked on the host when rows are padded (ld > m)
+    std::vector<double> rows;
+    double* dst = Binv;
+    if (p->ld != m) {
+      rows.resize((size_t)m * p->ld);
+      dst = rows.data();
+    }
+    HIP_TRY(pageable_copy(dst, p->d.Binv, sizeof(double) * (size_t)m * p->ld, hipMemcpyDeviceToHost, p->stream),
             "reading B^-1");
+    if (p->ld != m)
+      for (int i = 0; i < m; ++i) std::memcpy(Binv + (size_t)i * m, &rows[(size_t)i * p->ld], sizeof(double) * m);
+  }
   if (xB) HIP_TRY(pageable_copy(xB, p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
   if (W)
     HIP_TRY(pageable_copy(W, p->h_ctrl->wcur ? p->d.W1 : p->d.W0, sizeof(double) * m, hipMemcpyDeviceToHost,
@@ -1002,6 +1160,92 @@ int lp_reinvert(lp_problem* p) try {
 }
 
 void lp_destroy(lp_problem* p) { release(p); }
+
+int lp_solve_device_noalloc(int32_t m, int32_t n, const double* A_colmajor, const double* b, const double* c,
+                            const lp_options* opt, double* x, double* y, double* objective, int32_t* status,
+                            int64_t* iterations) try {
+  if (m <= 0 || n < 0) return fail(LP_ERR_ARG, "need m > 0 and n >= 0");
+  if (m > LP_MAX_ROWS) return fail(LP_ERR_ARG, "m exceeds LP_MAX_ROWS");
+  if ((int64_t)n + m > INT32_MAX / 2) return fail(LP_ERR_ARG, "n + m too large");
+  if (!b || (n > 0 && (!A_colmajor || !c))) return fail(LP_ERR_ARG, "NULL data pointer");
+  lp_options o;
+  lp_default_options(&o);
+  if (opt) o = *opt;
+  if (int rc = check_options(&o)) return rc;
+  if (o.precision != LP_FP64 || o.reinv_period > 0)
+    return fail(LP_ERR_ARG, "lp_solve_device_noalloc runs the FP64 form without reinversion only");
+  if (o.profile != 0) return fail(LP_ERR_ARG, "lp_solve_device_noalloc does not profile");
+  if (o.max_iter == 0) o.max_iter = 10 * ((int64_t)m + n);
+  if (o.max_iter > INT32_MAX) return fail(LP_ERR_ARG, "pivot limit above 2^31-1");
+  hipStream_t s = static_cast<hipStream_t>(o.stream);
+  int dev = 0, num_cu = 0;
+  HIP_TRY(hipGetDevice(&dev), "selecting the device");
+  HIP_TRY(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev), "querying the device");
+  DevLP d{};
+  int upd_block = 0, rc = LP_OK;
+  if ((rc = iteration_grids(m, n, num_cu, &d.price_grid, &d.update_grid, &upd_block)) != LP_OK) return rc;
+  double *b0 = nullptr, *c0 = nullptr;
+  int32_t* flag = nullptr;
+  {
+    Carver count{nullptr};
+    const size_t need = carve_lp(count, d, m, n, o.max_iter, &b0, &c0, &flag);
+    if (need > kScratchBytes)
+      return fail(LP_ERR_ARG, "LP needs " + std::to_string(need) + " bytes, beyond the " +
+                                  std::to_string(kScratchBytes) + "-byte array of lp_solve_device_noalloc");
+  }
+  unsigned char* base = nullptr;
+  if ((rc = scratch_address(dev, &base)) != LP_OK) return rc;
+  Carver cv{base};
+  carve_lp(cv, d, m, n, o.max_iter, &b0, &c0, &flag);
+  d.m = m;
+  d.n = n;
+  d.ld = (int32_t)round_up(m, 8);
+  d.upd_block = upd_block;
+  d.log_cap = o.max_iter;
+  d.Lcap = (int32_t)o.max_iter;
+  d.tenure = o.tabu_tenure;
+  d.use_llist = o.leaving_list ? 1 : 0;
+  d.eps_d = o.eps_d;
+  d.eps_p = o.eps_p;
+  d.eps_z = o.eps_z;
+  d.eps_t = o.eps_t;
+  d.sl_k = o.shortlist_k;
+  // Inputs: packed into the padded layout and validated on the device.
+  HIP_TRY(launch_clear_flag(flag, s), "validating the LP");
+  HIP_TRY(launch_pack_lp(const_cast<double*>(d.A), d.ld, A_colmajor, m, n, b0, b, c0, c, flag, s),
+          "copying the LP");
+  int32_t hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s), "validating the LP");
+  HIP_TRY(hipStreamSynchronize(s), "validating the LP");
+  if (hflag & 1) return fail(LP_ERR_ARG, "A, b or c contains a non-finite value");
+  if (hflag & 2) return fail(LP_ERR_NEG_RHS, "b_i < 0: the slack basis is infeasible");
+  HIP_TRY(launch_init(d, b0, c0, o.sense == LP_MAX ? -1.0 : 1.0, s), "initialising the slack basis");
+  HIP_TRY(launch_arm(d.ctrl, o.max_iter, s), "arming the solve");
+  // Iterations launched directly (a graph would be created and instantiated), iters_per_sync
+  // per read-back of the control block; the kernels do nothing once the status has changed.
+  Ctrl hc{};
+  const int K = o.iters_per_sync;
+  int64_t t_before = 0;
+  for (;;) {
+    for (int k = 0; k < K; ++k) {
+      HIP_TRY(launch_price(d, d.price_grid, s), "launching the pricing kernel");
+      HIP_TRY(launch_update(d, d.update_grid, s), "launching the update kernel");
+      HIP_TRY(launch_finish(d, s), "launching the finishing kernel");
+    }
+    HIP_TRY(hipMemcpyAsync(&hc, d.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s), "reading status");
+    HIP_TRY(hipStreamSynchronize(s), "reading status");
+    if (hc.status != LP_RUNNING) break;
+    if (hc.t != t_before + K) return fail(LP_ERR_DEVICE, "iterations made no progress while RUNNING");
+    t_before = hc.t;
+  }
+  HIP_TRY(launch_solution(d, c0, o.sense == LP_MAX ? -1.0 : 1.0, x, y, objective, s), "writing the solution");
+  HIP_TRY(hipStreamSynchronize(s), "writing the solution");
+  if (status) *status = hc.status;
+  if (iterations) *iterations = hc.t;
+  return LP_OK;
+} catch (...) {
+  return host_exception();
+}
 
 const char* lp_error_string(int code) {
   static thread_local std::string text;

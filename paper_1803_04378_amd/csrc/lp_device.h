@@ -176,6 +176,17 @@ __host__ __device__ __forceinline__ bool sparse_columns(int nD, int ld) {
   return ld >= kSparseMinLd && nD * 8 <= ld;
 }
 
+// One term of the upload check's hash: the SplitMix64 finaliser (Steele, Lea & Flood,
+// OOPSLA 2014) of a double's bit pattern mixed with its index; the hash of an array is the
+// wrapping sum of its terms, so it does not depend on the order they are added in.
+__host__ __device__ __forceinline__ uint64_t hash_word(uint64_t bits, uint64_t index) {
+  uint64_t z = bits ^ (index * 0x9E3779B97F4A7C15ull);
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // Launchers (lp_kernels.hip).  grid sizes are chosen by the caller.
 hipError_t launch_init(const DevLP& lp, const double* b, const double* c, double sense, hipStream_t s);
 hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s);
@@ -183,6 +194,19 @@ hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s);
 hipError_t launch_finish(const DevLP& lp, hipStream_t s);
 // Sets *flag when some |x_k| exceeds bound (or is NaN).
 hipError_t launch_check_finite(const double* x, int64_t count, double bound, int32_t* flag, hipStream_t s);
+// Entry point without allocation: *flag = 0; A' packed into ld x n with zero padding, b and
+// c copied, bit 1 of *flag for non-finite data, bit 2 for b_i < 0; the pivot limit armed;
+// x, y = ysign W and the objective written to device memory.
+hipError_t launch_clear_flag(int32_t* flag, hipStream_t s);
+// *out = the hash of x (nx doubles, indices base..), then of y (ny, indices base + nx ..) and
+// z (nz, after y); out is cleared first.
+hipError_t launch_hash(const double* x, size_t nx, uint64_t base, const double* y, size_t ny, const double* z,
+                       size_t nz, unsigned long long* out, hipStream_t s);
+hipError_t launch_pack_lp(double* dA, int ld, const double* A, int m, int n, double* b0, const double* b, double* c0,
+                          const double* c, int32_t* flag, hipStream_t s);
+hipError_t launch_arm(Ctrl* ctl, int64_t max_iter, hipStream_t s);
+hipError_t launch_solution(const DevLP& lp, const double* c, double ysign, double* x, double* y, double* objective,
+                           hipStream_t s);
 // Kernel entry points for explicit graph construction.
 const void* price_kernel();
 const void* update_kernel(int ld);

@@ -348,6 +348,8 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
   hold_store<B>(hold, s_rho, rho2, tid, ld2);
   if (tid < dcap) s_dl[tid] = dl0;
   if (tid + B < dcap) s_dl[tid + B] = dl1;
+  // (ld/8 exceeds 2B only for 512-thread workgroups above ld = 8192)
+  for (int k = tid + 2 * B; k < dcap; k += B) s_dl[k] = lp.dlist[k];
 
   // Step 4 decision: in the mixed form from the re-priced shortlist (none improving: the
   // fallback verdict below), else, and in the mixed form's FP64 pass, from the pricing
@@ -883,6 +885,95 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Helpers of the entry point that allocates nothing (its buffers live in a fixed array).
+
+// *flag = 0 (a kernel rather than a memset, so that a captured stream holds no memset node).
+__global__ void k_clear_flag(int32_t* flag) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+}
+
+// Copies the caller's A' (m x n, column-major, lda = m) into the padded ld x n layout with
+// zero padding, and b, c into b0, c0; sets bit 1 of *flag for a non-finite entry of A', b
+// or c, bit 2 for some b_i < 0.
+__global__ void k_pack_lp(double* __restrict__ dA, int ld, const double* __restrict__ A, int m, int n,
+                          double* __restrict__ b0, const double* __restrict__ b, double* __restrict__ c0,
+                          const double* __restrict__ c, int32_t* flag) {
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  const size_t total = (size_t)ld * n;
+  for (size_t k = tid; k < total; k += stride) {
+    const size_t j = k / ld, i = k - j * ld;
+    double v = 0.0;
+    if (i < (size_t)m) {
+      v = A[j * m + i];
+      bad |= isfinite(v) ? 0 : 1;
+    }
+    dA[k] = v;
+  }
+  for (size_t i = tid; i < (size_t)m; i += stride) {
+    const double v = b[i];
+    b0[i] = v;
+    bad |= isfinite(v) ? 0 : 1;
+    bad |= v < 0.0 ? 2 : 0;
+  }
+  for (size_t j = tid; j < (size_t)n; j += stride) {
+    const double v = c[j];
+    c0[j] = v;
+    bad |= isfinite(v) ? 0 : 1;
+  }
+  if (bad) atomicOr(flag, bad);
+}
+
+// Adds the hash terms of x[0..nx) (indices base + k), y and z (indices following x's) to *out.
+__global__ void k_hash(const double* __restrict__ x, size_t nx, uint64_t base, const double* __restrict__ y, size_t ny,
+                       const double* __restrict__ z, size_t nz, unsigned long long* out) {
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  uint64_t h = 0;
+  for (size_t k = tid; k < nx; k += stride) h += hash_word(__double_as_longlong(x[k]), base + k);
+  for (size_t k = tid; k < ny; k += stride) h += hash_word(__double_as_longlong(y[k]), base + nx + k);
+  for (size_t k = tid; k < nz; k += stride) h += hash_word(__double_as_longlong(z[k]), base + nx + ny + k);
+  if (h) atomicAdd(out, (unsigned long long)h);
+}
+
+__global__ void k_clear_u64(unsigned long long* out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *out = 0;
+}
+
+// The pivot limit and the RUNNING status of a fresh solve.
+__global__ void k_arm(Ctrl* ctl, int64_t max_iter) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->max_iter = max_iter;
+    ctl->status = kStatusRunning;
+  }
+}
+
+// x (n), y = ysign * W (m) and the objective sum_j c_j x_j over structural basics in
+// ascending j (the order of lp_get_solution); any pointer may be null.
+__global__ void k_solution(DevLP lp, const double* __restrict__ c, double ysign, double* __restrict__ x,
+                           double* __restrict__ y, double* __restrict__ objective) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  const double* W = lp.ctrl->wcur ? lp.W1 : lp.W0;
+  if (x)
+    for (int j = tid; j < lp.n; j += stride) {
+      const int r = lp.pos[j];
+      x[j] = r >= 0 ? lp.xB[r] : 0.0;
+    }
+  if (y)
+    for (int i = tid; i < lp.m; i += stride) y[i] = ysign * W[i];
+  if (objective && tid == 0) {
+    double s = 0.0;
+    for (int j = 0; j < lp.n; ++j) {
+      const int r = lp.pos[j];
+      if (r >= 0) s = __dadd_rn(s, __dmul_rn(c[j], lp.xB[r]));
+    }
+    *objective = s;
+  }
+}
+
 // Sets *flag when some |x_k| exceeds bound or is NaN.
 __global__ void k_check_finite(const double* __restrict__ x, int64_t count, double bound, int32_t* flag) {
   const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -970,6 +1061,40 @@ hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s) {
 
 hipError_t launch_finish(const DevLP& lp, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_flag(int32_t* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, s, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash(const double* x, size_t nx, uint64_t base, const double* y, size_t ny, const double* z,
+                       size_t nz, unsigned long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, s, out);
+  const size_t work = std::max(nx, std::max(ny, nz));
+  const int grid = (int)std::max<size_t>(1, std::min<size_t>(2048, (work + 255) / 256));
+  hipLaunchKernelGGL(k_hash, dim3(grid), dim3(256), 0, s, x, nx, base, y, ny, z, nz, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_lp(double* dA, int ld, const double* A, int m, int n, double* b0, const double* b, double* c0,
+                          const double* c, int32_t* flag, hipStream_t s) {
+  const size_t work = std::max<size_t>((size_t)ld * n, (size_t)std::max(m, n));
+  const int grid = (int)std::min<size_t>(4096, (work + 255) / 256);
+  hipLaunchKernelGGL(k_pack_lp, dim3(grid), dim3(256), 0, s, dA, ld, A, m, n, b0, b, c0, c, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_arm(Ctrl* ctl, int64_t max_iter, hipStream_t s) {
+  hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, s, ctl, max_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_solution(const DevLP& lp, const double* c, double ysign, double* x, double* y, double* objective,
+                           hipStream_t s) {
+  const int grid = (int)std::min<int>(256, (std::max(lp.m, lp.n) + 255) / 256);
+  hipLaunchKernelGGL(k_solution, dim3(grid), dim3(256), 0, s, lp, c, ysign, x, y, objective);
   return hipGetLastError();
 }
 
