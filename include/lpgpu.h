@@ -114,6 +114,17 @@ typedef struct lp_options {
   int32_t batch_binv_lds_m; /* batched solver: wide LPs with m <= this keep B^-1 in LDS (run by a
                              second persistent launch); 0 = never; -1 = the threshold is chosen by
                              timing the whole batch on its first solve (default) */
+  int64_t device_budget;  /* bytes of device memory the LP may use (Section 3, Figure 2): 0 = the free
+                             memory hipMemGetInfo reports (default); > 0 = at most this much.  When
+                             the whole tableau fits, it stays in device memory for the whole solve
+                             (Case 1).  Otherwise (Case 2) B^-1 is kept in pinned host memory in panels
+                             of consecutive rows: every iteration streams each panel to the device,
+                             updates it (with FTRAN and the ratio test of its rows) and streams it
+                             back, except the last panel, which stays in device memory; row r is
+                             fetched once per iteration for the pricing step.  Case 2 needs A', the
+                             vectors and three panel buffers in the budget, runs the FP64 form
+                             without reinversion and without profiling, and is not available to
+                             lp_create_general (LP_ERR_ARG); results equal Case 1's bit for bit. */
 } lp_options;
 
 typedef struct lp_stats {
@@ -156,6 +167,10 @@ typedef struct lp_stats {
                                 drive-outs); -1 while phase 1 runs or when it was not needed */
   int64_t drive_outs;       /* pivots flagged LP_PIVOT_DRIVEOUT */
   double phase_switch_ms;   /* host wall time of the switch (drive-outs and re-pricing) */
+  int64_t memory_case;      /* 1: the tableau is in device memory (Section 3, Case 1); 2: B^-1 is
+                               streamed in row panels from host memory (Case 2) */
+  int64_t panel_rows;       /* Case 2: rows of B^-1 per panel (0 in Case 1) */
+  int64_t panels;           /* Case 2: panels, the last one resident in device memory (0 in Case 1) */
 } lp_stats;
 
 typedef struct lp_problem lp_problem;

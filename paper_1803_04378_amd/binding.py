@@ -42,6 +42,7 @@ class lp_options(C.Structure):
         ("shortlist_k", C.c_int32),
         ("reinv_period", C.c_int32),
         ("batch_binv_lds_m", C.c_int32),
+        ("device_budget", C.c_int64),
     ]
 
 
@@ -74,6 +75,9 @@ class lp_stats(C.Structure):
         ("phase1_iterations", C.c_int64),
         ("drive_outs", C.c_int64),
         ("phase_switch_ms", C.c_double),
+        ("memory_case", C.c_int64),
+        ("panel_rows", C.c_int64),
+        ("panels", C.c_int64),
     ]
 
 

@@ -169,6 +169,15 @@ struct lp_problem {
   int64_t phase1_t = -1;
   int64_t drive_outs = 0;
   double switch_ms = 0.0;
+  // Out-of-core panel mode (Section 3, Case 2): B^-1 in pinned host memory, streamed in
+  // panels of panel_rows rows; the last panel (rows res_lo..m-1) stays on the device.
+  bool panel = false;
+  int panel_rows = 0, npanels = 0, res_lo = 0;
+  double* binv_host = nullptr;      // m x ld, pinned
+  double* binv_host_dev = nullptr;  // its address for kernels
+  double* pbuf[2] = {nullptr, nullptr};
+  double* res = nullptr;
+  double* rowbuf = nullptr;  // row r of B^-1 for the pricing kernel
 };
 
 namespace {
@@ -217,6 +226,7 @@ void release(lp_problem* p) {
   p->allocs.clear();
   if (p->h_ctrl) (void)hipHostFree(p->h_ctrl);
   if (p->h_stage) (void)hipHostFree(p->h_stage);
+  if (p->binv_host) (void)hipHostFree(p->binv_host);
   reinv_free(p->rv);
   for (hipEvent_t e : p->rv_ev)
     if (e) (void)hipEventDestroy(e);
@@ -235,6 +245,7 @@ int check_options(const lp_options* o) {
     return fail(LP_ERR_ARG, "options.precision must be LP_FP64 or LP_MIXED");
   if (o->shortlist_k < 1 || o->shortlist_k > kShortlist) return fail(LP_ERR_ARG, "options.shortlist_k must be in [1, 16]");
   if (o->reinv_period < -1) return fail(LP_ERR_ARG, "options.reinv_period must be >= -1");
+  if (o->device_budget < 0) return fail(LP_ERR_ARG, "options.device_budget must be >= 0");
   if (!(o->eps_d >= 0.0) || !(o->eps_p >= 0.0) || !(o->eps_z >= 0.0) || !(o->eps_t >= 0.0) ||
       !std::isfinite(o->eps_d) || !std::isfinite(o->eps_p) || !std::isfinite(o->eps_z) || !std::isfinite(o->eps_t))
     return fail(LP_ERR_ARG, "options.eps_* must be finite and >= 0");
@@ -398,6 +409,63 @@ int launch_direct(lp_problem* p, int K) {
   return LP_OK;
 }
 
+// Out-of-core panel mode: B^-1 = I in the pinned host copy (after the stream has drained)
+// and in the device-resident last panel.
+int init_panels(lp_problem* p) {
+  if (!p->panel) return LP_OK;
+  const int m = p->m, ld = p->ld;
+  HIP_TRY(hipStreamSynchronize(p->stream), "initialising B^-1");
+  std::memset(p->binv_host, 0, sizeof(double) * (size_t)m * ld);
+  for (int i = 0; i < m; ++i) p->binv_host[(size_t)i * ld + i] = 1.0;
+  HIP_TRY(hipMemcpyAsync(p->res, p->binv_host + (size_t)p->res_lo * ld, sizeof(double) * (size_t)(m - p->res_lo) * ld,
+                         hipMemcpyHostToDevice, p->stream),
+          "initialising B^-1");
+  HIP_TRY(hipStreamSynchronize(p->stream), "initialising B^-1");
+  return LP_OK;
+}
+
+// Out-of-core panel mode: k iterations launched directly.  Each runs the pricing kernel,
+// then for every panel (in row order) a copy to the device, the update kernel on its rows
+// (partials in its own slice) and a copy back, except for the resident last panel; then the
+// finishing kernel over every panel's partials and the fetch of row r for the next pricing.
+int launch_panel_iters(lp_problem* p, int k) {
+  hipStream_t s = p->stream;
+  const int ld = p->ld, P = p->panel_rows, np = p->npanels, g = p->update_grid;
+  const size_t row_bytes = sizeof(double) * ld;
+  DevLP fin = p->d;
+  fin.update_grid = g * np;
+  for (int it = 0; it < k; ++it) {
+    HIP_TRY(launch_price(p->d, p->price_grid, s), "launching the pricing kernel");
+    for (int pi = 0; pi < np; ++pi) {
+      const int lo = pi * P, hi = std::min(p->m, lo + P);
+      const bool resident = pi == np - 1;
+      double* dev = resident ? p->res : p->pbuf[pi & 1];
+      if (!resident)
+        HIP_TRY(hipMemcpyAsync(dev, p->binv_host + (size_t)lo * ld, (hi - lo) * row_bytes, hipMemcpyHostToDevice, s),
+                "streaming a panel of B^-1 to the device");
+      DevLP dp = p->d;
+      dp.Binv = dev;
+      dp.row_lo = lo;
+      dp.row_hi = hi;
+      const size_t off = (size_t)pi * g;
+      dp.part_th += off;
+      dp.part_low += off;
+      dp.part_t1 += off;
+      dp.part_t2 += off;
+      dp.part_al += off;
+      dp.part_bv += off;
+      HIP_TRY(launch_update(dp, g, s), "launching the update kernel");
+      if (!resident)
+        HIP_TRY(hipMemcpyAsync(p->binv_host + (size_t)lo * ld, dev, (hi - lo) * row_bytes, hipMemcpyDeviceToHost, s),
+                "streaming a panel of B^-1 back");
+    }
+    HIP_TRY(launch_finish(fin, s), "launching the finishing kernel");
+    HIP_TRY(launch_fetch_row(p->d.ctrl, p->binv_host_dev, p->res, p->res_lo, ld, p->rowbuf, s),
+            "fetching the pivot row");
+  }
+  return LP_OK;
+}
+
 // Workgroup counts of the iteration kernels for an m x n LP (FP64 form) on a device with
 // num_cu compute units, from the occupancy the kernels' LDS allows.
 int iteration_grids(int32_t m, int32_t n, int num_cu, int* price_grid, int* update_grid, int* upd_block) {
@@ -498,14 +566,29 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
     p->price_grid = p->price32_grid;
   }
 
-  // Device memory: A' (ld x n) + B^-1 (m x ld) dominate.
+  // Device memory (Section 3, Figure 2): A' (ld x n) + B^-1 (m x ld) dominate.  Against the
+  // free memory, or the caller's budget: the whole tableau (Case 1), or B^-1 in row panels
+  // streamed from host memory (Case 2).
   {
     size_t freeb = 0, totalb = 0;
     hipError_t e = hipMemGetInfo(&freeb, &totalb);
     if (e != hipSuccess) return bail(fail_hip(e, "querying device memory"));
-    const double need = (mixed ? 12.0 : 8.0) * ld * (double)n + 8.0 * m * (double)ld + 64.0 * N + 64.0 * ld +
-                        64.0 * o.max_iter;
-    if (need > (double)freeb) return bail(fail(LP_ERR_NOMEM, "LP does not fit in free device memory"));
+    const double budget = o.device_budget > 0 ? std::min((double)o.device_budget, (double)freeb) : (double)freeb;
+    const double rest = (mixed ? 12.0 : 8.0) * ld * (double)n + 64.0 * N + 64.0 * ld + 64.0 * o.max_iter +
+                        16.0 * (p->update_grid + p->price_grid) * 8.0;
+    const double binv = 8.0 * m * (double)ld;
+    if (rest + binv > budget) {
+      // three panel buffers: two streamed alternately and the resident last panel
+      const double rows = std::floor((budget - rest) / (3.0 * 8.0 * ld));
+      if (rows < 8) return bail(fail(LP_ERR_NOMEM, "LP does not fit in the device memory budget"));
+      if (mixed || p->reinv_period > 0 || o.profile != 0)
+        return bail(fail(LP_ERR_ARG, "B^-1 does not fit the device memory budget; the out-of-core panel mode runs "
+                                     "the FP64 form without reinversion or profiling"));
+      p->panel = true;
+      p->panel_rows = (int)std::min<double>(rows, m);
+      p->npanels = (m + p->panel_rows - 1) / p->panel_rows;
+      p->res_lo = (p->npanels - 1) * p->panel_rows;
+    }
   }
   double* dA = nullptr;
   double* chat = nullptr;
@@ -516,7 +599,15 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   } while (0)
   ALLOC(dA, (size_t)ld * std::max(n, 1));
   ALLOC(chat, (size_t)N);
-  ALLOC(p->d.Binv, (size_t)m * ld);
+  const size_t nparts_u = (size_t)p->update_grid * (p->panel ? p->npanels : 1);
+  if (p->panel) {
+    ALLOC(p->pbuf[0], (size_t)p->panel_rows * ld);
+    ALLOC(p->pbuf[1], (size_t)p->panel_rows * ld);
+    ALLOC(p->res, (size_t)(m - p->res_lo) * ld);
+    ALLOC(p->rowbuf, (size_t)ld);
+  } else {
+    ALLOC(p->d.Binv, (size_t)m * ld);
+  }
   ALLOC(p->d.xB, (size_t)m);
   ALLOC(p->d.W0, (size_t)ld);
   ALLOC(p->d.W1, (size_t)ld);
@@ -532,12 +623,12 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   ALLOC(p->d.excl, (size_t)N);
   ALLOC(p->d.part_d, 2 * (size_t)p->price_grid);
   ALLOC(p->d.part_j, 2 * (size_t)p->price_grid);
-  ALLOC(p->d.part_th, (size_t)p->update_grid);
-  ALLOC(p->d.part_low, (size_t)p->update_grid);
-  ALLOC(p->d.part_t1, (size_t)p->update_grid);
-  ALLOC(p->d.part_t2, (size_t)p->update_grid);
-  ALLOC(p->d.part_al, (size_t)p->update_grid);
-  ALLOC(p->d.part_bv, (size_t)p->update_grid);
+  ALLOC(p->d.part_th, nparts_u);
+  ALLOC(p->d.part_low, nparts_u);
+  ALLOC(p->d.part_t1, nparts_u);
+  ALLOC(p->d.part_t2, nparts_u);
+  ALLOC(p->d.part_al, nparts_u);
+  ALLOC(p->d.part_bv, nparts_u);
   ALLOC(p->d.ctrl, 1);
   ALLOC(p->b0, (size_t)m);
   ALLOC(p->c0, (size_t)std::max(n, 1));
@@ -567,6 +658,16 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   p->d.sl_k = o.shortlist_k;
   p->d.A32 = dA32;
   p->d.price32_grid = p->price32_grid;
+  p->d.row_lo = 0;
+  p->d.row_hi = m;
+  p->d.rowsrc = p->panel ? p->rowbuf : nullptr;
+  if (p->panel) {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p->binv_host), sizeof(double) * (size_t)m * ld,
+                                 hipHostMallocDefault);
+    if (e != hipSuccess) return bail(fail_hip(e, "allocating pinned memory for B^-1"));
+    e = hipHostGetDevicePointer(reinterpret_cast<void**>(&p->binv_host_dev), p->binv_host, 0);
+    if (e != hipSuccess) return bail(fail_hip(e, "mapping the host copy of B^-1"));
+  }
   {
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p->h_ctrl), sizeof(Ctrl), hipHostMallocDefault);
     if (e != hipSuccess) return bail(fail_hip(e, "allocating pinned memory"));
@@ -635,6 +736,7 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   }
   e = launch_init(p->d, p->b0, p->c0, o.sense == LP_MAX ? -1.0 : 1.0, s);
   if (e != hipSuccess) return bail(fail_hip(e, "initialising the slack basis"));
+  if ((rc = init_panels(p)) != LP_OK) return bail(rc);
   if ((rc = read_ctrl(p)) != LP_OK) return bail(rc);
   if (p->reinv_period > 0 && (rc = reinv_prepare(&p->rv, m, ld)) != LP_OK) return bail(rc);
   p->hc = std::move(hc);
@@ -710,7 +812,7 @@ int run_until(lp_problem* p, int64_t iter_cap, bool decide, int32_t* status_out)
   // (drive-out pivots of a phase switch may add up to m log entries past the limit)
   if ((rc = ensure_capacity(p, iter_cap + (p->phase == 1 ? p->m : 0))) != LP_OK) return rc;
   const bool direct = p->opt.profile == 2;
-  if (!direct && (!p->gexec || p->graph_k != p->opt.iters_per_sync)) {
+  if (!direct && !p->panel && (!p->gexec || p->graph_k != p->opt.iters_per_sync)) {
     if ((rc = build_graph(p)) != LP_OK) return rc;
   }
   if (!decide && p->h_ctrl->t >= iter_cap) {
@@ -743,7 +845,9 @@ int run_until(lp_problem* p, int64_t iter_cap, bool decide, int32_t* status_out)
     const int64_t cols_before = p->h_ctrl->price_cols;
     const int64_t nsb_before = p->h_ctrl->nsb;
     const int64_t ubytes_before = p->h_ctrl->update_bytes;
-    if (direct) {
+    if (p->panel) {
+      if ((rc = launch_panel_iters(p, k)) != LP_OK) return rc;
+    } else if (direct) {
       if ((rc = launch_direct(p, k)) != LP_OK) return rc;
     } else if (k == K) {
       HIP_TRY(hipGraphLaunch(p->gexec, p->stream), "launching the iteration graph");
@@ -910,6 +1014,7 @@ int lp_default_options(lp_options* opt) try {
   opt->precision = LP_FP64;
   opt->shortlist_k = kShortlist;
   opt->reinv_period = -1;
+  opt->device_budget = 0;
   return LP_OK;
 } catch (...) {
   return host_exception();
@@ -975,6 +1080,7 @@ int lp_create_general(lp_problem** out, int32_t m, int32_t n, const double* A_co
   const auto drop = on_scope_exit([&] {  // an exception before the hand-over releases it too
     if (p) release(p);
   });
+  if (p->panel) return bail(fail(LP_ERR_ARG, "the two-phase start needs the tableau in device memory (Case 1)"));
   p->n_user = n;
   p->rsign = std::move(sg);
   p->eps_f = 1e-9 * (1.0 + bmax);
@@ -1033,7 +1139,9 @@ int lp_solve(lp_problem* p, int32_t* status_out) try {
 int lp_reset(lp_problem* p) try {
   if (!p) return fail(LP_ERR_ARG, "p is NULL");
   HIP_TRY(launch_init(p->d, p->b0, p->c0, p->opt.sense == LP_MAX ? -1.0 : 1.0, p->stream), "resetting");
-  int rc = read_ctrl(p);
+  int rc = init_panels(p);
+  if (rc != LP_OK) return rc;
+  rc = read_ctrl(p);
   if (rc != LP_OK) return rc;
   p->rv_timing = false;
   p->last_reinv_t = 0;
@@ -1102,16 +1210,25 @@ int lp_get_tableau(const lp_problem* pc, double* Binv, double* xB, double* W, do
   const int m = p->m;
   if (p->h_ctrl->r >= 0) return fail(LP_ERR_STATE, "a pivot is pending; call lp_solve to completion first");
   if (Binv) {
-    // one contiguous copy, unpacked on the host when rows are padded (ld > m)
+    // one contiguous copy, unpacked on the host when rows are padded (ld > m); in the
+    // out-of-core mode the host copy holds every row but the resident panel's
     std::vector<double> rows;
     double* dst = Binv;
-    if (p->ld != m) {
+    if (p->ld != m || p->panel) {
       rows.resize((size_t)m * p->ld);
       dst = rows.data();
     }
-    HIP_TRY(pageable_copy(dst, p->d.Binv, sizeof(double) * (size_t)m * p->ld, hipMemcpyDeviceToHost, p->stream),
-            "reading B^-1");
-    if (p->ld != m)
+    if (p->panel) {
+      HIP_TRY(hipStreamSynchronize(p->stream), "reading B^-1");
+      std::memcpy(dst, p->binv_host, sizeof(double) * (size_t)p->res_lo * p->ld);
+      HIP_TRY(pageable_copy(dst + (size_t)p->res_lo * p->ld, p->res, sizeof(double) * (size_t)(m - p->res_lo) * p->ld,
+                            hipMemcpyDeviceToHost, p->stream),
+              "reading B^-1");
+    } else {
+      HIP_TRY(pageable_copy(dst, p->d.Binv, sizeof(double) * (size_t)m * p->ld, hipMemcpyDeviceToHost, p->stream),
+              "reading B^-1");
+    }
+    if (dst != Binv)
       for (int i = 0; i < m; ++i) std::memcpy(Binv + (size_t)i * m, &rows[(size_t)i * p->ld], sizeof(double) * m);
   }
   if (xB) HIP_TRY(pageable_copy(xB, p->d.xB, sizeof(double) * m, hipMemcpyDeviceToHost, p->stream), "reading x_B");
@@ -1140,6 +1257,9 @@ int lp_get_stats(const lp_problem* p, lp_stats* s) try {
   s->reinversions = p->h_ctrl->n_reinv;
   s->reinv_failed = p->h_ctrl->n_reinv_failed;
   s->phase1_iterations = p->phase1_t;
+  s->memory_case = p->panel ? 2 : 1;
+  s->panel_rows = p->panel ? p->panel_rows : 0;
+  s->panels = p->panel ? p->npanels : 0;
   s->drive_outs = p->drive_outs;
   s->phase_switch_ms = p->switch_ms;
   return LP_OK;
@@ -1149,6 +1269,7 @@ int lp_get_stats(const lp_problem* p, lp_stats* s) try {
 
 int lp_reinvert(lp_problem* p) try {
   if (!p) return fail(LP_ERR_ARG, "p is NULL");
+  if (p->panel) return fail(LP_ERR_STATE, "no reinversion in the out-of-core panel mode");
   int rc = read_ctrl(p);  // the structural count and the list D of the current basis
   if (rc != LP_OK) return rc;
   rc = run_reinversion(p);
@@ -1201,6 +1322,9 @@ int lp_solve_device_noalloc(int32_t m, int32_t n, const double* A_colmajor, cons
   d.n = n;
   d.ld = (int32_t)round_up(m, 8);
   d.upd_block = upd_block;
+  d.row_lo = 0;
+  d.row_hi = m;
+  d.rowsrc = nullptr;
   d.log_cap = o.max_iter;
   d.Lcap = (int32_t)o.max_iter;
   d.tenure = o.tabu_tenure;

@@ -157,6 +157,12 @@ struct DevLP {
   // artificial variable of row i; such a variable is barred (pos = kPosBarred) once it
   // leaves the basis.
   const int8_t* art;
+  // Rows of B^-1 that k_update processes: row_lo..row_hi-1, row i at Binv + (i - row_lo) ld
+  // (0..m-1 unless the out-of-core panel mode launches it once per panel).
+  int32_t row_lo, row_hi;
+  // Out-of-core panel mode: device copy of row r of B^-1 for the pricing kernel (nullptr:
+  // row r is read from Binv).
+  const double* rowsrc;
 };
 
 // The top row W this iteration prices with: W + d_q rho of the pending pivot, which the
@@ -198,6 +204,10 @@ hipError_t launch_check_finite(const double* x, int64_t count, double bound, int
 // c copied, bit 1 of *flag for non-finite data, bit 2 for b_i < 0; the pivot limit armed;
 // x, y = ysign W and the objective written to device memory.
 hipError_t launch_clear_flag(int32_t* flag, hipStream_t s);
+// Out-of-core panel mode: row ctl->r of B^-1 into row (from res for rows >= res_lo, else
+// from the host copy, read through its device address).
+hipError_t launch_fetch_row(const Ctrl* ctl, const double* host, const double* res, int res_lo, int ld, double* row,
+                            hipStream_t s);
 // *out = the hash of x (nx doubles, indices base..), then of y (ny, indices base + nx ..) and
 // z (nz, after y); out is cleared first.
 hipError_t launch_hash(const double* x, size_t nx, uint64_t base, const double* y, size_t ny, const double* z,

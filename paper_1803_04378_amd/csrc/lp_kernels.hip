@@ -42,7 +42,8 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
   const int m = lp.m, n = lp.n, ld = lp.ld, N = n + m;
   const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
-  const size_t total = (size_t)m * ld;
+  // (out-of-core panel mode: B^-1 lives in host memory and is set up by the host)
+  const size_t total = lp.Binv ? (size_t)m * ld : 0;
   for (size_t k = tid; k < total; k += stride) {
     const size_t i = k / ld, j = k - i * ld;
     lp.Binv[k] = (i == j) ? 1.0 : 0.0;
@@ -123,7 +124,8 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
 
   if (r >= 0) {
     const double2* Wold = reinterpret_cast<const double2*>(wc ? lp.W1 : lp.W0);
-    const double2* rowr = reinterpret_cast<const double2*>(lp.Binv + (size_t)r * lp.ld);
+    // row r of B^-1: in the out-of-core panel mode a device copy fetched after the ratio test
+    const double2* rowr = reinterpret_cast<const double2*>(lp.rowsrc ? lp.rowsrc : lp.Binv + (size_t)r * lp.ld);
     double2* Wnew = reinterpret_cast<double2*>(wc ? lp.W0 : lp.W1);
     double2* rho2 = reinterpret_cast<double2*>(lp.rho);
     const bool writer = blockIdx.x == 0;
@@ -289,6 +291,11 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
   __shared__ int s_bv[waves * kMaxRowsPerWave];
   __shared__ int s_nf;  // some row of this workgroup has a non-finite alpha
   const int m = lp.m, n = lp.n, ld = lp.ld, ld2 = ld / 2;
+  // Rows lo..hi-1 of B^-1, row i at Binv + (i - lo) ld: all of them, or one panel of the
+  // out-of-core mode (a launch per panel; the first one also does the iteration's
+  // bookkeeping in the control block).
+  const int lo = lp.row_lo, hi = lp.row_hi;
+  const bool first_panel = lo == 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) s_nf = 0;  // read after the barriers below
   const int gw = blockIdx.x * waves + wave;
@@ -324,11 +331,12 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
     dl0 = lp.dlist[min(tid, dcap - 1)];
     dl1 = lp.dlist[min(tid + B, dcap - 1)];
   }
-  const int g0 = min(gw, m - 1);
+  const int i0 = lo + gw;  // this wavefront's first row
+  const int g0 = min(i0, hi - 1);
   double x0 = lp.xB[g0], al00 = lp.alpha0[g0], al10 = lp.alpha1[g0];
   int bv0 = lp.basis[g0];
   double2 v[kUpdBatch];
-  const bool pre_now = !can_sparse && gw < m;  // dense for certain: first batch of the row now
+  const bool pre_now = !can_sparse && i0 < hi;  // dense for certain: first batch of the row now
   if (pre_now) load_batch(reinterpret_cast<const double2*>(lp.Binv + (size_t)gw * ld), lane, ld2, v);
   double sd = __builtin_inf();
   int sj = INT_MAX;
@@ -424,7 +432,7 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
     dq = da;
     flags = kFlagAspiration;
   }
-  if (blockIdx.x == 0 && tid == 0) {
+  if (blockIdx.x == 0 && tid == 0 && first_panel) {
     // Only fields no k_update workgroup reads: the status itself changes in k_finish.
     Ctrl* cw = lp.ctrl;
     if (lp.mixed && !fb) cw->price32_launches += 1;
@@ -467,11 +475,11 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
   // unit vector): the sparse FTRAN adds its unit term, and k_finish needs it for the
   // leaving variable
   int in0 = 1;
-  if (gw < m && bv0 >= n) in0 = lp.inD[bv0 - n];
+  if (i0 < hi && bv0 >= n) in0 = lp.inD[bv0 - n];
   int c = 0;
   if (sparse) {
     double g[kGather];
-    if (gw < m) {
+    if (i0 < hi) {
       const double* row = lp.Binv + (size_t)gw * ld;
 #pragma unroll
       for (int u = 0; u < kGather; ++u) {
@@ -485,7 +493,7 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
       const int e = q - n;
       for (int k = tid; k < ld2; k += B) s_a[k] = make_double2(2 * k == e ? 1.0 : 0.0, 2 * k + 1 == e ? 1.0 : 0.0);
     }
-    if (blockIdx.x == 0) {
+    if (blockIdx.x == 0 && first_panel) {
       // bytes: D entries read in every row but r, the changed ones written in every
       // row, and one unit lookup (basis, membership, a_q entry) per row
       int nz = 0;
@@ -495,8 +503,8 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
       if (tid == 0) lp.ctrl->update_bytes += 8 * ((int64_t)(m - 1) * nD + (int64_t)m * nz) + 16 * (int64_t)m;
     }
     __syncthreads();  // a_q is in LDS
-    for (int i = gw; i < m; i += nw, ++c) {
-      double* row = lp.Binv + (size_t)i * ld;
+    for (int i = i0; i < hi; i += nw, ++c) {
+      double* row = lp.Binv + (size_t)(i - lo) * ld;
       double x, alp;
       int bv, in;
       if (c == 0) {
@@ -571,7 +579,7 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
     }
   } else {
     // dense mode with rows long enough for sparse mode: the first batch of the row now
-    const bool pre_late = can_sparse && gw < m;
+    const bool pre_late = can_sparse && i0 < hi;
     if (pre_late) load_batch(reinterpret_cast<const double2*>(lp.Binv + (size_t)gw * ld), lane, ld2, v);
     if (q_col) {
       hold_store<B>(hold, s_a, aq2, tid, ld2);
@@ -581,8 +589,8 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
     }
     __syncthreads();  // a_q is in LDS
     const bool pre = pre_now || pre_late;
-    for (int i = gw; i < m; i += nw, ++c) {
-      double2* row = reinterpret_cast<double2*>(lp.Binv + (size_t)i * ld);
+    for (int i = i0; i < hi; i += nw, ++c) {
+      double2* row = reinterpret_cast<double2*>(lp.Binv + (size_t)(i - lo) * ld);
       const bool first = c == 0 && pre;
       double acc;
       double x = c == 0 ? x0 : lp.xB[i];
@@ -886,6 +894,18 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Out-of-core panel mode: after the ratio test, row r of B^-1 (the rows already updated by
+// this iteration's panel pass) is copied into `row` for the next pricing kernel, from the
+// device-resident last panel (rows res_lo..) or from the pinned host copy.
+__global__ void k_fetch_row(const Ctrl* __restrict__ ctl, const double* __restrict__ host, const double* __restrict__ res,
+                            int res_lo, int ld, double* __restrict__ row) {
+  const int r = ctl->r;
+  if (r < 0) return;
+  const double* src = r >= res_lo ? res + (size_t)(r - res_lo) * ld : host + (size_t)r * ld;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ld; k += gridDim.x * blockDim.x) row[k] = src[k];
+}
+
+// ---------------------------------------------------------------------------------------
 // Helpers of the entry point that allocates nothing (its buffers live in a fixed array).
 
 // *flag = 0 (a kernel rather than a memset, so that a captured stream holds no memset node).
@@ -1061,6 +1081,12 @@ hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s) {
 
 hipError_t launch_finish(const DevLP& lp, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, s, lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_fetch_row(const Ctrl* ctl, const double* host, const double* res, int res_lo, int ld, double* row,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_fetch_row, dim3((ld + 255) / 256), dim3(256), 0, s, ctl, host, res, res_lo, ld, row);
   return hipGetLastError();
 }
 
