@@ -239,7 +239,9 @@ def batch_leg(lpg, count, serial_sample):
     bt0 = lpg.Batch(lps)  # host -> device upload of every LP (and the pooled work memory)
     create = time.perf_counter() - t0
     with bt0 as bt:
+        t0 = time.perf_counter()
         bt.solve()  # the first solve also runs the autotuner
+        first = time.perf_counter() - t0
         t0 = time.perf_counter()
         bt.solve()
         wall = time.perf_counter() - t0
@@ -258,13 +260,98 @@ def batch_leg(lpg, count, serial_sample):
     for h in handles:
         h.close()
     lps_per_s = count / (st["solve_ms"] * 1e-3)
+    model = batch_bytes(lps, res["iterations"])
     return dict(lps=count, lps_per_s=round(lps_per_s, 1), solve_ms=round(st["solve_ms"], 3),
+                model_bytes=model, model_gbs=round(model / (st["solve_ms"] * 1e-3) / 1e9, 1),
+                first_solve_ms_with_tuning=round(first * 1e3, 3),
+                lps_per_s_first_solve=round(count / first, 1),
                 create_ms=round(create * 1e3, 3),
                 lps_per_s_with_upload=round(count / (create + st["solve_ms"] * 1e-3), 1),
                 wall_ms=round(wall * 1e3, 3), pivots=iters, all_optimal=bool((res["status"] == 1).all()),
                 narrow_lps=st["narrow_lps"], wide_lps=st["wide_lps"], tune_ms=round(st["tune_ms"], 1),
                 serial_ms_per_lp=round(serial * 1e3, 4), serial_sample=len(handles),
                 serial_lps_per_s=round(1.0 / serial, 1), speedup_vs_serial=round(lps_per_s * serial, 1))
+
+
+def batch_bytes(lps, iters):
+    """Algorithmic bytes of the batched solve: per pivot of an m x n LP, pricing reads A'
+    (8 m n, nonbasic columns bounded by n) and the update reads and writes B^-1 with FTRAN
+    on the way (16 m ld); the B^-1 term is an upper bound (the sparse-column mode of LPs with
+    ld >= 1024 touches fewer columns, none here)."""
+    total = 0.0
+    for (A, _, _), k in zip(lps, iters):
+        m, n = A.shape
+        ld = (m + 7) // 8 * 8
+        total += float(k) * (8.0 * m * n + 16.0 * m * ld)
+    return total
+
+
+def reinversion_leg(lpg, torch, m, stream, reps=3):
+    """One reinversion of an all-structural basis (k = m): the nearly diagonal law m x m is
+    solved to its optimum, whose basis holds every structural column, then lp_reinvert is
+    timed.  FLOPs: LU 2/3 k^3, the two triangular solves of X = M^-1 2 k^3 (m = k: no
+    -B21 B11^-1 product); rate against the FP64 matrix peak of 78.6 TFLOP/s."""
+    import lpgen
+    A, b, c = lpgen.diagonal_lp(1, m, m)
+    with lpg.LP(A, b, c, stream=stream.cuda_stream) as lp:
+        st = lp.solve()
+        k = int((lp.solution()["basis"] < m).sum())
+        lp.reinvert()  # warm
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            lp.reinvert()
+            times.append(time.perf_counter() - t0)
+        failed = lp.stats()["reinv_failed"]
+    ts = statistics.median(times)
+    flops = (2.0 / 3.0) * k ** 3 + 2.0 * k ** 3
+    return dict(workload=f"nearly diagonal LP m=n={m} at its optimum (status {lpg.STATUS_NAMES[st]}), "
+                         f"basis block k={k}", k=k, ms=round(ts * 1e3, 3), runs_ms=[round(t * 1e3, 3) for t in times],
+                gflop=round(flops / 1e9, 2), tflops=round(flops / ts / 1e12, 3),
+                frac_fp64_mfma_peak=round(flops / ts / 78.6e12, 4), failed=failed)
+
+
+def degenerate_leg(lpg, torch, stream, warmup=200, steps=2000):
+    """The degenerate law at full size (5000 x 10000, and 5001 x 10000 with the budget row):
+    iterations/s over `steps` pivots after `warmup`."""
+    import lpgen
+    out = {}
+    for name, budget in (("degenerate_m5000_n10000", False), ("degenerate_budget_m5001_n10000", True)):
+        A, b, c = lpgen.degenerate_lp(0, 5000, 10000, budget_row=budget)
+        with lpg.LP(A, b, c, stream=stream.cuda_stream) as lp:
+            run_steps(lp, warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run_steps(lp, steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            stt = lp.stats()
+        out[name] = dict(pivots=steps, after=warmup, seconds=round(dt, 4), iter_per_s=round(steps / dt, 1),
+                         degenerate=stt["degenerate"], ties=stt["ties"])
+    return out
+
+
+def out_of_core_leg(lpg, torch, dev, m, n, panel_rows, steps=60, warmup=10):
+    """Section 3's Case 2 on the benchmark LP: a device budget that leaves room for three
+    panels of about panel_rows rows of B^-1; every iteration streams the other panels to the
+    device and back over PCIe.  Host traffic per iteration: 2 x 8 ld (m - resident rows)."""
+    ld = (m + 7) // 8 * 8
+    budget = 8 * ld * n + 64 * (n + m) + 64 * ld + 64 * 10 * (m + n) + 3 * 8 * ld * panel_rows + 300_000
+    with lpg.LP.from_torch(*dev, device_budget=budget) as lp:
+        run_steps(lp, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_steps(lp, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stt = lp.stats()
+    res_rows = m - (stt["panels"] - 1) * stt["panel_rows"]
+    host_bytes = 2.0 * 8 * ld * (m - res_rows)
+    return dict(workload=f"dense LP m={m}, n={n}, device budget {budget / 2**20:.0f} MiB (B^-1 alone is "
+                         f"{8 * m * ld / 2**20:.0f} MiB)", memory_case=stt["memory_case"], panels=stt["panels"],
+                panel_rows=stt["panel_rows"], pivots=steps, iter_per_s=round(steps / dt, 1),
+                host_bytes_per_iter=host_bytes, host_gbs=round(host_bytes * steps / dt / 1e9, 2))
 
 
 def cpu_baseline(A, b, c, pivots, budget_s=20.0):
@@ -313,6 +400,10 @@ def main():
     ap.add_argument("--general-n", type=int, default=8000)
     ap.add_argument("--mixed-profile-only", action="store_true",
                     help="only the profiled stretch of the mixed-precision form (for profiler runs)")
+    ap.add_argument("--reinv-m", type=int, default=3000, help="order of the reinversion leg's basis block (0 = skip)")
+    ap.add_argument("--degenerate", type=int, default=1, help="degenerate-law leg at 5000 x 10000 (0 = skip)")
+    ap.add_argument("--panel-rows", type=int, default=500,
+                    help="rows per panel of the out-of-core leg on the benchmark LP (0 = skip)")
     ap.add_argument("--serial-sample", type=int, default=256,
                     help="LPs of the batch also solved one by one with lp_solve")
     ap.add_argument("--quick", action="store_true",
@@ -388,6 +479,18 @@ def main():
     if not args.quick and args.general_m > 0:
         _log(f"bench: two-phase leg m={args.general_m} n={args.general_n}")
         extra["two_phase"] = general_leg(lpg, torch, args.general_m, args.general_n, args.seed, stream)
+
+    if not args.quick and args.reinv_m > 0:
+        _log(f"bench: reinversion leg, k = m = {args.reinv_m}")
+        extra["reinversion"] = reinversion_leg(lpg, torch, args.reinv_m, stream)
+
+    if not args.quick and args.degenerate:
+        _log("bench: degenerate law 5000 x 10000")
+        extra["degenerate"] = degenerate_leg(lpg, torch, stream)
+
+    if not args.quick and args.panel_rows > 0:
+        _log(f"bench: out-of-core leg, ~{args.panel_rows} rows per panel")
+        extra["out_of_core"] = out_of_core_leg(lpg, torch, dev, m, n, args.panel_rows)
 
     if not args.quick and args.batch > 0:
         _log(f"bench: batched leg, {args.batch} LPs")
