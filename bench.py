@@ -238,15 +238,25 @@ def batch_leg(lpg, count, serial_sample):
     t0 = time.perf_counter()
     bt0 = lpg.Batch(lps)  # host -> device upload of every LP (and the pooled work memory)
     create = time.perf_counter() - t0
+    import tempfile
+    table = os.path.join(tempfile.mkdtemp(prefix="lpgpu_tune_"), "batch_tune.json")
     with bt0 as bt:
         t0 = time.perf_counter()
         bt.solve()  # the first solve also runs the autotuner
         first = time.perf_counter() - t0
+        bt.tune_save(table)
         t0 = time.perf_counter()
         bt.solve()
         wall = time.perf_counter() - t0
         st = bt.stats()
         res = bt.results()
+    # a second batch of the same law that takes the saved table: its first solve times nothing
+    with lpg.Batch(lps) as bt2:
+        bt2.tune_load(table)
+        t0 = time.perf_counter()
+        bt2.solve()
+        first_cached = time.perf_counter() - t0
+        st2 = bt2.stats()
     iters = int(res["iterations"].sum())
     idx = list(range(0, count, max(1, count // serial_sample)))[:serial_sample]
     handles = [lpg.LP(*lps[i]) for i in idx]
@@ -265,6 +275,9 @@ def batch_leg(lpg, count, serial_sample):
                 model_bytes=model, model_gbs=round(model / (st["solve_ms"] * 1e-3) / 1e9, 1),
                 first_solve_ms_with_tuning=round(first * 1e3, 3),
                 lps_per_s_first_solve=round(count / first, 1),
+                first_solve_ms_from_tune_table=round(first_cached * 1e3, 3),
+                tune_ms_from_table=round(st2["tune_ms"], 1), buckets_from_table=st2["tuned_from_table"],
+                lps_per_s_first_solve_from_table=round(count / first_cached, 1),
                 create_ms=round(create * 1e3, 3),
                 lps_per_s_with_upload=round(count / (create + st["solve_ms"] * 1e-3), 1),
                 wall_ms=round(wall * 1e3, 3), pivots=iters, all_optimal=bool((res["status"] == 1).all()),

@@ -326,6 +326,7 @@ typedef struct lp_batch_stats {
   double tune_ms;             /* host time spent by the autotuner */
   int64_t binv_lds_lps;       /* LPs that kept B^-1 in LDS in the last solve */
   int64_t binv_lds_m;         /* the threshold in effect (option or tuned) */
+  int64_t tuned_from_table;   /* m-buckets whose mode came from a tune table (not timed) */
 } lp_batch_stats;
 
 /*
@@ -359,6 +360,21 @@ int lp_batch_get_stats(const lp_batch *bt, lp_batch_stats *s);
 
 /* NULL-safe. */
 void lp_batch_destroy(lp_batch *bt);
+
+/*
+ * The autotuner's table (Section 3.3's block-size choice, made by timing): the mode chosen
+ * for each m-bucket (one wavefront or one workgroup per LP; m in (16k, 16k+16]) and the
+ * B^-1-in-LDS threshold, keyed by the device's architecture name and the precision, in a
+ * JSON file of one record per line.  lp_batch_tune_load, before the first lp_batch_solve,
+ * takes the records of this device's architecture: those buckets are not timed again, and a
+ * recorded threshold is used.  lp_batch_tune_save merges the batch's tuned buckets and
+ * threshold into the file (created if missing; the other records are kept).  With the
+ * environment variable LPGPU_BATCH_TUNE naming a file, lp_batch_create loads it and every
+ * lp_batch_solve that tuned something saves it.  A missing or unreadable file is an empty
+ * table.  Errors: LP_ERR_ARG (NULL argument, a file that cannot be written).
+ */
+int lp_batch_tune_load(lp_batch *bt, const char *path);
+int lp_batch_tune_save(const lp_batch *bt, const char *path);
 
 /* lp_batch_create + lp_batch_solve + lp_batch_results + lp_batch_destroy. */
 int lp_solve_batch(int32_t count, const int32_t *m, const int32_t *n, const double *const *A, const double *const *b,

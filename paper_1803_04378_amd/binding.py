@@ -94,6 +94,7 @@ class lp_batch_stats(C.Structure):
         ("tune_ms", C.c_double),
         ("binv_lds_lps", C.c_int64),
         ("binv_lds_m", C.c_int64),
+        ("tuned_from_table", C.c_int64),
     ]
 
 
@@ -137,6 +138,8 @@ SIGNATURES = {
     "lp_batch_get": (C.c_int, [_P, C.c_int32, _DP, _IP, _IP, _IP, _IP, C.c_int64, _LP]),
     "lp_batch_get_stats": (C.c_int, [_P, C.POINTER(lp_batch_stats)]),
     "lp_batch_destroy": (None, [_P]),
+    "lp_batch_tune_load": (C.c_int, [_P, C.c_char_p]),
+    "lp_batch_tune_save": (C.c_int, [_P, C.c_char_p]),
     "lp_solve_batch": (C.c_int, [C.c_int32, _IP, _IP, C.POINTER(_DP), C.POINTER(_DP), C.POINTER(_DP),
                                  C.POINTER(lp_options), _IP, _DP, _LP]),
 }
@@ -360,6 +363,14 @@ class Batch:
 
     def solve(self):
         _check(lib().lp_batch_solve(self._h), "lp_batch_solve")
+
+    def tune_load(self, path):
+        """Takes this device's records of a tune table file (before the first solve)."""
+        _check(lib().lp_batch_tune_load(self._h, os.fsencode(path)), "lp_batch_tune_load")
+
+    def tune_save(self, path):
+        """Merges the tuned modes and threshold into a tune table file."""
+        _check(lib().lp_batch_tune_save(self._h, os.fsencode(path)), "lp_batch_tune_save")
 
     def results(self):
         st = np.empty(self.count, dtype=np.int32)

@@ -4,8 +4,13 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
+#include <sstream>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -90,6 +95,8 @@ struct lp_batch {
   size_t region_l = 0;  // LDS bytes per workgroup of that launch
   int grid_l = 0;
   bool solved = false;
+  std::string arch;     // the device's architecture name, the key of the tune table
+  int64_t loaded_buckets = 0;  // buckets whose mode came from a tune table
   double solve_ms = 0.0, tune_ms = 0.0;
   int64_t narrow_lps = 0, wide_lps = 0, binv_lds_lps = 0, items_last = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -196,9 +203,9 @@ int autotune(lp_batch* p) {
     if ((int)buckets.size() <= bk) buckets.resize(bk + 1);
     buckets[bk].push_back(i);
   }
-  p->bucket_narrow.assign(buckets.size(), 0);
+  if (p->bucket_narrow.size() < buckets.size()) p->bucket_narrow.resize(buckets.size(), -1);
   for (size_t bk = 0; bk < buckets.size(); ++bk) {
-    if (buckets[bk].empty()) continue;
+    if (buckets[bk].empty() || p->bucket_narrow[bk] >= 0) continue;  // none, or from a tune table
     float best[2] = {0.f, 0.f};
     for (int narrow = 0; narrow < 2; ++narrow) {
       for (int i : buckets[bk]) p->lps[i].waves = narrow ? 1 : kBatchWaves;
@@ -230,7 +237,7 @@ int assign_modes(lp_batch* p) {
         narrow = L.m <= p->small_m;
       } else {
         const int bk = bucket_of(L.m);
-        narrow = bk < (int)p->bucket_narrow.size() && p->bucket_narrow[bk] == 1;
+        narrow = bk < (int)p->bucket_narrow.size() && p->bucket_narrow[bk] == 1;  // -1: no LP timed it
       }
     }
     L.waves = narrow ? 1 : kBatchWaves;
@@ -296,6 +303,110 @@ int tune_binv(lp_batch* p) {
   p->binv_tuned = true;
   p->tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return LP_OK;
+}
+
+// ---- the persistent tune table ----
+// A JSON array with one object per line: {"arch": A, "precision": "fp64", "bucket_width":
+// 16, "bucket": k, "narrow": 0|1} for the mode of m-bucket k (m in (16k, 16k+16]) on
+// architecture A, and {"arch": A, "precision": "fp64", "binv_lds_m": t} for the B^-1-in-LDS
+// threshold last chosen there.
+struct TuneTable {
+  std::map<std::pair<std::string, int>, int> narrow;  // (arch, bucket) -> mode
+  std::map<std::string, int> binv;                    // arch -> threshold
+};
+
+bool json_str(const std::string& line, const char* key, std::string* out) {
+  const std::string k = std::string("\"") + key + "\": \"";
+  const size_t a = line.find(k);
+  if (a == std::string::npos) return false;
+  const size_t b = line.find('"', a + k.size());
+  if (b == std::string::npos) return false;
+  *out = line.substr(a + k.size(), b - a - k.size());
+  return true;
+}
+
+bool json_int(const std::string& line, const char* key, long* out) {
+  const std::string k = std::string("\"") + key + "\": ";
+  const size_t a = line.find(k);
+  if (a == std::string::npos) return false;
+  char* end = nullptr;
+  const long v = std::strtol(line.c_str() + a + k.size(), &end, 10);
+  if (end == line.c_str() + a + k.size()) return false;
+  *out = v;
+  return true;
+}
+
+// Reads the records of precision fp64 (a missing file is an empty table).
+void read_table(const char* path, TuneTable* t) {
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::string arch, prec;
+    long v = 0, w = 0, bk = 0;
+    if (!json_str(line, "arch", &arch) || !json_str(line, "precision", &prec) || prec != "fp64") continue;
+    if (json_int(line, "binv_lds_m", &v)) {
+      t->binv[arch] = (int)v;
+    } else if (json_int(line, "bucket", &bk) && json_int(line, "narrow", &v) && json_int(line, "bucket_width", &w) &&
+               w == kBucketWidth && bk >= 0 && bk < 4096) {
+      t->narrow[{arch, (int)bk}] = v ? 1 : 0;
+    }
+  }
+}
+
+int write_table(const char* path, const TuneTable& t) {
+  std::ostringstream o;
+  o << "[\n";
+  bool first = true;
+  for (const auto& kv : t.narrow) {
+    o << (first ? "" : ",\n") << "{\"arch\": \"" << kv.first.first << "\", \"precision\": \"fp64\", \"bucket_width\": "
+      << kBucketWidth << ", \"bucket\": " << kv.first.second << ", \"m_lo\": " << kv.first.second * kBucketWidth + 1
+      << ", \"m_hi\": " << (kv.first.second + 1) * kBucketWidth << ", \"narrow\": " << kv.second << "}";
+    first = false;
+  }
+  for (const auto& kv : t.binv) {
+    o << (first ? "" : ",\n") << "{\"arch\": \"" << kv.first << "\", \"precision\": \"fp64\", \"binv_lds_m\": "
+      << kv.second << "}";
+    first = false;
+  }
+  o << "\n]\n";
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return fail(LP_ERR_ARG, std::string("cannot write the tune table ") + tmp);
+    f << o.str();
+    if (!f.good()) return fail(LP_ERR_ARG, std::string("cannot write the tune table ") + tmp);
+  }
+  if (std::rename(tmp.c_str(), path) != 0) return fail(LP_ERR_ARG, std::string("cannot replace ") + path);
+  return LP_OK;
+}
+
+int load_table(lp_batch* p, const char* path) {
+  TuneTable t;
+  read_table(path, &t);
+  int64_t got = 0;
+  for (const auto& kv : t.narrow) {
+    if (kv.first.first != p->arch) continue;
+    const int bk = kv.first.second;
+    if ((int)p->bucket_narrow.size() <= bk) p->bucket_narrow.resize(bk + 1, -1);
+    p->bucket_narrow[bk] = kv.second;
+    ++got;
+  }
+  p->loaded_buckets = got;
+  auto it = t.binv.find(p->arch);
+  if (it != t.binv.end() && p->binv_opt < 0) {
+    p->binv_m = it->second;
+    p->binv_tuned = true;
+  }
+  return LP_OK;
+}
+
+int save_table(const lp_batch* p, const char* path) {
+  TuneTable t;
+  read_table(path, &t);
+  for (size_t bk = 0; bk < p->bucket_narrow.size(); ++bk)
+    if (p->bucket_narrow[bk] >= 0) t.narrow[{p->arch, (int)bk}] = p->bucket_narrow[bk];
+  if (p->binv_tuned) t.binv[p->arch] = p->binv_m;
+  return write_table(path, t);
 }
 
 }  // namespace
@@ -368,6 +479,7 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
     e = hipGetDeviceProperties(&prop, dev);
     if (e != hipSuccess) return bail(fail_hip(e, "querying the device"));
     p->num_cu = prop.multiProcessorCount;
+    p->arch = prop.gcnArchName;
     e = batch_occupancy(&p->per_cu, region, false);
     if (e != hipSuccess) return bail(fail_hip(e, "querying occupancy"));
     if (p->per_cu < 1) return bail(fail(LP_ERR_ARG, "batched solver does not fit the device"));
@@ -526,6 +638,9 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
     if (e == hipSuccess) e = hipMemcpy(dc, hc.data(), sizeof(double) * hc.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(fail_hip(e, "uploading the batch"));
   }
+  if (const char* path = std::getenv("LPGPU_BATCH_TUNE")) {
+    if (*path) load_table(p, path);
+  }
   *out = p;
   p = nullptr;  // handed over
   return LP_OK;
@@ -536,13 +651,21 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
 int lp_batch_solve(lp_batch* p) try {
   if (!p) return fail(LP_ERR_ARG, "p is NULL");
   int rc;
-  if (p->small_m < 0 && p->bucket_narrow.empty()) {
-    if ((rc = autotune(p)) != LP_OK) return rc;
+  bool tuned = false;
+  if (p->small_m < 0 && !p->solved) {
+    p->tune_ms = 0.0;
+    if ((rc = autotune(p)) != LP_OK) return rc;  // times only buckets no table named
+    tuned = true;
   }
   if (p->binv_opt >= 0) {
     p->binv_m = p->binv_opt;
   } else if (!p->binv_tuned) {
     if ((rc = tune_binv(p)) != LP_OK) return rc;
+    tuned = true;
+  }
+  if (tuned) {
+    if (const char* path = std::getenv("LPGPU_BATCH_TUNE"))
+      if (*path && (rc = save_table(p, path)) != LP_OK) return rc;
   }
   if ((rc = assign_modes(p)) != LP_OK) return rc;
   float ms = 0.f;
@@ -633,6 +756,7 @@ int lp_batch_get_stats(const lp_batch* p, lp_batch_stats* s) try {
   s->lds_bytes = (int64_t)p->region;
   s->binv_lds_lps = p->binv_lds_lps;
   s->binv_lds_m = p->binv_m;
+  s->tuned_from_table = p->loaded_buckets;
   int64_t mask = 0;
   for (size_t bk = 0; bk < p->bucket_narrow.size() && bk < 63; ++bk)
     if (p->bucket_narrow[bk] == 1) mask |= (int64_t)1 << bk;
@@ -643,6 +767,20 @@ int lp_batch_get_stats(const lp_batch* p, lp_batch_stats* s) try {
 }
 
 void lp_batch_destroy(lp_batch* p) { release(p); }
+
+int lp_batch_tune_load(lp_batch* p, const char* path) try {
+  if (!p || !path) return fail(LP_ERR_ARG, "NULL argument");
+  return load_table(p, path);
+} catch (...) {
+  return host_exception();
+}
+
+int lp_batch_tune_save(const lp_batch* p, const char* path) try {
+  if (!p || !path) return fail(LP_ERR_ARG, "NULL argument");
+  return save_table(p, path);
+} catch (...) {
+  return host_exception();
+}
 
 int lp_solve_batch(int32_t count, const int32_t* m, const int32_t* n, const double* const* A, const double* const* b,
                    const double* const* c, const lp_options* opt, int32_t* status, double* objective,

@@ -195,3 +195,29 @@ def test_batch_4096_mixed_sizes(lpg):
             M = np.hstack([A, np.eye(m)])
             y = np.linalg.solve(M[:, g["basis"]].T, np.concatenate([c, np.zeros(m)])[g["basis"]])
             assert_kkt(A, b, c, g["x"], y)
+
+
+def test_tune_table_round_trip(lpg, tmp_path):
+    """The autotuner's modes saved to a JSON table are taken by a new batch without timing,
+    and the results do not depend on where the modes came from."""
+    lps = _mixed_batch(5, 300, 16, 200)
+    path = str(tmp_path / "tune.json")
+    with lpg.Batch(lps) as bt:
+        bt.solve()
+        bt.tune_save(path)
+        s1 = bt.stats()
+        r1 = bt.results()
+    text = open(path).read()
+    recs = json.loads(text)
+    assert any("bucket" in r for r in recs) and any("binv_lds_m" in r for r in recs)
+    with lpg.Batch(lps) as bt:
+        bt.tune_load(path)
+        bt.solve()
+        s2 = bt.stats()
+        r2 = bt.results()
+    _say(f"  tune {s1['tune_ms']:.1f} ms from scratch, {s2['tune_ms']:.1f} ms with the table "
+         f"({s2['tuned_from_table']} buckets)")
+    assert s2["tuned_from_table"] > 0
+    assert s2["narrow_bucket_mask"] == s1["narrow_bucket_mask"] and s2["binv_lds_m"] == s1["binv_lds_m"]
+    for k in ("status", "iterations", "objective"):
+        np.testing.assert_array_equal(r1[k], r2[k])
