@@ -73,10 +73,12 @@ extern "C" {
 #define LP_FP64 0  /* every step in FP64 */
 #define LP_MIXED 1 /* FP32 screening of the reduced costs, shortlist re-priced in FP64 */
 
-/* Largest m the library accepts: the update kernel stages the pivot row rho and the entering
- * column a_q (8 bytes per row each) and the sparse-column index list (ld/8 int32) in the
- * 160 KB of LDS of one CU, next to 2.2 KB of its own: 16.5 * 9792 + 2256 <= 163840. */
-#define LP_MAX_ROWS 9792
+/* Largest m the library accepts: the pricing kernel stages the top row W (8 bytes per row)
+ * in the 160 KB of LDS of one CU (8 * 20000 + its own 0.2 KB <= 163840).  Up to m = 9792
+ * the update kernel stages the pivot row and the entering column whole in LDS; above, it
+ * stages them in chunks (or, in sparse-column mode, only at the entries of list D).  The
+ * batched form has its own, smaller limit (LP_ERR_ARG from lp_batch_create). */
+#define LP_MAX_ROWS 20000
 
 typedef struct lp_options {
   int32_t sense;          /* LP_MIN or LP_MAX (default LP_MAX) */

@@ -334,7 +334,8 @@ int iteration_kernels(const lp_problem* p, IterKernel* out) {
   } else {
     out[c++] = {price_kernel(), p->price_grid, kPriceBlock, price_lds_bytes(p->ld)};
   }
-  out[c++] = {update_kernel_for_block(p->d.upd_block), p->update_grid, p->d.upd_block, update_lds_bytes(p->ld)};
+  out[c++] = {update_kernel_for_block(p->d.upd_block), p->update_grid, std::abs(p->d.upd_block),
+              update_lds_for_block(p->d.upd_block, p->ld)};
   out[c++] = {finish_kernel(), 1, kFinishBlock, 0};
   return c;
 }
@@ -475,7 +476,7 @@ int iteration_grids(int32_t m, int32_t n, int num_cu, int* price_grid, int* upda
   if (e != hipSuccess) return fail_hip(e, "querying kernel occupancy");
   if (price_per_cu < 1 || update_per_cu < 1) return fail(LP_ERR_ARG, "m too large for the kernels' LDS");
   *upd_block = update_block(ld);
-  const int pw = kPriceBlock / 64, uw = *upd_block / 64;
+  const int pw = kPriceBlock / 64, uw = std::abs(*upd_block) / 64;
   *price_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)price_per_cu * num_cu, (n + pw - 1) / pw));
   *update_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)update_per_cu * num_cu, (m + uw - 1) / uw));
   if ((m + (int64_t)*update_grid * uw - 1) / ((int64_t)*update_grid * uw) > kMaxRowsPerWave)

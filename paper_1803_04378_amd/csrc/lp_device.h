@@ -98,7 +98,8 @@ struct Ctrl {
 
 struct DevLP {
   int32_t m, n, ld;
-  int32_t upd_block;  // k_update's workgroup size, update_block(ld), fixed at creation
+  int32_t upd_block;  // k_update's workgroup size, update_block(ld), fixed at creation (negative:
+                      //   k_update_wide with that many threads)
   const double* A;
   const double* chat;
   double* Binv;
@@ -178,6 +179,9 @@ __device__ __forceinline__ const double* pricing_w(const DevLP& lp) {
 // B^-1 can differ from unit vectors, and only for rows long enough (ld >= 1024) that
 // skipping the unit columns saves more than the index indirection costs.
 constexpr int kSparseMinLd = 1024;
+// Largest row stride whose whole rho and a_q k_update stages in LDS; longer rows go to
+// k_update_wide.
+constexpr int kUpdateStageMaxLd = 9792;
 __host__ __device__ __forceinline__ bool sparse_columns(int nD, int ld) {
   return ld >= kSparseMinLd && nD * 8 <= ld;
 }
@@ -225,6 +229,9 @@ int update_block(int ld);
 const void* finish_kernel();
 size_t price_lds_bytes(int ld);
 size_t update_lds_bytes(int ld);
+// LDS of the update kernel update_block(ld) selects (block < 0: k_update_wide).
+size_t update_lds_for_block(int block, int ld);
+size_t wide_lds_bytes(int ld);
 hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld);
 
 // Two-phase start (lp_phase.hip): W and z from their definitions for the current costs,

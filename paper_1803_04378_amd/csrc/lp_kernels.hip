@@ -681,6 +681,325 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
 }
 
 // ---------------------------------------------------------------------------------------
+// k_update for rows too long for k_update's staging of the whole of rho and a_q (16.5 ld
+// bytes of LDS, so above ld = 9792).  The same steps and the same arithmetic, staged
+// differently: in sparse-column mode only the list D and rho, a_q at its entries (20 bytes
+// per entry, ld / 8 entries at most); in dense mode rho and a_q in chunks of kWideChunk2
+// element pairs, each wavefront carrying the running dot products of its rows from chunk
+// to chunk.  Lane l still owns pairs l, l + 64, ... of a row in ascending order (chunks are
+// multiples of 64 pairs) and D entries l, l + 64, ..., so every alpha_i is the same fma
+// chain and butterfly as in k_update.
+constexpr int kWideChunk2 = 2048;
+
+template <int B>
+__global__ __launch_bounds__(B) void k_update_wide(DevLP lp) {
+  constexpr int waves = B / 64;
+  constexpr int R = kMaxRowsPerWave;
+  extern __shared__ double2 wsm[];
+  __shared__ double red_d[2 * waves];
+  __shared__ int red_j[2 * waves];
+  __shared__ double s_rt[waves * R];
+  __shared__ double s_tau[waves * R];
+  __shared__ int s_row[waves * R];
+  __shared__ double s_al[waves * R];
+  __shared__ int s_bv[waves * R];
+  __shared__ int s_nf;
+  const int n = lp.n, ld = lp.ld, ld2 = ld / 2;
+  const int lo = lp.row_lo, hi = lp.row_hi;
+  const bool first_panel = lo == 0;
+  const int m = lp.m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_nf = 0;
+  const int gw = blockIdx.x * waves + wave;
+  const int nw = gridDim.x * waves;
+  const int i0 = lo + gw;
+
+  const Ctrl* ctl = lp.ctrl;
+  const int status = ctl->status;
+  const int r = ctl->r;
+  const int nD = ctl->nD;
+  const int cur = ctl->cur;
+  const int64_t t = ctl->t;
+  const int64_t max_iter = ctl->max_iter;
+  const double theta = ctl->theta;
+  const int fb = ctl->fb;
+
+  // Step 4 decision, as in k_update.
+  double da = __builtin_inf(), df = __builtin_inf();
+  int ja = INT_MAX, jf = INT_MAX;
+  bool from_shortlist = false;
+  const bool use_parts = !lp.mixed || fb;
+  if (lp.mixed && !fb) {
+    double sd = __builtin_inf();
+    int sj = INT_MAX;
+    const int w = min(lane, lp.sl_k - 1);
+    sd = lp.sl_d[w];
+    sj = lp.sl_j[w];
+    if (!(lane < lp.sl_k && sj != INT_MAX && sd < -lp.eps_d)) {
+      sd = __builtin_inf();
+      sj = INT_MAX;
+    }
+    wave_lexmin(sd, sj);
+    df = sd;
+    jf = sj;
+    from_shortlist = jf != INT_MAX;
+    da = df;
+    ja = jf;
+  }
+  if (use_parts) {
+    for (int k = tid; k < lp.price_grid; k += B) {
+      const double d0 = lp.part_d[2 * k], d1 = lp.part_d[2 * k + 1];
+      const int j0 = lp.part_j[2 * k], j1 = lp.part_j[2 * k + 1];
+      if (lex_less(d0, j0, da, ja)) {
+        da = d0;
+        ja = j0;
+      }
+      if (lex_less(d1, j1, df, jf)) {
+        df = d1;
+        jf = j1;
+      }
+    }
+    wave_lexmin(da, ja);
+    wave_lexmin(df, jf);
+    if (lane == 0) {
+      red_d[wave] = da;
+      red_j[wave] = ja;
+      red_d[waves + wave] = df;
+      red_j[waves + wave] = jf;
+    }
+    __syncthreads();
+    da = lane < waves ? red_d[lane] : __builtin_inf();
+    ja = lane < waves ? red_j[lane] : INT_MAX;
+    df = lane < waves ? red_d[waves + lane] : __builtin_inf();
+    jf = lane < waves ? red_j[waves + lane] : INT_MAX;
+    wave_lexmin(da, ja);
+    wave_lexmin(df, jf);
+  }
+  __syncthreads();
+  if (status != kStatusRunning) return;
+  const bool sparse = sparse_columns(nD, ld);
+  int verdict = kStatusRunning, q = -1, flags = 0;
+  double dq = 0.0;
+  if (!use_parts && !from_shortlist) {
+    verdict = kVerdictFallback;
+  } else if (ja == INT_MAX) {
+    verdict = kStatusOptimal;
+  } else if (t >= max_iter) {
+    verdict = kStatusIterLimit;
+  } else if (jf != INT_MAX) {
+    q = jf;
+    dq = df;
+  } else {
+    q = ja;
+    dq = da;
+    flags = kFlagAspiration;
+  }
+  if (blockIdx.x == 0 && tid == 0 && first_panel) {
+    Ctrl* cw = lp.ctrl;
+    if (lp.mixed && !fb) cw->price32_launches += 1;
+    if (use_parts) {
+      cw->price_cols += n - cw->nsb;
+      cw->price_launches += 1;
+      if (lp.mixed) cw->full_prices += 1;
+    }
+    if (r >= 0) cw->wcur ^= 1;
+    cw->verdict = verdict;
+    cw->q = q;
+    cw->dq = dq;
+    cw->flags = flags;
+    if (flags & kFlagAspiration) cw->n_aspiration += 1;
+    if (r >= 0) {
+      cw->update_launches += 1;
+      cw->update_rows_written += m;
+    } else if (q >= 0) {
+      cw->update_launches += 1;
+    }
+    if (!sparse && (r >= 0 || q >= 0)) {
+      cw->update_bytes += 8 * (int64_t)m * m;
+      if (r >= 0) cw->update_bytes += 16 * ((int64_t)(m - 1) * cw->rho_nz2 + ld / 2);
+    }
+  }
+  if (r < 0 && q < 0) return;
+
+  const double* __restrict__ al_p = cur ? lp.alpha1 : lp.alpha0;
+  double* __restrict__ al_n = cur ? lp.alpha0 : lp.alpha1;
+  const double eps_p = lp.eps_p, eps_z = lp.eps_z;
+  const bool q_col = q >= 0 && q < n;
+  const int qs = q >= n ? q - n : -1;  // a slack entering: a_q = e_qs
+  const double* __restrict__ aq = lp.A + (size_t)(q_col ? q : 0) * ld;
+  // This wavefront's rows and their state.
+  double xr[R], nar[R], acc[R];
+  int bvr[R], inr[R];
+  int nrows = 0;
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    const int i = i0 + c * nw;
+    acc[c] = 0.0;
+    if (i < hi) {
+      nrows = c + 1;
+      xr[c] = lp.xB[i];
+      const int bv = lp.basis[i];
+      bvr[c] = bv;
+      inr[c] = bv >= n ? lp.inD[bv - n] : 1;
+      nar[c] = (r >= 0 && i != r) ? -al_p[i] : 0.0;
+    }
+  }
+  if (sparse) {
+    const int dcap = ld / 8;
+    double* s_rD = reinterpret_cast<double*>(wsm);
+    double* s_aD = s_rD + dcap;
+    int* s_dl = reinterpret_cast<int*>(s_aD + dcap);
+    int nz = 0;
+    for (int k = tid; k < nD; k += B) {
+      const int j = lp.dlist[k];
+      s_dl[k] = j;
+      const double rr = r >= 0 ? lp.rho[j] : 0.0;
+      s_rD[k] = rr;
+      nz += rr != 0.0 ? 1 : 0;
+      s_aD[k] = q_col ? aq[j] : (j == qs ? 1.0 : 0.0);
+    }
+    if (blockIdx.x == 0 && first_panel) {
+      nz = block_sum_int<B>(nz, red_j);
+      if (tid == 0) lp.ctrl->update_bytes += 8 * ((int64_t)(m - 1) * nD + (int64_t)m * nz) + 16 * (int64_t)m;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      if (c >= nrows) break;
+      const int i = i0 + c * nw;
+      double* row = lp.Binv + (size_t)(i - lo) * ld;
+      const bool isr = i == r;
+      for (int a = lane; a < nD; a += 64) {
+        const int j = s_dl[a];
+        double val = row[j];
+        if (r >= 0) {
+          const double rr = s_rD[a];
+          val = isr ? rr : fma(nar[c], rr, val);
+          if (rr != 0.0) row[j] = val;
+        }
+        if (q >= 0) acc[c] = fma(val, s_aD[a], acc[c]);
+      }
+    }
+  } else {
+    double2* s_rho = wsm;
+    double2* s_a = wsm + kWideChunk2;
+    const double2* rho2 = reinterpret_cast<const double2*>(lp.rho);
+    const double2* aq2 = reinterpret_cast<const double2*>(aq);
+    for (int c0 = 0; c0 < ld2; c0 += kWideChunk2) {
+      const int cn = min(kWideChunk2, ld2 - c0);
+      __syncthreads();  // the previous chunk has been used
+      for (int k = tid; k < cn; k += B) {
+        if (r >= 0) s_rho[k] = rho2[c0 + k];
+        if (q >= 0) {
+          const int e = 2 * (c0 + k);
+          s_a[k] = q_col ? aq2[c0 + k] : make_double2(e == qs ? 1.0 : 0.0, e + 1 == qs ? 1.0 : 0.0);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (c >= nrows) break;
+        const int i = i0 + c * nw;
+        double2* row = reinterpret_cast<double2*>(lp.Binv + (size_t)(i - lo) * ld) + c0;
+        const bool isr = i == r;
+        for (int k = lane; k < cn; k += 64) {
+          double2 v = row[k];
+          if (r >= 0) {
+            const double2 rr = s_rho[k];
+            if (isr) {
+              v = rr;
+              row[k] = v;
+            } else {
+              v.x = fma(nar[c], rr.x, v.x);
+              v.y = fma(nar[c], rr.y, v.y);
+              if (rr.x != 0.0 || rr.y != 0.0) row[k] = v;
+            }
+          }
+          if (q >= 0) {
+            const double2 w = s_a[k];
+            acc[c] = fma(v.x, w.x, acc[c]);
+            acc[c] = fma(v.y, w.y, acc[c]);
+          }
+        }
+      }
+    }
+  }
+  // x_B, alpha and the per-row part of Step 6, as in k_update.
+  int c = 0;
+#pragma unroll
+  for (int cc = 0; cc < R; ++cc) {
+    if (cc >= nrows) break;
+    c = cc + 1;
+    const int i = i0 + cc * nw;
+    const bool isr = i == r;
+    double x = xr[cc];
+    if (r >= 0) {
+      x = isr ? theta : fma(nar[cc], theta, x);
+      if (fabs(x) < eps_z) x = 0.0;
+      if (lane == 0) lp.xB[i] = x;
+    }
+    if (q >= 0) {
+      double a = wave_sum(acc[cc]);
+      const int bv = bvr[cc];
+      if (sparse && bv >= n && !inr[cc]) a += q_col ? aq[bv - n] : (bv - n == qs ? 1.0 : 0.0);
+      double rt = __builtin_inf(), tau = __builtin_inf();
+      if (a > eps_p) {
+        const double xp = fmax(x, 0.0);
+        rt = xp / a;
+        tau = (xp - lp.eps_t) / a;
+        tau -= 1e-12 * (fabs(tau) + 1.0);
+      }
+      if (lane == 0) {
+        al_n[i] = a;
+        s_rt[wave * R + cc] = rt;
+        s_tau[wave * R + cc] = tau;
+        s_row[wave * R + cc] = a > eps_p ? i : INT_MAX;
+        if (!isfinite(a)) s_nf = 1;
+        s_al[wave * R + cc] = a;
+        s_bv[wave * R + cc] = 2 * bv + ((bv < n || inr[cc]) ? 1 : 0);
+      }
+    }
+  }
+  if (q < 0) return;
+  for (int k = c; k < R; ++k)
+    if (lane == 0) {
+      s_rt[wave * R + k] = __builtin_inf();
+      s_tau[wave * R + k] = __builtin_inf();
+      s_row[wave * R + k] = INT_MAX;
+    }
+  __syncthreads();
+  if (wave == 0) {
+    constexpr int slots = waves * R;
+    double th = __builtin_inf(), t1 = __builtin_inf(), t2 = __builtin_inf();
+    int low = INT_MAX, slot = 0;
+    for (int k = lane; k < slots; k += 64) {
+      if (lex_less(s_rt[k], s_row[k], th, low)) {
+        th = s_rt[k];
+        low = s_row[k];
+        slot = k;
+      }
+      const double tk = s_tau[k];
+      if (tk < t1) {
+        t2 = t1;
+        t1 = tk;
+      } else if (tk < t2) {
+        t2 = tk;
+      }
+    }
+    wave_lexmin_payload(th, low, slot);
+    wave_two_smallest(t1, t2);
+    if (lane == 0) {
+      lp.part_th[blockIdx.x] = s_nf ? -__builtin_inf() : th;
+      lp.part_low[blockIdx.x] = s_nf ? -1 : low;
+      lp.part_t1[blockIdx.x] = t1;
+      lp.part_t2[blockIdx.x] = t2;
+      lp.part_al[blockIdx.x] = low != INT_MAX ? s_al[slot] : 0.0;
+      lp.part_bv[blockIdx.x] = low != INT_MAX ? s_bv[slot] : 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // Step 6 finish and the scalar part of Step 8 (one workgroup).  Every k_update workgroup
 // left its minimum ratio (with the lowest row attaining it, that row's alpha and basic
 // variable) and the two smallest tie thresholds of its rows; x_B and alpha of this
@@ -1007,17 +1326,21 @@ __global__ void k_check_finite(const double* __restrict__ x, int64_t count, doub
 const void* price_kernel() { return reinterpret_cast<const void*>(&k_price); }
 // k_update's workgroup size for a row stride ld: kUpdateBlock threads, or twice that where
 // the staging in LDS admits only one such workgroup per CU and one of the larger ones
-// fits (it keeps twice the wavefronts in flight).
+// fits (it keeps twice the wavefronts in flight); -kUpdateBlock: k_update_wide, for rows
+// whose staging does not fit at all.
+size_t wide_lds_bytes(int ld) {
+  return std::max<size_t>(2 * sizeof(double2) * (size_t)kWideChunk2, (2 * sizeof(double) + sizeof(int)) * (size_t)(ld / 8));
+}
 int update_block(int ld) {
   const int lds = (int)update_lds_bytes(ld);
   int small = 0, large = 0;
   const void* fs = reinterpret_cast<const void*>(&k_update<kUpdateBlock>);
   const void* fl = reinterpret_cast<const void*>(&k_update<2 * kUpdateBlock>);
-  if (hipFuncSetAttribute(fs, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&small, k_update<kUpdateBlock>, kUpdateBlock, lds) !=
-          hipSuccess) {
-    (void)hipGetLastError();  // reported by the caller's own occupancy query
-    return kUpdateBlock;
+  if (ld > kUpdateStageMaxLd || hipFuncSetAttribute(fs, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&small, k_update<kUpdateBlock>, kUpdateBlock, lds) != hipSuccess ||
+      small < 1) {
+    (void)hipGetLastError();
+    return -kUpdateBlock;
   }
   if (small >= 2) return kUpdateBlock;
   // The larger workgroup has more static LDS: near the largest ld it may not fit at all,
@@ -1032,7 +1355,8 @@ int update_block(int ld) {
 }
 const void* update_kernel_for_block(int block) {
   return block == kUpdateBlock ? reinterpret_cast<const void*>(&k_update<kUpdateBlock>)
-                               : reinterpret_cast<const void*>(&k_update<2 * kUpdateBlock>);
+         : block > 0           ? reinterpret_cast<const void*>(&k_update<2 * kUpdateBlock>)
+                               : reinterpret_cast<const void*>(&k_update_wide<kUpdateBlock>);
 }
 const void* update_kernel(int ld) { return update_kernel_for_block(update_block(ld)); }
 const void* finish_kernel() { return reinterpret_cast<const void*>(&k_finish); }
@@ -1042,20 +1366,24 @@ size_t price_lds_bytes(int ld) { return sizeof(double) * (size_t)ld; }
 size_t update_lds_bytes(int ld) {
   return 2 * sizeof(double) * (size_t)ld + (ld >= kSparseMinLd ? sizeof(int) * (size_t)(ld / 8) : 0);
 }
+size_t update_lds_for_block(int block, int ld) { return block > 0 ? update_lds_bytes(ld) : wide_lds_bytes(ld); }
 
 hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_price),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)price_lds_bytes(ld));
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(update_kernel(ld), hipFuncAttributeMaxDynamicSharedMemorySize, (int)update_lds_bytes(ld));
+  const int blk = update_block(ld);
+  const int lds = (int)update_lds_for_block(blk, ld);
+  e = hipFuncSetAttribute(update_kernel_for_block(blk), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(price_per_cu, k_price, kPriceBlock, price_lds_bytes(ld));
   if (e != hipSuccess) return e;
-  if (update_block(ld) == kUpdateBlock)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update<kUpdateBlock>, kUpdateBlock,
-                                                        update_lds_bytes(ld));
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update<2 * kUpdateBlock>, 2 * kUpdateBlock,
-                                                      update_lds_bytes(ld));
+  if (blk == kUpdateBlock)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update<kUpdateBlock>, kUpdateBlock, lds);
+  if (blk > 0)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update<2 * kUpdateBlock>, 2 * kUpdateBlock,
+                                                        lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update_wide<kUpdateBlock>, kUpdateBlock, lds);
 }
 
 hipError_t launch_init(const DevLP& lp, const double* b, const double* c, double sense, hipStream_t s) {
@@ -1071,7 +1399,9 @@ hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s) {
 }
 
 hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s) {
-  if (lp.upd_block == kUpdateBlock)
+  if (lp.upd_block < 0)
+    hipLaunchKernelGGL(k_update_wide<kUpdateBlock>, dim3(grid), dim3(kUpdateBlock), wide_lds_bytes(lp.ld), s, lp);
+  else if (lp.upd_block == kUpdateBlock)
     hipLaunchKernelGGL(k_update<kUpdateBlock>, dim3(grid), dim3(kUpdateBlock), update_lds_bytes(lp.ld), s, lp);
   else
     hipLaunchKernelGGL(k_update<2 * kUpdateBlock>, dim3(grid), dim3(2 * kUpdateBlock), update_lds_bytes(lp.ld), s,

@@ -926,7 +926,7 @@ int invert_large(ReinvState* st, int k, int m, int32_t* rowperm, int32_t* opos, 
       const int R = k - j0, room = J0 + JBo - j0;
       int jb;
       hipError_t e;
-      // Inner panel shapes that keep the rows in registers without spills; R <= LP_MAX_ROWS.
+      // Inner panel shapes that keep the rows in registers without spills; R <= LP_MAX_ROWS <= 20480.
       // The per-column cost is synchronisation across the workgroup's wavefronts, so the
       // workgroup is no larger than the panel needs.
       if (R <= 256) {
@@ -944,9 +944,12 @@ int invert_large(ReinvState* st, int k, int m, int32_t* rowperm, int32_t* opos, 
       } else if (R <= 4096) {
         jb = std::min(4, room);
         e = launch_inner_panel<1024, 4, 4>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
-      } else {
+      } else if (R <= 10240) {
         jb = std::min(2, room);
         e = launch_inner_panel<1024, 10, 2>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
+      } else {
+        jb = 1;
+        e = launch_inner_panel<1024, 20, 1>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
       }
       R_HIP(e, "launching a panel factorisation");
       const int rows = k - j0 - jb, cols = J0 + JBo - j0 - jb;

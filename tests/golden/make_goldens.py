@@ -36,6 +36,11 @@ GOLDENS = {
                             "a row stride above 4800, where the update runs its larger workgroups"),
     "diagonal_m9700_n1300_s0": ("diagonal", 0, 9700, 1300, None,
                                 "near the row limit, with more than 1024 slacks leaving the basis"),
+    "dense_m12000_n150_s0": ("dense", 0, 12000, 150, None,
+                             "rows longer than the update kernel's whole-vector staging (chunked dense pass)"),
+    "diagonal_m12000_n1600_s0": ("diagonal", 0, 12000, 1600, None,
+                                 "long rows in sparse-column mode (staging at the entries of D) until D "
+                                 "passes ld/8, then chunked dense"),
     "degenerate_m5000_n10000_s0": ("degenerate", 0, 5000, 10000, 3000,
                                    "the degenerate law at full size: a 3000-pivot prefix"),
     "degenerate_budget_m5001_n10000_s0": ("degenerate_budget", 0, 5000, 10000, 3000,

@@ -183,12 +183,13 @@ def test_degenerate_budget_500_full_parity(lpg):
 
 
 def test_max_rows(lpg):
-    """m = LP_MAX_ROWS (the largest m whose update-kernel staging fits the LDS of one CU):
-    the solve runs and takes the oracle's pivots; one row more is rejected."""
+    """m = LP_MAX_ROWS (the largest m whose pricing kernel stages W in the LDS of one CU; the
+    update kernel stages its vectors in chunks there): the solve runs and takes the
+    oracle's pivots; one row more is rejected."""
     m, n = lpg.binding.LP_MAX_ROWS, 24
     _say(f"case: dense law m={m} n={n} seed 0 (LP_MAX_ROWS)")
     A, b, c = lpgen.dense_lp(0, m, n)
-    ref = oracle.solve(A, b, c)
+    ref = oracle.solve(A, b, c, lib_path=oracle.omp_lib())
     with lpg.LP(A, b, c) as p:
         st = p.solve()
         piv = p.pivots()
