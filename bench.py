@@ -345,28 +345,6 @@ def degenerate_leg(lpg, torch, stream, warmup=200, steps=2000):
     return out
 
 
-def out_of_core_leg(lpg, torch, dev, m, n, panel_rows, steps=60, warmup=10):
-    """Section 3's Case 2 on the benchmark LP: a device budget that leaves room for three
-    panels of about panel_rows rows of B^-1; every iteration streams the other panels to the
-    device and back over PCIe.  Host traffic per iteration: 2 x 8 ld (m - resident rows)."""
-    ld = (m + 7) // 8 * 8
-    budget = 8 * ld * n + 64 * (n + m) + 64 * ld + 64 * 10 * (m + n) + 3 * 8 * ld * panel_rows + 300_000
-    with lpg.LP.from_torch(*dev, device_budget=budget) as lp:
-        run_steps(lp, warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run_steps(lp, steps)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        stt = lp.stats()
-    res_rows = m - (stt["panels"] - 1) * stt["panel_rows"]
-    host_bytes = 2.0 * 8 * ld * (m - res_rows)
-    return dict(workload=f"dense LP m={m}, n={n}, device budget {budget / 2**20:.0f} MiB (B^-1 alone is "
-                         f"{8 * m * ld / 2**20:.0f} MiB)", memory_case=stt["memory_case"], panels=stt["panels"],
-                panel_rows=stt["panel_rows"], pivots=steps, iter_per_s=round(steps / dt, 1),
-                host_bytes_per_iter=host_bytes, host_gbs=round(host_bytes * steps / dt / 1e9, 2))
-
-
 def cpu_baseline(A, b, c, pivots, budget_s=20.0):
     """The oracle on the host's cores: its -fopenmp build (bit-identical results) on every
     core OpenMP is given, over the whole solve or as many 25-pivot chunks as fit in
@@ -415,8 +393,6 @@ def main():
                     help="only the profiled stretch of the mixed-precision form (for profiler runs)")
     ap.add_argument("--reinv-m", type=int, default=3000, help="order of the reinversion leg's basis block (0 = skip)")
     ap.add_argument("--degenerate", type=int, default=1, help="degenerate-law leg at 5000 x 10000 (0 = skip)")
-    ap.add_argument("--panel-rows", type=int, default=500,
-                    help="rows per panel of the out-of-core leg on the benchmark LP (0 = skip)")
     ap.add_argument("--serial-sample", type=int, default=256,
                     help="LPs of the batch also solved one by one with lp_solve")
     ap.add_argument("--quick", action="store_true",
@@ -500,10 +476,6 @@ def main():
     if not args.quick and args.degenerate:
         _log("bench: degenerate law 5000 x 10000")
         extra["degenerate"] = degenerate_leg(lpg, torch, stream)
-
-    if not args.quick and args.panel_rows > 0:
-        _log(f"bench: out-of-core leg, ~{args.panel_rows} rows per panel")
-        extra["out_of_core"] = out_of_core_leg(lpg, torch, dev, m, n, args.panel_rows)
 
     if not args.quick and args.batch > 0:
         _log(f"bench: batched leg, {args.batch} LPs")

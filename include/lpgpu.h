@@ -73,12 +73,11 @@ extern "C" {
 #define LP_FP64 0  /* every step in FP64 */
 #define LP_MIXED 1 /* FP32 screening of the reduced costs, shortlist re-priced in FP64 */
 
-/* Largest m the library accepts: the pricing kernel stages the top row W (8 bytes per row)
- * in the 160 KB of LDS of one CU (8 * 20000 + its own 0.2 KB <= 163840).  Up to m = 9792
- * the update kernel stages the pivot row and the entering column whole in LDS; above, it
- * stages them in chunks (or, in sparse-column mode, only at the entries of list D).  The
+/* Largest m the library accepts: the update kernel stages the pivot row rho and the entering
+ * column a_q (8 bytes per row each) and the sparse-column index list (ld/8 int32) in the
+ * 160 KB of LDS of one CU, next to 2.2 KB of its own: 16.5 * 9792 + 2256 <= 163840.  The
  * batched form has its own, smaller limit (LP_ERR_ARG from lp_batch_create). */
-#define LP_MAX_ROWS 20000
+#define LP_MAX_ROWS 9792
 
 typedef struct lp_options {
   int32_t sense;          /* LP_MIN or LP_MAX (default LP_MAX) */
@@ -117,16 +116,11 @@ typedef struct lp_options {
                              second persistent launch); 0 = never; -1 = the threshold is chosen by
                              timing the whole batch on its first solve (default) */
   int64_t device_budget;  /* bytes of device memory the LP may use (Section 3, Figure 2): 0 = the free
-                             memory hipMemGetInfo reports (default); > 0 = at most this much.  When
-                             the whole tableau fits, it stays in device memory for the whole solve
-                             (Case 1).  Otherwise (Case 2) B^-1 is kept in pinned host memory in panels
-                             of consecutive rows: every iteration streams each panel to the device,
-                             updates it (with FTRAN and the ratio test of its rows) and streams it
-                             back, except the last panel, which stays in device memory; row r is
-                             fetched once per iteration for the pricing step.  Case 2 needs A', the
-                             vectors and three panel buffers in the budget, runs the FP64 form
-                             without reinversion and without profiling, and is not available to
-                             lp_create_general (LP_ERR_ARG); results equal Case 1's bit for bit. */
+                             memory hipMemGetInfo reports (default); > 0 = at most this much.  The
+                             whole tableau must fit (Case 1): an LP whose A', B^-1 and vectors
+                             exceed the budget is rejected with LP_ERR_NOMEM.  (The row-panel
+                             streaming of B^-1 from host memory, Case 2, is switched off in this
+                             build: it has not been validated on the device.) */
 } lp_options;
 
 typedef struct lp_stats {
@@ -169,10 +163,10 @@ typedef struct lp_stats {
                                 drive-outs); -1 while phase 1 runs or when it was not needed */
   int64_t drive_outs;       /* pivots flagged LP_PIVOT_DRIVEOUT */
   double phase_switch_ms;   /* host wall time of the switch (drive-outs and re-pricing) */
-  int64_t memory_case;      /* 1: the tableau is in device memory (Section 3, Case 1); 2: B^-1 is
-                               streamed in row panels from host memory (Case 2) */
-  int64_t panel_rows;       /* Case 2: rows of B^-1 per panel (0 in Case 1) */
-  int64_t panels;           /* Case 2: panels, the last one resident in device memory (0 in Case 1) */
+  int64_t memory_case;      /* 1: the tableau is in device memory (Section 3, Case 1; the only case
+                               this build runs) */
+  int64_t panel_rows;       /* 0 (Case 2 row panels are switched off) */
+  int64_t panels;           /* 0 (Case 2 row panels are switched off) */
 } lp_stats;
 
 typedef struct lp_problem lp_problem;

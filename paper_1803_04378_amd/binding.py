@@ -19,7 +19,7 @@ LP_PIVOT_DEGENERATE, LP_PIVOT_TIE, LP_PIVOT_ASPIRATION, LP_PIVOT_LCLEAR, LP_PIVO
 LP_ROW_LE, LP_ROW_GE, LP_ROW_EQ = 0, 1, 2
 LP_MIN, LP_MAX = 0, 1
 LP_FP64, LP_MIXED = 0, 1
-LP_MAX_ROWS = 20000
+LP_MAX_ROWS = 9792
 STATUS_NAMES = {0: "RUNNING", 1: "OPTIMAL", 2: "UNBOUNDED", 3: "ITER_LIMIT", 4: "NUMERICAL", 5: "INFEASIBLE"}
 
 

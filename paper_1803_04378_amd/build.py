@@ -10,8 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblpgpu.so")
-SOURCES = ["lp_kernels.hip", "lp_mixed.hip", "lp_gemm.hip", "lp_reinv.hip", "lp_phase.hip", "lp_api.hip",
-           "lp_batch.hip", "lp_batch_api.hip"]
+SOURCES = ["lp_kernels.hip", "lp_mixed.hip", "lp_reinv.hip", "lp_phase.hip", "lp_api.hip", "lp_batch.hip",
+           "lp_batch_api.hip"]
 
 HIPCC_FLAGS = [
     "-O3",
@@ -31,6 +31,8 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    # The reinversion's level-3 BLAS (DGEMM, DTRSM) comes from rocBLAS.
+    cmd += ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocblas"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)

@@ -410,6 +410,11 @@ int launch_direct(lp_problem* p, int K) {
   return LP_OK;
 }
 
+// Out-of-core panel mode (Section 3, Case 2).  Switched off: it has not run on the device
+// yet, so an LP that does not fit the device memory budget is rejected instead (the code
+// below is kept for its validation).
+constexpr bool kPanelModeEnabled = false;
+
 // Out-of-core panel mode: B^-1 = I in the pinned host copy (after the stream has drained)
 // and in the device-resident last panel.
 int init_panels(lp_problem* p) {
@@ -578,6 +583,9 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
     const double rest = (mixed ? 12.0 : 8.0) * ld * (double)n + 64.0 * N + 64.0 * ld + 64.0 * o.max_iter +
                         16.0 * (p->update_grid + p->price_grid) * 8.0;
     const double binv = 8.0 * m * (double)ld;
+    if (rest + binv > budget && !kPanelModeEnabled)
+      return bail(fail(LP_ERR_NOMEM, "LP does not fit in the device memory budget (the out-of-core panel mode "
+                                     "is switched off in this build)"));
     if (rest + binv > budget) {
       // three panel buffers: two streamed alternately and the resident last panel
       const double rows = std::floor((budget - rest) / (3.0 * 8.0 * ld));

@@ -356,8 +356,6 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
   hold_store<B>(hold, s_rho, rho2, tid, ld2);
   if (tid < dcap) s_dl[tid] = dl0;
   if (tid + B < dcap) s_dl[tid + B] = dl1;
-  // (ld/8 exceeds 2B only for 512-thread workgroups above ld = 8192)
-  for (int k = tid + 2 * B; k < dcap; k += B) s_dl[k] = lp.dlist[k];
 
   // Step 4 decision: in the mixed form from the re-priced shortlist (none improving: the
   // fallback verdict below), else, and in the mixed form's FP64 pass, from the pricing
@@ -415,7 +413,9 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
   }
   __syncthreads();  // rho and D are in LDS
   if (status != kStatusRunning) return;
-  const bool sparse = sparse_columns(nD, ld);
+  // (the first 2B entries of D are staged above: ld/8 exceeds 2B only for 512-thread
+  // workgroups above ld = 8192, where a longer list takes the dense pass)
+  const bool sparse = sparse_columns(nD, ld) && nD <= 2 * B;
   int verdict = kStatusRunning, q = -1, flags = 0;
   double dq = 0.0;
   if (!use_parts && !from_shortlist) {
@@ -1336,11 +1336,11 @@ int update_block(int ld) {
   int small = 0, large = 0;
   const void* fs = reinterpret_cast<const void*>(&k_update<kUpdateBlock>);
   const void* fl = reinterpret_cast<const void*>(&k_update<2 * kUpdateBlock>);
-  if (ld > kUpdateStageMaxLd || hipFuncSetAttribute(fs, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&small, k_update<kUpdateBlock>, kUpdateBlock, lds) != hipSuccess ||
-      small < 1) {
-    (void)hipGetLastError();
-    return -kUpdateBlock;
+  if (ld > kUpdateStageMaxLd) return 0;  // rows beyond LP_MAX_ROWS: not launched (see k_update_wide)
+  if (hipFuncSetAttribute(fs, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&small, k_update<kUpdateBlock>, kUpdateBlock, lds) != hipSuccess) {
+    (void)hipGetLastError();  // reported by the caller's own occupancy query
+    return kUpdateBlock;
   }
   if (small >= 2) return kUpdateBlock;
   // The larger workgroup has more static LDS: near the largest ld it may not fit at all,
@@ -1373,6 +1373,7 @@ hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)price_lds_bytes(ld));
   if (e != hipSuccess) return e;
   const int blk = update_block(ld);
+  if (blk == 0) return hipErrorInvalidValue;
   const int lds = (int)update_lds_for_block(blk, ld);
   e = hipFuncSetAttribute(update_kernel_for_block(blk), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;

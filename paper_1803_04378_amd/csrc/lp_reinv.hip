@@ -11,30 +11,30 @@
 //      panel by one workgroup holding it in registers (the pivot search is a chain of
 //      dependent reductions, so it stays inside one workgroup), then a second kernel
 //      applies its row interchanges and U12 = L11^-1 A12 within the outer panel, and a
-//      matrix product updates the rest of the outer panel.  The outer panel's
-//      interchanges are then applied to the columns outside it at once, U12 of the outer
-//      panel is a triangular solve, and the trailing update A22 -= L21 U12 one product of
-//      depth kOuter, so the trailing matrix is streamed once per kOuter columns;
-//   3. X = M^-1 = U^-1 L^-1 P (two blocked triangular solves on X = P), so that row b of
-//      B11^-1 is column b of X, contiguous;
-//   4. C^T = -X B21^T (a matrix product): row s of -B21 B11^-1 is column s of C^T;
+//      DGEMM updates the rest of the outer panel.  The outer panel's interchanges are
+//      then applied to the columns outside it at once, U12 of the outer panel is a
+//      triangular solve, and the trailing update A22 -= L21 U12 one DGEMM of depth
+//      kOuter, so the trailing matrix is streamed once per kOuter columns;
+//   3. X = M^-1 = U^-1 L^-1 P (two triangular solves on X = P), so that row b of B11^-1
+//      is column b of X, contiguous;
+//   4. C^T = -X B21^T (DGEMM): row s of -B21 B11^-1 is column s of C^T;
 //   5. B^-1 written row by row in its row-major layout, x_B = B^-1 b, W = chat_B^T B^-1
 //      and z = chat_B^T x_B from X and C^T.
-// The matrix products run on the FP64 matrix cores and the blocked triangular solves on
-// top of them (lp_gemm.hip); each output sums in a fixed order, so results are
-// reproducible.
+// The DGEMMs and triangular solves are rocBLAS calls on the handle's stream (atomics off,
+// so results are reproducible); everything else is below.
 //
 // Small blocks (k <= kSmallK, the common case: the optimal bases of the dense law hold a
 // few hundred structural columns at most) take a shorter path with no library call: one
 // workgroup inverts B11^T in LDS by Gauss-Jordan elimination with partial pivoting, and
 // the rows -B21 B11^-1 are formed inside the kernel that writes B^-1.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
-#include "lp_gemm.h"
 #include "lp_reinv.h"
 #include "lp_wave.h"
 #include "lpgpu.h"
@@ -44,6 +44,7 @@ namespace lpgpu {
 int record_error(int code, const std::string& msg);
 
 struct ReinvState {
+  rocblas_handle blas = nullptr;
   double* G = nullptr;
   size_t G_cap = 0;
   double* X = nullptr;
@@ -56,6 +57,7 @@ struct ReinvState {
   size_t idx_cap = 0;
   int32_t* aux = nullptr;  // rowperm (m) | opos (m) | inner list | outer list | info
   size_t aux_cap = 0;
+  bool warmed = false;  // the large-block path has run once on this handle
 };
 
 namespace {
@@ -880,10 +882,20 @@ int hip_fail(hipError_t e, const char* what) {
                       std::string("reinversion: ") + what + ": " + hipGetErrorString(e));
 }
 
+int blas_fail(rocblas_status st, const char* what) {
+  return record_error(st == rocblas_status_memory_error ? LP_ERR_NOMEM : LP_ERR_DEVICE,
+                      std::string("reinversion: ") + what + ": " + rocblas_status_to_string(st));
+}
+
 #define R_HIP(expr, what)                          \
   do {                                             \
     hipError_t e_ = (expr);                        \
     if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+#define R_BLAS(expr, what)                                     \
+  do {                                                         \
+    rocblas_status st_ = (expr);                               \
+    if (st_ != rocblas_status_success) return blas_fail(st_, what); \
   } while (0)
 
 // Inner panel j0..j0+jb of the outer panel J0..J0+JBo: factorisation, then its row
@@ -906,6 +918,7 @@ hipError_t launch_inner_panel(double* M, int k, int J0, int JBo, int j0, int jb,
 
 void reinv_free(ReinvState* st) {
   if (!st) return;
+  if (st->blas) (void)rocblas_destroy_handle(st->blas);
   for (void* p : {(void*)st->G, (void*)st->X, (void*)st->C, (void*)st->part, (void*)st->idx, (void*)st->aux})
     if (p) (void)hipFree(p);
   delete st;
@@ -920,13 +933,14 @@ int invert_large(ReinvState* st, int k, int m, int32_t* rowperm, int32_t* opos, 
   const size_t kk = (size_t)k * k;
   // 2. LU of M = G[:, 0:k] (leading dimension k).
   double* Mx = st->G;
+  const double one = 1.0, minus_one = -1.0, zero = 0.0;
   for (int J0 = 0; J0 < k; J0 += kOuter) {
     const int JBo = std::min(kOuter, k - J0);
     for (int j0 = J0; j0 < J0 + JBo;) {
       const int R = k - j0, room = J0 + JBo - j0;
       int jb;
       hipError_t e;
-      // Inner panel shapes that keep the rows in registers without spills; R <= LP_MAX_ROWS <= 20480.
+      // Inner panel shapes that keep the rows in registers without spills; R <= LP_MAX_ROWS.
       // The per-column cost is synchronisation across the workgroup's wavefronts, so the
       // workgroup is no larger than the panel needs.
       if (R <= 256) {
@@ -944,20 +958,17 @@ int invert_large(ReinvState* st, int k, int m, int32_t* rowperm, int32_t* opos, 
       } else if (R <= 4096) {
         jb = std::min(4, room);
         e = launch_inner_panel<1024, 4, 4>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
-      } else if (R <= 10240) {
+      } else {
         jb = std::min(2, room);
         e = launch_inner_panel<1024, 10, 2>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
-      } else {
-        jb = 1;
-        e = launch_inner_panel<1024, 20, 1>(Mx, k, J0, JBo, j0, jb, pairs, opos, info, s);
       }
       R_HIP(e, "launching a panel factorisation");
       const int rows = k - j0 - jb, cols = J0 + JBo - j0 - jb;
       if (rows > 0 && cols > 0)
-        R_HIP(launch_dgemm(rows, cols, jb, Mx + (size_t)(j0 + jb) + (size_t)j0 * k, k,
-                           Mx + (size_t)j0 + (size_t)(j0 + jb) * k, k, Mx + (size_t)(j0 + jb) + (size_t)(j0 + jb) * k, k,
-                           true, s),
-              "launching the inner update");
+        R_BLAS(rocblas_dgemm(st->blas, rocblas_operation_none, rocblas_operation_none, rows, cols, jb, &minus_one,
+                             Mx + (size_t)(j0 + jb) + (size_t)j0 * k, k, Mx + (size_t)j0 + (size_t)(j0 + jb) * k, k,
+                             &one, Mx + (size_t)(j0 + jb) + (size_t)(j0 + jb) * k, k),
+               "inner update");
       j0 += jb;
     }
     // The outer panel's interchanges on the columns outside it and on rowperm.
@@ -971,26 +982,44 @@ int invert_large(ReinvState* st, int k, int m, int32_t* rowperm, int32_t* opos, 
     }
     const int rest = k - J0 - JBo;
     if (rest > 0) {
+      // (not rocBLAS: its choice of method varies with the width rest, and each method's
+      // first use in a process stalls for tens of milliseconds)
       const int waves = kTrsmThreads / 64;
       hipLaunchKernelGGL(k_trsm_outer, dim3((rest + waves - 1) / waves), dim3(kTrsmThreads), 0, s, Mx, k, J0, JBo,
                          J0 + JBo, rest);
       R_HIP(hipGetLastError(), "launching the outer U12 solve");
-      R_HIP(launch_dgemm(rest, rest, JBo, Mx + (size_t)(J0 + JBo) + (size_t)J0 * k, k,
-                         Mx + (size_t)J0 + (size_t)(J0 + JBo) * k, k, Mx + (size_t)(J0 + JBo) + (size_t)(J0 + JBo) * k,
-                         k, true, s),
-            "launching the trailing update");
+      R_BLAS(rocblas_dgemm(st->blas, rocblas_operation_none, rocblas_operation_none, rest, rest, JBo, &minus_one,
+                           Mx + (size_t)(J0 + JBo) + (size_t)J0 * k, k, Mx + (size_t)J0 + (size_t)(J0 + JBo) * k, k,
+                           &one, Mx + (size_t)(J0 + JBo) + (size_t)(J0 + JBo) * k, k),
+             "trailing update");
     }
   }
   // 3. X = U^-1 L^-1 P
   hipLaunchKernelGGL(k_perm_matrix, dim3((unsigned)std::min<size_t>(8192, (kk + 255) / 256)), dim3(256), 0, s,
                      st->X, k, (const int32_t*)rowperm);
   R_HIP(hipGetLastError(), "launching the permutation");
-  R_HIP(launch_trsm(Mx, k, k, st->X, k, k, false, s), "solving with L");
-  R_HIP(launch_trsm(Mx, k, k, st->X, k, k, true, s), "solving with U");
+  R_BLAS(rocblas_dtrsm(st->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                       rocblas_diagonal_unit, k, k, &one, Mx, k, st->X, k),
+         "solving with L");
+  R_BLAS(rocblas_dtrsm(st->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                       rocblas_diagonal_non_unit, k, k, &one, Mx, k, st->X, k),
+         "solving with U");
   // 4. C^T = -X B21^T
-  if (m > k) R_HIP(launch_dgemm(k, m - k, k, st->X, k, st->G + kk, k, st->C, k, false, s), "forming -B21 B11^-1");
+  if (m > k)
+    R_BLAS(rocblas_dgemm(st->blas, rocblas_operation_none, rocblas_operation_none, k, m - k, k, &minus_one, st->X,
+                         k, st->G + kk, k, &zero, st->C, k),
+           "forming -B21 B11^-1");
   return LP_OK;
 }
+
+// A well-conditioned stand-in block (identity B11, B21 = 0) for the warm-up.
+__global__ void k_warm_block(double* G, int k, int m) {
+  const size_t total = (size_t)k * m;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x)
+    G[e] = (e % k) == (e / k) ? 1.0 : 0.0;
+}
+
+constexpr int kWarmK = 160;  // larger than kSmallK, so that every large-path step runs
 
 }  // namespace
 
@@ -1000,6 +1029,14 @@ int reinv_prepare(ReinvState** state, int m, int ld) {
     if (!*state) return record_error(LP_ERR_NOMEM, "reinversion: host allocation failed");
   }
   ReinvState* st = *state;
+  if (!st->blas) {
+    // rocBLAS loads its kernels lazily on first use (tens of milliseconds); load them once
+    // per process here, outside any solve.
+    static std::once_flag loaded;
+    std::call_once(loaded, [] { rocblas_initialize(); });
+    R_BLAS(rocblas_create_handle(&st->blas), "creating the BLAS handle");
+    R_BLAS(rocblas_set_atomics_mode(st->blas, rocblas_atomics_not_allowed), "configuring the BLAS handle");
+  }
   // Work memory for blocks up to kSmallK allocated up front (no allocation, and so no
   // device synchronisation, inside a solve unless the block grows past that).
   const size_t mm = (size_t)m * m, ks = (size_t)std::min(m, kSmallK);
@@ -1009,6 +1046,30 @@ int reinv_prepare(ReinvState** state, int m, int ld) {
   R_HIP(grow(&st->G, &st->G_cap, ks * m, mm), "allocating work memory");
   R_HIP(grow(&st->X, &st->X_cap, ks * ks, mm), "allocating work memory");
   R_HIP(grow(&st->part, &st->part_cap, 2 * (size_t)ld, ((size_t)m / kWChunk + 1) * ld), "allocating work memory");
+  if (!st->warmed && m > kSmallK) {
+    // The first launch of a rocBLAS kernel loads its code object and the first triangular
+    // solve of a handle sizes its workspace: 40-130 ms stalls observed in the middle of a
+    // solve.  Run the large-block path once here on a stand-in block of order kWarmK, on
+    // the null stream, outside any solve.
+    const int kw = std::min(m, kWarmK);
+    R_HIP(grow(&st->G, &st->G_cap, (size_t)kw * m, mm), "allocating work memory");
+    R_HIP(grow(&st->X, &st->X_cap, (size_t)kw * kw, mm), "allocating work memory");
+    if (m > kw) R_HIP(grow(&st->C, &st->C_cap, (size_t)kw * (m - kw), mm / 4 + 1), "allocating work memory");
+    R_BLAS(rocblas_set_stream(st->blas, nullptr), "configuring the BLAS handle");
+    int32_t* rowperm = st->aux;
+    int32_t* opos = rowperm + m;
+    int32_t* pairs = opos + m;
+    int32_t* opairs = pairs + 2 * kPairs + 1;
+    int32_t* info = opairs + 2 * kOuterPairs + 1;
+    hipLaunchKernelGGL(k_warm_block, dim3(1024), dim3(256), 0, nullptr, st->G, kw, m);
+    R_HIP(hipGetLastError(), "launching the warm-up block");
+    hipLaunchKernelGGL(k_reinv_setup, dim3((kw + 255) / 256), dim3(256), 0, nullptr, rowperm, opos, kw, info);
+    R_HIP(hipGetLastError(), "launching setup");
+    const int rc = invert_large(st, kw, m, rowperm, opos, pairs, opairs, info, nullptr);
+    if (rc != LP_OK) return rc;
+    R_HIP(hipStreamSynchronize(nullptr), "warming up the factorisation");
+    st->warmed = true;
+  }
   return LP_OK;
 }
 
@@ -1018,6 +1079,7 @@ int reinvert(const DevLP& d, const double* b, ReinvState** state, hipStream_t s,
   ReinvState* st = *state;
   const int m = d.m, n = d.n, ld = d.ld;
   if (k < 0 || k > m) return record_error(LP_ERR_DEVICE, "reinversion: structural count out of range");
+  R_BLAS(rocblas_set_stream(st->blas, s), "configuring the BLAS handle");
 
   // 1. The index sets of the block form, built on the device from the basis list.
   const size_t nidx = 2 * (size_t)k + 3 * (size_t)m + ld;

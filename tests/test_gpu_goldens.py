@@ -50,7 +50,17 @@ def _compare(name, g, piv, st, sol, lpg):
         assert rel <= OBJ_RTOL
 
 
-@pytest.mark.parametrize("name", list(make_goldens.GOLDENS))
+# Cases whose kernels are switched off in the library: rows above LP_MAX_ROWS (the chunked
+# update kernel) and, near the row limit, sparse-column mode with more than 2B entries of D.
+# A GPU run that first exercised these paths (with others new at the time) faulted the
+# device without output naming the kernel; the CPU emulation of the kernels found no
+# out-of-bounds access, so they stay off until they are validated on the device.
+SWITCHED_OFF = {"dense_m12000_n150_s0", "diagonal_m12000_n1600_s0", "diagonal_m9700_n1300_s0"}
+
+
+@pytest.mark.parametrize("name", [pytest.param(n, marks=pytest.mark.skip(reason="kernel path switched off until "
+                                                                            "validated on the device"))
+                                  if n in SWITCHED_OFF else n for n in make_goldens.GOLDENS])
 def test_gpu_follows_oracle_log(lpg, name):
     g = make_goldens.load(name)
     law, seed, m, n, cap, what = make_goldens.GOLDENS[name]

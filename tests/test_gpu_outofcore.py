@@ -11,7 +11,12 @@ import pytest
 import lpgen
 import oracle
 
-pytestmark = pytest.mark.gpu
+# Case 2 is switched off in the library (an LP beyond the budget gets LP_ERR_NOMEM): a GPU run
+# that exercised it, among other paths new at the time, faulted the device with no output to
+# name the failing kernel, and the CPU emulation of the kernels found no out-of-bounds access.
+pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason="out-of-core panel mode switched off until it is validated "
+                                                       "on the device (unexplained device fault in the run that "
+                                                       "first exercised it)")]
 
 
 def _say(msg):
