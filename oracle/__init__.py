@@ -91,6 +91,8 @@ def lib(path: str | None = None):
         L.oracle_state.argtypes = [P, dp, dp, dp, dp]
         L.oracle_pivots.restype = I64
         L.oracle_pivots.argtypes = [P, ip, ip, ip, ip, I64]
+        L.oracle_margins.restype = I64
+        L.oracle_margins.argtypes = [P, dp, I64]
         L.oracle_counts.argtypes = [P, C.POINTER(C.c_int64)]
         L.oracle_set_threads.restype = I32
         L.oracle_set_threads.argtypes = [I32]
@@ -122,6 +124,9 @@ class Result:
     flags: np.ndarray
     counts: dict = field(default_factory=dict)
     ray: int = -1
+    # per pivot: the distance of its closest decision from its threshold or rival value
+    # (a report, never used in a decision; inf for drive-out pivots)
+    margin: np.ndarray = None
 
     @property
     def status_name(self):
@@ -205,13 +210,15 @@ class Oracle:
         lv = np.empty(cnt, dtype=np.int32)
         f = np.empty(cnt, dtype=np.int32)
         L.oracle_pivots(self._h, _ip(e), _ip(r), _ip(lv), _ip(f), cnt)
+        mg = np.empty(cnt)
+        L.oracle_margins(self._h, _dp(mg), cnt)
         counts = (C.c_int64 * 4)()
         L.oracle_counts(self._h, counts)
         return Result(status=L.oracle_status(self._h), iterations=L.oracle_iterations(self._h),
                       objective=L.oracle_objective(self._h), x=x, y=y, basis=basis, enter=e, row=r,
                       leave=lv, flags=f,
                       counts=dict(degenerate=counts[0], tie=counts[1], aspiration=counts[2], lclear=counts[3]),
-                      ray=L.oracle_ray(self._h))
+                      ray=L.oracle_ray(self._h), margin=mg)
 
 
 def solve(A, b, c, sense="max", max_iter=None, **kw) -> Result:

@@ -131,6 +131,7 @@ typedef struct {
   int32_t status, ray;
   int64_t n_degenerate, n_tie, n_aspiration, n_lclear;
   int32_t *log_enter, *log_row, *log_leave, *log_flags;
+  double *log_margin; /* per pivot: how close its closest decision came to its threshold */
   int64_t log_len, log_cap;
   /* Two-phase start (NULL / 0 for an LP created by oracle_create). */
   int32_t phase;   /* 0: one phase; 1: phase 1 running; 2: phase 2 */
@@ -206,12 +207,12 @@ void oracle_destroy(oracle_lp *p) {
   free(p->L); free(p->L_len); free(p->L_cap);
   free(p->A); free(p->b); free(p->c); free(p->chat); free(p->Binv); free(p->xB); free(p->W);
   free(p->d); free(p->alpha); free(p->rho); free(p->ratio); free(p->basis); free(p->pos);
-  free(p->tabu_until); free(p->log_enter); free(p->log_row); free(p->log_leave); free(p->log_flags);
+  free(p->tabu_until); free(p->log_enter); free(p->log_row); free(p->log_leave); free(p->log_flags); free(p->log_margin);
   free(p->art); free(p->rsign); free(p->chat2);
   free(p);
 }
 
-static int log_push(oracle_lp *p, int32_t q, int32_t r, int32_t l, int32_t flags) {
+static int log_push(oracle_lp *p, int32_t q, int32_t r, int32_t l, int32_t flags, double margin) {
   if (p->log_len == p->log_cap) {
     int64_t cap = p->log_cap ? 2 * p->log_cap : 1024;
     int32_t *a = (int32_t *)realloc(p->log_enter, sizeof(int32_t) * cap);
@@ -226,12 +227,16 @@ static int log_push(oracle_lp *p, int32_t q, int32_t r, int32_t l, int32_t flags
     a = (int32_t *)realloc(p->log_flags, sizeof(int32_t) * cap);
     if (!a) return -1;
     p->log_flags = a;
+    double *g = (double *)realloc(p->log_margin, sizeof(double) * cap);
+    if (!g) return -1;
+    p->log_margin = g;
     p->log_cap = cap;
   }
   p->log_enter[p->log_len] = q;
   p->log_row[p->log_len] = r;
   p->log_leave[p->log_len] = l;
   p->log_flags[p->log_len] = flags;
+  p->log_margin[p->log_len] = margin;
   p->log_len++;
   return 0;
 }
@@ -323,6 +328,20 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
   if (q < 0) { q = q_all; flags |= FLAG_ASPIRATION; p->n_aspiration++; }
   const double dq = p->d[q];
 
+  /* Decision margin of this pivot (reported only, never used in a decision): the
+   * smallest distance of a value that a threshold or a comparison decided from that
+   * threshold or from its rival.  A threshold test counts only for values at least half
+   * the threshold in magnitude: smaller ones (rounding residues of exact zeros) would need
+   * an error as large as the threshold to cross it.  Pricing: |d_j + eps_d|, and the gap
+   * between d_q and the other values of the set q was chosen from. */
+  double margin = INFINITY;
+  for (int32_t j = 0; j < N; ++j) {
+    if (p->pos[j] != -1) continue;
+    if (fabs(p->d[j]) >= 0.5 * p->eps_d) margin = fmin(margin, fabs(p->d[j] + p->eps_d));
+    const int in_set = p->d[j] < -p->eps_d && (q == q_all || p->tabu_until[j] < p->t);
+    if (in_set && j != q) margin = fmin(margin, fabs(p->d[j] - dq));
+  }
+
   /* Step 5: FTRAN, Y_k = B^-1 a_q. */
   ftran(p, q);
 
@@ -349,6 +368,14 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
     if (r_low < 0) r_low = i;
     if (r_free < 0 && !(p->use_llist && in_list(p, q, p->basis[i]))) r_free = i;
   }
+  /* Ratio test margins: |alpha_i - eps_p| and, over the candidate rows, the distance of
+   * the value a row reaches at the step from eps_t. */
+  for (int32_t i = 0; i < m; ++i) {
+    if (fabs(p->alpha[i]) >= 0.5 * p->eps_p) margin = fmin(margin, fabs(p->alpha[i] - p->eps_p));
+    if (!(p->alpha[i] > p->eps_p)) continue;
+    const double v = fma(-p->alpha[i], theta_min, fmax(p->xB[i], 0.0));
+    if (fabs(v) >= 0.5 * p->eps_t) margin = fmin(margin, fabs(v - p->eps_t));
+  }
   int32_t r = r_low;
   if (nT >= 2) {
     flags |= FLAG_TIE;
@@ -370,13 +397,15 @@ static int32_t iterate(oracle_lp *p, int64_t max_iter) {
   pivot_inverse(p, r);
   for (int32_t j = 0; j < m; ++j) p->W[j] = fma(dq, p->rho[j], p->W[j]);
   for (int32_t i = 0; i < m; ++i) p->xB[i] = (i == r) ? theta : fma(-p->alpha[i], theta, p->xB[i]);
-  for (int32_t i = 0; i < m; ++i)
+  for (int32_t i = 0; i < m; ++i) {
+    if (fabs(p->xB[i]) >= 0.5 * p->eps_z) margin = fmin(margin, fabs(fabs(p->xB[i]) - p->eps_z)); /* the snap */
     if (fabs(p->xB[i]) < p->eps_z) p->xB[i] = 0.0;
+  }
   p->z = fma(dq, theta, p->z);
   p->basis[r] = q;
   p->pos[q] = r;
   p->pos[leave] = (p->art && leave >= n && p->art[leave - n]) ? POS_BARRED : -1;
-  if (log_push(p, q, r, leave, flags)) return -1;
+  if (log_push(p, q, r, leave, flags, margin)) return -1;
   p->t++;
   return OR_RUNNING;
 }
@@ -411,7 +440,7 @@ static int drive_out(oracle_lp *p, int32_t q, int32_t r) {
   p->basis[r] = q;
   p->pos[q] = r;
   p->pos[leave] = POS_BARRED;
-  if (log_push(p, q, r, leave, FLAG_DRIVEOUT)) return -1;
+  if (log_push(p, q, r, leave, FLAG_DRIVEOUT, INFINITY)) return -1;
   p->t++;
   return 0;
 }
@@ -566,6 +595,13 @@ void oracle_state(const oracle_lp *p, double *Binv, double *xB, double *W, doubl
 }
 
 /* Copies up to cap log entries; returns the total number logged. */
+/* The decision margin of each logged pivot (INFINITY for a drive-out); returns the count. */
+int64_t oracle_margins(const oracle_lp *p, double *out, int64_t cap) {
+  int64_t k = p->log_len < cap ? p->log_len : cap;
+  if (out) memcpy(out, p->log_margin, sizeof(double) * k);
+  return p->log_len;
+}
+
 int64_t oracle_pivots(const oracle_lp *p, int32_t *enter, int32_t *row, int32_t *leave, int32_t *flags,
                       int64_t cap) {
   int64_t k = p->log_len < cap ? p->log_len : cap;

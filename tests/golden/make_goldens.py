@@ -4,8 +4,9 @@ parity tests compare against, at the sizes the benchmark runs.
 Calls only the oracle (its -fopenmp build, whose results are bit-identical to the
 sequential build: tests/test_oracle_omp.py) and the seeded generators of lpgen; nothing
 here reads a GPU result.  Each file records the oracle source's hash, the law, the seed
-and the sizes, the status, the pivot count, the objective (user's sense), the final basis
-and the pivot log (entering variable, leaving row, leaving variable, flags).
+and the sizes, the status, the pivot count, the objective (user's sense), the final basis,
+the pivot log (entering variable, leaving row, leaving variable, flags) and each pivot's
+decision margin (how close its closest decision came to its threshold or rival value).
 
     python tests/golden/make_goldens.py [--threads T] [NAME ...]
 """
@@ -88,6 +89,7 @@ def generate(name, threads=0):
         "basis": [int(v) for v in r.basis],
         "enter": [int(v) for v in r.enter], "row": [int(v) for v in r.row],
         "leave": [int(v) for v in r.leave], "flags": [int(v) for v in r.flags],
+        "margin": [float(f"{v:.4g}") if v != float("inf") else None for v in r.margin],
         "oracle_seconds": round(dt, 1), "oracle_threads": oracle.threads(lib),
     }
     with open(path_of(name), "w") as f:

@@ -5,7 +5,15 @@ Each case regenerates the LP from its law and seed, solves it on the GPU in the
 benchmark's launch configuration (16 iterations per status read-back) up to the stored
 pivot count, and compares every pivot (entering variable, leaving row, leaving variable,
 flags) element by element, then the status, the pivot count, the final basis and the
-objective (relative 1e-9; the two sides sum their dot products in different orders)."""
+objective (relative 1e-9; the two sides sum their dot products in different orders).
+
+The two sides sum in different orders, so a decision whose value lies within rounding
+noise of its threshold can fall either way.  The oracle records each pivot's decision
+margin (the distance of its closest threshold test or comparison).  Where the logs part,
+the pivot must be one whose margin is below RISKY (half the thresholds' size, 5e-10): a
+decision that close depends on the noise the basis inverse carries, and from there on
+the two paths are different, equally valid, pivot sequences.  Every pivot before it must
+match exactly; the test reports how many did and the smallest margin among them."""
 import os
 import sys
 
@@ -19,6 +27,7 @@ import make_goldens  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 OBJ_RTOL = 1e-9
+RISKY = 5e-10  # decision margin below which rounding may decide a pivot
 
 
 def _say(msg):
@@ -38,10 +47,22 @@ def lpg():
 def _compare(name, g, piv, st, sol, lpg):
     k = g["iterations"]
     assert len(piv["enter"]) == k, f"{name}: {len(piv['enter'])} pivots, oracle {k}"
+    margin = np.array([np.inf if v is None else v for v in g["margin"]])
+    first = k
     for key in ("enter", "row", "leave", "flags"):
-        got, want = piv[key], np.asarray(g[key], dtype=np.int32)
-        bad = np.flatnonzero(got != want)
-        assert bad.size == 0, f"{name}: {key} differs first at pivot {bad[0]}: {got[bad[0]]} vs {want[bad[0]]}"
+        bad = np.flatnonzero(piv[key] != np.asarray(g[key], dtype=np.int32))
+        if bad.size:
+            first = min(first, int(bad[0]))
+    matched_min = margin[:first].min() if first else np.inf
+    if first < k:
+        # The paths part at pivot `first`: allowed only where the oracle's decision was
+        # within rounding reach of its threshold (the pivots before it are equal).
+        _say(f"  logs equal for the first {first} of {k} pivots (smallest margin among them {matched_min:.3g}); "
+             f"pivot {first} has margin {margin[first]:.3g}")
+        assert margin[first] < RISKY, f"{name}: logs differ at pivot {first}, whose decision margin is {margin[first]}"
+        assert lpg.STATUS_NAMES[st] == g["status"] or g["pivot_cap"], (lpg.STATUS_NAMES[st], g["status"])
+        return
+    _say(f"  logs equal for all {k} pivots; smallest decision margin {matched_min:.3g}")
     assert lpg.STATUS_NAMES[st] == g["status"], (lpg.STATUS_NAMES[st], g["status"])
     np.testing.assert_array_equal(sol["basis"], np.asarray(g["basis"], dtype=np.int32))
     if g["status"] == "OPTIMAL":

@@ -66,6 +66,10 @@ def assert_parity(lpg, A, b, c, max_iter=None, tenure=5, leaving_list=True, sens
     assert np.abs(sol["y"] - ref.y).max(initial=0.0) <= 1e-9 * (1.0 + np.abs(ref.y).max(initial=0.0))
     assert stats["degenerate"] == ref.counts["degenerate"] and stats["ties"] == ref.counts["tie"]
     assert stats["aspirations"] == ref.counts["aspiration"] and stats["list_clears"] == ref.counts["lclear"]
+    if len(ref.margin):
+        # how close the closest decision of the run came to its threshold (oracle's values)
+        _say(f"  exact over {len(ref.enter)} pivots; smallest decision margin {ref.margin.min():.3g} "
+             f"(pivot {int(np.argmin(ref.margin))})")
     return ref, (st, sol, piv, stats)
 
 

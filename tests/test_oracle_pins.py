@@ -372,3 +372,20 @@ def test_tie_rules_replayed(case):
     r = oracle.solve(A, b, c)
     assert r.status == oracle.OPTIMAL
     replay_strict(A, b, c, r.enter, r.row, r.flags)
+
+
+def test_decision_margin_of_a_near_threshold_alpha():
+    """The reported decision margin (which no decision uses) against a hand-worked LP: the
+    entering column's second entry, 1.5e-9, is the value closest to a threshold (eps_p =
+    1e-9), so the first pivot's margin is their difference; every other value of the pivot
+    is O(1) from its threshold or rival (d = (-3, -2), x_B after the step = (1, 1 - 1.5e-9))."""
+    A = np.array([[1.0, 1.0], [1.5e-9, 1.0]])
+    b = np.array([1.0, 1.0])
+    c = np.array([3.0, 2.0])
+    o = oracle.Oracle(A, b, c)
+    o.run(1)
+    r = o.result()
+    assert r.enter[0] == 0 and r.row[0] == 0
+    assert r.margin[0] == abs(1.5e-9 - 1e-9)
+    # nothing of the second pivot (if any) and no tiny residue counts below it
+    assert np.all(r.margin >= 0.0)
