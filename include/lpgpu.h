@@ -167,6 +167,9 @@ typedef struct lp_stats {
                                this build runs) */
   int64_t panel_rows;       /* 0 (Case 2 row panels are switched off) */
   int64_t panels;           /* 0 (Case 2 row panels are switched off) */
+  int64_t price_fin_launches; /* FP64 form: pricing passes that also finished the previous iteration's
+                                 ratio test (k_price_fin; counted in price_launches too) */
+  double price_fin_ms;      /* their share of price_ms */
 } lp_stats;
 
 typedef struct lp_problem lp_problem;

@@ -78,6 +78,8 @@ class lp_stats(C.Structure):
         ("memory_case", C.c_int64),
         ("panel_rows", C.c_int64),
         ("panels", C.c_int64),
+        ("price_fin_launches", C.c_int64),
+        ("price_fin_ms", C.c_double),
     ]
 
 

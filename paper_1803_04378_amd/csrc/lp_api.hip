@@ -317,36 +317,50 @@ int collect_reinv_time(lp_problem* p) {
   return LP_OK;
 }
 
-// Kernels of one iteration, in launch order: k_price -> k_update -> k_finish; in the mixed
-// form k_price32 -> k_shortlist -> k_update -> k_finish (k_price32 runs the FP64 pass in
-// the iteration after a fallback verdict).
+// The kernels of K iterations, in launch order.  FP64 form: k_price -> k_update, then
+// (k_price_fin -> k_update) for each further iteration, and k_finish last: k_price_fin
+// finishes the previous iteration's ratio test and prices the next one in one launch, so
+// K iterations take 2K + 1 launches.  Mixed form: K times k_price32 -> k_shortlist ->
+// k_update -> k_finish (k_price32 runs the FP64 pass in the iteration after a fallback
+// verdict).  kind: what each launch is counted as in the profile (kinds below).
+enum { kKindPrice = 0, kKindShortlist = 1, kKindUpdate = 2, kKindFinish = 3, kKindPriceFin = 4 };
 struct IterKernel {
   const void* fn;
   int grid, block;
   size_t lds;
+  int kind;
 };
 
-int iteration_kernels(const lp_problem* p, IterKernel* out) {
-  int c = 0;
+std::vector<IterKernel> iteration_kernels(const lp_problem* p, int K) {
+  std::vector<IterKernel> out;
+  const IterKernel upd{update_kernel_for_block(p->d.upd_block), p->update_grid, std::abs(p->d.upd_block),
+                       update_lds_for_block(p->d.upd_block, p->ld), kKindUpdate};
+  const IterKernel fin{finish_kernel(), 1, kFinishBlock, 0, kKindFinish};
   if (p->d.mixed) {
-    out[c++] = {price32_kernel(), p->price32_grid, kPrice32Block, price32_lds_bytes(p->ld)};
-    out[c++] = {shortlist_kernel(), p->d.sl_k, shortlist_block(), 0};
-  } else {
-    out[c++] = {price_kernel(), p->price_grid, kPriceBlock, price_lds_bytes(p->ld)};
+    for (int k = 0; k < K; ++k) {
+      out.push_back({price32_kernel(), p->price32_grid, kPrice32Block, price32_lds_bytes(p->ld), kKindPrice});
+      out.push_back({shortlist_kernel(), p->d.sl_k, shortlist_block(), 0, kKindShortlist});
+      out.push_back(upd);
+      out.push_back(fin);
+    }
+    return out;
   }
-  out[c++] = {update_kernel_for_block(p->d.upd_block), p->update_grid, std::abs(p->d.upd_block),
-              update_lds_for_block(p->d.upd_block, p->ld)};
-  out[c++] = {finish_kernel(), 1, kFinishBlock, 0};
-  return c;
+  for (int k = 0; k < K; ++k) {
+    out.push_back({k == 0 ? price_kernel() : price_fin_kernel(), p->price_grid, kPriceBlock, price_lds_bytes(p->ld),
+                   k == 0 ? kKindPrice : kKindPriceFin});
+    out.push_back(upd);
+  }
+  out.push_back(fin);
+  return out;
 }
 
 // An iteration graph: K iterations as a linear chain of kernel nodes.  With events (the
 // main graph under profile = 1) an event-record node sits before every kernel and at the end.
 int build_chain(lp_problem* p, int K, bool prof, hipGraph_t* graph, hipGraphExec_t* gexec) {
-  IterKernel ks[5];
-  const int E = iteration_kernels(p, ks);
+  const std::vector<IterKernel> ks = iteration_kernels(p, K);
+  const int E = (int)ks.size();
   if (prof) {
-    p->events.resize(E * K + 1, nullptr);
+    p->events.resize(E + 1, nullptr);
     for (auto& e : p->events) HIP_TRY(hipEventCreate(&e), "creating profiling events");
   }
   HIP_TRY(hipGraphCreate(graph, 0), "creating the iteration graph");
@@ -371,12 +385,11 @@ int build_chain(lp_problem* p, int K, bool prof, hipGraph_t* graph, hipGraphExec
     if (e == hipSuccess) prev = node;
     return e;
   };
-  for (int k = 0; k < K; ++k)
-    for (int i = 0; i < E; ++i) {
-      if (prof) HIP_TRY(add_event(p->events[E * k + i]), "adding a profiling event");
-      HIP_TRY(add_kernel(ks[i]), "adding a kernel node");
-    }
-  if (prof) HIP_TRY(add_event(p->events[E * K]), "adding a profiling event");
+  for (int i = 0; i < E; ++i) {
+    if (prof) HIP_TRY(add_event(p->events[i]), "adding a profiling event");
+    HIP_TRY(add_kernel(ks[i]), "adding a kernel node");
+  }
+  if (prof) HIP_TRY(add_event(p->events[E]), "adding a profiling event");
   HIP_TRY(hipGraphInstantiate(gexec, *graph, nullptr, nullptr, 0), "instantiating the iteration graph");
   return LP_OK;
 }
@@ -392,21 +405,19 @@ int build_graph(lp_problem* p) {
 // kernel with a start and a stop event bound to its own dispatch, so that the elapsed
 // time between them is the kernel's execution alone (no launch gap).
 int launch_direct(lp_problem* p, int K) {
-  IterKernel ks[5];
-  const int E = iteration_kernels(p, ks);
-  if ((int)p->events.size() != 2 * E * p->opt.iters_per_sync) {
+  const std::vector<IterKernel> ks = iteration_kernels(p, K);
+  const int E = (int)ks.size();
+  if ((int)p->events.size() < 2 * E) {
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
-    p->events.assign(2 * E * p->opt.iters_per_sync, nullptr);
+    p->events.assign(2 * E, nullptr);
     for (auto& e : p->events) HIP_TRY(hipEventCreate(&e), "creating profiling events");
   }
-  for (int k = 0; k < K; ++k)
-    for (int i = 0; i < E; ++i) {
-      void* args[] = {&p->d};
-      const int ev = 2 * (E * k + i);
-      HIP_TRY(hipExtLaunchKernel(ks[i].fn, dim3(ks[i].grid), dim3(ks[i].block), args, ks[i].lds, p->stream,
-                                 p->events[ev], p->events[ev + 1], 0),
-              "launching an iteration kernel");
-    }
+  for (int i = 0; i < E; ++i) {
+    void* args[] = {&p->d};
+    HIP_TRY(hipExtLaunchKernel(ks[i].fn, dim3(ks[i].grid), dim3(ks[i].block), args, ks[i].lds, p->stream,
+                               p->events[2 * i], p->events[2 * i + 1], 0),
+            "launching an iteration kernel");
+  }
   return LP_OK;
 }
 
@@ -840,7 +851,6 @@ int run_until(lp_problem* p, int64_t iter_cap, bool decide, int32_t* status_out)
   const bool prof = p->opt.profile != 0;
   const int K = p->opt.iters_per_sync;
   const bool mixed = p->d.mixed != 0;
-  const int E = mixed ? 4 : 3;
   for (;;) {
     const int64_t left = iter_cap - p->h_ctrl->t;
     int k = K;
@@ -873,28 +883,31 @@ int run_until(lp_problem* p, int64_t iter_cap, bool decide, int32_t* status_out)
     if ((rc = collect_reinv_time(p)) != LP_OK) return rc;
     if (prof && k == K && p->h_ctrl->status == LP_RUNNING && t_before > 0 && p->h_ctrl->t == t_before + K) {
       // Steady state: every kernel of the replay did a full pass (K pivots, so in the
-      // mixed form no fallback iteration and no FP64 pass).
-      for (int it = 0; it < K; ++it) {
-        float ms[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int i = 0; i < E; ++i) {
-          // profile = 1: between the event nodes around kernel i (its launch gap
-          // included); profile = 2: the kernel's own start and stop.
-          const int a = direct ? 2 * (E * it + i) : E * it + i;
-          HIP_TRY(hipEventElapsedTime(&ms[i], p->events[a], p->events[a + 1]), "reading profile events");
+      // mixed form no fallback iteration and no FP64 pass).  profile = 1: the time between
+      // the event nodes around a kernel (its launch gap included); profile = 2: the
+      // kernel's own start and stop.
+      const std::vector<IterKernel> ks = iteration_kernels(p, K);
+      for (size_t i = 0; i < ks.size(); ++i) {
+        float ms = 0.f;
+        const int a = direct ? (int)(2 * i) : (int)i;
+        HIP_TRY(hipEventElapsedTime(&ms, p->events[a], p->events[a + 1]), "reading profile events");
+        switch (ks[i].kind) {
+          case kKindPrice:
+            if (mixed) p->stats.price32_ms += ms;
+            else p->stats.price_ms += ms;
+            break;
+          case kKindPriceFin: p->stats.price_ms += ms; p->stats.price_fin_ms += ms; break;
+          case kKindShortlist: p->stats.shortlist_ms += ms; break;
+          case kKindUpdate: p->stats.update_ms += ms; break;
+          default: p->stats.finish_ms += ms; break;
         }
-        const int o = mixed ? 2 : 1;
-        if (mixed) {
-          p->stats.price32_ms += ms[0];
-          p->stats.shortlist_ms += ms[1];
-        } else {
-          p->stats.price_ms += ms[0];
-        }
-        p->stats.update_ms += ms[o];
-        p->stats.finish_ms += ms[o + 1];
       }
-      if (!mixed) p->stats.price_launches += K;
+      if (!mixed) {
+        p->stats.price_launches += K;
+        p->stats.price_fin_launches += K - 1;
+      }
       p->stats.update_launches += K;
-      p->stats.finish_launches += K;
+      p->stats.finish_launches += mixed ? K : 1;
       p->stats.price_bytes += 8.0 * p->m * (double)(p->h_ctrl->price_cols - cols_before);
       // algorithmic bytes of the update passes, counted on the device
       p->stats.update_bytes += (double)(p->h_ctrl->update_bytes - ubytes_before);

@@ -94,6 +94,15 @@ struct Ctrl {
   int32_t nD;                // columns in the list D (below)
   int32_t pad5;
   int64_t n_fallback;        // mixed form: iterations that ended with kVerdictFallback (no pivot)
+  // Taken by k_update for k_price_fin (the ratio-test finish fused with the next pricing
+  // pass), whose workgroup 0 rewrites the live fields while the others still read: t, z,
+  // the length of D, the structural count, the tabu list's length and the alpha buffer.
+  int64_t snap_t;
+  double snap_z;
+  int32_t snap_nD, snap_nsb, snap_nL, snap_cur;
+  // Left by k_price_fin for the next k_update: basis[r] = q_pend (bpend != 0), and the
+  // tabu list's generation bump gen[gen_q] = gen_val (gen_q >= 0).
+  int32_t q_pend, bpend, gen_q, gen_val;
 };
 
 struct DevLP {
@@ -223,6 +232,8 @@ hipError_t launch_solution(const DevLP& lp, const double* c, double ysign, doubl
                            hipStream_t s);
 // Kernel entry points for explicit graph construction.
 const void* price_kernel();
+// k_finish fused with the next k_price (iterations after the first of a launch sequence).
+const void* price_fin_kernel();
 const void* update_kernel(int ld);
 const void* update_kernel_for_block(int block);
 int update_block(int ld);

@@ -76,17 +76,39 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
     ctl->r = -1;
     ctl->ray = -1;
     ctl->verdict = -1;
+    ctl->gen_q = -1;
   }
 }
 
 // ---------------------------------------------------------------------------------------
+// Inputs and result of the ratio-test finish (finish_step, below).
+struct FinishIn {
+  int verdict, q, cur, flags0, nD0, nsb0, nL;
+  int64_t t;
+  double dq, z0;
+};
+struct FinishOut {
+  int pivot;  // 1: a pivot on row r was committed; 0: the solve stopped or (mixed) no pivot
+  int r, leave;
+  double ar;
+};
+
+template <int B, bool FUSED>
+__device__ FinishOut finish_step(const DevLP& lp, const FinishIn& in, double pth, double pt1, double pt2, double pal,
+                                 int plow, int pbv);
+
 // Steps 3-4, preceded by Step 8 on the top row of the tableau for the pending pivot:
 // every workgroup forms W_new = W + d_q rho, rho = B^-1[r,:] / alpha_r, while staging it
 // into LDS (B^-1 still holds the pre-pivot rows, the row update runs in k_update);
 // workgroup 0 also stores rho and W_new for the rest of the iteration.  (The mixed form
 // does not launch this kernel: k_price32 screens, and runs the FP64 pass when needed.)
-__global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
-  extern __shared__ double2 s_w2[];
+//
+// FUSED (k_price_fin): the pending pivot is the one this kernel finishes first from
+// k_update's partials (finish_step, in every workgroup).  Its bookkeeping may or may not
+// be visible to a workgroup yet, so the entering variable counts as basic and the leaving
+// one as nonbasic (and tabu) whatever pos and tabu_until read.
+template <bool FUSED>
+__device__ __forceinline__ void price_pass(const DevLP& lp, double2* s_w2) {
   __shared__ double red_d[2 * (kPriceBlock / 64)];
   __shared__ int red_j[2 * (kPriceBlock / 64)];
   const int m = lp.m, n = lp.n, ld2 = lp.ld / 2;
@@ -96,16 +118,47 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
   const int gw = blockIdx.x * waves + wave;
   const int nw = gridDim.x * waves;
 
-  // Requested together, before anything waits on memory: the control block, the state of
-  // this wave's columns (lane c holds column gw + c*nw) and, in the FP64 form, the first
-  // batch of its first column of A' (read even when the solve has stopped; then unused).
+  // Requested together, before anything waits on memory: the control block (in the fused
+  // kernel also the first update partial of every thread), the state of this wave's
+  // columns (lane c holds column gw + c*nw) and the first batch of its first column of A'
+  // (read even when the solve has stopped; then unused).
   const Ctrl* ctl = lp.ctrl;
   const int status = ctl->status;
-  const int64_t t = ctl->t;
-  const int r = ctl->r;
   const int wc = ctl->wcur;
-  const double ar = ctl->ar;
-  const double dq = ctl->pdq;
+  int64_t t;
+  int r;
+  double ar, dq;
+  FinishIn fin;
+  double pth = 0.0, pt1 = 0.0, pt2 = 0.0, pal = 0.0;
+  int plow = 0, pbv = 0;
+  if (FUSED) {
+    fin.verdict = ctl->verdict;
+    fin.q = ctl->q;
+    fin.cur = ctl->snap_cur;
+    fin.t = ctl->snap_t;
+    fin.flags0 = ctl->flags;
+    fin.dq = ctl->dq;
+    fin.z0 = ctl->snap_z;
+    fin.nD0 = ctl->snap_nD;
+    fin.nsb0 = ctl->snap_nsb;
+    fin.nL = ctl->snap_nL;
+    const int pk = min((int)threadIdx.x, lp.update_grid - 1);
+    pth = lp.part_th[pk];
+    pt1 = lp.part_t1[pk];
+    pt2 = lp.part_t2[pk];
+    pal = lp.part_al[pk];
+    plow = lp.part_low[pk];
+    pbv = lp.part_bv[pk];
+    t = fin.t + 1;
+    dq = fin.dq;
+    r = -1;
+    ar = 0.0;
+  } else {
+    t = ctl->t;
+    r = ctl->r;
+    ar = ctl->ar;
+    dq = ctl->pdq;
+  }
   const int jl = gw + lane * nw;
   int c_pos = 0, c_tabu = 0;
   double c_chat = 0.0;
@@ -120,7 +173,22 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
     if (kStreamA) load_batch_nt(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
     else load_batch(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
   }
+  if (FUSED) asm volatile("" ::: "memory");  // compiler-only: all of the above is requested first
   if (status != kStatusRunning) return;
+
+  // The pivot just finished (fused): its entering and leaving variables, and the leaving
+  // one's view of pos and tabu_until after the pivot.
+  int pq = -1, pl = -1, pl_pos = 0, pl_tabu = 0;
+  if (FUSED) {
+    const FinishOut fo = finish_step<kPriceBlock, true>(lp, fin, pth, pt1, pt2, pal, plow, pbv);
+    if (!fo.pivot) return;
+    r = fo.r;
+    ar = fo.ar;
+    pq = fin.q;
+    pl = fo.leave;
+    pl_pos = (lp.art && pl >= n && lp.art[pl - n]) ? kPosBarred : -1;
+    pl_tabu = lp.tenure > 0 ? (int)(fin.t + lp.tenure) : lp.tabu_until[pl];
+  }
 
   if (r >= 0) {
     const double2* Wold = reinterpret_cast<const double2*>(wc ? lp.W1 : lp.W0);
@@ -170,6 +238,13 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
       tabu = lp.tabu_until[j];
       ch = lp.chat[j];
     }
+    if (FUSED) {
+      if (j == pq) pos = r;
+      if (j == pl) {
+        pos = pl_pos;
+        tabu = pl_tabu;
+      }
+    }
     const bool first = c == 0;
     if (pos >= 0) continue;
     const double s = wave_dot<kStreamA>(reinterpret_cast<const double2*>(lp.A + (size_t)j * lp.ld), s_w2, ld2,
@@ -188,14 +263,22 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
   }
   for (int i = blockIdx.x * kPriceBlock + threadIdx.x; i < m; i += gridDim.x * kPriceBlock) {
     const int vv = n + i;
-    if (lp.pos[vv] >= 0) continue;
+    int pos = lp.pos[vv], tabu = lp.tabu_until[vv];
+    if (FUSED) {
+      if (vv == pq) pos = r;
+      if (vv == pl) {
+        pos = pl_pos;
+        tabu = pl_tabu;
+      }
+    }
+    if (pos >= 0) continue;
     const double d = lp.chat[vv] - s_w[i];  // a_{n+i} = e_i
     if (d < neg_eps) {
       if (lex_less(d, vv, da, ja)) {
         da = d;
         ja = vv;
       }
-      if (lp.tabu_until[vv] < t && lex_less(d, vv, df, jf)) {
+      if (tabu < t && lex_less(d, vv, df, jf)) {
         df = d;
         jf = vv;
       }
@@ -225,6 +308,21 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
       lp.part_j[2 * blockIdx.x + 1] = jf;
     }
   }
+}
+
+__global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
+  extern __shared__ double2 s_w2[];
+  price_pass<false>(lp, s_w2);
+}
+
+// The ratio-test finish of the pending iteration (k_finish's work, in every workgroup)
+// fused with the next pricing pass: one launch instead of two, and the finish's loads
+// overlap the first batch of A'.
+// Held to k_price's register budget (six waves per SIMD), so that the grid sized for
+// k_price stays resident in one round.
+__global__ __launch_bounds__(kPriceBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_price_fin(DevLP lp) {
+  extern __shared__ double2 s_w2[];
+  price_pass<true>(lp, s_w2);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -318,6 +416,8 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
   const int64_t max_iter = ctl->max_iter;
   const double theta = ctl->theta;
   const int fb = ctl->fb;
+  // basis[r] of a pivot k_price_fin finished is written below; until then it reads as q_pend
+  const int bpend = ctl->bpend, q_pend = ctl->q_pend;
   // Indices are clamped into range rather than guarded, so that no load waits behind a
   // branch; the values of clamped lanes are discarded below.
   const int pk = min(tid, lp.price_grid - 1);
@@ -335,6 +435,7 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
   const int g0 = min(i0, hi - 1);
   double x0 = lp.xB[g0], al00 = lp.alpha0[g0], al10 = lp.alpha1[g0];
   int bv0 = lp.basis[g0];
+  if (bpend && g0 == r) bv0 = q_pend;
   double2 v[kUpdBatch];
   const bool pre_now = !can_sparse && i0 < hi;  // dense for certain: first batch of the row now
   if (pre_now) load_batch(reinterpret_cast<const double2*>(lp.Binv + (size_t)gw * ld), lane, ld2, v);
@@ -435,6 +536,17 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
   if (blockIdx.x == 0 && tid == 0 && first_panel) {
     // Only fields no k_update workgroup reads: the status itself changes in k_finish.
     Ctrl* cw = lp.ctrl;
+    if (bpend) lp.basis[r] = q_pend;
+    if (cw->gen_q >= 0) {
+      lp.gen[cw->gen_q] = cw->gen_val;
+      cw->gen_q = -1;
+    }
+    cw->snap_t = t;
+    cw->snap_z = cw->z;
+    cw->snap_nD = nD;
+    cw->snap_nsb = cw->nsb;
+    cw->snap_nL = cw->nL;
+    cw->snap_cur = cur;
     if (lp.mixed && !fb) cw->price32_launches += 1;
     if (use_parts) {
       cw->price_cols += n - cw->nsb;
@@ -515,7 +627,7 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
       } else {
         x = lp.xB[i];
         alp = al_p[i];
-        bv = lp.basis[i];
+        bv = (bpend && i == r) ? q_pend : lp.basis[i];
         in = bv >= n ? lp.inD[bv - n] : 1;
 #pragma unroll
         for (int u = 0; u < kGather; ++u) {
@@ -596,7 +708,7 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
       double x = c == 0 ? x0 : lp.xB[i];
       int bv = bv0, in = in0;
       if (c > 0 && q >= 0) {
-        bv = lp.basis[i];
+        bv = (bpend && i == r) ? q_pend : lp.basis[i];
         in = bv >= n ? lp.inD[bv - n] : 1;
       }
       if (r < 0) {
@@ -1000,55 +1112,56 @@ __global__ __launch_bounds__(B) void k_update_wide(DevLP lp) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Step 6 finish and the scalar part of Step 8 (one workgroup).  Every k_update workgroup
-// left its minimum ratio (with the lowest row attaining it, that row's alpha and basic
-// variable) and the two smallest tie thresholds of its rows; x_B and alpha of this
-// iteration are in memory.
-__global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
-  constexpr int B = kFinishBlock;
+// Step 6 finish and the scalar part of Step 8.  Every k_update workgroup left its minimum
+// ratio (with the lowest row attaining it, that row's alpha and basic variable) and the two
+// smallest tie thresholds of its rows; x_B and alpha of this iteration are in memory.
+//
+// finish_step is run by the one workgroup of k_finish, and by every workgroup of
+// k_price_fin, the kernel that fuses it with the next pricing pass.  Each workgroup takes
+// the same decision from the same inputs; one thread of workgroup 0 commits it.  In the
+// fused kernel the other workgroups still read while that thread writes, so there the
+// commit leaves alone what they read: the inputs come from the snapshot k_update took
+// (FinishIn), basis[r] and the tabu list's generation bump are left for the next k_update
+// to apply, and the pricing part patches its own view of pos and tabu_until.
+template <int B, bool FUSED>
+__device__ FinishOut finish_step(const DevLP& lp, const FinishIn& in, double pth, double pt1, double pt2, double pal,
+                                 int plow, int pbv) {
   __shared__ double red_d[B / 64 + 8];
   __shared__ int red_j[2 * (B / 64) + 8];
   __shared__ double s_pick_al;
   __shared__ int s_pick[3];
   Ctrl* ctl = lp.ctrl;
   const int m = lp.m, tid = threadIdx.x, nparts = lp.update_grid;
-  // One round of requests: the control block and the first partial of every thread.
-  const int verdict = ctl->verdict;
-  const int q = ctl->q;
-  const int cur = ctl->cur;
-  const int64_t t = ctl->t;
-  const int flags0 = ctl->flags;
-  const double dq = ctl->dq;
-  const double z0 = ctl->z;
-  const int nD0 = ctl->nD;
-  const int nsb0 = ctl->nsb;
-  const int pk = min(tid, nparts - 1);  // clamped, not guarded: no load waits behind a branch
-  double pth = lp.part_th[pk], pt1 = lp.part_t1[pk], pt2 = lp.part_t2[pk], pal = lp.part_al[pk];
-  int plow = lp.part_low[pk], pbv = lp.part_bv[pk];
-  asm volatile("" ::: "memory");  // compiler-only: all of the above is requested first
+  const bool writer = tid == 0 && (!FUSED || blockIdx.x == 0);
+  const int verdict = in.verdict, q = in.q, cur = in.cur, flags0 = in.flags0, nD0 = in.nD0, nsb0 = in.nsb0;
+  const int64_t t = in.t;
+  const double dq = in.dq, z0 = in.z0;
+  FinishOut out{0, -1, -1, 0.0};
   if (tid >= nparts) {
     pth = pt1 = pt2 = __builtin_inf();
     plow = INT_MAX;
   }
-  if (verdict < 0) return;  // k_update did not run
-  if (tid == 0) ctl->fb = verdict == kVerdictFallback ? 1 : 0;
+  if (verdict < 0) return out;  // k_update did not run
+  if (!FUSED && writer) ctl->fb = verdict == kVerdictFallback ? 1 : 0;
   if (verdict == kVerdictFallback) {  // no pivot; k_update applied the pending one
-    if (tid == 0) {
+    if (writer) {
       ctl->verdict = -1;
       ctl->r = -1;
       ctl->q = -1;
       ctl->n_fallback += 1;
     }
-    return;
+    return out;
   }
   if (verdict != kStatusRunning) {  // OPTIMAL or ITER_LIMIT; k_update applied the pending pivot
-    if (tid == 0) {
+    if (writer) {
       ctl->status = verdict;
-      ctl->verdict = -1;
       ctl->r = -1;
-      ctl->q = -1;
+      if (!FUSED) {
+        ctl->verdict = -1;
+        ctl->q = -1;
+      }
     }
-    return;
+    return out;
   }
 
   const double* al = cur ? lp.alpha0 : lp.alpha1;  // FTRAN result of this iteration
@@ -1067,18 +1180,20 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
   block_lexmin<B>(th, lowc, red_d, red_j);
   const bool nonfinite = th == -__builtin_inf() || (lowc != INT_MAX && !isfinite(th));
   if (nonfinite || lowc == INT_MAX) {
-    if (tid == 0) {
+    if (writer) {
       if (nonfinite) {
         ctl->status = kStatusNumerical;
       } else {  // Step 5: Y_k <= 0
         ctl->status = kStatusUnbounded;
         ctl->ray = q;
       }
-      ctl->verdict = -1;
-      ctl->q = -1;
       ctl->r = -1;
+      if (!FUSED) {
+        ctl->verdict = -1;
+        ctl->q = -1;
+      }
     }
-    return;
+    return out;
   }
   // A row is tied when it reaches zero (within eps_t) at the step th; exact test below.
   const double eps_p = lp.eps_p, eps_t = lp.eps_t;
@@ -1134,9 +1249,10 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
   if (cnt >= 2) {
     flags |= kFlagTie;
     if (lp.use_llist) {
+      // (every workgroup of the fused kernel stamps the same entries with the same value)
       const int stamp = (int)t + 1;
       const int g = lp.gen[q];
-      const int nL = ctl->nL;
+      const int nL = in.nL;
       for (int k = tid; k < nL; k += B)
         if (lp.Lq[k] == q && lp.Lgen[k] == g) lp.excl[lp.Ll[k]] = stamp;
       __syncthreads();
@@ -1154,8 +1270,15 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
       } else {
         r = fl;
       }
-      if (tid == 0) {
-        if (gnew != g) lp.gen[q] = gnew;
+      if (writer) {
+        if (gnew != g) {
+          if (FUSED) {
+            ctl->gen_q = q;  // applied by the next k_update (gen[q] is read above)
+            ctl->gen_val = gnew;
+          } else {
+            lp.gen[q] = gnew;
+          }
+        }
         if (nL < lp.Lcap) {
           lp.Lq[nL] = q;
           lp.Ll[nL] = lp.basis[r];
@@ -1165,21 +1288,21 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
       }
     }
   }
-  if (tid == 0) {
-    // Step 8 pivots on row r with the step th.
+  // Step 8 pivots on row r with the step th.
+  int leave, kept;  // kept: the leaving variable is structural or its slack is in D already
+  double ar;
+  if (fast) {
+    leave = s_pick[2] >> 1;
+    kept = s_pick[2] & 1;
+    ar = s_pick_al;
+  } else {
+    leave = lp.basis[r];
+    kept = leave < lp.n || lp.inD[leave - lp.n];
+    ar = al[r];
+  }
+  if (writer) {
     const double thr = th;
     if (thr == 0.0) flags |= kFlagDegenerate;
-    int leave, kept;  // kept: the leaving variable is structural or its slack is in D already
-    double ar;
-    if (fast) {
-      leave = s_pick[2] >> 1;
-      kept = s_pick[2] & 1;
-      ar = s_pick_al;
-    } else {
-      leave = lp.basis[r];
-      kept = leave < lp.n || lp.inD[leave - lp.n];
-      ar = al[r];
-    }
     if (lp.tenure > 0) lp.tabu_until[leave] = (int)(t + lp.tenure);
     if (!kept) {  // its column of B^-1 stops being a unit vector
       lp.inD[leave - lp.n] = 1;
@@ -1187,7 +1310,13 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
       ctl->nD = nD0 + 1;
     }
     ctl->z = fma(dq, thr, z0);
-    lp.basis[r] = q;
+    if (FUSED) {
+      ctl->q_pend = q;  // basis[r] = q, applied by the next k_update
+      ctl->bpend = 1;
+    } else {
+      lp.basis[r] = q;
+      ctl->bpend = 0;
+    }
     lp.pos[q] = r;
     lp.pos[leave] = (lp.art && leave >= lp.n && lp.art[leave - lp.n]) ? kPosBarred : -1;
     ctl->nsb = nsb0 + (q < lp.n ? 1 : 0) - (leave < lp.n ? 1 : 0);
@@ -1206,10 +1335,41 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
     ctl->pdq = dq;
     ctl->ar = ar;
     ctl->cur = cur ^ 1;
-    ctl->q = -1;
-    ctl->flags = 0;
-    ctl->verdict = -1;
+    if (!FUSED) {
+      ctl->q = -1;
+      ctl->flags = 0;
+      ctl->verdict = -1;
+    }
   }
+  out.pivot = 1;
+  out.r = r;
+  out.leave = leave;
+  out.ar = ar;
+  return out;
+}
+
+__global__ __launch_bounds__(kFinishBlock) void k_finish(DevLP lp) {
+  const Ctrl* ctl = lp.ctrl;
+  const int tid = threadIdx.x, nparts = lp.update_grid;
+  // One round of requests: the control block and the first partial of every thread.
+  FinishIn in;
+  const int status = ctl->status;
+  in.verdict = ctl->verdict;
+  in.q = ctl->q;
+  in.cur = ctl->cur;
+  in.t = ctl->t;
+  in.flags0 = ctl->flags;
+  in.dq = ctl->dq;
+  in.z0 = ctl->z;
+  in.nD0 = ctl->nD;
+  in.nsb0 = ctl->nsb;
+  in.nL = ctl->nL;
+  const int pk = min(tid, nparts - 1);  // clamped, not guarded: no load waits behind a branch
+  const double pth = lp.part_th[pk], pt1 = lp.part_t1[pk], pt2 = lp.part_t2[pk], pal = lp.part_al[pk];
+  const int plow = lp.part_low[pk], pbv = lp.part_bv[pk];
+  asm volatile("" ::: "memory");  // compiler-only: all of the above is requested first
+  if (status != kStatusRunning) return;
+  finish_step<kFinishBlock, false>(lp, in, pth, pt1, pt2, pal, plow, pbv);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1324,6 +1484,7 @@ __global__ void k_check_finite(const double* __restrict__ x, int64_t count, doub
 
 // ---------------------------------------------------------------------------------------
 const void* price_kernel() { return reinterpret_cast<const void*>(&k_price); }
+const void* price_fin_kernel() { return reinterpret_cast<const void*>(&k_price_fin); }
 // k_update's workgroup size for a row stride ld: kUpdateBlock threads, or twice that where
 // the staging in LDS admits only one such workgroup per CU and one of the larger ones
 // fits (it keeps twice the wavefronts in flight); -kUpdateBlock: k_update_wide, for rows
@@ -1372,13 +1533,21 @@ hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_price),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)price_lds_bytes(ld));
   if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_price_fin), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)price_lds_bytes(ld));
+  if (e != hipSuccess) return e;
   const int blk = update_block(ld);
   if (blk == 0) return hipErrorInvalidValue;
   const int lds = (int)update_lds_for_block(blk, ld);
   e = hipFuncSetAttribute(update_kernel_for_block(blk), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
+  // The pricing grid serves both pricing kernels: size it for the one that fits fewer.
+  int fin_per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(price_per_cu, k_price, kPriceBlock, price_lds_bytes(ld));
   if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&fin_per_cu, k_price_fin, kPriceBlock, price_lds_bytes(ld));
+  if (e != hipSuccess) return e;
+  *price_per_cu = std::min(*price_per_cu, fin_per_cu);
   if (blk == kUpdateBlock)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update<kUpdateBlock>, kUpdateBlock, lds);
   if (blk > 0)

@@ -40,7 +40,7 @@ def test_header_constants_match_binding():
 def test_struct_layouts():
     assert C.sizeof(binding.lp_options) == 104
     assert C.sizeof(binding.lp_batch_stats) == 96
-    assert C.sizeof(binding.lp_stats) == 240
+    assert C.sizeof(binding.lp_stats) == 256
 
 
 def test_default_options():

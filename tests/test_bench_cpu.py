@@ -18,13 +18,13 @@ def test_more_than_one_gpu_is_refused():
 
 def test_defaults_are_the_headline_workload():
     """Defaults (read from bench.py's argument declarations, not by running it): one GPU,
-    the m = 4000, n = 8000 dense LP, 16 pivots per graph replay; the roofline peak is the
+    the m = 4000, n = 8000 dense LP, 64 pivots per graph replay; the roofline peak is the
     MI355X's 8 TB/s."""
     sys.path.insert(0, ROOT)
     import bench
     src = open(os.path.join(ROOT, "bench.py")).read()
     for decl in ('"--gpus", type=int, default=1', '"--m", type=int, default=4000', '"--n", type=int, default=8000',
-                 '"--iters-per-sync", type=int, default=16'):
+                 '"--iters-per-sync", type=int, default=64'):
         assert decl in src, decl
     assert bench.HBM_PEAK_GBS == 8000.0
     assert set(bench.KERNEL_NAMES) >= {"price", "update", "finish"}
