@@ -295,12 +295,15 @@ int run_reinversion(lp_problem* p) {
   for (auto& e : p->rv_ev)
     if (!e) HIP_TRY(hipEventCreate(&e), "creating reinversion events");
   HIP_TRY(hipEventRecord(p->rv_ev[0], p->stream), "recording an event");
+  // compact columns: Binv up to date first (a reinversion abandoned on a zero pivot keeps it)
+  if (p->d.cmode) HIP_TRY(launch_materialize(p->d, p->stream), "writing B^-1 out");
   int k = 0;
   int rc = reinvert(p->d, p->b0, &p->rv, p->stream, p->h_ctrl->nsb, p->h_ctrl->nD, &k);
   if (rc != LP_OK) return rc;
   // The reinversion forms W from the structural basic variables' costs; in phase 1 the
   // artificial variables cost 1, so W and z are recomputed from their definitions.
   if (p->phase == 1) HIP_TRY(launch_reprice(p->d, p->stream), "pricing the phase-1 basis");
+  if (p->d.cmode) HIP_TRY(launch_rebuild_compact(p->d, p->stream), "compacting B^-1");
   HIP_TRY(hipEventRecord(p->rv_ev[1], p->stream), "recording an event");
   p->rv_timing = true;
   p->last_reinv_t = p->h_ctrl->t;
@@ -333,8 +336,9 @@ struct IterKernel {
 
 std::vector<IterKernel> iteration_kernels(const lp_problem* p, int K) {
   std::vector<IterKernel> out;
-  const IterKernel upd{update_kernel_for_block(p->d.upd_block), p->update_grid, std::abs(p->d.upd_block),
-                       update_lds_for_block(p->d.upd_block, p->ld), kKindUpdate};
+  const IterKernel upd{update_kernel_for(p->d), p->update_grid, std::abs(p->d.upd_block),
+                       p->d.cmode ? compact_lds_bytes(p->ld) : update_lds_for_block(p->d.upd_block, p->ld),
+                       kKindUpdate};
   const IterKernel fin{finish_kernel(), 1, kFinishBlock, 0, kKindFinish};
   if (p->d.mixed) {
     for (int k = 0; k < K; ++k) {
@@ -485,13 +489,14 @@ int launch_panel_iters(lp_problem* p, int k) {
 
 // Workgroup counts of the iteration kernels for an m x n LP (FP64 form) on a device with
 // num_cu compute units, from the occupancy the kernels' LDS allows.
-int iteration_grids(int32_t m, int32_t n, int num_cu, int* price_grid, int* update_grid, int* upd_block) {
+int iteration_grids(int32_t m, int32_t n, int num_cu, bool cmode, int* price_grid, int* update_grid,
+                    int* upd_block) {
   const int ld = (int)round_up(m, 8);
   int price_per_cu = 0, update_per_cu = 0;
-  hipError_t e = kernel_occupancy(&price_per_cu, &update_per_cu, ld);
+  hipError_t e = kernel_occupancy(&price_per_cu, &update_per_cu, ld, cmode);
   if (e != hipSuccess) return fail_hip(e, "querying kernel occupancy");
   if (price_per_cu < 1 || update_per_cu < 1) return fail(LP_ERR_ARG, "m too large for the kernels' LDS");
-  *upd_block = update_block(ld);
+  *upd_block = cmode ? kUpdateBlock : update_block(ld);  // (k_update_c runs kUpdateBlock threads)
   const int pw = kPriceBlock / 64, uw = std::abs(*upd_block) / 64;
   *price_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)price_per_cu * num_cu, (n + pw - 1) / pw));
   *update_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)update_per_cu * num_cu, (m + uw - 1) / uw));
@@ -569,7 +574,10 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
     p->num_cu = prop.multiProcessorCount;
   }
   int upd_block = 0;
-  if ((rc = iteration_grids(m, n, p->num_cu, &p->price_grid, &p->update_grid, &upd_block)) != LP_OK) return bail(rc);
+  // Compact columns for the FP64 form on rows long enough for the sparse-column update.
+  bool cmode = !mixed && compact_columns(ld);
+  if ((rc = iteration_grids(m, n, p->num_cu, cmode, &p->price_grid, &p->update_grid, &upd_block)) != LP_OK)
+    return bail(rc);
   p->reinv_period = o.reinv_period >= 0 ? o.reinv_period : (mixed ? 64 : 0);
   if (mixed) {
     int per_cu = 0;
@@ -593,7 +601,7 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
     const double budget = o.device_budget > 0 ? std::min((double)o.device_budget, (double)freeb) : (double)freeb;
     const double rest = (mixed ? 12.0 : 8.0) * ld * (double)n + 64.0 * N + 64.0 * ld + 64.0 * o.max_iter +
                         16.0 * (p->update_grid + p->price_grid) * 8.0;
-    const double binv = 8.0 * m * (double)ld;
+    const double binv = (cmode ? 16.0 : 8.0) * m * (double)ld;  // B^-1 (and Bc)
     if (rest + binv > budget && !kPanelModeEnabled)
       return bail(fail(LP_ERR_NOMEM, "LP does not fit in the device memory budget (the out-of-core panel mode "
                                      "is switched off in this build)"));
@@ -606,6 +614,10 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
                                      "the FP64 form without reinversion or profiling"));
       p->panel = true;
       p->panel_rows = (int)std::min<double>(rows, m);
+      // the panel mode streams rows of Binv itself: no compact columns
+      cmode = false;
+      if ((rc = iteration_grids(m, n, p->num_cu, false, &p->price_grid, &p->update_grid, &upd_block)) != LP_OK)
+        return bail(rc);
       p->npanels = (m + p->panel_rows - 1) / p->panel_rows;
       p->res_lo = (p->npanels - 1) * p->panel_rows;
     }
@@ -627,6 +639,10 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
     ALLOC(p->rowbuf, (size_t)ld);
   } else {
     ALLOC(p->d.Binv, (size_t)m * ld);
+  }
+  if (cmode) {
+    ALLOC(p->d.Bc, (size_t)m * ld);
+    ALLOC(p->d.rho_c, (size_t)ld);
   }
   ALLOC(p->d.xB, (size_t)m);
   ALLOC(p->d.W0, (size_t)ld);
@@ -662,6 +678,7 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
 #undef ALLOC
   p->d.m = m;
   p->d.n = n;
+  p->d.cmode = cmode ? 1 : 0;
   p->d.upd_block = upd_block;
   p->d.price_grid = p->price_grid;
   p->d.update_grid = p->update_grid;
@@ -798,6 +815,8 @@ int phase_switch(lp_problem* p) {
   std::vector<int32_t> bas(m);
   HIP_TRY(pageable_copy(bas.data(), p->d.basis, sizeof(int32_t) * m, hipMemcpyDeviceToHost, p->stream),
           "reading the basis");
+  // the switch reads and pivots B^-1 by its own columns: compact columns written out first
+  if (p->d.cmode) HIP_TRY(launch_materialize(p->d, p->stream), "writing B^-1 out");
   for (int r = 0; r < m; ++r) {
     // A drive-out changes only its own row of the basis: this list stays valid.
     if (bas[r] < n || !p->art_h[bas[r] - n]) continue;
@@ -807,6 +826,7 @@ int phase_switch(lp_problem* p) {
                          hipMemcpyDeviceToDevice, p->stream),
           "restoring the costs");
   HIP_TRY(launch_reprice(p->d, p->stream), "pricing the phase-2 basis");
+  if (p->d.cmode) HIP_TRY(launch_rebuild_compact(p->d, p->stream), "compacting B^-1");
   p->h_stage->status = LP_RUNNING;
   HIP_TRY(hipMemcpyAsync(&p->d.ctrl->status, &p->h_stage->status, sizeof(int32_t), hipMemcpyHostToDevice, p->stream),
           "setting the status");
@@ -977,6 +997,10 @@ size_t carve_lp(Carver& cv, DevLP& d, int32_t m, int32_t n, int64_t cap, double*
   d.A = cv.take<double>(ld * std::max(n, 1));
   d.chat = cv.take<double>(N);
   d.Binv = cv.take<double>((size_t)m * ld);
+  if (d.cmode) {
+    d.Bc = cv.take<double>((size_t)m * ld);
+    d.rho_c = cv.take<double>(ld);
+  }
   d.xB = cv.take<double>(m);
   d.W0 = cv.take<double>(ld);
   d.W1 = cv.take<double>(ld);
@@ -1231,6 +1255,7 @@ int lp_get_tableau(const lp_problem* pc, double* Binv, double* xB, double* W, do
   lp_problem* p = const_cast<lp_problem*>(pc);
   const int m = p->m;
   if (p->h_ctrl->r >= 0) return fail(LP_ERR_STATE, "a pivot is pending; call lp_solve to completion first");
+  if (Binv && p->d.cmode) HIP_TRY(launch_materialize(p->d, p->stream), "writing B^-1 out");
   if (Binv) {
     // one contiguous copy, unpacked on the host when rows are padded (ld > m); in the
     // out-of-core mode the host copy holds every row but the resident panel's
@@ -1326,7 +1351,9 @@ int lp_solve_device_noalloc(int32_t m, int32_t n, const double* A_colmajor, cons
   HIP_TRY(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev), "querying the device");
   DevLP d{};
   int upd_block = 0, rc = LP_OK;
-  if ((rc = iteration_grids(m, n, num_cu, &d.price_grid, &d.update_grid, &upd_block)) != LP_OK) return rc;
+  d.cmode = compact_columns((int)round_up(m, 8)) ? 1 : 0;  // as lp_create for the FP64 form
+  if ((rc = iteration_grids(m, n, num_cu, d.cmode != 0, &d.price_grid, &d.update_grid, &upd_block)) != LP_OK)
+    return rc;
   double *b0 = nullptr, *c0 = nullptr;
   int32_t* flag = nullptr;
   {

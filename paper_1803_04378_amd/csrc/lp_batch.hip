@@ -263,7 +263,9 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
     // Section 3.1 update of the pending pivot fused with Step 5 and the per-row ratios.
     double* al_p = cur ? al1 : al0;
     double* al_n = cur ? al0 : al1;
-    const bool sparse = sparse_columns(nD, ld);  // the same switch and arithmetic as k_update
+    // the same switch and arithmetic as the FP64 form of lp_solve (k_update_c): over D in
+    // D order on rows long enough, at any |D|
+    const bool sparse = compact_columns(ld);
     if ((r >= 0 || q >= 0) && sparse) {
       for (int i = wave; i < m; i += G) {
         double* rowd = B + (size_t)i * ld;

@@ -7,6 +7,9 @@
 //   W0, W1, rho ld  W = chat_B^T B^-1 (top row of the Figure 1 tableau, two copies: one is
 //                   read while the next is written), rho = pivot row / alpha_r
 //   dlist, inD      m int32 each: the columns of B^-1 that may differ from unit vectors
+//   Bc     m x ld   row-major, FP64 form with ld >= 1024 only: column a holds column dlist[a]
+//                   of B^-1 (a < |D|; zero beyond), so that the update and FTRAN read a row's
+//                   entries on D contiguously; rho_c (ld) is rho at those columns
 //   xB, alpha[2]    m
 //   chat            n + m   (minimisation costs; slacks 0)
 //   basis (m), pos (n+m), tabu_until (n+m), the leaving-side tabu list, the pivot log: int32
@@ -103,6 +106,13 @@ struct Ctrl {
   // Left by k_price_fin for the next k_update: basis[r] = q_pend (bpend != 0), and the
   // tabu list's generation bump gen[gen_q] = gen_val (gen_q >= 0).
   int32_t q_pend, bpend, gen_q, gen_val;
+  // Compact columns (Bc): the index in D the latest finished pivot appended (the leaving
+  // slack's column), -1 if none.  Its entry in row r of Bc is not stored yet: it is the
+  // unit column's 1.
+  int32_t dapp;
+  // Left by k_price_fin for the next k_update: inD[ind_pend] = 1 (>= 0), the leaving
+  // slack's membership in D, which the finish in every workgroup reads as it was.
+  int32_t ind_pend;
 };
 
 struct DevLP {
@@ -173,6 +183,15 @@ struct DevLP {
   // Out-of-core panel mode: device copy of row r of B^-1 for the pricing kernel (nullptr:
   // row r is read from Binv).
   const double* rowsrc;
+  // Compact columns (FP64 form, ld >= kSparseMinLd): B^-1 lives in Bc (column a = column
+  // dlist[a], zero for a >= |D|; the columns outside D are the unit vectors e_p of the rows
+  // p holding their slacks, never stored), rho_c[a] = rho at column dlist[a].  Binv is then
+  // brought up to date only on request (k_materialize), for the steps that read B^-1 by
+  // its own columns: the tableau read-back, the phase switch, the reinversion.
+  int32_t cmode;
+  int32_t pad3;
+  double* Bc;
+  double* rho_c;
 };
 
 // The top row W this iteration prices with: W + d_q rho of the pending pivot, which the
@@ -194,6 +213,9 @@ constexpr int kUpdateStageMaxLd = 9792;
 __host__ __device__ __forceinline__ bool sparse_columns(int nD, int ld) {
   return ld >= kSparseMinLd && nD * 8 <= ld;
 }
+// The FP64 form with compact columns sums over D in D order at any |D| (k_update_c); the
+// batched solver, whose results equal lp_solve's bit for bit, takes the same rule.
+__host__ __device__ __forceinline__ bool compact_columns(int ld) { return ld >= kSparseMinLd; }
 
 // One term of the upload check's hash: the SplitMix64 finaliser (Steele, Lea & Flood,
 // OOPSLA 2014) of a double's bit pattern mixed with its index; the hash of an array is the
@@ -210,6 +232,10 @@ __host__ __device__ __forceinline__ uint64_t hash_word(uint64_t bits, uint64_t i
 hipError_t launch_init(const DevLP& lp, const double* b, const double* c, double sense, hipStream_t s);
 hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s);
 hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s);
+// Compact columns: Binv's columns in D from Bc (the others are unit vectors already), and
+// Bc from Binv and the list D (zero beyond |D|); no pivot may be pending.
+hipError_t launch_materialize(const DevLP& lp, hipStream_t s);
+hipError_t launch_rebuild_compact(const DevLP& lp, hipStream_t s);
 hipError_t launch_finish(const DevLP& lp, hipStream_t s);
 // Sets *flag when some |x_k| exceeds bound (or is NaN).
 hipError_t launch_check_finite(const double* x, int64_t count, double bound, int32_t* flag, hipStream_t s);
@@ -236,6 +262,8 @@ const void* price_kernel();
 const void* price_fin_kernel();
 const void* update_kernel(int ld);
 const void* update_kernel_for_block(int block);
+// the update kernel an LP launches: k_update_c with compact columns, else by its block
+const void* update_kernel_for(const DevLP& lp);
 int update_block(int ld);
 const void* finish_kernel();
 size_t price_lds_bytes(int ld);
@@ -243,7 +271,8 @@ size_t update_lds_bytes(int ld);
 // LDS of the update kernel update_block(ld) selects (block < 0: k_update_wide).
 size_t update_lds_for_block(int block, int ld);
 size_t wide_lds_bytes(int ld);
-hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld);
+size_t compact_lds_bytes(int ld);
+hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld, bool cmode);
 
 // Two-phase start (lp_phase.hip): W and z from their definitions for the current costs,
 // and the step-0 pivot that replaces the artificial variable basic in row r (no-op for a

@@ -48,6 +48,9 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
     const size_t i = k / ld, j = k - i * ld;
     lp.Binv[k] = (i == j) ? 1.0 : 0.0;
   }
+  // compact columns: D is empty, every column of Bc zero
+  const size_t ctotal = lp.cmode ? (size_t)m * ld : 0;
+  for (size_t k = tid; k < ctotal; k += stride) lp.Bc[k] = 0.0;
   for (size_t k = tid; k < (size_t)ld; k += stride) {
     lp.W0[k] = 0.0;
     lp.W1[k] = 0.0;
@@ -77,6 +80,8 @@ __global__ void k_init(DevLP lp, const double* __restrict__ b, const double* __r
     ctl->ray = -1;
     ctl->verdict = -1;
     ctl->gen_q = -1;
+    ctl->dapp = -1;
+    ctl->ind_pend = -1;
   }
 }
 
@@ -90,6 +95,7 @@ struct FinishIn {
 struct FinishOut {
   int pivot;  // 1: a pivot on row r was committed; 0: the solve stopped or (mixed) no pivot
   int r, leave;
+  int kept;  // 0: the leaving slack's column joined D (at index nD0)
   double ar;
 };
 
@@ -159,6 +165,12 @@ __device__ __forceinline__ void price_pass(const DevLP& lp, double2* s_w2) {
     ar = ctl->ar;
     dq = ctl->pdq;
   }
+  // compact columns: the length of D after the pending pivot, and the index it appended
+  int nDn = 0, a_app = -1, j_app = -1;
+  if (!FUSED && lp.cmode) {
+    nDn = ctl->nD;
+    a_app = ctl->dapp;
+  }
   const int jl = gw + lane * nw;
   int c_pos = 0, c_tabu = 0;
   double c_chat = 0.0;
@@ -188,9 +200,52 @@ __device__ __forceinline__ void price_pass(const DevLP& lp, double2* s_w2) {
     pl = fo.leave;
     pl_pos = (lp.art && pl >= n && lp.art[pl - n]) ? kPosBarred : -1;
     pl_tabu = lp.tenure > 0 ? (int)(fin.t + lp.tenure) : lp.tabu_until[pl];
+    // (dlist[nD0] is written by workgroup 0 in this launch: the appended column is pl - n)
+    nDn = fin.nD0 + (fo.kept ? 0 : 1);
+    a_app = fo.kept ? -1 : fin.nD0;
+    j_app = pl - n;
   }
 
-  if (r >= 0) {
+  if (r >= 0 && lp.cmode) {
+    // Compact columns: rho = B^-1[r,:] / alpha_r is zero outside D, and row r of Bc holds
+    // it on D (at the appended index the unit column's 1, not stored yet).  W is staged as
+    // it is, then W + d_q rho is formed at the columns of D: the same values as the dense
+    // formation, which leaves every other entry unchanged.  Workgroup 0 stores rho_c and
+    // W_new.
+    const double2* Wold = reinterpret_cast<const double2*>(wc ? lp.W1 : lp.W0);
+    double2* Wnew = reinterpret_cast<double2*>(wc ? lp.W0 : lp.W1);
+    const double* crow = lp.Bc + (size_t)r * lp.ld;
+    const bool writer = blockIdx.x == 0;
+    const int a0 = threadIdx.x, a1 = threadIdx.x + kPriceBlock;
+    double b0 = 0.0, b1 = 0.0;
+    int j0 = 0, j1 = 0;
+    if (a0 < nDn) {
+      b0 = crow[a0];
+      j0 = lp.dlist[a0];
+    }
+    if (a1 < nDn) {
+      b1 = crow[a1];
+      j1 = lp.dlist[a1];
+    }
+    for (int k = threadIdx.x; k < ld2; k += kPriceBlock) s_w2[k] = Wold[k];
+    __syncthreads();
+    double* s_wd = reinterpret_cast<double*>(s_w2);
+    auto apply = [&](int a, double b, int j) {
+      if (a == a_app) {
+        b = 1.0;
+        if (FUSED) j = j_app;
+      }
+      const double rr = b / ar;
+      s_wd[j] = fma(dq, rr, s_wd[j]);
+      if (writer) lp.rho_c[a] = rr;
+    };
+    if (a0 < nDn) apply(a0, b0, j0);
+    if (a1 < nDn) apply(a1, b1, j1);
+    for (int a = a1 + kPriceBlock; a < nDn; a += kPriceBlock) apply(a, crow[a], lp.dlist[a]);
+    __syncthreads();
+    if (writer)
+      for (int k = threadIdx.x; k < ld2; k += kPriceBlock) Wnew[k] = s_w2[k];
+  } else if (r >= 0) {
     const double2* Wold = reinterpret_cast<const double2*>(wc ? lp.W1 : lp.W0);
     // row r of B^-1: in the out-of-core panel mode a device copy fetched after the ratio test
     const double2* rowr = reinterpret_cast<const double2*>(lp.rowsrc ? lp.rowsrc : lp.Binv + (size_t)r * lp.ld);
@@ -536,10 +591,15 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
   if (blockIdx.x == 0 && tid == 0 && first_panel) {
     // Only fields no k_update workgroup reads: the status itself changes in k_finish.
     Ctrl* cw = lp.ctrl;
-    if (bpend) lp.basis[r] = q_pend;
+    // (bpend outlives its pivot: after a stop, a reinversion or the phase switch r is -1)
+    if (bpend && r >= 0) lp.basis[r] = q_pend;
     if (cw->gen_q >= 0) {
       lp.gen[cw->gen_q] = cw->gen_val;
       cw->gen_q = -1;
+    }
+    if (cw->ind_pend >= 0) {  // (no row of this launch has that slack basic)
+      lp.inD[cw->ind_pend] = 1;
+      cw->ind_pend = -1;
     }
     cw->snap_t = t;
     cw->snap_z = cw->z;
@@ -789,6 +849,318 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
       lp.part_al[blockIdx.x] = low != INT_MAX ? s_al[slot] : 0.0;
       lp.part_bv[blockIdx.x] = low != INT_MAX ? s_bv[slot] : 0;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// k_update with compact columns (FP64 form, ld >= kSparseMinLd): the steps and the
+// arithmetic of k_update's sparse-column pass at any length of D.  A row's entries on D
+// are contiguous in Bc instead of scattered over a row of Binv, and rho comes compact
+// (rho_c, formed by the pricing kernel): this wavefront's entries of its first row, of
+// rho_c and of the list D are requested in the first round with the control block (they
+// wait only for the scalar load of |D|), so only a_q waits for q.  Lane l owns entries
+// l, l + 64, ... in ascending order, the fma chain and butterfly of k_update.
+template <int B>
+__global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
+  constexpr int waves = B / 64;
+  extern __shared__ double2 smem2[];  // a_q
+  __shared__ double red_d[2 * waves];
+  __shared__ int red_j[2 * waves];
+  __shared__ double s_rt[waves * kMaxRowsPerWave];
+  __shared__ double s_tau[waves * kMaxRowsPerWave];
+  __shared__ int s_row[waves * kMaxRowsPerWave];
+  __shared__ double s_al[waves * kMaxRowsPerWave];
+  __shared__ int s_bv[waves * kMaxRowsPerWave];
+  __shared__ int s_nf;  // some row of this workgroup has a non-finite alpha
+  const int m = lp.m, n = lp.n, ld = lp.ld, ld2 = ld / 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_nf = 0;  // read after the barriers below
+  const int gw = blockIdx.x * waves + wave;
+  const int nw = gridDim.x * waves;
+
+  // ---- first round ----
+  const Ctrl* ctl = lp.ctrl;
+  const int status = ctl->status;
+  const int r = ctl->r;
+  const int nD = ctl->nD;
+  const int cur = ctl->cur;
+  const int64_t t = ctl->t;
+  const int64_t max_iter = ctl->max_iter;
+  const double theta = ctl->theta;
+  const int bpend = ctl->bpend, q_pend = ctl->q_pend;
+  const int pk = min(tid, lp.price_grid - 1);
+  double pd0 = lp.part_d[2 * pk], pd1 = lp.part_d[2 * pk + 1];
+  int pj0 = lp.part_j[2 * pk], pj1 = lp.part_j[2 * pk + 1];
+  const int g0 = min(gw, m - 1);
+  double x0 = lp.xB[g0], al00 = lp.alpha0[g0], al10 = lp.alpha1[g0];
+  int bv0 = lp.basis[g0];
+  if (bpend && g0 == r) bv0 = q_pend;
+  double g[kGather], rr[kGather];
+  int dj[kGather];
+  {
+    const double* row = lp.Bc + (size_t)g0 * ld;
+#pragma unroll
+    for (int u = 0; u < kGather; ++u) {
+      const int a = lane + 64 * u;
+      g[u] = 0.0;
+      rr[u] = 0.0;
+      dj[u] = 0;
+      if (a < nD) {
+        g[u] = row[a];
+        rr[u] = lp.rho_c[a];  // (unused when no pivot is pending)
+        dj[u] = lp.dlist[a];
+      }
+    }
+  }
+  asm volatile("" ::: "memory");  // compiler-only: every request above is issued first
+  if (tid >= lp.price_grid) {
+    pd0 = pd1 = __builtin_inf();
+    pj0 = pj1 = INT_MAX;
+  }
+
+  // Step 4 decision from the pricing partials (every workgroup reaches the same q).
+  double da = pd0, df = pd1;
+  int ja = pj0, jf = pj1;
+  for (int k = tid + B; k < lp.price_grid; k += B) {
+    const double d0 = lp.part_d[2 * k], d1 = lp.part_d[2 * k + 1];
+    const int j0 = lp.part_j[2 * k], j1 = lp.part_j[2 * k + 1];
+    if (lex_less(d0, j0, da, ja)) {
+      da = d0;
+      ja = j0;
+    }
+    if (lex_less(d1, j1, df, jf)) {
+      df = d1;
+      jf = j1;
+    }
+  }
+  wave_lexmin(da, ja);
+  wave_lexmin(df, jf);
+  if (lane == 0) {
+    red_d[wave] = da;
+    red_j[wave] = ja;
+    red_d[waves + wave] = df;
+    red_j[waves + wave] = jf;
+  }
+  __syncthreads();
+  da = lane < waves ? red_d[lane] : __builtin_inf();
+  ja = lane < waves ? red_j[lane] : INT_MAX;
+  df = lane < waves ? red_d[waves + lane] : __builtin_inf();
+  jf = lane < waves ? red_j[waves + lane] : INT_MAX;
+  wave_lexmin(da, ja);
+  wave_lexmin(df, jf);
+  if (status != kStatusRunning) return;
+  int verdict = kStatusRunning, q = -1, flags = 0;
+  double dq = 0.0;
+  if (ja == INT_MAX) {
+    verdict = kStatusOptimal;
+  } else if (t >= max_iter) {
+    verdict = kStatusIterLimit;
+  } else if (jf != INT_MAX) {
+    q = jf;
+    dq = df;
+  } else {
+    q = ja;
+    dq = da;
+    flags = kFlagAspiration;
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    // Only fields no workgroup of this launch reads (as in k_update).
+    Ctrl* cw = lp.ctrl;
+    // (bpend outlives its pivot: after a stop, a reinversion or the phase switch r is -1)
+    if (bpend && r >= 0) lp.basis[r] = q_pend;
+    if (cw->gen_q >= 0) {
+      lp.gen[cw->gen_q] = cw->gen_val;
+      cw->gen_q = -1;
+    }
+    if (cw->ind_pend >= 0) {  // (no row of this launch has that slack basic)
+      lp.inD[cw->ind_pend] = 1;
+      cw->ind_pend = -1;
+    }
+    cw->snap_t = t;
+    cw->snap_z = cw->z;
+    cw->snap_nD = nD;
+    cw->snap_nsb = cw->nsb;
+    cw->snap_nL = cw->nL;
+    cw->snap_cur = cur;
+    cw->price_cols += n - cw->nsb;
+    cw->price_launches += 1;
+    if (r >= 0) cw->wcur ^= 1;  // pricing stored W_new: it is the current top row now
+    cw->verdict = verdict;
+    cw->q = q;
+    cw->dq = dq;
+    cw->flags = flags;
+    if (flags & kFlagAspiration) cw->n_aspiration += 1;
+    if (r >= 0) {
+      cw->update_launches += 1;
+      cw->update_rows_written += m;
+    } else if (q >= 0) {
+      cw->update_launches += 1;
+    }
+  }
+  if (r < 0 && q < 0) return;
+
+  // ---- second round: a_q ----
+  const double* __restrict__ al_p = cur ? lp.alpha1 : lp.alpha0;  // pending pivot's alpha
+  double* __restrict__ al_n = cur ? lp.alpha0 : lp.alpha1;        // FTRAN result for q
+  const double eps_p = lp.eps_p, eps_z = lp.eps_z;
+  const bool q_col = q >= 0 && q < n;
+  const double2* aq2 = reinterpret_cast<const double2*>(lp.A + (size_t)(q_col ? q : 0) * ld);
+  Hold5 hold;
+  if (q_col) hold_load<B>(hold, aq2, tid, ld2);
+  // whether the first row's basic variable is a slack outside D (its column of B^-1 is a
+  // unit vector): the FTRAN adds its unit term, and the finish needs it for the leaving
+  // variable
+  int in0 = 1;
+  if (gw < m && bv0 >= n) in0 = lp.inD[bv0 - n];
+  double2* s_a = smem2;
+  const double* s_ad = reinterpret_cast<const double*>(s_a);
+  if (q_col) {
+    hold_store<B>(hold, s_a, aq2, tid, ld2);
+  } else if (q >= 0) {
+    const int e = q - n;
+    for (int k = tid; k < ld2; k += B) s_a[k] = make_double2(2 * k == e ? 1.0 : 0.0, 2 * k + 1 == e ? 1.0 : 0.0);
+  }
+  if (blockIdx.x == 0) {
+    // bytes: the D entries of every row but r read, the changed ones written in every row,
+    // one unit lookup (basis, membership, a_q entry) per row
+    int nz = 0;
+    if (r >= 0)
+      for (int a = tid; a < nD; a += B) nz += lp.rho_c[a] != 0.0 ? 1 : 0;
+    nz = block_sum_int<B>(nz, red_j);
+    if (tid == 0) lp.ctrl->update_bytes += 8 * ((int64_t)(m - 1) * nD + (int64_t)m * nz) + 16 * (int64_t)m;
+  }
+  __syncthreads();  // a_q is in LDS
+  int c = 0;
+  for (int i = gw; i < m; i += nw, ++c) {
+    double* row = lp.Bc + (size_t)i * ld;
+    double x, alp;
+    int bv, in;
+    if (c == 0) {
+      x = x0;
+      alp = cur ? al10 : al00;
+      bv = bv0;
+      in = in0;
+    } else {
+      x = lp.xB[i];
+      alp = al_p[i];
+      bv = (bpend && i == r) ? q_pend : lp.basis[i];
+      in = bv >= n ? lp.inD[bv - n] : 1;
+#pragma unroll
+      for (int u = 0; u < kGather; ++u) {
+        const int a = lane + 64 * u;
+        if (a < nD) g[u] = row[a];
+      }
+    }
+    const bool isr = i == r;
+    const double na = (r >= 0 && !isr) ? -alp : 0.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < kGather; ++u) {
+      const int a = lane + 64 * u;
+      if (a < nD) {
+        double val = g[u];
+        if (r >= 0) {
+          const double rv = rr[u];
+          val = isr ? rv : fma(na, rv, val);  // row r := rho (zero wherever rho is zero)
+          if (rv != 0.0) row[a] = val;
+        }
+        if (q >= 0) acc = fma(val, s_ad[dj[u]], acc);
+      }
+    }
+    for (int a = lane + 64 * kGather; a < nD; a += 64) {
+      double val = row[a];
+      if (r >= 0) {
+        const double rv = lp.rho_c[a];
+        val = isr ? rv : fma(na, rv, val);
+        if (rv != 0.0) row[a] = val;
+      }
+      if (q >= 0) acc = fma(val, s_ad[lp.dlist[a]], acc);
+    }
+    if (r >= 0) {
+      x = isr ? theta : fma(na, theta, x);
+      if (fabs(x) < eps_z) x = 0.0;
+      if (lane == 0) lp.xB[i] = x;
+    }
+    if (q >= 0) {
+      acc = wave_sum(acc);
+      // the unit column of this row's basic slack, when it is not in D
+      if (bv >= n && !in) acc += s_ad[bv - n];
+      double rt = __builtin_inf(), tau = __builtin_inf();
+      if (acc > eps_p) {
+        const double xp = fmax(x, 0.0);
+        rt = xp / acc;
+        tau = (xp - lp.eps_t) / acc;
+        tau -= 1e-12 * (fabs(tau) + 1.0);
+      }
+      if (lane == 0) {
+        al_n[i] = acc;
+        s_rt[wave * kMaxRowsPerWave + c] = rt;
+        s_tau[wave * kMaxRowsPerWave + c] = tau;
+        s_row[wave * kMaxRowsPerWave + c] = acc > eps_p ? i : INT_MAX;  // INT_MAX: not a candidate
+        if (!isfinite(acc)) s_nf = 1;
+        s_al[wave * kMaxRowsPerWave + c] = acc;
+        s_bv[wave * kMaxRowsPerWave + c] = 2 * bv + ((bv < n || in) ? 1 : 0);
+      }
+    }
+  }
+  if (q < 0) return;
+  // Workgroup partial of Step 6 (as k_update).
+  for (int k = c; k < kMaxRowsPerWave; ++k)
+    if (lane == 0) {
+      s_rt[wave * kMaxRowsPerWave + k] = __builtin_inf();
+      s_tau[wave * kMaxRowsPerWave + k] = __builtin_inf();
+      s_row[wave * kMaxRowsPerWave + k] = INT_MAX;
+    }
+  __syncthreads();
+  if (wave == 0) {
+    constexpr int slots = waves * kMaxRowsPerWave;
+    double th = __builtin_inf(), t1 = __builtin_inf(), t2 = __builtin_inf();
+    int low = INT_MAX, slot = 0;
+    for (int k = lane; k < slots; k += 64) {
+      if (lex_less(s_rt[k], s_row[k], th, low)) {
+        th = s_rt[k];
+        low = s_row[k];
+        slot = k;
+      }
+      const double tk = s_tau[k];
+      if (tk < t1) {
+        t2 = t1;
+        t1 = tk;
+      } else if (tk < t2) {
+        t2 = tk;
+      }
+    }
+    wave_lexmin_payload(th, low, slot);
+    wave_two_smallest(t1, t2);
+    if (lane == 0) {
+      lp.part_th[blockIdx.x] = s_nf ? -__builtin_inf() : th;
+      lp.part_low[blockIdx.x] = s_nf ? -1 : low;
+      lp.part_t1[blockIdx.x] = t1;
+      lp.part_t2[blockIdx.x] = t2;
+      lp.part_al[blockIdx.x] = low != INT_MAX ? s_al[slot] : 0.0;
+      lp.part_bv[blockIdx.x] = low != INT_MAX ? s_bv[slot] : 0;
+    }
+  }
+}
+
+// Compact columns on request (no pivot pending): Binv's columns in D from Bc (each thread
+// one row entry), and Bc from Binv (zero beyond |D|).
+__global__ void k_materialize(DevLP lp) {
+  const int nD = lp.ctrl->nD, ld = lp.ld;
+  const size_t total = (size_t)lp.m * nD;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < total; k += stride) {
+    const size_t i = k / nD, a = k - i * nD;
+    lp.Binv[i * ld + lp.dlist[a]] = lp.Bc[i * ld + a];
+  }
+}
+__global__ void k_rebuild_compact(DevLP lp) {
+  const int nD = lp.ctrl->nD, ld = lp.ld;
+  const size_t total = (size_t)lp.m * ld;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < total; k += stride) {
+    const size_t i = k / ld, a = k - i * ld;
+    lp.Bc[k] = (int)a < nD ? lp.Binv[i * ld + lp.dlist[a]] : 0.0;
   }
 }
 
@@ -1136,7 +1508,7 @@ __device__ FinishOut finish_step(const DevLP& lp, const FinishIn& in, double pth
   const int verdict = in.verdict, q = in.q, cur = in.cur, flags0 = in.flags0, nD0 = in.nD0, nsb0 = in.nsb0;
   const int64_t t = in.t;
   const double dq = in.dq, z0 = in.z0;
-  FinishOut out{0, -1, -1, 0.0};
+  FinishOut out{0, -1, -1, 1, 0.0};
   if (tid >= nparts) {
     pth = pt1 = pt2 = __builtin_inf();
     plow = INT_MAX;
@@ -1305,10 +1677,15 @@ __device__ FinishOut finish_step(const DevLP& lp, const FinishIn& in, double pth
     if (thr == 0.0) flags |= kFlagDegenerate;
     if (lp.tenure > 0) lp.tabu_until[leave] = (int)(t + lp.tenure);
     if (!kept) {  // its column of B^-1 stops being a unit vector
-      lp.inD[leave - lp.n] = 1;
+      if (FUSED) {
+        ctl->ind_pend = leave - lp.n;  // set by the next k_update (inD is read above)
+      } else {
+        lp.inD[leave - lp.n] = 1;
+      }
       lp.dlist[nD0] = leave - lp.n;
       ctl->nD = nD0 + 1;
     }
+    ctl->dapp = kept ? -1 : nD0;
     ctl->z = fma(dq, thr, z0);
     if (FUSED) {
       ctl->q_pend = q;  // basis[r] = q, applied by the next k_update
@@ -1344,6 +1721,7 @@ __device__ FinishOut finish_step(const DevLP& lp, const FinishIn& in, double pth
   out.pivot = 1;
   out.r = r;
   out.leave = leave;
+  out.kept = kept;
   out.ar = ar;
   return out;
 }
@@ -1520,6 +1898,9 @@ const void* update_kernel_for_block(int block) {
                                : reinterpret_cast<const void*>(&k_update_wide<kUpdateBlock>);
 }
 const void* update_kernel(int ld) { return update_kernel_for_block(update_block(ld)); }
+const void* update_kernel_for(const DevLP& lp) {
+  return lp.cmode ? reinterpret_cast<const void*>(&k_update_c<kUpdateBlock>) : update_kernel_for_block(lp.upd_block);
+}
 const void* finish_kernel() { return reinterpret_cast<const void*>(&k_finish); }
 
 size_t price_lds_bytes(int ld) { return sizeof(double) * (size_t)ld; }
@@ -1528,8 +1909,10 @@ size_t update_lds_bytes(int ld) {
   return 2 * sizeof(double) * (size_t)ld + (ld >= kSparseMinLd ? sizeof(int) * (size_t)(ld / 8) : 0);
 }
 size_t update_lds_for_block(int block, int ld) { return block > 0 ? update_lds_bytes(ld) : wide_lds_bytes(ld); }
+// k_update_c stages a_q only
+size_t compact_lds_bytes(int ld) { return sizeof(double) * (size_t)ld; }
 
-hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld) {
+hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld, bool cmode) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_price),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)price_lds_bytes(ld));
   if (e != hipSuccess) return e;
@@ -1541,6 +1924,11 @@ hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld) {
   const int lds = (int)update_lds_for_block(blk, ld);
   e = hipFuncSetAttribute(update_kernel_for_block(blk), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
+  if (cmode) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update_c<kUpdateBlock>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)compact_lds_bytes(ld));
+    if (e != hipSuccess) return e;
+  }
   // The pricing grid serves both pricing kernels: size it for the one that fits fewer.
   int fin_per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(price_per_cu, k_price, kPriceBlock, price_lds_bytes(ld));
@@ -1548,6 +1936,9 @@ hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld) {
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&fin_per_cu, k_price_fin, kPriceBlock, price_lds_bytes(ld));
   if (e != hipSuccess) return e;
   *price_per_cu = std::min(*price_per_cu, fin_per_cu);
+  if (cmode)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update_c<kUpdateBlock>, kUpdateBlock,
+                                                        compact_lds_bytes(ld));
   if (blk == kUpdateBlock)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update<kUpdateBlock>, kUpdateBlock, lds);
   if (blk > 0)
@@ -1569,13 +1960,29 @@ hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s) {
 }
 
 hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s) {
-  if (lp.upd_block < 0)
+  if (lp.cmode)
+    hipLaunchKernelGGL(k_update_c<kUpdateBlock>, dim3(grid), dim3(kUpdateBlock), compact_lds_bytes(lp.ld), s, lp);
+  else if (lp.upd_block < 0)
     hipLaunchKernelGGL(k_update_wide<kUpdateBlock>, dim3(grid), dim3(kUpdateBlock), wide_lds_bytes(lp.ld), s, lp);
   else if (lp.upd_block == kUpdateBlock)
     hipLaunchKernelGGL(k_update<kUpdateBlock>, dim3(grid), dim3(kUpdateBlock), update_lds_bytes(lp.ld), s, lp);
   else
     hipLaunchKernelGGL(k_update<2 * kUpdateBlock>, dim3(grid), dim3(2 * kUpdateBlock), update_lds_bytes(lp.ld), s,
                        lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_materialize(const DevLP& lp, hipStream_t s) {
+  const size_t work = (size_t)lp.m * lp.ld;
+  const int grid = (int)std::max<size_t>(1, std::min<size_t>(4096, (work + 255) / 256));
+  hipLaunchKernelGGL(k_materialize, dim3(grid), dim3(256), 0, s, lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_rebuild_compact(const DevLP& lp, hipStream_t s) {
+  const size_t work = (size_t)lp.m * lp.ld;
+  const int grid = (int)std::max<size_t>(1, std::min<size_t>(4096, (work + 255) / 256));
+  hipLaunchKernelGGL(k_rebuild_compact, dim3(grid), dim3(256), 0, s, lp);
   return hipGetLastError();
 }
 

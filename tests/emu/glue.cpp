@@ -11,6 +11,11 @@ static const char* kname(const void* fn) {
   if (fn == update_kernel_for_block(512)) return "k_update<512>";
   if (fn == update_kernel_for_block(1024)) return "k_update<1024>";
   if (fn == update_kernel_for_block(-512)) return "k_update_wide";
+  {
+    DevLP c{};
+    c.cmode = 1;
+    if (fn == update_kernel_for(c)) return "k_update_c";
+  }
   if (fn == price32_kernel()) return "k_price32";
   if (fn == shortlist_kernel()) return "k_shortlist";
   return "struct-arg kernel";

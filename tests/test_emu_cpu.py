@@ -25,7 +25,7 @@ def emu_lib():
     return emu_build.build()
 
 
-def _run(lib, body, timeout=600):
+def _run(lib, body, timeout=600, env=None):
     code = textwrap.dedent(f"""
         import sys
         sys.path[:0] = [{ROOT!r}, {os.path.join(ROOT, "tests")!r}]
@@ -37,7 +37,8 @@ def _run(lib, body, timeout=600):
         def same_log(piv, ref):
             return all(np.array_equal(piv[k], getattr(ref, k)) for k in ("enter", "row", "leave", "flags"))
     """) + textwrap.dedent(body)
-    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=timeout)
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=timeout,
+                         env=dict(os.environ, **(env or {})))
     assert res.returncode == 0, res.stdout[-2000:] + res.stderr[-4000:]
     return res.stdout
 
@@ -99,4 +100,119 @@ def test_batch_and_noalloc_equal_the_handle_path(emu_lib):
             assert np.array_equal(x, sol["x"]) and np.array_equal(y, sol["y"]) and obj[0] == sol["objective"]
         print("ok")
     """)
+    assert "ok" in out
+
+
+def test_compact_columns_follow_oracle(emu_lib):
+    """Rows of 1024 and more: the FP64 form keeps B^-1 as compact columns over the list D
+    (k_update_c, and rho formed from them by the pricing kernels).  Pivot logs equal the
+    oracle's on the nearly diagonal law (|D| grows by one per pivot, past the 512 entries a
+    lane holds in registers and far past ld/8), on ties with the leaving-side list, and on a
+    two-phase LP with a drive-out and a redundant row (the switch writes B^-1 out and
+    compacts it again); the tableau read-back is B^-1 to rounding; an FP64 reinversion (B^-1 written
+    out, reinverted, compacted) keeps the oracle's objective."""
+    out = _run(emu_lib, """
+        def check_inverse(p, A, basis):
+            Binv = p.tableau()[0]
+            m = A.shape[0]
+            B = np.hstack([A, np.eye(m)])[:, basis]
+            err = np.abs(Binv @ B - np.eye(m)).max()
+            assert err < 1e-9, err
+        A, b, c = lpgen.diagonal_lp(0, 1032, 560)
+        ref = oracle.solve(A, b, c)
+        with lpg.LP(A, b, c, iters_per_sync=64) as p:
+            st = p.solve(); piv = p.pivots(); sol = p.solution()
+            assert st == ref.status and same_log(piv, ref)
+            assert abs(sol["objective"] - ref.objective) <= 1e-9 * abs(ref.objective)
+            check_inverse(p, A, sol["basis"])
+        A, b, c = lpgen.degenerate_lp(4, 1030, 100, budget_row=True)
+        ref = oracle.solve(A, b, c)
+        with lpg.LP(A, b, c, iters_per_sync=3) as p:
+            st = p.solve(); piv = p.pivots(); s = p.stats()
+        assert st == ref.status and same_log(piv, ref) and s["ties"] == ref.counts["tie"] > 0
+        # plus an empty >= row and an empty = row, both with b = 0: phase 1 ends with their
+        # artificial variables basic at zero; the first is driven out by its surplus
+        # column, the second row is redundant
+        A, b, c, rt = lpgen.general_lp(0, 1022, 60)
+        A = np.vstack([A, np.zeros((2, 60))])
+        b = np.concatenate([b, [0.0, 0.0]])
+        rt = np.concatenate([rt, [1, 2]]).astype(np.int32)
+        ref = oracle.solve(A, b, c, row_type=rt)
+        with lpg.LP(A, b, c, row_type=rt) as p:
+            st = p.solve(); piv = p.pivots(); s = p.stats()
+        assert st == ref.status and same_log(piv, ref)
+        assert s["drive_outs"] == int(np.count_nonzero(ref.flags & oracle.FLAG_DRIVEOUT)) > 0
+        A, b, c = lpgen.diagonal_lp(1, 1032, 200)
+        ref = oracle.solve(A, b, c)
+        with lpg.LP(A, b, c, reinv_period=16) as p:
+            st = p.solve(); sol = p.solution(); s = p.stats()
+            assert st == ref.status and s["reinversions"] > 0 and s["reinv_failed"] == 0
+            assert abs(sol["objective"] - ref.objective) <= 1e-9 * abs(ref.objective)
+            check_inverse(p, A, sol["basis"])
+        print("ok")
+    """, timeout=900)
+    assert "ok" in out
+
+
+def test_compact_columns_batch_and_noalloc(emu_lib):
+    """The batched solver sums over D in D order at any |D| on rows of 1024 and more, as the
+    FP64 form does: its results equal lp_solve's bit for bit; so do the allocation-free
+    entry point's."""
+    out = _run(emu_lib, """
+        import ctypes as C
+        lps = [lpgen.diagonal_lp(1, 1032, 200), lpgen.dense_lp(7, 1024, 40),
+               lpgen.degenerate_lp(5, 1030, 60, budget_row=True)]
+        with lpg.Batch(lps) as bt:
+            bt.solve(); res = bt.results()
+            for i, (A, b, c) in enumerate(lps):
+                with lpg.LP(A, b, c) as p:
+                    st = p.solve(); sol = p.solution(); piv = p.pivots()
+                g = bt.get(i)
+                assert res["status"][i] == st and res["iterations"][i] == sol["iterations"]
+                assert res["objective"][i] == sol["objective"]
+                for k in ("enter", "row", "flags"):
+                    assert np.array_equal(g[k], piv[k]), (i, k)
+                assert np.array_equal(g["x"], sol["x"]) and np.array_equal(g["basis"], sol["basis"])
+        L = lpg.lib()
+        dp = lambda a: a.ctypes.data_as(C.c_void_p)
+        A, b, c = lps[1]
+        with lpg.LP(A, b, c) as p:
+            st = p.solve(); sol = p.solution()
+        m, n = A.shape
+        Af = np.asfortranarray(A); x = np.full(n, np.nan); y = np.full(m, np.nan); obj = np.full(1, np.nan)
+        s2 = C.c_int32(); it = C.c_int64(); o = binding.default_options()
+        rc = L.lp_solve_device_noalloc(m, n, dp(Af), dp(b), dp(c), C.byref(o), dp(x), dp(y), dp(obj),
+                                       C.byref(s2), C.byref(it))
+        assert rc == 0 and s2.value == st and it.value == sol["iterations"]
+        assert np.array_equal(x, sol["x"]) and np.array_equal(y, sol["y"]) and obj[0] == sol["objective"]
+        print("ok")
+    """, timeout=900)
+    assert "ok" in out
+
+
+def test_front_guards_after_a_stop(emu_lib):
+    """Every allocation starts at a guard page (EMU_GUARD_FRONT), so an access one element
+    before an array faults.  A solve that stops inside a launch sequence (phase 1 priced
+    out optimal) leaves the deferred bookkeeping of its last fused pivot behind with no
+    pivot pending (r = -1); after the phase switch, and when a solve resumes past its pivot
+    limit or after a reinversion, the next update must not apply it."""
+    out = _run(emu_lib, """
+        A, b, c, rt = lpgen.general_lp(0, 40, 80)
+        ref = oracle.solve(A, b, c, row_type=rt)
+        for ips in (3, 16):
+            with lpg.LP(A, b, c, row_type=rt, iters_per_sync=ips) as p:
+                st = p.solve(); piv = p.pivots()
+            assert st == ref.status and same_log(piv, ref), ips
+        A, b, c = lpgen.dense_lp(2, 64, 128)
+        ref = oracle.solve(A, b, c)
+        with lpg.LP(A, b, c, iters_per_sync=4) as p:
+            assert p.solve(7) == lpg.LP_ITER_LIMIT
+            st = p.solve(); piv = p.pivots()
+        assert st == ref.status and same_log(piv, ref)
+        with lpg.LP(A, b, c, reinv_period=5, iters_per_sync=4) as p:
+            st = p.solve(); sol = p.solution(); s = p.stats()
+        assert st == ref.status and s["reinversions"] > 0
+        assert abs(sol["objective"] - ref.objective) <= 1e-9 * abs(ref.objective)
+        print("ok")
+    """, env={"EMU_GUARD_FRONT": "1"})
     assert "ok" in out
