@@ -303,7 +303,7 @@ int run_reinversion(lp_problem* p) {
   // The reinversion forms W from the structural basic variables' costs; in phase 1 the
   // artificial variables cost 1, so W and z are recomputed from their definitions.
   if (p->phase == 1) HIP_TRY(launch_reprice(p->d, p->stream), "pricing the phase-1 basis");
-  if (p->d.cmode) HIP_TRY(launch_rebuild_compact(p->d, p->stream), "compacting B^-1");
+  if (p->d.cmode) HIP_TRY(launch_rebuild_compact(p->d, p->h_ctrl->nD, p->stream), "compacting B^-1");
   HIP_TRY(hipEventRecord(p->rv_ev[1], p->stream), "recording an event");
   p->rv_timing = true;
   p->last_reinv_t = p->h_ctrl->t;
@@ -826,7 +826,7 @@ int phase_switch(lp_problem* p) {
                          hipMemcpyDeviceToDevice, p->stream),
           "restoring the costs");
   HIP_TRY(launch_reprice(p->d, p->stream), "pricing the phase-2 basis");
-  if (p->d.cmode) HIP_TRY(launch_rebuild_compact(p->d, p->stream), "compacting B^-1");
+  if (p->d.cmode) HIP_TRY(launch_rebuild_compact(p->d, p->h_ctrl->nD, p->stream), "compacting B^-1");
   p->h_stage->status = LP_RUNNING;
   HIP_TRY(hipMemcpyAsync(&p->d.ctrl->status, &p->h_stage->status, sizeof(int32_t), hipMemcpyHostToDevice, p->stream),
           "setting the status");

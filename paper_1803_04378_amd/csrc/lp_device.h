@@ -233,9 +233,10 @@ hipError_t launch_init(const DevLP& lp, const double* b, const double* c, double
 hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s);
 hipError_t launch_update(const DevLP& lp, int grid, hipStream_t s);
 // Compact columns: Binv's columns in D from Bc (the others are unit vectors already), and
-// Bc from Binv and the list D (zero beyond |D|); no pivot may be pending.
+// Bc from Binv and the list D (zero beyond |D|, given that it was zero beyond nd_prev, the
+// length of D before); no pivot may be pending.
 hipError_t launch_materialize(const DevLP& lp, hipStream_t s);
-hipError_t launch_rebuild_compact(const DevLP& lp, hipStream_t s);
+hipError_t launch_rebuild_compact(const DevLP& lp, int nd_prev, hipStream_t s);
 hipError_t launch_finish(const DevLP& lp, hipStream_t s);
 // Sets *flag when some |x_k| exceeds bound (or is NaN).
 hipError_t launch_check_finite(const double* x, int64_t count, double bound, int32_t* flag, hipStream_t s);

@@ -1144,7 +1144,9 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
 }
 
 // Compact columns on request (no pivot pending): Binv's columns in D from Bc (each thread
-// one row entry), and Bc from Binv (zero beyond |D|).
+// one row entry), and Bc from Binv and the list D.  Columns of Bc from |D| on must be zero:
+// the rebuild clears those below nd_prev, the length of D before the step that changed it
+// (the ones beyond were zero already).
 __global__ void k_materialize(DevLP lp) {
   const int nD = lp.ctrl->nD, ld = lp.ld;
   const size_t total = (size_t)lp.m * nD;
@@ -1154,13 +1156,14 @@ __global__ void k_materialize(DevLP lp) {
     lp.Binv[i * ld + lp.dlist[a]] = lp.Bc[i * ld + a];
   }
 }
-__global__ void k_rebuild_compact(DevLP lp) {
+__global__ void k_rebuild_compact(DevLP lp, int nd_prev) {
   const int nD = lp.ctrl->nD, ld = lp.ld;
-  const size_t total = (size_t)lp.m * ld;
+  const int w = max(nD, nd_prev);
+  const size_t total = (size_t)lp.m * w;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < total; k += stride) {
-    const size_t i = k / ld, a = k - i * ld;
-    lp.Bc[k] = (int)a < nD ? lp.Binv[i * ld + lp.dlist[a]] : 0.0;
+    const size_t i = k / w, a = k - i * w;
+    lp.Bc[i * ld + a] = (int)a < nD ? lp.Binv[i * ld + lp.dlist[a]] : 0.0;
   }
 }
 
@@ -1979,10 +1982,10 @@ hipError_t launch_materialize(const DevLP& lp, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_rebuild_compact(const DevLP& lp, hipStream_t s) {
+hipError_t launch_rebuild_compact(const DevLP& lp, int nd_prev, hipStream_t s) {
   const size_t work = (size_t)lp.m * lp.ld;
   const int grid = (int)std::max<size_t>(1, std::min<size_t>(4096, (work + 255) / 256));
-  hipLaunchKernelGGL(k_rebuild_compact, dim3(grid), dim3(256), 0, s, lp);
+  hipLaunchKernelGGL(k_rebuild_compact, dim3(grid), dim3(256), 0, s, lp, nd_prev);
   return hipGetLastError();
 }
 

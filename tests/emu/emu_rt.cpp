@@ -49,6 +49,12 @@ struct Alloc { void* base; size_t len; size_t n; };
 static std::map<void*, Alloc> g_allocs;
 static const size_t kPage = 4096;
 static bool front_mode() { static int m = getenv("EMU_GUARD_FRONT") ? 1 : 0; return m; }
+// The byte new device, pinned and LDS memory is filled with (EMU_FILL, default 0xFF: an
+// uninitialised int reads as -1): runs with other fills expose reads of memory never written.
+static int fill_byte() {
+  static int f = getenv("EMU_FILL") ? (int)strtol(getenv("EMU_FILL"), nullptr, 0) & 0xFF : 0xFF;
+  return f;
+}
 void* galloc(size_t n, int fill) {
   const size_t data = (std::max<size_t>(n, 1) + kPage - 1) / kPage * kPage;
   const size_t len = data + 2 * kPage;
@@ -275,7 +281,7 @@ void launch_(const std::function<void()>& body, dim3 grid, dim3 block, size_t sh
     g_stacks.push_back(s + kPage);
   }
   if ((int)g_f.size() < nslots) g_f.resize(nslots);
-  void* dyn = shmem ? galloc(shmem, 0xFF) : nullptr;
+  void* dyn = shmem ? galloc(shmem, fill_byte()) : nullptr;
   g_dyn = dyn; g_dyn_n = shmem; g_body = &body; g_kname = name;
   gridDim = {grid.x, grid.y, grid.z};
   blockDim = {block.x, block.y, block.z};
@@ -283,7 +289,7 @@ void launch_(const std::function<void()>& body, dim3 grid, dim3 block, size_t sh
     for (unsigned y = 0; y < grid.y; ++y)
       for (unsigned x = 0; x < grid.x; ++x) {
         blockIdx = {x, y, z};
-        if (dyn) memset(dyn, 0xFF, shmem);
+        if (dyn) memset(dyn, fill_byte(), shmem);
         run_block(nt);
       }
   g_cur = nullptr;
@@ -294,9 +300,9 @@ void launch_(const std::function<void()>& body, dim3 grid, dim3 block, size_t sh
 
 using namespace emu;
 
-hipError_t hipMalloc(void** p, size_t n) { *p = galloc(n, 0xFF); return *p ? hipSuccess : hipErrorOutOfMemory; }
+hipError_t hipMalloc(void** p, size_t n) { *p = galloc(n, fill_byte()); return *p ? hipSuccess : hipErrorOutOfMemory; }
 hipError_t hipFree(void* p) { return gfree(p); }
-hipError_t hipHostMalloc(void** p, size_t n, unsigned) { *p = galloc(n, 0xFF); return *p ? hipSuccess : hipErrorOutOfMemory; }
+hipError_t hipHostMalloc(void** p, size_t n, unsigned) { *p = galloc(n, fill_byte()); return *p ? hipSuccess : hipErrorOutOfMemory; }
 hipError_t hipHostFree(void* p) { return gfree(p); }
 hipError_t hipHostGetDevicePointer(void** d, void* h, unsigned) { *d = h; return hipSuccess; }
 hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { if (n) memmove(d, s, n); return hipSuccess; }
