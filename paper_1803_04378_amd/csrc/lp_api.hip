@@ -350,7 +350,8 @@ std::vector<IterKernel> iteration_kernels(const lp_problem* p, int K) {
     return out;
   }
   for (int k = 0; k < K; ++k) {
-    out.push_back({k == 0 ? price_kernel() : price_fin_kernel(), p->price_grid, kPriceBlock, price_lds_bytes(p->ld),
+    const bool nt = p->d.a_nt != 0;
+    out.push_back({k == 0 ? price_kernel(nt) : price_fin_kernel(nt), p->price_grid, kPriceBlock, price_lds_bytes(p->ld),
                    k == 0 ? kKindPrice : kKindPriceFin});
     out.push_back(upd);
   }
@@ -574,8 +575,8 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
     p->num_cu = prop.multiProcessorCount;
   }
   int upd_block = 0;
-  // Compact columns for the FP64 form on rows long enough for the sparse-column update.
-  bool cmode = !mixed && compact_columns(ld);
+  // Compact columns on rows long enough for the sparse-column update.
+  bool cmode = compact_columns(ld);
   if ((rc = iteration_grids(m, n, p->num_cu, cmode, &p->price_grid, &p->update_grid, &upd_block)) != LP_OK)
     return bail(rc);
   p->reinv_period = o.reinv_period >= 0 ? o.reinv_period : (mixed ? 64 : 0);
@@ -679,6 +680,7 @@ int create_common(lp_problem** out, int32_t m, int32_t n, const double* A, const
   p->d.m = m;
   p->d.n = n;
   p->d.cmode = cmode ? 1 : 0;
+  p->d.a_nt = price_nt(ld, n) ? 1 : 0;
   p->d.upd_block = upd_block;
   p->d.price_grid = p->price_grid;
   p->d.update_grid = p->update_grid;
@@ -1370,6 +1372,7 @@ int lp_solve_device_noalloc(int32_t m, int32_t n, const double* A_colmajor, cons
   d.m = m;
   d.n = n;
   d.ld = (int32_t)round_up(m, 8);
+  d.a_nt = price_nt(d.ld, n) ? 1 : 0;
   d.upd_block = upd_block;
   d.row_lo = 0;
   d.row_hi = m;

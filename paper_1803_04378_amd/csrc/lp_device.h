@@ -7,7 +7,7 @@
 //   W0, W1, rho ld  W = chat_B^T B^-1 (top row of the Figure 1 tableau, two copies: one is
 //                   read while the next is written), rho = pivot row / alpha_r
 //   dlist, inD      m int32 each: the columns of B^-1 that may differ from unit vectors
-//   Bc     m x ld   row-major, FP64 form with ld >= 1024 only: column a holds column dlist[a]
+//   Bc     m x ld   row-major, rows with ld >= 1024 only: column a holds column dlist[a]
 //                   of B^-1 (a < |D|; zero beyond), so that the update and FTRAN read a row's
 //                   entries on D contiguously; rho_c (ld) is rho at those columns
 //   xB, alpha[2]    m
@@ -183,13 +183,14 @@ struct DevLP {
   // Out-of-core panel mode: device copy of row r of B^-1 for the pricing kernel (nullptr:
   // row r is read from Binv).
   const double* rowsrc;
-  // Compact columns (FP64 form, ld >= kSparseMinLd): B^-1 lives in Bc (column a = column
+  // Compact columns (ld >= kSparseMinLd, both precision forms): B^-1 lives in Bc (column a = column
   // dlist[a], zero for a >= |D|; the columns outside D are the unit vectors e_p of the rows
   // p holding their slacks, never stored), rho_c[a] = rho at column dlist[a].  Binv is then
   // brought up to date only on request (k_materialize), for the steps that read B^-1 by
   // its own columns: the tableau read-back, the phase switch, the reinversion.
   int32_t cmode;
-  int32_t pad3;
+  // The pricing kernels read A' with non-temporal loads (it exceeds the last-level cache).
+  int32_t a_nt;
   double* Bc;
   double* rho_c;
 };
@@ -213,7 +214,7 @@ constexpr int kUpdateStageMaxLd = 9792;
 __host__ __device__ __forceinline__ bool sparse_columns(int nD, int ld) {
   return ld >= kSparseMinLd && nD * 8 <= ld;
 }
-// The FP64 form with compact columns sums over D in D order at any |D| (k_update_c); the
+// With compact columns the update sums over D in D order at any |D| (k_update_c); the
 // batched solver, whose results equal lp_solve's bit for bit, takes the same rule.
 __host__ __device__ __forceinline__ bool compact_columns(int ld) { return ld >= kSparseMinLd; }
 
@@ -258,9 +259,13 @@ hipError_t launch_arm(Ctrl* ctl, int64_t max_iter, hipStream_t s);
 hipError_t launch_solution(const DevLP& lp, const double* c, double ysign, double* x, double* y, double* objective,
                            hipStream_t s);
 // Kernel entry points for explicit graph construction.
-const void* price_kernel();
+const void* price_kernel(bool nt);
 // k_finish fused with the next k_price (iterations after the first of a launch sequence).
-const void* price_fin_kernel();
+const void* price_fin_kernel(bool nt);
+// Whether an ld x n A' is read with non-temporal loads by the pricing kernels: when it is
+// larger than the device's last-level cache (the 256 MB MALL of MI355X).
+constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;
+bool price_nt(int ld, int n);
 const void* update_kernel(int ld);
 const void* update_kernel_for_block(int block);
 // the update kernel an LP launches: k_update_c with compact columns, else by its block

@@ -113,7 +113,10 @@ __device__ FinishOut finish_step(const DevLP& lp, const FinishIn& in, double pth
 // k_update's partials (finish_step, in every workgroup).  Its bookkeeping may or may not
 // be visible to a workgroup yet, so the entering variable counts as basic and the leaving
 // one as nonbasic (and tabu) whatever pos and tabu_until read.
-template <bool FUSED>
+// NT: A' is read with non-temporal loads (it does not fit the 256 MB last-level cache, so
+// lines kept would be evicted before the next pass reads them); else with ordinary loads,
+// which let A' stay in that cache from one pricing pass to the next.
+template <bool FUSED, bool NT>
 __device__ __forceinline__ void price_pass(const DevLP& lp, double2* s_w2) {
   __shared__ double red_d[2 * (kPriceBlock / 64)];
   __shared__ int red_j[2 * (kPriceBlock / 64)];
@@ -182,7 +185,7 @@ __device__ __forceinline__ void price_pass(const DevLP& lp, double2* s_w2) {
   double2 v[kBatch];
   const bool pre = gw < n;
   if (pre) {
-    if (kStreamA) load_batch_nt(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
+    if (NT) load_batch_nt(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
     else load_batch(reinterpret_cast<const double2*>(lp.A + (size_t)gw * lp.ld), lane, ld2, v);
   }
   if (FUSED) asm volatile("" ::: "memory");  // compiler-only: all of the above is requested first
@@ -302,7 +305,7 @@ __device__ __forceinline__ void price_pass(const DevLP& lp, double2* s_w2) {
     }
     const bool first = c == 0;
     if (pos >= 0) continue;
-    const double s = wave_dot<kStreamA>(reinterpret_cast<const double2*>(lp.A + (size_t)j * lp.ld), s_w2, ld2,
+    const double s = wave_dot<NT>(reinterpret_cast<const double2*>(lp.A + (size_t)j * lp.ld), s_w2, ld2,
                                         lane, v, first && pre);
     const double d = ch - s;
     if (d < neg_eps) {
@@ -365,9 +368,10 @@ __device__ __forceinline__ void price_pass(const DevLP& lp, double2* s_w2) {
   }
 }
 
+template <bool NT>
 __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
   extern __shared__ double2 s_w2[];
-  price_pass<false>(lp, s_w2);
+  price_pass<false, NT>(lp, s_w2);
 }
 
 // The ratio-test finish of the pending iteration (k_finish's work, in every workgroup)
@@ -375,9 +379,10 @@ __global__ __launch_bounds__(kPriceBlock) void k_price(DevLP lp) {
 // overlap the first batch of A'.
 // Held to k_price's register budget (six waves per SIMD), so that the grid sized for
 // k_price stays resident in one round.
+template <bool NT>
 __global__ __launch_bounds__(kPriceBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_price_fin(DevLP lp) {
   extern __shared__ double2 s_w2[];
-  price_pass<true>(lp, s_w2);
+  price_pass<true, NT>(lp, s_w2);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -853,7 +858,7 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
 }
 
 // ---------------------------------------------------------------------------------------
-// k_update with compact columns (FP64 form, ld >= kSparseMinLd): the steps and the
+// k_update with compact columns (ld >= kSparseMinLd): the steps and the
 // arithmetic of k_update's sparse-column pass at any length of D.  A row's entries on D
 // are contiguous in Bc instead of scattered over a row of Binv, and rho comes compact
 // (rho_c, formed by the pricing kernel): this wavefront's entries of its first row, of
@@ -887,6 +892,7 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
   const int64_t t = ctl->t;
   const int64_t max_iter = ctl->max_iter;
   const double theta = ctl->theta;
+  const int fb = ctl->fb;
   const int bpend = ctl->bpend, q_pend = ctl->q_pend;
   const int pk = min(tid, lp.price_grid - 1);
   double pd0 = lp.part_d[2 * pk], pd1 = lp.part_d[2 * pk + 1];
@@ -912,46 +918,77 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
       }
     }
   }
+  double sd = __builtin_inf();
+  int sj = INT_MAX;
+  if (lp.mixed) {
+    const int w = min(lane, lp.sl_k - 1);
+    sd = lp.sl_d[w];
+    sj = lp.sl_j[w];
+  }
   asm volatile("" ::: "memory");  // compiler-only: every request above is issued first
   if (tid >= lp.price_grid) {
     pd0 = pd1 = __builtin_inf();
     pj0 = pj1 = INT_MAX;
   }
 
-  // Step 4 decision from the pricing partials (every workgroup reaches the same q).
-  double da = pd0, df = pd1;
-  int ja = pj0, jf = pj1;
-  for (int k = tid + B; k < lp.price_grid; k += B) {
-    const double d0 = lp.part_d[2 * k], d1 = lp.part_d[2 * k + 1];
-    const int j0 = lp.part_j[2 * k], j1 = lp.part_j[2 * k + 1];
-    if (lex_less(d0, j0, da, ja)) {
-      da = d0;
-      ja = j0;
+  // Step 4 decision (every workgroup reaches the same q): in the mixed form from the
+  // re-priced shortlist (none improving: the fallback verdict), else, and in the mixed
+  // form's FP64 pass, from the pricing partials.  As in k_update.
+  double da = __builtin_inf(), df = __builtin_inf();
+  int ja = INT_MAX, jf = INT_MAX;
+  bool from_shortlist = false;
+  const bool use_parts = !lp.mixed || fb;
+  if (lp.mixed && !fb) {
+    if (!(lane < lp.sl_k && sj != INT_MAX && sd < -lp.eps_d)) {
+      sd = __builtin_inf();
+      sj = INT_MAX;
     }
-    if (lex_less(d1, j1, df, jf)) {
-      df = d1;
-      jf = j1;
+    wave_lexmin(sd, sj);
+    df = sd;
+    jf = sj;
+    from_shortlist = jf != INT_MAX;
+    da = df;
+    ja = jf;
+  }
+  if (use_parts) {
+    da = pd0;
+    df = pd1;
+    ja = pj0;
+    jf = pj1;
+    for (int k = tid + B; k < lp.price_grid; k += B) {
+      const double d0 = lp.part_d[2 * k], d1 = lp.part_d[2 * k + 1];
+      const int j0 = lp.part_j[2 * k], j1 = lp.part_j[2 * k + 1];
+      if (lex_less(d0, j0, da, ja)) {
+        da = d0;
+        ja = j0;
+      }
+      if (lex_less(d1, j1, df, jf)) {
+        df = d1;
+        jf = j1;
+      }
     }
+    wave_lexmin(da, ja);
+    wave_lexmin(df, jf);
+    if (lane == 0) {
+      red_d[wave] = da;
+      red_j[wave] = ja;
+      red_d[waves + wave] = df;
+      red_j[waves + wave] = jf;
+    }
+    __syncthreads();
+    da = lane < waves ? red_d[lane] : __builtin_inf();
+    ja = lane < waves ? red_j[lane] : INT_MAX;
+    df = lane < waves ? red_d[waves + lane] : __builtin_inf();
+    jf = lane < waves ? red_j[waves + lane] : INT_MAX;
+    wave_lexmin(da, ja);  // every wave reduces the same values: no second exchange needed
+    wave_lexmin(df, jf);
   }
-  wave_lexmin(da, ja);
-  wave_lexmin(df, jf);
-  if (lane == 0) {
-    red_d[wave] = da;
-    red_j[wave] = ja;
-    red_d[waves + wave] = df;
-    red_j[waves + wave] = jf;
-  }
-  __syncthreads();
-  da = lane < waves ? red_d[lane] : __builtin_inf();
-  ja = lane < waves ? red_j[lane] : INT_MAX;
-  df = lane < waves ? red_d[waves + lane] : __builtin_inf();
-  jf = lane < waves ? red_j[waves + lane] : INT_MAX;
-  wave_lexmin(da, ja);
-  wave_lexmin(df, jf);
   if (status != kStatusRunning) return;
   int verdict = kStatusRunning, q = -1, flags = 0;
   double dq = 0.0;
-  if (ja == INT_MAX) {
+  if (!use_parts && !from_shortlist) {
+    verdict = kVerdictFallback;
+  } else if (ja == INT_MAX) {
     verdict = kStatusOptimal;
   } else if (t >= max_iter) {
     verdict = kStatusIterLimit;
@@ -982,8 +1019,12 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
     cw->snap_nsb = cw->nsb;
     cw->snap_nL = cw->nL;
     cw->snap_cur = cur;
-    cw->price_cols += n - cw->nsb;
-    cw->price_launches += 1;
+    if (lp.mixed && !fb) cw->price32_launches += 1;
+    if (use_parts) {
+      cw->price_cols += n - cw->nsb;
+      cw->price_launches += 1;
+      if (lp.mixed) cw->full_prices += 1;
+    }
     if (r >= 0) cw->wcur ^= 1;  // pricing stored W_new: it is the current top row now
     cw->verdict = verdict;
     cw->q = q;
@@ -1026,7 +1067,7 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
     int nz = 0;
     if (r >= 0)
       for (int a = tid; a < nD; a += B) nz += lp.rho_c[a] != 0.0 ? 1 : 0;
-    nz = block_sum_int<B>(nz, red_j);
+    nz = block_sum_int<B>(nz, red_j);  // (its first barrier: every wave has read red_j)
     if (tid == 0) lp.ctrl->update_bytes += 8 * ((int64_t)(m - 1) * nD + (int64_t)m * nz) + 16 * (int64_t)m;
   }
   __syncthreads();  // a_q is in LDS
@@ -1864,8 +1905,13 @@ __global__ void k_check_finite(const double* __restrict__ x, int64_t count, doub
 }
 
 // ---------------------------------------------------------------------------------------
-const void* price_kernel() { return reinterpret_cast<const void*>(&k_price); }
-const void* price_fin_kernel() { return reinterpret_cast<const void*>(&k_price_fin); }
+const void* price_kernel(bool nt) {
+  return nt ? reinterpret_cast<const void*>(&k_price<true>) : reinterpret_cast<const void*>(&k_price<false>);
+}
+const void* price_fin_kernel(bool nt) {
+  return nt ? reinterpret_cast<const void*>(&k_price_fin<true>) : reinterpret_cast<const void*>(&k_price_fin<false>);
+}
+bool price_nt(int ld, int n) { return sizeof(double) * (size_t)ld * (size_t)n > kLastLevelCacheBytes; }
 // k_update's workgroup size for a row stride ld: kUpdateBlock threads, or twice that where
 // the staging in LDS admits only one such workgroup per CU and one of the larger ones
 // fits (it keeps twice the wavefronts in flight); -kUpdateBlock: k_update_wide, for rows
@@ -1916,12 +1962,14 @@ size_t update_lds_for_block(int block, int ld) { return block > 0 ? update_lds_b
 size_t compact_lds_bytes(int ld) { return sizeof(double) * (size_t)ld; }
 
 hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld, bool cmode) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_price),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)price_lds_bytes(ld));
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_price_fin), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)price_lds_bytes(ld));
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  for (const bool nt : {false, true}) {
+    e = hipFuncSetAttribute(price_kernel(nt), hipFuncAttributeMaxDynamicSharedMemorySize, (int)price_lds_bytes(ld));
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(price_fin_kernel(nt), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)price_lds_bytes(ld));
+    if (e != hipSuccess) return e;
+  }
   const int blk = update_block(ld);
   if (blk == 0) return hipErrorInvalidValue;
   const int lds = (int)update_lds_for_block(blk, ld);
@@ -1932,13 +1980,17 @@ hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld, bool 
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)compact_lds_bytes(ld));
     if (e != hipSuccess) return e;
   }
-  // The pricing grid serves both pricing kernels: size it for the one that fits fewer.
-  int fin_per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(price_per_cu, k_price, kPriceBlock, price_lds_bytes(ld));
+  // The pricing grid serves every pricing kernel: size it for the one that fits fewest.
+  int occ[4] = {0, 0, 0, 0};
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], k_price<false>, kPriceBlock, price_lds_bytes(ld));
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], k_price<true>, kPriceBlock, price_lds_bytes(ld));
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], k_price_fin<false>, kPriceBlock, price_lds_bytes(ld));
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[3], k_price_fin<true>, kPriceBlock, price_lds_bytes(ld));
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&fin_per_cu, k_price_fin, kPriceBlock, price_lds_bytes(ld));
-  if (e != hipSuccess) return e;
-  *price_per_cu = std::min(*price_per_cu, fin_per_cu);
+  *price_per_cu = std::min(std::min(occ[0], occ[1]), std::min(occ[2], occ[3]));
   if (cmode)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(update_per_cu, k_update_c<kUpdateBlock>, kUpdateBlock,
                                                         compact_lds_bytes(ld));
@@ -1958,7 +2010,10 @@ hipError_t launch_init(const DevLP& lp, const double* b, const double* c, double
 }
 
 hipError_t launch_price(const DevLP& lp, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_price, dim3(grid), dim3(kPriceBlock), price_lds_bytes(lp.ld), s, lp);
+  if (lp.a_nt)
+    hipLaunchKernelGGL(k_price<true>, dim3(grid), dim3(kPriceBlock), price_lds_bytes(lp.ld), s, lp);
+  else
+    hipLaunchKernelGGL(k_price<false>, dim3(grid), dim3(kPriceBlock), price_lds_bytes(lp.ld), s, lp);
   return hipGetLastError();
 }
 

@@ -207,7 +207,34 @@ __global__ __launch_bounds__(kPrice32Block) void k_price32(DevLP lp) {
   // Step 8 on the top row for the pending pivot, as in k_price: W_new = W + d_q rho is
   // formed in FP64 and staged rounded to FP32; workgroup 0 stores rho and W_new.
   float* s_w = reinterpret_cast<float*>(s_w4);
-  if (r >= 0) {
+  if (r >= 0 && lp.cmode) {
+    // Compact columns (as in k_price): rho is zero outside D and row r of Bc holds it on D
+    // (at the index the pivot appended, the unit column's 1, not stored yet); W_new equals
+    // W elsewhere.  Workgroup 0 stores W_new (a copy of W, then the entries on D) and rho_c.
+    const double* Wold = wc ? lp.W1 : lp.W0;
+    double* Wnew = wc ? lp.W0 : lp.W1;
+    const double ar = lp.ctrl->ar;
+    const double dq = lp.ctrl->pdq;
+    const int nDn = lp.ctrl->nD, a_app = lp.ctrl->dapp;
+    const double* crow = lp.Bc + (size_t)r * lp.ld;
+    const bool writer = blockIdx.x == 0;
+    for (int k = threadIdx.x; k < lp.ld; k += kPrice32Block) {
+      const double w = Wold[k];
+      s_w[k] = (float)w;
+      if (writer) Wnew[k] = w;
+    }
+    __syncthreads();  // (the copy of W is stored before the entries on D overwrite it)
+    for (int a = threadIdx.x; a < nDn; a += kPrice32Block) {
+      const int j = lp.dlist[a];
+      const double rr = (a == a_app ? 1.0 : crow[a]) / ar;
+      const double wn = fma(dq, rr, Wold[j]);
+      s_w[j] = (float)wn;
+      if (writer) {
+        Wnew[j] = wn;
+        lp.rho_c[a] = rr;
+      }
+    }
+  } else if (r >= 0) {
     const double2* Wold = reinterpret_cast<const double2*>(wc ? lp.W1 : lp.W0);
     double2* Wnew = reinterpret_cast<double2*>(wc ? lp.W0 : lp.W1);
     const double ar = lp.ctrl->ar;

@@ -5,8 +5,10 @@ static void call_devlp(const void* fn, void* arg) {
 extern const char* (*emu_kernel_name)(const void* fn);
 static const char* kname(const void* fn) {
   using namespace lpgpu;
-  if (fn == price_kernel()) return "k_price";
-  if (fn == price_fin_kernel()) return "k_price_fin";
+  if (fn == price_kernel(false)) return "k_price<false>";
+  if (fn == price_kernel(true)) return "k_price<true>";
+  if (fn == price_fin_kernel(false)) return "k_price_fin<false>";
+  if (fn == price_fin_kernel(true)) return "k_price_fin<true>";
   if (fn == finish_kernel()) return "k_finish";
   if (fn == update_kernel_for_block(512)) return "k_update<512>";
   if (fn == update_kernel_for_block(1024)) return "k_update<1024>";

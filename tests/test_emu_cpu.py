@@ -118,7 +118,7 @@ def test_compact_columns_follow_oracle(emu_lib):
             B = np.hstack([A, np.eye(m)])[:, basis]
             err = np.abs(Binv @ B - np.eye(m)).max()
             assert err < 1e-9, err
-        A, b, c = lpgen.diagonal_lp(0, 1032, 560)
+        A, b, c = lpgen.diagonal_lp(0, 1032, 520)
         ref = oracle.solve(A, b, c)
         with lpg.LP(A, b, c, iters_per_sync=64) as p:
             st = p.solve(); piv = p.pivots(); sol = p.solution()
@@ -215,4 +215,29 @@ def test_front_guards_after_a_stop(emu_lib):
         assert abs(sol["objective"] - ref.objective) <= 1e-9 * abs(ref.objective)
         print("ok")
     """, env={"EMU_GUARD_FRONT": "1"})
+    assert "ok" in out
+
+
+def test_compact_columns_mixed_form(emu_lib):
+    """The mixed form on compact columns (rows of 1024 and more): FP32 screening forms W_new
+    from row r of Bc; without reinversion the pivots are the oracle's, with reinversion
+    (B^-1 written out, reinverted, compacted) the objective is the oracle's and the tableau
+    read-back is B^-1 to rounding."""
+    out = _run(emu_lib, """
+        A, b, c = lpgen.dense_lp(3, 1024, 200)
+        ref = oracle.solve(A, b, c)
+        with lpg.LP(A, b, c, precision="mixed", reinv_period=0, iters_per_sync=8) as p:
+            st = p.solve(); piv = p.pivots()
+        assert st == ref.status and same_log(piv, ref)
+        A, b, c = lpgen.diagonal_lp(1, 1032, 300)
+        ref = oracle.solve(A, b, c)
+        with lpg.LP(A, b, c, precision="mixed", reinv_period=16, iters_per_sync=4) as p:
+            st = p.solve(); sol = p.solution(); s = p.stats()
+            assert st == ref.status and s["reinversions"] > 0 and s["reinv_failed"] == 0
+            assert abs(sol["objective"] - ref.objective) <= 1e-9 * abs(ref.objective)
+            Binv = p.tableau()[0]
+        B = np.hstack([A, np.eye(A.shape[0])])[:, sol["basis"]]
+        assert np.abs(Binv @ B - np.eye(A.shape[0])).max() < 1e-9
+        print("ok")
+    """, timeout=900)
     assert "ok" in out
