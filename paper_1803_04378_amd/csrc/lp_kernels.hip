@@ -868,7 +868,6 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
 template <int B>
 __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
   constexpr int waves = B / 64;
-  extern __shared__ double2 smem2[];  // a_q
   __shared__ double red_d[2 * waves];
   __shared__ int red_j[2 * waves];
   __shared__ double s_rt[waves * kMaxRowsPerWave];
@@ -1044,23 +1043,24 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
   const double* __restrict__ al_p = cur ? lp.alpha1 : lp.alpha0;  // pending pivot's alpha
   double* __restrict__ al_n = cur ? lp.alpha0 : lp.alpha1;        // FTRAN result for q
   const double eps_p = lp.eps_p, eps_z = lp.eps_z;
+  // a_q at this lane's entries of D, gathered from the column (no staging, no barrier); a
+  // slack's column is the unit vector e_{q-n}
   const bool q_col = q >= 0 && q < n;
-  const double2* aq2 = reinterpret_cast<const double2*>(lp.A + (size_t)(q_col ? q : 0) * ld);
-  Hold5 hold;
-  if (q_col) hold_load<B>(hold, aq2, tid, ld2);
+  const double* colq = lp.A + (size_t)(q_col ? q : 0) * ld;
+  const int e = q - n;
+  double aq[kGather];
+#pragma unroll
+  for (int u = 0; u < kGather; ++u) {
+    const int a = lane + 64 * u;
+    aq[u] = 0.0;
+    if (q >= 0 && a < nD) aq[u] = q_col ? colq[dj[u]] : (dj[u] == e ? 1.0 : 0.0);
+  }
+  auto aq_at = [&](int j) { return q_col ? colq[j] : (j == e ? 1.0 : 0.0); };
   // whether the first row's basic variable is a slack outside D (its column of B^-1 is a
   // unit vector): the FTRAN adds its unit term, and the finish needs it for the leaving
   // variable
   int in0 = 1;
   if (gw < m && bv0 >= n) in0 = lp.inD[bv0 - n];
-  double2* s_a = smem2;
-  const double* s_ad = reinterpret_cast<const double*>(s_a);
-  if (q_col) {
-    hold_store<B>(hold, s_a, aq2, tid, ld2);
-  } else if (q >= 0) {
-    const int e = q - n;
-    for (int k = tid; k < ld2; k += B) s_a[k] = make_double2(2 * k == e ? 1.0 : 0.0, 2 * k + 1 == e ? 1.0 : 0.0);
-  }
   if (blockIdx.x == 0) {
     // bytes: the D entries of every row but r read, the changed ones written in every row,
     // one unit lookup (basis, membership, a_q entry) per row
@@ -1070,7 +1070,6 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
     nz = block_sum_int<B>(nz, red_j);  // (its first barrier: every wave has read red_j)
     if (tid == 0) lp.ctrl->update_bytes += 8 * ((int64_t)(m - 1) * nD + (int64_t)m * nz) + 16 * (int64_t)m;
   }
-  __syncthreads();  // a_q is in LDS
   int c = 0;
   for (int i = gw; i < m; i += nw, ++c) {
     double* row = lp.Bc + (size_t)i * ld;
@@ -1094,6 +1093,9 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
     }
     const bool isr = i == r;
     const double na = (r >= 0 && !isr) ? -alp : 0.0;
+    // the unit column of this row's basic slack, when it is not in D
+    const bool unit = q >= 0 && bv >= n && !in;
+    const double au = unit ? aq_at(bv - n) : 0.0;
     double acc = 0.0;
 #pragma unroll
     for (int u = 0; u < kGather; ++u) {
@@ -1105,7 +1107,7 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
           val = isr ? rv : fma(na, rv, val);  // row r := rho (zero wherever rho is zero)
           if (rv != 0.0) row[a] = val;
         }
-        if (q >= 0) acc = fma(val, s_ad[dj[u]], acc);
+        if (q >= 0) acc = fma(val, aq[u], acc);
       }
     }
     for (int a = lane + 64 * kGather; a < nD; a += 64) {
@@ -1115,7 +1117,7 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
         val = isr ? rv : fma(na, rv, val);
         if (rv != 0.0) row[a] = val;
       }
-      if (q >= 0) acc = fma(val, s_ad[lp.dlist[a]], acc);
+      if (q >= 0) acc = fma(val, aq_at(lp.dlist[a]), acc);
     }
     if (r >= 0) {
       x = isr ? theta : fma(na, theta, x);
@@ -1124,8 +1126,7 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
     }
     if (q >= 0) {
       acc = wave_sum(acc);
-      // the unit column of this row's basic slack, when it is not in D
-      if (bv >= n && !in) acc += s_ad[bv - n];
+      if (unit) acc += au;
       double rt = __builtin_inf(), tau = __builtin_inf();
       if (acc > eps_p) {
         const double xp = fmax(x, 0.0);
@@ -1958,8 +1959,8 @@ size_t update_lds_bytes(int ld) {
   return 2 * sizeof(double) * (size_t)ld + (ld >= kSparseMinLd ? sizeof(int) * (size_t)(ld / 8) : 0);
 }
 size_t update_lds_for_block(int block, int ld) { return block > 0 ? update_lds_bytes(ld) : wide_lds_bytes(ld); }
-// k_update_c stages a_q only
-size_t compact_lds_bytes(int ld) { return sizeof(double) * (size_t)ld; }
+// k_update_c stages nothing in dynamic LDS
+size_t compact_lds_bytes(int) { return 0; }
 
 hipError_t kernel_occupancy(int* price_per_cu, int* update_per_cu, int ld, bool cmode) {
   hipError_t e = hipSuccess;

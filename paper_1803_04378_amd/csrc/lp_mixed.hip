@@ -48,19 +48,26 @@ __device__ __forceinline__ float wave_sum32(float a) {
   return a;
 }
 
+// One batch of x (float4 elements k0, k0 + 64, ...), streamed.
+__device__ __forceinline__ void load_batch32(const float4* __restrict__ x, int k0, int n4, float4 (&v)[kBatch]) {
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u) {
+    const int k = k0 + 64 * u;
+    if (k < n4) {
+      const v4f t = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(x + k));
+      v[u] = make_float4(t.x, t.y, t.z, t.w);
+    }
+  }
+}
+
 // FP32 dot(x, y), x streamed from HBM, y in LDS; lane l owns float4 elements l, l+64, ...
-__device__ __forceinline__ float wave_dot32(const float4* __restrict__ x, const float4* y, int n4, int lane) {
+// pre: v already holds the first batch.
+__device__ __forceinline__ float wave_dot32(const float4* __restrict__ x, const float4* y, int n4, int lane,
+                                            float4 (&v)[kBatch], bool pre) {
   float acc = 0.f;
   for (int k0 = lane; k0 < n4; k0 += 64 * kBatch) {
-    float4 v[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int k = k0 + 64 * u;
-      if (k < n4) {
-        const v4f t = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(x + k));
-        v[u] = make_float4(t.x, t.y, t.z, t.w);
-      }
-    }
+    if (!pre) load_batch32(x, k0, n4, v);
+    pre = false;
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const int k = k0 + 64 * u;
@@ -204,6 +211,18 @@ __global__ __launch_bounds__(kPrice32Block) void k_price32(DevLP lp) {
   const int gw = blockIdx.x * waves + wave;
   const int nw = gridDim.x * waves;
 
+  // Requested before the top row is formed (as in k_price): the state of this wave's
+  // columns (lane c holds column gw + c nw).  (Holding a first batch of A' across the
+  // staging would cost more registers than this kernel's occupancy allows.)
+  const int jl = gw + lane * nw;
+  int c_pos = 0, c_tabu = 0;
+  double c_chat = 0.0;
+  if (jl < N) {
+    c_pos = lp.pos[jl];
+    c_tabu = lp.tabu_until[jl];
+    c_chat = lp.chat[jl];
+  }
+
   // Step 8 on the top row for the pending pivot, as in k_price: W_new = W + d_q rho is
   // formed in FP64 and staged rounded to FP32; workgroup 0 stores rho and W_new.
   float* s_w = reinterpret_cast<float*>(s_w4);
@@ -270,14 +289,27 @@ __global__ __launch_bounds__(kPrice32Block) void k_price32(DevLP lp) {
 
   uint64_t key = kNoKey;  // lane l < S: the wave's l-th smallest key
   uint64_t worst = kNoKey;
-  for (int j = gw; j < N; j += nw) {
-    if (lp.pos[j] >= 0 || lp.tabu_until[j] >= t) continue;
+  int c = 0;
+  for (int j = gw; j < N; j += nw, ++c) {
+    int pos, tabu;
+    double ch;
+    if (c < 64) {
+      pos = __shfl(c_pos, c);
+      tabu = __shfl(c_tabu, c);
+      ch = __shfl(c_chat, c);
+    } else {
+      pos = lp.pos[j];
+      tabu = lp.tabu_until[j];
+      ch = lp.chat[j];
+    }
+    if (pos >= 0 || tabu >= t) continue;
     float d;
     if (j < n) {
-      const float s = wave_dot32(reinterpret_cast<const float4*>(lp.A32 + (size_t)j * lp.ld), s_w4, n4, lane);
-      d = (float)lp.chat[j] - s;
+      float4 v[kBatch];
+      const float s = wave_dot32(reinterpret_cast<const float4*>(lp.A32 + (size_t)j * lp.ld), s_w4, n4, lane, v, false);
+      d = (float)ch - s;
     } else {
-      d = (float)lp.chat[j] - s_w[j - n];
+      d = (float)ch - s_w[j - n];
     }
     if (d != d) continue;
     const uint64_t kn = make_key(d, j);

@@ -333,8 +333,8 @@ hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipS
 hipError_t emu_occupancy(int* out, const char* name, int block, size_t dyn) {
   struct K { const char* n; int lds, vgpr; };
   static const K t[] = {{"k_update_wide<kUpdateBlock>", 2256, 122}, {"k_update<2 * kUpdateBlock>", 4496, 107},
-                        {"k_update<kUpdateBlock>", 2256, 105}, {"k_price32", 2496, 60}, {"k_price<false>", 192, 76},
-                        {"k_price<true>", 192, 76}, {"k_price_fin<false>", 448, 79}, {"k_price_fin<true>", 448, 79}, {"k_update_c<kUpdateBlock>", 2256, 115},
+                        {"k_update<kUpdateBlock>", 2256, 105}, {"k_price32", 2496, 62}, {"k_price<false>", 192, 76},
+                        {"k_price<true>", 192, 76}, {"k_price_fin<false>", 448, 79}, {"k_price_fin<true>", 448, 79}, {"k_update_c<kUpdateBlock>", 2248, 119},
                         {"k_batch<true>", 112, 195}, {"k_batch<false>", 112, 217}};
   const K* k = nullptr;
   for (const K& e : t) if (std::string(name) == e.n) { k = &e; break; }
