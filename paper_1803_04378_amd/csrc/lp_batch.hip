@@ -33,7 +33,7 @@ using namespace detail;
 namespace {
 
 #ifndef LPGPU_BATCH_SMALL
-#define LPGPU_BATCH_SMALL 4
+#define LPGPU_BATCH_SMALL 2
 #endif
 constexpr int kBatchSmall = LPGPU_BATCH_SMALL;
 // Pricing reads an LP's A' at every pivot.  Up to this many rows (ld) it is loaded
@@ -452,8 +452,12 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
   }
 }
 
+// Held to 128 VGPRs: four 256-thread workgroups per CU instead of two.  The solver is
+// bound by the latency of each LP's dependent reductions, so twice the LPs in flight pay
+// for the registers it then spills (4096-LP batch: 40.6 -> 30.1 ms; with 2 instead of 4
+// double2 per lane per load round, fewer spills: 29.3 ms).
 template <bool BLDS>
-__global__ __launch_bounds__(kBatchBlock) void k_batch(BatchDev bd) {
+__global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchDev bd) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ double xd[2 * kBatchWaves];
   __shared__ int xj[2 * kBatchWaves];

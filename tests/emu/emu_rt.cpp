@@ -335,7 +335,7 @@ hipError_t emu_occupancy(int* out, const char* name, int block, size_t dyn) {
   static const K t[] = {{"k_update_wide<kUpdateBlock>", 2256, 122}, {"k_update<2 * kUpdateBlock>", 4496, 107},
                         {"k_update<kUpdateBlock>", 2256, 105}, {"k_price32", 2496, 62}, {"k_price<false>", 192, 76},
                         {"k_price<true>", 192, 76}, {"k_price_fin<false>", 448, 79}, {"k_price_fin<true>", 448, 79}, {"k_update_c<kUpdateBlock>", 2248, 119},
-                        {"k_batch<true>", 112, 195}, {"k_batch<false>", 112, 217}};
+                        {"k_batch<true>", 112, 128}, {"k_batch<false>", 112, 128}};
   const K* k = nullptr;
   for (const K& e : t) if (std::string(name) == e.n) { k = &e; break; }
   if (!k) { fprintf(stderr, "emu: occupancy of unknown kernel %s\n", name); abort(); }
