@@ -137,7 +137,9 @@ def solve_leg(lpg, torch, dev, opts, reps=5):
 def mixed_leg(lpg, torch, m, n, seed, steps, stream, profile_only=False, reps=5):
     """Mixed-precision form on its own configuration (dense law, m x n): time to optimality
     against the FP64 path on the same GPU, objective error and KKT residuals against the
-    FP64 path's optimum, and a profiled stretch of iterations for the per-kernel split."""
+    FP64 path's optimum, the objective errors of both against the FP64 oracle's optimum
+    where its whole solve is stored, and a profiled stretch of iterations for the
+    per-kernel split."""
     import numpy as np
 
     import lpgen
@@ -190,6 +192,18 @@ def mixed_leg(lpg, torch, m, n, seed, steps, stream, profile_only=False, reps=5)
                                     primal=float(max(0.0, -slack.min(), -x.min())),
                                     dual=float(max(0.0, -red.min(), -y.min())),
                                     gap=float(abs(c @ x - b @ y)))
+        # against the FP64 oracle's optimum, stored with its whole solve by
+        # tests/golden/make_goldens.py (the default workload only)
+        gold = os.path.join(_ROOT, "tests", "golden", f"dense_m{m}_n{n}_s{seed}.json")
+        if os.path.exists(gold):
+            with open(gold) as f:
+                g = json.load(f)
+            go = g["objective"]
+            out["error_vs_oracle"] = dict(
+                oracle_objective=go, oracle_pivots=len(g["enter"]),
+                mixed_objective_rel=abs(sols["mixed"]["objective"] - go) / max(1.0, abs(go)),
+                fp64_objective_rel=abs(sols["fp64"]["objective"] - go) / max(1.0, abs(go)),
+                fp64_pivots_equal=sols["fp64"]["iterations"] == len(g["enter"]))
     with lpg.LP.from_torch(*dev, precision="mixed", profile=2, **opts) as lp:
         run_steps(lp, 40)
         torch.cuda.synchronize()
