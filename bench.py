@@ -253,7 +253,10 @@ def general_leg(lpg, torch, m, n, seed, stream, reps=3):
 
 def batch_leg(lpg, count, serial_sample):
     """Batched form: `count` LPs, m ~ U{16..256}, n = 2m, dense law with per-instance seeds,
-    solved in one persistent launch, against serial lp_solve calls on a sample of them."""
+    solved in one persistent launch, against serial lp_solve calls on a sample of them; and
+    the same batch generated in device memory (creation without the host -> device upload)."""
+    import numpy as np
+
     import lpgen
     lps = lpgen.batch_lps(0, count)
     t0 = time.perf_counter()
@@ -278,6 +281,18 @@ def batch_leg(lpg, count, serial_sample):
         bt2.solve()
         first_cached = time.perf_counter() - t0
         st2 = bt2.stats()
+    # the same batch generated in device memory (no host arrays, no upload): creation time,
+    # and its results against the uploaded batch's, bit for bit
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with lpg.Batch.dense(count, 0) as bg:
+        gen_create = time.perf_counter() - t0
+        bg.tune_load(table)
+        bg.solve()
+        stg = bg.stats()
+        rg = bg.results()
+    gen_same = all(np.array_equal(rg[k], res[k]) for k in ("status", "objective", "iterations"))
     iters = int(res["iterations"].sum())
     idx = list(range(0, count, max(1, count // serial_sample)))[:serial_sample]
     handles = [lpg.LP(*lps[i]) for i in idx]
@@ -301,6 +316,9 @@ def batch_leg(lpg, count, serial_sample):
                 lps_per_s_first_solve_from_table=round(count / first_cached, 1),
                 create_ms=round(create * 1e3, 3),
                 lps_per_s_with_upload=round(count / (create + st["solve_ms"] * 1e-3), 1),
+                create_ms_generated_on_device=round(gen_create * 1e3, 3),
+                lps_per_s_with_generation=round(count / (gen_create + stg["solve_ms"] * 1e-3), 1),
+                generated_equals_uploaded=bool(gen_same),
                 wall_ms=round(wall * 1e3, 3), pivots=iters, all_optimal=bool((res["status"] == 1).all()),
                 narrow_lps=st["narrow_lps"], wide_lps=st["wide_lps"], tune_ms=round(st["tune_ms"], 1),
                 serial_ms_per_lp=round(serial * 1e3, 4), serial_sample=len(handles),

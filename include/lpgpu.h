@@ -339,6 +339,21 @@ typedef struct lp_batch_stats {
 int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32_t *n, const double *const *A,
                     const double *const *b, const double *const *c, const lp_options *opt);
 
+/*
+ * A batch of `count` seeded synthetic LPs generated in device memory, for benchmarks and
+ * tests (no host arrays and no upload: the device writes every A', b and c itself).  With
+ * the counter-based hash h(s, k, i) = mix(mix(mix(s) ^ k) ^ i), mix the SplitMix64
+ * finaliser (Steele, Lea & Flood, OOPSLA 2014), u = (h >> 11) 2^-53 and U(a,b) = a + (b-a) u:
+ * LP i has m_i = m_lo + (h(seed, 6, i) mod (m_hi - m_lo + 1)) rows and n_i = 2 m_i columns,
+ * and with s_i = h(seed, 7, i), the dense law A'_rj = U(0,1) drawn at (s_i, 1, j m_i + r),
+ * b_r = U(1,10) at (s_i, 2, r), c_j = U(1,10) at (s_i, 3, j); maximised by default (*opt as
+ * in lp_batch_create).  The same bits as host arrays built by that definition.
+ * Errors: LP_ERR_ARG (count <= 0, m_lo < 1, m_hi < m_lo, an LP too large for the solver's
+ * LDS budget), LP_ERR_NOMEM, LP_ERR_DEVICE.
+ */
+int lp_batch_create_dense(lp_batch **out, int32_t count, uint64_t seed, int32_t m_lo, int32_t m_hi,
+                          const lp_options *opt);
+
 /* Solves every LP of the batch from its slack basis: one persistent launch for the LPs
  * whose B^-1 stays in HBM, then one for those that keep it in LDS (none by default on
  * mixed batches; see batch_binv_lds_m).  The first call with batch_small_m = -1 first times
@@ -356,6 +371,10 @@ int lp_batch_get(const lp_batch *bt, int32_t i, double *x, int32_t *basis, int32
                  int32_t *flags, int64_t capacity, int64_t *count);
 
 int lp_batch_get_stats(const lp_batch *bt, lp_batch_stats *s);
+
+/* The batch's sizes: m[i] rows and n[i] columns of LP i, arrays of `count` entries, either
+ * may be NULL (the sizes lp_batch_create_dense drew). */
+int lp_batch_get_sizes(const lp_batch *bt, int32_t *m, int32_t *n);
 
 /* NULL-safe. */
 void lp_batch_destroy(lp_batch *bt);

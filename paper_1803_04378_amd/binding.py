@@ -135,6 +135,9 @@ SIGNATURES = {
     "lp_error_string": (C.c_char_p, [C.c_int]),
     "lp_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, _IP, _IP, C.POINTER(_DP), C.POINTER(_DP),
                                   C.POINTER(_DP), C.POINTER(lp_options)]),
+    "lp_batch_create_dense": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_uint64, C.c_int32, C.c_int32,
+                                        C.POINTER(lp_options)]),
+    "lp_batch_get_sizes": (C.c_int, [_P, _IP, _IP]),
     "lp_batch_solve": (C.c_int, [_P]),
     "lp_batch_results": (C.c_int, [_P, _IP, _DP, _LP]),
     "lp_batch_get": (C.c_int, [_P, C.c_int32, _DP, _IP, _IP, _IP, _IP, C.c_int64, _LP]),
@@ -348,6 +351,22 @@ class Batch:
                                      C.byref(o)), "lp_batch_create")
         self._h = h
         self.count, self.m, self.n = cnt, ms, ns
+
+    @classmethod
+    def dense(cls, count, seed, m_lo=16, m_hi=256, sense="max", **opts):
+        """A batch of seeded dense LPs generated in device memory (lp_batch_create_dense)."""
+        o = default_options(sense=LP_MAX if sense == "max" else LP_MIN, **opts)
+        self = cls.__new__(cls)
+        h = _P()
+        _check(lib().lp_batch_create_dense(C.byref(h), int(count), int(seed) & ((1 << 64) - 1), int(m_lo), int(m_hi),
+                                           C.byref(o)), "lp_batch_create_dense")
+        self._h = h
+        ms = np.empty(count, dtype=np.int32)
+        ns = np.empty(count, dtype=np.int32)
+        _check(lib().lp_batch_get_sizes(h, ms.ctypes.data_as(_IP), ns.ctypes.data_as(_IP)), "lp_batch_get_sizes")
+        self._keep = None
+        self.count, self.m, self.n = int(count), ms, ns
+        return self
 
     def close(self):
         h = getattr(self, "_h", None)

@@ -64,6 +64,11 @@ __host__ __device__ inline size_t batch_lds_bytes_binv(int m, int n) {
 }
 // Launches k_batch<binv_lds>: B^-1 in the pooled HBM array, or in LDS.
 hipError_t launch_batch(const BatchDev& bd, int grid, size_t lds, bool binv_lds, hipStream_t s);
+// The dense law of lp_batch_create_dense into the pools: LP i (layout lps[i], per-LP seed
+// h(seed, 7, i)) gets A'_rj ~ U(0,1) at index j m + r, b_r ~ U(1,10), c_j ~ U(1,10), and zero
+// padding rows; one workgroup per LP.
+hipError_t launch_gen_batch(const BatchLP* lps, int32_t count, uint64_t seed, double* A, double* b, double* c,
+                            hipStream_t s);
 hipError_t batch_occupancy(int* per_cu, size_t lds, bool binv_lds);
 
 }  // namespace lpgpu

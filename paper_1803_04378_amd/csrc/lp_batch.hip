@@ -25,6 +25,7 @@
 
 #include "lp_batch.h"
 #include "lp_device.h"
+#include "lp_gen.h"
 #include "lp_wave.h"
 
 namespace lpgpu {
@@ -483,6 +484,31 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))
 hipError_t launch_batch(const BatchDev& bd, int grid, size_t lds, bool binv_lds, hipStream_t s) {
   if (binv_lds) hipLaunchKernelGGL(k_batch<true>, dim3(grid), dim3(kBatchBlock), lds, s, bd);
   else hipLaunchKernelGGL(k_batch<false>, dim3(grid), dim3(kBatchBlock), lds, s, bd);
+  return hipGetLastError();
+}
+
+// One workgroup per LP: its A' column by column (padding rows zero), then b and c.
+__global__ __launch_bounds__(256) void k_gen_batch(const BatchLP* __restrict__ lps, uint64_t seed,
+                                                    double* __restrict__ A, double* __restrict__ b,
+                                                    double* __restrict__ c) {
+  const BatchLP L = lps[blockIdx.x];
+  const uint64_t iseed = gen::hash(gen::stream_key(seed, gen::kStreamInst), blockIdx.x);
+  const uint64_t ka = gen::stream_key(iseed, gen::kStreamA), kb = gen::stream_key(iseed, gen::kStreamB),
+                 kc = gen::stream_key(iseed, gen::kStreamC);
+  const int m = L.m, n = L.n, ld = L.ld;
+  double* a = A + L.offA;
+  const size_t total = (size_t)ld * (n > 0 ? n : 1);
+  for (size_t k = threadIdx.x; k < total; k += 256) {
+    const int j = (int)(k / ld), r = (int)(k - (size_t)j * ld);
+    a[k] = (r < m && j < n) ? gen::uniform(ka, (uint64_t)j * m + r, 0.0, 1.0) : 0.0;
+  }
+  for (int r = threadIdx.x; r < m; r += 256) b[L.offb + r] = gen::uniform(kb, r, 1.0, 10.0);
+  for (int j = threadIdx.x; j < n; j += 256) c[L.offc + j] = gen::uniform(kc, j, 1.0, 10.0);
+}
+
+hipError_t launch_gen_batch(const BatchLP* lps, int32_t count, uint64_t seed, double* A, double* b, double* c,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_gen_batch, dim3(count), dim3(256), 0, s, lps, seed, A, b, c);
   return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@
 
 #include "lp_batch.h"
 #include "lp_device.h"
+#include "lp_gen.h"
 #include "lpgpu.h"
 
 using namespace lpgpu;
@@ -86,6 +87,7 @@ struct lp_batch {
   int4* d_items = nullptr;
   int32_t max_items = 0;
   size_t region = 0;  // LDS bytes per workgroup (B^-1 in HBM)
+  int64_t poolA = 0, poolb = 0, poolc = 0;  // doubles in the A', b and c pools
   int grid = 0, per_cu = 0, num_cu = 0;
   int small_m = -1;   // LPs with m <= small_m are solved one per wavefront (after tuning)
   std::vector<int> bucket_narrow;  // per bucket: 1 narrow, 0 wide, -1 untuned
@@ -413,31 +415,16 @@ int save_table(const lp_batch* p, const char* path) {
 
 extern "C" {
 
-int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32_t* n, const double* const* A,
-                    const double* const* b, const double* const* c, const lp_options* opt) try {
-  if (!out) return fail(LP_ERR_ARG, "out is NULL");
-  *out = nullptr;
-  if (count <= 0 || !m || !n || !A || !b || !c) return fail(LP_ERR_ARG, "empty batch or NULL array");
-  lp_options o;
-  lp_default_options(&o);
-  if (opt) o = *opt;
-  if (o.sense != LP_MIN && o.sense != LP_MAX) return fail(LP_ERR_ARG, "options.sense must be LP_MIN or LP_MAX");
-  if (o.tabu_tenure < 0 || o.max_iter < 0 || o.batch_binv_lds_m < -1) return fail(LP_ERR_ARG, "invalid options");
-  if (o.precision != LP_FP64 || o.reinv_period > 0)
-    return fail(LP_ERR_ARG, "the batched solver runs in FP64 without reinversion (precision LP_FP64, reinv_period <= 0)");
+}  // extern "C"
+
+namespace {
+
+// A batch of count LPs of sizes m[i] x n[i] with every device buffer allocated and laid
+// out (A', b and c not filled yet; c_host holds no data yet).  On success *out owns it.
+int batch_alloc(lp_batch** out, int32_t count, const int32_t* m, const int32_t* n, const lp_options& o) {
   size_t max_bytes = 0, max_small = 0;
   for (int32_t i = 0; i < count; ++i) {
-    if (m[i] <= 0 || n[i] < 0 || !b[i] || (n[i] > 0 && (!A[i] || !c[i])))
-      return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": invalid size or NULL data");
-    const size_t cnt = (size_t)m[i] * n[i];
-    for (size_t k = 0; k < cnt; ++k)
-      if (!std::isfinite(A[i][k])) return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": non-finite A");
-    for (int32_t k = 0; k < m[i]; ++k) {
-      if (!std::isfinite(b[i][k])) return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": non-finite b");
-      if (b[i][k] < 0.0) return fail(LP_ERR_NEG_RHS, "LP " + std::to_string(i) + ": b_i < 0");
-    }
-    for (int32_t k = 0; k < n[i]; ++k)
-      if (!std::isfinite(c[i][k])) return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": non-finite c");
+    if (m[i] <= 0 || n[i] < 0) return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": invalid size");
     const size_t bytes = batch_lds_bytes(m[i], n[i]);
     max_bytes = std::max(max_bytes, bytes);
     if (m[i] <= 4 * kBucketWidth) max_small = std::max(max_small, bytes);
@@ -510,8 +497,10 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
     oI += 2 * ((int64_t)L.n + L.m);
     oL += L.cap;
     oO += L.m;
-    p->c[i].assign(c[i], c[i] + n[i]);
   }
+  p->poolA = oA;
+  p->poolb = ob;
+  p->poolc = oc;
   double* dA = nullptr;
   double* db = nullptr;
   double* dc = nullptr;
@@ -555,6 +544,66 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
   p->d.eps_p = o.eps_p;
   p->d.eps_z = o.eps_z;
   p->d.eps_t = o.eps_t;
+  *out = p;
+  p = nullptr;  // handed over
+  return LP_OK;
+}
+
+int batch_options(const lp_options* opt, lp_options* o) {
+  lp_default_options(o);
+  if (opt) *o = *opt;
+  if (o->sense != LP_MIN && o->sense != LP_MAX) return fail(LP_ERR_ARG, "options.sense must be LP_MIN or LP_MAX");
+  if (o->tabu_tenure < 0 || o->max_iter < 0 || o->batch_binv_lds_m < -1) return fail(LP_ERR_ARG, "invalid options");
+  if (o->precision != LP_FP64 || o->reinv_period > 0)
+    return fail(LP_ERR_ARG, "the batched solver runs in FP64 without reinversion (precision LP_FP64, reinv_period <= 0)");
+  return LP_OK;
+}
+
+void load_table_from_env(lp_batch* p) {
+  if (const char* path = std::getenv("LPGPU_BATCH_TUNE")) {
+    if (*path) load_table(p, path);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32_t* n, const double* const* A,
+                    const double* const* b, const double* const* c, const lp_options* opt) try {
+  if (!out) return fail(LP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (count <= 0 || !m || !n || !A || !b || !c) return fail(LP_ERR_ARG, "empty batch or NULL array");
+  lp_options o;
+  if (int rc = batch_options(opt, &o)) return rc;
+  for (int32_t i = 0; i < count; ++i) {
+    if (m[i] <= 0 || n[i] < 0 || !b[i] || (n[i] > 0 && (!A[i] || !c[i])))
+      return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": invalid size or NULL data");
+    const size_t cnt = (size_t)m[i] * n[i];
+    for (size_t k = 0; k < cnt; ++k)
+      if (!std::isfinite(A[i][k])) return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": non-finite A");
+    for (int32_t k = 0; k < m[i]; ++k) {
+      if (!std::isfinite(b[i][k])) return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": non-finite b");
+      if (b[i][k] < 0.0) return fail(LP_ERR_NEG_RHS, "LP " + std::to_string(i) + ": b_i < 0");
+    }
+    for (int32_t k = 0; k < n[i]; ++k)
+      if (!std::isfinite(c[i][k])) return fail(LP_ERR_ARG, "LP " + std::to_string(i) + ": non-finite c");
+  }
+  lp_batch* p = nullptr;
+  if (int rc = batch_alloc(&p, count, m, n, o)) return rc;
+  auto bail = [&](int code) {
+    release(p);
+    p = nullptr;
+    return code;
+  };
+  const auto drop = on_scope_exit([&] {
+    if (p) release(p);
+  });
+  for (int32_t i = 0; i < count; ++i) p->c[i].assign(c[i], c[i] + n[i]);
+  double* dA = const_cast<double*>(p->d.A);
+  double* db = const_cast<double*>(p->d.b);
+  double* dc = const_cast<double*>(p->d.c);
+  const int64_t oA = p->poolA, ob = p->poolb, oc = p->poolc;
   // Upload.  The LPs' A' blocks are consecutive in the pool, so runs of consecutive LPs
   // are packed (columns padded to ld rows with zeros) into one of two pinned staging
   // buffers while the other one's copy is in flight.
@@ -638,9 +687,51 @@ int lp_batch_create(lp_batch** out, int32_t count, const int32_t* m, const int32
     if (e == hipSuccess) e = hipMemcpy(dc, hc.data(), sizeof(double) * hc.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(fail_hip(e, "uploading the batch"));
   }
-  if (const char* path = std::getenv("LPGPU_BATCH_TUNE")) {
-    if (*path) load_table(p, path);
+  load_table_from_env(p);
+  *out = p;
+  p = nullptr;  // handed over
+  return LP_OK;
+} catch (...) {
+  return host_exception();
+}
+
+int lp_batch_create_dense(lp_batch** out, int32_t count, uint64_t seed, int32_t m_lo, int32_t m_hi,
+                          const lp_options* opt) try {
+  if (!out) return fail(LP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (count <= 0 || m_lo < 1 || m_hi < m_lo) return fail(LP_ERR_ARG, "need count > 0 and 1 <= m_lo <= m_hi");
+  lp_options o;
+  if (int rc = batch_options(opt, &o)) return rc;
+  // sizes: m_i = m_lo + (h(seed, 6, i) mod (m_hi - m_lo + 1)), n_i = 2 m_i
+  std::vector<int32_t> m(count), n(count);
+  const uint64_t ks = gen::stream_key(seed, gen::kStreamSize), span = (uint64_t)(m_hi - m_lo) + 1;
+  for (int32_t i = 0; i < count; ++i) {
+    m[i] = m_lo + (int32_t)(gen::hash(ks, (uint64_t)i) % span);
+    n[i] = 2 * m[i];
   }
+  lp_batch* p = nullptr;
+  if (int rc = batch_alloc(&p, count, m.data(), n.data(), o)) return rc;
+  auto bail = [&](int code) {
+    release(p);
+    p = nullptr;
+    return code;
+  };
+  const auto drop = on_scope_exit([&] {
+    if (p) release(p);
+  });
+  hipError_t e = pageable_copy(p->d_lps, p->lps.data(), sizeof(BatchLP) * p->lps.size(), hipMemcpyHostToDevice,
+                               p->stream);
+  if (e == hipSuccess)
+    e = launch_gen_batch(p->d_lps, count, seed, const_cast<double*>(p->d.A), const_cast<double*>(p->d.b),
+                         const_cast<double*>(p->d.c), p->stream);
+  // the costs on the host as well (the objective is formed there): copied back
+  std::vector<double> hc((size_t)p->poolc);
+  if (e == hipSuccess)
+    e = pageable_copy(hc.data(), p->d.c, sizeof(double) * hc.size(), hipMemcpyDeviceToHost, p->stream);
+  if (e != hipSuccess) return bail(fail_hip(e, "generating the batch"));
+  for (int32_t i = 0; i < count; ++i)
+    p->c[i].assign(hc.begin() + p->lps[i].offc, hc.begin() + p->lps[i].offc + n[i]);
+  load_table_from_env(p);
   *out = p;
   p = nullptr;  // handed over
   return LP_OK;
@@ -738,6 +829,17 @@ int lp_batch_get(const lp_batch* pc, int32_t i, double* x, int32_t* basis, int32
     if (dst[a] && k > 0)
       HIP_TRY(hipMemcpy(dst[a], src[a], sizeof(int32_t) * k, hipMemcpyDeviceToHost), "reading the pivot log");
   if (count) *count = have;
+  return LP_OK;
+} catch (...) {
+  return host_exception();
+}
+
+int lp_batch_get_sizes(const lp_batch* p, int32_t* m, int32_t* n) try {
+  if (!p) return fail(LP_ERR_ARG, "bt is NULL");
+  for (int32_t i = 0; i < p->count; ++i) {
+    if (m) m[i] = p->lps[i].m;
+    if (n) n[i] = p->lps[i].n;
+  }
   return LP_OK;
 } catch (...) {
   return host_exception();

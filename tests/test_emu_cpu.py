@@ -241,3 +241,22 @@ def test_compact_columns_mixed_form(emu_lib):
         print("ok")
     """, timeout=900)
     assert "ok" in out
+
+
+def test_device_generated_batch_equals_host_arrays(emu_lib):
+    """lp_batch_create_dense writes the batch law's LPs in device memory; a batch made from
+    host arrays of the same law (tests' generator) solves to the same bits."""
+    out = _run(emu_lib, """
+        with lpg.Batch.dense(6, 11, 16, 64) as g:
+            g.solve(); rg = g.results()
+            lps = lpgen.batch_lps(11, 6, 16, 64)
+            assert [A.shape for A, _, _ in lps] == list(zip(g.m.tolist(), g.n.tolist()))
+            with lpg.Batch(lps) as h:
+                h.solve(); rh = h.results()
+                for k in ("status", "objective", "iterations"):
+                    assert np.array_equal(rg[k], rh[k]), k
+                for i in range(6):
+                    assert np.array_equal(g.get(i)["x"], h.get(i)["x"])
+        print("ok")
+    """)
+    assert "ok" in out

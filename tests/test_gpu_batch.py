@@ -221,3 +221,25 @@ def test_tune_table_round_trip(lpg, tmp_path):
     assert s2["narrow_bucket_mask"] == s1["narrow_bucket_mask"] and s2["binv_lds_m"] == s1["binv_lds_m"]
     for k in ("status", "iterations", "objective"):
         np.testing.assert_array_equal(r1[k], r2[k])
+
+
+def test_batch_generated_on_device(lpg):
+    """lp_batch_create_dense: the 4096-LP batch law generated in device memory equals, bit
+    for bit in its results, the same law built by the tests' generator and uploaded."""
+    _say("case: 4096 LPs generated on the device vs the same LPs from host arrays")
+    lps = lpgen.batch_lps(0, 4096)
+    with lpg.Batch.dense(4096, 0) as g:
+        assert [A.shape for A, _, _ in lps] == list(zip(g.m.tolist(), g.n.tolist()))
+        g.solve()
+        rg = g.results()
+        sample = [0, 1, 2047, 4095]
+        xg = [g.get(i)["x"] for i in sample]
+    with lpg.Batch(lps) as h:
+        h.solve()
+        rh = h.results()
+        xh = [h.get(i)["x"] for i in sample]
+    for k in ("status", "objective", "iterations"):
+        np.testing.assert_array_equal(rg[k], rh[k])
+    for a, b in zip(xg, xh):
+        np.testing.assert_array_equal(a, b)
+    assert (rg["status"] == oracle.OPTIMAL).all()
