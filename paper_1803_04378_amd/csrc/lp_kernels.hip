@@ -1,7 +1,7 @@
 // Kernels of one dense revised simplex iteration for CDNA4 (gfx950, wave64).
 //
-// One iteration is three launches, ordered only by kernel boundaries (no grid-wide
-// fences, which cost an L2 write-back per workgroup on this part):
+// An iteration is ordered only by kernel boundaries (no grid-wide fences, which cost an
+// L2 write-back per workgroup on this part):
 //   k_price   Step 8 on the top row for the previous pivot (W += d_q rho, formed while
 //             staging W in LDS), then Steps 3-4: reduced costs d_j = chat_j - W a_j of
 //             every nonbasic column, one wavefront per column of A'; each workgroup
@@ -12,9 +12,13 @@
 //             Step 5 (FTRAN, alpha = B^-1 a_q) for q: one wavefront per row of B^-1
 //             reads the row once, writes the updated row, dots it with a_q on the fly,
 //             and forms that row's ratio (Step 6); each workgroup leaves its minimum
-//             ratio and its rows within the tie bound.
+//             ratio and its rows within the tie bound.  k_update_c does the same on the
+//             compact columns of B^-1 (rows of 1024 and more), k_update on whole rows.
 //   k_finish  one workgroup: Step 6 ties and tabu list, then the scalar part of Step 8
 //             (basis, entering mask, objective, pivot log).
+// In the FP64 form k_price_fin, run by every iteration of a launch sequence but the
+// first, is k_finish's work for the previous iteration (in every workgroup) followed by
+// k_price's: K iterations take 2K + 1 launches.
 //
 // The B^-1 update of pivot t therefore runs in the same pass as the FTRAN of pivot
 // t+1.  This is legal because pricing for t+1 needs only W_{t+1} = W_t + d_q rho_t,
@@ -862,8 +866,10 @@ __global__ __launch_bounds__(B) void k_update(DevLP lp) {
 // arithmetic of k_update's sparse-column pass at any length of D.  A row's entries on D
 // are contiguous in Bc instead of scattered over a row of Binv, and rho comes compact
 // (rho_c, formed by the pricing kernel): this wavefront's entries of its first row, of
-// rho_c and of the list D are requested in the first round with the control block (they
-// wait only for the scalar load of |D|), so only a_q waits for q.  Lane l owns entries
+// rho_c and of the list D are requested in the first round with the control block (the
+// first 64 at once, since Bc, rho_c and D hold at least that many entries at these sizes;
+// the rest after the scalar load of |D|), so only a_q waits for q.  Workgroup 0 counts the
+// changed entries for the byte statistics in one wave, from those registers.  Lane l owns entries
 // l, l + 64, ... in ascending order, the fma chain and butterfly of k_update.
 template <int B>
 __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
@@ -910,7 +916,7 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
       g[u] = 0.0;
       rr[u] = 0.0;
       dj[u] = 0;
-      if (a < nD) {
+      if (u == 0 || a < nD) {
         g[u] = row[a];
         rr[u] = lp.rho_c[a];  // (unused when no pivot is pending)
         dj[u] = lp.dlist[a];
@@ -1061,14 +1067,17 @@ __global__ __launch_bounds__(B) void k_update_c(DevLP lp) {
   // variable
   int in0 = 1;
   if (gw < m && bv0 >= n) in0 = lp.inD[bv0 - n];
-  if (blockIdx.x == 0) {
+  if (blockIdx.x == 0 && wave == 0) {
     // bytes: the D entries of every row but r read, the changed ones written in every row,
     // one unit lookup (basis, membership, a_q entry) per row
     int nz = 0;
-    if (r >= 0)
-      for (int a = tid; a < nD; a += B) nz += lp.rho_c[a] != 0.0 ? 1 : 0;
-    nz = block_sum_int<B>(nz, red_j);  // (its first barrier: every wave has read red_j)
-    if (tid == 0) lp.ctrl->update_bytes += 8 * ((int64_t)(m - 1) * nD + (int64_t)m * nz) + 16 * (int64_t)m;
+    if (r >= 0) {
+#pragma unroll
+      for (int u = 0; u < kGather; ++u) nz += (lane + 64 * u < nD && rr[u] != 0.0) ? 1 : 0;
+      for (int a = lane + 64 * kGather; a < nD; a += 64) nz += lp.rho_c[a] != 0.0 ? 1 : 0;
+    }
+    nz = wave_sum_int(nz);
+    if (lane == 0) lp.ctrl->update_bytes += 8 * ((int64_t)(m - 1) * nD + (int64_t)m * nz) + 16 * (int64_t)m;
   }
   int c = 0;
   for (int i = gw; i < m; i += nw, ++c) {

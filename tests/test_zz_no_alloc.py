@@ -1,7 +1,8 @@
 """The entry point that allocates nothing (lp_solve_device_noalloc), through the C ABI,
 against the entry points it stands for (lp_create_device + lp_solve + lp_get_solution):
 two calls in a row on one GPU, the second with a smaller LP, so that the second runs on the
-array the first one left behind."""
+array the first one left behind (the last pair with rows of 1024 and more: B^-1 as compact
+columns in the array too)."""
 import sys
 
 import numpy as np
@@ -32,7 +33,8 @@ def _device(torch, A, b, c):
     return dA, torch.from_numpy(b).cuda(), torch.from_numpy(c).cuda()
 
 
-@pytest.mark.parametrize("sizes", [((400, 800, 0), (130, 257, 1)), ((1000, 2000, 2), (61, 90, 3))])
+@pytest.mark.parametrize("sizes", [((400, 800, 0), (130, 257, 1)), ((1000, 2000, 2), (61, 90, 3)),
+                                   ((1100, 600, 4), (1030, 300, 5))])
 def test_noalloc_matches_the_handle_path(lpg, sizes):
     import torch
     torch.cuda.set_device(0)
