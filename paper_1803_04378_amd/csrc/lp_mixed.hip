@@ -237,10 +237,29 @@ __global__ __launch_bounds__(kPrice32Block) void k_price32(DevLP lp) {
     const int nDn = lp.ctrl->nD, a_app = lp.ctrl->dapp;
     const double* crow = lp.Bc + (size_t)r * lp.ld;
     const bool writer = blockIdx.x == 0;
-    for (int k = threadIdx.x; k < lp.ld; k += kPrice32Block) {
-      const double w = Wold[k];
-      s_w[k] = (float)w;
-      if (writer) Wnew[k] = w;
+    {
+      // every load of a round before its stores (a load-store loop waits for each load)
+      const double2* Wo2 = reinterpret_cast<const double2*>(Wold);
+      double2* Wn2 = reinterpret_cast<double2*>(Wnew);
+      const int ld2 = lp.ld / 2;
+      constexpr int U = 4;
+      for (int k0 = threadIdx.x; k0 < ld2; k0 += U * kPrice32Block) {
+        double2 tw[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + u * kPrice32Block;
+          if (k < ld2) tw[u] = Wo2[k];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + u * kPrice32Block;
+          if (k < ld2) {
+            s_w[2 * k] = (float)tw[u].x;
+            s_w[2 * k + 1] = (float)tw[u].y;
+            if (writer) Wn2[k] = tw[u];
+          }
+        }
+      }
     }
     __syncthreads();  // (the copy of W is stored before the entries on D overwrite it)
     for (int a = threadIdx.x; a < nDn; a += kPrice32Block) {
@@ -283,7 +302,25 @@ __global__ __launch_bounds__(kPrice32Block) void k_price32(DevLP lp) {
     }
   } else {
     const double* W = wc ? lp.W1 : lp.W0;
-    for (int k = threadIdx.x; k < lp.ld; k += kPrice32Block) s_w[k] = (float)W[k];
+    const double2* W2 = reinterpret_cast<const double2*>(W);
+    const int ld2 = lp.ld / 2;
+    constexpr int U = 4;
+    for (int k0 = threadIdx.x; k0 < ld2; k0 += U * kPrice32Block) {
+      double2 tw[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * kPrice32Block;
+        if (k < ld2) tw[u] = W2[k];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * kPrice32Block;
+        if (k < ld2) {
+          s_w[2 * k] = (float)tw[u].x;
+          s_w[2 * k + 1] = (float)tw[u].y;
+        }
+      }
+    }
   }
   __syncthreads();
 
@@ -384,7 +421,21 @@ __global__ __launch_bounds__(kShortlistBlock) void k_shortlist(DevLP lp) {
     const int k = tid + u * kShortlistBlock;
     wv[u] = k < ld2 ? reinterpret_cast<const double2*>(Wc)[k] : make_double2(0.0, 0.0);
   }
-  for (int e = tid; e < G * S; e += kShortlistBlock) s_all[e] = lp.part32[e];
+  {
+    // every load first, then the stores (a loop of load-then-store waits for each load)
+    constexpr int kPer = kMaxLists * S / kShortlistBlock;
+    uint64_t kv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + u * kShortlistBlock;
+      kv[u] = e < G * S ? lp.part32[e] : kNoKey;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + u * kShortlistBlock;
+      if (e < G * S) s_all[e] = kv[u];
+    }
+  }
   if (tid < S) s_sel[tid] = -1;
   __syncthreads();
   // Bitonic sort of this wave's 64 heads (ascending), each carrying its list index.
