@@ -1549,6 +1549,10 @@ __global__ __launch_bounds__(B) void k_update_wide(DevLP lp) {
 // commit leaves alone what they read: the inputs come from the snapshot k_update took
 // (FinishIn), basis[r] and the tabu list's generation bump are left for the next k_update
 // to apply, and the pricing part patches its own view of pos and tabu_until.
+// Rows of B^-1 per thread per round in the tie scans below, every load of a round issued
+// before any test (a loop over the rows waits for each row's loads in turn); more per round
+// spill registers in k_price_fin, where the first batch of A' is held across the finish.
+constexpr int kTieRound = 2;
 template <int B, bool FUSED>
 __device__ FinishOut finish_step(const DevLP& lp, const FinishIn& in, double pth, double pt1, double pt2, double pal,
                                  int plow, int pbv) {
@@ -1661,11 +1665,25 @@ __device__ FinishOut finish_step(const DevLP& lp, const FinishIn& in, double pth
   } else {
     cnt = 0;
     low = INT_MAX;
-    for (int i = tid; i < m; i += B) {
-      const double a = al[i];
-      if (a > eps_p && fma(-a, th, fmax(lp.xB[i], 0.0)) <= eps_t) {
-        ++cnt;
-        low = min(low, i);
+    for (int i0 = tid; i0 < m; i0 += kTieRound * B) {
+      double a[kTieRound], x[kTieRound];
+#pragma unroll
+      for (int u = 0; u < kTieRound; ++u) {
+        const int i = i0 + u * B;
+        a[u] = 0.0;
+        x[u] = 0.0;
+        if (i < m) {
+          a[u] = al[i];
+          x[u] = lp.xB[i];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kTieRound; ++u) {
+        const int i = i0 + u * B;
+        if (i < m && a[u] > eps_p && fma(-a[u], th, fmax(x[u], 0.0)) <= eps_t) {
+          ++cnt;
+          low = min(low, i);
+        }
       }
     }
     block_sum_min_int<B>(cnt, low, red_j);
@@ -1683,10 +1701,27 @@ __device__ FinishOut finish_step(const DevLP& lp, const FinishIn& in, double pth
         if (lp.Lq[k] == q && lp.Lgen[k] == g) lp.excl[lp.Ll[k]] = stamp;
       __syncthreads();
       int fl = INT_MAX;
-      for (int i = tid; i < m; i += B) {
-        const double a = al[i];
-        if (a > eps_p && fma(-a, th, fmax(lp.xB[i], 0.0)) <= eps_t && lp.excl[lp.basis[i]] != stamp)
-          fl = min(fl, i);
+      for (int i0 = tid; i0 < m; i0 += kTieRound * B) {
+        double a[kTieRound], x[kTieRound];
+        int bv[kTieRound];
+#pragma unroll
+        for (int u = 0; u < kTieRound; ++u) {
+          const int i = i0 + u * B;
+          a[u] = 0.0;
+          x[u] = 0.0;
+          bv[u] = 0;
+          if (i < m) {
+            a[u] = al[i];
+            x[u] = lp.xB[i];
+            bv[u] = lp.basis[i];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kTieRound; ++u) {
+          const int i = i0 + u * B;
+          if (i < m && a[u] > eps_p && fma(-a[u], th, fmax(x[u], 0.0)) <= eps_t && lp.excl[bv[u]] != stamp)
+            fl = min(fl, i);
+        }
       }
       fl = block_min_int<B>(fl, red_j);
       int gnew = g;
