@@ -33,6 +33,39 @@ using namespace detail;
 
 namespace {
 
+// dot(x0, y) and, when `two`, dot(x1, y): both columns' loads of a round are issued before
+// either is consumed.  Each is wave_dot's fma chain per lane and butterfly, so the results
+// are those of two wave_dot calls.
+template <bool NT, int NB>
+__device__ __forceinline__ void wave_dot2(const double2* __restrict__ x0, const double2* __restrict__ x1, bool two,
+                                          const double2* y, int n2, int lane, double2 (&v0)[NB], double2 (&v1)[NB],
+                                          double& s0, double& s1) {
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int k0 = lane; k0 < n2; k0 += 64 * NB) {
+    if (NT) load_batch_nt(x0, k0, n2, v0);
+    else load_batch(x0, k0, n2, v0);
+    if (two) {
+      if (NT) load_batch_nt(x1, k0, n2, v1);
+      else load_batch(x1, k0, n2, v1);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int k = k0 + 64 * u;
+      if (k < n2) {
+        const double2 w = y[k];
+        acc0 = fma(v0[u].x, w.x, acc0);
+        acc0 = fma(v0[u].y, w.y, acc0);
+        if (two) {
+          acc1 = fma(v1[u].x, w.x, acc1);
+          acc1 = fma(v1[u].y, w.y, acc1);
+        }
+      }
+    }
+  }
+  s0 = wave_sum(acc0);
+  s1 = wave_sum(acc1);  // (zero when not two: every lane takes part in the butterfly)
+}
+
 #ifndef LPGPU_BATCH_SMALL
 #define LPGPU_BATCH_SMALL 2
 #endif
@@ -200,15 +233,14 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
   double theta = 0.0, z = 0.0;
   const double neg_eps = -bd.eps_d;
   double2 v[kBatchSmall];  // rows here are short: a shallow batch keeps registers for occupancy
+  double2 v2[kBatchSmall];
   for (;;) {
-    // Steps 3-4: reduced costs with W in LDS.
+    // Steps 3-4: reduced costs with W in LDS, two nonbasic columns per wavefront at a time
+    // (twice the loads in flight; the minima do not depend on the order).
     double da = __builtin_inf(), df = __builtin_inf();
     int ja = INT_MAX, jf = INT_MAX;
     const bool cached_a = ld <= kBatchCachedLd;
-    for (int j = wave; j < n; j += G) {
-      if (pos[j] >= 0) continue;
-      const double s = cached_a ? wave_dot<false>(A2 + (size_t)j * ld2, W2, ld2, lane, v, false)
-                                : wave_dot<kStreamA>(A2 + (size_t)j * ld2, W2, ld2, lane, v, false);
+    auto consider = [&](int j, double s) {
       const double d = sense * cc[j] - s;
       if (d < neg_eps) {
         if (lex_less(d, j, da, ja)) {
@@ -220,6 +252,20 @@ __device__ void solve_lp(const BatchDev& bd, int id, unsigned char* base, int ti
           jf = j;
         }
       }
+    };
+    for (int j0 = wave; j0 < n; j0 += 2 * G) {
+      const int j1 = j0 + G;
+      const bool u0 = pos[j0] < 0, u1 = j1 < n && pos[j1] < 0;
+      if (!u0 && !u1) continue;
+      const int ja0 = u0 ? j0 : j1;  // the first priced column
+      const bool two = u0 && u1;
+      double s0, s1;
+      if (cached_a)
+        wave_dot2<false>(A2 + (size_t)ja0 * ld2, A2 + (size_t)j1 * ld2, two, W2, ld2, lane, v, v2, s0, s1);
+      else
+        wave_dot2<kStreamA>(A2 + (size_t)ja0 * ld2, A2 + (size_t)j1 * ld2, two, W2, ld2, lane, v, v2, s0, s1);
+      consider(ja0, s0);
+      if (two) consider(j1, s1);
     }
     for (int i = tid; i < m; i += T) {
       const int vv = n + i;
