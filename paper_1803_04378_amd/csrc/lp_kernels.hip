@@ -1553,6 +1553,9 @@ __global__ __launch_bounds__(B) void k_update_wide(DevLP lp) {
 // before any test (a loop over the rows waits for each row's loads in turn); more per round
 // spill registers in k_price_fin, where the first batch of A' is held across the finish.
 constexpr int kTieRound = 2;
+// Entries of the leaving-side list per thread per round in its scan (the same reason; the
+// list grows by one entry per tied pivot).
+constexpr int kListRound = 4;
 template <int B, bool FUSED>
 __device__ FinishOut finish_step(const DevLP& lp, const FinishIn& in, double pth, double pt1, double pt2, double pal,
                                  int plow, int pbv) {
@@ -1697,8 +1700,24 @@ __device__ FinishOut finish_step(const DevLP& lp, const FinishIn& in, double pth
       const int stamp = (int)t + 1;
       const int g = lp.gen[q];
       const int nL = in.nL;
-      for (int k = tid; k < nL; k += B)
-        if (lp.Lq[k] == q && lp.Lgen[k] == g) lp.excl[lp.Ll[k]] = stamp;
+      for (int k0 = tid; k0 < nL; k0 += kListRound * B) {
+        int lq[kListRound], lg[kListRound];
+#pragma unroll
+        for (int u = 0; u < kListRound; ++u) {
+          const int k = k0 + u * B;
+          lq[u] = -1;
+          lg[u] = 0;
+          if (k < nL) {
+            lq[u] = lp.Lq[k];
+            lg[u] = lp.Lgen[k];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kListRound; ++u) {
+          const int k = k0 + u * B;
+          if (k < nL && lq[u] == q && lg[u] == g) lp.excl[lp.Ll[k]] = stamp;
+        }
+      }
       __syncthreads();
       int fl = INT_MAX;
       for (int i0 = tid; i0 < m; i0 += kTieRound * B) {
